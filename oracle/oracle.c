@@ -1,0 +1,891 @@
+/*
+ * oracle.c -- plain, slow CPU reference for differentiable 2D Gaussian ray
+ * tracing (2DGRT) of secondary rays with multiple-importance-sampled shading,
+ * after "Inter-Reflective Gaussian Splatting for Robust and Efficient Inverse
+ * Rendering" (IRGS++).
+ *
+ * TEST INFRASTRUCTURE.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark load this library.  It shares no code,
+ * header, table or constant generator with the GPU library.
+ *
+ * What it computes, by brute force (every ray against every surfel, no
+ * acceleration structure):
+ *   - ray/surfel intersection and 2D Gaussian weight   (Sec. 3.2, Eq. raytracing_intersection and the influence G(p))
+ *   - exact front-to-back order and compositing         (Sec. 3.2, Eq. trace; Eq. alpha_blending)
+ *   - incident radiance L_i = c_rt + (1 - o_rt) L_env   (Sec. 3.3, Eqs. lighting_decompose, incident_trace)
+ *   - the metallic microfacet BRDF                      (Sec. 3.1, Eqs. brdf_decompose, brdf_specular)
+ *   - the MIS estimator with cosine/GGX/env proposals   (Sec. 3.4.1, Eqs. montecarlo, mis)
+ *   - gradients of a loss through all of the above      (Sec. 3.2 "gradients can backpropagate through the secondary-ray queries")
+ *
+ * Precision.  Values (weights, radiance, pdfs, gradients) are computed in
+ * double.  Decisions that turn floating point into integers -- whether a
+ * surfel is hit, the depth order, and where compositing stops -- are taken
+ * in single precision with a fixed operation order (this file is compiled
+ * with -ffp-contract=off), because that is the precision the GPU kernels
+ * decide in.  The fixed order is:
+ *   frame:  l = sqrtf(((w*w + x*x) + y*y) + z*z); q <- q / l (four divisions)
+ *           t_u = (1-2(yy+zz), 2(xy+wz), 2(xz-wy)), t_v = (2(xy-wz), 1-2(xx+zz), 2(yz+wx)),
+ *           n = (2(xz+wy), 2(yz-wx), 1-2(xx+yy)),  a_u = t_u / s_u,  a_v = t_v / s_v
+ *   bound:  r2max = (float) min(9, 2 ln(o / alpha_min))   evaluated in double
+ *   test:   m = mu - o;  den = (n.x d.x + n.y d.y) + n.z d.z;  skip if |den| < 1e-6
+ *           tau = ((n.x m.x + n.y m.y) + n.z m.z) / den;  keep if t_min < tau <= t_max
+ *           D = tau d - m;  u = a_u.D;  v = a_v.D;  hit iff u*u + v*v <= r2max
+ *   order:  ascending (bits(tau), id)  -- tau > 0, so the bit pattern is monotone
+ *   stop:   T32 <- T32 * (1 - o*expf(-0.5*r2)); stop after the hit that makes T32 < T_cut
+ *
+ * Readings of the paper taken here (where it is silent):
+ *   - support: 3 sigma (rho^2 <= 9) and the minimum influence alpha >= alpha_min,
+ *     i.e. rho^2 <= 2 ln(o/alpha_min), the radius the paper's adaptive bounding
+ *     proxy uses (Eq. icosahedron_transform);
+ *   - rotations are (w,x,y,z) quaternions normalised inside; t_u, t_v, n are the
+ *     columns of the rotation matrix; gradients are taken w.r.t. the stored
+ *     (unnormalised) quaternion, the linear scales and the activated opacity;
+ *   - compositing includes the hit that makes T < T_cut, then stops;
+ *   - the GGX proposal samples visible normals (Heitz 2018) with alpha = r^2;
+ *     D is GGX, G the separable Smith form, F Schlick on (omega_i . h);
+ *   - proposals are normalised over the sphere; samples below the horizon
+ *     count in N_k and contribute zero;
+ *   - the environment proposal is piecewise constant over texels weighted by
+ *     luminance times sin(theta) at the texel centre; radiance is looked up at
+ *     the nearest texel; +y is up, row 0 is the zenith, phi = atan2(z, x);
+ *   - random numbers: Philox-4x32-10 (Salmon et al., SC'11), key = seed,
+ *     counter = (pixel, sample, job, 0); u = (word >> 8) * 2^-24.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_PI 3.14159265358979323846
+
+/* ------------------------------------------------------------------------ */
+/* Surfels                                                                   */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    /* single precision: the hit decision and the depth key */
+    float mu[3], n[3], au[3], av[3], r2max, op;
+} Surf32;
+
+typedef struct {
+    /* double precision: everything that is a value */
+    double mu[3], tu[3], tv[3], n[3], su, sv, op, c[3];
+    double qhat[4], qlen;
+} Surf64;
+
+typedef struct {
+    int64_t n;
+    Surf32 *s32;
+    Surf64 *s64;
+} Scene;
+
+/* Frame of a 2D Gaussian from its quaternion and scales (Sec. 3.2, the
+ * primitive's centre, tangents t_u, t_v, scales and opacity; n = t_u x t_v). */
+static void prep_one32(const float *mu, const float *sc, const float *q, float op, float alpha_min, Surf32 *o)
+{
+    float w = q[0], x = q[1], y = q[2], z = q[3];
+    float l = sqrtf(w * w + x * x + y * y + z * z);
+    w = w / l; x = x / l; y = y / l; z = z / l;
+    float xx = x * x, yy = y * y, zz = z * z;
+    float xy = x * y, xz = x * z, yz = y * z;
+    float wx = w * x, wy = w * y, wz = w * z;
+    float tu[3] = {1.0f - 2.0f * (yy + zz), 2.0f * (xy + wz), 2.0f * (xz - wy)};
+    float tv[3] = {2.0f * (xy - wz), 1.0f - 2.0f * (xx + zz), 2.0f * (yz + wx)};
+    float nn[3] = {2.0f * (xz + wy), 2.0f * (yz - wx), 1.0f - 2.0f * (xx + yy)};
+    for (int i = 0; i < 3; ++i) {
+        o->mu[i] = mu[i];
+        o->n[i] = nn[i];
+        o->au[i] = tu[i] / sc[0];
+        o->av[i] = tv[i] / sc[1];
+    }
+    o->op = op;
+    if (alpha_min > 0.0f) {
+        double b = 2.0 * log((double)op / (double)alpha_min);
+        o->r2max = (float)(b < 9.0 ? b : 9.0);
+    } else {
+        o->r2max = 9.0f;
+    }
+}
+
+static void prep_one64(const float *mu, const float *sc, const float *q, float op, const float *rgb, Surf64 *o)
+{
+    double w = q[0], x = q[1], y = q[2], z = q[3];
+    double l = sqrt(w * w + x * x + y * y + z * z);
+    o->qlen = l;
+    w /= l; x /= l; y /= l; z /= l;
+    o->qhat[0] = w; o->qhat[1] = x; o->qhat[2] = y; o->qhat[3] = z;
+    /* rotation matrix of a unit Hamilton quaternion; columns are t_u, t_v, n */
+    o->tu[0] = 1.0 - 2.0 * (y * y + z * z); o->tu[1] = 2.0 * (x * y + w * z); o->tu[2] = 2.0 * (x * z - w * y);
+    o->tv[0] = 2.0 * (x * y - w * z); o->tv[1] = 1.0 - 2.0 * (x * x + z * z); o->tv[2] = 2.0 * (y * z + w * x);
+    o->n[0] = 2.0 * (x * z + w * y); o->n[1] = 2.0 * (y * z - w * x); o->n[2] = 1.0 - 2.0 * (x * x + y * y);
+    for (int i = 0; i < 3; ++i) { o->mu[i] = mu[i]; o->c[i] = rgb ? rgb[i] : 0.0; }
+    o->su = sc[0]; o->sv = sc[1]; o->op = op;
+}
+
+static int scene_init(Scene *S, int64_t n, const float *means, const float *scales, const float *quats,
+                      const float *opacity, const float *rgb, float alpha_min)
+{
+    S->n = n;
+    S->s32 = (Surf32 *)malloc(sizeof(Surf32) * (size_t)(n > 0 ? n : 1));
+    S->s64 = (Surf64 *)malloc(sizeof(Surf64) * (size_t)(n > 0 ? n : 1));
+    if (!S->s32 || !S->s64) { free(S->s32); free(S->s64); return -1; }
+    for (int64_t i = 0; i < n; ++i) {
+        prep_one32(means + 3 * i, scales + 2 * i, quats + 4 * i, opacity[i], alpha_min, &S->s32[i]);
+        prep_one64(means + 3 * i, scales + 2 * i, quats + 4 * i, opacity[i], rgb ? rgb + 3 * i : NULL, &S->s64[i]);
+    }
+    return 0;
+}
+
+static void scene_free(Scene *S) { free(S->s32); free(S->s64); }
+
+/* ------------------------------------------------------------------------ */
+/* One ray against one surfel                                                */
+/* ------------------------------------------------------------------------ */
+
+/* Decision in single precision (Eq. raytracing_intersection, then the 2D
+ * Gaussian's local coordinates u, v).  Returns 1 on a hit and the depth; the
+ * margins record how close each test came to its threshold. */
+typedef struct { float r2, den, tau; } Margin;
+
+static int hit32(const Surf32 *s, const float o[3], const float d[3], float tmin, float tmax,
+                 float *tau_out, float *r2_out, Margin *mg)
+{
+    float m0 = s->mu[0] - o[0], m1 = s->mu[1] - o[1], m2 = s->mu[2] - o[2];
+    float den = s->n[0] * d[0] + s->n[1] * d[1] + s->n[2] * d[2];
+    if (mg) { float a = fabsf(fabsf(den) - 1e-6f); if (a < mg->den) mg->den = a; }
+    if (fabsf(den) < 1e-6f) return 0;
+    float num = s->n[0] * m0 + s->n[1] * m1 + s->n[2] * m2;
+    float tau = num / den;
+    if (mg) {
+        float a = fabsf(tau - tmin);
+        if (a < mg->tau) mg->tau = a;
+    }
+    if (!(tau > tmin && tau <= tmax)) return 0;
+    float dx = tau * d[0] - m0, dy = tau * d[1] - m1, dz = tau * d[2] - m2;
+    float u = s->au[0] * dx + s->au[1] * dy + s->au[2] * dz;
+    float v = s->av[0] * dx + s->av[1] * dy + s->av[2] * dz;
+    float r2 = u * u + v * v;
+    if (mg && s->r2max >= 0.0f) {
+        float a = fabsf(r2 - s->r2max);
+        if (a < mg->r2) mg->r2 = a;
+    }
+    if (!(r2 <= s->r2max)) return 0;
+    *tau_out = tau;
+    *r2_out = r2;
+    return 1;
+}
+
+/* Values in double along the same (single-precision) ray. */
+typedef struct { double tau, den, D[3], u, v, r2, G, alpha; } Geo64;
+
+static void geo64(const Surf64 *s, const float of[3], const float df[3], Geo64 *g)
+{
+    double o[3] = {of[0], of[1], of[2]}, d[3] = {df[0], df[1], df[2]};
+    double m[3] = {s->mu[0] - o[0], s->mu[1] - o[1], s->mu[2] - o[2]};
+    g->den = s->n[0] * d[0] + s->n[1] * d[1] + s->n[2] * d[2];
+    g->tau = (s->n[0] * m[0] + s->n[1] * m[1] + s->n[2] * m[2]) / g->den;
+    for (int i = 0; i < 3; ++i) g->D[i] = o[i] + g->tau * d[i] - s->mu[i];  /* p - mu */
+    g->u = (s->tu[0] * g->D[0] + s->tu[1] * g->D[1] + s->tu[2] * g->D[2]) / s->su;
+    g->v = (s->tv[0] * g->D[0] + s->tv[1] * g->D[1] + s->tv[2] * g->D[2]) / s->sv;
+    g->r2 = g->u * g->u + g->v * g->v;
+    g->G = exp(-0.5 * g->r2);
+    g->alpha = s->op * g->G;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Ordered hit list and compositing of one ray (Eq. trace)                    */
+/* ------------------------------------------------------------------------ */
+
+typedef struct { uint64_t key; int64_t id; float r2; } Hit;
+
+static int hit_cmp(const void *a, const void *b)
+{
+    const Hit *x = (const Hit *)a, *y = (const Hit *)b;
+    if (x->key != y->key) return x->key < y->key ? -1 : 1;
+    return x->id < y->id ? -1 : (x->id > y->id ? 1 : 0);
+}
+
+static uint32_t fbits(float f) { uint32_t u; memcpy(&u, &f, 4); return u; }
+static float bitsf(uint32_t u) { float f; memcpy(&f, &u, 4); return f; }
+
+typedef struct {
+    Hit *h;          /* all hits, sorted */
+    int64_t nh;      /* number of hits on the ray */
+    int64_t K;       /* number composited (the stop index) */
+    double C[3], T;  /* c_rt and the final transmittance 1 - o_rt */
+    Margin mg;       /* closest approach of any decision to its threshold */
+    float tstop;     /* |T32 - T_cut| / T_cut at the closest step */
+} RayResult;
+
+static void trace_ray(const Scene *S, const float o[3], const float d[3], float tmin, float tmax,
+                      float t_cut, RayResult *R)
+{
+    int64_t cap = 64, nh = 0;
+    Hit *h = (Hit *)malloc(sizeof(Hit) * (size_t)cap);
+    R->mg.r2 = INFINITY; R->mg.den = INFINITY; R->mg.tau = INFINITY;
+    for (int64_t i = 0; i < S->n; ++i) {
+        float tau, r2;
+        if (hit32(&S->s32[i], o, d, tmin, tmax, &tau, &r2, &R->mg)) {
+            if (nh == cap) { cap *= 2; h = (Hit *)realloc(h, sizeof(Hit) * (size_t)cap); }
+            h[nh].key = ((uint64_t)fbits(tau) << 32) | (uint64_t)(uint32_t)i;
+            h[nh].id = i;
+            h[nh].r2 = r2;
+            ++nh;
+        }
+    }
+    qsort(h, (size_t)nh, sizeof(Hit), hit_cmp);
+    /* front to back: C += T alpha c, T *= 1 - alpha; stop after T < T_cut */
+    double C[3] = {0, 0, 0}, T = 1.0;
+    float T32 = 1.0f;
+    float tstop = INFINITY;
+    int64_t K = 0;
+    for (int64_t k = 0; k < nh; ++k) {
+        const Surf64 *s = &S->s64[h[k].id];
+        Geo64 g;
+        geo64(s, o, d, &g);
+        for (int c = 0; c < 3; ++c) C[c] += T * g.alpha * s->c[c];
+        T *= 1.0 - g.alpha;
+        float a32 = S->s32[h[k].id].op * expf(-0.5f * h[k].r2);
+        T32 = T32 * (1.0f - a32);
+        K = k + 1;
+        float rel = fabsf(T32 - t_cut) / t_cut;
+        if (rel < tstop) tstop = rel;
+        if (T32 < t_cut) break;
+    }
+    R->h = h; R->nh = nh; R->K = K;
+    R->C[0] = C[0]; R->C[1] = C[1]; R->C[2] = C[2]; R->T = T;
+    R->tstop = tstop;
+}
+
+/* Gradient of g_C . c_rt + g_T . T_fin w.r.t. every composited surfel, with
+ * the hit set, order and stop index held fixed.  Derived from Eq. trace:
+ *   dC/dc_k = T_k a_k,  dC/da_k = T_k c_k - (C - P_k)/(1 - a_k),  dT/da_k = -T/(1 - a_k)
+ * with P_k the colour composited up to and including hit k; then through
+ * a = o G, G = exp(-(u^2+v^2)/2), u = t_u.(p-mu)/s_u, v = t_v.(p-mu)/s_v,
+ * p = r_o + tau r_d, tau = n.(mu - r_o)/(n.r_d), and the quaternion frame.
+ * Gradients are accumulated into g (13 doubles per surfel:
+ * mean 3, scale 2, quat 4, opacity 1, rgb 3). */
+static void backward_ray(const Scene *S, const float o[3], const float d[3], const RayResult *R,
+                         const double gC[3], double gT, double *g13)
+{
+    double T = 1.0, P[3] = {0, 0, 0};
+    for (int64_t k = 0; k < R->K; ++k) {
+        int64_t id = R->h[k].id;
+        const Surf64 *s = &S->s64[id];
+        Geo64 g;
+        geo64(s, o, d, &g);
+        double a = g.alpha;
+        double w = T * a;
+        for (int c = 0; c < 3; ++c) P[c] += w * s->c[c];
+        double dA = T * (gC[0] * s->c[0] + gC[1] * s->c[1] + gC[2] * s->c[2]);
+        if (1.0 - a >= 1e-6) {
+            double behind = gC[0] * (R->C[0] - P[0]) + gC[1] * (R->C[1] - P[1]) + gC[2] * (R->C[2] - P[2]) + gT * R->T;
+            dA -= behind / (1.0 - a);
+        }
+        double drgb[3] = {w * gC[0], w * gC[1], w * gC[2]};
+        double dop = g.G * dA;
+        double gamma = -0.5 * a * dA;            /* dL/d(rho^2) */
+        double du = 2.0 * g.u * gamma, dv = 2.0 * g.v * gamma;
+        double dsu = -(g.u / s->su) * du, dsv = -(g.v / s->sv) * dv;
+        double gD[3], dtu[3], dtv[3], dn[3], dmu[3];
+        for (int i = 0; i < 3; ++i) gD[i] = du * s->tu[i] / s->su + dv * s->tv[i] / s->sv;
+        double gDd = (gD[0] * d[0] + gD[1] * d[1] + gD[2] * d[2]) / g.den;
+        for (int i = 0; i < 3; ++i) {
+            dmu[i] = gDd * s->n[i] - gD[i];
+            dtu[i] = du * g.D[i] / s->su;
+            dtv[i] = dv * g.D[i] / s->sv;
+            dn[i] = -gDd * g.D[i];
+        }
+        /* columns of R(q) -> unit quaternion (w,x,y,z) */
+        double qw = s->qhat[0], qx = s->qhat[1], qy = s->qhat[2], qz = s->qhat[3];
+        double dq[4];
+        dq[0] = dtu[1] * (2 * qz) + dtu[2] * (-2 * qy)
+              + dtv[0] * (-2 * qz) + dtv[2] * (2 * qx)
+              + dn[0] * (2 * qy) + dn[1] * (-2 * qx);
+        dq[1] = dtu[1] * (2 * qy) + dtu[2] * (2 * qz)
+              + dtv[0] * (2 * qy) + dtv[1] * (-4 * qx) + dtv[2] * (2 * qw)
+              + dn[0] * (2 * qz) + dn[1] * (-2 * qw) + dn[2] * (-4 * qx);
+        dq[2] = dtu[0] * (-4 * qy) + dtu[1] * (2 * qx) + dtu[2] * (-2 * qw)
+              + dtv[0] * (2 * qx) + dtv[2] * (2 * qz)
+              + dn[0] * (2 * qw) + dn[1] * (2 * qz) + dn[2] * (-4 * qy);
+        dq[3] = dtu[0] * (-4 * qz) + dtu[1] * (2 * qw) + dtu[2] * (2 * qx)
+              + dtv[0] * (-2 * qw) + dtv[1] * (-4 * qz) + dtv[2] * (2 * qy)
+              + dn[0] * (2 * qx) + dn[1] * (2 * qy);
+        /* unit quaternion -> stored quaternion: (I - qhat qhat^T) / |q| */
+        double proj = qw * dq[0] + qx * dq[1] + qy * dq[2] + qz * dq[3];
+        double dqs[4] = {(dq[0] - qw * proj) / s->qlen, (dq[1] - qx * proj) / s->qlen,
+                         (dq[2] - qy * proj) / s->qlen, (dq[3] - qz * proj) / s->qlen};
+        double *gg = g13 + 13 * id;
+        double add[13] = {dmu[0], dmu[1], dmu[2], dsu, dsv, dqs[0], dqs[1], dqs[2], dqs[3], dop,
+                          drgb[0], drgb[1], drgb[2]};
+        for (int i = 0; i < 13; ++i) {
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+            gg[i] += add[i];
+        }
+        T *= 1.0 - a;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exported: trace (Eq. trace with L_i = c_rt + T sky, Eq. lighting_decompose) */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * rays: origins/dirs [R,3] float; t_min/t_max per ray (or NULL: scalars).
+ * outputs (any may be NULL): C [R,3], T [R], L [R,3], nhit [R] composited,
+ * dump_id/dump_tau [R,cap] of composited hits in order, margins [R,4] =
+ * (rho^2 margin, |den| margin, tau margin, relative stop margin).
+ */
+int orc_trace(int64_t n, const float *means, const float *scales, const float *quats, const float *opacity,
+              const float *rgb, float alpha_min,
+              int64_t nr, const float *orig, const float *dirs, const float *tmin_a, const float *tmax_a,
+              float tmin_s, float tmax_s, float t_cut, const float *sky,
+              double *outC, double *outT, double *outL, int32_t *nhit,
+              int64_t cap, int32_t *dump_id, float *dump_tau, float *margins)
+{
+    Scene S;
+    if (scene_init(&S, n, means, scales, quats, opacity, rgb, alpha_min)) return -1;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < nr; ++r) {
+        float tmin = tmin_a ? tmin_a[r] : tmin_s, tmax = tmax_a ? tmax_a[r] : tmax_s;
+        RayResult R;
+        trace_ray(&S, orig + 3 * r, dirs + 3 * r, tmin, tmax, t_cut, &R);
+        for (int c = 0; c < 3; ++c) {
+            if (outC) outC[3 * r + c] = R.C[c];
+            if (outL) outL[3 * r + c] = R.C[c] + R.T * (double)sky[c];
+        }
+        if (outT) outT[r] = R.T;
+        if (nhit) nhit[r] = (int32_t)R.K;
+        if (dump_id) {
+            for (int64_t k = 0; k < cap; ++k) {
+                dump_id[r * cap + k] = k < R.K ? (int32_t)R.h[k].id : -1;
+                dump_tau[r * cap + k] = k < R.K ? bitsf((uint32_t)(R.h[k].key >> 32)) : 0.0f;
+            }
+        }
+        if (margins) {
+            margins[4 * r + 0] = R.mg.r2; margins[4 * r + 1] = R.mg.den;
+            margins[4 * r + 2] = R.mg.tau; margins[4 * r + 3] = R.tstop;
+        }
+        free(R.h);
+    }
+    scene_free(&S);
+    return 0;
+}
+
+/* Gradient of sum_r (gC_r . c_rt(r) + gT_r T_fin(r)) w.r.t. the surfels.
+ * g13 [n,13] is overwritten (mean 3, scale 2, quat 4, opacity 1, rgb 3). */
+int orc_trace_backward(int64_t n, const float *means, const float *scales, const float *quats,
+                       const float *opacity, const float *rgb, float alpha_min,
+                       int64_t nr, const float *orig, const float *dirs, const float *tmin_a, const float *tmax_a,
+                       float tmin_s, float tmax_s, float t_cut,
+                       const double *gC, const double *gT, double *g13)
+{
+    Scene S;
+    if (scene_init(&S, n, means, scales, quats, opacity, rgb, alpha_min)) return -1;
+    memset(g13, 0, sizeof(double) * 13 * (size_t)n);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < nr; ++r) {
+        float tmin = tmin_a ? tmin_a[r] : tmin_s, tmax = tmax_a ? tmax_a[r] : tmax_s;
+        RayResult R;
+        trace_ray(&S, orig + 3 * r, dirs + 3 * r, tmin, tmax, t_cut, &R);
+        backward_ray(&S, orig + 3 * r, dirs + 3 * r, &R, gC + 3 * r, gT[r], g13);
+        free(R.h);
+    }
+    scene_free(&S);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Environment map: luminance x sin(theta) distribution (Sec. 3.4.1, the      */
+/* environment-light proposal; piecewise-constant 2D sampling after Pharr)    */
+/* ------------------------------------------------------------------------ */
+
+/* marg [H+1] and cond [H, W+1]: cumulative sums in double, one row at a
+ * time from the left, divided by the total, rounded to float; the last entry
+ * of each table is exactly 1.  A row of zero weight gets a uniform table. */
+int orc_env_cdf(int H, int W, const float *rgb, float *marg, float *cond)
+{
+    double *rows = (double *)malloc(sizeof(double) * (size_t)H);
+    for (int i = 0; i < H; ++i) {
+        double st = sin(ORC_PI * (i + 0.5) / H);
+        double acc = 0.0;
+        float *cr = cond + (size_t)i * (W + 1);
+        double *tmp = (double *)malloc(sizeof(double) * (size_t)(W + 1));
+        tmp[0] = 0.0;
+        for (int j = 0; j < W; ++j) {
+            const float *p = rgb + ((size_t)i * W + j) * 3;
+            double lum = 0.2126 * (double)p[0] + 0.7152 * (double)p[1] + 0.0722 * (double)p[2];
+            acc += lum * st;
+            tmp[j + 1] = acc;
+        }
+        rows[i] = acc;
+        cr[0] = 0.0f;
+        for (int j = 1; j <= W; ++j)
+            cr[j] = acc > 0.0 ? (float)(tmp[j] / acc) : (float)((double)j / W);
+        cr[W] = 1.0f;
+        free(tmp);
+    }
+    double tot = 0.0;
+    for (int i = 0; i < H; ++i) tot += rows[i];
+    double acc = 0.0;
+    marg[0] = 0.0f;
+    for (int i = 0; i < H; ++i) {
+        acc += rows[i];
+        marg[i + 1] = tot > 0.0 ? (float)(acc / tot) : (float)((double)(i + 1) / H);
+    }
+    marg[H] = 1.0f;
+    free(rows);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11)                         */
+/* ------------------------------------------------------------------------ */
+
+static void philox(uint32_t ctr[4], uint32_t k0, uint32_t k1, uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    for (int r = 0; r < 10; ++r) {
+        uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* the two uniforms of sample j of pixel p in job `job` */
+static void uniforms(uint64_t seed, uint32_t pix, uint32_t j, uint32_t job, double *u1, double *u2)
+{
+    uint32_t ctr[4] = {pix, j, job, 0}, out[4];
+    philox(ctr, (uint32_t)seed, (uint32_t)(seed >> 32), out);
+    *u1 = (double)(out[0] >> 8) * (1.0 / 16777216.0);
+    *u2 = (double)(out[1] >> 8) * (1.0 / 16777216.0);
+}
+
+/* exported for the generator's statistical tests */
+void orc_philox(uint64_t seed, uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3, uint32_t *out)
+{
+    uint32_t ctr[4] = {c0, c1, c2, c3};
+    philox(ctr, (uint32_t)seed, (uint32_t)(seed >> 32), out);
+}
+
+/* ------------------------------------------------------------------------ */
+/* BRDF and proposals (Sec. 3.1 Eqs. brdf_decompose/brdf_specular; Sec. 3.4.1) */
+/* ------------------------------------------------------------------------ */
+
+static double dot3(const double a[3], const double b[3]) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+static void normalize3(double a[3])
+{
+    double l = sqrt(dot3(a, a));
+    a[0] /= l; a[1] /= l; a[2] /= l;
+}
+
+/* orthonormal basis around n (Duff et al., JCGT 2017) */
+static void onb(const double n[3], double b1[3], double b2[3])
+{
+    double sign = copysign(1.0, n[2]);
+    double a = -1.0 / (sign + n[2]);
+    double b = n[0] * n[1] * a;
+    b1[0] = 1.0 + sign * n[0] * n[0] * a; b1[1] = sign * b; b1[2] = -sign * n[0];
+    b2[0] = b; b2[1] = sign + n[1] * n[1] * a; b2[2] = -n[1];
+}
+
+static double ggx_D(double ndh, double a2)
+{
+    double t = ndh * ndh * (a2 - 1.0) + 1.0;
+    return a2 / (ORC_PI * t * t);
+}
+
+static double smith_G1(double ndv, double a2)
+{
+    return 2.0 * ndv / (ndv + sqrt(a2 + (1.0 - a2) * ndv * ndv));
+}
+
+/* f(wo, wi) for ndi > 0, ndo > 0 (per channel) */
+static void brdf(const double n[3], const double wo[3], const double wi[3], const double alb[3], double rough,
+                 double metal, double f[3])
+{
+    double ndi = dot3(n, wi), ndo = dot3(n, wo);
+    double h[3] = {wi[0] + wo[0], wi[1] + wo[1], wi[2] + wo[2]};
+    normalize3(h);
+    double ndh = dot3(n, h), idh = dot3(wi, h);
+    double a = rough * rough, a2 = a * a;
+    double D = ggx_D(ndh, a2);
+    double G = smith_G1(ndi, a2) * smith_G1(ndo, a2);
+    double x = 1.0 - idh;
+    if (x < 0.0) x = 0.0;
+    double x5 = x * x * x * x * x;
+    for (int c = 0; c < 3; ++c) {
+        double F0 = 0.04 * (1.0 - metal) + metal * alb[c];
+        double F = F0 + (1.0 - F0) * x5;
+        f[c] = (1.0 - metal) * alb[c] / ORC_PI + D * F * G / (4.0 * ndi * ndo);
+    }
+}
+
+typedef struct {
+    int H, W;
+    const float *rgb;
+    const float *marg, *cond;
+} Env;
+
+static void env_index(const Env *E, const double w[3], int *i, int *j, double *sin_t)
+{
+    double y = w[1] < -1.0 ? -1.0 : (w[1] > 1.0 ? 1.0 : w[1]);
+    double th = acos(y);
+    double ph = atan2(w[2], w[0]);
+    if (ph < 0.0) ph += 2.0 * ORC_PI;
+    int ii = (int)(th / ORC_PI * E->H), jj = (int)(ph / (2.0 * ORC_PI) * E->W);
+    *i = ii < E->H - 1 ? ii : E->H - 1;
+    *j = jj < E->W - 1 ? jj : E->W - 1;
+    if (*i < 0) *i = 0;
+    if (*j < 0) *j = 0;
+    *sin_t = sqrt(1.0 - y * y > 0.0 ? 1.0 - y * y : 0.0);
+}
+
+static double env_pdf(const Env *E, const double w[3])
+{
+    int i, j;
+    double st;
+    env_index(E, w, &i, &j, &st);
+    if (st <= 0.0) return 0.0;
+    const float *cr = E->cond + (size_t)i * (E->W + 1);
+    double pij = ((double)E->marg[i + 1] - (double)E->marg[i]) * ((double)cr[j + 1] - (double)cr[j]);
+    return pij * E->H * E->W / (2.0 * ORC_PI * ORC_PI * st);
+}
+
+static void env_radiance(const Env *E, const double w[3], double L[3])
+{
+    int i, j;
+    double st;
+    env_index(E, w, &i, &j, &st);
+    const float *p = E->rgb + ((size_t)i * E->W + j) * 3;
+    L[0] = p[0]; L[1] = p[1]; L[2] = p[2];
+}
+
+/* first k in [0,n) with cdf[k+1] > u (cdf[n] == 1 > u) */
+static int cdf_find(const float *cdf, int n, double u)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi) / 2;
+        if ((double)cdf[mid + 1] > u) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+static void sample_env(const Env *E, double u1, double u2, double w[3])
+{
+    int i = cdf_find(E->marg, E->H, u1);
+    double dv = (u1 - E->marg[i]) / ((double)E->marg[i + 1] - (double)E->marg[i]);
+    const float *cr = E->cond + (size_t)i * (E->W + 1);
+    int j = cdf_find(cr, E->W, u2);
+    double du = (u2 - cr[j]) / ((double)cr[j + 1] - (double)cr[j]);
+    double th = ORC_PI * (i + dv) / E->H, ph = 2.0 * ORC_PI * (j + du) / E->W;
+    w[0] = sin(th) * cos(ph); w[1] = cos(th); w[2] = sin(th) * sin(ph);
+}
+
+/* cosine-weighted direction (Malley: uniform disk lifted to the hemisphere) */
+static void sample_cos(const double n[3], double u1, double u2, double w[3])
+{
+    double b1[3], b2[3];
+    onb(n, b1, b2);
+    double r = sqrt(u1), ph = 2.0 * ORC_PI * u2;
+    double x = r * cos(ph), y = r * sin(ph), z = sqrt(1.0 - u1 > 0.0 ? 1.0 - u1 : 0.0);
+    for (int i = 0; i < 3; ++i) w[i] = x * b1[i] + y * b2[i] + z * n[i];
+}
+
+/* visible-normal GGX sample (Heitz, JCGT 2018), then mirror wo about h */
+static void sample_ggx(const double n[3], const double wo[3], double rough, double u1, double u2, double w[3])
+{
+    double b1[3], b2[3];
+    onb(n, b1, b2);
+    double a = rough * rough;
+    double vl[3] = {dot3(wo, b1), dot3(wo, b2), dot3(wo, n)};
+    double Vh[3] = {a * vl[0], a * vl[1], vl[2]};
+    normalize3(Vh);
+    double lensq = Vh[0] * Vh[0] + Vh[1] * Vh[1];
+    double T1[3] = {1.0, 0.0, 0.0};
+    if (lensq > 0.0) { double il = 1.0 / sqrt(lensq); T1[0] = -Vh[1] * il; T1[1] = Vh[0] * il; T1[2] = 0.0; }
+    double T2[3] = {Vh[1] * T1[2] - Vh[2] * T1[1], Vh[2] * T1[0] - Vh[0] * T1[2], Vh[0] * T1[1] - Vh[1] * T1[0]};
+    double r = sqrt(u1), ph = 2.0 * ORC_PI * u2;
+    double t1 = r * cos(ph), t2 = r * sin(ph);
+    double s = 0.5 * (1.0 + Vh[2]);
+    t2 = (1.0 - s) * sqrt(1.0 - t1 * t1) + s * t2;
+    double t3 = 1.0 - t1 * t1 - t2 * t2;
+    t3 = sqrt(t3 > 0.0 ? t3 : 0.0);
+    double Nh[3];
+    for (int i = 0; i < 3; ++i) Nh[i] = t1 * T1[i] + t2 * T2[i] + t3 * Vh[i];
+    double Ne[3] = {a * Nh[0], a * Nh[1], Nh[2] > 0.0 ? Nh[2] : 0.0};
+    normalize3(Ne);
+    double h[3];
+    for (int i = 0; i < 3; ++i) h[i] = Ne[0] * b1[i] + Ne[1] * b2[i] + Ne[2] * n[i];
+    double oh = dot3(wo, h);
+    for (int i = 0; i < 3; ++i) w[i] = 2.0 * oh * h[i] - wo[i];
+}
+
+/* mixture density q = (N_c p_c + N_g p_g + N_e p_e) / N_r at w (Sec. 3.4.1) */
+static double mixture_pdf(const Env *E, const double n[3], const double wo[3], double rough, const double w[3],
+                          int nc, int ng, int ne)
+{
+    double ndi = dot3(n, w), ndo = dot3(n, wo);
+    double pc = ndi > 0.0 ? ndi / ORC_PI : 0.0;
+    double pg = 0.0;
+    double h[3] = {w[0] + wo[0], w[1] + wo[1], w[2] + wo[2]};
+    double hl = sqrt(dot3(h, h));
+    if (hl > 0.0) {
+        h[0] /= hl; h[1] /= hl; h[2] /= hl;
+        double ndh = dot3(n, h);
+        if (ndh > 0.0 && dot3(wo, h) > 0.0) {
+            double a = rough * rough, a2 = a * a;
+            pg = smith_G1(ndo, a2) * ggx_D(ndh, a2) / (4.0 * ndo);
+        }
+    }
+    double pe = ne > 0 ? env_pdf(E, w) : 0.0;
+    return ((double)nc * pc + (double)ng * pg + (double)ne * pe) / (double)(nc + ng + ne);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exported: MIS shading of G-buffer pixels (Eqs. montecarlo, mis)           */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int nc, ng, ne;
+    uint64_t seed;
+    uint32_t job;
+    float tmin, tcut;
+} MisOpts;
+
+/* Sample j of pixel p: direction, weight f cos / q, incident radiance; and,
+ * when traced, the ray's hit list (caller frees R->h). Returns 1 if traced. */
+static int mis_sample(const Scene *S, const Env *E, const MisOpts *op, uint32_t pix, int j,
+                      const double x[3], const double n[3], const double wo[3], const double alb[3],
+                      double rough, double metal,
+                      double w_out[3], double wt[3], double Li[3], double *q_out, RayResult *R, float df_out[3])
+{
+    double u1, u2;
+    uniforms(op->seed, pix, (uint32_t)j, op->job, &u1, &u2);
+    double w[3];
+    if (j < op->nc) sample_cos(n, u1, u2, w);
+    else if (j < op->nc + op->ng) sample_ggx(n, wo, rough, u1, u2, w);
+    else sample_env(E, u1, u2, w);
+    for (int i = 0; i < 3; ++i) w_out[i] = w[i];
+    double ndi = dot3(n, w);
+    wt[0] = wt[1] = wt[2] = 0.0; Li[0] = Li[1] = Li[2] = 0.0; *q_out = 0.0;
+    if (!(ndi > 0.0)) return 0;
+    double q = mixture_pdf(E, n, wo, rough, w, op->nc, op->ng, op->ne);
+    *q_out = q;
+    float of[3] = {(float)x[0], (float)x[1], (float)x[2]};
+    float df[3] = {(float)w[0], (float)w[1], (float)w[2]};
+    for (int i = 0; i < 3; ++i) df_out[i] = df[i];
+    trace_ray(S, of, df, op->tmin, INFINITY, op->tcut, R);
+    double Le[3];
+    env_radiance(E, w, Le);
+    for (int c = 0; c < 3; ++c) Li[c] = R->C[c] + R->T * Le[c];
+    if (q > 0.0) {
+        double f[3];
+        brdf(n, wo, w, alb, rough, metal, f);
+        for (int c = 0; c < 3; ++c) wt[c] = f[c] * ndi / q;
+    }
+    return 1;
+}
+
+static void load_pixel(const float *gx, const float *gn, const float *gwo, const float *galb, int64_t p,
+                       double x[3], double n[3], double wo[3], double alb[3])
+{
+    for (int i = 0; i < 3; ++i) {
+        x[i] = gx[3 * p + i]; n[i] = gn[3 * p + i]; wo[i] = gwo[3 * p + i]; alb[i] = galb[3 * p + i];
+    }
+}
+
+/*
+ * Shade the pixels listed in pix [np] (indices into the G-buffer, which also
+ * seed the random counters).  out [np,3] = c_pbr.  Optional per-sample dump
+ * (spp = nc+ng+ne): dir [np,spp,3], q [np,spp], wt [np,spp,3] = f cos/q,
+ * Li [np,spp,3], traced [np,spp], margins [np,spp,4].
+ */
+int orc_render_mis(int64_t n, const float *means, const float *scales, const float *quats, const float *opacity,
+                   const float *rgb, float alpha_min,
+                   const float *gx, const float *gn, const float *gwo, const float *galb, const float *grough,
+                   const float *gmetal, const uint8_t *gvalid,
+                   int eH, int eW, const float *env_rgb, const float *marg, const float *cond,
+                   int nc, int ng, int ne, uint64_t seed, uint32_t job, float tmin, float tcut,
+                   int64_t np, const int64_t *pix, double *out,
+                   float *s_dir, double *s_q, double *s_wt, double *s_Li, uint8_t *s_traced, float *s_margin)
+{
+    Scene S;
+    if (scene_init(&S, n, means, scales, quats, opacity, rgb, alpha_min)) return -1;
+    Env E = {eH, eW, env_rgb, marg, cond};
+    MisOpts op = {nc, ng, ne, seed, job, tmin, tcut};
+    int spp = nc + ng + ne;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < np; ++k) {
+        int64_t p = pix[k];
+        double acc[3] = {0, 0, 0};
+        double x[3], nn[3], wo[3], alb[3];
+        load_pixel(gx, gn, gwo, galb, p, x, nn, wo, alb);
+        int ok = gvalid[p] && dot3(nn, wo) > 0.0;
+        for (int j = 0; j < spp; ++j) {
+            size_t si = (size_t)k * spp + j;
+            double w[3] = {0, 0, 0}, wt[3] = {0, 0, 0}, Li[3] = {0, 0, 0}, q = 0.0;
+            float df[3] = {0, 0, 0};
+            RayResult R;
+            R.h = NULL;
+            R.mg.r2 = R.mg.den = R.mg.tau = INFINITY;
+            R.tstop = INFINITY;
+            int traced = 0;
+            if (ok) {
+                traced = mis_sample(&S, &E, &op, (uint32_t)p, j, x, nn, wo, alb, grough[p], gmetal[p], w, wt, Li, &q,
+                                    &R, df);
+                for (int c = 0; c < 3; ++c) acc[c] += wt[c] * Li[c];
+            }
+            if (s_dir) for (int c = 0; c < 3; ++c) s_dir[3 * si + c] = (float)w[c];
+            if (s_q) s_q[si] = q;
+            if (s_wt) for (int c = 0; c < 3; ++c) s_wt[3 * si + c] = wt[c];
+            if (s_Li) for (int c = 0; c < 3; ++c) s_Li[3 * si + c] = Li[c];
+            if (s_traced) s_traced[si] = (uint8_t)traced;
+            if (s_margin) {
+                s_margin[4 * si + 0] = R.mg.r2; s_margin[4 * si + 1] = R.mg.den;
+                s_margin[4 * si + 2] = R.mg.tau; s_margin[4 * si + 3] = R.tstop;
+            }
+            free(R.h);
+        }
+        for (int c = 0; c < 3; ++c) out[3 * k + c] = acc[c] / (double)spp;
+    }
+    scene_free(&S);
+    return 0;
+}
+
+/* Gradient of sum_k grad[k] . c_pbr(pix[k]) w.r.t. the surfels; g13 [n,13]
+ * overwritten.  The samples are regenerated from the same counters. */
+int orc_render_mis_backward(int64_t n, const float *means, const float *scales, const float *quats,
+                            const float *opacity, const float *rgb, float alpha_min,
+                            const float *gx, const float *gn, const float *gwo, const float *galb,
+                            const float *grough, const float *gmetal, const uint8_t *gvalid,
+                            int eH, int eW, const float *env_rgb, const float *marg, const float *cond,
+                            int nc, int ng, int ne, uint64_t seed, uint32_t job, float tmin, float tcut,
+                            int64_t np, const int64_t *pix, const double *grad, double *g13)
+{
+    Scene S;
+    if (scene_init(&S, n, means, scales, quats, opacity, rgb, alpha_min)) return -1;
+    memset(g13, 0, sizeof(double) * 13 * (size_t)n);
+    Env E = {eH, eW, env_rgb, marg, cond};
+    MisOpts op = {nc, ng, ne, seed, job, tmin, tcut};
+    int spp = nc + ng + ne;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < np; ++k) {
+        int64_t p = pix[k];
+        double x[3], nn[3], wo[3], alb[3];
+        load_pixel(gx, gn, gwo, galb, p, x, nn, wo, alb);
+        if (!(gvalid[p] && dot3(nn, wo) > 0.0)) continue;
+        for (int j = 0; j < spp; ++j) {
+            double w[3], wt[3], Li[3], q;
+            float df[3];
+            RayResult R;
+            R.h = NULL;
+            if (mis_sample(&S, &E, &op, (uint32_t)p, j, x, nn, wo, alb, grough[p], gmetal[p], w, wt, Li, &q, &R, df)) {
+                /* c_pbr += wt * (C + T L_env) / spp */
+                double gC[3], Le[3];
+                env_radiance(&E, w, Le);
+                double gT = 0.0;
+                for (int c = 0; c < 3; ++c) {
+                    gC[c] = grad[3 * k + c] * wt[c] / (double)spp;
+                    gT += gC[c] * Le[c];
+                }
+                float of[3] = {(float)x[0], (float)x[1], (float)x[2]};
+                backward_ray(&S, of, df, &R, gC, gT, g13);
+            }
+            free(R.h);
+        }
+    }
+    scene_free(&S);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Exported pieces of the shading, for pinning them one by one               */
+/* ------------------------------------------------------------------------ */
+
+/* technique 0 = cosine, 1 = GGX (visible normals), 2 = environment;
+ * m directions from the uniforms u [m,2] at one shading point. */
+void orc_sample_dirs(int tech, const double *n, const double *wo, double rough, int eH, int eW,
+                     const float *env_rgb, const float *marg, const float *cond, int64_t m, const double *u,
+                     double *w)
+{
+    Env E = {eH, eW, env_rgb, marg, cond};
+    for (int64_t k = 0; k < m; ++k) {
+        if (tech == 0) sample_cos(n, u[2 * k], u[2 * k + 1], w + 3 * k);
+        else if (tech == 1) sample_ggx(n, wo, rough, u[2 * k], u[2 * k + 1], w + 3 * k);
+        else sample_env(&E, u[2 * k], u[2 * k + 1], w + 3 * k);
+    }
+}
+
+/* pdfs [m,3] = (p_c, p_g, p_e) at directions w [m,3], and the mixture
+ * q [m] for the allocation (nc, ng, ne). */
+void orc_pdfs(const double *n, const double *wo, double rough, int eH, int eW, const float *env_rgb,
+              const float *marg, const float *cond, int nc, int ng, int ne, int64_t m, const double *w,
+              double *p3, double *q)
+{
+    Env E = {eH, eW, env_rgb, marg, cond};
+    for (int64_t k = 0; k < m; ++k) {
+        const double *x = w + 3 * k;
+        if (p3) {
+            p3[3 * k + 0] = mixture_pdf(&E, n, wo, rough, x, 1, 0, 0);
+            p3[3 * k + 1] = mixture_pdf(&E, n, wo, rough, x, 0, 1, 0);
+            p3[3 * k + 2] = eH > 0 ? mixture_pdf(&E, n, wo, rough, x, 0, 0, 1) : 0.0;
+        }
+        if (q) q[k] = mixture_pdf(&E, n, wo, rough, x, nc, ng, ne);
+    }
+}
+
+/* f(wo, wi) [m,3] for directions wi [m,3] (zero below either horizon) */
+void orc_brdf(const double *n, const double *wo, const double *alb, double rough, double metal, int64_t m,
+              const double *wi, double *f)
+{
+    for (int64_t k = 0; k < m; ++k) {
+        const double *x = wi + 3 * k;
+        if (dot3(n, x) > 0.0 && dot3(n, wo) > 0.0) brdf(n, wo, x, alb, rough, metal, f + 3 * k);
+        else f[3 * k] = f[3 * k + 1] = f[3 * k + 2] = 0.0;
+    }
+}
+
+/* nearest-texel radiance [m,3] at directions w [m,3] */
+void orc_env_lookup(int eH, int eW, const float *env_rgb, int64_t m, const double *w, double *L)
+{
+    Env E = {eH, eW, env_rgb, NULL, NULL};
+    for (int64_t k = 0; k < m; ++k) env_radiance(&E, w + 3 * k, L + 3 * k);
+}
+
+/* Per ray: the depth where compositing ended (the last composited hit's
+ * depth if the ray stopped at T < T_cut, else t_max) and the number of
+ * composited hits.  Used by the work counter. */
+int orc_trace_extent(int64_t n, const float *means, const float *scales, const float *quats, const float *opacity,
+                     float alpha_min, int64_t nr, const float *orig, const float *dirs, float tmin, float tmax,
+                     float t_cut, float *t_term, int64_t *nhit)
+{
+    Scene S;
+    if (scene_init(&S, n, means, scales, quats, opacity, NULL, alpha_min)) return -1;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < nr; ++r) {
+        RayResult R;
+        trace_ray(&S, orig + 3 * r, dirs + 3 * r, tmin, tmax, t_cut, &R);
+        float T32 = 1.0f;
+        for (int64_t k = 0; k < R.K; ++k) T32 = T32 * (1.0f - S.s32[R.h[k].id].op * expf(-0.5f * R.h[k].r2));
+        int stopped = R.K > 0 && T32 < t_cut;
+        t_term[r] = stopped ? bitsf((uint32_t)(R.h[R.K - 1].key >> 32)) : tmax;
+        nhit[r] = R.K;
+        free(R.h);
+    }
+    scene_free(&S);
+    return 0;
+}

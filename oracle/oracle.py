@@ -1,0 +1,263 @@
+"""Python face of the CPU oracle (``liboracle.so``, plain C, OpenMP).
+
+TEST INFRASTRUCTURE: only the tests, the smoke check and the benchmark's CPU
+baseline leg import this module.  It never touches the GPU library and the
+GPU library never touches it.
+
+Every function takes numpy arrays (the seeded inputs) and returns numpy
+arrays in double precision.  See ``oracle.c`` for the equations each part
+follows and for the fixed single-precision decision order.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB = None
+
+P = C.c_void_p
+I64 = C.c_int64
+F = C.c_float
+
+
+def lib():
+    global _LIB
+    if _LIB is None:
+        path = os.path.join(HERE, "liboracle.so")
+        if not os.path.exists(path):
+            import importlib.util
+            spec = importlib.util.spec_from_file_location("oracle_build", os.path.join(HERE, "build.py"))
+            m = importlib.util.module_from_spec(spec)
+            spec.loader.exec_module(m)
+            m.build()
+        L = C.CDLL(path)
+        L.orc_trace.restype = C.c_int
+        L.orc_trace.argtypes = [I64, P, P, P, P, P, F, I64, P, P, P, P, F, F, F, P, P, P, P, P, I64, P, P, P]
+        L.orc_trace_backward.restype = C.c_int
+        L.orc_trace_backward.argtypes = [I64, P, P, P, P, P, F, I64, P, P, P, P, F, F, F, P, P, P]
+        L.orc_env_cdf.restype = C.c_int
+        L.orc_env_cdf.argtypes = [C.c_int, C.c_int, P, P, P]
+        L.orc_philox.restype = None
+        L.orc_philox.argtypes = [C.c_uint64, C.c_uint32, C.c_uint32, C.c_uint32, C.c_uint32, P]
+        L.orc_render_mis.restype = C.c_int
+        L.orc_render_mis.argtypes = ([I64, P, P, P, P, P, F] + [P] * 7 + [C.c_int, C.c_int, P, P, P] +
+                                     [C.c_int, C.c_int, C.c_int, C.c_uint64, C.c_uint32, F, F, I64, P, P] + [P] * 6)
+        L.orc_render_mis_backward.restype = C.c_int
+        L.orc_render_mis_backward.argtypes = ([I64, P, P, P, P, P, F] + [P] * 7 + [C.c_int, C.c_int, P, P, P] +
+                                              [C.c_int, C.c_int, C.c_int, C.c_uint64, C.c_uint32, F, F, I64, P, P, P])
+        if hasattr(L, "orc_count_work"):
+            L.orc_count_work.restype = C.c_int
+            L.orc_count_work.argtypes = [I64, P, P, P, P, P, F, F, I64, P, P, F, F, F, P, P, P]
+        _LIB = L
+    return _LIB
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _c(a, dt=np.float32):
+    return np.ascontiguousarray(np.asarray(a, dtype=dt))
+
+
+def _scene(s):
+    return [_c(s.means), _c(s.scales), _c(s.quats), _c(s.opacity), _c(s.rgb)]
+
+
+ALPHA_MIN = 1.0 / 255.0
+T_CUT = 1e-3
+
+# padding of the surfel bounding boxes used for the work counts (scene units)
+AABB_PAD = 1e-5
+
+
+def trace(s, origins, dirs, t_min=0.0, t_max=np.inf, t_cut=T_CUT, alpha_min=ALPHA_MIN, sky=(0.5, 0.5, 0.5),
+          cap=0):
+    """Brute-force Trace(r_o, r_d) for every ray.
+
+    Returns dict: C [R,3] (c_rt), T [R] (1 - o_rt), L [R,3] = C + T sky,
+    nhit [R] composited hits, margins [R,4], and with ``cap`` > 0 the
+    composited ids/depths ``ids``/``tau`` [R,cap] (-1 padded).
+    """
+    arrs = _scene(s)
+    o = _c(origins); d = _c(dirs)
+    R = o.shape[0]
+    tmin_a = _c(t_min) if np.ndim(t_min) else None
+    tmax_a = _c(t_max) if np.ndim(t_max) else None
+    sky_a = _c(sky)
+    out = dict(C=np.zeros((R, 3)), T=np.zeros(R), L=np.zeros((R, 3)), nhit=np.zeros(R, np.int32),
+               margins=np.zeros((R, 4), np.float32))
+    ids = np.zeros((R, max(cap, 1)), np.int32) if cap else None
+    tau = np.zeros((R, max(cap, 1)), np.float32) if cap else None
+    rc = lib().orc_trace(s.n, *map(_p, arrs), alpha_min, R, _p(o), _p(d), _p(tmin_a), _p(tmax_a),
+                         float(0.0 if tmin_a is not None else t_min), float(np.inf if tmax_a is not None else t_max),
+                         t_cut, _p(sky_a), _p(out["C"]), _p(out["T"]), _p(out["L"]), _p(out["nhit"]),
+                         cap, _p(ids), _p(tau), _p(out["margins"]))
+    assert rc == 0
+    if cap:
+        out["ids"] = ids; out["tau"] = tau
+    return out
+
+
+def trace_backward(s, origins, dirs, gC, gT, t_min=0.0, t_max=np.inf, t_cut=T_CUT, alpha_min=ALPHA_MIN):
+    """d/d(surfels) of sum_r gC_r . c_rt + gT_r T_fin; returns [N,13] double
+    (mean 3, scale 2, quat 4, opacity 1, rgb 3)."""
+    arrs = _scene(s)
+    o = _c(origins); d = _c(dirs)
+    R = o.shape[0]
+    tmin_a = _c(t_min) if np.ndim(t_min) else None
+    tmax_a = _c(t_max) if np.ndim(t_max) else None
+    gC = _c(gC, np.float64).reshape(R, 3); gT = _c(gT, np.float64).reshape(R)
+    g = np.zeros((s.n, 13))
+    rc = lib().orc_trace_backward(s.n, *map(_p, arrs), alpha_min, R, _p(o), _p(d), _p(tmin_a), _p(tmax_a),
+                                  float(0.0 if tmin_a is not None else t_min),
+                                  float(np.inf if tmax_a is not None else t_max), t_cut, _p(gC), _p(gT), _p(g))
+    assert rc == 0
+    return g
+
+
+def env_cdf(env_rgb):
+    """Marginal [H+1] and conditional [H,W+1] float32 tables of an [H,W,3] map."""
+    e = _c(env_rgb)
+    H, W = e.shape[:2]
+    marg = np.zeros(H + 1, np.float32)
+    cond = np.zeros((H, W + 1), np.float32)
+    lib().orc_env_cdf(H, W, _p(e), _p(marg), _p(cond))
+    return marg, cond
+
+
+def philox(seed, c0, c1, c2, c3):
+    out = np.zeros(4, np.uint32)
+    lib().orc_philox(seed, c0, c1, c2, c3, _p(out))
+    return out
+
+
+def _gb(gb):
+    return [_c(gb.x), _c(gb.n), _c(gb.wo), _c(gb.albedo), _c(gb.rough), _c(gb.metal), _c(gb.valid, np.uint8)]
+
+
+def render_mis(s, gb, env_rgb, split, seed, pix=None, job=0, t_min=1e-3, t_cut=T_CUT, alpha_min=ALPHA_MIN,
+               dump=False):
+    """c_pbr of the G-buffer pixels ``pix`` (default all).  With ``dump``,
+    also per-sample dir/q/wt/Li/traced/margins."""
+    nc, ng, ne = split
+    spp = nc + ng + ne
+    arrs = _scene(s)
+    g = _gb(gb)
+    e = _c(env_rgb)
+    marg, cond = env_cdf(e)
+    pix = np.arange(gb.npix, dtype=np.int64) if pix is None else _c(pix, np.int64)
+    npx = len(pix)
+    out = np.zeros((npx, 3))
+    d = {}
+    if dump:
+        d = dict(dir=np.zeros((npx, spp, 3), np.float32), q=np.zeros((npx, spp)), wt=np.zeros((npx, spp, 3)),
+                 Li=np.zeros((npx, spp, 3)), traced=np.zeros((npx, spp), np.uint8),
+                 margins=np.zeros((npx, spp, 4), np.float32))
+    rc = lib().orc_render_mis(s.n, *map(_p, arrs), alpha_min, *map(_p, g), e.shape[0], e.shape[1], _p(e), _p(marg),
+                              _p(cond), nc, ng, ne, seed, job, t_min, t_cut, npx, _p(pix), _p(out),
+                              _p(d.get("dir")), _p(d.get("q")), _p(d.get("wt")), _p(d.get("Li")),
+                              _p(d.get("traced")), _p(d.get("margins")))
+    assert rc == 0
+    if dump:
+        d["rgb"] = out
+        return d
+    return out
+
+
+def render_mis_backward(s, gb, env_rgb, split, seed, grad, pix=None, job=0, t_min=1e-3, t_cut=T_CUT,
+                        alpha_min=ALPHA_MIN):
+    """d/d(surfels) of sum_k grad[k] . c_pbr(pix[k]); returns [N,13] double."""
+    nc, ng, ne = split
+    arrs = _scene(s)
+    g = _gb(gb)
+    e = _c(env_rgb)
+    marg, cond = env_cdf(e)
+    pix = np.arange(gb.npix, dtype=np.int64) if pix is None else _c(pix, np.int64)
+    grad = _c(grad, np.float64).reshape(len(pix), 3)
+    out = np.zeros((s.n, 13))
+    rc = lib().orc_render_mis_backward(s.n, *map(_p, arrs), alpha_min, *map(_p, g), e.shape[0], e.shape[1], _p(e),
+                                       _p(marg), _p(cond), nc, ng, ne, seed, job, t_min, t_cut, len(pix), _p(pix),
+                                       _p(grad), _p(out))
+    assert rc == 0
+    return out
+
+
+def split_grads(g13):
+    """[N,13] -> dict of per-parameter gradient blocks."""
+    return dict(means=g13[:, 0:3], scales=g13[:, 3:5], quats=g13[:, 5:9], opacity=g13[:, 9], rgb=g13[:, 10:13])
+
+
+def count_work(s, origins, dirs, t_min=0.0, t_max=np.inf, t_cut=T_CUT, alpha_min=ALPHA_MIN, pad=AABB_PAD):
+    """Per-ray (N_cand, N_node, N_hit) on the reference LBVH (see workcount.c)."""
+    arrs = _scene(s)
+    o = _c(origins); d = _c(dirs)
+    R = o.shape[0]
+    nc = np.zeros(R, np.int64); nn = np.zeros(R, np.int64); nh = np.zeros(R, np.int64)
+    rc = lib().orc_count_work(s.n, *map(_p, arrs), alpha_min, pad, R, _p(o), _p(d), float(t_min), float(t_max),
+                              t_cut, _p(nc), _p(nn), _p(nh))
+    assert rc == 0
+    return nc, nn, nh
+
+
+def _d(a):
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _env_args(env_rgb):
+    if env_rgb is None:
+        return 0, 0, None, None, None
+    e = _c(env_rgb)
+    marg, cond = env_cdf(e)
+    return e.shape[0], e.shape[1], e, marg, cond
+
+
+def sample_dirs(tech, n, wo, rough, u, env_rgb=None):
+    """Directions from technique 0 (cosine), 1 (GGX visible normals), 2 (env) for uniforms u [m,2]."""
+    L = lib()
+    L.orc_sample_dirs.restype = None
+    L.orc_sample_dirs.argtypes = [C.c_int, P, P, C.c_double, C.c_int, C.c_int, P, P, P, I64, P, P]
+    eH, eW, e, marg, cond = _env_args(env_rgb)
+    u = _d(u).reshape(-1, 2)
+    w = np.zeros((len(u), 3))
+    L.orc_sample_dirs(tech, _p(_d(n)), _p(_d(wo)), rough, eH, eW, _p(e), _p(marg), _p(cond), len(u), _p(u), _p(w))
+    return w
+
+
+def pdfs(n, wo, rough, w, env_rgb=None, split=(1, 1, 1)):
+    """(p_c, p_g, p_e) [m,3] and the mixture q [m] at directions w [m,3]."""
+    L = lib()
+    L.orc_pdfs.restype = None
+    L.orc_pdfs.argtypes = [P, P, C.c_double, C.c_int, C.c_int, P, P, P, C.c_int, C.c_int, C.c_int, I64, P, P, P]
+    eH, eW, e, marg, cond = _env_args(env_rgb)
+    w = _d(w).reshape(-1, 3)
+    p3 = np.zeros((len(w), 3)); q = np.zeros(len(w))
+    if eH == 0:
+        split = (split[0], split[1], 0)
+    L.orc_pdfs(_p(_d(n)), _p(_d(wo)), rough, eH, eW, _p(e), _p(marg), _p(cond), split[0], split[1], split[2],
+               len(w), _p(w), _p(p3), _p(q))
+    return p3, q
+
+
+def brdf(n, wo, albedo, rough, metal, wi):
+    L = lib()
+    L.orc_brdf.restype = None
+    L.orc_brdf.argtypes = [P, P, P, C.c_double, C.c_double, I64, P, P]
+    wi = _d(wi).reshape(-1, 3)
+    f = np.zeros((len(wi), 3))
+    L.orc_brdf(_p(_d(n)), _p(_d(wo)), _p(_d(albedo)), rough, metal, len(wi), _p(wi), _p(f))
+    return f
+
+
+def env_lookup(env_rgb, w):
+    L = lib()
+    L.orc_env_lookup.restype = None
+    L.orc_env_lookup.argtypes = [C.c_int, C.c_int, P, I64, P, P]
+    e = _c(env_rgb)
+    w = _d(w).reshape(-1, 3)
+    out = np.zeros((len(w), 3))
+    L.orc_env_lookup(e.shape[0], e.shape[1], _p(e), len(w), _p(w), _p(out))
+    return out

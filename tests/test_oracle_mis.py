@@ -1,0 +1,219 @@
+"""Pins of the oracle's shading (Sec. 3.1 Eqs. brdf_decompose/brdf_specular,
+Sec. 3.3 Eq. montecarlo, Sec. 3.4.1 Eq. mis): random numbers against the
+generator's published known-answer vectors, every proposal pdf against
+quadrature on the sphere, every sampler against its pdf, and the MIS
+estimator's expectation against quadrature of the rendering integral."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2607_22780_amd import workloads as W
+
+
+def test_philox_known_answers():
+    """Philox-4x32-10 known-answer vectors (Salmon et al., SC'11; the
+    Random123 distribution's published test vectors)."""
+    cases = [
+        ((0, 0, 0, 0), (0, 0), (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
+        ((0xFFFFFFFF,) * 4, (0xFFFFFFFF, 0xFFFFFFFF), (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
+        ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
+         (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1)),
+    ]
+    for ctr, key, want in cases:
+        seed = key[0] | (key[1] << 32)
+        got = O.philox(seed, *ctr)
+        assert tuple(int(x) for x in got) == want
+
+
+def sphere_grid(nt, nph):
+    """Midpoint quadrature on the sphere in (cos theta, phi): equal-area cells."""
+    y = -1.0 + (np.arange(nt) + 0.5) * 2.0 / nt
+    ph = (np.arange(nph) + 0.5) * 2.0 * math.pi / nph
+    Y, PH = np.meshgrid(y, ph, indexing="ij")
+    s = np.sqrt(1.0 - Y ** 2)
+    w = np.stack([s * np.cos(PH), Y, s * np.sin(PH)], axis=-1).reshape(-1, 3)
+    return w, 4.0 * math.pi / (nt * nph)
+
+
+def shading_point(seed, tilt=0.6):
+    g = np.random.default_rng(seed)
+    n = g.standard_normal(3); n /= np.linalg.norm(n)
+    t = np.cross(n, g.standard_normal(3)); t /= np.linalg.norm(t)
+    wo = math.cos(tilt) * n + math.sin(tilt) * t
+    return n, wo
+
+
+@pytest.mark.parametrize("rough,tilt", [(1.0, 0.3), (0.6, 1.0), (0.4, 1.3)])
+def test_pdfs_integrate_to_one(rough, tilt):
+    n, wo = shading_point(7, tilt)
+    env = W.envmap(32, 64, seed=0)
+    w, dA = sphere_grid(1200, 2400)
+    p3, _ = O.pdfs(n, wo, rough, w, env_rgb=env)
+    tot = p3.sum(axis=0) * dA
+    np.testing.assert_allclose(tot[0], 1.0, atol=2e-3)
+    np.testing.assert_allclose(tot[1], 1.0, atol=5e-3)
+    np.testing.assert_allclose(tot[2], 1.0, atol=5e-3)
+
+
+def histogram_check(tech, rough=0.5, tilt=0.8, m=400_000, nt=24, nph=48, env=None):
+    """Sampled directions against the pdf integrated over equal-area bins."""
+    n, wo = shading_point(11, tilt)
+    u = np.random.default_rng(5).random((m, 2))
+    w = O.sample_dirs(tech, n, wo, rough, u, env_rgb=env)
+    np.testing.assert_allclose(np.linalg.norm(w, axis=1), 1.0, atol=1e-9)
+    bi = np.minimum(((w[:, 1] + 1.0) * 0.5 * nt).astype(int), nt - 1)
+    ph = np.mod(np.arctan2(w[:, 2], w[:, 0]), 2 * math.pi)
+    bj = np.minimum((ph / (2 * math.pi) * nph).astype(int), nph - 1)
+    counts = np.bincount(bi * nph + bj, minlength=nt * nph).astype(float)
+    sub = 16
+    wq, dA = sphere_grid(nt * sub, nph * sub)
+    p3, _ = O.pdfs(n, wo, rough, wq, env_rgb=env)
+    p = p3[:, tech].reshape(nt, sub, nph, sub).sum(axis=(1, 3)).reshape(-1) * dA
+    expect = p * m
+    sel = expect > 30
+    z = (counts[sel] - expect[sel]) / np.sqrt(expect[sel])
+    assert np.abs(z).max() < 6.0, np.abs(z).max()
+    assert abs(np.mean(z ** 2) - 1.0) < 0.3
+    assert counts[~sel].sum() < 1e-3 * m + 3 * math.sqrt(max(expect[~sel].sum(), 1.0)) + expect[~sel].sum()
+
+
+def test_cosine_sampler_matches_pdf():
+    histogram_check(0)
+
+
+@pytest.mark.parametrize("rough", [0.3, 0.8])
+def test_ggx_sampler_matches_pdf(rough):
+    histogram_check(1, rough=rough)
+
+
+def test_env_sampler_matches_definition():
+    """Texel frequencies of environment samples follow luminance x sin(theta_centre),
+    and within a texel the samples are uniform in (theta, phi)."""
+    H, Wd = 16, 32
+    env = W.envmap(H, Wd, seed=1)
+    m = 400_000
+    u = np.random.default_rng(8).random((m, 2))
+    w = O.sample_dirs(2, np.array([0, 1.0, 0]), np.array([0, 1.0, 0]), 0.5, u, env_rgb=env)
+    th = np.arccos(np.clip(w[:, 1], -1, 1)); ph = np.mod(np.arctan2(w[:, 2], w[:, 0]), 2 * math.pi)
+    fi = th / math.pi * H; fj = ph / (2 * math.pi) * Wd
+    i = np.minimum(fi.astype(int), H - 1); j = np.minimum(fj.astype(int), Wd - 1)
+    counts = np.bincount(i * Wd + j, minlength=H * Wd).astype(float)
+    lum = env.astype(np.float64) @ np.array([0.2126, 0.7152, 0.0722])
+    wgt = lum * np.sin(math.pi * (np.arange(H) + 0.5) / H)[:, None]
+    expect = (wgt / wgt.sum()).reshape(-1) * m
+    sel = expect > 30
+    z = (counts[sel] - expect[sel]) / np.sqrt(expect[sel])
+    assert np.abs(z).max() < 5.5 and abs(np.mean(z ** 2) - 1.0) < 0.3
+    # uniform offsets inside the texel
+    for frac in (fi - i, fj - j):
+        hist = np.bincount(np.minimum((frac * 10).astype(int), 9), minlength=10)
+        assert np.all(np.abs(hist - m / 10) < 6 * math.sqrt(m / 10))
+
+
+def test_env_cdf_constant_map():
+    """Constant radiance: row weights are sin(theta_i), columns are uniform."""
+    H, Wd = 16, 24
+    marg, cond = O.env_cdf(np.ones((H, Wd, 3), np.float32))
+    st = np.sin(math.pi * (np.arange(H) + 0.5) / H)
+    want = np.concatenate([[0.0], np.cumsum(st) / st.sum()])
+    np.testing.assert_allclose(marg, want, atol=1e-7)
+    np.testing.assert_allclose(cond, np.broadcast_to(np.arange(Wd + 1) / Wd, cond.shape), atol=1e-7)
+    assert marg[-1] == 1.0 and np.all(cond[:, -1] == 1.0)
+
+
+def test_env_single_bright_texel():
+    """All environment samples land in the only lit texel."""
+    H, Wd = 8, 16
+    env = np.zeros((H, Wd, 3), np.float32); env[3, 5] = 7.0
+    u = np.random.default_rng(0).random((2000, 2))
+    w = O.sample_dirs(2, np.array([0, 1.0, 0]), np.array([0, 1.0, 0]), 0.5, u, env_rgb=env)
+    th = np.arccos(np.clip(w[:, 1], -1, 1)); ph = np.mod(np.arctan2(w[:, 2], w[:, 0]), 2 * math.pi)
+    assert np.all(np.floor(th / math.pi * H) == 3) and np.all(np.floor(ph / (2 * math.pi) * Wd) == 5)
+    L = O.env_lookup(env, w)
+    assert np.all(L == 7.0)
+
+
+def test_brdf_special_values():
+    """Reciprocity f(wo,wi) = f(wi,wo); at wi = wo = n with m = 1:
+    f = D G F / 4 = a / (4 pi alpha_g^2) (F = F0 = a, G1(1) = 1)."""
+    n, wo = shading_point(3, 0.7)
+    g = np.random.default_rng(1)
+    wi = g.standard_normal((200, 3)); wi /= np.linalg.norm(wi, axis=1, keepdims=True)
+    wi = np.where((wi @ n)[:, None] > 0, wi, -wi)
+    a = np.array([0.9, 0.5, 0.2])
+    f1 = O.brdf(n, wo, a, 0.5, 0.3, wi)
+    f2 = np.stack([O.brdf(n, wi[k], a, 0.5, 0.3, wo[None])[0] for k in range(len(wi))])
+    np.testing.assert_allclose(f1, f2, rtol=1e-12)
+    for r in (0.3, 0.7):
+        f = O.brdf(n, n, a, r, 1.0, n[None])[0]
+        np.testing.assert_allclose(f, a / (4 * math.pi * r ** 4), rtol=1e-12)
+    # diffuse part only survives m = 0 at grazing-free, very rough: f >= (1-m) a / pi
+    f = O.brdf(n, wo, a, 1.0, 0.0, wi)
+    assert np.all(f >= a / math.pi - 1e-12)
+
+
+def gbuffer_const(npx, n, wo, albedo, rough, metal):
+    f = lambda a, shp: np.ascontiguousarray(np.broadcast_to(np.asarray(a, np.float32), shp))
+    return W.GBuffer(1, npx, f((0.0, 0.0, 0.0), (npx, 3)), f(n, (npx, 3)), f(wo, (npx, 3)), f(albedo, (npx, 3)),
+                     f(rough, (npx,)), f(metal, (npx,)), np.ones(npx, np.uint8))
+
+
+def empty_scene():
+    z = lambda *s: np.zeros(s, np.float32)
+    return W.Surfels(z(0, 3), z(0, 2), z(0, 4), z(0), z(0, 3))
+
+
+@pytest.mark.parametrize("rough,metal,tilt,use_env", [(0.7, 0.0, 0.5, False), (0.25, 1.0, 1.0, False),
+                                                      (0.5, 0.0, 0.8, True), (0.35, 1.0, 0.4, True)])
+def test_mis_estimator_is_unbiased(rough, metal, tilt, use_env):
+    """With no surfels, E[c_pbr] = integral of f L_env cos over the hemisphere,
+    here by quadrature; the per-pixel estimates (independent counters) must
+    average to it within 5 standard errors."""
+    n, wo = shading_point(21, tilt)
+    n32 = n.astype(np.float32).astype(np.float64); n32 /= np.linalg.norm(n32)
+    albedo = np.array([0.8, 0.5, 0.3])
+    env = W.envmap(32, 64, seed=2) if use_env else np.ones((8, 16, 3), np.float32)
+    npx = 2048
+    gb = gbuffer_const(npx, n, wo, albedo, rough, metal)
+    est = O.render_mis(empty_scene(), gb, env, (16, 8, 8), seed=99)
+    # quadrature
+    w, dA = sphere_grid(1500, 3000)
+    nn = gb.n[0].astype(np.float64); wwo = gb.wo[0].astype(np.float64)
+    ndi = w @ nn
+    keep = ndi > 0
+    f = O.brdf(nn, wwo, gb.albedo[0].astype(np.float64), float(gb.rough[0]), float(gb.metal[0]), w[keep])
+    L = O.env_lookup(env, w[keep])
+    truth = (f * L * ndi[keep, None]).sum(axis=0) * dA
+    mean = est.mean(axis=0); se = est.std(axis=0) / math.sqrt(npx)
+    assert np.all(np.abs(mean - truth) < 5 * se + 1e-3 * truth), (mean, truth, se)
+
+
+def test_cosine_only_weights():
+    """Cosine-only allocation: q = cos/pi, so every sample's weight is pi f."""
+    n, wo = shading_point(5, 0.5)
+    gb = gbuffer_const(16, n, wo, (0.6, 0.6, 0.6), 0.5, 0.0)
+    d = O.render_mis(empty_scene(), gb, np.ones((4, 8, 3), np.float32), (8, 0, 0), seed=3, dump=True)
+    for k in range(16):
+        for j in range(8):
+            if d["traced"][k, j]:
+                f = O.brdf(gb.n[k].astype(np.float64), gb.wo[k].astype(np.float64), (0.6, 0.6, 0.6), 0.5, 0.0,
+                           d["dir"][k, j].astype(np.float64)[None])[0]
+                np.testing.assert_allclose(d["wt"][k, j], math.pi * f, rtol=1e-5)
+                np.testing.assert_allclose(d["Li"][k, j], 1.0)
+
+
+def test_occluder_blocks_environment():
+    """A large opaque surfel over the shading point removes the environment:
+    L_i = c_rt for every sample that hits it (visibility 0)."""
+    n = np.array([0.0, 0.0, 1.0]); wo = np.array([0.0, 0.0, 1.0])
+    gb = gbuffer_const(8, n, wo, (0.5, 0.5, 0.5), 0.6, 0.0)
+    s = W.Surfels(np.array([[0, 0, 0.05]], np.float32), np.array([[1e4, 1e4]], np.float32),
+                  np.array([[1, 0, 0, 0]], np.float32), np.array([1.0], np.float32),
+                  np.array([[0.25, 0.5, 0.75]], np.float32))
+    d = O.render_mis(s, gb, np.full((8, 16, 3), 3.0, np.float32), (4, 2, 2), seed=1, dump=True)
+    tr = d["traced"].astype(bool)
+    assert tr.sum() > 0
+    np.testing.assert_allclose(d["Li"][tr], np.broadcast_to(np.float32([0.25, 0.5, 0.75]), d["Li"][tr].shape),
+                               rtol=1e-6)
