@@ -1,0 +1,264 @@
+/*
+ * grt.h -- C ABI of libgrt: differentiable 2D Gaussian ray tracing (2DGRT) of
+ * secondary rays with multiple-importance-sampled (MIS) shading, for AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The operations follow "Inter-Reflective Gaussian Splatting for Robust and
+ * Efficient Inverse Rendering" (IRGS++):
+ *   - a surfel is a 2D Gaussian disk (centre, tangents t_u, t_v, scales s_u,
+ *     s_v, opacity o, outgoing radiance c)            -- Sec. 3.1, "2D Gaussian splatting";
+ *   - Trace(r_o, r_d) -> (c_rt, o_rt) composites the ray's intersected
+ *     surfels front to back                           -- Sec. 3.2, Eq. raytracing_intersection, Eq. trace;
+ *   - L_i = V L_dir + L_ind with V = 1 - o_rt, L_ind = c_rt
+ *                                                      -- Sec. 3.3, Eqs. lighting_decompose, incident_trace;
+ *   - c_pbr = (1/N_r) sum g(w)/q(w) with the deterministic mixture q of a
+ *     cosine, a GGX and an environment proposal       -- Sec. 3.3 Eq. montecarlo, Sec. 3.4.1 Eq. mis;
+ *   - gradients flow back through the secondary-ray queries (Sec. 3.2).
+ *
+ * Conventions (every entry point):
+ *   - Return value: GRT_OK (0) or a negative GRT_ERR_* code; nothing throws or
+ *     aborts across the ABI.  grt_last_error() gives the message of the last
+ *     failure on the calling thread.
+ *   - Array arguments are DEVICE pointers to contiguous row-major float32
+ *     (uint8 for masks) unless stated, owned by the caller and borrowed only
+ *     until the work queued on `stream` has finished.  `stream` is a
+ *     hipStream_t passed as void* (NULL = the null stream).
+ *   - Calls are asynchronous on `stream`; a kernel fault surfaces as
+ *     GRT_ERR_DEVICE from a later call that synchronises.
+ *   - Device scratch is caller-allocated ("workspace"); the library allocates
+ *     device memory only inside the relighting server (from its budget).
+ *   - Surfel quaternions are (w, x, y, z) and need not be unit; t_u, t_v and
+ *     the normal n are the columns of the rotation matrix of q/|q|.
+ *   - A surfel is hit where the ray crosses its plane at t_min < tau <= t_max,
+ *     |n . d| >= 1e-6, and rho^2 = u^2 + v^2 <= min(9, 2 ln(o / alpha_min))
+ *     (three standard deviations and the minimum influence alpha_min).  Hits
+ *     are composited in ascending (tau, surfel id); compositing includes the
+ *     hit that takes the transmittance below t_cut and then stops.
+ */
+#ifndef GRT_H
+#define GRT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GRT_OK 0
+#define GRT_ERR_INVALID (-1)    /* bad argument, size or state */
+#define GRT_ERR_OOM (-2)        /* workspace too small / budget exhausted */
+#define GRT_ERR_NOT_BUILT (-3)  /* scene or environment used before its build call */
+#define GRT_ERR_DEVICE (-4)     /* a HIP runtime call failed */
+#define GRT_ERR_ADMISSION (-5)  /* server: job can never fit the memory budget */
+#define GRT_ERR_BUSY (-6)       /* server: queue full, retry later */
+#define GRT_ERR_CANCELLED (-7)  /* server: job was cancelled */
+#define GRT_ERR_TIMEOUT (-8)    /* server: wait timed out */
+
+typedef struct grt_ctx grt_ctx;
+typedef struct grt_scene grt_scene;
+typedef struct grt_env grt_env;
+typedef struct grt_server grt_server;
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *grt_last_error(void);
+/* Static name of a status code. */
+const char *grt_status_str(int status);
+/* Library version, (major << 16) | minor. */
+int grt_version(void);
+
+/* ---------------------------------------------------------------- context */
+
+/* Bind to HIP device `device`.  *out receives a handle freed by
+ * grt_ctx_destroy.  Fails with GRT_ERR_DEVICE if the device is absent. */
+int grt_ctx_create(int device, grt_ctx **out);
+int grt_ctx_destroy(grt_ctx *ctx);
+
+/* ------------------------------------------------------------------ scene */
+
+/* Surfel parameters, device pointers, SoA (Sec. 3.1 "2D Gaussian splatting";
+ * Sec. 3.2 "Bounding proxy and ray-splat intersection"):
+ *   means [n,3], scales [n,2] (s_u, s_v > 0, linear standard deviations),
+ *   quats [n,4] (w,x,y,z), opacity [n] in [0,1], rgb [n,3] outgoing radiance. */
+typedef struct {
+    int64_t n;
+    const float *means;
+    const float *scales;
+    const float *quats;
+    const float *opacity;
+    const float *rgb;
+} grt_surfels;
+
+/* Bytes of device workspace a scene of n surfels needs (records, bounding
+ * boxes, LBVH nodes, sort buffers).  256-byte aligned pointer required. */
+size_t grt_scene_workspace_bytes(int64_t n);
+
+/* Create a scene over borrowed surfel arrays and a caller-owned workspace of
+ * `ws_bytes` >= grt_scene_workspace_bytes(n).  alpha_min is the minimum
+ * influence (1/255 in the workloads; 0 keeps only the 3-sigma bound).  The
+ * scene is not usable until grt_scene_build.  n may be 0 (empty scene). */
+int grt_scene_create(grt_ctx *ctx, const grt_surfels *surfels, float alpha_min, void *workspace, size_t ws_bytes,
+                     grt_scene **out);
+
+/* Build the acceleration structure on `stream`: per-surfel frames and
+ * 3-sigma bounding boxes (the paper's adaptive bounding proxy, Eq.
+ * icosahedron_transform, as an axis-aligned box), then an LBVH (Morton codes
+ * of box centres, LSD radix sort, Karras hierarchy, bottom-up refit) -- the
+ * BVH the paper builds over its proxies (Sec. 3.2).  Reads the surfel arrays;
+ * call again after any parameter change. */
+int grt_scene_build(grt_scene *scene, void *stream);
+
+/* Re-point the scene at new surfel arrays of the same count (no build). */
+int grt_scene_set_surfels(grt_scene *scene, const grt_surfels *surfels);
+int grt_scene_destroy(grt_scene *scene);
+
+/* Device pointers into the built scene, for inspection by tests:
+ * records [n,16] float (sorted order; word 11 holds the surfel id as bits),
+ * nodes [max(n-1,0),16] (child boxes lo/hi as floats 0..11, children as
+ * int32 words 12,13: >= 0 internal node, < 0 leaf -(pos+1)), order [n]
+ * int32 (sorted position -> surfel id). */
+typedef struct {
+    int64_t n;
+    const float *records;
+    const float *nodes;
+    const int32_t *order;
+    const float *leaf_boxes; /* [n,6] lo.xyz, hi.xyz in sorted order */
+} grt_scene_view;
+int grt_scene_view_get(const grt_scene *scene, grt_scene_view *out);
+
+/* ------------------------------------------------------------------ trace */
+
+/* Rays (Sec. 3.2, r_o + tau r_d).  origins/dirs [n,3]; dirs unit length.
+ * t_min/t_max per ray [n] or NULL to use the scalars; 0 <= t_min < t_max. */
+typedef struct {
+    int64_t n;
+    const float *origins;
+    const float *dirs;
+    const float *t_min;
+    const float *t_max;
+    float t_min_all;
+    float t_max_all;
+} grt_rays;
+
+/* k: k-nearest hit buffer size per traversal round, one of 1,2,4,8,16,32
+ *    (results do not depend on k).
+ * t_cut: transmittance cutoff (1e-3 in the workloads).
+ * sky: radiance of escaped rays, L = c_rt + T sky.
+ * hit_ids/hit_tau: optional [n, hit_cap] dump of the composited hits in
+ *    order (surfel id, depth), -1 / 0 padded; NULL to skip. */
+typedef struct {
+    int k;
+    float t_cut;
+    float sky[3];
+    int32_t *hit_ids;
+    float *hit_tau;
+    int hit_cap;
+} grt_trace_opts;
+
+/* Trace(r_o, r_d) for every ray (Eq. trace):
+ *   out_rgb [n,3] = c_rt, out_T [n] = 1 - o_rt (transmittance after the last
+ *   composited hit), out_L [n,3] = c_rt + T sky (NULL to skip),
+ *   out_nhit [n] int32 composited hits (NULL to skip). */
+int grt_trace(const grt_scene *scene, const grt_rays *rays, const grt_trace_opts *opts, float *out_rgb,
+              float *out_T, float *out_L, int32_t *out_nhit, void *stream);
+
+/* Gradient accumulators (device, float32, ADDED to): means [n,3], scales
+ * [n,2], quats [n,4], opacity [n], rgb [n,3].  Gradients are w.r.t. the
+ * stored parameters (unnormalised quaternion, linear scales, opacity). */
+typedef struct {
+    float *means;
+    float *scales;
+    float *quats;
+    float *opacity;
+    float *rgb;
+} grt_surfel_grads;
+
+/* Backward of grt_trace by re-traversal (Sec. 3.2: gradients backpropagate
+ * through the traced radiance): accumulates d/d(surfels) of
+ *   sum_r grad_rgb[r] . c_rt(r) + grad_T[r] T(r)
+ * given the forward's fwd_rgb/fwd_T.  grad_T may be NULL (zero).  Same
+ * rays/opts as the forward (the dump fields are ignored). */
+int grt_trace_backward(const grt_scene *scene, const grt_rays *rays, const grt_trace_opts *opts,
+                       const float *fwd_rgb, const float *fwd_T, const float *grad_rgb, const float *grad_T,
+                       grt_surfel_grads *grads, void *stream);
+
+/* ------------------------------------------------------------ environment */
+
+/* Equirectangular environment L_dir (Sec. 3.3 "Light parametrization"):
+ * rgb [H,W,3] device; row 0 is the zenith (+y), texel (i,j) spans polar
+ * angle [pi i/H, pi (i+1)/H) and azimuth [2pi j/W, 2pi (j+1)/W), azimuth
+ * measured from +x towards +z.  Radiance lookups take the nearest texel. */
+size_t grt_env_workspace_bytes(int H, int W);
+int grt_env_create(grt_ctx *ctx, const float *rgb, int H, int W, void *workspace, size_t ws_bytes, grt_env **out);
+
+/* Build the environment proposal's tables (Sec. 3.4.1: drawn from the
+ * intensity distribution of the map, with the texel's solid angle): texel
+ * weight = Rec.709 luminance x sin(theta at the texel centre); per-row
+ * cumulative sums and the row marginal accumulated left to right in double,
+ * divided by the total and rounded to float; last entries exactly 1. */
+int grt_env_build(grt_env *env, void *stream);
+/* Device pointers to the built tables: marg [H+1], cond [H, W+1]. */
+int grt_env_tables(const grt_env *env, const float **marg, const float **cond);
+int grt_env_destroy(grt_env *env);
+
+/* ------------------------------------------------------------ MIS render */
+
+/* Deferred shading state per pixel (Sec. 3.3 "Shading state", Eq.
+ * deferred_maps): npix = H*W; x [npix,3] surface point, n [npix,3] unit
+ * normal, wo [npix,3] unit direction to the viewer, albedo [npix,3],
+ * rough [npix], metal [npix], valid [npix] uint8 (0 = background, shaded 0). */
+typedef struct {
+    int H, W;
+    const float *x;
+    const float *n;
+    const float *wo;
+    const float *albedo;
+    const float *rough;
+    const float *metal;
+    const uint8_t *valid;
+} grt_gbuffer;
+
+/* n_cos/n_ggx/n_env: the allocations N_c, N_g, N_e (Sec. 3.4.1; the paper's
+ * efficient setting is 16/8/8).  Sample j of pixel p uses the first two
+ * words of Philox-4x32-10 with key `seed` and counter (p, j, job, 0), as
+ * u = (word >> 8) 2^-24; j < N_c is cosine, then N_g GGX (visible normals,
+ * alpha = roughness^2), then N_e environment samples.
+ * t_min: self-intersection offset along the secondary ray (1e-3).
+ * sample_dump: optional [npix, spp, 10] floats per sample: direction (3),
+ *   mixture pdf q, weight f cos/q (3), incident radiance L_i (3); zeros for
+ *   samples below the horizon or invalid pixels. */
+typedef struct {
+    int n_cos, n_ggx, n_env;
+    uint64_t seed;
+    uint32_t job;
+    float t_min;
+    float t_cut;
+    int k;
+    float *sample_dump;
+} grt_mis_opts;
+
+/* Bytes of per-ray state the forward saves for grt_render_mis_backward. */
+size_t grt_render_saved_bytes(int64_t npix, int spp);
+
+/* c_pbr for every pixel (Eq. mis): out_rgb [npix,3] = (1/N_r) sum_j
+ * f(wo, w_j) L_i(w_j) (w_j . n) / q(w_j), L_i = c_rt + T L_env(w_j) from one
+ * secondary trace per sample above the horizon.  Per-pixel sums use a fixed
+ * order (results are reproducible run to run).  `saved` (device, >=
+ * grt_render_saved_bytes) receives what the backward needs, or NULL. */
+int grt_render_mis(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *opts,
+                   float *out_rgb, void *saved, void *stream);
+
+/* Backward of grt_render_mis by re-traversal: regenerates every sample from
+ * its counter, retraces, and accumulates d/d(surfels) of
+ * sum_p grad_rgb[p] . c_pbr(p) into `grads` (atomic adds; the order of the
+ * additions is not fixed).  `saved` must come from the forward with the same
+ * scene build, environment, G-buffer and opts. */
+int grt_render_mis_backward(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g,
+                            const grt_mis_opts *opts, const float *grad_rgb, const void *saved,
+                            grt_surfel_grads *grads, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRT_H */

@@ -149,7 +149,7 @@ static void scene_free(Scene *S) { free(S->s32); free(S->s64); }
 /* Decision in single precision (Eq. raytracing_intersection, then the 2D
  * Gaussian's local coordinates u, v).  Returns 1 on a hit and the depth; the
  * margins record how close each test came to its threshold. */
-typedef struct { float r2, den, tau; } Margin;
+typedef struct { float r2, den, tau, texel; } Margin;
 
 static int hit32(const Surf32 *s, const float o[3], const float d[3], float tmin, float tmax,
                  float *tau_out, float *r2_out, Margin *mg)
@@ -160,19 +160,30 @@ static int hit32(const Surf32 *s, const float o[3], const float d[3], float tmin
     if (fabsf(den) < 1e-6f) return 0;
     float num = s->n[0] * m0 + s->n[1] * m1 + s->n[2] * m2;
     float tau = num / den;
-    if (mg) {
-        float a = fabsf(tau - tmin);
-        if (a < mg->tau) mg->tau = a;
-    }
-    if (!(tau > tmin && tau <= tmax)) return 0;
+    int in_range = tau > tmin && tau <= tmax;
+    if (!in_range && !mg) return 0;
     float dx = tau * d[0] - m0, dy = tau * d[1] - m1, dz = tau * d[2] - m2;
     float u = s->au[0] * dx + s->au[1] * dy + s->au[2] * dz;
     float v = s->av[0] * dx + s->av[1] * dy + s->av[2] * dz;
     float r2 = u * u + v * v;
-    if (mg && s->r2max >= 0.0f) {
-        float a = fabsf(r2 - s->r2max);
-        if (a < mg->r2) mg->r2 = a;
+    if (mg && s->r2max >= 0.0f && r2 < 4.0f * s->r2max + 1.0f && tau > 0.0f) {
+        /* How far each decision is from flipping, expressed as the change of
+         * ray direction (radians, to first order) that would flip it.  Only
+         * crossings near the support count: far ones cannot flip. */
+        float amax = fmaxf(fmaxf(fabsf(s->au[0]), fabsf(s->au[1])), fmaxf(fabsf(s->au[2]),
+                     fmaxf(fmaxf(fabsf(s->av[0]), fabsf(s->av[1])), fabsf(s->av[2]))));
+        float ad = fabsf(den);
+        float sens = 2.0f * sqrtf(r2) * 1.7320508f * amax * tau * (1.0f + 1.0f / ad) + 1e-30f;
+        if (in_range) {
+            float a = fabsf(r2 - s->r2max) / sens;
+            if (a < mg->r2) mg->r2 = a;
+        }
+        if (r2 <= s->r2max) {
+            float b = fabsf(tau - tmin) * ad / tau;
+            if (b < mg->tau) mg->tau = b;
+        }
     }
+    if (!in_range) return 0;
     if (!(r2 <= s->r2max)) return 0;
     *tau_out = tau;
     *r2_out = r2;
@@ -226,7 +237,7 @@ static void trace_ray(const Scene *S, const float o[3], const float d[3], float 
 {
     int64_t cap = 64, nh = 0;
     Hit *h = (Hit *)malloc(sizeof(Hit) * (size_t)cap);
-    R->mg.r2 = INFINITY; R->mg.den = INFINITY; R->mg.tau = INFINITY;
+    R->mg.r2 = INFINITY; R->mg.den = INFINITY; R->mg.tau = INFINITY; R->mg.texel = INFINITY;
     for (int64_t i = 0; i < S->n; ++i) {
         float tau, r2;
         if (hit32(&S->s32[i], o, d, tmin, tmax, &tau, &r2, &R->mg)) {
@@ -339,8 +350,9 @@ static void backward_ray(const Scene *S, const float o[3], const float d[3], con
 /*
  * rays: origins/dirs [R,3] float; t_min/t_max per ray (or NULL: scalars).
  * outputs (any may be NULL): C [R,3], T [R], L [R,3], nhit [R] composited,
- * dump_id/dump_tau [R,cap] of composited hits in order, margins [R,4] =
- * (rho^2 margin, |den| margin, tau margin, relative stop margin).
+ * dump_id/dump_tau [R,cap] of composited hits in order, margins [R,5] =
+ * (support margin in radians of ray direction, |den| margin, tau margin,
+ * relative stop margin, environment texel margin (infinite here)).
  */
 int orc_trace(int64_t n, const float *means, const float *scales, const float *quats, const float *opacity,
               const float *rgb, float alpha_min,
@@ -369,8 +381,8 @@ int orc_trace(int64_t n, const float *means, const float *scales, const float *q
             }
         }
         if (margins) {
-            margins[4 * r + 0] = R.mg.r2; margins[4 * r + 1] = R.mg.den;
-            margins[4 * r + 2] = R.mg.tau; margins[4 * r + 3] = R.tstop;
+            margins[5 * r + 0] = R.mg.r2; margins[5 * r + 1] = R.mg.den;
+            margins[5 * r + 2] = R.mg.tau; margins[5 * r + 3] = R.tstop; margins[5 * r + 4] = R.mg.texel;
         }
         free(R.h);
     }
@@ -681,6 +693,16 @@ static int mis_sample(const Scene *S, const Env *E, const MisOpts *op, uint32_t 
     else sample_env(E, u1, u2, w);
     for (int i = 0; i < 3; ++i) w_out[i] = w[i];
     double ndi = dot3(n, w);
+    double texel = INFINITY;
+    {
+        double y = w[1] < -1.0 ? -1.0 : (w[1] > 1.0 ? 1.0 : w[1]);
+        double th = acos(y), ph = atan2(w[2], w[0]);
+        if (ph < 0.0) ph += 2.0 * ORC_PI;
+        double ft = th / ORC_PI * E->H, fp = ph / (2.0 * ORC_PI) * E->W;
+        double dt = fabs(ft - floor(ft + 0.5)) * ORC_PI / E->H;
+        double dp = fabs(fp - floor(fp + 0.5)) * 2.0 * ORC_PI / E->W * sin(th);
+        texel = dt < dp ? dt : dp;
+    }
     wt[0] = wt[1] = wt[2] = 0.0; Li[0] = Li[1] = Li[2] = 0.0; *q_out = 0.0;
     if (!(ndi > 0.0)) return 0;
     double q = mixture_pdf(E, n, wo, rough, w, op->nc, op->ng, op->ne);
@@ -689,6 +711,7 @@ static int mis_sample(const Scene *S, const Env *E, const MisOpts *op, uint32_t 
     float df[3] = {(float)w[0], (float)w[1], (float)w[2]};
     for (int i = 0; i < 3; ++i) df_out[i] = df[i];
     trace_ray(S, of, df, op->tmin, INFINITY, op->tcut, R);
+    R->mg.texel = (float)texel;
     double Le[3];
     env_radiance(E, w, Le);
     for (int c = 0; c < 3; ++c) Li[c] = R->C[c] + R->T * Le[c];
@@ -700,19 +723,27 @@ static int mis_sample(const Scene *S, const Env *E, const MisOpts *op, uint32_t 
     return 1;
 }
 
+/* The normal and the view direction are directions (Sec. 3.3, "Shading
+ * state": N sets the hemisphere and the cosine); they are normalised here, as
+ * single-precision storage leaves |n| = 1 +- 1e-7, which sharp GGX lobes
+ * (alpha^2 ~ 1e-5) would otherwise feel through 1 - (n.h)^2. */
 static void load_pixel(const float *gx, const float *gn, const float *gwo, const float *galb, int64_t p,
                        double x[3], double n[3], double wo[3], double alb[3])
 {
     for (int i = 0; i < 3; ++i) {
         x[i] = gx[3 * p + i]; n[i] = gn[3 * p + i]; wo[i] = gwo[3 * p + i]; alb[i] = galb[3 * p + i];
     }
+    if (dot3(n, n) > 0.0) normalize3(n);
+    if (dot3(wo, wo) > 0.0) normalize3(wo);
 }
 
 /*
  * Shade the pixels listed in pix [np] (indices into the G-buffer, which also
  * seed the random counters).  out [np,3] = c_pbr.  Optional per-sample dump
  * (spp = nc+ng+ne): dir [np,spp,3], q [np,spp], wt [np,spp,3] = f cos/q,
- * Li [np,spp,3], traced [np,spp], margins [np,spp,4].
+ * Li [np,spp,3], traced [np,spp], margins [np,spp,5] (as in orc_trace, the
+ * texel margin being the angle from the sampled direction to the nearest
+ * environment texel edge).
  */
 int orc_render_mis(int64_t n, const float *means, const float *scales, const float *quats, const float *opacity,
                    const float *rgb, float alpha_min,
@@ -741,7 +772,7 @@ int orc_render_mis(int64_t n, const float *means, const float *scales, const flo
             float df[3] = {0, 0, 0};
             RayResult R;
             R.h = NULL;
-            R.mg.r2 = R.mg.den = R.mg.tau = INFINITY;
+            R.mg.r2 = R.mg.den = R.mg.tau = R.mg.texel = INFINITY;
             R.tstop = INFINITY;
             int traced = 0;
             if (ok) {
@@ -755,8 +786,8 @@ int orc_render_mis(int64_t n, const float *means, const float *scales, const flo
             if (s_Li) for (int c = 0; c < 3; ++c) s_Li[3 * si + c] = Li[c];
             if (s_traced) s_traced[si] = (uint8_t)traced;
             if (s_margin) {
-                s_margin[4 * si + 0] = R.mg.r2; s_margin[4 * si + 1] = R.mg.den;
-                s_margin[4 * si + 2] = R.mg.tau; s_margin[4 * si + 3] = R.tstop;
+                s_margin[5 * si + 0] = R.mg.r2; s_margin[5 * si + 1] = R.mg.den;
+                s_margin[5 * si + 2] = R.mg.tau; s_margin[5 * si + 3] = R.tstop; s_margin[5 * si + 4] = R.mg.texel;
             }
             free(R.h);
         }

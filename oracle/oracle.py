@@ -79,7 +79,9 @@ def trace(s, origins, dirs, t_min=0.0, t_max=np.inf, t_cut=T_CUT, alpha_min=ALPH
     """Brute-force Trace(r_o, r_d) for every ray.
 
     Returns dict: C [R,3] (c_rt), T [R] (1 - o_rt), L [R,3] = C + T sky,
-    nhit [R] composited hits, margins [R,4], and with ``cap`` > 0 the
+    nhit [R] composited hits, margins [R,5] (support margin in radians of
+    ray direction, grazing margin, depth margin, relative cutoff margin,
+    environment texel margin), and with ``cap`` > 0 the
     composited ids/depths ``ids``/``tau`` [R,cap] (-1 padded).
     """
     arrs = _scene(s)
@@ -89,7 +91,7 @@ def trace(s, origins, dirs, t_min=0.0, t_max=np.inf, t_cut=T_CUT, alpha_min=ALPH
     tmax_a = _c(t_max) if np.ndim(t_max) else None
     sky_a = _c(sky)
     out = dict(C=np.zeros((R, 3)), T=np.zeros(R), L=np.zeros((R, 3)), nhit=np.zeros(R, np.int32),
-               margins=np.zeros((R, 4), np.float32))
+               margins=np.zeros((R, 5), np.float32))
     ids = np.zeros((R, max(cap, 1)), np.int32) if cap else None
     tau = np.zeros((R, max(cap, 1)), np.float32) if cap else None
     rc = lib().orc_trace(s.n, *map(_p, arrs), alpha_min, R, _p(o), _p(d), _p(tmin_a), _p(tmax_a),
@@ -156,7 +158,7 @@ def render_mis(s, gb, env_rgb, split, seed, pix=None, job=0, t_min=1e-3, t_cut=T
     if dump:
         d = dict(dir=np.zeros((npx, spp, 3), np.float32), q=np.zeros((npx, spp)), wt=np.zeros((npx, spp, 3)),
                  Li=np.zeros((npx, spp, 3)), traced=np.zeros((npx, spp), np.uint8),
-                 margins=np.zeros((npx, spp, 4), np.float32))
+                 margins=np.zeros((npx, spp, 5), np.float32))
     rc = lib().orc_render_mis(s.n, *map(_p, arrs), alpha_min, *map(_p, g), e.shape[0], e.shape[1], _p(e), _p(marg),
                               _p(cond), nc, ng, ne, seed, job, t_min, t_cut, npx, _p(pix), _p(out),
                               _p(d.get("dir")), _p(d.get("q")), _p(d.get("wt")), _p(d.get("Li")),

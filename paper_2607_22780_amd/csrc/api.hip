@@ -1,0 +1,413 @@
+// api.hip -- the extern "C" entry points of libgrt: argument checks, handle
+// bookkeeping and kernel dispatch.  No exception or abort crosses the ABI.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "grt_internal.h"
+
+struct grt_scene {
+    grt_ctx *ctx;
+    grt_surfels s;
+    float alpha_min;
+    void *ws;
+    size_t ws_bytes;
+    grt::SceneWS w;
+    bool built;
+};
+
+struct grt_env {
+    grt_ctx *ctx;
+    const float *rgb;
+    int H, W;
+    grt::EnvWS w;
+    bool built;
+};
+
+namespace {
+
+thread_local char g_err[512] = "";
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    return fail(GRT_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+grt::SceneDev scene_dev(const grt_scene *s)
+{
+    grt::SceneDev d;
+    d.rec = s->w.rec;
+    d.col = s->w.col;
+    d.nodes = s->w.nodes;
+    d.n = (int32_t)s->s.n;
+    return d;
+}
+
+int check_rays(const grt_rays *r)
+{
+    if (!r) return fail(GRT_ERR_INVALID, "rays is NULL");
+    if (r->n < 0 || r->n > (int64_t)1 << 40) return fail(GRT_ERR_INVALID, "ray count %lld out of range", (long long)r->n);
+    if (r->n > 0 && (!r->origins || !r->dirs)) return fail(GRT_ERR_INVALID, "ray origins/dirs NULL");
+    if (!r->t_min && !(r->t_min_all >= 0.0f)) return fail(GRT_ERR_INVALID, "t_min must be >= 0");
+    if (!r->t_min && !r->t_max && !(r->t_max_all > r->t_min_all))
+        return fail(GRT_ERR_INVALID, "t_max must exceed t_min");
+    return GRT_OK;
+}
+
+int check_k(int k)
+{
+    if (k == 1 || k == 2 || k == 4 || k == 8 || k == 16 || k == 32) return GRT_OK;
+    return fail(GRT_ERR_INVALID, "k = %d is not one of 1,2,4,8,16,32", k);
+}
+
+int check_scene(const grt_scene *s)
+{
+    if (!s) return fail(GRT_ERR_INVALID, "scene is NULL");
+    if (!s->built) return fail(GRT_ERR_NOT_BUILT, "scene used before grt_scene_build");
+    return GRT_OK;
+}
+
+int check_grads(const grt_surfel_grads *g, int64_t n)
+{
+    if (!g) return fail(GRT_ERR_INVALID, "grads is NULL");
+    if (n > 0 && (!g->means || !g->scales || !g->quats || !g->opacity || !g->rgb))
+        return fail(GRT_ERR_INVALID, "a gradient accumulator is NULL");
+    return GRT_OK;
+}
+
+grt::GradPtrs grad_ptrs(const grt_scene *s, const grt_surfel_grads *g)
+{
+    grt::GradPtrs p;
+    p.means = g->means; p.scales = g->scales; p.quats = g->quats; p.opacity = g->opacity; p.rgb = g->rgb;
+    p.order = nullptr;
+    p.p_scales = s->s.scales;
+    p.p_quats = s->s.quats;
+    return p;
+}
+
+int set_device(grt_ctx *c)
+{
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    return GRT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *grt_last_error(void) { return g_err; }
+
+const char *grt_status_str(int status)
+{
+    switch (status) {
+    case GRT_OK: return "GRT_OK";
+    case GRT_ERR_INVALID: return "GRT_ERR_INVALID";
+    case GRT_ERR_OOM: return "GRT_ERR_OOM";
+    case GRT_ERR_NOT_BUILT: return "GRT_ERR_NOT_BUILT";
+    case GRT_ERR_DEVICE: return "GRT_ERR_DEVICE";
+    case GRT_ERR_ADMISSION: return "GRT_ERR_ADMISSION";
+    case GRT_ERR_BUSY: return "GRT_ERR_BUSY";
+    case GRT_ERR_CANCELLED: return "GRT_ERR_CANCELLED";
+    case GRT_ERR_TIMEOUT: return "GRT_ERR_TIMEOUT";
+    default: return "GRT_ERR_UNKNOWN";
+    }
+}
+
+int grt_version(void) { return (1 << 16) | 0; }
+
+int grt_ctx_create(int device, grt_ctx **out)
+{
+    if (!out) return fail(GRT_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= count) return fail(GRT_ERR_DEVICE, "device %d not present (%d devices)", device, count);
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    grt_ctx *c = new (std::nothrow) grt_ctx;
+    if (!c) return fail(GRT_ERR_OOM, "host allocation failed");
+    c->device = device;
+    c->num_cu = prop.multiProcessorCount;
+    *out = c;
+    return GRT_OK;
+}
+
+int grt_ctx_destroy(grt_ctx *ctx)
+{
+    delete ctx;
+    return GRT_OK;
+}
+
+size_t grt_scene_workspace_bytes(int64_t n)
+{
+    if (n < 0) return 0;
+    return grt::carve_scene(nullptr, n).bytes;
+}
+
+static int check_surfels(const grt_surfels *s)
+{
+    if (!s) return fail(GRT_ERR_INVALID, "surfels is NULL");
+    if (s->n < 0 || s->n > 0x7fffffff) return fail(GRT_ERR_INVALID, "surfel count %lld out of range", (long long)s->n);
+    if (s->n > 0 && (!s->means || !s->scales || !s->quats || !s->opacity || !s->rgb))
+        return fail(GRT_ERR_INVALID, "a surfel array is NULL");
+    if (s->quats && !aligned(s->quats, 16)) return fail(GRT_ERR_INVALID, "quats must be 16-byte aligned");
+    return GRT_OK;
+}
+
+int grt_scene_create(grt_ctx *ctx, const grt_surfels *surfels, float alpha_min, void *workspace, size_t ws_bytes,
+                     grt_scene **out)
+{
+    if (!ctx || !out) return fail(GRT_ERR_INVALID, "ctx/out is NULL");
+    *out = nullptr;
+    int rc = check_surfels(surfels);
+    if (rc) return rc;
+    if (!(alpha_min >= 0.0f && alpha_min < 1.0f)) return fail(GRT_ERR_INVALID, "alpha_min must be in [0,1)");
+    size_t need = grt_scene_workspace_bytes(surfels->n);
+    if (!workspace || ws_bytes < need)
+        return fail(GRT_ERR_OOM, "scene workspace of %zu bytes < %zu needed", ws_bytes, need);
+    if (!aligned(workspace, 256)) return fail(GRT_ERR_INVALID, "workspace must be 256-byte aligned");
+    grt_scene *s = new (std::nothrow) grt_scene;
+    if (!s) return fail(GRT_ERR_OOM, "host allocation failed");
+    s->ctx = ctx;
+    s->s = *surfels;
+    s->alpha_min = alpha_min;
+    s->ws = workspace;
+    s->ws_bytes = ws_bytes;
+    s->w = grt::carve_scene(workspace, surfels->n);
+    s->built = false;
+    *out = s;
+    return GRT_OK;
+}
+
+int grt_scene_set_surfels(grt_scene *scene, const grt_surfels *surfels)
+{
+    if (!scene) return fail(GRT_ERR_INVALID, "scene is NULL");
+    int rc = check_surfels(surfels);
+    if (rc) return rc;
+    if (surfels->n != scene->s.n) return fail(GRT_ERR_INVALID, "surfel count changed (%lld -> %lld)",
+                                              (long long)scene->s.n, (long long)surfels->n);
+    scene->s = *surfels;
+    scene->built = false;
+    return GRT_OK;
+}
+
+int grt_scene_build(grt_scene *scene, void *stream)
+{
+    if (!scene) return fail(GRT_ERR_INVALID, "scene is NULL");
+    int rc = set_device(scene->ctx);
+    if (rc) return rc;
+    hipError_t e = grt::launch_scene_build(scene->s, scene->alpha_min, scene->w, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "scene build launch");
+    scene->built = true;
+    return GRT_OK;
+}
+
+int grt_scene_destroy(grt_scene *scene)
+{
+    delete scene;
+    return GRT_OK;
+}
+
+int grt_scene_view_get(const grt_scene *scene, grt_scene_view *out)
+{
+    if (!scene || !out) return fail(GRT_ERR_INVALID, "scene/out is NULL");
+    out->n = scene->s.n;
+    out->records = reinterpret_cast<const float *>(scene->w.rec);
+    out->nodes = reinterpret_cast<const float *>(scene->w.nodes);
+    out->order = reinterpret_cast<const int32_t *>(scene->w.vals0);
+    out->leaf_boxes = scene->w.leaf_box;
+    return GRT_OK;
+}
+
+static int fill_trace_args(const grt_scene *scene, const grt_rays *rays, const grt_trace_opts *opts,
+                           grt::TraceArgs &a)
+{
+    int rc = check_scene(scene);
+    if (rc) return rc;
+    if ((rc = check_rays(rays))) return rc;
+    if (!opts) return fail(GRT_ERR_INVALID, "opts is NULL");
+    if ((rc = check_k(opts->k))) return rc;
+    if (!(opts->t_cut >= 0.0f && opts->t_cut < 1.0f)) return fail(GRT_ERR_INVALID, "t_cut must be in [0,1)");
+    memset(&a, 0, sizeof(a));
+    a.S = scene_dev(scene);
+    a.n = rays->n;
+    a.o = rays->origins; a.d = rays->dirs;
+    a.tmin_a = rays->t_min; a.tmax_a = rays->t_max;
+    a.tmin = rays->t_min_all; a.tmax = rays->t_max_all;
+    a.tcut = opts->t_cut;
+    for (int c = 0; c < 3; ++c) a.sky[c] = opts->sky[c];
+    return GRT_OK;
+}
+
+int grt_trace(const grt_scene *scene, const grt_rays *rays, const grt_trace_opts *opts, float *out_rgb, float *out_T,
+              float *out_L, int32_t *out_nhit, void *stream)
+{
+    grt::TraceArgs a;
+    int rc = fill_trace_args(scene, rays, opts, a);
+    if (rc) return rc;
+    if (rays->n > 0 && (!out_rgb || !out_T)) return fail(GRT_ERR_INVALID, "out_rgb/out_T is NULL");
+    if (opts->hit_ids && (!opts->hit_tau || opts->hit_cap <= 0))
+        return fail(GRT_ERR_INVALID, "hit dump needs hit_tau and hit_cap > 0");
+    a.out_rgb = out_rgb; a.out_T = out_T; a.out_L = out_L; a.out_nhit = out_nhit;
+    a.dump_id = opts->hit_ids; a.dump_tau = opts->hit_tau; a.cap = opts->hit_ids ? opts->hit_cap : 0;
+    if ((rc = set_device(scene->ctx))) return rc;
+    hipError_t e = grt::launch_trace(a, opts->k, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "trace launch");
+    return GRT_OK;
+}
+
+int grt_trace_backward(const grt_scene *scene, const grt_rays *rays, const grt_trace_opts *opts, const float *fwd_rgb,
+                       const float *fwd_T, const float *grad_rgb, const float *grad_T, grt_surfel_grads *grads,
+                       void *stream)
+{
+    grt::TraceBwdArgs b;
+    int rc = fill_trace_args(scene, rays, opts, b.f);
+    if (rc) return rc;
+    if (rays->n > 0 && (!fwd_rgb || !fwd_T || !grad_rgb)) return fail(GRT_ERR_INVALID, "fwd_rgb/fwd_T/grad_rgb NULL");
+    if ((rc = check_grads(grads, scene->s.n))) return rc;
+    b.fwd_rgb = fwd_rgb; b.fwd_T = fwd_T; b.grad_rgb = grad_rgb; b.grad_T = grad_T;
+    b.g = grad_ptrs(scene, grads);
+    if ((rc = set_device(scene->ctx))) return rc;
+    hipError_t e = grt::launch_trace_backward(b, opts->k, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "trace backward launch");
+    return GRT_OK;
+}
+
+size_t grt_env_workspace_bytes(int H, int W)
+{
+    if (H <= 0 || W <= 0) return 0;
+    return grt::carve_env(nullptr, H, W).bytes;
+}
+
+int grt_env_create(grt_ctx *ctx, const float *rgb, int H, int W, void *workspace, size_t ws_bytes, grt_env **out)
+{
+    if (!ctx || !out) return fail(GRT_ERR_INVALID, "ctx/out is NULL");
+    *out = nullptr;
+    if (H <= 0 || W <= 0 || (int64_t)H * W > ((int64_t)1 << 28)) return fail(GRT_ERR_INVALID, "bad env size %dx%d", H, W);
+    if (!rgb) return fail(GRT_ERR_INVALID, "env rgb is NULL");
+    size_t need = grt_env_workspace_bytes(H, W);
+    if (!workspace || ws_bytes < need) return fail(GRT_ERR_OOM, "env workspace of %zu bytes < %zu needed", ws_bytes, need);
+    if (!aligned(workspace, 256)) return fail(GRT_ERR_INVALID, "workspace must be 256-byte aligned");
+    grt_env *e = new (std::nothrow) grt_env;
+    if (!e) return fail(GRT_ERR_OOM, "host allocation failed");
+    e->ctx = ctx;
+    e->rgb = rgb;
+    e->H = H; e->W = W;
+    e->w = grt::carve_env(workspace, H, W);
+    e->built = false;
+    *out = e;
+    return GRT_OK;
+}
+
+int grt_env_build(grt_env *env, void *stream)
+{
+    if (!env) return fail(GRT_ERR_INVALID, "env is NULL");
+    int rc = set_device(env->ctx);
+    if (rc) return rc;
+    hipError_t e = grt::launch_env_build(env->rgb, env->H, env->W, env->w, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "env build launch");
+    env->built = true;
+    return GRT_OK;
+}
+
+int grt_env_tables(const grt_env *env, const float **marg, const float **cond)
+{
+    if (!env || !marg || !cond) return fail(GRT_ERR_INVALID, "NULL argument");
+    *marg = env->w.marg;
+    *cond = env->w.cond;
+    return GRT_OK;
+}
+
+int grt_env_destroy(grt_env *env)
+{
+    delete env;
+    return GRT_OK;
+}
+
+size_t grt_render_saved_bytes(int64_t npix, int spp)
+{
+    if (npix < 0 || spp <= 0) return 0;
+    return (size_t)npix * (size_t)spp * 16u;
+}
+
+static int fill_render_args(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *o,
+                            grt::RenderArgs &a)
+{
+    int rc = check_scene(scene);
+    if (rc) return rc;
+    if (!env) return fail(GRT_ERR_INVALID, "env is NULL");
+    if (!env->built) return fail(GRT_ERR_NOT_BUILT, "environment used before grt_env_build");
+    if (!g || !o) return fail(GRT_ERR_INVALID, "gbuffer/opts is NULL");
+    if (g->H < 0 || g->W < 0 || (int64_t)g->H * g->W > 0x7fffffff) return fail(GRT_ERR_INVALID, "bad G-buffer size");
+    if ((int64_t)g->H * g->W > 0 && (!g->x || !g->n || !g->wo || !g->albedo || !g->rough || !g->metal || !g->valid))
+        return fail(GRT_ERR_INVALID, "a G-buffer array is NULL");
+    if (o->n_cos < 0 || o->n_ggx < 0 || o->n_env < 0 || o->n_cos + o->n_ggx + o->n_env <= 0 ||
+        o->n_cos + o->n_ggx + o->n_env > 65536)
+        return fail(GRT_ERR_INVALID, "bad sample allocation %d/%d/%d", o->n_cos, o->n_ggx, o->n_env);
+    if ((rc = check_k(o->k))) return rc;
+    if (!(o->t_min >= 0.0f)) return fail(GRT_ERR_INVALID, "t_min must be >= 0");
+    if (!(o->t_cut >= 0.0f && o->t_cut < 1.0f)) return fail(GRT_ERR_INVALID, "t_cut must be in [0,1)");
+    memset(&a, 0, sizeof(a));
+    a.S = scene_dev(scene);
+    a.E.H = env->H; a.E.W = env->W; a.E.rgb = env->rgb; a.E.marg = env->w.marg; a.E.cond = env->w.cond;
+    a.H = g->H; a.W = g->W;
+    a.x = g->x; a.n = g->n; a.wo = g->wo; a.alb = g->albedo; a.rough = g->rough; a.metal = g->metal; a.valid = g->valid;
+    a.nc = o->n_cos; a.ng = o->n_ggx; a.ne = o->n_env;
+    a.seed = o->seed; a.job = o->job;
+    a.tmin = o->t_min; a.tcut = o->t_cut;
+    return GRT_OK;
+}
+
+int grt_render_mis(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *opts,
+                   float *out_rgb, void *saved, void *stream)
+{
+    grt::RenderArgs a;
+    int rc = fill_render_args(scene, env, g, opts, a);
+    if (rc) return rc;
+    if ((int64_t)g->H * g->W > 0 && !out_rgb) return fail(GRT_ERR_INVALID, "out_rgb is NULL");
+    if (saved && !aligned(saved, 16)) return fail(GRT_ERR_INVALID, "saved must be 16-byte aligned");
+    a.out = out_rgb;
+    a.saved = reinterpret_cast<float4 *>(saved);
+    a.dump = opts->sample_dump;
+    if ((rc = set_device(scene->ctx))) return rc;
+    hipError_t e = grt::launch_render(a, opts->k, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "render launch");
+    return GRT_OK;
+}
+
+int grt_render_mis_backward(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *opts,
+                            const float *grad_rgb, const void *saved, grt_surfel_grads *grads, void *stream)
+{
+    grt::RenderArgs a;
+    int rc = fill_render_args(scene, env, g, opts, a);
+    if (rc) return rc;
+    if ((int64_t)g->H * g->W > 0 && (!grad_rgb || !saved)) return fail(GRT_ERR_INVALID, "grad_rgb/saved is NULL");
+    if (saved && !aligned(saved, 16)) return fail(GRT_ERR_INVALID, "saved must be 16-byte aligned");
+    if ((rc = check_grads(grads, scene->s.n))) return rc;
+    a.grad = grad_rgb;
+    a.saved = const_cast<float4 *>(reinterpret_cast<const float4 *>(saved));
+    a.g = grad_ptrs(scene, grads);
+    if ((rc = set_device(scene->ctx))) return rc;
+    hipError_t e = grt::launch_render_backward(a, opts->k, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "render backward launch");
+    return GRT_OK;
+}
+
+}  // extern "C"

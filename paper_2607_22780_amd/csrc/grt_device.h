@@ -1,0 +1,251 @@
+// grt_device.h -- device-side data layout and the shared traversal of libgrt.
+//
+// Scene layout in the caller's workspace (all in Morton order of the surfel
+// bounding-box centres, so neighbouring surfels sit in neighbouring lines):
+//   rec  [n][4] float4   r0 = (mu.xyz, r2max)      r1 = (n.xyz, opacity)
+//                        r2 = (a_u.xyz, id bits)   r3 = (a_v.xyz, 0)
+//                        with a_u = t_u / s_u, a_v = t_v / s_v      (64 B)
+//   col  [n]    float4   (rgb, 0)                                    (16 B)
+//   node [n-1]  Node     both child boxes + child references        (64 B)
+// A child reference >= 0 is an internal node, < 0 is leaf -(pos+1).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace grt {
+
+constexpr int kStack = 64;        // LBVH depth <= 62 (30-bit codes + 32-bit index tie-break)
+constexpr float kGrazing = 1e-6f; // |n . d| below this is no intersection
+constexpr float kPad = 1e-5f;     // absolute padding of surfel boxes (scene units)
+
+struct alignas(16) Node {
+    float4 a;  // L.lo.x L.lo.y L.lo.z L.hi.x
+    float4 b;  // L.hi.y L.hi.z R.lo.x R.lo.y
+    float4 c;  // R.lo.z R.hi.x R.hi.y R.hi.z
+    int4 d;    // left, right, unused, unused
+};
+
+struct SceneDev {
+    const float4 *rec;
+    const float4 *col;
+    const Node *nodes;
+    int32_t n;
+};
+
+// ---------------------------------------------------------------------------
+// Canonical single-precision arithmetic of the hit decision.  The operation
+// order is fixed and contraction is off, so the decision, the depth and the
+// (depth, id) order are reproducible bit for bit by any IEEE implementation
+// of the same sequence.
+// ---------------------------------------------------------------------------
+
+// Frame of a surfel: t_u, t_v, n are the columns of R(q/|q|) (Hamilton, w first).
+__device__ __forceinline__ void frame32(float w, float x, float y, float z, float3 &tu, float3 &tv, float3 &n)
+{
+#pragma clang fp contract(off)
+    float l = sqrtf(w * w + x * x + y * y + z * z);
+    w = w / l; x = x / l; y = y / l; z = z / l;
+    float xx = x * x, yy = y * y, zz = z * z;
+    float xy = x * y, xz = x * z, yz = y * z;
+    float wx = w * x, wy = w * y, wz = w * z;
+    tu = make_float3(1.0f - 2.0f * (yy + zz), 2.0f * (xy + wz), 2.0f * (xz - wy));
+    tv = make_float3(2.0f * (xy - wz), 1.0f - 2.0f * (xx + zz), 2.0f * (yz + wx));
+    n = make_float3(2.0f * (xz + wy), 2.0f * (yz - wx), 1.0f - 2.0f * (xx + yy));
+}
+
+// Canonical crossing: m = mu - o, den = n.d, tau = n.m / den, D = tau d - m,
+// u = a_u.D, v = a_v.D, rho^2 = u^2 + v^2 (fixed order, no contraction).
+__device__ __forceinline__ void canon_geo(const float4 r0, const float4 r1, const float4 r2, const float4 r3,
+                                          const float3 o, const float3 d, float &den, float &tau, float &rho2)
+{
+#pragma clang fp contract(off)
+    float m0 = r0.x - o.x, m1 = r0.y - o.y, m2 = r0.z - o.z;
+    den = r1.x * d.x + r1.y * d.y + r1.z * d.z;
+    float num = r1.x * m0 + r1.y * m1 + r1.z * m2;
+    tau = num / den;
+    float dx = tau * d.x - m0, dy = tau * d.y - m1, dz = tau * d.z - m2;
+    float u = r2.x * dx + r2.y * dy + r2.z * dz;
+    float v = r3.x * dx + r3.y * dy + r3.z * dz;
+    rho2 = u * u + v * v;
+}
+
+// Ray/surfel test: plane crossing tau = n.(mu - o) / n.d in (tmin, tmax],
+// then rho^2 = u^2 + v^2 of the crossing in units of the scales, against
+// the surfel's bound r2max = min(9, 2 ln(o / alpha_min)).
+__device__ __forceinline__ bool hit_test(const float4 r0, const float4 r1, const float4 r2, const float4 r3,
+                                         const float3 o, const float3 d, float tmin, float tmax, float &tau)
+{
+#pragma clang fp contract(off)
+    float m0 = r0.x - o.x, m1 = r0.y - o.y, m2 = r0.z - o.z;
+    float den = r1.x * d.x + r1.y * d.y + r1.z * d.z;
+    if (fabsf(den) < kGrazing) return false;
+    float num = r1.x * m0 + r1.y * m1 + r1.z * m2;
+    float t = num / den;
+    if (!(t > tmin && t <= tmax)) return false;
+    float dx = t * d.x - m0, dy = t * d.y - m1, dz = t * d.z - m2;
+    float u = r2.x * dx + r2.y * dy + r2.z * dz;
+    float v = r3.x * dx + r3.y * dy + r3.z * dz;
+    float rr = u * u + v * v;
+    if (!(rr <= r0.w)) return false;
+    tau = t;
+    return true;
+}
+
+// Value geometry of a hit: the same crossing evaluated in double from the
+// single-precision record (the in-plane offset D = tau d - m cancels badly in
+// single precision for small surfels seen from afar).
+struct HitGeo {
+    float u, v, rho2, den;
+    float3 D;
+};
+
+__device__ __forceinline__ void value_geo(const float4 r0, const float4 r1, const float4 r2, const float4 r3,
+                                          const float3 o, const float3 d, HitGeo &g)
+{
+    const double mx = (double)r0.x - (double)o.x, my = (double)r0.y - (double)o.y, mz = (double)r0.z - (double)o.z;
+    const double dx = d.x, dy = d.y, dz = d.z;
+    const double den = (double)r1.x * dx + (double)r1.y * dy + (double)r1.z * dz;
+    const double tau = ((double)r1.x * mx + (double)r1.y * my + (double)r1.z * mz) / den;
+    const double Dx = tau * dx - mx, Dy = tau * dy - my, Dz = tau * dz - mz;
+    const double u = (double)r2.x * Dx + (double)r2.y * Dy + (double)r2.z * Dz;
+    const double v = (double)r3.x * Dx + (double)r3.y * Dy + (double)r3.z * Dz;
+    g.u = (float)u;
+    g.v = (float)v;
+    g.rho2 = (float)(u * u + v * v);
+    g.den = (float)den;
+    g.D = make_float3((float)Dx, (float)Dy, (float)Dz);
+}
+
+// Opacity contribution of a hit, alpha = o exp(-rho^2 / 2), and the
+// single-precision transmittance step that decides where compositing stops.
+__device__ __forceinline__ float hit_alpha(float op, float rho2)
+{
+#pragma clang fp contract(off)
+    return op * expf(-0.5f * rho2);
+}
+
+__device__ __forceinline__ float trans_step(float T, float a)
+{
+#pragma clang fp contract(off)
+    return T * (1.0f - a);
+}
+
+// ---------------------------------------------------------------------------
+// Slab test against one box, clipped to [t0, t1]; conservative by a few ulps.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool slab(float lx, float ly, float lz, float hx, float hy, float hz, const float3 o,
+                                     const float3 inv, float t0, float t1, float &tnear)
+{
+    float ax = (lx - o.x) * inv.x, bx = (hx - o.x) * inv.x;
+    float ay = (ly - o.y) * inv.y, by = (hy - o.y) * inv.y;
+    float az = (lz - o.z) * inv.z, bz = (hz - o.z) * inv.z;
+    float tn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), t0));
+    float tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), t1));
+    tnear = tn;
+    return tn <= tf * 1.0000005f + 1e-30f;
+}
+
+__device__ __forceinline__ float safe_inv(float d)
+{
+    return 1.0f / (fabsf(d) > 1e-30f ? d : copysignf(1e-30f, d));
+}
+
+__device__ __forceinline__ uint64_t make_key(float tau, uint32_t id)
+{
+    return ((uint64_t)__float_as_uint(tau) << 32) | (uint64_t)id;
+}
+
+// ---------------------------------------------------------------------------
+// Ordered traversal with a k-nearest hit buffer, re-traversed in rounds.
+//
+// Each round walks the LBVH from the root, keeping the K smallest keys
+// (bits(tau), id) strictly greater than the last key composited in the
+// previous round (registers, sorted by unrolled insertion).  Once the buffer
+// is full its largest depth bounds the interval, which prunes far subtrees.
+// The buffered hits are then handed to `visit` (record position, surfel id,
+// depth) in order; `visit` returns true to stop (transmittance cutoff).  A round that ends with a full buffer
+// is followed by another that resumes strictly after its last key, so hits
+// of equal depth are neither lost nor repeated.  Results do not depend on K.
+// ---------------------------------------------------------------------------
+template <int K, class Visit>
+__device__ __forceinline__ void traverse(const SceneDev &S, const float3 o, const float3 d, float tmin, float tmax,
+                                         Visit &visit)
+{
+    if (S.n <= 0) return;
+    const float3 inv = make_float3(safe_inv(d.x), safe_inv(d.y), safe_inv(d.z));
+    uint64_t last = 0;
+    float tlo = tmin;
+    int stack[kStack];
+    for (;;) {
+        uint64_t key[K];
+        uint32_t pos[K];
+#pragma unroll
+        for (int i = 0; i < K; ++i) { key[i] = ~0ull; pos[i] = 0; }
+        int cnt = 0;
+        float thi = tmax;
+
+        auto test_leaf = [&](uint32_t p) {
+            const float4 *r = S.rec + 4 * (size_t)p;
+            float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+            float t;
+            if (!hit_test(r0, r1, r2, r3, o, d, tmin, tmax, t)) return;
+            uint64_t k = make_key(t, __float_as_uint(r2.w));
+            if (k <= last || k >= key[K - 1]) return;
+            // sorted insertion, largest key drops out
+            bool placed = false;
+#pragma unroll
+            for (int i = K - 1; i > 0; --i) {
+                bool shift = key[i - 1] > k;
+                uint64_t nk = shift ? key[i - 1] : (placed ? key[i] : k);
+                uint32_t np = shift ? pos[i - 1] : (placed ? pos[i] : p);
+                placed = placed || !shift;
+                key[i] = nk; pos[i] = np;
+            }
+            if (!placed) { key[0] = k; pos[0] = p; }
+            ++cnt;
+            if (cnt >= K) thi = __uint_as_float((uint32_t)(key[K - 1] >> 32));
+        };
+
+        if (S.n == 1) {
+            test_leaf(0);
+        } else {
+            int sp = 0;
+            int node = 0;
+            for (;;) {
+                const Node nd = S.nodes[node];
+                float tl, tr;
+                bool hl = slab(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, o, inv, tlo, thi, tl);
+                bool hr = slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, o, inv, tlo, thi, tr);
+                int cl = nd.d.x, cr = nd.d.y;
+                if (hl && cl < 0) { test_leaf((uint32_t)(-cl - 1)); hl = false; }
+                if (hr && cr < 0) { test_leaf((uint32_t)(-cr - 1)); hr = false; }
+                if (hl && hr) {
+                    bool lfirst = tl <= tr;
+                    stack[sp++] = lfirst ? cr : cl;
+                    node = lfirst ? cl : cr;
+                } else if (hl) {
+                    node = cl;
+                } else if (hr) {
+                    node = cr;
+                } else {
+                    if (sp == 0) break;
+                    node = stack[--sp];
+                }
+            }
+        }
+
+        bool stop = false;
+        const int m = cnt < K ? cnt : K;
+#pragma unroll
+        for (int i = 0; i < K; ++i) {
+            if (i < m && !stop)
+                stop = visit(pos[i], (uint32_t)(key[i] & 0xffffffffu), __uint_as_float((uint32_t)(key[i] >> 32)));
+        }
+        if (stop || cnt < K) break;
+        last = key[K - 1];
+        tlo = __uint_as_float((uint32_t)(last >> 32));
+    }
+}
+
+}  // namespace grt

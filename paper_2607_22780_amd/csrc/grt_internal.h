@@ -1,0 +1,154 @@
+// grt_internal.h -- host-side structures shared by the translation units of
+// libgrt (workspace carving and kernel launchers).  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "grt.h"
+#include "grt_device.h"
+
+struct grt_ctx {
+    int device;
+    int num_cu;
+};
+
+namespace grt {
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;
+constexpr int kSortTile = kSortThreads * kSortItems;
+
+inline int64_t sort_blocks(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
+
+// Carving of a scene workspace; the same function sizes and places.
+struct SceneWS {
+    float4 *rec;
+    float4 *col;
+    Node *nodes;
+    float *leaf_box;   // [n,6] sorted order
+    float *box_tmp;    // [n,6] surfel order
+    uint32_t *keys0, *keys1, *vals0, *vals1;
+    int32_t *parent_int;   // [n-1]
+    int32_t *parent_leaf;  // [n]
+    uint32_t *flags;       // [n-1]
+    uint32_t *hist;        // [256 * blocks]
+    int32_t *bounds;       // [8]
+    size_t bytes;
+};
+
+inline SceneWS carve_scene(void *base, int64_t n)
+{
+    SceneWS w{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? (char *)base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    size_t nn = (size_t)(n > 0 ? n : 1);
+    size_t ni = (size_t)(n > 1 ? n - 1 : 1);
+    w.rec = (float4 *)take(64 * nn);
+    w.col = (float4 *)take(16 * nn);
+    w.nodes = (Node *)take(sizeof(Node) * ni);
+    w.leaf_box = (float *)take(24 * nn);
+    w.box_tmp = (float *)take(24 * nn);
+    w.keys0 = (uint32_t *)take(4 * nn);
+    w.keys1 = (uint32_t *)take(4 * nn);
+    w.vals0 = (uint32_t *)take(4 * nn);
+    w.vals1 = (uint32_t *)take(4 * nn);
+    w.parent_int = (int32_t *)take(4 * ni);
+    w.parent_leaf = (int32_t *)take(4 * nn);
+    w.flags = (uint32_t *)take(4 * ni);
+    w.hist = (uint32_t *)take(4 * 256 * (size_t)(sort_blocks(n) > 0 ? sort_blocks(n) : 1));
+    w.bounds = (int32_t *)take(4 * 8);
+    w.bytes = off;
+    return w;
+}
+
+struct EnvWS {
+    float *marg;   // [H+1]
+    float *cond;   // [H,W+1]
+    double *rows;  // [H]
+    size_t bytes;
+};
+
+inline EnvWS carve_env(void *base, int H, int W)
+{
+    EnvWS w{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? (char *)base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    w.marg = (float *)take(4 * (size_t)(H + 1));
+    w.cond = (float *)take(4 * (size_t)H * (size_t)(W + 1));
+    w.rows = (double *)take(8 * (size_t)H);
+    w.bytes = off;
+    return w;
+}
+
+// Scene build (scene.hip)
+hipError_t launch_scene_build(const grt_surfels &s, float alpha_min, const SceneWS &w, hipStream_t st);
+
+// Trace forward/backward (trace.hip)
+struct TraceArgs {
+    SceneDev S;
+    int64_t n;
+    const float *o, *d, *tmin_a, *tmax_a;
+    float tmin, tmax, tcut;
+    float sky[3];
+    float *out_rgb, *out_T, *out_L;
+    int32_t *out_nhit;
+    int32_t *dump_id;
+    float *dump_tau;
+    int cap;
+};
+hipError_t launch_trace(const TraceArgs &a, int k, hipStream_t st);
+
+struct GradPtrs {
+    float *means, *scales, *quats, *opacity, *rgb;
+    const int32_t *order;  // unused by kernels (ids travel in records)
+    const float *p_scales, *p_quats;
+};
+struct TraceBwdArgs {
+    TraceArgs f;
+    const float *fwd_rgb, *fwd_T, *grad_rgb, *grad_T;
+    GradPtrs g;
+};
+hipError_t launch_trace_backward(const TraceBwdArgs &a, int k, hipStream_t st);
+
+// Environment and MIS (render.hip)
+struct EnvDev {
+    int H, W;
+    const float *rgb;
+    const float *marg;
+    const float *cond;
+};
+hipError_t launch_env_build(const float *rgb, int H, int W, const EnvWS &w, hipStream_t st);
+
+struct RenderArgs {
+    SceneDev S;
+    EnvDev E;
+    int H, W;
+    const float *x, *n, *wo, *alb, *rough, *metal;
+    const uint8_t *valid;
+    int nc, ng, ne;
+    uint64_t seed;
+    uint32_t job;
+    float tmin, tcut;
+    float *out;
+    float4 *saved;
+    float *dump;
+    // backward
+    const float *grad;
+    GradPtrs g;
+};
+hipError_t launch_render(const RenderArgs &a, int k, hipStream_t st);
+hipError_t launch_render_backward(const RenderArgs &a, int k, hipStream_t st);
+
+}  // namespace grt

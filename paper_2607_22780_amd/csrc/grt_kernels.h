@@ -1,0 +1,142 @@
+// grt_kernels.h -- per-hit work shared by the trace and render kernels:
+// front-to-back compositing (forward) and its gradient (backward).
+#pragma once
+
+#include "grt_internal.h"
+
+namespace grt {
+
+// Forward compositing (Sec. 3.2, Eq. trace; Eq. alpha_blending along the ray).
+// Where to stop is decided on the transmittance of the canonical
+// single-precision alphas (Td); the composited values use alphas from the
+// double-precision crossing.
+struct CompositeVisit {
+    const float4 *rec;
+    const float4 *col;
+    float3 o, d;
+    float tcut;
+    float3 C;
+    float T, Td;
+    int cnt;
+    int32_t *did = nullptr;
+    float *dtau = nullptr;
+    int cap = 0;
+
+    __device__ CompositeVisit(const SceneDev &S, float3 o_, float3 d_, float t_cut)
+        : rec(S.rec), col(S.col), o(o_), d(d_), tcut(t_cut), C(make_float3(0.f, 0.f, 0.f)), T(1.0f), Td(1.0f),
+          cnt(0) {}
+
+    __device__ __forceinline__ bool operator()(uint32_t p, uint32_t id, float tau)
+    {
+        const float4 *r = rec + 4 * (size_t)p;
+        const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+        const float4 c = col[p];
+        float cden, ctau, crho2;
+        canon_geo(r0, r1, r2, r3, o, d, cden, ctau, crho2);
+        HitGeo g;
+        value_geo(r0, r1, r2, r3, o, d, g);
+        const float a = r1.w * expf(-0.5f * g.rho2);
+        const float w = T * a;
+        C.x += w * c.x; C.y += w * c.y; C.z += w * c.z;
+        if (did && cnt < cap) { did[cnt] = (int32_t)id; dtau[cnt] = tau; }
+        ++cnt;
+        T = T * (1.0f - a);
+        Td = trans_step(Td, hit_alpha(r1.w, crho2));
+        return Td < tcut;
+    }
+};
+
+__device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+
+// Backward of g_C . C + g_T . T_fin through every composited hit, with the
+// hit set, order and stop index of the forward.
+struct GradVisit {
+    const float4 *rec;
+    const float4 *col;
+    float tcut;
+    GradPtrs g;
+    float3 o, d, gC, Cf;
+    float gT, Tf;
+    float T, Td;
+    float3 P;
+
+    __device__ GradVisit(const SceneDev &S, float t_cut, const GradPtrs &gp, float3 o_, float3 d_, float3 gC_, float gT_,
+                         float3 Cf_, float Tf_)
+        : rec(S.rec), col(S.col), tcut(t_cut), g(gp), o(o_), d(d_), gC(gC_), Cf(Cf_), gT(gT_), Tf(Tf_), T(1.0f),
+          Td(1.0f), P(make_float3(0.f, 0.f, 0.f)) {}
+
+    __device__ __forceinline__ bool operator()(uint32_t p, uint32_t id, float tau)
+    {
+        const float4 *r = rec + 4 * (size_t)p;
+        const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+        const float4 c = col[p];
+        const float op = r1.w;
+        float cden, ctau, crho2;
+        canon_geo(r0, r1, r2, r3, o, d, cden, ctau, crho2);
+        HitGeo hg;
+        value_geo(r0, r1, r2, r3, o, d, hg);
+        const float G = expf(-0.5f * hg.rho2);
+        const float a = op * G;
+        const float w = T * a;
+        P.x += w * c.x; P.y += w * c.y; P.z += w * c.z;
+        float dA = T * (gC.x * c.x + gC.y * c.y + gC.z * c.z);
+        const float om = 1.0f - a;
+        if (om >= 1e-6f) {
+            float behind = gC.x * (Cf.x - P.x) + gC.y * (Cf.y - P.y) + gC.z * (Cf.z - P.z) + gT * Tf;
+            dA -= behind / om;
+        }
+        const float3 n = make_float3(r1.x, r1.y, r1.z);
+        const float den = hg.den;
+        const float3 D = hg.D;
+        const float3 au = make_float3(r2.x, r2.y, r2.z), av = make_float3(r3.x, r3.y, r3.z);
+        const float u = hg.u, v = hg.v;
+        const float gamma = -0.5f * a * dA;  // dL/d(rho^2)
+        const float du = 2.0f * u * gamma, dv = 2.0f * v * gamma;
+        // parameters of the surfel in its stored form
+        const float4 q = reinterpret_cast<const float4 *>(g.p_quats)[id];
+        const float su = g.p_scales[2 * (size_t)id], sv = g.p_scales[2 * (size_t)id + 1];
+        const float ql = sqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
+        const float iq = 1.0f / ql;
+        const float qw = q.x * iq, qx = q.y * iq, qy = q.z * iq, qz = q.w * iq;
+        const float dsu = -(u / su) * du, dsv = -(v / sv) * dv;
+        const float3 gD = make_float3(du * au.x + dv * av.x, du * au.y + dv * av.y, du * au.z + dv * av.z);
+        const float gDd = dot3(gD, d) / den;
+        const float3 dmu = make_float3(gDd * n.x - gD.x, gDd * n.y - gD.y, gDd * n.z - gD.z);
+        const float ku = du / su, kv = dv / sv;
+        const float3 dtu = make_float3(ku * D.x, ku * D.y, ku * D.z);
+        const float3 dtv = make_float3(kv * D.x, kv * D.y, kv * D.z);
+        const float3 dn = make_float3(-gDd * D.x, -gDd * D.y, -gDd * D.z);
+        // d(columns of R)/d(unit quaternion)
+        float dqw = 2.f * (dtu.y * qz - dtu.z * qy - dtv.x * qz + dtv.z * qx + dn.x * qy - dn.y * qx);
+        float dqx = 2.f * (dtu.y * qy + dtu.z * qz + dtv.x * qy - 2.f * dtv.y * qx + dtv.z * qw + dn.x * qz - dn.y * qw -
+                           2.f * dn.z * qx);
+        float dqy = 2.f * (-2.f * dtu.x * qy + dtu.y * qx - dtu.z * qw + dtv.x * qx + dtv.z * qz + dn.x * qw +
+                           dn.y * qz - 2.f * dn.z * qy);
+        float dqz = 2.f * (-2.f * dtu.x * qz + dtu.y * qw + dtu.z * qx - dtv.x * qw - 2.f * dtv.y * qz + dtv.z * qy +
+                           dn.x * qx + dn.y * qy);
+        const float proj = qw * dqw + qx * dqx + qy * dqy + qz * dqz;
+        dqw = (dqw - qw * proj) * iq; dqx = (dqx - qx * proj) * iq;
+        dqy = (dqy - qy * proj) * iq; dqz = (dqz - qz * proj) * iq;
+
+        const size_t i = id;
+        unsafeAtomicAdd(&g.means[3 * i], dmu.x);
+        unsafeAtomicAdd(&g.means[3 * i + 1], dmu.y);
+        unsafeAtomicAdd(&g.means[3 * i + 2], dmu.z);
+        unsafeAtomicAdd(&g.scales[2 * i], dsu);
+        unsafeAtomicAdd(&g.scales[2 * i + 1], dsv);
+        unsafeAtomicAdd(&g.quats[4 * i], dqw);
+        unsafeAtomicAdd(&g.quats[4 * i + 1], dqx);
+        unsafeAtomicAdd(&g.quats[4 * i + 2], dqy);
+        unsafeAtomicAdd(&g.quats[4 * i + 3], dqz);
+        unsafeAtomicAdd(&g.opacity[i], G * dA);
+        unsafeAtomicAdd(&g.rgb[3 * i], w * gC.x);
+        unsafeAtomicAdd(&g.rgb[3 * i + 1], w * gC.y);
+        unsafeAtomicAdd(&g.rgb[3 * i + 2], w * gC.z);
+
+        T = T * (1.0f - a);
+        Td = trans_step(Td, hit_alpha(op, crho2));
+        return Td < tcut;
+    }
+};
+
+}  // namespace grt

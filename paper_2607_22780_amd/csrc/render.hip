@@ -1,0 +1,480 @@
+// render.hip -- environment tables and the fused MIS render (forward and
+// backward by re-traversal).
+//
+// One lane per (pixel, sample).  A pixel's samples occupy S = min(64,
+// pow2 >= spp) consecutive lanes of one wavefront; lane j handles samples
+// j, j+S, ...  Each sample (Sec. 3.3 Eq. montecarlo, Sec. 3.4.1 Eq. mis):
+//   u1,u2  <- Philox-4x32-10(key = seed, counter = (pixel, j, job, 0))
+//   w      <- cosine (j < N_c) | GGX visible normal (j < N_c+N_g) | env texel
+//   q      =  (N_c p_c + N_g p_g + N_e p_e) / N_r          (balance heuristic)
+//   if w.n > 0:  (C, T) <- Trace(x, w);  L_i = C + T L_env(w)   (Eqs. incident_trace, lighting_decompose)
+//                g/q = f(wo, w) L_i (w.n) / q              (Eqs. brdf_decompose, brdf_specular)
+// and the pixel's estimate (1/N_r) sum g/q is reduced across its lanes with a
+// fixed butterfly, so it is reproducible and independent of other pixels.
+#include "grt_internal.h"
+#include "grt_kernels.h"
+
+namespace grt {
+
+constexpr float kPi = 3.14159265358979323846f;
+
+// ---------------------------------------------------------------------------
+// Environment proposal tables: texel weight = luminance x sin(theta_centre);
+// cumulative sums in double, left to right, rounded to float at the end.
+// ---------------------------------------------------------------------------
+__global__ void k_env_rows(int H, int W, const float *__restrict__ rgb, float *__restrict__ cond,
+                           double *__restrict__ rows)
+{
+#pragma clang fp contract(off)
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= H) return;
+    const double st = sin(3.14159265358979323846 * (i + 0.5) / H);
+    double acc = 0.0;
+    for (int j = 0; j < W; ++j) {
+        const float *p = rgb + ((size_t)i * W + j) * 3;
+        double lum = 0.2126 * (double)p[0] + 0.7152 * (double)p[1] + 0.0722 * (double)p[2];
+        acc += lum * st;
+    }
+    rows[i] = acc;
+    float *cr = cond + (size_t)i * (W + 1);
+    cr[0] = 0.0f;
+    double run = 0.0;
+    for (int j = 0; j < W; ++j) {
+        const float *p = rgb + ((size_t)i * W + j) * 3;
+        double lum = 0.2126 * (double)p[0] + 0.7152 * (double)p[1] + 0.0722 * (double)p[2];
+        run += lum * st;
+        cr[j + 1] = acc > 0.0 ? (float)(run / acc) : (float)((double)(j + 1) / W);
+    }
+    cr[W] = 1.0f;
+}
+
+__global__ void k_env_marginal(int H, const double *__restrict__ rows, float *__restrict__ marg)
+{
+#pragma clang fp contract(off)
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double tot = 0.0;
+    for (int i = 0; i < H; ++i) tot += rows[i];
+    double acc = 0.0;
+    marg[0] = 0.0f;
+    for (int i = 0; i < H; ++i) {
+        acc += rows[i];
+        marg[i + 1] = tot > 0.0 ? (float)(acc / tot) : (float)((double)(i + 1) / H);
+    }
+    marg[H] = 1.0f;
+}
+
+hipError_t launch_env_build(const float *rgb, int H, int W, const EnvWS &w, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_env_rows, dim3((H + 63) / 64), dim3(64), 0, st, H, W, rgb, w.cond, w.rows);
+    hipLaunchKernelGGL(k_env_marginal, dim3(1), dim3(64), 0, st, H, w.rows, w.marg);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Random numbers: Philox-4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void uniforms(uint64_t seed, uint32_t pix, uint32_t j, uint32_t job, float &u1, float &u2)
+{
+    uint32_t c0 = pix, c1 = j, c2 = job, c3 = 0u;
+    uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c0), lo0 = 0xD2511F53u * c0;
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2), lo1 = 0xCD9E8D57u * c2;
+        const uint32_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += 0x9E3779B9u; k1 += 0xBB67AE85u;
+    }
+    u1 = (float)(c0 >> 8) * (1.0f / 16777216.0f);
+    u2 = (float)(c1 >> 8) * (1.0f / 16777216.0f);
+}
+
+// ---------------------------------------------------------------------------
+// Proposals, pdfs and the BRDF, per sample in double precision with a fixed
+// operation order (a few hundred flops per sample against thousands of bytes
+// of traversal): the sampled direction, rounded once to single precision, is
+// then reproducible to the last bit, and so is every hit decision downstream.
+// ---------------------------------------------------------------------------
+constexpr double kPiD = 3.14159265358979323846;
+
+struct V3 {
+    double x, y, z;
+};
+
+__device__ __forceinline__ V3 v3(double x, double y, double z) { return V3{x, y, z}; }
+__device__ __forceinline__ double dot(V3 a, V3 b)
+{
+#pragma clang fp contract(off)
+    return a.x * b.x + a.y * b.y + a.z * b.z;
+}
+__device__ __forceinline__ V3 normalized(V3 a)
+{
+#pragma clang fp contract(off)
+    double l = sqrt(dot(a, a));
+    return v3(a.x / l, a.y / l, a.z / l);
+}
+// x b1 + y b2 + z n, summed left to right
+__device__ __forceinline__ V3 combine(double x, V3 b1, double y, V3 b2, double z, V3 n)
+{
+#pragma clang fp contract(off)
+    return v3(x * b1.x + y * b2.x + z * n.x, x * b1.y + y * b2.y + z * n.y, x * b1.z + y * b2.z + z * n.z);
+}
+
+// orthonormal basis around n (Duff et al., JCGT 2017)
+__device__ __forceinline__ void onb(V3 n, V3 &b1, V3 &b2)
+{
+#pragma clang fp contract(off)
+    double sign = copysign(1.0, n.z);
+    double a = -1.0 / (sign + n.z);
+    double b = n.x * n.y * a;
+    b1 = v3(1.0 + sign * n.x * n.x * a, sign * b, -sign * n.x);
+    b2 = v3(b, sign + n.y * n.y * a, -n.y);
+}
+
+__device__ __forceinline__ double ggx_D(double ndh, double a2)
+{
+#pragma clang fp contract(off)
+    double t = ndh * ndh * (a2 - 1.0) + 1.0;
+    return a2 / (kPiD * t * t);
+}
+
+__device__ __forceinline__ double smith_G1(double ndv, double a2)
+{
+#pragma clang fp contract(off)
+    return 2.0 * ndv / (ndv + sqrt(a2 + (1.0 - a2) * ndv * ndv));
+}
+
+// cosine-weighted direction (Malley: uniform disk lifted to the hemisphere)
+__device__ __forceinline__ V3 sample_cos(V3 n, double u1, double u2)
+{
+#pragma clang fp contract(off)
+    V3 b1, b2;
+    onb(n, b1, b2);
+    double r = sqrt(u1), ph = 2.0 * kPiD * u2;
+    double x = r * cos(ph), y = r * sin(ph), z = sqrt(1.0 - u1 > 0.0 ? 1.0 - u1 : 0.0);
+    return combine(x, b1, y, b2, z, n);
+}
+
+// visible-normal sampling of GGX (Heitz, JCGT 2018), then reflect wo about h
+__device__ __forceinline__ V3 sample_ggx(V3 n, V3 wo, double rough, double u1, double u2)
+{
+#pragma clang fp contract(off)
+    V3 b1, b2;
+    onb(n, b1, b2);
+    double a = rough * rough;
+    V3 Vh = normalized(v3(a * dot(wo, b1), a * dot(wo, b2), dot(wo, n)));
+    double lensq = Vh.x * Vh.x + Vh.y * Vh.y;
+    V3 T1 = v3(1.0, 0.0, 0.0);
+    if (lensq > 0.0) {
+        double il = 1.0 / sqrt(lensq);
+        T1 = v3(-Vh.y * il, Vh.x * il, 0.0);
+    }
+    V3 T2 = v3(Vh.y * T1.z - Vh.z * T1.y, Vh.z * T1.x - Vh.x * T1.z, Vh.x * T1.y - Vh.y * T1.x);
+    double r = sqrt(u1), ph = 2.0 * kPiD * u2;
+    double t1 = r * cos(ph), t2 = r * sin(ph);
+    double s = 0.5 * (1.0 + Vh.z);
+    t2 = (1.0 - s) * sqrt(1.0 - t1 * t1) + s * t2;
+    double t3 = 1.0 - t1 * t1 - t2 * t2;
+    t3 = sqrt(t3 > 0.0 ? t3 : 0.0);
+    V3 Nh = v3(t1 * T1.x + t2 * T2.x + t3 * Vh.x, t1 * T1.y + t2 * T2.y + t3 * Vh.y, t1 * T1.z + t2 * T2.z + t3 * Vh.z);
+    V3 Ne = normalized(v3(a * Nh.x, a * Nh.y, Nh.z > 0.0 ? Nh.z : 0.0));
+    V3 h = combine(Ne.x, b1, Ne.y, b2, Ne.z, n);
+    double oh = dot(wo, h);
+    return v3(2.0 * oh * h.x - wo.x, 2.0 * oh * h.y - wo.y, 2.0 * oh * h.z - wo.z);
+}
+
+// first k in [0, n) with cdf[k+1] > u (cdf[n] == 1 > u)
+__device__ __forceinline__ int cdf_find(const float *__restrict__ cdf, int n, double u)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi) >> 1;
+        if ((double)cdf[mid + 1] > u) hi = mid; else lo = mid + 1;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ V3 sample_env(const EnvDev &E, double u1, double u2)
+{
+#pragma clang fp contract(off)
+    int i = cdf_find(E.marg, E.H, u1);
+    double dv = (u1 - (double)E.marg[i]) / ((double)E.marg[i + 1] - (double)E.marg[i]);
+    const float *cr = E.cond + (size_t)i * (E.W + 1);
+    int j = cdf_find(cr, E.W, u2);
+    double du = (u2 - (double)cr[j]) / ((double)cr[j + 1] - (double)cr[j]);
+    double th = kPiD * (i + dv) / E.H, ph = 2.0 * kPiD * (j + du) / E.W;
+    return v3(sin(th) * cos(ph), cos(th), sin(th) * sin(ph));
+}
+
+// nearest texel of a direction; sin(theta) for the pdf
+__device__ __forceinline__ void env_index(const EnvDev &E, V3 w, int &i, int &j, double &sin_t)
+{
+#pragma clang fp contract(off)
+    double y = w.y < -1.0 ? -1.0 : (w.y > 1.0 ? 1.0 : w.y);
+    double th = acos(y);
+    double ph = atan2(w.z, w.x);
+    if (ph < 0.0) ph += 2.0 * kPiD;
+    int ii = (int)(th / kPiD * E.H), jj = (int)(ph / (2.0 * kPiD) * E.W);
+    i = ii < E.H - 1 ? ii : E.H - 1;
+    j = jj < E.W - 1 ? jj : E.W - 1;
+    if (i < 0) i = 0;
+    if (j < 0) j = 0;
+    sin_t = sqrt(1.0 - y * y > 0.0 ? 1.0 - y * y : 0.0);
+}
+
+__device__ __forceinline__ float3 env_radiance(const EnvDev &E, V3 w)
+{
+    int i, j;
+    double st;
+    env_index(E, w, i, j, st);
+    const float *p = E.rgb + ((size_t)i * E.W + j) * 3;
+    return make_float3(p[0], p[1], p[2]);
+}
+
+__device__ __forceinline__ double env_pdf(const EnvDev &E, V3 w)
+{
+#pragma clang fp contract(off)
+    int i, j;
+    double st;
+    env_index(E, w, i, j, st);
+    if (st <= 0.0) return 0.0;
+    const float *cr = E.cond + (size_t)i * (E.W + 1);
+    double pij = ((double)E.marg[i + 1] - (double)E.marg[i]) * ((double)cr[j + 1] - (double)cr[j]);
+    return pij * E.H * E.W / (2.0 * kPiD * kPiD * st);
+}
+
+// q = (N_c p_c + N_g p_g + N_e p_e) / N_r (Sec. 3.4.1, deterministic mixture)
+__device__ __forceinline__ double mixture_pdf(const EnvDev &E, V3 n, V3 wo, double rough, V3 w, int nc, int ng,
+                                              int ne)
+{
+#pragma clang fp contract(off)
+    double ndi = dot(n, w), ndo = dot(n, wo);
+    double pc = ndi > 0.0 ? ndi / kPiD : 0.0;
+    double pg = 0.0;
+    V3 h = v3(w.x + wo.x, w.y + wo.y, w.z + wo.z);
+    double hl = sqrt(dot(h, h));
+    if (hl > 0.0) {
+        h = v3(h.x / hl, h.y / hl, h.z / hl);
+        double ndh = dot(n, h);
+        if (ndh > 0.0 && dot(wo, h) > 0.0) {
+            double a = rough * rough, a2 = a * a;
+            pg = smith_G1(ndo, a2) * ggx_D(ndh, a2) / (4.0 * ndo);
+        }
+    }
+    double pe = ne > 0 ? env_pdf(E, w) : 0.0;
+    return ((double)nc * pc + (double)ng * pg + (double)ne * pe) / (double)(nc + ng + ne);
+}
+
+// f(wo, wi) for wi.n > 0, wo.n > 0 (Eqs. brdf_decompose, brdf_specular;
+// F0 = 0.04 (1 - m) + m a; D GGX, G separable Smith, F Schlick on wi.h)
+__device__ __forceinline__ V3 brdf(V3 n, V3 wo, V3 wi, V3 alb, double rough, double metal)
+{
+#pragma clang fp contract(off)
+    double ndi = dot(n, wi), ndo = dot(n, wo);
+    V3 h = normalized(v3(wi.x + wo.x, wi.y + wo.y, wi.z + wo.z));
+    double ndh = dot(n, h), idh = dot(wi, h);
+    double a = rough * rough, a2 = a * a;
+    double D = ggx_D(ndh, a2);
+    double G = smith_G1(ndi, a2) * smith_G1(ndo, a2);
+    double x = 1.0 - idh;
+    if (x < 0.0) x = 0.0;
+    double x5 = x * x * x * x * x;
+    double al[3] = {alb.x, alb.y, alb.z}, f[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double F0 = 0.04 * (1.0 - metal) + metal * al[c];
+        double F = F0 + (1.0 - F0) * x5;
+        f[c] = (1.0 - metal) * al[c] / kPiD + D * F * G / (4.0 * ndi * ndo);
+    }
+    return v3(f[0], f[1], f[2]);
+}
+
+// ---------------------------------------------------------------------------
+// Lane layout
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int group_size(int spp)
+{
+    int s = 1;
+    while (s < spp && s < 64) s <<= 1;
+    return s;
+}
+
+// Contiguous ranges of blocks per XCD: blocks are dealt round-robin to the 8
+// XCDs, so consecutive logical tiles (neighbouring pixels, similar rays) are
+// remapped to land on the same XCD and share its L2.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb)
+{
+    const unsigned full = nb & ~7u;
+    if (b >= full) return b;
+    return (b & 7u) * (full >> 3) + (b >> 3);
+}
+
+struct Shade {
+    V3 n, wo, alb;
+    float3 x;
+    double rough, metal;
+};
+
+// the normal and the view direction are directions: normalised in double
+__device__ __forceinline__ bool load_pixel(const RenderArgs &a, int64_t p, Shade &s)
+{
+    if (p >= (int64_t)a.H * a.W || !a.valid[p]) return false;
+    s.x = make_float3(a.x[3 * p], a.x[3 * p + 1], a.x[3 * p + 2]);
+    V3 n = v3(a.n[3 * p], a.n[3 * p + 1], a.n[3 * p + 2]);
+    V3 wo = v3(a.wo[3 * p], a.wo[3 * p + 1], a.wo[3 * p + 2]);
+    s.n = dot(n, n) > 0.0 ? normalized(n) : n;
+    s.wo = dot(wo, wo) > 0.0 ? normalized(wo) : wo;
+    s.alb = v3(a.alb[3 * p], a.alb[3 * p + 1], a.alb[3 * p + 2]);
+    s.rough = a.rough[p];
+    s.metal = a.metal[p];
+    return dot(s.n, s.wo) > 0.0;
+}
+
+// Sample j of pixel p: direction w (double, and its single-precision ray
+// direction wf), mixture pdf q and weight f cos / q; false below the horizon.
+__device__ __forceinline__ bool draw(const RenderArgs &a, const Shade &s, int64_t p, int j, V3 &w, float3 &wf,
+                                     double &q, float3 &wt)
+{
+    uint32_t c0 = (uint32_t)p, c1 = (uint32_t)j;
+    float u1f, u2f;
+    uniforms(a.seed, c0, c1, a.job, u1f, u2f);
+    const double u1 = u1f, u2 = u2f;  // exact: 24-bit integers times 2^-24
+    if (j < a.nc) w = sample_cos(s.n, u1, u2);
+    else if (j < a.nc + a.ng) w = sample_ggx(s.n, s.wo, s.rough, u1, u2);
+    else w = sample_env(a.E, u1, u2);
+    wf = make_float3((float)w.x, (float)w.y, (float)w.z);
+    double ndi = dot(s.n, w);
+    q = 0.0;
+    wt = make_float3(0.f, 0.f, 0.f);
+    if (!(ndi > 0.0)) return false;
+    q = mixture_pdf(a.E, s.n, s.wo, s.rough, w, a.nc, a.ng, a.ne);
+    if (q > 0.0) {
+        V3 f = brdf(s.n, s.wo, w, s.alb, s.rough, s.metal);
+        wt = make_float3((float)(f.x * ndi / q), (float)(f.y * ndi / q), (float)(f.z * ndi / q));
+    }
+    return true;
+}
+
+template <int K>
+__global__ void __launch_bounds__(256) k_render(RenderArgs a)
+{
+    const int spp = a.nc + a.ng + a.ne;
+    const int S = group_size(spp);
+    const int per_block = 256 / S;
+    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t p = (int64_t)b * per_block + threadIdx.x / S;
+    const int lane = threadIdx.x % S;
+    Shade s;
+    const bool ok = load_pixel(a, p, s);
+    float3 acc = make_float3(0.f, 0.f, 0.f);
+    if (ok) {
+        for (int j = lane; j < spp; j += S) {
+            V3 w;
+            float3 wf, wt;
+            double q;
+            float3 Li = make_float3(0.f, 0.f, 0.f);
+            const int64_t ray = p * spp + j;
+            if (draw(a, s, p, j, w, wf, q, wt)) {
+                CompositeVisit v(a.S, s.x, wf, a.tcut);
+                traverse<K>(a.S, s.x, wf, a.tmin, INFINITY, v);
+                const float3 Le = env_radiance(a.E, w);
+                Li = make_float3(v.C.x + v.T * Le.x, v.C.y + v.T * Le.y, v.C.z + v.T * Le.z);
+                acc.x += wt.x * Li.x; acc.y += wt.y * Li.y; acc.z += wt.z * Li.z;
+                if (a.saved) a.saved[ray] = make_float4(v.C.x, v.C.y, v.C.z, v.T);
+            }
+            if (a.dump) {
+                float *dp = a.dump + ray * 10;
+                dp[0] = wf.x; dp[1] = wf.y; dp[2] = wf.z; dp[3] = (float)q;
+                dp[4] = wt.x; dp[5] = wt.y; dp[6] = wt.z;
+                dp[7] = Li.x; dp[8] = Li.y; dp[9] = Li.z;
+            }
+        }
+    } else if (a.dump && p < (int64_t)a.H * a.W) {
+        for (int j = lane; j < spp; j += S)
+            for (int c = 0; c < 10; ++c) a.dump[(p * spp + j) * 10 + c] = 0.0f;
+    }
+    // fixed-order butterfly over the pixel's S lanes
+    for (int off = S >> 1; off > 0; off >>= 1) {
+        acc.x += __shfl_xor(acc.x, off, 64);
+        acc.y += __shfl_xor(acc.y, off, 64);
+        acc.z += __shfl_xor(acc.z, off, 64);
+    }
+    if (lane == 0 && p < (int64_t)a.H * a.W) {
+        const float inv = ok ? 1.0f / (float)spp : 0.0f;
+        a.out[3 * p] = acc.x * inv;
+        a.out[3 * p + 1] = acc.y * inv;
+        a.out[3 * p + 2] = acc.z * inv;
+    }
+}
+
+template <int K>
+__global__ void __launch_bounds__(256) k_render_bwd(RenderArgs a)
+{
+    const int spp = a.nc + a.ng + a.ne;
+    const int S = group_size(spp);
+    const int per_block = 256 / S;
+    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
+    const int64_t p = (int64_t)b * per_block + threadIdx.x / S;
+    const int lane = threadIdx.x % S;
+    Shade s;
+    if (!load_pixel(a, p, s)) return;
+    const float inv = 1.0f / (float)spp;
+    const float3 gp = make_float3(a.grad[3 * p] * inv, a.grad[3 * p + 1] * inv, a.grad[3 * p + 2] * inv);
+    if (gp.x == 0.0f && gp.y == 0.0f && gp.z == 0.0f) return;
+    for (int j = lane; j < spp; j += S) {
+        V3 w;
+        float3 wf, wt;
+        double q;
+        if (!draw(a, s, p, j, w, wf, q, wt)) continue;
+        const float3 gC = make_float3(wt.x * gp.x, wt.y * gp.y, wt.z * gp.z);
+        const float3 Le = env_radiance(a.E, w);
+        const float gT = gC.x * Le.x + gC.y * Le.y + gC.z * Le.z;
+        const float4 sv = a.saved[p * spp + j];
+        GradVisit v(a.S, a.tcut, a.g, s.x, wf, gC, gT, make_float3(sv.x, sv.y, sv.z), sv.w);
+        traverse<K>(a.S, s.x, wf, a.tmin, INFINITY, v);
+    }
+}
+
+static dim3 render_grid(const RenderArgs &a)
+{
+    const int spp = a.nc + a.ng + a.ne;
+    int S = 1;
+    while (S < spp && S < 64) S <<= 1;
+    const int64_t npix = (int64_t)a.H * a.W;
+    const int per_block = 256 / S;
+    return dim3((unsigned)((npix + per_block - 1) / per_block));
+}
+
+hipError_t launch_render(const RenderArgs &a, int k, hipStream_t st)
+{
+    if ((int64_t)a.H * a.W <= 0) return hipSuccess;
+    dim3 grid = render_grid(a), block(256);
+    switch (k) {
+    case 1: hipLaunchKernelGGL(k_render<1>, grid, block, 0, st, a); break;
+    case 2: hipLaunchKernelGGL(k_render<2>, grid, block, 0, st, a); break;
+    case 4: hipLaunchKernelGGL(k_render<4>, grid, block, 0, st, a); break;
+    case 8: hipLaunchKernelGGL(k_render<8>, grid, block, 0, st, a); break;
+    case 16: hipLaunchKernelGGL(k_render<16>, grid, block, 0, st, a); break;
+    case 32: hipLaunchKernelGGL(k_render<32>, grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_render_backward(const RenderArgs &a, int k, hipStream_t st)
+{
+    if ((int64_t)a.H * a.W <= 0) return hipSuccess;
+    dim3 grid = render_grid(a), block(256);
+    switch (k) {
+    case 1: hipLaunchKernelGGL(k_render_bwd<1>, grid, block, 0, st, a); break;
+    case 2: hipLaunchKernelGGL(k_render_bwd<2>, grid, block, 0, st, a); break;
+    case 4: hipLaunchKernelGGL(k_render_bwd<4>, grid, block, 0, st, a); break;
+    case 8: hipLaunchKernelGGL(k_render_bwd<8>, grid, block, 0, st, a); break;
+    case 16: hipLaunchKernelGGL(k_render_bwd<16>, grid, block, 0, st, a); break;
+    case 32: hipLaunchKernelGGL(k_render_bwd<32>, grid, block, 0, st, a); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace grt

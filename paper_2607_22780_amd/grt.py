@@ -1,0 +1,528 @@
+"""Python binding of libgrt (ctypes over the C ABI in ``include/grt.h``).
+
+Argument marshalling only: every step of the path runs in the HIP kernels of
+``libgrt.so``.  The functions named ``grt_*`` mirror the C entry points one to
+one and take torch tensors (device memory) plus the current HIP stream; the
+classes below them only own workspaces and keep borrowed tensors alive.  If
+the library is missing or no GPU is present, calls raise ``GrtError``: there
+is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgrt.so")
+
+OK = 0
+ERR_INVALID = -1
+ERR_OOM = -2
+ERR_NOT_BUILT = -3
+ERR_DEVICE = -4
+ERR_ADMISSION = -5
+ERR_BUSY = -6
+ERR_CANCELLED = -7
+ERR_TIMEOUT = -8
+
+
+class GrtError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (status {code})")
+        self.code = code
+
+
+VP = C.c_void_p
+
+
+class grt_surfels(C.Structure):
+    _fields_ = [("n", C.c_int64), ("means", VP), ("scales", VP), ("quats", VP), ("opacity", VP), ("rgb", VP)]
+
+
+class grt_scene_view(C.Structure):
+    _fields_ = [("n", C.c_int64), ("records", VP), ("nodes", VP), ("order", VP), ("leaf_boxes", VP)]
+
+
+class grt_rays(C.Structure):
+    _fields_ = [("n", C.c_int64), ("origins", VP), ("dirs", VP), ("t_min", VP), ("t_max", VP),
+                ("t_min_all", C.c_float), ("t_max_all", C.c_float)]
+
+
+class grt_trace_opts(C.Structure):
+    _fields_ = [("k", C.c_int), ("t_cut", C.c_float), ("sky", C.c_float * 3), ("hit_ids", VP), ("hit_tau", VP),
+                ("hit_cap", C.c_int)]
+
+
+class grt_surfel_grads(C.Structure):
+    _fields_ = [("means", VP), ("scales", VP), ("quats", VP), ("opacity", VP), ("rgb", VP)]
+
+
+class grt_gbuffer(C.Structure):
+    _fields_ = [("H", C.c_int), ("W", C.c_int), ("x", VP), ("n", VP), ("wo", VP), ("albedo", VP), ("rough", VP),
+                ("metal", VP), ("valid", VP)]
+
+
+class grt_mis_opts(C.Structure):
+    _fields_ = [("n_cos", C.c_int), ("n_ggx", C.c_int), ("n_env", C.c_int), ("seed", C.c_uint64),
+                ("job", C.c_uint32), ("t_min", C.c_float), ("t_cut", C.c_float), ("k", C.c_int),
+                ("sample_dump", VP)]
+
+
+# every symbol include/grt.h declares, with (restype, argtypes)
+P = C.POINTER
+SIGNATURES = {
+    "grt_last_error": (C.c_char_p, []),
+    "grt_status_str": (C.c_char_p, [C.c_int]),
+    "grt_version": (C.c_int, []),
+    "grt_ctx_create": (C.c_int, [C.c_int, P(VP)]),
+    "grt_ctx_destroy": (C.c_int, [VP]),
+    "grt_scene_workspace_bytes": (C.c_size_t, [C.c_int64]),
+    "grt_scene_create": (C.c_int, [VP, P(grt_surfels), C.c_float, VP, C.c_size_t, P(VP)]),
+    "grt_scene_build": (C.c_int, [VP, VP]),
+    "grt_scene_set_surfels": (C.c_int, [VP, P(grt_surfels)]),
+    "grt_scene_destroy": (C.c_int, [VP]),
+    "grt_scene_view_get": (C.c_int, [VP, P(grt_scene_view)]),
+    "grt_trace": (C.c_int, [VP, P(grt_rays), P(grt_trace_opts), VP, VP, VP, VP, VP]),
+    "grt_trace_backward": (C.c_int, [VP, P(grt_rays), P(grt_trace_opts), VP, VP, VP, VP, P(grt_surfel_grads), VP]),
+    "grt_env_workspace_bytes": (C.c_size_t, [C.c_int, C.c_int]),
+    "grt_env_create": (C.c_int, [VP, VP, C.c_int, C.c_int, VP, C.c_size_t, P(VP)]),
+    "grt_env_build": (C.c_int, [VP, VP]),
+    "grt_env_tables": (C.c_int, [VP, P(VP), P(VP)]),
+    "grt_env_destroy": (C.c_int, [VP]),
+    "grt_render_saved_bytes": (C.c_size_t, [C.c_int64, C.c_int]),
+    "grt_render_mis": (C.c_int, [VP, VP, P(grt_gbuffer), P(grt_mis_opts), VP, VP, VP]),
+    "grt_render_mis_backward": (C.c_int, [VP, VP, P(grt_gbuffer), P(grt_mis_opts), VP, VP, P(grt_surfel_grads), VP]),
+}
+OPTIONAL = {}
+
+_LIB = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libgrt.so and declare every signature; raises if it is missing."""
+    global _LIB
+    if _LIB is not None:
+        return _LIB
+    if not os.path.exists(path):
+        raise GrtError(ERR_DEVICE, f"libgrt.so not built at {path}: run __graft_entry__.build()")
+    lib = C.CDLL(path)
+    for name, (res, args) in {**SIGNATURES, **OPTIONAL}.items():
+        if not hasattr(lib, name):
+            if name in OPTIONAL:
+                continue
+            raise GrtError(ERR_INVALID, f"libgrt.so lacks {name}")
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _LIB = lib
+    return lib
+
+
+def _check(rc: int):
+    if rc != OK:
+        lib = load_library()
+        raise GrtError(rc, f"{lib.grt_status_str(rc).decode()}: {lib.grt_last_error().decode()}")
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    return VP(t.data_ptr())
+
+
+def _stream(stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return VP(stream.cuda_stream)
+
+
+def _dev_f32(t, shape_tail, name, device):
+    if not isinstance(t, torch.Tensor):
+        raise GrtError(ERR_INVALID, f"{name} must be a tensor")
+    if t.dtype != torch.float32 or t.device != device or not t.is_contiguous():
+        raise GrtError(ERR_INVALID, f"{name} must be contiguous float32 on {device}")
+    if tuple(t.shape[1:]) != tuple(shape_tail):
+        raise GrtError(ERR_INVALID, f"{name} has shape {tuple(t.shape)}, want [n,{shape_tail}]")
+    return t
+
+
+# --------------------------------------------------------------------------
+# One-to-one wrappers of the C entry points
+# --------------------------------------------------------------------------
+
+def grt_version() -> int:
+    return load_library().grt_version()
+
+
+def grt_ctx_create(device: int = 0):
+    out = VP()
+    _check(load_library().grt_ctx_create(device, C.byref(out)))
+    return out
+
+
+def grt_ctx_destroy(ctx):
+    _check(load_library().grt_ctx_destroy(ctx))
+
+
+def grt_scene_workspace_bytes(n: int) -> int:
+    return int(load_library().grt_scene_workspace_bytes(n))
+
+
+def _surfels_struct(means, scales, quats, opacity, rgb):
+    dev = means.device
+    n = means.shape[0]
+    _dev_f32(means, (3,), "means", dev); _dev_f32(scales, (2,), "scales", dev); _dev_f32(quats, (4,), "quats", dev)
+    _dev_f32(rgb, (3,), "rgb", dev)
+    if opacity.dtype != torch.float32 or opacity.device != dev or not opacity.is_contiguous() or opacity.dim() != 1:
+        raise GrtError(ERR_INVALID, "opacity must be contiguous float32 [n]")
+    for t in (scales, quats, opacity, rgb):
+        if t.shape[0] != n:
+            raise GrtError(ERR_INVALID, "surfel arrays disagree in length")
+    return grt_surfels(n, _ptr(means), _ptr(scales), _ptr(quats), _ptr(opacity), _ptr(rgb))
+
+
+def grt_scene_create(ctx, surfels: grt_surfels, alpha_min: float, workspace: torch.Tensor):
+    out = VP()
+    _check(load_library().grt_scene_create(ctx, C.byref(surfels), alpha_min, _ptr(workspace), workspace.numel(),
+                                           C.byref(out)))
+    return out
+
+
+def grt_scene_build(scene, stream=None):
+    _check(load_library().grt_scene_build(scene, _stream(stream)))
+
+
+def grt_scene_set_surfels(scene, surfels: grt_surfels):
+    _check(load_library().grt_scene_set_surfels(scene, C.byref(surfels)))
+
+
+def grt_scene_destroy(scene):
+    _check(load_library().grt_scene_destroy(scene))
+
+
+def grt_scene_view_get(scene) -> grt_scene_view:
+    v = grt_scene_view()
+    _check(load_library().grt_scene_view_get(scene, C.byref(v)))
+    return v
+
+
+def grt_trace(scene, rays: grt_rays, opts: grt_trace_opts, out_rgb, out_T, out_L=None, out_nhit=None, stream=None):
+    _check(load_library().grt_trace(scene, C.byref(rays), C.byref(opts), _ptr(out_rgb), _ptr(out_T), _ptr(out_L),
+                                    _ptr(out_nhit), _stream(stream)))
+
+
+def grt_trace_backward(scene, rays, opts, fwd_rgb, fwd_T, grad_rgb, grad_T, grads: grt_surfel_grads, stream=None):
+    _check(load_library().grt_trace_backward(scene, C.byref(rays), C.byref(opts), _ptr(fwd_rgb), _ptr(fwd_T),
+                                             _ptr(grad_rgb), _ptr(grad_T), C.byref(grads), _stream(stream)))
+
+
+def grt_env_workspace_bytes(H: int, W: int) -> int:
+    return int(load_library().grt_env_workspace_bytes(H, W))
+
+
+def grt_env_create(ctx, rgb, H, W, workspace):
+    out = VP()
+    _check(load_library().grt_env_create(ctx, _ptr(rgb), H, W, _ptr(workspace), workspace.numel(), C.byref(out)))
+    return out
+
+
+def grt_env_build(env, stream=None):
+    _check(load_library().grt_env_build(env, _stream(stream)))
+
+
+def grt_env_tables(env):
+    m, c = VP(), VP()
+    _check(load_library().grt_env_tables(env, C.byref(m), C.byref(c)))
+    return m.value, c.value
+
+
+def grt_env_destroy(env):
+    _check(load_library().grt_env_destroy(env))
+
+
+def grt_render_saved_bytes(npix: int, spp: int) -> int:
+    return int(load_library().grt_render_saved_bytes(npix, spp))
+
+
+def grt_render_mis(scene, env, gbuf: grt_gbuffer, opts: grt_mis_opts, out_rgb, saved=None, stream=None):
+    _check(load_library().grt_render_mis(scene, env, C.byref(gbuf), C.byref(opts), _ptr(out_rgb), _ptr(saved),
+                                         _stream(stream)))
+
+
+def grt_render_mis_backward(scene, env, gbuf, opts, grad_rgb, saved, grads: grt_surfel_grads, stream=None):
+    _check(load_library().grt_render_mis_backward(scene, env, C.byref(gbuf), C.byref(opts), _ptr(grad_rgb),
+                                                  _ptr(saved), C.byref(grads), _stream(stream)))
+
+
+# --------------------------------------------------------------------------
+# Owners of handles and workspaces
+# --------------------------------------------------------------------------
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+class Context:
+    def __init__(self, device: int = 0):
+        self.device = torch.device("cuda", device)
+        self.handle = grt_ctx_create(device)
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _LIB is not None:
+            _LIB.grt_ctx_destroy(self.handle)
+            self.handle = None
+
+
+class Scene:
+    """A built LBVH over borrowed surfel tensors (kept alive here)."""
+
+    def __init__(self, ctx: Context, means, scales, quats, opacity, rgb, alpha_min: float = 1.0 / 255.0,
+                 build: bool = True, stream=None):
+        self.ctx = ctx
+        self.n = int(means.shape[0])
+        self.tensors = (means, scales, quats, opacity, rgb)
+        st = _surfels_struct(*self.tensors)
+        self.workspace = _workspace(grt_scene_workspace_bytes(self.n), ctx.device)
+        self.handle = grt_scene_create(ctx.handle, st, alpha_min, self.workspace)
+        self.alpha_min = alpha_min
+        if build:
+            self.build(stream)
+
+    def set_surfels(self, means, scales, quats, opacity, rgb):
+        self.tensors = (means, scales, quats, opacity, rgb)
+        grt_scene_set_surfels(self.handle, _surfels_struct(*self.tensors))
+
+    def build(self, stream=None):
+        grt_scene_build(self.handle, stream)
+
+    def view(self):
+        return grt_scene_view_get(self.handle)
+
+    def arrays(self):
+        """Torch views into the built scene: records [n,16], nodes [n-1,16]
+        (float32; children as int32 in words 12-13), leaf boxes [n,6], order [n]."""
+        v = self.view()
+        base = self.workspace.data_ptr()
+
+        def sl(ptr, count, dtype):
+            off = ptr - base
+            return self.workspace[off:off + 4 * count].view(dtype)
+
+        n = self.n
+        return dict(records=sl(v.records, 16 * n, torch.float32).view(n, 16),
+                    nodes=sl(v.nodes, 16 * max(n - 1, 0), torch.float32).view(max(n - 1, 0), 16),
+                    leaf_boxes=sl(v.leaf_boxes, 6 * n, torch.float32).view(n, 6),
+                    order=sl(v.order, n, torch.int32))
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _LIB is not None:
+            _LIB.grt_scene_destroy(self.handle)
+            self.handle = None
+
+
+class Env:
+    """Environment map [H,W,3] with its sampling tables."""
+
+    def __init__(self, ctx: Context, rgb: torch.Tensor, stream=None):
+        if rgb.dim() != 3 or rgb.shape[2] != 3 or rgb.dtype != torch.float32 or not rgb.is_contiguous():
+            raise GrtError(ERR_INVALID, "env must be contiguous float32 [H,W,3]")
+        self.ctx = ctx
+        self.rgb = rgb
+        self.H, self.W = int(rgb.shape[0]), int(rgb.shape[1])
+        self.workspace = _workspace(grt_env_workspace_bytes(self.H, self.W), ctx.device)
+        self.handle = grt_env_create(ctx.handle, rgb, self.H, self.W, self.workspace)
+        grt_env_build(self.handle, stream)
+
+    def tables(self):
+        """(marg [H+1], cond [H,W+1]) as tensors viewing the workspace."""
+        m, c = grt_env_tables(self.handle)
+        base = self.workspace.data_ptr()
+        ws = self.workspace
+        mo, co = (m - base), (c - base)
+        marg = ws[mo:mo + 4 * (self.H + 1)].view(torch.float32)
+        cond = ws[co:co + 4 * self.H * (self.W + 1)].view(torch.float32).view(self.H, self.W + 1)
+        return marg, cond
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _LIB is not None:
+            _LIB.grt_env_destroy(self.handle)
+            self.handle = None
+
+
+def make_rays(origins, dirs, t_min=0.0, t_max=float("inf")):
+    dev = origins.device
+    _dev_f32(origins, (3,), "origins", dev); _dev_f32(dirs, (3,), "dirs", dev)
+    r = grt_rays(origins.shape[0], _ptr(origins), _ptr(dirs), None, None, 0.0, 0.0)
+    if isinstance(t_min, torch.Tensor):
+        r.t_min = _ptr(t_min)
+    else:
+        r.t_min_all = float(t_min)
+    if isinstance(t_max, torch.Tensor):
+        r.t_max = _ptr(t_max)
+    else:
+        r.t_max_all = float(t_max)
+    return r
+
+
+def make_trace_opts(k=16, t_cut=1e-3, sky=(0.5, 0.5, 0.5), hit_ids=None, hit_tau=None):
+    o = grt_trace_opts()
+    o.k = k
+    o.t_cut = t_cut
+    for i in range(3):
+        o.sky[i] = sky[i]
+    o.hit_ids = _ptr(hit_ids)
+    o.hit_tau = _ptr(hit_tau)
+    o.hit_cap = int(hit_ids.shape[1]) if hit_ids is not None else 0
+    return o
+
+
+def trace(scene: Scene, origins, dirs, t_min=0.0, t_max=float("inf"), k=16, t_cut=1e-3, sky=(0.5, 0.5, 0.5),
+          dump_cap=0, stream=None):
+    """Trace every ray; returns dict of rgb [R,3], T [R], L [R,3], nhit [R]
+    (and ids/tau [R,dump_cap] when dump_cap > 0)."""
+    dev = origins.device
+    R = origins.shape[0]
+    out = dict(rgb=torch.empty(R, 3, device=dev), T=torch.empty(R, device=dev), L=torch.empty(R, 3, device=dev),
+               nhit=torch.empty(R, dtype=torch.int32, device=dev))
+    ids = tau = None
+    if dump_cap:
+        ids = torch.empty(R, dump_cap, dtype=torch.int32, device=dev)
+        tau = torch.empty(R, dump_cap, dtype=torch.float32, device=dev)
+        out["ids"], out["tau"] = ids, tau
+    rays = make_rays(origins, dirs, t_min, t_max)
+    opts = make_trace_opts(k, t_cut, sky, ids, tau)
+    grt_trace(scene.handle, rays, opts, out["rgb"], out["T"], out["L"], out["nhit"], stream)
+    return out
+
+
+def zero_grads(n: int, device):
+    return dict(means=torch.zeros(n, 3, device=device), scales=torch.zeros(n, 2, device=device),
+                quats=torch.zeros(n, 4, device=device), opacity=torch.zeros(n, device=device),
+                rgb=torch.zeros(n, 3, device=device))
+
+
+def _grads_struct(g):
+    return grt_surfel_grads(_ptr(g["means"]), _ptr(g["scales"]), _ptr(g["quats"]), _ptr(g["opacity"]),
+                            _ptr(g["rgb"]))
+
+
+def trace_backward(scene: Scene, origins, dirs, fwd_rgb, fwd_T, grad_rgb, grad_T=None, t_min=0.0,
+                   t_max=float("inf"), k=16, t_cut=1e-3, grads=None, stream=None):
+    """Accumulate d/d(surfels) of sum grad_rgb . c_rt + grad_T . T into ``grads``."""
+    if grads is None:
+        grads = zero_grads(scene.n, origins.device)
+    rays = make_rays(origins, dirs, t_min, t_max)
+    opts = make_trace_opts(k, t_cut)
+    grt_trace_backward(scene.handle, rays, opts, fwd_rgb, fwd_T, grad_rgb.contiguous(),
+                       None if grad_T is None else grad_T.contiguous(), _grads_struct(grads), stream)
+    return grads
+
+
+class GBuffer:
+    """Device copy of a shading-state buffer (x, n, wo, albedo, rough, metal, valid)."""
+
+    def __init__(self, H, W, x, n, wo, albedo, rough, metal, valid):
+        self.H, self.W = int(H), int(W)
+        self.x, self.n, self.wo, self.albedo, self.rough, self.metal, self.valid = x, n, wo, albedo, rough, metal, valid
+
+    @staticmethod
+    def from_numpy(gb, device):
+        t = lambda a: torch.from_numpy(a).to(device).contiguous()
+        return GBuffer(gb.H, gb.W, t(gb.x), t(gb.n), t(gb.wo), t(gb.albedo), t(gb.rough), t(gb.metal), t(gb.valid))
+
+    @property
+    def npix(self):
+        return self.H * self.W
+
+    def struct(self):
+        return grt_gbuffer(self.H, self.W, _ptr(self.x), _ptr(self.n), _ptr(self.wo), _ptr(self.albedo),
+                           _ptr(self.rough), _ptr(self.metal), _ptr(self.valid))
+
+
+def make_mis_opts(split=(16, 8, 8), seed=0, job=0, t_min=1e-3, t_cut=1e-3, k=16, dump=None):
+    o = grt_mis_opts()
+    o.n_cos, o.n_ggx, o.n_env = split
+    o.seed = seed
+    o.job = job
+    o.t_min = t_min
+    o.t_cut = t_cut
+    o.k = k
+    o.sample_dump = _ptr(dump)
+    return o
+
+
+def render_mis(scene: Scene, env: Env, gb: GBuffer, split=(16, 8, 8), seed=0, job=0, t_min=1e-3, t_cut=1e-3, k=16,
+               save=False, dump=False, stream=None):
+    """c_pbr [npix,3]; with ``save`` also the per-ray state for the backward,
+    with ``dump`` the per-sample record [npix, spp, 10]."""
+    dev = gb.x.device
+    spp = sum(split)
+    out = torch.empty(gb.npix, 3, device=dev)
+    saved = torch.empty(gb.npix * spp, 4, device=dev) if save else None
+    dmp = torch.zeros(gb.npix, spp, 10, device=dev) if dump else None
+    opts = make_mis_opts(split, seed, job, t_min, t_cut, k, dmp)
+    grt_render_mis(scene.handle, env.handle, gb.struct(), opts, out, saved, stream)
+    res = dict(rgb=out)
+    if save:
+        res["saved"] = saved
+    if dump:
+        res["dump"] = dmp
+    return res
+
+
+def render_mis_backward(scene: Scene, env: Env, gb: GBuffer, grad_rgb, saved, split=(16, 8, 8), seed=0, job=0,
+                        t_min=1e-3, t_cut=1e-3, k=16, grads=None, stream=None):
+    if grads is None:
+        grads = zero_grads(scene.n, gb.x.device)
+    opts = make_mis_opts(split, seed, job, t_min, t_cut, k)
+    grt_render_mis_backward(scene.handle, env.handle, gb.struct(), opts, grad_rgb.contiguous(), saved,
+                            _grads_struct(grads), stream)
+    return grads
+
+
+# --------------------------------------------------------------------------
+# Autograd (Sec. 3.2: gradients backpropagate through the secondary rays)
+# --------------------------------------------------------------------------
+
+class TraceFn(torch.autograd.Function):
+    """(c_rt, T) = Trace(origins, dirs) as a function of the surfel parameters."""
+
+    @staticmethod
+    def forward(ctx_, means, scales, quats, opacity, rgb, origins, dirs, gctx, t_min, k, t_cut, alpha_min):
+        scene = Scene(gctx, means.detach().contiguous(), scales.detach().contiguous(), quats.detach().contiguous(),
+                      opacity.detach().contiguous(), rgb.detach().contiguous(), alpha_min)
+        out = trace(scene, origins, dirs, t_min=t_min, k=k, t_cut=t_cut)
+        ctx_.scene = scene
+        ctx_.cfg = (t_min, k, t_cut)
+        ctx_.save_for_backward(origins, dirs, out["rgb"], out["T"])
+        return out["rgb"], out["T"]
+
+    @staticmethod
+    def backward(ctx_, g_rgb, g_T):
+        origins, dirs, rgb, T = ctx_.saved_tensors
+        t_min, k, t_cut = ctx_.cfg
+        g = trace_backward(ctx_.scene, origins, dirs, rgb, T,
+                           torch.zeros_like(rgb) if g_rgb is None else g_rgb,
+                           None if g_T is None else g_T, t_min=t_min, k=k, t_cut=t_cut)
+        return g["means"], g["scales"], g["quats"], g["opacity"], g["rgb"], None, None, None, None, None, None, None
+
+
+class RenderMISFn(torch.autograd.Function):
+    """c_pbr image as a function of the surfel parameters (Eq. mis)."""
+
+    @staticmethod
+    def forward(ctx_, means, scales, quats, opacity, rgb, gctx, env, gb, split, seed, k, alpha_min):
+        scene = Scene(gctx, means.detach().contiguous(), scales.detach().contiguous(), quats.detach().contiguous(),
+                      opacity.detach().contiguous(), rgb.detach().contiguous(), alpha_min)
+        res = render_mis(scene, env, gb, split=split, seed=seed, k=k, save=True)
+        ctx_.scene, ctx_.env, ctx_.gb, ctx_.cfg = scene, env, gb, (split, seed, k)
+        ctx_.saved_state = res["saved"]
+        return res["rgb"]
+
+    @staticmethod
+    def backward(ctx_, g_rgb):
+        split, seed, k = ctx_.cfg
+        g = render_mis_backward(ctx_.scene, ctx_.env, ctx_.gb, g_rgb, ctx_.saved_state, split=split, seed=seed, k=k)
+        return g["means"], g["scales"], g["quats"], g["opacity"], g["rgb"], None, None, None, None, None, None, None
