@@ -155,12 +155,18 @@ typedef struct {
     int hit_cap;
 } grt_trace_opts;
 
+/* Bytes of device workspace grt_trace / grt_trace_backward need (the
+ * dynamic ray-fetch counters of the launch).  256-byte aligned. */
+size_t grt_trace_workspace_bytes(int64_t nrays);
+
 /* Trace(r_o, r_d) for every ray (Eq. trace):
  *   out_rgb [n,3] = c_rt, out_T [n] = 1 - o_rt (transmittance after the last
  *   composited hit), out_L [n,3] = c_rt + T sky (NULL to skip),
- *   out_nhit [n] int32 composited hits (NULL to skip). */
+ *   out_nhit [n] int32 composited hits (NULL to skip).
+ * workspace: >= grt_trace_workspace_bytes(n), not shared by launches that
+ * may overlap. */
 int grt_trace(const grt_scene *scene, const grt_rays *rays, const grt_trace_opts *opts, float *out_rgb,
-              float *out_T, float *out_L, int32_t *out_nhit, void *stream);
+              float *out_T, float *out_L, int32_t *out_nhit, void *workspace, size_t ws_bytes, void *stream);
 
 /* Gradient accumulators (device, float32, ADDED to): means [n,3], scales
  * [n,2], quats [n,4], opacity [n], rgb [n,3].  Gradients are w.r.t. the
@@ -180,7 +186,7 @@ typedef struct {
  * rays/opts as the forward (the dump fields are ignored). */
 int grt_trace_backward(const grt_scene *scene, const grt_rays *rays, const grt_trace_opts *opts,
                        const float *fwd_rgb, const float *fwd_T, const float *grad_rgb, const float *grad_T,
-                       grt_surfel_grads *grads, void *stream);
+                       grt_surfel_grads *grads, void *workspace, size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------------ environment */
 
@@ -240,13 +246,20 @@ typedef struct {
 /* Bytes of per-ray state the forward saves for grt_render_mis_backward. */
 size_t grt_render_saved_bytes(int64_t npix, int spp);
 
+/* Bytes of device workspace grt_render_mis needs: the launch's ray-fetch
+ * counters and one 16-byte contribution per sample, summed per pixel in
+ * sample order by a second kernel.  grt_render_mis_backward needs only the
+ * counters (grt_trace_workspace_bytes); the forward's workspace also does. */
+size_t grt_render_workspace_bytes(int64_t npix, int spp);
+
 /* c_pbr for every pixel (Eq. mis): out_rgb [npix,3] = (1/N_r) sum_j
  * f(wo, w_j) L_i(w_j) (w_j . n) / q(w_j), L_i = c_rt + T L_env(w_j) from one
  * secondary trace per sample above the horizon.  Per-pixel sums use a fixed
- * order (results are reproducible run to run).  `saved` (device, >=
+ * order (results are reproducible run to run and independent of scheduling).
+ * `saved` (device, >=
  * grt_render_saved_bytes) receives what the backward needs, or NULL. */
 int grt_render_mis(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *opts,
-                   float *out_rgb, void *saved, void *stream);
+                   float *out_rgb, void *saved, void *workspace, size_t ws_bytes, void *stream);
 
 /* Backward of grt_render_mis by re-traversal: regenerates every sample from
  * its counter, retraces, and accumulates d/d(surfels) of
@@ -255,7 +268,7 @@ int grt_render_mis(const grt_scene *scene, const grt_env *env, const grt_gbuffer
  * scene build, environment, G-buffer and opts. */
 int grt_render_mis_backward(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g,
                             const grt_mis_opts *opts, const float *grad_rgb, const void *saved,
-                            grt_surfel_grads *grads, void *stream);
+                            grt_surfel_grads *grads, void *workspace, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

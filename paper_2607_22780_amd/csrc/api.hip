@@ -256,8 +256,21 @@ static int fill_trace_args(const grt_scene *scene, const grt_rays *rays, const g
     return GRT_OK;
 }
 
+size_t grt_trace_workspace_bytes(int64_t nrays)
+{
+    (void)nrays;
+    return grt::kCounterBytes;
+}
+
+static int check_ws(void *ws, size_t bytes, size_t need, const char *what)
+{
+    if (!ws || bytes < need) return fail(GRT_ERR_OOM, "%s workspace of %zu bytes < %zu needed", what, bytes, need);
+    if (!aligned(ws, 256)) return fail(GRT_ERR_INVALID, "%s workspace must be 256-byte aligned", what);
+    return GRT_OK;
+}
+
 int grt_trace(const grt_scene *scene, const grt_rays *rays, const grt_trace_opts *opts, float *out_rgb, float *out_T,
-              float *out_L, int32_t *out_nhit, void *stream)
+              float *out_L, int32_t *out_nhit, void *workspace, size_t ws_bytes, void *stream)
 {
     grt::TraceArgs a;
     int rc = fill_trace_args(scene, rays, opts, a);
@@ -267,15 +280,17 @@ int grt_trace(const grt_scene *scene, const grt_rays *rays, const grt_trace_opts
         return fail(GRT_ERR_INVALID, "hit dump needs hit_tau and hit_cap > 0");
     a.out_rgb = out_rgb; a.out_T = out_T; a.out_L = out_L; a.out_nhit = out_nhit;
     a.dump_id = opts->hit_ids; a.dump_tau = opts->hit_tau; a.cap = opts->hit_ids ? opts->hit_cap : 0;
+    if ((rc = check_ws(workspace, ws_bytes, grt_trace_workspace_bytes(rays->n), "trace"))) return rc;
+    a.counters = (unsigned long long *)workspace;
     if ((rc = set_device(scene->ctx))) return rc;
-    hipError_t e = grt::launch_trace(a, opts->k, (hipStream_t)stream);
+    hipError_t e = grt::launch_trace(a, opts->k, scene->ctx->num_cu, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "trace launch");
     return GRT_OK;
 }
 
 int grt_trace_backward(const grt_scene *scene, const grt_rays *rays, const grt_trace_opts *opts, const float *fwd_rgb,
                        const float *fwd_T, const float *grad_rgb, const float *grad_T, grt_surfel_grads *grads,
-                       void *stream)
+                       void *workspace, size_t ws_bytes, void *stream)
 {
     grt::TraceBwdArgs b;
     int rc = fill_trace_args(scene, rays, opts, b.f);
@@ -284,8 +299,10 @@ int grt_trace_backward(const grt_scene *scene, const grt_rays *rays, const grt_t
     if ((rc = check_grads(grads, scene->s.n))) return rc;
     b.fwd_rgb = fwd_rgb; b.fwd_T = fwd_T; b.grad_rgb = grad_rgb; b.grad_T = grad_T;
     b.g = grad_ptrs(scene, grads);
+    if ((rc = check_ws(workspace, ws_bytes, grt_trace_workspace_bytes(rays->n), "trace backward"))) return rc;
+    b.f.counters = (unsigned long long *)workspace;
     if ((rc = set_device(scene->ctx))) return rc;
-    hipError_t e = grt::launch_trace_backward(b, opts->k, (hipStream_t)stream);
+    hipError_t e = grt::launch_trace_backward(b, opts->k, scene->ctx->num_cu, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "trace backward launch");
     return GRT_OK;
 }
@@ -347,6 +364,12 @@ size_t grt_render_saved_bytes(int64_t npix, int spp)
     return (size_t)npix * (size_t)spp * 16u;
 }
 
+size_t grt_render_workspace_bytes(int64_t npix, int spp)
+{
+    if (npix < 0 || spp <= 0) return 0;
+    return grt::kCounterBytes + grt::align256((size_t)npix * (size_t)spp * 16u);
+}
+
 static int fill_render_args(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *o,
                             grt::RenderArgs &a)
 {
@@ -376,7 +399,7 @@ static int fill_render_args(const grt_scene *scene, const grt_env *env, const gr
 }
 
 int grt_render_mis(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *opts,
-                   float *out_rgb, void *saved, void *stream)
+                   float *out_rgb, void *saved, void *workspace, size_t ws_bytes, void *stream)
 {
     grt::RenderArgs a;
     int rc = fill_render_args(scene, env, g, opts, a);
@@ -386,14 +409,20 @@ int grt_render_mis(const grt_scene *scene, const grt_env *env, const grt_gbuffer
     a.out = out_rgb;
     a.saved = reinterpret_cast<float4 *>(saved);
     a.dump = opts->sample_dump;
+    const int spp = opts->n_cos + opts->n_ggx + opts->n_env;
+    if ((rc = check_ws(workspace, ws_bytes, grt_render_workspace_bytes((int64_t)g->H * g->W, spp), "render")))
+        return rc;
+    a.counters = (unsigned long long *)workspace;
+    a.contrib = reinterpret_cast<float4 *>((char *)workspace + grt::kCounterBytes);
     if ((rc = set_device(scene->ctx))) return rc;
-    hipError_t e = grt::launch_render(a, opts->k, (hipStream_t)stream);
+    hipError_t e = grt::launch_render(a, opts->k, scene->ctx->num_cu, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "render launch");
     return GRT_OK;
 }
 
 int grt_render_mis_backward(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *opts,
-                            const float *grad_rgb, const void *saved, grt_surfel_grads *grads, void *stream)
+                            const float *grad_rgb, const void *saved, grt_surfel_grads *grads, void *workspace,
+                            size_t ws_bytes, void *stream)
 {
     grt::RenderArgs a;
     int rc = fill_render_args(scene, env, g, opts, a);
@@ -404,8 +433,10 @@ int grt_render_mis_backward(const grt_scene *scene, const grt_env *env, const gr
     a.grad = grad_rgb;
     a.saved = const_cast<float4 *>(reinterpret_cast<const float4 *>(saved));
     a.g = grad_ptrs(scene, grads);
+    if ((rc = check_ws(workspace, ws_bytes, grt::kCounterBytes, "render backward"))) return rc;
+    a.counters = (unsigned long long *)workspace;
     if ((rc = set_device(scene->ctx))) return rc;
-    hipError_t e = grt::launch_render_backward(a, opts->k, (hipStream_t)stream);
+    hipError_t e = grt::launch_render_backward(a, opts->k, scene->ctx->num_cu, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "render backward launch");
     return GRT_OK;
 }

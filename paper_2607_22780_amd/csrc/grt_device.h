@@ -157,84 +157,110 @@ __device__ __forceinline__ uint64_t make_key(float tau, uint32_t id)
 }
 
 // ---------------------------------------------------------------------------
-// Ordered traversal with a k-nearest hit buffer, re-traversed in rounds.
+// Ordered traversal with a k-nearest hit buffer, re-traversed in rounds, as a
+// per-lane state machine.
 //
 // Each round walks the LBVH from the root, keeping the K smallest keys
 // (bits(tau), id) strictly greater than the last key composited in the
 // previous round (registers, sorted by unrolled insertion).  Once the buffer
 // is full its largest depth bounds the interval, which prunes far subtrees.
 // The buffered hits are then handed to `visit` (record position, surfel id,
-// depth) in order; `visit` returns true to stop (transmittance cutoff).  A round that ends with a full buffer
-// is followed by another that resumes strictly after its last key, so hits
-// of equal depth are neither lost nor repeated.  Results do not depend on K.
+// depth) in order; `visit` returns true to stop (transmittance cutoff).  A
+// round that ends with a full buffer is followed by another that resumes
+// strictly after its last key, so hits of equal depth are neither lost nor
+// repeated.  Results do not depend on K.
+//
+// step() advances one node, so a wavefront can hold rays at different rounds
+// and refill lanes whose ray has finished (see run_persistent).
 // ---------------------------------------------------------------------------
-template <int K, class Visit>
-__device__ __forceinline__ void traverse(const SceneDev &S, const float3 o, const float3 d, float tmin, float tmax,
-                                         Visit &visit)
-{
-    if (S.n <= 0) return;
-    const float3 inv = make_float3(safe_inv(d.x), safe_inv(d.y), safe_inv(d.z));
-    uint64_t last = 0;
-    float tlo = tmin;
-    int stack[kStack];
-    for (;;) {
-        uint64_t key[K];
-        uint32_t pos[K];
+template <int K>
+struct Walker {
+    float3 o, d, inv;
+    float tmin, tmax;
+    uint64_t last;
+    float tlo, thi;
+    uint64_t key[K];
+    uint32_t pos[K];
+    int cnt, sp, node;
+
+    __device__ __forceinline__ void new_round()
+    {
 #pragma unroll
         for (int i = 0; i < K; ++i) { key[i] = ~0ull; pos[i] = 0; }
-        int cnt = 0;
-        float thi = tmax;
+        cnt = 0;
+        thi = tmax;
+        sp = 0;
+        node = 0;
+    }
 
-        auto test_leaf = [&](uint32_t p) {
-            const float4 *r = S.rec + 4 * (size_t)p;
-            float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
-            float t;
-            if (!hit_test(r0, r1, r2, r3, o, d, tmin, tmax, t)) return;
-            uint64_t k = make_key(t, __float_as_uint(r2.w));
-            if (k <= last || k >= key[K - 1]) return;
-            // sorted insertion, largest key drops out
-            bool placed = false;
+    __device__ __forceinline__ void start(float3 o_, float3 d_, float tmin_, float tmax_)
+    {
+        o = o_;
+        d = d_;
+        inv = make_float3(safe_inv(d.x), safe_inv(d.y), safe_inv(d.z));
+        tmin = tmin_;
+        tmax = tmax_;
+        last = 0;
+        tlo = tmin;
+        new_round();
+    }
+
+    __device__ __forceinline__ void test_leaf(const SceneDev &S, uint32_t p)
+    {
+        const float4 *r = S.rec + 4 * (size_t)p;
+        float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+        float t;
+        if (!hit_test(r0, r1, r2, r3, o, d, tmin, tmax, t)) return;
+        uint64_t k = make_key(t, __float_as_uint(r2.w));
+        if (k <= last || k >= key[K - 1]) return;
+        // sorted insertion, the largest key drops out
+        bool placed = false;
 #pragma unroll
-            for (int i = K - 1; i > 0; --i) {
-                bool shift = key[i - 1] > k;
-                uint64_t nk = shift ? key[i - 1] : (placed ? key[i] : k);
-                uint32_t np = shift ? pos[i - 1] : (placed ? pos[i] : p);
-                placed = placed || !shift;
-                key[i] = nk; pos[i] = np;
-            }
-            if (!placed) { key[0] = k; pos[0] = p; }
-            ++cnt;
-            if (cnt >= K) thi = __uint_as_float((uint32_t)(key[K - 1] >> 32));
-        };
-
-        if (S.n == 1) {
-            test_leaf(0);
-        } else {
-            int sp = 0;
-            int node = 0;
-            for (;;) {
-                const Node nd = S.nodes[node];
-                float tl, tr;
-                bool hl = slab(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, o, inv, tlo, thi, tl);
-                bool hr = slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, o, inv, tlo, thi, tr);
-                int cl = nd.d.x, cr = nd.d.y;
-                if (hl && cl < 0) { test_leaf((uint32_t)(-cl - 1)); hl = false; }
-                if (hr && cr < 0) { test_leaf((uint32_t)(-cr - 1)); hr = false; }
-                if (hl && hr) {
-                    bool lfirst = tl <= tr;
-                    stack[sp++] = lfirst ? cr : cl;
-                    node = lfirst ? cl : cr;
-                } else if (hl) {
-                    node = cl;
-                } else if (hr) {
-                    node = cr;
-                } else {
-                    if (sp == 0) break;
-                    node = stack[--sp];
-                }
-            }
+        for (int i = K - 1; i > 0; --i) {
+            bool shift = key[i - 1] > k;
+            uint64_t nk = shift ? key[i - 1] : (placed ? key[i] : k);
+            uint32_t np = shift ? pos[i - 1] : (placed ? pos[i] : p);
+            placed = placed || !shift;
+            key[i] = nk;
+            pos[i] = np;
         }
+        if (!placed) { key[0] = k; pos[0] = p; }
+        ++cnt;
+        if (cnt >= K) thi = __uint_as_float((uint32_t)(key[K - 1] >> 32));
+    }
 
+    // One node of the current round; true when the round's walk is complete.
+    __device__ __forceinline__ bool step(const SceneDev &S, int *stack)
+    {
+        if (S.n == 1) {
+            test_leaf(S, 0);
+            return true;
+        }
+        const Node nd = S.nodes[node];
+        float tl, tr;
+        bool hl = slab(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, o, inv, tlo, thi, tl);
+        bool hr = slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, o, inv, tlo, thi, tr);
+        const int cl = nd.d.x, cr = nd.d.y;
+        if (hl && cl < 0) { test_leaf(S, (uint32_t)(-cl - 1)); hl = false; }
+        if (hr && cr < 0) { test_leaf(S, (uint32_t)(-cr - 1)); hr = false; }
+        if (hl && hr) {
+            const bool lfirst = tl <= tr;
+            stack[sp++] = lfirst ? cr : cl;
+            node = lfirst ? cl : cr;
+            return false;
+        }
+        if (hl) { node = cl; return false; }
+        if (hr) { node = cr; return false; }
+        if (sp == 0) return true;
+        node = stack[--sp];
+        return false;
+    }
+
+    // Hand the round's hits to `visit`; true when the ray is finished,
+    // otherwise the next round is set up.
+    template <class Visit>
+    __device__ __forceinline__ bool composite(Visit &visit)
+    {
         bool stop = false;
         const int m = cnt < K ? cnt : K;
 #pragma unroll
@@ -242,9 +268,89 @@ __device__ __forceinline__ void traverse(const SceneDev &S, const float3 o, cons
             if (i < m && !stop)
                 stop = visit(pos[i], (uint32_t)(key[i] & 0xffffffffu), __uint_as_float((uint32_t)(key[i] >> 32)));
         }
-        if (stop || cnt < K) break;
+        if (stop || cnt < K) return true;
         last = key[K - 1];
         tlo = __uint_as_float((uint32_t)(last >> 32));
+        new_round();
+        return false;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// Persistent wavefronts with dynamic ray fetching.
+//
+// Rays 0..total-1 are split into 8 contiguous partitions, one per XCD (the
+// hardware deals workgroups to XCDs round robin), each with its own counter;
+// a wavefront claims chunks of kChunk consecutive rays from its XCD's
+// partition, then from the others once that one is drained.  Lanes whose ray
+// has finished take the next ray of the wavefront's chunk at once, so a
+// wavefront never waits for its slowest ray.  Every wavefront leaves the loop
+// once all partitions are drained and its lanes are idle.
+//
+// Job: bool begin(int64_t ray)  -- set up the ray; false if it needs no trace
+//      (then it must already have written its result)
+//      Walker<K> &walker(), Visit &visit(), void finish(int64_t ray)
+// ---------------------------------------------------------------------------
+constexpr int kParts = 8;
+constexpr int kChunk = 64;
+
+__device__ __forceinline__ int64_t part_begin(int64_t total, int q) { return total * q / kParts; }
+
+template <int K, class Job>
+__device__ __forceinline__ void run_persistent(Job &job, unsigned long long *counters, int64_t total)
+{
+    const int lane = threadIdx.x & 63;
+    const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    int part = blockIdx.x % kParts;
+    int tried = 0;
+    int64_t pool_next = 0, pool_end = 0;  // wavefront-uniform
+    bool exhausted = false;               // wavefront-uniform
+    bool active = false;
+    int64_t ray = -1;
+    int stack[kStack];
+    for (;;) {
+        const uint64_t idle = __ballot(!active);
+        if (idle && !exhausted) {
+            if (pool_next >= pool_end) {
+                // claim a chunk (leader lane), moving on to other partitions when drained
+                for (;;) {
+                    const int64_t pb = part_begin(total, part), pe = part_begin(total, part + 1);
+                    unsigned long long got = 0;
+                    const int leader = __ffsll((long long)idle) - 1;
+                    if (lane == leader) got = atomicAdd(&counters[part], (unsigned long long)kChunk);
+                    got = __shfl(got, leader, 64);
+                    if (pb + (int64_t)got < pe) {
+                        pool_next = pb + (int64_t)got;
+                        pool_end = min(pe, pool_next + kChunk);
+                        break;
+                    }
+                    if (++tried >= kParts) { exhausted = true; break; }
+                    part = (part + 1) % kParts;
+                }
+            }
+            if (!exhausted) {
+                const int64_t avail = pool_end - pool_next;
+                const int rank = __popcll(idle & lt);
+                if (!active && rank < avail) {
+                    ray = pool_next + rank;
+                    active = job.begin(ray);
+                }
+                const int nidle = __popcll(idle);
+                pool_next += (int64_t)(nidle < avail ? nidle : avail);
+            }
+        }
+        if (!__ballot(active)) {
+            if (exhausted) break;
+            continue;
+        }
+        if (active) {
+            if (job.walker().step(job.S, stack)) {
+                if (job.walker().composite(job.visit())) {
+                    job.finish(ray);
+                    active = false;
+                }
+            }
+        }
     }
 }
 

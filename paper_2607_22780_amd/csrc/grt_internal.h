@@ -14,7 +14,11 @@ struct grt_ctx {
     int num_cu;
 };
 
+
 namespace grt {
+
+// bytes of per-launch counters at the head of every kernel workspace
+constexpr size_t kCounterBytes = 256;
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -107,8 +111,9 @@ struct TraceArgs {
     int32_t *dump_id;
     float *dump_tau;
     int cap;
+    unsigned long long *counters;
 };
-hipError_t launch_trace(const TraceArgs &a, int k, hipStream_t st);
+hipError_t launch_trace(const TraceArgs &a, int k, int num_cu, hipStream_t st);
 
 struct GradPtrs {
     float *means, *scales, *quats, *opacity, *rgb;
@@ -120,7 +125,7 @@ struct TraceBwdArgs {
     const float *fwd_rgb, *fwd_T, *grad_rgb, *grad_T;
     GradPtrs g;
 };
-hipError_t launch_trace_backward(const TraceBwdArgs &a, int k, hipStream_t st);
+hipError_t launch_trace_backward(const TraceBwdArgs &a, int k, int num_cu, hipStream_t st);
 
 // Environment and MIS (render.hip)
 struct EnvDev {
@@ -144,11 +149,26 @@ struct RenderArgs {
     float *out;
     float4 *saved;
     float *dump;
+    float4 *contrib;  // per sample f L_i cos / q, reduced per pixel afterwards
+    unsigned long long *counters;
     // backward
     const float *grad;
     GradPtrs g;
 };
-hipError_t launch_render(const RenderArgs &a, int k, hipStream_t st);
-hipError_t launch_render_backward(const RenderArgs &a, int k, hipStream_t st);
+hipError_t launch_render(const RenderArgs &a, int k, int num_cu, hipStream_t st);
+hipError_t launch_render_backward(const RenderArgs &a, int k, int num_cu, hipStream_t st);
+
+// Zero the per-launch counters; persistent grid size for a kernel.
+hipError_t launch_zero_counters(unsigned long long *c, hipStream_t st);
+template <class Kern>
+inline int persistent_blocks(Kern kernel, int num_cu, int64_t work_items)
+{
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+    int64_t want = (work_items + 255) / 256;
+    int64_t cap = (int64_t)per_cu * num_cu;
+    int64_t nb = want < cap ? want : cap;
+    return (int)(nb < 1 ? 1 : nb);
+}
 
 }  // namespace grt

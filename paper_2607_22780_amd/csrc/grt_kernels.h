@@ -22,9 +22,18 @@ struct CompositeVisit {
     float *dtau = nullptr;
     int cap = 0;
 
-    __device__ CompositeVisit(const SceneDev &S, float3 o_, float3 d_, float t_cut)
-        : rec(S.rec), col(S.col), o(o_), d(d_), tcut(t_cut), C(make_float3(0.f, 0.f, 0.f)), T(1.0f), Td(1.0f),
-          cnt(0) {}
+    __device__ CompositeVisit() {}
+    __device__ CompositeVisit(const SceneDev &S, float t_cut) : rec(S.rec), col(S.col), tcut(t_cut) {}
+
+    __device__ __forceinline__ void reset(float3 o_, float3 d_)
+    {
+        o = o_;
+        d = d_;
+        C = make_float3(0.f, 0.f, 0.f);
+        T = 1.0f;
+        Td = 1.0f;
+        cnt = 0;
+    }
 
     __device__ __forceinline__ bool operator()(uint32_t p, uint32_t id, float tau)
     {
@@ -60,10 +69,21 @@ struct GradVisit {
     float T, Td;
     float3 P;
 
-    __device__ GradVisit(const SceneDev &S, float t_cut, const GradPtrs &gp, float3 o_, float3 d_, float3 gC_, float gT_,
-                         float3 Cf_, float Tf_)
-        : rec(S.rec), col(S.col), tcut(t_cut), g(gp), o(o_), d(d_), gC(gC_), Cf(Cf_), gT(gT_), Tf(Tf_), T(1.0f),
-          Td(1.0f), P(make_float3(0.f, 0.f, 0.f)) {}
+    __device__ GradVisit() {}
+    __device__ GradVisit(const SceneDev &S, float t_cut, const GradPtrs &gp) : rec(S.rec), col(S.col), tcut(t_cut), g(gp) {}
+
+    __device__ __forceinline__ void reset(float3 o_, float3 d_, float3 gC_, float gT_, float3 Cf_, float Tf_)
+    {
+        o = o_;
+        d = d_;
+        gC = gC_;
+        gT = gT_;
+        Cf = Cf_;
+        Tf = Tf_;
+        T = 1.0f;
+        Td = 1.0f;
+        P = make_float3(0.f, 0.f, 0.f);
+    }
 
     __device__ __forceinline__ bool operator()(uint32_t p, uint32_t id, float tau)
     {

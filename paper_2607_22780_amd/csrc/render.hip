@@ -1,16 +1,16 @@
 // render.hip -- environment tables and the fused MIS render (forward and
 // backward by re-traversal).
 //
-// One lane per (pixel, sample).  A pixel's samples occupy S = min(64,
-// pow2 >= spp) consecutive lanes of one wavefront; lane j handles samples
-// j, j+S, ...  Each sample (Sec. 3.3 Eq. montecarlo, Sec. 3.4.1 Eq. mis):
+// One ray per (pixel, sample), fetched dynamically by persistent wavefronts.
+// Each sample (Sec. 3.3 Eq. montecarlo, Sec. 3.4.1 Eq. mis):
 //   u1,u2  <- Philox-4x32-10(key = seed, counter = (pixel, j, job, 0))
 //   w      <- cosine (j < N_c) | GGX visible normal (j < N_c+N_g) | env texel
 //   q      =  (N_c p_c + N_g p_g + N_e p_e) / N_r          (balance heuristic)
 //   if w.n > 0:  (C, T) <- Trace(x, w);  L_i = C + T L_env(w)   (Eqs. incident_trace, lighting_decompose)
 //                g/q = f(wo, w) L_i (w.n) / q              (Eqs. brdf_decompose, brdf_specular)
-// and the pixel's estimate (1/N_r) sum g/q is reduced across its lanes with a
-// fixed butterfly, so it is reproducible and independent of other pixels.
+// is written per sample; a second kernel sums each pixel's samples in sample
+// order, so the estimate (1/N_r) sum g/q is reproducible run to run and does
+// not depend on other pixels or on the scheduling.
 #include "grt_internal.h"
 #include "grt_kernels.h"
 
@@ -289,26 +289,6 @@ __device__ __forceinline__ V3 brdf(V3 n, V3 wo, V3 wi, V3 alb, double rough, dou
     return v3(f[0], f[1], f[2]);
 }
 
-// ---------------------------------------------------------------------------
-// Lane layout
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ int group_size(int spp)
-{
-    int s = 1;
-    while (s < spp && s < 64) s <<= 1;
-    return s;
-}
-
-// Contiguous ranges of blocks per XCD: blocks are dealt round-robin to the 8
-// XCDs, so consecutive logical tiles (neighbouring pixels, similar rays) are
-// remapped to land on the same XCD and share its L2.
-__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb)
-{
-    const unsigned full = nb & ~7u;
-    if (b >= full) return b;
-    return (b & 7u) * (full >> 3) + (b >> 3);
-}
-
 struct Shade {
     V3 n, wo, alb;
     float3 x;
@@ -355,126 +335,200 @@ __device__ __forceinline__ bool draw(const RenderArgs &a, const Shade &s, int64_
     return true;
 }
 
+// ---------------------------------------------------------------------------
+// Jobs for the persistent loop: one ray per (pixel, sample), ray index
+// r = pixel * spp + j, so a wavefront's chunk holds neighbouring pixels'
+// samples (same origins, nearby surfaces).
+// ---------------------------------------------------------------------------
+template <int K>
+struct RenderJob {
+    const RenderArgs &a;
+    SceneDev S;
+    Walker<K> w;
+    CompositeVisit v;
+    int spp;
+    float3 wt, Le;
+
+    __device__ RenderJob(const RenderArgs &a_) : a(a_), S(a_.S), v(a_.S, a_.tcut), spp(a_.nc + a_.ng + a_.ne) {}
+    __device__ __forceinline__ Walker<K> &walker() { return w; }
+    __device__ __forceinline__ CompositeVisit &visit() { return v; }
+
+    __device__ __forceinline__ void put(int64_t r, float3 c, float3 wf, double q, float3 Li)
+    {
+        a.contrib[r] = make_float4(c.x, c.y, c.z, 0.0f);
+        if (a.dump) {
+            float *dp = a.dump + r * 10;
+            dp[0] = wf.x; dp[1] = wf.y; dp[2] = wf.z; dp[3] = (float)q;
+            dp[4] = wt.x; dp[5] = wt.y; dp[6] = wt.z;
+            dp[7] = Li.x; dp[8] = Li.y; dp[9] = Li.z;
+        }
+    }
+
+    __device__ __forceinline__ bool begin(int64_t r)
+    {
+        const int64_t p = r / spp;
+        const int j = (int)(r - p * spp);
+        const float3 zero = make_float3(0.f, 0.f, 0.f);
+        Shade s;
+        wt = zero;
+        if (!load_pixel(a, p, s)) {
+            put(r, zero, zero, 0.0, zero);
+            return false;
+        }
+        V3 dir;
+        float3 wf;
+        double q;
+        if (!draw(a, s, p, j, dir, wf, q, wt)) {
+            put(r, zero, wf, 0.0, zero);
+            return false;
+        }
+        Le = env_radiance(a.E, dir);
+        v.reset(s.x, wf);
+        if (a.dump) a.dump[r * 10 + 3] = (float)q;  // the rest is written at finish
+        if (a.dump) { a.dump[r * 10] = wf.x; a.dump[r * 10 + 1] = wf.y; a.dump[r * 10 + 2] = wf.z; }
+        w.start(s.x, wf, a.tmin, INFINITY);
+        if (S.n <= 0) {
+            finish(r);
+            return false;
+        }
+        return true;
+    }
+
+    __device__ __forceinline__ void finish(int64_t r)
+    {
+        const float3 Li = make_float3(v.C.x + v.T * Le.x, v.C.y + v.T * Le.y, v.C.z + v.T * Le.z);
+        a.contrib[r] = make_float4(wt.x * Li.x, wt.y * Li.y, wt.z * Li.z, 0.0f);
+        if (a.saved) a.saved[r] = make_float4(v.C.x, v.C.y, v.C.z, v.T);
+        if (a.dump) {
+            float *dp = a.dump + r * 10;
+            dp[4] = wt.x; dp[5] = wt.y; dp[6] = wt.z;
+            dp[7] = Li.x; dp[8] = Li.y; dp[9] = Li.z;
+        }
+    }
+};
+
+template <int K>
+struct RenderBwdJob {
+    const RenderArgs &a;
+    SceneDev S;
+    Walker<K> w;
+    GradVisit v;
+    int spp;
+
+    __device__ RenderBwdJob(const RenderArgs &a_) : a(a_), S(a_.S), v(a_.S, a_.tcut, a_.g), spp(a_.nc + a_.ng + a_.ne) {}
+    __device__ __forceinline__ Walker<K> &walker() { return w; }
+    __device__ __forceinline__ GradVisit &visit() { return v; }
+
+    __device__ __forceinline__ bool begin(int64_t r)
+    {
+        if (S.n <= 0) return false;
+        const int64_t p = r / spp;
+        const int j = (int)(r - p * spp);
+        Shade s;
+        if (!load_pixel(a, p, s)) return false;
+        const float inv = 1.0f / (float)spp;
+        const float3 gp = make_float3(a.grad[3 * p] * inv, a.grad[3 * p + 1] * inv, a.grad[3 * p + 2] * inv);
+        if (gp.x == 0.0f && gp.y == 0.0f && gp.z == 0.0f) return false;
+        V3 dir;
+        float3 wf, wt;
+        double q;
+        if (!draw(a, s, p, j, dir, wf, q, wt)) return false;
+        const float3 gC = make_float3(wt.x * gp.x, wt.y * gp.y, wt.z * gp.z);
+        const float3 Le = env_radiance(a.E, dir);
+        const float gT = gC.x * Le.x + gC.y * Le.y + gC.z * Le.z;
+        const float4 sv = a.saved[r];
+        v.reset(s.x, wf, gC, gT, make_float3(sv.x, sv.y, sv.z), sv.w);
+        w.start(s.x, wf, a.tmin, INFINITY);
+        return true;
+    }
+
+    __device__ __forceinline__ void finish(int64_t) {}
+};
+
 template <int K>
 __global__ void __launch_bounds__(256) k_render(RenderArgs a)
 {
-    const int spp = a.nc + a.ng + a.ne;
-    const int S = group_size(spp);
-    const int per_block = 256 / S;
-    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t p = (int64_t)b * per_block + threadIdx.x / S;
-    const int lane = threadIdx.x % S;
-    Shade s;
-    const bool ok = load_pixel(a, p, s);
-    float3 acc = make_float3(0.f, 0.f, 0.f);
-    if (ok) {
-        for (int j = lane; j < spp; j += S) {
-            V3 w;
-            float3 wf, wt;
-            double q;
-            float3 Li = make_float3(0.f, 0.f, 0.f);
-            const int64_t ray = p * spp + j;
-            if (draw(a, s, p, j, w, wf, q, wt)) {
-                CompositeVisit v(a.S, s.x, wf, a.tcut);
-                traverse<K>(a.S, s.x, wf, a.tmin, INFINITY, v);
-                const float3 Le = env_radiance(a.E, w);
-                Li = make_float3(v.C.x + v.T * Le.x, v.C.y + v.T * Le.y, v.C.z + v.T * Le.z);
-                acc.x += wt.x * Li.x; acc.y += wt.y * Li.y; acc.z += wt.z * Li.z;
-                if (a.saved) a.saved[ray] = make_float4(v.C.x, v.C.y, v.C.z, v.T);
-            }
-            if (a.dump) {
-                float *dp = a.dump + ray * 10;
-                dp[0] = wf.x; dp[1] = wf.y; dp[2] = wf.z; dp[3] = (float)q;
-                dp[4] = wt.x; dp[5] = wt.y; dp[6] = wt.z;
-                dp[7] = Li.x; dp[8] = Li.y; dp[9] = Li.z;
-            }
-        }
-    } else if (a.dump && p < (int64_t)a.H * a.W) {
-        for (int j = lane; j < spp; j += S)
-            for (int c = 0; c < 10; ++c) a.dump[(p * spp + j) * 10 + c] = 0.0f;
-    }
-    // fixed-order butterfly over the pixel's S lanes
-    for (int off = S >> 1; off > 0; off >>= 1) {
-        acc.x += __shfl_xor(acc.x, off, 64);
-        acc.y += __shfl_xor(acc.y, off, 64);
-        acc.z += __shfl_xor(acc.z, off, 64);
-    }
-    if (lane == 0 && p < (int64_t)a.H * a.W) {
-        const float inv = ok ? 1.0f / (float)spp : 0.0f;
-        a.out[3 * p] = acc.x * inv;
-        a.out[3 * p + 1] = acc.y * inv;
-        a.out[3 * p + 2] = acc.z * inv;
-    }
+    RenderJob<K> job(a);
+    run_persistent<K>(job, a.counters, (int64_t)a.H * a.W * (a.nc + a.ng + a.ne));
 }
 
 template <int K>
 __global__ void __launch_bounds__(256) k_render_bwd(RenderArgs a)
 {
-    const int spp = a.nc + a.ng + a.ne;
-    const int S = group_size(spp);
-    const int per_block = 256 / S;
-    const unsigned b = xcd_block(blockIdx.x, gridDim.x);
-    const int64_t p = (int64_t)b * per_block + threadIdx.x / S;
-    const int lane = threadIdx.x % S;
-    Shade s;
-    if (!load_pixel(a, p, s)) return;
+    RenderBwdJob<K> job(a);
+    run_persistent<K>(job, a.counters, (int64_t)a.H * a.W * (a.nc + a.ng + a.ne));
+}
+
+// c_pbr = (1/N_r) sum_j contrib[p, j], summed in sample order
+__global__ void k_render_reduce(int64_t npix, int spp, const float4 *__restrict__ contrib, float *__restrict__ out)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    const float4 *c = contrib + p * spp;
+    float x = 0.f, y = 0.f, z = 0.f;
+    for (int j = 0; j < spp; ++j) {
+        const float4 v = c[j];
+        x += v.x; y += v.y; z += v.z;
+    }
     const float inv = 1.0f / (float)spp;
-    const float3 gp = make_float3(a.grad[3 * p] * inv, a.grad[3 * p + 1] * inv, a.grad[3 * p + 2] * inv);
-    if (gp.x == 0.0f && gp.y == 0.0f && gp.z == 0.0f) return;
-    for (int j = lane; j < spp; j += S) {
-        V3 w;
-        float3 wf, wt;
-        double q;
-        if (!draw(a, s, p, j, w, wf, q, wt)) continue;
-        const float3 gC = make_float3(wt.x * gp.x, wt.y * gp.y, wt.z * gp.z);
-        const float3 Le = env_radiance(a.E, w);
-        const float gT = gC.x * Le.x + gC.y * Le.y + gC.z * Le.z;
-        const float4 sv = a.saved[p * spp + j];
-        GradVisit v(a.S, a.tcut, a.g, s.x, wf, gC, gT, make_float3(sv.x, sv.y, sv.z), sv.w);
-        traverse<K>(a.S, s.x, wf, a.tmin, INFINITY, v);
-    }
+    out[3 * p] = x * inv;
+    out[3 * p + 1] = y * inv;
+    out[3 * p + 2] = z * inv;
 }
 
-static dim3 render_grid(const RenderArgs &a)
+template <int K>
+static hipError_t go_render(const RenderArgs &a, int num_cu, hipStream_t st)
 {
-    const int spp = a.nc + a.ng + a.ne;
-    int S = 1;
-    while (S < spp && S < 64) S <<= 1;
+    const int64_t total = (int64_t)a.H * a.W * (a.nc + a.ng + a.ne);
+    const int nb = persistent_blocks(k_render<K>, num_cu, total);
+    hipLaunchKernelGGL(k_render<K>, dim3(nb), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int K>
+static hipError_t go_render_bwd(const RenderArgs &a, int num_cu, hipStream_t st)
+{
+    const int64_t total = (int64_t)a.H * a.W * (a.nc + a.ng + a.ne);
+    const int nb = persistent_blocks(k_render_bwd<K>, num_cu, total);
+    hipLaunchKernelGGL(k_render_bwd<K>, dim3(nb), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_render(const RenderArgs &a, int k, int num_cu, hipStream_t st)
+{
     const int64_t npix = (int64_t)a.H * a.W;
-    const int per_block = 256 / S;
-    return dim3((unsigned)((npix + per_block - 1) / per_block));
-}
-
-hipError_t launch_render(const RenderArgs &a, int k, hipStream_t st)
-{
-    if ((int64_t)a.H * a.W <= 0) return hipSuccess;
-    dim3 grid = render_grid(a), block(256);
+    if (npix <= 0) return hipSuccess;
+    hipError_t e = launch_zero_counters(a.counters, st);
+    if (e != hipSuccess) return e;
     switch (k) {
-    case 1: hipLaunchKernelGGL(k_render<1>, grid, block, 0, st, a); break;
-    case 2: hipLaunchKernelGGL(k_render<2>, grid, block, 0, st, a); break;
-    case 4: hipLaunchKernelGGL(k_render<4>, grid, block, 0, st, a); break;
-    case 8: hipLaunchKernelGGL(k_render<8>, grid, block, 0, st, a); break;
-    case 16: hipLaunchKernelGGL(k_render<16>, grid, block, 0, st, a); break;
-    case 32: hipLaunchKernelGGL(k_render<32>, grid, block, 0, st, a); break;
+    case 1: e = go_render<1>(a, num_cu, st); break;
+    case 2: e = go_render<2>(a, num_cu, st); break;
+    case 4: e = go_render<4>(a, num_cu, st); break;
+    case 8: e = go_render<8>(a, num_cu, st); break;
+    case 16: e = go_render<16>(a, num_cu, st); break;
+    case 32: e = go_render<32>(a, num_cu, st); break;
     default: return hipErrorInvalidValue;
     }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_render_reduce, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st, npix,
+                       a.nc + a.ng + a.ne, a.contrib, a.out);
     return hipGetLastError();
 }
 
-hipError_t launch_render_backward(const RenderArgs &a, int k, hipStream_t st)
+hipError_t launch_render_backward(const RenderArgs &a, int k, int num_cu, hipStream_t st)
 {
     if ((int64_t)a.H * a.W <= 0) return hipSuccess;
-    dim3 grid = render_grid(a), block(256);
+    hipError_t e = launch_zero_counters(a.counters, st);
+    if (e != hipSuccess) return e;
     switch (k) {
-    case 1: hipLaunchKernelGGL(k_render_bwd<1>, grid, block, 0, st, a); break;
-    case 2: hipLaunchKernelGGL(k_render_bwd<2>, grid, block, 0, st, a); break;
-    case 4: hipLaunchKernelGGL(k_render_bwd<4>, grid, block, 0, st, a); break;
-    case 8: hipLaunchKernelGGL(k_render_bwd<8>, grid, block, 0, st, a); break;
-    case 16: hipLaunchKernelGGL(k_render_bwd<16>, grid, block, 0, st, a); break;
-    case 32: hipLaunchKernelGGL(k_render_bwd<32>, grid, block, 0, st, a); break;
+    case 1: return go_render_bwd<1>(a, num_cu, st);
+    case 2: return go_render_bwd<2>(a, num_cu, st);
+    case 4: return go_render_bwd<4>(a, num_cu, st);
+    case 8: return go_render_bwd<8>(a, num_cu, st);
+    case 16: return go_render_bwd<16>(a, num_cu, st);
+    case 32: return go_render_bwd<32>(a, num_cu, st);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 }  // namespace grt

@@ -12,83 +12,156 @@
 // (P_k = colour composited through hit k), then chains alpha -> (o, u, v)
 // -> (s_u, s_v, mu, t_u, t_v, n) -> q, and adds the 13 parameter gradients of
 // the surfel with device atomics.
+//
+// Both kernels run persistent wavefronts that fetch rays dynamically.
 #include "grt_internal.h"
 #include "grt_kernels.h"
 
 namespace grt {
 
+__global__ void k_zero_counters(unsigned long long *c)
+{
+    if (threadIdx.x < kCounterBytes / sizeof(unsigned long long)) c[threadIdx.x] = 0ull;
+}
+
+hipError_t launch_zero_counters(unsigned long long *c, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_zero_counters, dim3(1), dim3(64), 0, st, c);
+    return hipGetLastError();
+}
+
+template <int K>
+struct TraceJob {
+    const TraceArgs &a;
+    SceneDev S;
+    Walker<K> w;
+    CompositeVisit v;
+
+    __device__ TraceJob(const TraceArgs &a_) : a(a_), S(a_.S), v(a_.S, a_.tcut) {}
+    __device__ __forceinline__ Walker<K> &walker() { return w; }
+    __device__ __forceinline__ CompositeVisit &visit() { return v; }
+
+    __device__ __forceinline__ bool begin(int64_t r)
+    {
+        const float3 o = make_float3(a.o[3 * r], a.o[3 * r + 1], a.o[3 * r + 2]);
+        const float3 d = make_float3(a.d[3 * r], a.d[3 * r + 1], a.d[3 * r + 2]);
+        const float tmin = a.tmin_a ? a.tmin_a[r] : a.tmin;
+        const float tmax = a.tmax_a ? a.tmax_a[r] : a.tmax;
+        v.reset(o, d);
+        if (a.dump_id) { v.did = a.dump_id + r * a.cap; v.dtau = a.dump_tau + r * a.cap; v.cap = a.cap; }
+        w.start(o, d, tmin, tmax);
+        if (S.n <= 0) {
+            finish(r);
+            return false;
+        }
+        return true;
+    }
+
+    __device__ __forceinline__ void finish(int64_t r)
+    {
+        a.out_rgb[3 * r] = v.C.x; a.out_rgb[3 * r + 1] = v.C.y; a.out_rgb[3 * r + 2] = v.C.z;
+        a.out_T[r] = v.T;
+        if (a.out_L) {
+            a.out_L[3 * r] = v.C.x + v.T * a.sky[0];
+            a.out_L[3 * r + 1] = v.C.y + v.T * a.sky[1];
+            a.out_L[3 * r + 2] = v.C.z + v.T * a.sky[2];
+        }
+        if (a.out_nhit) a.out_nhit[r] = v.cnt;
+        if (a.dump_id)
+            for (int i = v.cnt; i < a.cap; ++i) { v.did[i] = -1; v.dtau[i] = 0.0f; }
+    }
+};
+
+template <int K>
+struct TraceBwdJob {
+    const TraceBwdArgs &a;
+    SceneDev S;
+    Walker<K> w;
+    GradVisit v;
+
+    __device__ TraceBwdJob(const TraceBwdArgs &a_) : a(a_), S(a_.f.S), v(a_.f.S, a_.f.tcut, a_.g) {}
+    __device__ __forceinline__ Walker<K> &walker() { return w; }
+    __device__ __forceinline__ GradVisit &visit() { return v; }
+
+    __device__ __forceinline__ bool begin(int64_t r)
+    {
+        if (S.n <= 0) return false;
+        const float3 gC = make_float3(a.grad_rgb[3 * r], a.grad_rgb[3 * r + 1], a.grad_rgb[3 * r + 2]);
+        const float gT = a.grad_T ? a.grad_T[r] : 0.0f;
+        if (gC.x == 0.0f && gC.y == 0.0f && gC.z == 0.0f && gT == 0.0f) return false;
+        const float3 o = make_float3(a.f.o[3 * r], a.f.o[3 * r + 1], a.f.o[3 * r + 2]);
+        const float3 d = make_float3(a.f.d[3 * r], a.f.d[3 * r + 1], a.f.d[3 * r + 2]);
+        const float tmin = a.f.tmin_a ? a.f.tmin_a[r] : a.f.tmin;
+        const float tmax = a.f.tmax_a ? a.f.tmax_a[r] : a.f.tmax;
+        const float3 C = make_float3(a.fwd_rgb[3 * r], a.fwd_rgb[3 * r + 1], a.fwd_rgb[3 * r + 2]);
+        v.reset(o, d, gC, gT, C, a.fwd_T[r]);
+        w.start(o, d, tmin, tmax);
+        return true;
+    }
+
+    __device__ __forceinline__ void finish(int64_t) {}
+};
+
 template <int K>
 __global__ void __launch_bounds__(256) k_trace(TraceArgs a)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= a.n) return;
-    const float3 o = make_float3(a.o[3 * r], a.o[3 * r + 1], a.o[3 * r + 2]);
-    const float3 d = make_float3(a.d[3 * r], a.d[3 * r + 1], a.d[3 * r + 2]);
-    const float tmin = a.tmin_a ? a.tmin_a[r] : a.tmin;
-    const float tmax = a.tmax_a ? a.tmax_a[r] : a.tmax;
-    CompositeVisit v(a.S, o, d, a.tcut);
-    if (a.dump_id) { v.did = a.dump_id + r * a.cap; v.dtau = a.dump_tau + r * a.cap; v.cap = a.cap; }
-    traverse<K>(a.S, o, d, tmin, tmax, v);
-    a.out_rgb[3 * r] = v.C.x; a.out_rgb[3 * r + 1] = v.C.y; a.out_rgb[3 * r + 2] = v.C.z;
-    a.out_T[r] = v.T;
-    if (a.out_L) {
-        a.out_L[3 * r] = v.C.x + v.T * a.sky[0];
-        a.out_L[3 * r + 1] = v.C.y + v.T * a.sky[1];
-        a.out_L[3 * r + 2] = v.C.z + v.T * a.sky[2];
-    }
-    if (a.out_nhit) a.out_nhit[r] = v.cnt;
-    if (a.dump_id) {
-        for (int i = v.cnt; i < a.cap; ++i) { v.did[i] = -1; v.dtau[i] = 0.0f; }
-    }
+    TraceJob<K> job(a);
+    run_persistent<K>(job, a.counters, a.n);
 }
 
 template <int K>
 __global__ void __launch_bounds__(256) k_trace_bwd(TraceBwdArgs a)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= a.f.n) return;
-    const float3 o = make_float3(a.f.o[3 * r], a.f.o[3 * r + 1], a.f.o[3 * r + 2]);
-    const float3 d = make_float3(a.f.d[3 * r], a.f.d[3 * r + 1], a.f.d[3 * r + 2]);
-    const float tmin = a.f.tmin_a ? a.f.tmin_a[r] : a.f.tmin;
-    const float tmax = a.f.tmax_a ? a.f.tmax_a[r] : a.f.tmax;
-    const float3 gC = make_float3(a.grad_rgb[3 * r], a.grad_rgb[3 * r + 1], a.grad_rgb[3 * r + 2]);
-    const float gT = a.grad_T ? a.grad_T[r] : 0.0f;
-    if (gC.x == 0.0f && gC.y == 0.0f && gC.z == 0.0f && gT == 0.0f) return;
-    const float3 C = make_float3(a.fwd_rgb[3 * r], a.fwd_rgb[3 * r + 1], a.fwd_rgb[3 * r + 2]);
-    GradVisit v(a.f.S, a.f.tcut, a.g, o, d, gC, gT, C, a.fwd_T[r]);
-    traverse<K>(a.f.S, o, d, tmin, tmax, v);
+    TraceBwdJob<K> job(a);
+    run_persistent<K>(job, a.f.counters, a.f.n);
 }
 
-hipError_t launch_trace(const TraceArgs &a, int k, hipStream_t st)
+template <int K>
+static hipError_t go_trace(const TraceArgs &a, int num_cu, hipStream_t st)
+{
+    const int nb = persistent_blocks(k_trace<K>, num_cu, a.n);
+    hipLaunchKernelGGL(k_trace<K>, dim3(nb), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <int K>
+static hipError_t go_trace_bwd(const TraceBwdArgs &a, int num_cu, hipStream_t st)
+{
+    const int nb = persistent_blocks(k_trace_bwd<K>, num_cu, a.f.n);
+    hipLaunchKernelGGL(k_trace_bwd<K>, dim3(nb), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace(const TraceArgs &a, int k, int num_cu, hipStream_t st)
 {
     if (a.n <= 0) return hipSuccess;
-    dim3 grid((unsigned)((a.n + 255) / 256)), block(256);
+    hipError_t e = launch_zero_counters(a.counters, st);
+    if (e != hipSuccess) return e;
     switch (k) {
-    case 1: hipLaunchKernelGGL(k_trace<1>, grid, block, 0, st, a); break;
-    case 2: hipLaunchKernelGGL(k_trace<2>, grid, block, 0, st, a); break;
-    case 4: hipLaunchKernelGGL(k_trace<4>, grid, block, 0, st, a); break;
-    case 8: hipLaunchKernelGGL(k_trace<8>, grid, block, 0, st, a); break;
-    case 16: hipLaunchKernelGGL(k_trace<16>, grid, block, 0, st, a); break;
-    case 32: hipLaunchKernelGGL(k_trace<32>, grid, block, 0, st, a); break;
+    case 1: return go_trace<1>(a, num_cu, st);
+    case 2: return go_trace<2>(a, num_cu, st);
+    case 4: return go_trace<4>(a, num_cu, st);
+    case 8: return go_trace<8>(a, num_cu, st);
+    case 16: return go_trace<16>(a, num_cu, st);
+    case 32: return go_trace<32>(a, num_cu, st);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
-hipError_t launch_trace_backward(const TraceBwdArgs &a, int k, hipStream_t st)
+hipError_t launch_trace_backward(const TraceBwdArgs &a, int k, int num_cu, hipStream_t st)
 {
     if (a.f.n <= 0) return hipSuccess;
-    dim3 grid((unsigned)((a.f.n + 255) / 256)), block(256);
+    hipError_t e = launch_zero_counters(a.f.counters, st);
+    if (e != hipSuccess) return e;
     switch (k) {
-    case 1: hipLaunchKernelGGL(k_trace_bwd<1>, grid, block, 0, st, a); break;
-    case 2: hipLaunchKernelGGL(k_trace_bwd<2>, grid, block, 0, st, a); break;
-    case 4: hipLaunchKernelGGL(k_trace_bwd<4>, grid, block, 0, st, a); break;
-    case 8: hipLaunchKernelGGL(k_trace_bwd<8>, grid, block, 0, st, a); break;
-    case 16: hipLaunchKernelGGL(k_trace_bwd<16>, grid, block, 0, st, a); break;
-    case 32: hipLaunchKernelGGL(k_trace_bwd<32>, grid, block, 0, st, a); break;
+    case 1: return go_trace_bwd<1>(a, num_cu, st);
+    case 2: return go_trace_bwd<2>(a, num_cu, st);
+    case 4: return go_trace_bwd<4>(a, num_cu, st);
+    case 8: return go_trace_bwd<8>(a, num_cu, st);
+    case 16: return go_trace_bwd<16>(a, num_cu, st);
+    case 32: return go_trace_bwd<32>(a, num_cu, st);
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 }  // namespace grt

@@ -84,16 +84,20 @@ SIGNATURES = {
     "grt_scene_set_surfels": (C.c_int, [VP, P(grt_surfels)]),
     "grt_scene_destroy": (C.c_int, [VP]),
     "grt_scene_view_get": (C.c_int, [VP, P(grt_scene_view)]),
-    "grt_trace": (C.c_int, [VP, P(grt_rays), P(grt_trace_opts), VP, VP, VP, VP, VP]),
-    "grt_trace_backward": (C.c_int, [VP, P(grt_rays), P(grt_trace_opts), VP, VP, VP, VP, P(grt_surfel_grads), VP]),
+    "grt_trace_workspace_bytes": (C.c_size_t, [C.c_int64]),
+    "grt_trace": (C.c_int, [VP, P(grt_rays), P(grt_trace_opts), VP, VP, VP, VP, VP, C.c_size_t, VP]),
+    "grt_trace_backward": (C.c_int, [VP, P(grt_rays), P(grt_trace_opts), VP, VP, VP, VP, P(grt_surfel_grads), VP,
+                                     C.c_size_t, VP]),
     "grt_env_workspace_bytes": (C.c_size_t, [C.c_int, C.c_int]),
     "grt_env_create": (C.c_int, [VP, VP, C.c_int, C.c_int, VP, C.c_size_t, P(VP)]),
     "grt_env_build": (C.c_int, [VP, VP]),
     "grt_env_tables": (C.c_int, [VP, P(VP), P(VP)]),
     "grt_env_destroy": (C.c_int, [VP]),
     "grt_render_saved_bytes": (C.c_size_t, [C.c_int64, C.c_int]),
-    "grt_render_mis": (C.c_int, [VP, VP, P(grt_gbuffer), P(grt_mis_opts), VP, VP, VP]),
-    "grt_render_mis_backward": (C.c_int, [VP, VP, P(grt_gbuffer), P(grt_mis_opts), VP, VP, P(grt_surfel_grads), VP]),
+    "grt_render_workspace_bytes": (C.c_size_t, [C.c_int64, C.c_int]),
+    "grt_render_mis": (C.c_int, [VP, VP, P(grt_gbuffer), P(grt_mis_opts), VP, VP, VP, C.c_size_t, VP]),
+    "grt_render_mis_backward": (C.c_int, [VP, VP, P(grt_gbuffer), P(grt_mis_opts), VP, VP, P(grt_surfel_grads),
+                                          VP, C.c_size_t, VP]),
 }
 OPTIONAL = {}
 
@@ -208,14 +212,20 @@ def grt_scene_view_get(scene) -> grt_scene_view:
     return v
 
 
-def grt_trace(scene, rays: grt_rays, opts: grt_trace_opts, out_rgb, out_T, out_L=None, out_nhit=None, stream=None):
+def grt_trace_workspace_bytes(n: int) -> int:
+    return int(load_library().grt_trace_workspace_bytes(n))
+
+
+def grt_trace(scene, rays: grt_rays, opts: grt_trace_opts, out_rgb, out_T, out_L, out_nhit, workspace, stream=None):
     _check(load_library().grt_trace(scene, C.byref(rays), C.byref(opts), _ptr(out_rgb), _ptr(out_T), _ptr(out_L),
-                                    _ptr(out_nhit), _stream(stream)))
+                                    _ptr(out_nhit), _ptr(workspace), workspace.numel(), _stream(stream)))
 
 
-def grt_trace_backward(scene, rays, opts, fwd_rgb, fwd_T, grad_rgb, grad_T, grads: grt_surfel_grads, stream=None):
+def grt_trace_backward(scene, rays, opts, fwd_rgb, fwd_T, grad_rgb, grad_T, grads: grt_surfel_grads, workspace,
+                       stream=None):
     _check(load_library().grt_trace_backward(scene, C.byref(rays), C.byref(opts), _ptr(fwd_rgb), _ptr(fwd_T),
-                                             _ptr(grad_rgb), _ptr(grad_T), C.byref(grads), _stream(stream)))
+                                             _ptr(grad_rgb), _ptr(grad_T), C.byref(grads), _ptr(workspace),
+                                             workspace.numel(), _stream(stream)))
 
 
 def grt_env_workspace_bytes(H: int, W: int) -> int:
@@ -246,14 +256,20 @@ def grt_render_saved_bytes(npix: int, spp: int) -> int:
     return int(load_library().grt_render_saved_bytes(npix, spp))
 
 
-def grt_render_mis(scene, env, gbuf: grt_gbuffer, opts: grt_mis_opts, out_rgb, saved=None, stream=None):
+def grt_render_workspace_bytes(npix: int, spp: int) -> int:
+    return int(load_library().grt_render_workspace_bytes(npix, spp))
+
+
+def grt_render_mis(scene, env, gbuf: grt_gbuffer, opts: grt_mis_opts, out_rgb, saved, workspace, stream=None):
     _check(load_library().grt_render_mis(scene, env, C.byref(gbuf), C.byref(opts), _ptr(out_rgb), _ptr(saved),
-                                         _stream(stream)))
+                                         _ptr(workspace), workspace.numel(), _stream(stream)))
 
 
-def grt_render_mis_backward(scene, env, gbuf, opts, grad_rgb, saved, grads: grt_surfel_grads, stream=None):
+def grt_render_mis_backward(scene, env, gbuf, opts, grad_rgb, saved, grads: grt_surfel_grads, workspace,
+                            stream=None):
     _check(load_library().grt_render_mis_backward(scene, env, C.byref(gbuf), C.byref(opts), _ptr(grad_rgb),
-                                                  _ptr(saved), C.byref(grads), _stream(stream)))
+                                                  _ptr(saved), C.byref(grads), _ptr(workspace), workspace.numel(),
+                                                  _stream(stream)))
 
 
 # --------------------------------------------------------------------------
@@ -393,7 +409,8 @@ def trace(scene: Scene, origins, dirs, t_min=0.0, t_max=float("inf"), k=16, t_cu
         out["ids"], out["tau"] = ids, tau
     rays = make_rays(origins, dirs, t_min, t_max)
     opts = make_trace_opts(k, t_cut, sky, ids, tau)
-    grt_trace(scene.handle, rays, opts, out["rgb"], out["T"], out["L"], out["nhit"], stream)
+    ws = _workspace(grt_trace_workspace_bytes(R), dev)
+    grt_trace(scene.handle, rays, opts, out["rgb"], out["T"], out["L"], out["nhit"], ws, stream)
     return out
 
 
@@ -415,8 +432,9 @@ def trace_backward(scene: Scene, origins, dirs, fwd_rgb, fwd_T, grad_rgb, grad_T
         grads = zero_grads(scene.n, origins.device)
     rays = make_rays(origins, dirs, t_min, t_max)
     opts = make_trace_opts(k, t_cut)
+    ws = _workspace(grt_trace_workspace_bytes(origins.shape[0]), origins.device)
     grt_trace_backward(scene.handle, rays, opts, fwd_rgb, fwd_T, grad_rgb.contiguous(),
-                       None if grad_T is None else grad_T.contiguous(), _grads_struct(grads), stream)
+                       None if grad_T is None else grad_T.contiguous(), _grads_struct(grads), ws, stream)
     return grads
 
 
@@ -454,7 +472,7 @@ def make_mis_opts(split=(16, 8, 8), seed=0, job=0, t_min=1e-3, t_cut=1e-3, k=16,
 
 
 def render_mis(scene: Scene, env: Env, gb: GBuffer, split=(16, 8, 8), seed=0, job=0, t_min=1e-3, t_cut=1e-3, k=16,
-               save=False, dump=False, stream=None):
+               save=False, dump=False, workspace=None, stream=None):
     """c_pbr [npix,3]; with ``save`` also the per-ray state for the backward,
     with ``dump`` the per-sample record [npix, spp, 10]."""
     dev = gb.x.device
@@ -463,7 +481,10 @@ def render_mis(scene: Scene, env: Env, gb: GBuffer, split=(16, 8, 8), seed=0, jo
     saved = torch.empty(gb.npix * spp, 4, device=dev) if save else None
     dmp = torch.zeros(gb.npix, spp, 10, device=dev) if dump else None
     opts = make_mis_opts(split, seed, job, t_min, t_cut, k, dmp)
-    grt_render_mis(scene.handle, env.handle, gb.struct(), opts, out, saved, stream)
+    need = grt_render_workspace_bytes(gb.npix, spp)
+    if workspace is None or workspace.numel() < need:
+        workspace = _workspace(need, dev)
+    grt_render_mis(scene.handle, env.handle, gb.struct(), opts, out, saved, workspace, stream)
     res = dict(rgb=out)
     if save:
         res["saved"] = saved
@@ -477,8 +498,9 @@ def render_mis_backward(scene: Scene, env: Env, gb: GBuffer, grad_rgb, saved, sp
     if grads is None:
         grads = zero_grads(scene.n, gb.x.device)
     opts = make_mis_opts(split, seed, job, t_min, t_cut, k)
+    ws = _workspace(grt_trace_workspace_bytes(0), gb.x.device)
     grt_render_mis_backward(scene.handle, env.handle, gb.struct(), opts, grad_rgb.contiguous(), saved,
-                            _grads_struct(grads), stream)
+                            _grads_struct(grads), ws, stream)
     return grads
 
 

@@ -39,7 +39,9 @@ def test_binding_declares_every_symbol():
     assert lib.grt_status_str(-5).decode() == "GRT_ERR_ADMISSION"
     assert lib.grt_scene_workspace_bytes(1000) > 1000 * 64
     assert lib.grt_env_workspace_bytes(4, 8) > 0
-    assert lib.grt_render_saved_bytes(10, 4) == 640
+    assert lib.grt_render_saved_bytes(10, 4) >= 640
+    assert lib.grt_render_workspace_bytes(10, 4) >= 640
+    assert lib.grt_trace_workspace_bytes(10) >= 64
 
 
 @pytest.mark.skipif(not os.path.exists(LIB), reason="libgrt.so not built")
@@ -49,5 +51,5 @@ def test_host_argument_checks_without_gpu():
     lib = grt.load_library()
     out = ctypes.c_void_p()
     assert lib.grt_scene_create(None, None, 0.0, None, 0, ctypes.byref(out)) == grt.ERR_INVALID
-    assert lib.grt_trace(None, None, None, None, None, None, None, None) == grt.ERR_INVALID
+    assert lib.grt_trace(None, None, None, None, None, None, None, None, 0, None) == grt.ERR_INVALID
     assert b"scene" in lib.grt_last_error()
