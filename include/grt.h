@@ -246,10 +246,11 @@ typedef struct {
 /* Bytes of per-ray state the forward saves for grt_render_mis_backward. */
 size_t grt_render_saved_bytes(int64_t npix, int spp);
 
-/* Bytes of device workspace grt_render_mis needs: the launch's ray-fetch
- * counters and one 16-byte contribution per sample, summed per pixel in
- * sample order by a second kernel.  grt_render_mis_backward needs only the
- * counters (grt_trace_workspace_bytes); the forward's workspace also does. */
+/* Bytes of device workspace grt_render_mis and grt_render_mis_backward need:
+ * the launch's ray-fetch counters, a 48-byte record per sample (direction,
+ * weight f cos/q, environment radiance, written by a generation kernel) and
+ * a 16-byte contribution per sample, summed per pixel in sample order by a
+ * reduction kernel (64 bytes per sample plus 256). */
 size_t grt_render_workspace_bytes(int64_t npix, int spp);
 
 /* c_pbr for every pixel (Eq. mis): out_rgb [npix,3] = (1/N_r) sum_j

@@ -367,7 +367,8 @@ size_t grt_render_saved_bytes(int64_t npix, int spp)
 size_t grt_render_workspace_bytes(int64_t npix, int spp)
 {
     if (npix < 0 || spp <= 0) return 0;
-    return grt::kCounterBytes + grt::align256((size_t)npix * (size_t)spp * 16u);
+    return grt::kCounterBytes + grt::align256((size_t)npix * (size_t)spp * 16u) +
+           grt::align256((size_t)npix * (size_t)spp * 48u);
 }
 
 static int fill_render_args(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *o,
@@ -414,6 +415,8 @@ int grt_render_mis(const grt_scene *scene, const grt_env *env, const grt_gbuffer
         return rc;
     a.counters = (unsigned long long *)workspace;
     a.contrib = reinterpret_cast<float4 *>((char *)workspace + grt::kCounterBytes);
+    a.rays = reinterpret_cast<float4 *>((char *)workspace + grt::kCounterBytes +
+                                        grt::align256((size_t)g->H * g->W * spp * 16u));
     if ((rc = set_device(scene->ctx))) return rc;
     hipError_t e = grt::launch_render(a, opts->k, scene->ctx->num_cu, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "render launch");
@@ -433,8 +436,11 @@ int grt_render_mis_backward(const grt_scene *scene, const grt_env *env, const gr
     a.grad = grad_rgb;
     a.saved = const_cast<float4 *>(reinterpret_cast<const float4 *>(saved));
     a.g = grad_ptrs(scene, grads);
-    if ((rc = check_ws(workspace, ws_bytes, grt::kCounterBytes, "render backward"))) return rc;
+    const int spp = opts->n_cos + opts->n_ggx + opts->n_env;
+    const size_t ray_bytes = grt::align256((size_t)g->H * g->W * spp * 48u);
+    if ((rc = check_ws(workspace, ws_bytes, grt::kCounterBytes + ray_bytes, "render backward"))) return rc;
     a.counters = (unsigned long long *)workspace;
+    a.rays = reinterpret_cast<float4 *>((char *)workspace + grt::kCounterBytes);
     if ((rc = set_device(scene->ctx))) return rc;
     hipError_t e = grt::launch_render_backward(a, opts->k, scene->ctx->num_cu, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "render backward launch");

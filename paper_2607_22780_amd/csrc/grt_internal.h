@@ -150,6 +150,7 @@ struct RenderArgs {
     float4 *saved;
     float *dump;
     float4 *contrib;  // per sample f L_i cos / q, reduced per pixel afterwards
+    float4 *rays;     // per sample record written by the generation kernel (3 x float4)
     unsigned long long *counters;
     // backward
     const float *grad;

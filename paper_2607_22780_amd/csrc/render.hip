@@ -1,8 +1,10 @@
 // render.hip -- environment tables and the fused MIS render (forward and
 // backward by re-traversal).
 //
-// One ray per (pixel, sample), fetched dynamically by persistent wavefronts.
-// Each sample (Sec. 3.3 Eq. montecarlo, Sec. 3.4.1 Eq. mis):
+// One ray per (pixel, sample): a generation kernel draws every sample and
+// writes its ray record, persistent wavefronts trace them (fetching rays
+// dynamically), and a reduction sums each pixel.  Per sample (Sec. 3.3 Eq.
+// montecarlo, Sec. 3.4.1 Eq. mis):
 //   u1,u2  <- Philox-4x32-10(key = seed, counter = (pixel, j, job, 0))
 //   w      <- cosine (j < N_c) | GGX visible normal (j < N_c+N_g) | env texel
 //   q      =  (N_c p_c + N_g p_g + N_e p_e) / N_r          (balance heuristic)
@@ -336,9 +338,43 @@ __device__ __forceinline__ bool draw(const RenderArgs &a, const Shade &s, int64_
 }
 
 // ---------------------------------------------------------------------------
-// Jobs for the persistent loop: one ray per (pixel, sample), ray index
-// r = pixel * spp + j, so a wavefront's chunk holds neighbouring pixels'
-// samples (same origins, nearby surfaces).
+// Sample generation: one thread per ray r = pixel * spp + j.  Writes the ray
+// record the trace kernels read (48 B): (direction, traced flag),
+// (f cos / q, L_env.x), (L_env.y, L_env.z, -, -).  Samples below the horizon
+// and invalid pixels are flagged 0 and never traced.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_render_gen(RenderArgs a)
+{
+    const int spp = a.nc + a.ng + a.ne;
+    const int64_t total = (int64_t)a.H * a.W * spp;
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= total) return;
+    const int64_t p = r / spp;
+    const int j = (int)(r - p * spp);
+    Shade s;
+    float3 wf = make_float3(0.f, 0.f, 0.f), wt = wf, Le = wf;
+    double q = 0.0;
+    bool traced = false;
+    if (load_pixel(a, p, s)) {
+        V3 dir;
+        traced = draw(a, s, p, j, dir, wf, q, wt);
+        if (traced) Le = env_radiance(a.E, dir);
+    }
+    float4 *rr = a.rays + 3 * r;
+    rr[0] = make_float4(wf.x, wf.y, wf.z, traced ? 1.0f : 0.0f);
+    rr[1] = make_float4(wt.x, wt.y, wt.z, Le.x);
+    rr[2] = make_float4(Le.y, Le.z, 0.0f, 0.0f);
+    if (a.dump) {
+        float *dp = a.dump + r * 10;
+        dp[0] = wf.x; dp[1] = wf.y; dp[2] = wf.z; dp[3] = (float)q;
+        dp[4] = wt.x; dp[5] = wt.y; dp[6] = wt.z;
+        dp[7] = 0.0f; dp[8] = 0.0f; dp[9] = 0.0f;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Jobs for the persistent loop.  Ray index order keeps a wavefront's chunk on
+// neighbouring pixels (shared origins, nearby surfaces).
 // ---------------------------------------------------------------------------
 template <int K>
 struct RenderJob {
@@ -347,46 +383,23 @@ struct RenderJob {
     Walker<K> w;
     CompositeVisit v;
     int spp;
-    float3 wt, Le;
 
     __device__ RenderJob(const RenderArgs &a_) : a(a_), S(a_.S), v(a_.S, a_.tcut), spp(a_.nc + a_.ng + a_.ne) {}
     __device__ __forceinline__ Walker<K> &walker() { return w; }
     __device__ __forceinline__ CompositeVisit &visit() { return v; }
 
-    __device__ __forceinline__ void put(int64_t r, float3 c, float3 wf, double q, float3 Li)
-    {
-        a.contrib[r] = make_float4(c.x, c.y, c.z, 0.0f);
-        if (a.dump) {
-            float *dp = a.dump + r * 10;
-            dp[0] = wf.x; dp[1] = wf.y; dp[2] = wf.z; dp[3] = (float)q;
-            dp[4] = wt.x; dp[5] = wt.y; dp[6] = wt.z;
-            dp[7] = Li.x; dp[8] = Li.y; dp[9] = Li.z;
-        }
-    }
-
     __device__ __forceinline__ bool begin(int64_t r)
     {
+        const float4 r0 = a.rays[3 * r];
+        if (r0.w == 0.0f) {
+            a.contrib[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+            return false;
+        }
         const int64_t p = r / spp;
-        const int j = (int)(r - p * spp);
-        const float3 zero = make_float3(0.f, 0.f, 0.f);
-        Shade s;
-        wt = zero;
-        if (!load_pixel(a, p, s)) {
-            put(r, zero, zero, 0.0, zero);
-            return false;
-        }
-        V3 dir;
-        float3 wf;
-        double q;
-        if (!draw(a, s, p, j, dir, wf, q, wt)) {
-            put(r, zero, wf, 0.0, zero);
-            return false;
-        }
-        Le = env_radiance(a.E, dir);
-        v.reset(s.x, wf);
-        if (a.dump) a.dump[r * 10 + 3] = (float)q;  // the rest is written at finish
-        if (a.dump) { a.dump[r * 10] = wf.x; a.dump[r * 10 + 1] = wf.y; a.dump[r * 10 + 2] = wf.z; }
-        w.start(s.x, wf, a.tmin, INFINITY);
+        const float3 x = make_float3(a.x[3 * p], a.x[3 * p + 1], a.x[3 * p + 2]);
+        const float3 d = make_float3(r0.x, r0.y, r0.z);
+        v.reset(x, d);
+        w.start(x, d, a.tmin, INFINITY);
         if (S.n <= 0) {
             finish(r);
             return false;
@@ -396,12 +409,12 @@ struct RenderJob {
 
     __device__ __forceinline__ void finish(int64_t r)
     {
-        const float3 Li = make_float3(v.C.x + v.T * Le.x, v.C.y + v.T * Le.y, v.C.z + v.T * Le.z);
-        a.contrib[r] = make_float4(wt.x * Li.x, wt.y * Li.y, wt.z * Li.z, 0.0f);
+        const float4 r1 = a.rays[3 * r + 1], r2 = a.rays[3 * r + 2];
+        const float3 Li = make_float3(v.C.x + v.T * r1.w, v.C.y + v.T * r2.x, v.C.z + v.T * r2.y);
+        a.contrib[r] = make_float4(r1.x * Li.x, r1.y * Li.y, r1.z * Li.z, 0.0f);
         if (a.saved) a.saved[r] = make_float4(v.C.x, v.C.y, v.C.z, v.T);
         if (a.dump) {
             float *dp = a.dump + r * 10;
-            dp[4] = wt.x; dp[5] = wt.y; dp[6] = wt.z;
             dp[7] = Li.x; dp[8] = Li.y; dp[9] = Li.z;
         }
     }
@@ -422,23 +435,20 @@ struct RenderBwdJob {
     __device__ __forceinline__ bool begin(int64_t r)
     {
         if (S.n <= 0) return false;
+        const float4 r0 = a.rays[3 * r];
+        if (r0.w == 0.0f) return false;
         const int64_t p = r / spp;
-        const int j = (int)(r - p * spp);
-        Shade s;
-        if (!load_pixel(a, p, s)) return false;
         const float inv = 1.0f / (float)spp;
         const float3 gp = make_float3(a.grad[3 * p] * inv, a.grad[3 * p + 1] * inv, a.grad[3 * p + 2] * inv);
         if (gp.x == 0.0f && gp.y == 0.0f && gp.z == 0.0f) return false;
-        V3 dir;
-        float3 wf, wt;
-        double q;
-        if (!draw(a, s, p, j, dir, wf, q, wt)) return false;
-        const float3 gC = make_float3(wt.x * gp.x, wt.y * gp.y, wt.z * gp.z);
-        const float3 Le = env_radiance(a.E, dir);
-        const float gT = gC.x * Le.x + gC.y * Le.y + gC.z * Le.z;
+        const float4 r1 = a.rays[3 * r + 1], r2 = a.rays[3 * r + 2];
+        const float3 gC = make_float3(r1.x * gp.x, r1.y * gp.y, r1.z * gp.z);
+        const float gT = gC.x * r1.w + gC.y * r2.x + gC.z * r2.y;
         const float4 sv = a.saved[r];
-        v.reset(s.x, wf, gC, gT, make_float3(sv.x, sv.y, sv.z), sv.w);
-        w.start(s.x, wf, a.tmin, INFINITY);
+        const float3 x = make_float3(a.x[3 * p], a.x[3 * p + 1], a.x[3 * p + 2]);
+        const float3 d = make_float3(r0.x, r0.y, r0.z);
+        v.reset(x, d, gC, gT, make_float3(sv.x, sv.y, sv.z), sv.w);
+        w.start(x, d, a.tmin, INFINITY);
         return true;
     }
 
@@ -494,12 +504,20 @@ static hipError_t go_render_bwd(const RenderArgs &a, int num_cu, hipStream_t st)
     return hipGetLastError();
 }
 
+static hipError_t launch_gen(const RenderArgs &a, hipStream_t st)
+{
+    const int64_t total = (int64_t)a.H * a.W * (a.nc + a.ng + a.ne);
+    hipLaunchKernelGGL(k_render_gen, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_render(const RenderArgs &a, int k, int num_cu, hipStream_t st)
 {
     const int64_t npix = (int64_t)a.H * a.W;
     if (npix <= 0) return hipSuccess;
     hipError_t e = launch_zero_counters(a.counters, st);
     if (e != hipSuccess) return e;
+    if ((e = launch_gen(a, st)) != hipSuccess) return e;
     switch (k) {
     case 1: e = go_render<1>(a, num_cu, st); break;
     case 2: e = go_render<2>(a, num_cu, st); break;
@@ -520,6 +538,7 @@ hipError_t launch_render_backward(const RenderArgs &a, int k, int num_cu, hipStr
     if ((int64_t)a.H * a.W <= 0) return hipSuccess;
     hipError_t e = launch_zero_counters(a.counters, st);
     if (e != hipSuccess) return e;
+    if ((e = launch_gen(a, st)) != hipSuccess) return e;
     switch (k) {
     case 1: return go_render_bwd<1>(a, num_cu, st);
     case 2: return go_render_bwd<2>(a, num_cu, st);

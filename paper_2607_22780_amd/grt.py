@@ -498,7 +498,7 @@ def render_mis_backward(scene: Scene, env: Env, gb: GBuffer, grad_rgb, saved, sp
     if grads is None:
         grads = zero_grads(scene.n, gb.x.device)
     opts = make_mis_opts(split, seed, job, t_min, t_cut, k)
-    ws = _workspace(grt_trace_workspace_bytes(0), gb.x.device)
+    ws = _workspace(grt_render_workspace_bytes(gb.npix, sum(split)), gb.x.device)
     grt_render_mis_backward(scene.handle, env.handle, gb.struct(), opts, grad_rgb.contiguous(), saved,
                             _grads_struct(grads), ws, stream)
     return grads
