@@ -13,6 +13,17 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+// Minimum waves per SIMD requested for the persistent trace kernels (caps
+// their register budget); 0 leaves the choice to the compiler.
+#ifndef GRT_WAVES_PER_EU
+#define GRT_WAVES_PER_EU 0
+#endif
+#if GRT_WAVES_PER_EU > 0
+#define GRT_OCCUPANCY __attribute__((amdgpu_waves_per_eu(GRT_WAVES_PER_EU)))
+#else
+#define GRT_OCCUPANCY
+#endif
+
 namespace grt {
 
 constexpr int kStack = 64;        // LBVH depth <= 62 (30-bit codes + 32-bit index tie-break)
@@ -170,8 +181,8 @@ __device__ __forceinline__ uint64_t make_key(float tau, uint32_t id)
 // strictly after its last key, so hits of equal depth are neither lost nor
 // repeated.  Results do not depend on K.
 //
-// step() advances one node, so a wavefront can hold rays at different rounds
-// and refill lanes whose ray has finished (see run_persistent).
+// advance() does one node or one hit, so a wavefront can hold rays at
+// different rounds and refill lanes whose ray has finished (run_persistent).
 // ---------------------------------------------------------------------------
 template <int K>
 struct Walker {
@@ -182,6 +193,8 @@ struct Walker {
     uint64_t key[K];
     uint32_t pos[K];
     int cnt, sp, node;
+    int ncomp;            // buffered hits still to composite (0 while walking)
+    uint64_t round_last;  // largest key of the round's full buffer
 
     __device__ __forceinline__ void new_round()
     {
@@ -202,6 +215,7 @@ struct Walker {
         tmax = tmax_;
         last = 0;
         tlo = tmin;
+        ncomp = 0;
         new_round();
     }
 
@@ -256,22 +270,36 @@ struct Walker {
         return false;
     }
 
-    // Hand the round's hits to `visit`; true when the ray is finished,
-    // otherwise the next round is set up.
+    // One unit of work: a node of the walk, or, once the round's walk is
+    // complete, one buffered hit handed to `visit` (front of the buffer, which
+    // then shifts down).  Compositing a hit per call keeps a lane that ends
+    // its round from holding the wavefront for K hits.  Returns true when the
+    // ray is finished; after the last buffered hit of a full round the next
+    // round is set up.
     template <class Visit>
-    __device__ __forceinline__ bool composite(Visit &visit)
+    __device__ __forceinline__ bool advance(const SceneDev &S, int *stack, Visit &visit)
     {
-        bool stop = false;
-        const int m = cnt < K ? cnt : K;
-#pragma unroll
-        for (int i = 0; i < K; ++i) {
-            if (i < m && !stop)
-                stop = visit(pos[i], (uint32_t)(key[i] & 0xffffffffu), __uint_as_float((uint32_t)(key[i] >> 32)));
+        if (ncomp == 0) {
+            if (!step(S, stack)) return false;
+            const int m = cnt < K ? cnt : K;
+            if (m == 0) return true;
+            ncomp = m;
+            round_last = key[K - 1];
+            return false;
         }
-        if (stop || cnt < K) return true;
-        last = key[K - 1];
-        tlo = __uint_as_float((uint32_t)(last >> 32));
-        new_round();
+        const bool stop =
+            visit(pos[0], (uint32_t)(key[0] & 0xffffffffu), __uint_as_float((uint32_t)(key[0] >> 32)));
+#pragma unroll
+        for (int i = 0; i < K - 1; ++i) { key[i] = key[i + 1]; pos[i] = pos[i + 1]; }
+        key[K - 1] = ~0ull;
+        --ncomp;
+        if (stop) return true;
+        if (ncomp == 0) {
+            if (cnt < K) return true;
+            last = round_last;
+            tlo = __uint_as_float((uint32_t)(last >> 32));
+            new_round();
+        }
         return false;
     }
 };
@@ -344,11 +372,9 @@ __device__ __forceinline__ void run_persistent(Job &job, unsigned long long *cou
             continue;
         }
         if (active) {
-            if (job.walker().step(job.S, stack)) {
-                if (job.walker().composite(job.visit())) {
-                    job.finish(ray);
-                    active = false;
-                }
+            if (job.walker().advance(job.S, stack, job.visit())) {
+                job.finish(ray);
+                active = false;
             }
         }
     }

@@ -456,14 +456,14 @@ struct RenderBwdJob {
 };
 
 template <int K>
-__global__ void __launch_bounds__(256) k_render(RenderArgs a)
+__global__ void __launch_bounds__(256) GRT_OCCUPANCY k_render(RenderArgs a)
 {
     RenderJob<K> job(a);
     run_persistent<K>(job, a.counters, (int64_t)a.H * a.W * (a.nc + a.ng + a.ne));
 }
 
 template <int K>
-__global__ void __launch_bounds__(256) k_render_bwd(RenderArgs a)
+__global__ void __launch_bounds__(256) GRT_OCCUPANCY k_render_bwd(RenderArgs a)
 {
     RenderBwdJob<K> job(a);
     run_persistent<K>(job, a.counters, (int64_t)a.H * a.W * (a.nc + a.ng + a.ne));

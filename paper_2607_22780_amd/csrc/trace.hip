@@ -103,14 +103,14 @@ struct TraceBwdJob {
 };
 
 template <int K>
-__global__ void __launch_bounds__(256) k_trace(TraceArgs a)
+__global__ void __launch_bounds__(256) GRT_OCCUPANCY k_trace(TraceArgs a)
 {
     TraceJob<K> job(a);
     run_persistent<K>(job, a.counters, a.n);
 }
 
 template <int K>
-__global__ void __launch_bounds__(256) k_trace_bwd(TraceBwdArgs a)
+__global__ void __launch_bounds__(256) GRT_OCCUPANCY k_trace_bwd(TraceBwdArgs a)
 {
     TraceBwdJob<K> job(a);
     run_persistent<K>(job, a.f.counters, a.f.n);
