@@ -26,7 +26,6 @@
 
 namespace grt {
 
-constexpr int kStack = 64;        // LBVH depth <= 62 (30-bit codes + 32-bit index tie-break)
 constexpr float kGrazing = 1e-6f; // |n . d| below this is no intersection
 constexpr float kPad = 1e-5f;     // absolute padding of surfel boxes (scene units)
 
@@ -114,18 +113,25 @@ struct HitGeo {
 __device__ __forceinline__ void value_geo(const float4 r0, const float4 r1, const float4 r2, const float4 r3,
                                           const float3 o, const float3 d, HitGeo &g)
 {
+    // with num = n.m and den = n.d:  den * u = num (a_u.d) - den (a_u.m), the
+    // cancelling terms taken in double; one single-precision reciprocal
     const double mx = (double)r0.x - (double)o.x, my = (double)r0.y - (double)o.y, mz = (double)r0.z - (double)o.z;
     const double dx = d.x, dy = d.y, dz = d.z;
-    const double den = (double)r1.x * dx + (double)r1.y * dy + (double)r1.z * dz;
-    const double tau = ((double)r1.x * mx + (double)r1.y * my + (double)r1.z * mz) / den;
-    const double Dx = tau * dx - mx, Dy = tau * dy - my, Dz = tau * dz - mz;
-    const double u = (double)r2.x * Dx + (double)r2.y * Dy + (double)r2.z * Dz;
-    const double v = (double)r3.x * Dx + (double)r3.y * Dy + (double)r3.z * Dz;
-    g.u = (float)u;
-    g.v = (float)v;
-    g.rho2 = (float)(u * u + v * v);
-    g.den = (float)den;
-    g.D = make_float3((float)Dx, (float)Dy, (float)Dz);
+    const double nx = r1.x, ny = r1.y, nz = r1.z;
+    const double den = nx * dx + ny * dy + nz * dz;
+    const double num = nx * mx + ny * my + nz * mz;
+    const double U = num * ((double)r2.x * dx + (double)r2.y * dy + (double)r2.z * dz) -
+                     den * ((double)r2.x * mx + (double)r2.y * my + (double)r2.z * mz);
+    const double V = num * ((double)r3.x * dx + (double)r3.y * dy + (double)r3.z * dz) -
+                     den * ((double)r3.x * mx + (double)r3.y * my + (double)r3.z * mz);
+    const float fden = (float)den;
+    const float rden = 1.0f / fden;
+    g.u = (float)U * rden;
+    g.v = (float)V * rden;
+    g.rho2 = g.u * g.u + g.v * g.v;
+    g.den = fden;
+    g.D = make_float3((float)(num * dx - den * mx) * rden, (float)(num * dy - den * my) * rden,
+                      (float)(num * dz - den * mz) * rden);
 }
 
 // Opacity contribution of a hit, alpha = o exp(-rho^2 / 2), and the
@@ -168,22 +174,38 @@ __device__ __forceinline__ uint64_t make_key(float tau, uint32_t id)
 }
 
 // ---------------------------------------------------------------------------
-// Ordered traversal with a k-nearest hit buffer, re-traversed in rounds, as a
-// per-lane state machine.
+// Ordered traversal with a k-nearest hit buffer, in rounds that resume from a
+// deferred frontier, as a per-lane state machine.
 //
-// Each round walks the LBVH from the root, keeping the K smallest keys
-// (bits(tau), id) strictly greater than the last key composited in the
-// previous round (registers, sorted by unrolled insertion).  Once the buffer
-// is full its largest depth bounds the interval, which prunes far subtrees.
-// The buffered hits are then handed to `visit` (record position, surfel id,
-// depth) in order; `visit` returns true to stop (transmittance cutoff).  A
-// round that ends with a full buffer is followed by another that resumes
-// strictly after its last key, so hits of equal depth are neither lost nor
-// repeated.  Results do not depend on K.
+// A round walks the LBVH keeping the K smallest keys (bits(tau), id) strictly
+// greater than the last key composited in the previous round (registers,
+// sorted by unrolled insertion).  Once the buffer is full its largest depth
+// thi bounds the walk.  Everything the bound excludes is not dropped but
+// deferred to the next round: subtrees whose box is entered beyond thi, hits
+// rejected by the full buffer and hits evicted from it.  The buffered hits
+// are then handed to `visit` (record position, surfel id, depth) in order;
+// `visit` returns true to stop (transmittance cutoff).  The next round starts
+// from the deferred items instead of the root, so a ray's hits cost about one
+// walk whatever K is; a round that defers nothing ends the ray.  Keys are
+// unique, so hits of equal depth are neither lost nor repeated, and results
+// do not depend on K.
+//
+// The walk stack and the deferred list share one private array, growing from
+// opposite ends; their roles swap every round.  If they would collide, the
+// deferred list is dropped and the next round restarts from the root, which
+// re-finds every hit beyond the last composited key.
 //
 // advance() does one node or one hit, so a wavefront can hold rays at
 // different rounds and refill lanes whose ray has finished (run_persistent).
 // ---------------------------------------------------------------------------
+// Private array shared by walk stack and deferred list.  A round's stack
+// starts with the previous round's deferred items (at most kMaxDeferred) and
+// grows by at most one entry per tree level below them (LBVH depth <= 63:
+// 30-bit codes + position tie-break), so it never exceeds kFrontier.
+constexpr int kFrontier = 256;
+constexpr int kMaxDeferred = kFrontier - 66;
+constexpr int kNone = 0x7fffffff;
+
 template <int K>
 struct Walker {
     float3 o, d, inv;
@@ -192,21 +214,25 @@ struct Walker {
     float tlo, thi;
     uint64_t key[K];
     uint32_t pos[K];
-    int cnt, sp, node;
+    int cnt;
+    int cur;              // item in hand: node >= 0, leaf -(pos+1), or kNone
+    int top, dtop, dir;   // walk stack top, deferred-list top, growth direction (+1 / -1)
+    bool lost;            // deferred list dropped: next round restarts at the root
     int ncomp;            // buffered hits still to composite (0 while walking)
     uint64_t round_last;  // largest key of the round's full buffer
+#ifdef GRT_STATS
+    int st_nodes, st_leaves, st_rounds, st_lost, st_deferred;
+#endif
 
-    __device__ __forceinline__ void new_round()
+    __device__ __forceinline__ void clear_buffer()
     {
 #pragma unroll
         for (int i = 0; i < K; ++i) { key[i] = ~0ull; pos[i] = 0; }
         cnt = 0;
         thi = tmax;
-        sp = 0;
-        node = 0;
     }
 
-    __device__ __forceinline__ void start(float3 o_, float3 d_, float tmin_, float tmax_)
+    __device__ __forceinline__ void start(const SceneDev &S, float3 o_, float3 d_, float tmin_, float tmax_)
     {
         o = o_;
         d = d_;
@@ -216,17 +242,68 @@ struct Walker {
         last = 0;
         tlo = tmin;
         ncomp = 0;
-        new_round();
+        dir = 1;
+        top = 0;
+        dtop = kFrontier - 1;
+        lost = false;
+        cur = S.n == 1 ? -1 : 0;
+        clear_buffer();
+#ifdef GRT_STATS
+        st_nodes = st_leaves = st_lost = st_deferred = 0;
+        st_rounds = 1;
+#endif
     }
 
-    __device__ __forceinline__ void test_leaf(const SceneDev &S, uint32_t p)
+    __device__ __forceinline__ bool stack_empty() const { return dir > 0 ? top == 0 : top == kFrontier - 1; }
+
+    __device__ __forceinline__ void push(int *st, int x)
     {
+        if (top == dtop + dir) {  // would meet the deferred list: drop it
+            lost = true;
+            dtop = dir > 0 ? kFrontier - 1 : 0;
+        }
+        st[top] = x;
+        top += dir;
+    }
+
+    __device__ __forceinline__ int pop(int *st)
+    {
+        top -= dir;
+        return st[top];
+    }
+
+    __device__ __forceinline__ void defer(int *st, int x)
+    {
+        if (lost) return;
+        const int ndef = dir > 0 ? kFrontier - 1 - dtop : dtop;
+        if (dtop == top - dir || ndef >= kMaxDeferred) {  // no room: drop the list
+            lost = true;
+            dtop = dir > 0 ? kFrontier - 1 : 0;
+            return;
+        }
+        st[dtop] = x;
+        dtop -= dir;
+#ifdef GRT_STATS
+        ++st_deferred;
+#endif
+    }
+
+    __device__ __forceinline__ void test_leaf(const SceneDev &S, int *st, uint32_t p)
+    {
+#ifdef GRT_STATS
+        ++st_leaves;
+#endif
         const float4 *r = S.rec + 4 * (size_t)p;
         float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
         float t;
         if (!hit_test(r0, r1, r2, r3, o, d, tmin, tmax, t)) return;
         uint64_t k = make_key(t, __float_as_uint(r2.w));
-        if (k <= last || k >= key[K - 1]) return;
+        if (k <= last) return;
+        if (k >= key[K - 1]) {  // beyond the full buffer: next round
+            defer(st, -(int)p - 1);
+            return;
+        }
+        if (cnt >= K) defer(st, -(int)pos[K - 1] - 1);  // evicted
         // sorted insertion, the largest key drops out
         bool placed = false;
 #pragma unroll
@@ -243,44 +320,94 @@ struct Walker {
         if (cnt >= K) thi = __uint_as_float((uint32_t)(key[K - 1] >> 32));
     }
 
-    // One node of the current round; true when the round's walk is complete.
-    __device__ __forceinline__ bool step(const SceneDev &S, int *stack)
+    // A child box met by the ray in [tlo, tmax]: process now if it starts
+    // within thi, else defer it.
+    __device__ __forceinline__ bool keep_child(int *st, int c, bool hit, float tn)
     {
-        if (S.n == 1) {
-            test_leaf(S, 0);
-            return true;
-        }
-        const Node nd = S.nodes[node];
-        float tl, tr;
-        bool hl = slab(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, o, inv, tlo, thi, tl);
-        bool hr = slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, o, inv, tlo, thi, tr);
-        const int cl = nd.d.x, cr = nd.d.y;
-        if (hl && cl < 0) { test_leaf(S, (uint32_t)(-cl - 1)); hl = false; }
-        if (hr && cr < 0) { test_leaf(S, (uint32_t)(-cr - 1)); hr = false; }
-        if (hl && hr) {
-            const bool lfirst = tl <= tr;
-            stack[sp++] = lfirst ? cr : cl;
-            node = lfirst ? cl : cr;
+        if (!hit) return false;
+        if (tn > thi) {
+            defer(st, c);
             return false;
         }
-        if (hl) { node = cl; return false; }
-        if (hr) { node = cr; return false; }
-        if (sp == 0) return true;
-        node = stack[--sp];
+        return true;
+    }
+
+    // One item of the current round; true when the round's walk is complete.
+    __device__ __forceinline__ bool step(const SceneDev &S, int *st)
+    {
+        if (cur == kNone) {
+            if (stack_empty()) return true;
+            cur = pop(st);
+        }
+        if (cur < 0) {
+            test_leaf(S, st, (uint32_t)(-cur - 1));
+            cur = kNone;
+            return false;
+        }
+#ifdef GRT_STATS
+        ++st_nodes;
+#endif
+        const Node nd = S.nodes[cur];
+        float tl, tr;
+        bool hl = slab(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, o, inv, tlo, tmax, tl);
+        bool hr = slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, o, inv, tlo, tmax, tr);
+        const int cl = nd.d.x, cr = nd.d.y;
+        hl = keep_child(st, cl, hl, tl);
+        if (hl && cl < 0) { test_leaf(S, st, (uint32_t)(-cl - 1)); hl = false; }
+        hr = keep_child(st, cr, hr, tr);
+        if (hr && cr < 0) { test_leaf(S, st, (uint32_t)(-cr - 1)); hr = false; }
+        if (hl && hr) {
+            const bool lfirst = tl <= tr;
+            push(st, lfirst ? cr : cl);
+            cur = lfirst ? cl : cr;
+        } else if (hl) {
+            cur = cl;
+        } else if (hr) {
+            cur = cr;
+        } else {
+            cur = kNone;
+        }
         return false;
     }
 
-    // One unit of work: a node of the walk, or, once the round's walk is
+    // Set up the next round from the deferred frontier (or the root).
+    __device__ __forceinline__ void next_round(const SceneDev &S)
+    {
+        last = round_last;
+        tlo = __uint_as_float((uint32_t)(last >> 32));
+        clear_buffer();
+#ifdef GRT_STATS
+        ++st_rounds;
+        st_lost += lost ? 1 : 0;
+#endif
+        if (lost) {
+            dir = 1; top = 0; dtop = kFrontier - 1;
+            lost = false;
+            cur = S.n == 1 ? -1 : 0;
+        } else {
+            // the deferred list becomes the walk stack, growing the other way
+            top = dtop;
+            dir = -dir;
+            dtop = dir > 0 ? kFrontier - 1 : 0;
+            cur = kNone;
+        }
+    }
+
+    __device__ __forceinline__ bool deferred_empty() const
+    {
+        return !lost && (dir > 0 ? dtop == kFrontier - 1 : dtop == 0);
+    }
+
+    // One unit of work: an item of the walk, or, once the round's walk is
     // complete, one buffered hit handed to `visit` (front of the buffer, which
     // then shifts down).  Compositing a hit per call keeps a lane that ends
     // its round from holding the wavefront for K hits.  Returns true when the
-    // ray is finished; after the last buffered hit of a full round the next
-    // round is set up.
+    // ray is finished.
     template <class Visit>
-    __device__ __forceinline__ bool advance(const SceneDev &S, int *stack, Visit &visit)
+    __device__ __forceinline__ bool advance(const SceneDev &S, int *st, Visit &visit)
     {
         if (ncomp == 0) {
-            if (!step(S, stack)) return false;
+            if (!step(S, st)) return false;
             const int m = cnt < K ? cnt : K;
             if (m == 0) return true;
             ncomp = m;
@@ -295,10 +422,8 @@ struct Walker {
         --ncomp;
         if (stop) return true;
         if (ncomp == 0) {
-            if (cnt < K) return true;
-            last = round_last;
-            tlo = __uint_as_float((uint32_t)(last >> 32));
-            new_round();
+            if (cnt < K || deferred_empty()) return true;
+            next_round(S);
         }
         return false;
     }
@@ -335,7 +460,7 @@ __device__ __forceinline__ void run_persistent(Job &job, unsigned long long *cou
     bool exhausted = false;               // wavefront-uniform
     bool active = false;
     int64_t ray = -1;
-    int stack[kStack];
+    int stack[kFrontier];
     for (;;) {
         const uint64_t idle = __ballot(!active);
         if (idle && !exhausted) {

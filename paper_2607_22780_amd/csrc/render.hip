@@ -399,7 +399,7 @@ struct RenderJob {
         const float3 x = make_float3(a.x[3 * p], a.x[3 * p + 1], a.x[3 * p + 2]);
         const float3 d = make_float3(r0.x, r0.y, r0.z);
         v.reset(x, d);
-        w.start(x, d, a.tmin, INFINITY);
+        w.start(S, x, d, a.tmin, INFINITY);
         if (S.n <= 0) {
             finish(r);
             return false;
@@ -416,6 +416,10 @@ struct RenderJob {
         if (a.dump) {
             float *dp = a.dump + r * 10;
             dp[7] = Li.x; dp[8] = Li.y; dp[9] = Li.z;
+#ifdef GRT_STATS
+            dp[3] = (float)w.st_nodes; dp[4] = (float)w.st_leaves; dp[5] = (float)w.st_rounds;
+            dp[6] = (float)w.st_lost; dp[7] = (float)w.st_deferred; dp[8] = (float)v.cnt;
+#endif
         }
     }
 };
@@ -448,7 +452,7 @@ struct RenderBwdJob {
         const float3 x = make_float3(a.x[3 * p], a.x[3 * p + 1], a.x[3 * p + 2]);
         const float3 d = make_float3(r0.x, r0.y, r0.z);
         v.reset(x, d, gC, gT, make_float3(sv.x, sv.y, sv.z), sv.w);
-        w.start(x, d, a.tmin, INFINITY);
+        w.start(S, x, d, a.tmin, INFINITY);
         return true;
     }
 

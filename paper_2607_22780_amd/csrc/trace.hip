@@ -49,7 +49,7 @@ struct TraceJob {
         const float tmax = a.tmax_a ? a.tmax_a[r] : a.tmax;
         v.reset(o, d);
         if (a.dump_id) { v.did = a.dump_id + r * a.cap; v.dtau = a.dump_tau + r * a.cap; v.cap = a.cap; }
-        w.start(o, d, tmin, tmax);
+        w.start(S, o, d, tmin, tmax);
         if (S.n <= 0) {
             finish(r);
             return false;
@@ -95,7 +95,7 @@ struct TraceBwdJob {
         const float tmax = a.f.tmax_a ? a.f.tmax_a[r] : a.f.tmax;
         const float3 C = make_float3(a.fwd_rgb[3 * r], a.fwd_rgb[3 * r + 1], a.fwd_rgb[3 * r + 2]);
         v.reset(o, d, gC, gT, C, a.fwd_T[r]);
-        w.start(o, d, tmin, tmax);
+        w.start(S, o, d, tmin, tmax);
         return true;
     }
 
