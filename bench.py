@@ -27,6 +27,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 WORKCOUNT = os.path.join(ROOT, "profiles", "workcount_room1m_1024px_32spp.json")
+TRAFFIC = os.path.join(ROOT, "profiles", "traffic_room1m_1024px_32spp.json")
+CSRC = os.path.join(ROOT, "paper_2607_22780_amd", "csrc")
+
+
+def source_hash():
+    """Hash of the HIP sources: traffic counters are only valid for the kernels they were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(CSRC)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            h.update(open(os.path.join(CSRC, name), "rb").read())
+    return h.hexdigest()[:16]
 SPLIT = (16, 8, 8)
 SEED = 7
 HBM_PEAK_GBS = 8000.0
@@ -107,9 +120,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--k", type=int, default=16)
+    ap.add_argument("--k", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--count-work", action="store_true", help="recount per-ray work with the oracle and exit")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (calibrates the HBM byte counters)")
     args = ap.parse_args()
 
     if args.count_work:
@@ -183,10 +198,22 @@ def main():
         ms = bwd_ms if dominant == "bwd" else fwd_ms
         per_ray = bb if dominant == "bwd" else bf
         achieved = per_ray * rays / (ms * 1e-3) / 1e9
+        kname = "k_render_bwd" if dominant == "bwd" else "k_render"
+        traffic = None
+        if os.path.exists(TRAFFIC):
+            tr = json.load(open(TRAFFIC))
+            if tr.get("source_hash") == source_hash() and kname in tr.get("kernels", {}):
+                traffic = tr["kernels"][kname]["hbm_bytes"]
         roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=round(achieved / HBM_PEAK_GBS, 4), traffic=None,
-                        kernel="k_render_bwd" if dominant == "bwd" else "k_render",
+                        frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=kname,
                         bytes_per_ray=round(per_ray, 1), kernel_ms=round(ms, 3))
+
+    if args.calib_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -198,13 +198,67 @@ __device__ __forceinline__ uint64_t make_key(float tau, uint32_t id)
 // advance() does one node or one hit, so a wavefront can hold rays at
 // different rounds and refill lanes whose ray has finished (run_persistent).
 // ---------------------------------------------------------------------------
-// Private array shared by walk stack and deferred list.  A round's stack
-// starts with the previous round's deferred items (at most kMaxDeferred) and
-// grows by at most one entry per tree level below them (LBVH depth <= 63:
-// 30-bit codes + position tie-break), so it never exceeds kFrontier.
-constexpr int kFrontier = 256;
-constexpr int kMaxDeferred = kFrontier - 66;
+// ---------------------------------------------------------------------------
+// A lane's stack: the top kLdsDepth entries live in LDS (lane-interleaved, so
+// a wavefront's accesses are conflict-free), deeper ones spill to a private
+// array.  Position p sits in LDS slot p % kLdsDepth; a push that reuses the
+// slot of position p - kLdsDepth first copies that entry out (entries never
+// change once pushed), and a pop reads the private copy for positions below
+// `spilled`.  Positions [0, spilled) always have valid private copies.
+// ---------------------------------------------------------------------------
+constexpr int kLdsDepth = 24;   // LDS entries per lane and stack
+constexpr int kStackCap = 160;  // logical capacity of a stack
 constexpr int kNone = 0x7fffffff;
+
+struct SpillStack {
+    int *lds;  // this lane's slot 0; slot i at lds[64 * i]
+    int *mem;  // private overflow array [kStackCap]
+    int sp, spilled;
+
+    __device__ __forceinline__ void reset() { sp = 0; spilled = 0; }
+
+    __device__ __forceinline__ void push(int x)
+    {
+        const int slot = sp % kLdsDepth;
+        if (sp >= kLdsDepth && sp - kLdsDepth >= spilled) {
+            mem[sp - kLdsDepth] = lds[64 * slot];
+            spilled = sp - kLdsDepth + 1;
+        }
+        lds[64 * slot] = x;
+        ++sp;
+    }
+
+    __device__ __forceinline__ int pop()
+    {
+        --sp;
+        if (sp < spilled) {
+            spilled = sp;
+            return mem[sp];
+        }
+        return lds[64 * (sp % kLdsDepth)];
+    }
+};
+
+// The walk stack and the deferred list of a lane; their roles swap each
+// round (the deferred list becomes the next round's walk stack).  A round's
+// stack starts with at most kMaxDeferred items and grows by at most one entry
+// per tree level below them (LBVH depth <= 63: 30-bit codes + position
+// tie-break), so it stays within kStackCap.
+constexpr int kMaxDeferred = kStackCap - 64;
+
+struct Frontier {
+    SpillStack walk;  // the current round's walk stack
+    SpillStack def;   // deferrals for the next round
+
+    // the deferred list becomes the walk stack (descriptor fields swapped, no copy)
+    __device__ __forceinline__ void swap_roles()
+    {
+        int *l = walk.lds, *m = walk.mem;
+        const int a = walk.sp, b = walk.spilled;
+        walk.lds = def.lds; walk.mem = def.mem; walk.sp = def.sp; walk.spilled = def.spilled;
+        def.lds = l; def.mem = m; def.sp = a; def.spilled = b;
+    }
+};
 
 template <int K>
 struct Walker {
@@ -216,8 +270,8 @@ struct Walker {
     uint32_t pos[K];
     int cnt;
     int cur;              // item in hand: node >= 0, leaf -(pos+1), or kNone
-    int top, dtop, dir;   // walk stack top, deferred-list top, growth direction (+1 / -1)
     bool lost;            // deferred list dropped: next round restarts at the root
+    Frontier F;           // walk stack and deferred list (LDS + private spill)
     int ncomp;            // buffered hits still to composite (0 while walking)
     uint64_t round_last;  // largest key of the round's full buffer
 #ifdef GRT_STATS
@@ -242,9 +296,8 @@ struct Walker {
         last = 0;
         tlo = tmin;
         ncomp = 0;
-        dir = 1;
-        top = 0;
-        dtop = kFrontier - 1;
+        F.walk.reset();
+        F.def.reset();
         lost = false;
         cur = S.n == 1 ? -1 : 0;
         clear_buffer();
@@ -254,41 +307,21 @@ struct Walker {
 #endif
     }
 
-    __device__ __forceinline__ bool stack_empty() const { return dir > 0 ? top == 0 : top == kFrontier - 1; }
-
-    __device__ __forceinline__ void push(int *st, int x)
-    {
-        if (top == dtop + dir) {  // would meet the deferred list: drop it
-            lost = true;
-            dtop = dir > 0 ? kFrontier - 1 : 0;
-        }
-        st[top] = x;
-        top += dir;
-    }
-
-    __device__ __forceinline__ int pop(int *st)
-    {
-        top -= dir;
-        return st[top];
-    }
-
-    __device__ __forceinline__ void defer(int *st, int x)
+    __device__ __forceinline__ void defer(int x)
     {
         if (lost) return;
-        const int ndef = dir > 0 ? kFrontier - 1 - dtop : dtop;
-        if (dtop == top - dir || ndef >= kMaxDeferred) {  // no room: drop the list
+        if (F.def.sp >= kMaxDeferred) {  // too many: drop the list, restart the next round at the root
             lost = true;
-            dtop = dir > 0 ? kFrontier - 1 : 0;
+            F.def.reset();
             return;
         }
-        st[dtop] = x;
-        dtop -= dir;
+        F.def.push(x);
 #ifdef GRT_STATS
         ++st_deferred;
 #endif
     }
 
-    __device__ __forceinline__ void test_leaf(const SceneDev &S, int *st, uint32_t p)
+    __device__ __forceinline__ void test_leaf(const SceneDev &S, uint32_t p)
     {
 #ifdef GRT_STATS
         ++st_leaves;
@@ -300,10 +333,10 @@ struct Walker {
         uint64_t k = make_key(t, __float_as_uint(r2.w));
         if (k <= last) return;
         if (k >= key[K - 1]) {  // beyond the full buffer: next round
-            defer(st, -(int)p - 1);
+            defer(-(int)p - 1);
             return;
         }
-        if (cnt >= K) defer(st, -(int)pos[K - 1] - 1);  // evicted
+        if (cnt >= K) defer(-(int)pos[K - 1] - 1);  // evicted
         // sorted insertion, the largest key drops out
         bool placed = false;
 #pragma unroll
@@ -322,25 +355,25 @@ struct Walker {
 
     // A child box met by the ray in [tlo, tmax]: process now if it starts
     // within thi, else defer it.
-    __device__ __forceinline__ bool keep_child(int *st, int c, bool hit, float tn)
+    __device__ __forceinline__ bool keep_child(int c, bool hit, float tn)
     {
         if (!hit) return false;
         if (tn > thi) {
-            defer(st, c);
+            defer(c);
             return false;
         }
         return true;
     }
 
     // One item of the current round; true when the round's walk is complete.
-    __device__ __forceinline__ bool step(const SceneDev &S, int *st)
+    __device__ __forceinline__ bool step(const SceneDev &S)
     {
         if (cur == kNone) {
-            if (stack_empty()) return true;
-            cur = pop(st);
+            if (F.walk.sp == 0) return true;
+            cur = F.walk.pop();
         }
         if (cur < 0) {
-            test_leaf(S, st, (uint32_t)(-cur - 1));
+            test_leaf(S, (uint32_t)(-cur - 1));
             cur = kNone;
             return false;
         }
@@ -352,13 +385,13 @@ struct Walker {
         bool hl = slab(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, o, inv, tlo, tmax, tl);
         bool hr = slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, o, inv, tlo, tmax, tr);
         const int cl = nd.d.x, cr = nd.d.y;
-        hl = keep_child(st, cl, hl, tl);
-        if (hl && cl < 0) { test_leaf(S, st, (uint32_t)(-cl - 1)); hl = false; }
-        hr = keep_child(st, cr, hr, tr);
-        if (hr && cr < 0) { test_leaf(S, st, (uint32_t)(-cr - 1)); hr = false; }
+        hl = keep_child(cl, hl, tl);
+        if (hl && cl < 0) { test_leaf(S, (uint32_t)(-cl - 1)); hl = false; }
+        hr = keep_child(cr, hr, tr);
+        if (hr && cr < 0) { test_leaf(S, (uint32_t)(-cr - 1)); hr = false; }
         if (hl && hr) {
             const bool lfirst = tl <= tr;
-            push(st, lfirst ? cr : cl);
+            F.walk.push(lfirst ? cr : cl);
             cur = lfirst ? cl : cr;
         } else if (hl) {
             cur = cl;
@@ -380,22 +413,20 @@ struct Walker {
         ++st_rounds;
         st_lost += lost ? 1 : 0;
 #endif
+        F.walk.reset();  // empty: the walk is complete
         if (lost) {
-            dir = 1; top = 0; dtop = kFrontier - 1;
+            F.def.reset();
             lost = false;
             cur = S.n == 1 ? -1 : 0;
         } else {
-            // the deferred list becomes the walk stack, growing the other way
-            top = dtop;
-            dir = -dir;
-            dtop = dir > 0 ? kFrontier - 1 : 0;
+            F.swap_roles();
             cur = kNone;
         }
     }
 
     __device__ __forceinline__ bool deferred_empty() const
     {
-        return !lost && (dir > 0 ? dtop == kFrontier - 1 : dtop == 0);
+        return !lost && F.def.sp == 0;
     }
 
     // One unit of work: an item of the walk, or, once the round's walk is
@@ -404,10 +435,10 @@ struct Walker {
     // its round from holding the wavefront for K hits.  Returns true when the
     // ray is finished.
     template <class Visit>
-    __device__ __forceinline__ bool advance(const SceneDev &S, int *st, Visit &visit)
+    __device__ __forceinline__ bool advance(const SceneDev &S, Visit &visit)
     {
         if (ncomp == 0) {
-            if (!step(S, st)) return false;
+            if (!step(S)) return false;
             const int m = cnt < K ? cnt : K;
             if (m == 0) return true;
             ncomp = m;
@@ -460,7 +491,18 @@ __device__ __forceinline__ void run_persistent(Job &job, unsigned long long *cou
     bool exhausted = false;               // wavefront-uniform
     bool active = false;
     int64_t ray = -1;
-    int stack[kFrontier];
+    __shared__ int lds_stacks[4][2][kLdsDepth][64];  // [wave][stack][slot][lane]
+    int spill0[kStackCap], spill1[kStackCap];
+    const int wave = (threadIdx.x >> 6) & 3;
+    {
+        Frontier &F = job.walker().F;
+        F.walk.lds = &lds_stacks[wave][0][0][lane];
+        F.def.lds = &lds_stacks[wave][1][0][lane];
+        F.walk.mem = spill0;
+        F.def.mem = spill1;
+        F.walk.reset();
+        F.def.reset();
+    }
     for (;;) {
         const uint64_t idle = __ballot(!active);
         if (idle && !exhausted) {
@@ -497,7 +539,7 @@ __device__ __forceinline__ void run_persistent(Job &job, unsigned long long *cou
             continue;
         }
         if (active) {
-            if (job.walker().advance(job.S, stack, job.visit())) {
+            if (job.walker().advance(job.S, job.visit())) {
                 job.finish(ray);
                 active = false;
             }
