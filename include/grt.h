@@ -271,6 +271,89 @@ int grt_render_mis_backward(const grt_scene *scene, const grt_env *env, const gr
                             const grt_mis_opts *opts, const float *grad_rgb, const void *saved,
                             grt_surfel_grads *grads, void *workspace, size_t ws_bytes, void *stream);
 
+/* ------------------------------------------------------- relighting server */
+
+/* A continuously batched relighting server over a resident built scene
+ * (Sec. 3.5.1: relighting evaluates the rendering equation with the MIS
+ * density for every pixel of a view under a new environment map).  One
+ * scheduler thread runs in epochs: it admits queued requests in arrival order
+ * while a slot and room in the device pool are free (uploads and sampling
+ * tables on a copy stream, overlapping compute), shares each epoch's ray
+ * budget equally among resident requests, and traces the rays of all of them
+ * in one generation launch plus one persistent trace launch; requests that
+ * complete are reduced per pixel and copied back.  A request's image equals
+ * grt_render_mis with the same inputs and opts (seed, job) whatever it was
+ * mixed with.  The scene must not be rebuilt or destroyed while the server
+ * exists.
+ *
+ * mem_budget: device bytes the server allocates for requests (its pool).
+ * max_jobs:   requests resident at once (1..256).
+ * epoch_rays: rays per epoch across all requests (0 = 4,194,304).
+ * k:          k-buffer size, 4, 8 or 16.  t_min, t_cut as in grt_mis_opts. */
+typedef struct {
+    size_t mem_budget;
+    int max_jobs;
+    int64_t epoch_rays;
+    int k;
+    float t_min;
+    float t_cut;
+} grt_server_opts;
+
+/* A request.  All pointers are HOST memory, borrowed until the request is
+ * done (pinned memory lets uploads overlap compute).  G-buffer arrays as in
+ * grt_gbuffer; env_rgb [env_H, env_W, 3] as in grt_env_create; sample
+ * allocation and random identity as in grt_mis_opts; out_rgb [H*W*3]
+ * receives c_pbr. */
+typedef struct {
+    int H, W;
+    const float *x;
+    const float *n;
+    const float *wo;
+    const float *albedo;
+    const float *rough;
+    const float *metal;
+    const uint8_t *valid;
+    const float *env_rgb;
+    int env_H, env_W;
+    int n_cos, n_ggx, n_env;
+    uint64_t seed;
+    uint32_t job;
+    float *out_rgb;
+} grt_job;
+
+/* Pool bytes a request occupies while resident (0 if malformed). */
+size_t grt_server_job_bytes(const grt_job *job);
+
+int grt_server_create(grt_ctx *ctx, const grt_scene *scene, const grt_server_opts *opts, grt_server **out);
+
+/* Queue a request; *id identifies it.  GRT_ERR_ADMISSION if it can never fit
+ * the memory budget, GRT_ERR_INVALID if malformed, GRT_ERR_BUSY if 4,096
+ * requests are already queued. */
+int grt_server_submit(grt_server *server, const grt_job *job, uint64_t *id);
+
+/* *state: 0 queued, 1 uploading, 2 running, 3 done, or the failing status
+ * (GRT_ERR_CANCELLED, GRT_ERR_DEVICE). */
+int grt_server_poll(grt_server *server, uint64_t id, int *state);
+
+/* Block until the request is done (returns its status) or timeout_s seconds
+ * pass (GRT_ERR_TIMEOUT). */
+int grt_server_wait(grt_server *server, uint64_t id, double timeout_s);
+
+/* Cancel a request: removed if queued, dropped at the next epoch boundary if
+ * resident (its pool memory is freed then). */
+int grt_server_cancel(grt_server *server, uint64_t id);
+
+/* Seconds since the server was created at which the request was submitted,
+ * started running (-1 if not yet) and finished (-1 if not yet). */
+int grt_server_job_times(grt_server *server, uint64_t id, double *submit_s, double *start_s, double *done_s);
+
+/* Epochs run, rays traced, and free pool bytes. */
+int grt_server_stats(grt_server *server, uint64_t *epochs, int64_t *rays, size_t *pool_free);
+
+/* Stop the scheduler (after its current epoch), cancel what is left, free
+ * the pool. */
+int grt_server_destroy(grt_server *server);
+
 #ifdef __cplusplus
 }
 #endif

@@ -99,6 +99,27 @@ grt::GradPtrs grad_ptrs(const grt_scene *s, const grt_surfel_grads *g)
     return p;
 }
 
+}  // namespace
+
+namespace grt {
+int scene_dev_of(const grt_scene *scene, SceneDev *out, const char **why)
+{
+    if (!scene->built) {
+        *why = "scene used before grt_scene_build";
+        return GRT_ERR_NOT_BUILT;
+    }
+    *out = scene_dev(scene);
+    return GRT_OK;
+}
+
+int set_error(int code, const char *msg)
+{
+    return fail(code, "%s", msg);
+}
+}  // namespace grt
+
+namespace {
+
 int set_device(grt_ctx *c)
 {
     hipError_t e = hipSetDevice(c->device);

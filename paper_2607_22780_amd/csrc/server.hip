@@ -1,0 +1,671 @@
+// server.hip -- continuously batched relighting server over a resident scene.
+//
+// Relighting requests (a G-buffer, an environment map, a sample budget) are
+// served by one scheduler thread that runs in short epochs.  Each epoch it
+//   1. admits queued requests in arrival order while a slot and room in the
+//      device pool are free: the request's G-buffer and environment are
+//      uploaded and its sampling tables built on a copy stream, overlapping
+//      the compute stream;
+//   2. gives every resident request a share of the epoch's ray budget
+//      (processor sharing, so a large request does not block small ones);
+//   3. launches one generation kernel and one persistent trace kernel over
+//      the rays of all requests of the epoch together (the mix), then, for the
+//      requests that complete, the per-pixel reduction and the copy back.
+// Every sample's random counter carries its request id and every pixel is
+// summed in sample order, so a request's image is the same alone or in any
+// mix.  Scene and LBVH stay resident; each epoch launch ends when its rays
+// are done, so no kernel outlives the epoch.
+#include <string.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "grt_render.h"
+
+namespace grt {
+// defined in api.hip (the scene handle is opaque here)
+int scene_dev_of(const grt_scene *scene, SceneDev *out, const char **why);
+int set_error(int code, const char *msg);
+
+struct ServeChunk {
+    int slot;       // job slot in the epoch's job table
+    int pad;
+    int64_t begin;  // first ray of the job in this chunk
+    int64_t offset; // position of the chunk in the epoch's ray range
+};
+
+struct ServeEpoch {
+    const RenderArgs *jobs;
+    const ServeChunk *chunks;
+    int nchunks;
+    int64_t total;
+    unsigned long long *counters;
+    SceneDev S;
+};
+
+__device__ __forceinline__ int find_chunk(const ServeEpoch &e, int64_t g)
+{
+    int lo = 0, hi = e.nchunks - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (e.chunks[mid].offset <= g) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ void __launch_bounds__(256) k_serve_gen(ServeEpoch e)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= e.total) return;
+    const ServeChunk ch = e.chunks[find_chunk(e, g)];
+    gen_ray(e.jobs[ch.slot], ch.begin + (g - ch.offset));
+}
+
+template <int K>
+struct ServeJob {
+    const ServeEpoch &e;
+    SceneDev S;
+    ShadeTrace<K> t;
+    const RenderArgs *a;
+    int64_t r;
+
+    __device__ ServeJob(const ServeEpoch &e_) : e(e_), S(e_.S), a(nullptr), r(0) {}
+    __device__ __forceinline__ Walker<K> &walker() { return t.w; }
+    __device__ __forceinline__ CompositeVisit &visit() { return t.v; }
+
+    __device__ __forceinline__ bool begin(int64_t g)
+    {
+        const ServeChunk ch = e.chunks[find_chunk(e, g)];
+        a = &e.jobs[ch.slot];
+        r = ch.begin + (g - ch.offset);
+        return t.begin(*a, S, r);
+    }
+
+    __device__ __forceinline__ void finish(int64_t) { t.finish(*a, r); }
+};
+
+template <int K>
+__global__ void __launch_bounds__(256) GRT_OCCUPANCY k_serve(ServeEpoch e)
+{
+    ServeJob<K> job(e);
+    run_persistent<K>(job, e.counters, e.total);
+}
+
+__global__ void k_serve_reduce(const RenderArgs *a, int64_t npix)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= npix) return;
+    reduce_pixel(p, a->nc + a->ng + a->ne, a->contrib, a->out);
+}
+
+template <int K>
+static hipError_t go_serve(const ServeEpoch &e, int num_cu, hipStream_t st)
+{
+    const int nb = persistent_blocks(k_serve<K>, num_cu, e.total);
+    hipLaunchKernelGGL(k_serve<K>, dim3(nb), dim3(256), 0, st, e);
+    return hipGetLastError();
+}
+
+static hipError_t launch_epoch(const ServeEpoch &e, int k, int num_cu, hipStream_t st)
+{
+    hipError_t err = launch_zero_counters(e.counters, st);
+    if (err != hipSuccess) return err;
+    hipLaunchKernelGGL(k_serve_gen, dim3((unsigned)((e.total + 255) / 256)), dim3(256), 0, st, e);
+    if ((err = hipGetLastError()) != hipSuccess) return err;
+    switch (k) {
+    case 4: return go_serve<4>(e, num_cu, st);
+    case 8: return go_serve<8>(e, num_cu, st);
+    case 16: return go_serve<16>(e, num_cu, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+using Clock = std::chrono::steady_clock;
+
+enum JobState { kQueued = 0, kUploading = 1, kRunning = 2, kDone = 3 };
+
+struct ServerJob {
+    uint64_t id = 0;
+    grt_job spec{};
+    int state = kQueued;
+    int status = GRT_OK;  // error code once failed or cancelled
+    bool cancel = false;
+    size_t bytes = 0, off = 0;
+    int slot = -1;
+    RenderArgs args{};
+    EnvWS env{};
+    int64_t npix = 0, total = 0, next = 0;
+    hipEvent_t ready = nullptr;
+    double t_submit = 0, t_start = -1, t_done = -1;
+};
+
+// First-fit allocator over the device pool (offsets, 256-byte granules).
+struct PoolAlloc {
+    std::map<size_t, size_t> free_;  // offset -> size
+    void init(size_t bytes) { free_.clear(); free_[0] = bytes; }
+    bool alloc(size_t bytes, size_t &off)
+    {
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= bytes) {
+                off = it->first;
+                const size_t rest = it->second - bytes;
+                free_.erase(it);
+                if (rest) free_[off + bytes] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        auto it = free_.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+};
+
+// bytes a job needs in the pool and where each array goes
+static size_t carve_job(ServerJob &j, char *base)
+{
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    const int spp = j.spec.n_cos + j.spec.n_ggx + j.spec.n_env;
+    const size_t npix = (size_t)j.spec.H * (size_t)j.spec.W, nray = npix * (size_t)spp;
+    RenderArgs &a = j.args;
+    a.x = (const float *)take(12 * npix);
+    a.n = (const float *)take(12 * npix);
+    a.wo = (const float *)take(12 * npix);
+    a.alb = (const float *)take(12 * npix);
+    a.rough = (const float *)take(4 * npix);
+    a.metal = (const float *)take(4 * npix);
+    a.valid = (const uint8_t *)take(npix);
+    a.E.rgb = (const float *)take(12 * (size_t)j.spec.env_H * j.spec.env_W);
+    char *envws = take(carve_env(nullptr, j.spec.env_H, j.spec.env_W).bytes);
+    j.env = carve_env(envws, j.spec.env_H, j.spec.env_W);
+    a.rays = (float4 *)take(48 * nray);
+    a.contrib = (float4 *)take(16 * nray);
+    a.out = (float *)take(12 * npix);
+    return off;
+}
+
+}  // namespace grt
+
+using grt::ServerJob;
+using grt::kQueued;
+using grt::kUploading;
+using grt::kRunning;
+using grt::kDone;
+
+struct grt_server {
+    grt_ctx *ctx = nullptr;
+    grt::SceneDev S{};
+    grt_server_opts opts{};
+    char *pool = nullptr;
+    grt::PoolAlloc alloc;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::thread th;
+    bool stop = false;
+    int error = GRT_OK;
+    std::deque<uint64_t> pending;
+    std::map<uint64_t, ServerJob> jobs;
+    std::vector<uint64_t> resident;  // uploading or running, in admission order
+    std::vector<int> free_slots;
+    hipStream_t compute = nullptr, copy = nullptr;
+    grt::RenderArgs *d_jobs = nullptr, *h_jobs = nullptr;
+    grt::ServeChunk *d_chunks = nullptr, *h_chunks = nullptr;
+    unsigned long long *counters = nullptr;
+    uint64_t next_id = 1;
+    grt::Clock::time_point t0;
+    // statistics
+    uint64_t epochs = 0;
+    int64_t rays_done = 0;
+
+    double now() const { return std::chrono::duration<double>(grt::Clock::now() - t0).count(); }
+};
+
+namespace {
+
+int sfail(int code, const char *msg) { return grt::set_error(code, msg); }
+
+size_t job_bytes(const grt_job &spec)
+{
+    ServerJob j;
+    j.spec = spec;
+    return grt::carve_job(j, nullptr);
+}
+
+int check_job(const grt_job *j)
+{
+    if (!j) return GRT_ERR_INVALID;
+    if (j->H <= 0 || j->W <= 0 || (int64_t)j->H * j->W > (1 << 26)) return GRT_ERR_INVALID;
+    if (j->env_H <= 0 || j->env_W <= 0 || (int64_t)j->env_H * j->env_W > (1 << 24)) return GRT_ERR_INVALID;
+    const int spp = j->n_cos + j->n_ggx + j->n_env;
+    if (j->n_cos < 0 || j->n_ggx < 0 || j->n_env < 0 || spp <= 0 || spp > 4096) return GRT_ERR_INVALID;
+    if (!j->x || !j->n || !j->wo || !j->albedo || !j->rough || !j->metal || !j->valid || !j->env_rgb || !j->out_rgb)
+        return GRT_ERR_INVALID;
+    return GRT_OK;
+}
+
+// Upload a job's inputs and build its tables on the copy stream.
+hipError_t upload(grt_server *s, ServerJob &j)
+{
+    hipError_t e;
+    const size_t npix = (size_t)j.spec.H * j.spec.W;
+    const grt_job &q = j.spec;
+    grt::RenderArgs &a = j.args;
+    struct Cp {
+        const void *dst;
+        const void *src;
+        size_t n;
+    } cps[] = {{a.x, q.x, 12 * npix},       {a.n, q.n, 12 * npix},         {a.wo, q.wo, 12 * npix},
+               {a.alb, q.albedo, 12 * npix}, {a.rough, q.rough, 4 * npix},  {a.metal, q.metal, 4 * npix},
+               {a.valid, q.valid, npix},     {a.E.rgb, q.env_rgb, 12 * (size_t)q.env_H * q.env_W}};
+    for (const Cp &c : cps)
+        if ((e = hipMemcpyAsync((void *)c.dst, c.src, c.n, hipMemcpyHostToDevice, s->copy)) != hipSuccess) return e;
+    if ((e = grt::launch_env_build(a.E.rgb, q.env_H, q.env_W, j.env, s->copy)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&j.ready, hipEventDisableTiming)) != hipSuccess) return e;
+    return hipEventRecord(j.ready, s->copy);
+}
+
+void setup_args(grt_server *s, ServerJob &j)
+{
+    grt::RenderArgs &a = j.args;
+    a.S = s->S;
+    a.E.H = j.spec.env_H;
+    a.E.W = j.spec.env_W;
+    a.E.marg = j.env.marg;
+    a.E.cond = j.env.cond;
+    a.H = j.spec.H;
+    a.W = j.spec.W;
+    a.nc = j.spec.n_cos;
+    a.ng = j.spec.n_ggx;
+    a.ne = j.spec.n_env;
+    a.seed = j.spec.seed;
+    a.job = j.spec.job;
+    a.tmin = s->opts.t_min;
+    a.tcut = s->opts.t_cut;
+    a.saved = nullptr;
+    a.dump = nullptr;
+    a.grad = nullptr;
+}
+
+void finish_job(grt_server *s, ServerJob &j, int status)
+{
+    if (j.ready) { (void)hipEventDestroy(j.ready); j.ready = nullptr; }
+    if (j.bytes) s->alloc.release(j.off, j.bytes);
+    j.bytes = 0;
+    if (j.slot >= 0) s->free_slots.push_back(j.slot);
+    j.slot = -1;
+    j.state = kDone;
+    j.status = status;
+    j.t_done = s->now();
+}
+
+void fail_all(grt_server *s, int status)
+{
+    for (uint64_t id : s->resident) finish_job(s, s->jobs[id], status);
+    s->resident.clear();
+    for (uint64_t id : s->pending) finish_job(s, s->jobs[id], status);
+    s->pending.clear();
+}
+
+void scheduler(grt_server *s)
+{
+    (void)hipSetDevice(s->ctx->device);
+    const int64_t budget = s->opts.epoch_rays > 0 ? s->opts.epoch_rays : (int64_t)4 << 20;
+    // a share below this is not worth a chunk of its own
+    const int64_t min_share = std::max<int64_t>(256, budget / (4 * (int64_t)s->opts.max_jobs));
+    std::vector<uint64_t> to_upload;
+    for (;;) {
+        std::vector<uint64_t> run, finishing;
+        std::vector<int64_t> takes;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            if (s->stop) break;
+            // admission in arrival order while a slot and pool room are free
+            while (!s->pending.empty() && !s->free_slots.empty()) {
+                ServerJob &j = s->jobs[s->pending.front()];
+                size_t off;
+                if (!s->alloc.alloc(j.bytes, off)) break;
+                j.off = off;
+                j.slot = s->free_slots.back();
+                s->free_slots.pop_back();
+                grt::carve_job(j, s->pool + off);
+                setup_args(s, j);
+                j.state = kUploading;
+                s->pending.pop_front();
+                s->resident.push_back(j.id);
+                to_upload.push_back(j.id);
+            }
+        }
+        for (uint64_t id : to_upload) {
+            ServerJob *j;
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                j = &s->jobs[id];
+            }
+            if (upload(s, *j) != hipSuccess) {
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->error = GRT_ERR_DEVICE;
+                fail_all(s, GRT_ERR_DEVICE);
+                s->cv.notify_all();
+                return;
+            }
+        }
+        to_upload.clear();
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            // drop cancelled residents; promote uploaded ones; plan the epoch
+            std::vector<uint64_t> keep;
+            for (uint64_t id : s->resident) {
+                ServerJob &j = s->jobs[id];
+                if (j.cancel) {
+                    if (j.ready) (void)hipEventSynchronize(j.ready);
+                    finish_job(s, j, GRT_ERR_CANCELLED);
+                    continue;
+                }
+                if (j.state == kUploading && hipEventQuery(j.ready) == hipSuccess) {
+                    j.state = kRunning;
+                    j.t_start = s->now();
+                }
+                keep.push_back(id);
+            }
+            s->resident.swap(keep);
+            for (uint64_t id : s->resident)
+                if (s->jobs[id].state == kRunning) run.push_back(id);
+            if (run.empty()) {
+                s->cv.notify_all();
+                if (s->resident.empty() && s->pending.empty())
+                    s->cv.wait(lk, [s] { return s->stop || !s->pending.empty(); });
+                else
+                    s->cv.wait_for(lk, std::chrono::microseconds(100));
+                continue;
+            }
+            // processor sharing: equal shares, leftovers to the earliest admitted
+            int64_t left = budget;
+            takes.assign(run.size(), 0);
+            for (int pass = 0; pass < 2 && left > 0; ++pass) {
+                int64_t share = pass == 0 ? std::max<int64_t>(budget / (int64_t)run.size(), min_share) : left;
+                for (size_t i = 0; i < run.size() && left > 0; ++i) {
+                    ServerJob &j = s->jobs[run[i]];
+                    const int64_t rem = j.total - j.next - takes[i];
+                    const int64_t t = std::min(rem, std::min(share, left));
+                    takes[i] += t;
+                    left -= t;
+                }
+            }
+            int nch = 0;
+            int64_t off = 0;
+            for (size_t i = 0; i < run.size(); ++i) {
+                ServerJob &j = s->jobs[run[i]];
+                s->h_jobs[j.slot] = j.args;
+                if (takes[i] <= 0) continue;
+                s->h_chunks[nch].slot = j.slot;
+                s->h_chunks[nch].begin = j.next;
+                s->h_chunks[nch].offset = off;
+                ++nch;
+                off += takes[i];
+                j.next += takes[i];
+                if (j.next >= j.total) finishing.push_back(run[i]);
+            }
+            grt::ServeEpoch e;
+            e.jobs = s->d_jobs;
+            e.chunks = s->d_chunks;
+            e.nchunks = nch;
+            e.total = off;
+            e.counters = s->counters;
+            e.S = s->S;
+            hipError_t err = hipSuccess;
+            if (nch > 0) {
+                err = hipMemcpyAsync(s->d_jobs, s->h_jobs, sizeof(grt::RenderArgs) * s->opts.max_jobs,
+                                     hipMemcpyHostToDevice, s->compute);
+                if (err == hipSuccess)
+                    err = hipMemcpyAsync(s->d_chunks, s->h_chunks, sizeof(grt::ServeChunk) * nch,
+                                         hipMemcpyHostToDevice, s->compute);
+                if (err == hipSuccess) err = grt::launch_epoch(e, s->opts.k, s->ctx->num_cu, s->compute);
+            }
+            for (uint64_t id : finishing) {
+                if (err != hipSuccess) break;
+                ServerJob &j = s->jobs[id];
+                hipLaunchKernelGGL(grt::k_serve_reduce, dim3((unsigned)((j.npix + 255) / 256)), dim3(256), 0,
+                                   s->compute, s->d_jobs + j.slot, j.npix);
+                err = hipGetLastError();
+                if (err == hipSuccess)
+                    err = hipMemcpyAsync(j.spec.out_rgb, j.args.out, 12 * (size_t)j.npix, hipMemcpyDeviceToHost,
+                                         s->compute);
+            }
+            s->rays_done += off;
+            ++s->epochs;
+            if (err != hipSuccess) {
+                s->error = GRT_ERR_DEVICE;
+                fail_all(s, GRT_ERR_DEVICE);
+                s->cv.notify_all();
+                return;
+            }
+        }
+        // the epoch runs while submitters keep queueing
+        const hipError_t err = hipStreamSynchronize(s->compute);
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (err != hipSuccess) {
+            s->error = GRT_ERR_DEVICE;
+            fail_all(s, GRT_ERR_DEVICE);
+            s->cv.notify_all();
+            return;
+        }
+        std::vector<uint64_t> keep;
+        for (uint64_t id : s->resident) {
+            bool fin = false;
+            for (uint64_t f : finishing) fin = fin || f == id;
+            if (fin) finish_job(s, s->jobs[id], GRT_OK);
+            else keep.push_back(id);
+        }
+        s->resident.swap(keep);
+        s->cv.notify_all();
+    }
+    std::lock_guard<std::mutex> lk(s->mu);
+    (void)hipStreamSynchronize(s->copy);
+    fail_all(s, GRT_ERR_CANCELLED);
+    s->cv.notify_all();
+}
+
+void destroy_resources(grt_server *s)
+{
+    if (s->compute) (void)hipStreamSynchronize(s->compute);
+    if (s->copy) (void)hipStreamSynchronize(s->copy);
+    if (s->pool) (void)hipFree(s->pool);
+    if (s->d_jobs) (void)hipFree(s->d_jobs);
+    if (s->d_chunks) (void)hipFree(s->d_chunks);
+    if (s->counters) (void)hipFree(s->counters);
+    if (s->h_jobs) (void)hipHostFree(s->h_jobs);
+    if (s->h_chunks) (void)hipHostFree(s->h_chunks);
+    if (s->compute) (void)hipStreamDestroy(s->compute);
+    if (s->copy) (void)hipStreamDestroy(s->copy);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t grt_server_job_bytes(const grt_job *job)
+{
+    if (check_job(job) != GRT_OK) return 0;
+    return job_bytes(*job);
+}
+
+int grt_server_create(grt_ctx *ctx, const grt_scene *scene, const grt_server_opts *opts, grt_server **out)
+{
+    if (!ctx || !scene || !opts || !out) return sfail(GRT_ERR_INVALID, "NULL argument");
+    *out = nullptr;
+    if (opts->max_jobs <= 0 || opts->max_jobs > 256) return sfail(GRT_ERR_INVALID, "max_jobs must be in 1..256");
+    if (opts->mem_budget < ((size_t)1 << 20)) return sfail(GRT_ERR_INVALID, "mem_budget below 1 MiB");
+    if (!(opts->k == 4 || opts->k == 8 || opts->k == 16)) return sfail(GRT_ERR_INVALID, "server k must be 4, 8 or 16");
+    if (!(opts->t_min >= 0.0f) || !(opts->t_cut >= 0.0f && opts->t_cut < 1.0f))
+        return sfail(GRT_ERR_INVALID, "bad t_min / t_cut");
+    grt_server *s = new (std::nothrow) grt_server;
+    if (!s) return sfail(GRT_ERR_OOM, "host allocation failed");
+    const char *why = nullptr;
+    if (grt::scene_dev_of(scene, &s->S, &why) != GRT_OK) {
+        delete s;
+        return sfail(GRT_ERR_NOT_BUILT, why ? why : "scene not built");
+    }
+    s->ctx = ctx;
+    s->opts = *opts;
+    s->t0 = grt::Clock::now();
+    bool ok = hipSetDevice(ctx->device) == hipSuccess;
+    ok = ok && hipMalloc((void **)&s->pool, opts->mem_budget) == hipSuccess;
+    ok = ok && hipMalloc((void **)&s->d_jobs, sizeof(grt::RenderArgs) * opts->max_jobs) == hipSuccess;
+    ok = ok && hipMalloc((void **)&s->d_chunks, sizeof(grt::ServeChunk) * opts->max_jobs) == hipSuccess;
+    ok = ok && hipMalloc((void **)&s->counters, grt::kCounterBytes) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&s->h_jobs, sizeof(grt::RenderArgs) * opts->max_jobs) == hipSuccess;
+    ok = ok && hipHostMalloc((void **)&s->h_chunks, sizeof(grt::ServeChunk) * opts->max_jobs) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) == hipSuccess;
+    if (!ok) {
+        destroy_resources(s);
+        delete s;
+        return sfail(GRT_ERR_OOM, "device allocation for the server failed");
+    }
+    memset(s->h_jobs, 0, sizeof(grt::RenderArgs) * opts->max_jobs);
+    s->alloc.init(opts->mem_budget & ~(size_t)255);
+    for (int i = opts->max_jobs - 1; i >= 0; --i) s->free_slots.push_back(i);
+    try {
+        s->th = std::thread(scheduler, s);
+    } catch (...) {
+        destroy_resources(s);
+        delete s;
+        return sfail(GRT_ERR_DEVICE, "could not start the scheduler thread");
+    }
+    *out = s;
+    return GRT_OK;
+}
+
+int grt_server_submit(grt_server *s, const grt_job *job, uint64_t *id)
+{
+    if (!s || !id) return sfail(GRT_ERR_INVALID, "NULL argument");
+    if (check_job(job) != GRT_OK) return sfail(GRT_ERR_INVALID, "malformed job");
+    const size_t bytes = job_bytes(*job);
+    if (bytes > (s->opts.mem_budget & ~(size_t)255)) return sfail(GRT_ERR_ADMISSION, "job exceeds the memory budget");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->error) return sfail(s->error, "server failed");
+    if (s->pending.size() >= 4096) return sfail(GRT_ERR_BUSY, "queue full");
+    ServerJob &j = s->jobs[s->next_id];
+    j.id = s->next_id++;
+    j.spec = *job;
+    j.bytes = bytes;
+    j.npix = (int64_t)job->H * job->W;
+    j.total = j.npix * (job->n_cos + job->n_ggx + job->n_env);
+    j.t_submit = s->now();
+    s->pending.push_back(j.id);
+    *id = j.id;
+    s->cv.notify_all();
+    return GRT_OK;
+}
+
+int grt_server_poll(grt_server *s, uint64_t id, int *state)
+{
+    if (!s || !state) return sfail(GRT_ERR_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(id);
+    if (it == s->jobs.end()) return sfail(GRT_ERR_INVALID, "unknown job id");
+    *state = it->second.state == kDone && it->second.status != GRT_OK ? it->second.status : it->second.state;
+    return GRT_OK;
+}
+
+int grt_server_wait(grt_server *s, uint64_t id, double timeout_s)
+{
+    if (!s) return sfail(GRT_ERR_INVALID, "NULL argument");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(id);
+    if (it == s->jobs.end()) return sfail(GRT_ERR_INVALID, "unknown job id");
+    const auto deadline = grt::Clock::now() + std::chrono::duration<double>(timeout_s);
+    while (it->second.state != kDone) {
+        if (s->cv.wait_until(lk, deadline) == std::cv_status::timeout && it->second.state != kDone)
+            return sfail(GRT_ERR_TIMEOUT, "wait timed out");
+    }
+    return it->second.status;
+}
+
+int grt_server_cancel(grt_server *s, uint64_t id)
+{
+    if (!s) return sfail(GRT_ERR_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(id);
+    if (it == s->jobs.end()) return sfail(GRT_ERR_INVALID, "unknown job id");
+    ServerJob &j = it->second;
+    if (j.state == kDone) return GRT_OK;
+    if (j.state == kQueued) {
+        for (auto p = s->pending.begin(); p != s->pending.end(); ++p)
+            if (*p == id) { s->pending.erase(p); break; }
+        finish_job(s, j, GRT_ERR_CANCELLED);
+        s->cv.notify_all();
+        return GRT_OK;
+    }
+    j.cancel = true;  // dropped at the next epoch boundary
+    return GRT_OK;
+}
+
+int grt_server_job_times(grt_server *s, uint64_t id, double *submit_s, double *start_s, double *done_s)
+{
+    if (!s) return sfail(GRT_ERR_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(id);
+    if (it == s->jobs.end()) return sfail(GRT_ERR_INVALID, "unknown job id");
+    if (submit_s) *submit_s = it->second.t_submit;
+    if (start_s) *start_s = it->second.t_start;
+    if (done_s) *done_s = it->second.t_done;
+    return GRT_OK;
+}
+
+int grt_server_stats(grt_server *s, uint64_t *epochs, int64_t *rays, size_t *pool_free)
+{
+    if (!s) return sfail(GRT_ERR_INVALID, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (epochs) *epochs = s->epochs;
+    if (rays) *rays = s->rays_done;
+    if (pool_free) {
+        size_t f = 0;
+        for (auto &kv : s->alloc.free_) f += kv.second;
+        *pool_free = f;
+    }
+    return GRT_OK;
+}
+
+int grt_server_destroy(grt_server *s)
+{
+    if (!s) return GRT_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+        s->cv.notify_all();
+    }
+    if (s->th.joinable()) s->th.join();
+    destroy_resources(s);
+    delete s;
+    return GRT_OK;
+}
+
+}  // extern "C"

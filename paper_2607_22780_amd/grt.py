@@ -70,6 +70,18 @@ class grt_mis_opts(C.Structure):
                 ("sample_dump", VP)]
 
 
+class grt_server_opts(C.Structure):
+    _fields_ = [("mem_budget", C.c_size_t), ("max_jobs", C.c_int), ("epoch_rays", C.c_int64), ("k", C.c_int),
+                ("t_min", C.c_float), ("t_cut", C.c_float)]
+
+
+class grt_job(C.Structure):
+    _fields_ = [("H", C.c_int), ("W", C.c_int), ("x", VP), ("n", VP), ("wo", VP), ("albedo", VP), ("rough", VP),
+                ("metal", VP), ("valid", VP), ("env_rgb", VP), ("env_H", C.c_int), ("env_W", C.c_int),
+                ("n_cos", C.c_int), ("n_ggx", C.c_int), ("n_env", C.c_int), ("seed", C.c_uint64),
+                ("job", C.c_uint32), ("out_rgb", VP)]
+
+
 # every symbol include/grt.h declares, with (restype, argtypes)
 P = C.POINTER
 SIGNATURES = {
@@ -98,6 +110,15 @@ SIGNATURES = {
     "grt_render_mis": (C.c_int, [VP, VP, P(grt_gbuffer), P(grt_mis_opts), VP, VP, VP, C.c_size_t, VP]),
     "grt_render_mis_backward": (C.c_int, [VP, VP, P(grt_gbuffer), P(grt_mis_opts), VP, VP, P(grt_surfel_grads),
                                           VP, C.c_size_t, VP]),
+    "grt_server_job_bytes": (C.c_size_t, [P(grt_job)]),
+    "grt_server_create": (C.c_int, [VP, VP, P(grt_server_opts), P(VP)]),
+    "grt_server_submit": (C.c_int, [VP, P(grt_job), P(C.c_uint64)]),
+    "grt_server_poll": (C.c_int, [VP, C.c_uint64, P(C.c_int)]),
+    "grt_server_wait": (C.c_int, [VP, C.c_uint64, C.c_double]),
+    "grt_server_cancel": (C.c_int, [VP, C.c_uint64]),
+    "grt_server_job_times": (C.c_int, [VP, C.c_uint64, P(C.c_double), P(C.c_double), P(C.c_double)]),
+    "grt_server_stats": (C.c_int, [VP, P(C.c_uint64), P(C.c_int64), P(C.c_size_t)]),
+    "grt_server_destroy": (C.c_int, [VP]),
 }
 OPTIONAL = {}
 
@@ -548,3 +569,117 @@ class RenderMISFn(torch.autograd.Function):
         split, seed, k = ctx_.cfg
         g = render_mis_backward(ctx_.scene, ctx_.env, ctx_.gb, g_rgb, ctx_.saved_state, split=split, seed=seed, k=k)
         return g["means"], g["scales"], g["quats"], g["opacity"], g["rgb"], None, None, None, None, None, None, None
+
+
+# --------------------------------------------------------------------------
+# Relighting server
+# --------------------------------------------------------------------------
+
+def grt_server_create(ctx, scene, opts: grt_server_opts):
+    out = VP()
+    _check(load_library().grt_server_create(ctx, scene, C.byref(opts), C.byref(out)))
+    return out
+
+
+def grt_server_submit(server, job: grt_job) -> int:
+    jid = C.c_uint64()
+    _check(load_library().grt_server_submit(server, C.byref(job), C.byref(jid)))
+    return jid.value
+
+
+def grt_server_poll(server, jid: int) -> int:
+    st = C.c_int()
+    _check(load_library().grt_server_poll(server, jid, C.byref(st)))
+    return st.value
+
+
+def grt_server_wait(server, jid: int, timeout_s: float) -> int:
+    return load_library().grt_server_wait(server, jid, timeout_s)
+
+
+def grt_server_cancel(server, jid: int):
+    _check(load_library().grt_server_cancel(server, jid))
+
+
+def grt_server_job_times(server, jid: int):
+    a, b, c = C.c_double(), C.c_double(), C.c_double()
+    _check(load_library().grt_server_job_times(server, jid, C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
+
+
+def grt_server_stats(server):
+    e, r, f = C.c_uint64(), C.c_int64(), C.c_size_t()
+    _check(load_library().grt_server_stats(server, C.byref(e), C.byref(r), C.byref(f)))
+    return dict(epochs=e.value, rays=r.value, pool_free=f.value)
+
+
+def grt_server_destroy(server):
+    _check(load_library().grt_server_destroy(server))
+
+
+def grt_server_job_bytes(job: grt_job) -> int:
+    return int(load_library().grt_server_job_bytes(C.byref(job)))
+
+
+class Request:
+    """A relighting request over host tensors (pinned when ``pin``), kept
+    alive until the server is done with it."""
+
+    def __init__(self, gb, env_rgb, split=(16, 8, 8), seed=0, job=0, pin=True):
+        def host(a):
+            t = torch.from_numpy(a) if not isinstance(a, torch.Tensor) else a
+            t = t.contiguous()
+            return t.pin_memory() if pin else t
+        self.arrays = [host(a) for a in (gb.x, gb.n, gb.wo, gb.albedo, gb.rough, gb.metal, gb.valid)]
+        self.env = host(env_rgb)
+        self.out = torch.zeros(gb.H * gb.W, 3)
+        if pin:
+            self.out = self.out.pin_memory()
+        self.H, self.W = int(gb.H), int(gb.W)
+        x, n, wo, alb, rough, metal, valid = self.arrays
+        self.struct = grt_job(self.H, self.W, _ptr(x), _ptr(n), _ptr(wo), _ptr(alb), _ptr(rough), _ptr(metal),
+                              _ptr(valid), _ptr(self.env), int(self.env.shape[0]), int(self.env.shape[1]),
+                              split[0], split[1], split[2], seed, job, _ptr(self.out))
+        self.rays = self.H * self.W * sum(split)
+
+
+class Server:
+    """Owns a grt_server over a built scene; submit Requests, wait, read times."""
+
+    def __init__(self, ctx: Context, scene: Scene, mem_budget: int, max_jobs: int = 16, epoch_rays: int = 0, k=8,
+                 t_min=1e-3, t_cut=1e-3):
+        self.ctx, self.scene = ctx, scene
+        self.opts = grt_server_opts(int(mem_budget), int(max_jobs), int(epoch_rays), int(k), float(t_min),
+                                    float(t_cut))
+        self.handle = grt_server_create(ctx.handle, scene.handle, self.opts)
+        self.requests = {}
+
+    def submit(self, req: Request) -> int:
+        jid = grt_server_submit(self.handle, req.struct)
+        self.requests[jid] = req
+        return jid
+
+    def wait(self, jid: int, timeout_s: float = 120.0) -> int:
+        return grt_server_wait(self.handle, jid, timeout_s)
+
+    def poll(self, jid: int) -> int:
+        return grt_server_poll(self.handle, jid)
+
+    def cancel(self, jid: int):
+        grt_server_cancel(self.handle, jid)
+
+    def times(self, jid: int):
+        return grt_server_job_times(self.handle, jid)
+
+    def stats(self):
+        return grt_server_stats(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            grt_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _LIB is not None:
+            _LIB.grt_server_destroy(self.handle)
+            self.handle = None

@@ -1,0 +1,133 @@
+"""The relighting server (continuous batching over a resident scene):
+every request's image equals grt_render_mis on the same inputs, alone and
+mixed with others; admission by memory and slots; cancellation; a small
+request submitted behind a large one finishes first (processor sharing)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2607_22780_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def setup():
+    from gpu_util import scene_tensors
+    from paper_2607_22780_amd import grt
+    ctx = grt.Context(0)
+    s = W.scene1(n=40000, seed=3, s_lo=0.005, s_hi=0.03)
+    scene = grt.Scene(ctx, *scene_tensors(s))
+    torch.cuda.synchronize()
+    return grt, ctx, scene
+
+
+def direct(grt, ctx, scene, gb, env, split, seed, job):
+    from gpu_util import t
+    E = grt.Env(ctx, t(env))
+    G = grt.GBuffer.from_numpy(gb, torch.device("cuda", 0))
+    out = grt.render_mis(scene, E, G, split=split, seed=seed, job=job, k=8)["rgb"].cpu().numpy()
+    torch.cuda.synchronize()
+    return out
+
+
+def requests(n, seed=0):
+    g = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        res = int(g.choice([24, 40, 64, 96]))
+        spp = int(g.choice([4, 8, 16, 32]))
+        gb = W.gbuffer1(res, res + 3, seed=3, cam_stream=10 + i)
+        env = W.envmap(32, 64, seed=i + 1)
+        out.append((gb, env, W.mis_split(spp), 100 + i, 7 + i))
+    return out
+
+
+def test_alone_and_mixed_match_direct_render(setup):
+    grt, ctx, scene = setup
+    reqs = requests(6)
+    ref = [direct(grt, ctx, scene, gb, env, split, seed, job) for gb, env, split, seed, job in reqs]
+    # alone: one at a time
+    srv = grt.Server(ctx, scene, mem_budget=1 << 30, max_jobs=8, epoch_rays=1 << 16)
+    for (gb, env, split, seed, job), want in zip(reqs, ref):
+        r = grt.Request(gb, env, split, seed, job)
+        jid = srv.submit(r)
+        assert srv.wait(jid) == 0
+        np.testing.assert_array_equal(r.out.numpy(), want)
+    # mixed: all at once, small epochs so they interleave
+    rs = [grt.Request(gb, env, split, seed, job) for gb, env, split, seed, job in reqs]
+    ids = [srv.submit(r) for r in rs]
+    for jid, r, want in zip(ids, rs, ref):
+        assert srv.wait(jid) == 0
+        np.testing.assert_array_equal(r.out.numpy(), want)
+    st = srv.stats()
+    assert st["epochs"] > len(reqs) and st["pool_free"] == (1 << 30)
+    srv.close()
+
+
+def test_admission_by_memory_and_queueing(setup):
+    grt, ctx, scene = setup
+    reqs = requests(4, seed=1)
+    rs = [grt.Request(gb, env, split, seed, job) for gb, env, split, seed, job in reqs]
+    need = max(grt.grt_server_job_bytes(r.struct) for r in rs)
+    # a pool that holds one request at a time: all still finish, in order
+    srv = grt.Server(ctx, scene, mem_budget=need + (1 << 20), max_jobs=4, epoch_rays=1 << 15)
+    ids = [srv.submit(r) for r in rs]
+    for jid in ids:
+        assert srv.wait(jid) == 0
+    start = [srv.times(j)[1] for j in ids]
+    assert start == sorted(start)  # admitted in arrival order
+    assert srv.stats()["pool_free"] >= need
+    # a request that can never fit is refused at submission
+    big = grt.Request(W.gbuffer1(200, 200, seed=3), W.envmap(32, 64), (16, 8, 8), 1, 1)
+    with pytest.raises(grt.GrtError) as e:
+        srv.submit(big)
+    assert e.value.code == grt.ERR_ADMISSION
+    srv.close()
+
+
+def test_malformed_request_rejected(setup):
+    grt, ctx, scene = setup
+    gb, env, split, seed, job = requests(1)[0]
+    r = grt.Request(gb, env, (0, 0, 0), seed, job)
+    srv = grt.Server(ctx, scene, mem_budget=1 << 28)
+    with pytest.raises(grt.GrtError) as e:
+        srv.submit(r)
+    assert e.value.code == grt.ERR_INVALID
+    srv.close()
+
+
+def test_cancel_queued_and_running(setup):
+    grt, ctx, scene = setup
+    big = grt.Request(W.gbuffer1(160, 160, seed=3), W.envmap(32, 64), (32, 16, 16), 5, 5)
+    small = grt.Request(W.gbuffer1(16, 16, seed=3), W.envmap(32, 64), (2, 1, 1), 6, 6)
+    srv = grt.Server(ctx, scene, mem_budget=1 << 31, max_jobs=1, epoch_rays=1 << 14)
+    a = srv.submit(big)
+    b = srv.submit(small)  # queued behind a (one slot)
+    srv.cancel(b)
+    assert srv.wait(b) == grt.ERR_CANCELLED
+    srv.cancel(a)
+    assert srv.wait(a) == grt.ERR_CANCELLED
+    assert srv.stats()["pool_free"] == (1 << 31)
+    c = srv.submit(small)
+    assert srv.wait(c) == 0
+    srv.close()
+
+
+def test_small_request_overtakes_large(setup):
+    """Continuous batching: a small request arriving while a large one runs
+    shares the epochs and completes first."""
+    grt, ctx, scene = setup
+    big = grt.Request(W.gbuffer1(192, 192, seed=3), W.envmap(32, 64), (32, 16, 16), 5, 5)
+    small = grt.Request(W.gbuffer1(16, 16, seed=3, cam_stream=4), W.envmap(32, 64, seed=2), (4, 2, 2), 6, 6)
+    srv = grt.Server(ctx, scene, mem_budget=1 << 31, max_jobs=4, epoch_rays=1 << 16)
+    a = srv.submit(big)
+    import time
+    t0 = time.time()
+    while 0 <= srv.poll(a) < 2 and time.time() - t0 < 60:
+        time.sleep(1e-4)
+    assert srv.poll(a) == 2
+    b = srv.submit(small)
+    assert srv.wait(b) == 0 and srv.wait(a) == 0
+    assert srv.times(b)[2] < srv.times(a)[2]
+    srv.close()
