@@ -95,10 +95,9 @@ def bytes_per_ray(wc, env_hw=(256, 512)):
     return fwd, bwd
 
 
-def cpu_baseline(npx: int = 48):
+def cpu_baseline(s, gb, env, npx: int = 128):
     """The oracle (brute force, OpenMP) on a bounded sample of the same step."""
     from oracle import oracle as O
-    s, gb, env = make_inputs()
     valid = np.nonzero(gb.valid)[0]
     pix = np.sort(np.random.default_rng(2).choice(valid, npx, replace=False))
     grad = np.random.default_rng(3).normal(0, 1, (npx, 3))
@@ -115,6 +114,117 @@ def cpu_baseline(npx: int = 48):
                        f"{t1 - t0:.2f}s + backward {t2 - t1:.2f}s, scene/G-buffer generation excluded")
 
 
+def _gbuffer_task(key):
+    from paper_2607_22780_amd import workloads as W
+    res, cam = key
+    return key, W.gbuffer3(res, res, cam_stream=10 + cam)
+
+
+def serve_inputs(n, rate):
+    """Relighting requests over the room scene: Poisson arrivals; resolution,
+    spp, camera and a 128x256 environment map per request."""
+    from concurrent.futures import ProcessPoolExecutor
+    from paper_2607_22780_amd import workloads as W
+    reqs = W.requests4(n, rate)
+    keys = sorted({(q.res, q.cam) for q in reqs}, key=lambda k: -k[0])
+    with ProcessPoolExecutor(max_workers=min(8, len(keys))) as ex:
+        gbs = dict(ex.map(_gbuffer_task, keys))
+    envs = [W.envmap(128, 256, seed=q.env_seed, stream=3, config_id=1) for q in reqs]
+    return reqs, gbs, envs
+
+
+def serve_leg(ctx, scene, k, reqs, gbs, envs, slack=-1.0, epoch=0, detail=False):
+    """The persistent batched server versus one launch per request (upload,
+    table build, render, copy back, in arrival order), on the same requests
+    replayed at their arrival times and then all at once."""
+    import torch
+    from paper_2607_22780_amd import grt
+    from paper_2607_22780_amd import workloads as W
+    dev = torch.device("cuda", 0)
+    from types import SimpleNamespace
+    splits = [W.mis_split(q.spp) for q in reqs]
+    pin = lambda a: torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
+    pinned = {key: SimpleNamespace(H=g.H, W=g.W, x=pin(g.x), n=pin(g.n), wo=pin(g.wo), albedo=pin(g.albedo),
+                                   rough=pin(g.rough), metal=pin(g.metal), valid=pin(g.valid))
+              for key, g in gbs.items()}
+    mk = lambda: [grt.Request(pinned[(q.res, q.cam)], pin(envs[i]), splits[i], q.seed, q.rid)
+                  for i, q in enumerate(reqs)]
+    req_srv, req_one = mk(), mk()
+    rays = sum(r.rays for r in req_srv)
+
+    def run_server(replay):
+        srv = grt.Server(ctx, scene, mem_budget=48 << 30, max_jobs=16, k=k, slack_per_ray=slack, epoch_rays=epoch)
+        warm = grt.Request(pinned[(reqs[0].res, reqs[0].cam)], pin(envs[0]), (1, 1, 1), 1, 1)
+        srv.wait(srv.submit(warm))
+        t0 = time.perf_counter()
+        ids = []
+        for q, r in zip(reqs, req_srv):
+            if replay:
+                dt = t0 + q.arrival_s - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+            ids.append(srv.submit(r))
+        for j in ids:
+            st = srv.wait(j, 600.0)
+            if st != 0:
+                raise grt.GrtError(st, "server request failed")
+        times = [srv.times(j) for j in ids]
+        lat = [d - s for s, _, d in times]
+        span = max(d for _, _, d in times) - min(s for s, _, _ in times)
+        stats = srv.stats()
+        srv.close()
+        return lat, span, stats
+
+    def run_one(replay):
+        stream = torch.cuda.current_stream()
+        t0 = time.perf_counter()
+        lat = []
+        for q, r in zip(reqs, req_one):
+            if replay:
+                dt = t0 + q.arrival_s - time.perf_counter()
+                if dt > 0:
+                    time.sleep(dt)
+            arrive = t0 + q.arrival_s if replay else t0
+            x, n, wo, alb, rough, metal, valid = (a.to(dev, non_blocking=True) for a in r.arrays)
+            G = grt.GBuffer(r.H, r.W, x, n, wo, alb, rough, metal, valid)
+            E = grt.Env(ctx, r.env.to(dev, non_blocking=True))
+            sp = (r.struct.n_cos, r.struct.n_ggx, r.struct.n_env)
+            out = grt.render_mis(scene, E, G, split=sp, seed=r.struct.seed, job=r.struct.job, k=k)["rgb"]
+            r.out.copy_(out, non_blocking=True)
+            stream.synchronize()
+            lat.append(time.perf_counter() - arrive)
+            del E
+        return lat, time.perf_counter() - t0
+
+    pct = lambda a, p: float(np.percentile(np.asarray(a), p))
+    res = {}
+    log("bench: server leg (replayed arrivals)")
+    lat_s, span_s, st = run_server(True)
+    log("bench: per-request leg (replayed arrivals)")
+    lat_o, span_o = run_one(True)
+    same = all(torch.equal(a.out, b.out) for a, b in zip(req_srv, req_one))
+    log("bench: server leg (all at once)")
+    _, burst_s, _ = run_server(False)
+    log("bench: per-request leg (all at once)")
+    _, burst_o = run_one(False)
+    res = {
+        "workload": f"room scene resident; {len(reqs)} requests, Poisson {reqs[-1].arrival_s / max(len(reqs) - 1, 1):.3f}"
+                    f" s mean gap, res in {{256,512,768,1024}}^2, spp in {{4..64}}, 128x256 env each",
+        "rays": rays,
+        "server": {"p50_s": round(pct(lat_s, 50), 4), "p99_s": round(pct(lat_s, 99), 4),
+                   "mrays_s_replay": round(rays / span_s / 1e6, 2), "mrays_s_burst": round(rays / burst_s / 1e6, 2),
+                   "epochs": st["epochs"]},
+        "one_launch_per_request": {"p50_s": round(pct(lat_o, 50), 4), "p99_s": round(pct(lat_o, 99), 4),
+                                   "mrays_s_replay": round(rays / span_o / 1e6, 2),
+                                   "mrays_s_burst": round(rays / burst_o / 1e6, 2)},
+        "images_identical": bool(same),
+    }
+    if detail:
+        res["latency_s"] = [dict(res=q.res, spp=q.spp, arrival=round(q.arrival_s, 3), server=round(a, 4),
+                                 one_launch=round(b, 4)) for q, a, b in zip(reqs, lat_s, lat_o)]
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +232,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--k", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-pixels", type=int, default=128, help="pixels of the step the oracle times")
+    ap.add_argument("--no-serve", action="store_true", help="skip the relighting-server leg")
+    ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--serve-rate", type=float, default=4.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-slack", type=float, default=-1.0, help="server deadline seconds per ray (-1: default)")
+    ap.add_argument("--serve-epoch", type=int, default=0, help="server rays per epoch (0: default)")
     ap.add_argument("--count-work", action="store_true", help="recount per-ray work with the oracle and exit")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (calibrates the HBM byte counters)")
@@ -215,10 +331,17 @@ def main():
         torch.cuda.synchronize()
         del a, b
 
+    serve = None
+    if not args.no_serve:
+        log("bench: generating relighting requests")
+        reqs, gbs, envs = serve_inputs(args.serve_requests, args.serve_rate)
+        serve = serve_leg(ctx, scene, args.k, reqs, gbs, envs, args.serve_slack, args.serve_epoch)
+        del reqs, gbs, envs
+
     cpu = None
     if not args.no_cpu_baseline:
         log("bench: cpu baseline (oracle)")
-        cpu = cpu_baseline()
+        cpu = cpu_baseline(s, gb, env, args.cpu_pixels)
 
     out = {
         "metric": "Mrays/s fwd & fwd+bwd (1M surfels, 32 spp); relight p50/p99 latency",
@@ -239,6 +362,7 @@ def main():
         "fwd_mrays_s": round(rays / (fwd_ms * 1e-3) / 1e6, 2),
         "phase_ms": {"build": round(build_ms, 3), "render_fwd": round(fwd_ms, 3), "render_bwd": round(bwd_ms, 3)},
         "roofline": roofline,
+        "relight_server": serve,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

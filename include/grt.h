@@ -277,19 +277,25 @@ int grt_render_mis_backward(const grt_scene *scene, const grt_env *env, const gr
  * (Sec. 3.5.1: relighting evaluates the rendering equation with the MIS
  * density for every pixel of a view under a new environment map).  One
  * scheduler thread runs in epochs: it admits queued requests in arrival order
- * while a slot and room in the device pool are free (uploads and sampling
- * tables on a copy stream, overlapping compute), shares each epoch's ray
- * budget equally among resident requests, and traces the rays of all of them
- * in one generation launch plus one persistent trace launch; requests that
- * complete are reduced per pixel and copied back.  A request's image equals
+ * while a slot and room in the device pool are free (uploads, sampling
+ * tables and every sample's ray record on a copy stream, overlapping the
+ * trace), hands each epoch's ray budget to resident requests in order of
+ * deadline (arrival time plus slack_per_ray times the request's ray count,
+ * so small requests pass large ones while a large one is never starved), and
+ * traces the rays of all of them in one persistent trace launch.  Two
+ * epochs are in flight at once on two streams, so the waves of the next
+ * epoch fill the tail of the current one.  Requests that complete are
+ * reduced per pixel and copied back.  A request's image equals
  * grt_render_mis with the same inputs and opts (seed, job) whatever it was
  * mixed with.  The scene must not be rebuilt or destroyed while the server
  * exists.
  *
- * mem_budget: device bytes the server allocates for requests (its pool).
- * max_jobs:   requests resident at once (1..256).
- * epoch_rays: rays per epoch across all requests (0 = 4,194,304).
- * k:          k-buffer size, 4, 8 or 16.  t_min, t_cut as in grt_mis_opts. */
+ * mem_budget:    device bytes the server allocates for requests (its pool).
+ * max_jobs:      requests resident at once (1..256).
+ * epoch_rays:    rays per epoch across all requests (0 = 2,097,152).
+ * k:             k-buffer size, 4, 8 or 16.  t_min, t_cut as in grt_mis_opts.
+ * slack_per_ray: seconds of deadline per ray (0 = arrival order only;
+ *                negative = 4e-8, about twice a request's time alone). */
 typedef struct {
     size_t mem_budget;
     int max_jobs;
@@ -297,6 +303,7 @@ typedef struct {
     int k;
     float t_min;
     float t_cut;
+    double slack_per_ray;
 } grt_server_opts;
 
 /* A request.  All pointers are HOST memory, borrowed until the request is

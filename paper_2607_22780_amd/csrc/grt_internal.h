@@ -156,6 +156,8 @@ struct RenderArgs {
     const float *grad;
     GradPtrs g;
 };
+// one ray record per sample of the whole G-buffer (sampling only, no trace)
+hipError_t launch_render_gen(const RenderArgs &a, hipStream_t st);
 hipError_t launch_render(const RenderArgs &a, int k, int num_cu, hipStream_t st);
 hipError_t launch_render_backward(const RenderArgs &a, int k, int num_cu, hipStream_t st);
 

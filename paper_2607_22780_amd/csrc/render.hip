@@ -170,7 +170,7 @@ static hipError_t go_render_bwd(const RenderArgs &a, int num_cu, hipStream_t st)
     return hipGetLastError();
 }
 
-static hipError_t launch_gen(const RenderArgs &a, hipStream_t st)
+hipError_t launch_render_gen(const RenderArgs &a, hipStream_t st)
 {
     const int64_t total = (int64_t)a.H * a.W * (a.nc + a.ng + a.ne);
     hipLaunchKernelGGL(k_render_gen, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a);
@@ -183,7 +183,7 @@ hipError_t launch_render(const RenderArgs &a, int k, int num_cu, hipStream_t st)
     if (npix <= 0) return hipSuccess;
     hipError_t e = launch_zero_counters(a.counters, st);
     if (e != hipSuccess) return e;
-    if ((e = launch_gen(a, st)) != hipSuccess) return e;
+    if ((e = launch_render_gen(a, st)) != hipSuccess) return e;
     switch (k) {
     case 1: e = go_render<1>(a, num_cu, st); break;
     case 2: e = go_render<2>(a, num_cu, st); break;
@@ -204,7 +204,7 @@ hipError_t launch_render_backward(const RenderArgs &a, int k, int num_cu, hipStr
     if ((int64_t)a.H * a.W <= 0) return hipSuccess;
     hipError_t e = launch_zero_counters(a.counters, st);
     if (e != hipSuccess) return e;
-    if ((e = launch_gen(a, st)) != hipSuccess) return e;
+    if ((e = launch_render_gen(a, st)) != hipSuccess) return e;
     switch (k) {
     case 1: return go_render_bwd<1>(a, num_cu, st);
     case 2: return go_render_bwd<2>(a, num_cu, st);

@@ -4,13 +4,16 @@
 // served by one scheduler thread that runs in short epochs.  Each epoch it
 //   1. admits queued requests in arrival order while a slot and room in the
 //      device pool are free: the request's G-buffer and environment are
-//      uploaded and its sampling tables built on a copy stream, overlapping
-//      the compute stream;
-//   2. gives every resident request a share of the epoch's ray budget
-//      (processor sharing, so a large request does not block small ones);
-//   3. launches one generation kernel and one persistent trace kernel over
-//      the rays of all requests of the epoch together (the mix), then, for the
-//      requests that complete, the per-pixel reduction and the copy back.
+//      uploaded, its sampling tables built and all its sample rays generated
+//      on a copy stream, overlapping the trace;
+//   2. hands the epoch's ray budget to running requests in order of deadline
+//      (arrival plus a slack proportional to the request's size, so small
+//      requests pass large ones and no request starves);
+//   3. launches one persistent trace kernel over the rays of all requests of
+//      the epoch together (the mix), then, for the requests that complete,
+//      the per-pixel reduction and the copy back.
+// Two epochs are in flight on two streams: the next epoch's waves take the
+// CUs that the current epoch's tail leaves idle.
 // Every sample's random counter carries its request id and every pixel is
 // summed in sample order, so a request's image is the same alone or in any
 // mix.  Scene and LBVH stay resident; each epoch launch ends when its rays
@@ -59,14 +62,6 @@ __device__ __forceinline__ int find_chunk(const ServeEpoch &e, int64_t g)
     return lo;
 }
 
-__global__ void __launch_bounds__(256) k_serve_gen(ServeEpoch e)
-{
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= e.total) return;
-    const ServeChunk ch = e.chunks[find_chunk(e, g)];
-    gen_ray(e.jobs[ch.slot], ch.begin + (g - ch.offset));
-}
-
 template <int K>
 struct ServeJob {
     const ServeEpoch &e;
@@ -97,6 +92,30 @@ __global__ void __launch_bounds__(256) GRT_OCCUPANCY k_serve(ServeEpoch e)
     run_persistent<K>(job, e.counters, e.total);
 }
 
+// An epoch holding a contiguous ray range of one request: the request's
+// arguments travel by value (uniform across the grid, as in a direct render).
+template <int K>
+struct ServeOneJob {
+    const RenderArgs &a;
+    SceneDev S;
+    ShadeTrace<K> t;
+    int64_t r0;
+
+    __device__ ServeOneJob(const RenderArgs &a_, int64_t r0_) : a(a_), S(a_.S), r0(r0_) {}
+    __device__ __forceinline__ Walker<K> &walker() { return t.w; }
+    __device__ __forceinline__ CompositeVisit &visit() { return t.v; }
+    __device__ __forceinline__ bool begin(int64_t g) { return t.begin(a, S, r0 + g); }
+    __device__ __forceinline__ void finish(int64_t g) { t.finish(a, r0 + g); }
+};
+
+template <int K>
+__global__ void __launch_bounds__(256) GRT_OCCUPANCY
+    k_serve_one(RenderArgs a, int64_t r0, int64_t n, unsigned long long *counters)
+{
+    ServeOneJob<K> job(a, r0);
+    run_persistent<K>(job, counters, n);
+}
+
 __global__ void k_serve_reduce(const RenderArgs *a, int64_t npix)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -112,12 +131,29 @@ static hipError_t go_serve(const ServeEpoch &e, int num_cu, hipStream_t st)
     return hipGetLastError();
 }
 
-static hipError_t launch_epoch(const ServeEpoch &e, int k, int num_cu, hipStream_t st)
+template <int K>
+static hipError_t go_serve_one(const RenderArgs &a, int64_t r0, int64_t n, unsigned long long *counters, int num_cu,
+                               hipStream_t st)
 {
-    hipError_t err = launch_zero_counters(e.counters, st);
+    const int nb = persistent_blocks(k_serve_one<K>, num_cu, n);
+    hipLaunchKernelGGL(k_serve_one<K>, dim3(nb), dim3(256), 0, st, a, r0, n, counters);
+    return hipGetLastError();
+}
+
+// one: the request of a single-request epoch (its chunk 0), else null
+static hipError_t launch_epoch(const ServeEpoch &e, const RenderArgs *one, int64_t r0, int k, int num_cu,
+                               hipStream_t st)
+{
+    const hipError_t err = launch_zero_counters(e.counters, st);
     if (err != hipSuccess) return err;
-    hipLaunchKernelGGL(k_serve_gen, dim3((unsigned)((e.total + 255) / 256)), dim3(256), 0, st, e);
-    if ((err = hipGetLastError()) != hipSuccess) return err;
+    if (one) {
+        switch (k) {
+        case 4: return go_serve_one<4>(*one, r0, e.total, e.counters, num_cu, st);
+        case 8: return go_serve_one<8>(*one, r0, e.total, e.counters, num_cu, st);
+        case 16: return go_serve_one<16>(*one, r0, e.total, e.counters, num_cu, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (k) {
     case 4: return go_serve<4>(e, num_cu, st);
     case 8: return go_serve<8>(e, num_cu, st);
@@ -144,6 +180,8 @@ struct ServerJob {
     RenderArgs args{};
     EnvWS env{};
     int64_t npix = 0, total = 0, next = 0;
+    int inflight = 0;      // epochs in flight that hold rays of this job
+    double deadline = 0;   // scheduling key
     hipEvent_t ready = nullptr;
     double t_submit = 0, t_start = -1, t_done = -1;
 };
@@ -211,6 +249,18 @@ static size_t carve_job(ServerJob &j, char *base)
     return off;
 }
 
+// One of the two epochs that can be in flight: its tables, stream and the
+// jobs it touches.
+struct EpochSlot {
+    RenderArgs *d_jobs = nullptr, *h_jobs = nullptr;
+    ServeChunk *d_chunks = nullptr, *h_chunks = nullptr;
+    unsigned long long *counters = nullptr;
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    bool inflight = false;
+    std::vector<uint64_t> members, finishing;
+};
+
 }  // namespace grt
 
 using grt::ServerJob;
@@ -223,6 +273,7 @@ struct grt_server {
     grt_ctx *ctx = nullptr;
     grt::SceneDev S{};
     grt_server_opts opts{};
+    double slack = 0;
     char *pool = nullptr;
     grt::PoolAlloc alloc;
     std::mutex mu;
@@ -234,10 +285,8 @@ struct grt_server {
     std::map<uint64_t, ServerJob> jobs;
     std::vector<uint64_t> resident;  // uploading or running, in admission order
     std::vector<int> free_slots;
-    hipStream_t compute = nullptr, copy = nullptr;
-    grt::RenderArgs *d_jobs = nullptr, *h_jobs = nullptr;
-    grt::ServeChunk *d_chunks = nullptr, *h_chunks = nullptr;
-    unsigned long long *counters = nullptr;
+    hipStream_t copy = nullptr;
+    grt::EpochSlot ep[2];
     uint64_t next_id = 1;
     grt::Clock::time_point t0;
     // statistics
@@ -287,6 +336,8 @@ hipError_t upload(grt_server *s, ServerJob &j)
     for (const Cp &c : cps)
         if ((e = hipMemcpyAsync((void *)c.dst, c.src, c.n, hipMemcpyHostToDevice, s->copy)) != hipSuccess) return e;
     if ((e = grt::launch_env_build(a.E.rgb, q.env_H, q.env_W, j.env, s->copy)) != hipSuccess) return e;
+    // every sample's ray record up front, so epochs only trace
+    if ((e = grt::launch_render_gen(a, s->copy)) != hipSuccess) return e;
     if ((e = hipEventCreateWithFlags(&j.ready, hipEventDisableTiming)) != hipSuccess) return e;
     return hipEventRecord(j.ready, s->copy);
 }
@@ -315,6 +366,7 @@ void setup_args(grt_server *s, ServerJob &j)
 
 void finish_job(grt_server *s, ServerJob &j, int status)
 {
+    if (j.state == kDone) return;
     if (j.ready) { (void)hipEventDestroy(j.ready); j.ready = nullptr; }
     if (j.bytes) s->alloc.release(j.off, j.bytes);
     j.bytes = 0;
@@ -325,6 +377,8 @@ void finish_job(grt_server *s, ServerJob &j, int status)
     j.t_done = s->now();
 }
 
+// Called with no epoch in flight (or after a device error, when nothing
+// more will be waited for).
 void fail_all(grt_server *s, int status)
 {
     for (uint64_t id : s->resident) finish_job(s, s->jobs[id], status);
@@ -333,176 +387,216 @@ void fail_all(grt_server *s, int status)
     s->pending.clear();
 }
 
+void device_failed(grt_server *s)
+{
+    s->error = GRT_ERR_DEVICE;
+    fail_all(s, GRT_ERR_DEVICE);
+    s->cv.notify_all();
+}
+
+// Admit queued jobs in arrival order while a slot and pool room are free.
+void admit(grt_server *s, std::vector<uint64_t> &to_upload)
+{
+    while (!s->pending.empty() && !s->free_slots.empty()) {
+        ServerJob &j = s->jobs[s->pending.front()];
+        size_t off;
+        if (!s->alloc.alloc(j.bytes, off)) break;
+        j.off = off;
+        j.slot = s->free_slots.back();
+        s->free_slots.pop_back();
+        grt::carve_job(j, s->pool + off);
+        setup_args(s, j);
+        j.state = kUploading;
+        s->pending.pop_front();
+        s->resident.push_back(j.id);
+        to_upload.push_back(j.id);
+    }
+}
+
+// An epoch has completed on the device: its finishing jobs are done,
+// cancelled jobs with no epoch left in flight are dropped.
+void retire(grt_server *s, grt::EpochSlot &E)
+{
+    for (uint64_t id : E.members) --s->jobs[id].inflight;
+    for (uint64_t id : E.finishing) {
+        ServerJob &j = s->jobs[id];
+        if (!j.cancel) finish_job(s, j, GRT_OK);
+    }
+    E.members.clear();
+    E.finishing.clear();
+    E.inflight = false;
+}
+
+// Drop cancelled jobs that no epoch references; promote uploaded jobs.
+void sweep(grt_server *s)
+{
+    std::vector<uint64_t> keep;
+    for (uint64_t id : s->resident) {
+        ServerJob &j = s->jobs[id];
+        if (j.state == kDone) continue;
+        if (j.cancel && j.inflight == 0) {
+            if (j.ready) (void)hipEventSynchronize(j.ready);
+            finish_job(s, j, GRT_ERR_CANCELLED);
+            continue;
+        }
+        if (j.state == kUploading && hipEventQuery(j.ready) == hipSuccess) {
+            j.state = kRunning;
+            j.t_start = s->now();
+        }
+        keep.push_back(id);
+    }
+    s->resident.swap(keep);
+}
+
+// An epoch below this many rays also takes rays of the next requests.
+constexpr int64_t kFillRays = 1 << 20;
+
+// Plan an epoch into slot E and launch it; false if no ray is left to trace.
+bool launch(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other, int64_t budget, hipError_t &err)
+{
+    std::vector<ServerJob *> run;
+    for (uint64_t id : s->resident) {
+        ServerJob &j = s->jobs[id];
+        if (j.state == kRunning && !j.cancel && j.next < j.total) run.push_back(&j);
+    }
+    if (run.empty()) return false;
+    // earliest deadline first; the budget goes down the list
+    std::stable_sort(run.begin(), run.end(),
+                     [](const ServerJob *a, const ServerJob *b) { return a->deadline < b->deadline; });
+    int nch = 0;
+    int64_t off = 0;
+    for (ServerJob *j : run) {
+        // an epoch is the head request's rest; small epochs are topped up
+        if (off >= budget || (nch > 0 && off >= kFillRays)) break;
+        const int64_t take = std::min(j->total - j->next, budget - off);
+        E.h_jobs[j->slot] = j->args;
+        E.h_chunks[nch].slot = j->slot;
+        E.h_chunks[nch].pad = 0;
+        E.h_chunks[nch].begin = j->next;
+        E.h_chunks[nch].offset = off;
+        ++nch;
+        off += take;
+        j->next += take;
+        ++j->inflight;
+        E.members.push_back(j->id);
+        if (j->next >= j->total) E.finishing.push_back(j->id);
+    }
+    grt::ServeEpoch e;
+    e.jobs = E.d_jobs;
+    e.chunks = E.d_chunks;
+    e.nchunks = nch;
+    e.total = off;
+    e.counters = E.counters;
+    e.S = s->S;
+    err = hipMemcpyAsync(E.d_jobs, E.h_jobs, sizeof(grt::RenderArgs) * s->opts.max_jobs, hipMemcpyHostToDevice,
+                         E.stream);
+    if (err == hipSuccess)
+        err = hipMemcpyAsync(E.d_chunks, E.h_chunks, sizeof(grt::ServeChunk) * nch, hipMemcpyHostToDevice, E.stream);
+    const grt::RenderArgs *one = nch == 1 ? &E.h_jobs[E.h_chunks[0].slot] : nullptr;
+    if (err == hipSuccess)
+        err = grt::launch_epoch(e, one, E.h_chunks[0].begin, s->opts.k, s->ctx->num_cu, E.stream);
+    // a finishing job may still have rays in the other epoch
+    if (err == hipSuccess && !E.finishing.empty() && other.inflight)
+        err = hipStreamWaitEvent(E.stream, other.done, 0);
+    for (uint64_t id : E.finishing) {
+        if (err != hipSuccess) break;
+        ServerJob &j = s->jobs[id];
+        hipLaunchKernelGGL(grt::k_serve_reduce, dim3((unsigned)((j.npix + 255) / 256)), dim3(256), 0, E.stream,
+                           E.d_jobs + j.slot, j.npix);
+        err = hipGetLastError();
+        if (err == hipSuccess)
+            err = hipMemcpyAsync(j.spec.out_rgb, j.args.out, 12 * (size_t)j.npix, hipMemcpyDeviceToHost, E.stream);
+    }
+    if (err == hipSuccess) err = hipEventRecord(E.done, E.stream);
+    E.inflight = true;
+    s->rays_done += off;
+    ++s->epochs;
+    return true;
+}
+
 void scheduler(grt_server *s)
 {
     (void)hipSetDevice(s->ctx->device);
-    const int64_t budget = s->opts.epoch_rays > 0 ? s->opts.epoch_rays : (int64_t)4 << 20;
-    // a share below this is not worth a chunk of its own
-    const int64_t min_share = std::max<int64_t>(256, budget / (4 * (int64_t)s->opts.max_jobs));
+    const int64_t budget = s->opts.epoch_rays > 0 ? s->opts.epoch_rays : (int64_t)1 << 26;
     std::vector<uint64_t> to_upload;
-    for (;;) {
-        std::vector<uint64_t> run, finishing;
-        std::vector<int64_t> takes;
-        {
-            std::unique_lock<std::mutex> lk(s->mu);
-            if (s->stop) break;
-            // admission in arrival order while a slot and pool room are free
-            while (!s->pending.empty() && !s->free_slots.empty()) {
-                ServerJob &j = s->jobs[s->pending.front()];
-                size_t off;
-                if (!s->alloc.alloc(j.bytes, off)) break;
-                j.off = off;
-                j.slot = s->free_slots.back();
-                s->free_slots.pop_back();
-                grt::carve_job(j, s->pool + off);
-                setup_args(s, j);
-                j.state = kUploading;
-                s->pending.pop_front();
-                s->resident.push_back(j.id);
-                to_upload.push_back(j.id);
+    std::unique_lock<std::mutex> lk(s->mu);
+    while (!s->stop) {
+        bool progressed = false;
+        admit(s, to_upload);
+        if (!to_upload.empty()) {
+            std::vector<uint64_t> ids;
+            ids.swap(to_upload);
+            for (uint64_t id : ids) {
+                ServerJob *j = &s->jobs[id];
+                lk.unlock();
+                const hipError_t e = upload(s, *j);
+                lk.lock();
+                if (e != hipSuccess) {
+                    device_failed(s);
+                    return;
+                }
             }
+            progressed = true;
         }
-        for (uint64_t id : to_upload) {
-            ServerJob *j;
-            {
-                std::lock_guard<std::mutex> lk(s->mu);
-                j = &s->jobs[id];
-            }
-            if (upload(s, *j) != hipSuccess) {
-                std::lock_guard<std::mutex> lk(s->mu);
-                s->error = GRT_ERR_DEVICE;
-                fail_all(s, GRT_ERR_DEVICE);
-                s->cv.notify_all();
+        // retire epochs that have completed (never block: arrivals keep
+        // being admitted and uploaded while epochs run)
+        for (grt::EpochSlot &E : s->ep) {
+            if (!E.inflight) continue;
+            const hipError_t e = hipEventQuery(E.done);
+            if (e == hipErrorNotReady) continue;
+            if (e != hipSuccess) {
+                device_failed(s);
                 return;
             }
+            retire(s, E);
+            progressed = true;
         }
-        to_upload.clear();
-        {
-            std::unique_lock<std::mutex> lk(s->mu);
-            // drop cancelled residents; promote uploaded ones; plan the epoch
-            std::vector<uint64_t> keep;
-            for (uint64_t id : s->resident) {
-                ServerJob &j = s->jobs[id];
-                if (j.cancel) {
-                    if (j.ready) (void)hipEventSynchronize(j.ready);
-                    finish_job(s, j, GRT_ERR_CANCELLED);
-                    continue;
-                }
-                if (j.state == kUploading && hipEventQuery(j.ready) == hipSuccess) {
-                    j.state = kRunning;
-                    j.t_start = s->now();
-                }
-                keep.push_back(id);
-            }
-            s->resident.swap(keep);
-            for (uint64_t id : s->resident)
-                if (s->jobs[id].state == kRunning) run.push_back(id);
-            if (run.empty()) {
-                s->cv.notify_all();
-                if (s->resident.empty() && s->pending.empty())
-                    s->cv.wait(lk, [s] { return s->stop || !s->pending.empty(); });
-                else
-                    s->cv.wait_for(lk, std::chrono::microseconds(100));
-                continue;
-            }
-            // processor sharing: equal shares, leftovers to the earliest admitted
-            int64_t left = budget;
-            takes.assign(run.size(), 0);
-            for (int pass = 0; pass < 2 && left > 0; ++pass) {
-                int64_t share = pass == 0 ? std::max<int64_t>(budget / (int64_t)run.size(), min_share) : left;
-                for (size_t i = 0; i < run.size() && left > 0; ++i) {
-                    ServerJob &j = s->jobs[run[i]];
-                    const int64_t rem = j.total - j.next - takes[i];
-                    const int64_t t = std::min(rem, std::min(share, left));
-                    takes[i] += t;
-                    left -= t;
-                }
-            }
-            int nch = 0;
-            int64_t off = 0;
-            for (size_t i = 0; i < run.size(); ++i) {
-                ServerJob &j = s->jobs[run[i]];
-                s->h_jobs[j.slot] = j.args;
-                if (takes[i] <= 0) continue;
-                s->h_chunks[nch].slot = j.slot;
-                s->h_chunks[nch].begin = j.next;
-                s->h_chunks[nch].offset = off;
-                ++nch;
-                off += takes[i];
-                j.next += takes[i];
-                if (j.next >= j.total) finishing.push_back(run[i]);
-            }
-            grt::ServeEpoch e;
-            e.jobs = s->d_jobs;
-            e.chunks = s->d_chunks;
-            e.nchunks = nch;
-            e.total = off;
-            e.counters = s->counters;
-            e.S = s->S;
+        sweep(s);
+        // fill free epoch slots
+        for (int b = 0; b < 2; ++b) {
+            grt::EpochSlot &E = s->ep[b];
+            if (E.inflight) continue;
             hipError_t err = hipSuccess;
-            if (nch > 0) {
-                err = hipMemcpyAsync(s->d_jobs, s->h_jobs, sizeof(grt::RenderArgs) * s->opts.max_jobs,
-                                     hipMemcpyHostToDevice, s->compute);
-                if (err == hipSuccess)
-                    err = hipMemcpyAsync(s->d_chunks, s->h_chunks, sizeof(grt::ServeChunk) * nch,
-                                         hipMemcpyHostToDevice, s->compute);
-                if (err == hipSuccess) err = grt::launch_epoch(e, s->opts.k, s->ctx->num_cu, s->compute);
-            }
-            for (uint64_t id : finishing) {
-                if (err != hipSuccess) break;
-                ServerJob &j = s->jobs[id];
-                hipLaunchKernelGGL(grt::k_serve_reduce, dim3((unsigned)((j.npix + 255) / 256)), dim3(256), 0,
-                                   s->compute, s->d_jobs + j.slot, j.npix);
-                err = hipGetLastError();
-                if (err == hipSuccess)
-                    err = hipMemcpyAsync(j.spec.out_rgb, j.args.out, 12 * (size_t)j.npix, hipMemcpyDeviceToHost,
-                                         s->compute);
-            }
-            s->rays_done += off;
-            ++s->epochs;
+            if (!launch(s, E, s->ep[b ^ 1], budget, err)) break;
             if (err != hipSuccess) {
-                s->error = GRT_ERR_DEVICE;
-                fail_all(s, GRT_ERR_DEVICE);
-                s->cv.notify_all();
+                device_failed(s);
                 return;
             }
+            progressed = true;
         }
-        // the epoch runs while submitters keep queueing
-        const hipError_t err = hipStreamSynchronize(s->compute);
-        std::lock_guard<std::mutex> lk(s->mu);
-        if (err != hipSuccess) {
-            s->error = GRT_ERR_DEVICE;
-            fail_all(s, GRT_ERR_DEVICE);
+        if (progressed) {
             s->cv.notify_all();
-            return;
+            continue;
         }
-        std::vector<uint64_t> keep;
-        for (uint64_t id : s->resident) {
-            bool fin = false;
-            for (uint64_t f : finishing) fin = fin || f == id;
-            if (fin) finish_job(s, s->jobs[id], GRT_OK);
-            else keep.push_back(id);
-        }
-        s->resident.swap(keep);
-        s->cv.notify_all();
+        if (s->resident.empty() && s->pending.empty() && !s->ep[0].inflight && !s->ep[1].inflight)
+            s->cv.wait(lk, [s] { return s->stop || !s->pending.empty(); });
+        else
+            s->cv.wait_for(lk, std::chrono::microseconds(50));
     }
-    std::lock_guard<std::mutex> lk(s->mu);
+    lk.unlock();
+    for (grt::EpochSlot &E : s->ep)
+        if (E.stream) (void)hipStreamSynchronize(E.stream);
     (void)hipStreamSynchronize(s->copy);
+    lk.lock();
+    for (grt::EpochSlot &E : s->ep) retire(s, E);
     fail_all(s, GRT_ERR_CANCELLED);
     s->cv.notify_all();
 }
 
 void destroy_resources(grt_server *s)
 {
-    if (s->compute) (void)hipStreamSynchronize(s->compute);
+    for (grt::EpochSlot &E : s->ep) {
+        if (E.stream) (void)hipStreamSynchronize(E.stream);
+        if (E.d_jobs) (void)hipFree(E.d_jobs);
+        if (E.d_chunks) (void)hipFree(E.d_chunks);
+        if (E.counters) (void)hipFree(E.counters);
+        if (E.h_jobs) (void)hipHostFree(E.h_jobs);
+        if (E.h_chunks) (void)hipHostFree(E.h_chunks);
+        if (E.done) (void)hipEventDestroy(E.done);
+        if (E.stream) (void)hipStreamDestroy(E.stream);
+    }
     if (s->copy) (void)hipStreamSynchronize(s->copy);
     if (s->pool) (void)hipFree(s->pool);
-    if (s->d_jobs) (void)hipFree(s->d_jobs);
-    if (s->d_chunks) (void)hipFree(s->d_chunks);
-    if (s->counters) (void)hipFree(s->counters);
-    if (s->h_jobs) (void)hipHostFree(s->h_jobs);
-    if (s->h_chunks) (void)hipHostFree(s->h_chunks);
-    if (s->compute) (void)hipStreamDestroy(s->compute);
     if (s->copy) (void)hipStreamDestroy(s->copy);
 }
 
@@ -535,21 +629,25 @@ int grt_server_create(grt_ctx *ctx, const grt_scene *scene, const grt_server_opt
     s->ctx = ctx;
     s->opts = *opts;
     s->t0 = grt::Clock::now();
+    s->slack = opts->slack_per_ray < 0.0 ? 4e-8 : opts->slack_per_ray;
     bool ok = hipSetDevice(ctx->device) == hipSuccess;
     ok = ok && hipMalloc((void **)&s->pool, opts->mem_budget) == hipSuccess;
-    ok = ok && hipMalloc((void **)&s->d_jobs, sizeof(grt::RenderArgs) * opts->max_jobs) == hipSuccess;
-    ok = ok && hipMalloc((void **)&s->d_chunks, sizeof(grt::ServeChunk) * opts->max_jobs) == hipSuccess;
-    ok = ok && hipMalloc((void **)&s->counters, grt::kCounterBytes) == hipSuccess;
-    ok = ok && hipHostMalloc((void **)&s->h_jobs, sizeof(grt::RenderArgs) * opts->max_jobs) == hipSuccess;
-    ok = ok && hipHostMalloc((void **)&s->h_chunks, sizeof(grt::ServeChunk) * opts->max_jobs) == hipSuccess;
-    ok = ok && hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) == hipSuccess;
+    for (grt::EpochSlot &E : s->ep) {
+        ok = ok && hipMalloc((void **)&E.d_jobs, sizeof(grt::RenderArgs) * opts->max_jobs) == hipSuccess;
+        ok = ok && hipMalloc((void **)&E.d_chunks, sizeof(grt::ServeChunk) * opts->max_jobs) == hipSuccess;
+        ok = ok && hipMalloc((void **)&E.counters, grt::kCounterBytes) == hipSuccess;
+        ok = ok && hipHostMalloc((void **)&E.h_jobs, sizeof(grt::RenderArgs) * opts->max_jobs) == hipSuccess;
+        ok = ok && hipHostMalloc((void **)&E.h_chunks, sizeof(grt::ServeChunk) * opts->max_jobs) == hipSuccess;
+        ok = ok && hipStreamCreateWithFlags(&E.stream, hipStreamNonBlocking) == hipSuccess;
+        ok = ok && hipEventCreateWithFlags(&E.done, hipEventDisableTiming) == hipSuccess;
+        if (ok) memset(E.h_jobs, 0, sizeof(grt::RenderArgs) * opts->max_jobs);
+    }
     if (!ok) {
         destroy_resources(s);
         delete s;
         return sfail(GRT_ERR_OOM, "device allocation for the server failed");
     }
-    memset(s->h_jobs, 0, sizeof(grt::RenderArgs) * opts->max_jobs);
     s->alloc.init(opts->mem_budget & ~(size_t)255);
     for (int i = opts->max_jobs - 1; i >= 0; --i) s->free_slots.push_back(i);
     try {
@@ -579,6 +677,7 @@ int grt_server_submit(grt_server *s, const grt_job *job, uint64_t *id)
     j.npix = (int64_t)job->H * job->W;
     j.total = j.npix * (job->n_cos + job->n_ggx + job->n_env);
     j.t_submit = s->now();
+    j.deadline = j.t_submit + s->slack * (double)j.total;
     s->pending.push_back(j.id);
     *id = j.id;
     s->cv.notify_all();

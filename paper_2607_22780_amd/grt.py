@@ -72,7 +72,7 @@ class grt_mis_opts(C.Structure):
 
 class grt_server_opts(C.Structure):
     _fields_ = [("mem_budget", C.c_size_t), ("max_jobs", C.c_int), ("epoch_rays", C.c_int64), ("k", C.c_int),
-                ("t_min", C.c_float), ("t_cut", C.c_float)]
+                ("t_min", C.c_float), ("t_cut", C.c_float), ("slack_per_ray", C.c_double)]
 
 
 class grt_job(C.Structure):
@@ -647,10 +647,10 @@ class Server:
     """Owns a grt_server over a built scene; submit Requests, wait, read times."""
 
     def __init__(self, ctx: Context, scene: Scene, mem_budget: int, max_jobs: int = 16, epoch_rays: int = 0, k=8,
-                 t_min=1e-3, t_cut=1e-3):
+                 t_min=1e-3, t_cut=1e-3, slack_per_ray=-1.0):
         self.ctx, self.scene = ctx, scene
         self.opts = grt_server_opts(int(mem_budget), int(max_jobs), int(epoch_rays), int(k), float(t_min),
-                                    float(t_cut))
+                                    float(t_cut), float(slack_per_ray))
         self.handle = grt_server_create(ctx.handle, scene.handle, self.opts)
         self.requests = {}
 
