@@ -4,6 +4,7 @@ generator's published known-answer vectors, every proposal pdf against
 quadrature on the sphere, every sampler against its pdf, and the MIS
 estimator's expectation against quadrature of the rendering integral."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -14,14 +15,15 @@ from paper_2607_22780_amd import workloads as W
 
 def test_philox_known_answers():
     """Philox-4x32-10 known-answer vectors (Salmon et al., SC'11; the
-    Random123 distribution's published test vectors)."""
-    cases = [
-        ((0, 0, 0, 0), (0, 0), (0x6627E8D5, 0xE169C58D, 0xBC57AC4C, 0x9B00DBD8)),
-        ((0xFFFFFFFF,) * 4, (0xFFFFFFFF, 0xFFFFFFFF), (0x408F276D, 0x41C83B0E, 0xA20BC7C6, 0x6D5451FD)),
-        ((0x243F6A88, 0x85A308D3, 0x13198A2E, 0x03707344), (0xA4093822, 0x299F31D0),
-         (0xD16CFE09, 0x94FDCCEB, 0x5001E420, 0x24126EA1)),
-    ]
-    for ctr, key, want in cases:
+    Random123 distribution's published test vectors), read from the golden
+    fixture."""
+    path = os.path.join(os.path.dirname(__file__), "golden", "philox4x32_10_kat.txt")
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        ctr = tuple(int(x, 16) for x in r[0:4])
+        key = tuple(int(x, 16) for x in r[4:6])
+        want = tuple(int(x, 16) for x in r[6:10])
         seed = key[0] | (key[1] << 32)
         got = O.philox(seed, *ctr)
         assert tuple(int(x) for x in got) == want
