@@ -95,7 +95,7 @@ def bytes_per_ray(wc, env_hw=(256, 512)):
     return fwd, bwd
 
 
-def cpu_baseline(s, gb, env, npx: int = 128):
+def cpu_baseline(s, gb, env, npx: int = 384):
     """The oracle (brute force, OpenMP) on a bounded sample of the same step."""
     from oracle import oracle as O
     valid = np.nonzero(gb.valid)[0]
@@ -232,7 +232,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--k", type=int, default=8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pixels", type=int, default=128, help="pixels of the step the oracle times")
+    ap.add_argument("--cpu-pixels", type=int, default=384, help="pixels of the step the oracle times")
     ap.add_argument("--no-serve", action="store_true", help="skip the relighting-server leg")
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-rate", type=float, default=4.0, help="Poisson arrival rate, requests/s")
