@@ -248,9 +248,11 @@ size_t grt_render_saved_bytes(int64_t npix, int spp);
 
 /* Bytes of device workspace grt_render_mis and grt_render_mis_backward need:
  * the launch's ray-fetch counters, a 48-byte record per sample (direction,
- * weight f cos/q, environment radiance, written by a generation kernel) and
- * a 16-byte contribution per sample, summed per pixel in sample order by a
- * reduction kernel (64 bytes per sample plus 256). */
+ * weight f cos/q, environment radiance, written by a generation kernel), a
+ * 16-byte contribution per sample, summed per pixel in sample order by a
+ * reduction kernel, and 16 bytes per sample plus a histogram for sorting the
+ * samples into a coherent traversal order (about 80 bytes per sample).
+ * At most 2^31 - 1 samples (H * W * spp) per call. */
 size_t grt_render_workspace_bytes(int64_t npix, int spp);
 
 /* c_pbr for every pixel (Eq. mis): out_rgb [npix,3] = (1/N_r) sum_j

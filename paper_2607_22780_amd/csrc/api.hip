@@ -388,8 +388,7 @@ size_t grt_render_saved_bytes(int64_t npix, int spp)
 size_t grt_render_workspace_bytes(int64_t npix, int spp)
 {
     if (npix < 0 || spp <= 0) return 0;
-    return grt::kCounterBytes + grt::align256((size_t)npix * (size_t)spp * 16u) +
-           grt::align256((size_t)npix * (size_t)spp * 48u);
+    return grt::carve_render(nullptr, npix * spp).bytes;
 }
 
 static int fill_render_args(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *o,
@@ -401,6 +400,8 @@ static int fill_render_args(const grt_scene *scene, const grt_env *env, const gr
     if (!env->built) return fail(GRT_ERR_NOT_BUILT, "environment used before grt_env_build");
     if (!g || !o) return fail(GRT_ERR_INVALID, "gbuffer/opts is NULL");
     if (g->H < 0 || g->W < 0 || (int64_t)g->H * g->W > 0x7fffffff) return fail(GRT_ERR_INVALID, "bad G-buffer size");
+    if (o && (int64_t)g->H * g->W * ((int64_t)o->n_cos + o->n_ggx + o->n_env) > 0x7fffffff)
+        return fail(GRT_ERR_INVALID, "more than 2^31 - 1 samples");
     if ((int64_t)g->H * g->W > 0 && (!g->x || !g->n || !g->wo || !g->albedo || !g->rough || !g->metal || !g->valid))
         return fail(GRT_ERR_INVALID, "a G-buffer array is NULL");
     if (o->n_cos < 0 || o->n_ggx < 0 || o->n_env < 0 || o->n_cos + o->n_ggx + o->n_env <= 0 ||
@@ -434,12 +435,13 @@ int grt_render_mis(const grt_scene *scene, const grt_env *env, const grt_gbuffer
     const int spp = opts->n_cos + opts->n_ggx + opts->n_env;
     if ((rc = check_ws(workspace, ws_bytes, grt_render_workspace_bytes((int64_t)g->H * g->W, spp), "render")))
         return rc;
-    a.counters = (unsigned long long *)workspace;
-    a.contrib = reinterpret_cast<float4 *>((char *)workspace + grt::kCounterBytes);
-    a.rays = reinterpret_cast<float4 *>((char *)workspace + grt::kCounterBytes +
-                                        grt::align256((size_t)g->H * g->W * spp * 16u));
+    const grt::RenderWS w = grt::carve_render(workspace, (int64_t)g->H * g->W * spp);
+    a.counters = w.counters;
+    a.contrib = w.contrib;
+    a.rays = w.rays;
+    a.order = a.S.n >= 2 ? w.v1 : nullptr;
     if ((rc = set_device(scene->ctx))) return rc;
-    hipError_t e = grt::launch_render(a, opts->k, scene->ctx->num_cu, (hipStream_t)stream);
+    hipError_t e = grt::launch_render(a, w, opts->k, scene->ctx->num_cu, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "render launch");
     return GRT_OK;
 }
@@ -458,12 +460,15 @@ int grt_render_mis_backward(const grt_scene *scene, const grt_env *env, const gr
     a.saved = const_cast<float4 *>(reinterpret_cast<const float4 *>(saved));
     a.g = grad_ptrs(scene, grads);
     const int spp = opts->n_cos + opts->n_ggx + opts->n_env;
-    const size_t ray_bytes = grt::align256((size_t)g->H * g->W * spp * 48u);
-    if ((rc = check_ws(workspace, ws_bytes, grt::kCounterBytes + ray_bytes, "render backward"))) return rc;
-    a.counters = (unsigned long long *)workspace;
-    a.rays = reinterpret_cast<float4 *>((char *)workspace + grt::kCounterBytes);
+    if ((rc = check_ws(workspace, ws_bytes, grt_render_workspace_bytes((int64_t)g->H * g->W, spp),
+                       "render backward")))
+        return rc;
+    const grt::RenderWS w = grt::carve_render(workspace, (int64_t)g->H * g->W * spp);
+    a.counters = w.counters;
+    a.rays = w.rays;
+    a.order = a.S.n >= 2 ? w.v1 : nullptr;
     if ((rc = set_device(scene->ctx))) return rc;
-    hipError_t e = grt::launch_render_backward(a, opts->k, scene->ctx->num_cu, (hipStream_t)stream);
+    hipError_t e = grt::launch_render_backward(a, w, opts->k, scene->ctx->num_cu, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "render backward launch");
     return GRT_OK;
 }

@@ -206,7 +206,10 @@ __device__ __forceinline__ uint64_t make_key(float tau, uint32_t id)
 // change once pushed), and a pop reads the private copy for positions below
 // `spilled`.  Positions [0, spilled) always have valid private copies.
 // ---------------------------------------------------------------------------
-constexpr int kLdsDepth = 24;   // LDS entries per lane and stack
+#ifndef GRT_LDS_DEPTH
+#define GRT_LDS_DEPTH 24
+#endif
+constexpr int kLdsDepth = GRT_LDS_DEPTH;  // LDS entries per lane and stack
 constexpr int kStackCap = 160;  // logical capacity of a stack
 constexpr int kNone = 0x7fffffff;
 
@@ -372,11 +375,21 @@ struct Walker {
             if (F.walk.sp == 0) return true;
             cur = F.walk.pop();
         }
+        int leaf = kNone;
         if (cur < 0) {
-            test_leaf(S, (uint32_t)(-cur - 1));
+            leaf = cur;
             cur = kNone;
-            return false;
+        } else {
+            walk_node(S, leaf);
         }
+        if (leaf != kNone) test_leaf(S, (uint32_t)(-leaf - 1));
+        return false;
+    }
+
+    // Test the two children of node `cur`; sets the next item and at most one
+    // leaf to test.
+    __device__ __forceinline__ void walk_node(const SceneDev &S, int &leaf)
+    {
 #ifdef GRT_STATS
         ++st_nodes;
 #endif
@@ -386,21 +399,34 @@ struct Walker {
         bool hr = slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, o, inv, tlo, tmax, tr);
         const int cl = nd.d.x, cr = nd.d.y;
         hl = keep_child(cl, hl, tl);
-        if (hl && cl < 0) { test_leaf(S, (uint32_t)(-cl - 1)); hl = false; }
         hr = keep_child(cr, hr, tr);
-        if (hr && cr < 0) { test_leaf(S, (uint32_t)(-cr - 1)); hr = false; }
+        // Kept children, nearer first.  A step tests at most one leaf, at the
+        // single site in step() (a wavefront then runs the leaf test once per
+        // step however its lanes' children are mixed); the other child
+        // becomes the item in hand or goes on the walk stack.
+        const bool lfirst = hl && (!hr || tl <= tr);
+        const int near = lfirst ? cl : cr, far = lfirst ? cr : cl;
         if (hl && hr) {
-            const bool lfirst = tl <= tr;
-            F.walk.push(lfirst ? cr : cl);
-            cur = lfirst ? cl : cr;
-        } else if (hl) {
-            cur = cl;
-        } else if (hr) {
-            cur = cr;
+            if (near < 0) {
+                leaf = near;
+                cur = far;
+            } else if (far < 0) {
+                leaf = far;
+                cur = near;
+            } else {
+                F.walk.push(far);
+                cur = near;
+            }
+        } else if (hl || hr) {
+            if (near < 0) {
+                leaf = near;
+                cur = kNone;
+            } else {
+                cur = near;
+            }
         } else {
             cur = kNone;
         }
-        return false;
     }
 
     // Set up the next round from the deferred frontier (or the root).

@@ -98,6 +98,11 @@ inline EnvWS carve_env(void *base, int H, int W)
 
 // Scene build (scene.hip)
 hipError_t launch_scene_build(const grt_surfels &s, float alpha_min, const SceneWS &w, hipStream_t st);
+// Stable LSD radix sort of n (key, value) pairs over the low 8*passes bits of
+// the keys; the result is in (k1, v1) after an odd number of passes, in
+// (k0, v0) after an even number.  hist holds 256 * sort_blocks(n) words.
+void launch_radix_sort(int n, int passes, uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, uint32_t *hist,
+                       hipStream_t st);
 
 // Trace forward/backward (trace.hip)
 struct TraceArgs {
@@ -151,15 +156,52 @@ struct RenderArgs {
     float *dump;
     float4 *contrib;  // per sample f L_i cos / q, reduced per pixel afterwards
     float4 *rays;     // per sample record written by the generation kernel (3 x float4)
+    const uint32_t *order;  // samples in traversal order (null: index order)
     unsigned long long *counters;
     // backward
     const float *grad;
     GradPtrs g;
 };
+// Render workspace: counters | contributions (16 B/sample) | ray records
+// (48 B/sample) | sort keys and values (2 x 2 x 4 B/sample) | sort histogram.
+struct RenderWS {
+    unsigned long long *counters;
+    float4 *contrib;
+    float4 *rays;
+    uint32_t *k0, *v0, *k1, *v1, *hist;
+    size_t bytes;
+};
+
+inline RenderWS carve_render(void *base, int64_t nray)
+{
+    RenderWS w{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? (char *)base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    const size_t n = (size_t)(nray > 0 ? nray : 1);
+    w.counters = (unsigned long long *)take(kCounterBytes);
+    w.contrib = (float4 *)take(16 * n);
+    w.rays = (float4 *)take(48 * n);
+    w.k0 = (uint32_t *)take(4 * n);
+    w.v0 = (uint32_t *)take(4 * n);
+    w.k1 = (uint32_t *)take(4 * n);
+    w.v1 = (uint32_t *)take(4 * n);
+    w.hist = (uint32_t *)take(4 * 256 * (size_t)sort_blocks((int64_t)n));
+    w.bytes = off;
+    return w;
+}
+
 // one ray record per sample of the whole G-buffer (sampling only, no trace)
 hipError_t launch_render_gen(const RenderArgs &a, hipStream_t st);
-hipError_t launch_render(const RenderArgs &a, int k, int num_cu, hipStream_t st);
-hipError_t launch_render_backward(const RenderArgs &a, int k, int num_cu, hipStream_t st);
+// Order the traced samples for coherent traversal: by direction bin, then by
+// the Morton code of the origin in the scene's root box (untraced last).
+// Sets nothing on the host; a.order must point at w.v1 afterwards.
+hipError_t launch_ray_order(const RenderArgs &a, const RenderWS &w, hipStream_t st);
+hipError_t launch_render(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st);
+hipError_t launch_render_backward(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st);
 
 // Zero the per-launch counters; persistent grid size for a kernel.
 hipError_t launch_zero_counters(unsigned long long *c, hipStream_t st);

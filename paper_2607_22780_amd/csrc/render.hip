@@ -88,12 +88,17 @@ struct RenderJob {
     const RenderArgs &a;
     SceneDev S;
     ShadeTrace<K> t;
+    int64_t r;  // sample index of the lane's ray
 
-    __device__ RenderJob(const RenderArgs &a_) : a(a_), S(a_.S) {}
+    __device__ RenderJob(const RenderArgs &a_) : a(a_), S(a_.S), r(0) {}
     __device__ __forceinline__ Walker<K> &walker() { return t.w; }
     __device__ __forceinline__ CompositeVisit &visit() { return t.v; }
-    __device__ __forceinline__ bool begin(int64_t r) { return t.begin(a, S, r); }
-    __device__ __forceinline__ void finish(int64_t r) { t.finish(a, r); }
+    __device__ __forceinline__ bool begin(int64_t g)
+    {
+        r = a.order ? (int64_t)a.order[g] : g;
+        return t.begin(a, S, r);
+    }
+    __device__ __forceinline__ void finish(int64_t) { t.finish(a, r); }
 };
 
 template <int K>
@@ -108,9 +113,10 @@ struct RenderBwdJob {
     __device__ __forceinline__ Walker<K> &walker() { return w; }
     __device__ __forceinline__ GradVisit &visit() { return v; }
 
-    __device__ __forceinline__ bool begin(int64_t r)
+    __device__ __forceinline__ bool begin(int64_t g)
     {
         if (S.n <= 0) return false;
+        const int64_t r = a.order ? (int64_t)a.order[g] : g;
         const float4 r0 = a.rays[3 * r];
         if (r0.w == 0.0f) return false;
         const int64_t p = r / spp;
@@ -177,13 +183,77 @@ hipError_t launch_render_gen(const RenderArgs &a, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_render(const RenderArgs &a, int k, int num_cu, hipStream_t st)
+// ---- coherent traversal order ------------------------------------------------
+// Samples of one pixel leave in all directions, so index order hands a
+// wavefront 64 unrelated rays.  Sorting by (direction bin, origin cell) gives
+// each wavefront rays that walk nearly the same nodes, which the per-XCD L2
+// then serves.  The order changes only which lane traces which ray: every
+// result is written at its sample index.
+
+__device__ __forceinline__ uint32_t spread3(uint32_t x)  // 6 bits -> every third bit
+{
+    x &= 63u;
+    x = (x | (x << 8)) & 0x0000F00Fu;
+    x = (x | (x << 4)) & 0x000C30C3u;
+    x = (x | (x << 2)) & 0x00249249u;
+    return x;
+}
+
+__global__ void __launch_bounds__(256) k_ray_keys(RenderArgs a, int n, uint32_t *__restrict__ keys,
+                                                  uint32_t *__restrict__ vals)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= n) return;
+    const float4 r0 = a.rays[3 * (int64_t)r];
+    uint32_t key = 0xFFFFFFu;  // untraced samples go last
+    if (r0.w != 0.0f) {
+        // scene root box from the two child boxes of node 0
+        const Node nd = a.S.nodes[0];
+        const float lx = fminf(nd.a.x, nd.b.z), ly = fminf(nd.a.y, nd.b.w), lz = fminf(nd.a.z, nd.c.x);
+        const float hx = fmaxf(nd.a.w, nd.c.y), hy = fmaxf(nd.b.x, nd.c.z), hz = fmaxf(nd.b.y, nd.c.w);
+        const int spp = a.nc + a.ng + a.ne;
+        const int64_t p = (int64_t)r / spp;
+        auto cell = [](float v, float lo, float hi) -> uint32_t {
+            const float t = (v - lo) / fmaxf(hi - lo, 1e-20f) * 64.0f;
+            return (uint32_t)fminf(fmaxf(t, 0.0f), 63.0f);
+        };
+        const uint32_t m = (spread3(cell(a.x[3 * p], lx, hx)) << 2) | (spread3(cell(a.x[3 * p + 1], ly, hy)) << 1) |
+                           spread3(cell(a.x[3 * p + 2], lz, hz));
+        // octahedral direction bin, 8 x 8
+        const float s = fabsf(r0.x) + fabsf(r0.y) + fabsf(r0.z);
+        float u = r0.x / s, v = r0.z / s;
+        if (r0.y < 0.0f) {
+            const float uu = (1.0f - fabsf(v)) * (u >= 0.0f ? 1.0f : -1.0f);
+            const float vv = (1.0f - fabsf(u)) * (v >= 0.0f ? 1.0f : -1.0f);
+            u = uu;
+            v = vv;
+        }
+        const uint32_t iu = (uint32_t)fminf(fmaxf((u * 0.5f + 0.5f) * 8.0f, 0.0f), 7.0f);
+        const uint32_t iv = (uint32_t)fminf(fmaxf((v * 0.5f + 0.5f) * 8.0f, 0.0f), 7.0f);
+        key = ((iv * 8u + iu) << 18) | m;
+    }
+    keys[r] = key;
+    vals[r] = (uint32_t)r;
+}
+
+hipError_t launch_ray_order(const RenderArgs &a, const RenderWS &w, hipStream_t st)
+{
+    const int64_t n = (int64_t)a.H * a.W * (a.nc + a.ng + a.ne);
+    if (n <= 0 || a.S.n < 2) return hipSuccess;
+    hipLaunchKernelGGL(k_ray_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, (int)n, w.k0, w.v0);
+    // 24-bit keys: three passes leave the order in (k1, v1)
+    launch_radix_sort((int)n, 3, w.k0, w.v0, w.k1, w.v1, w.hist, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_render(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st)
 {
     const int64_t npix = (int64_t)a.H * a.W;
     if (npix <= 0) return hipSuccess;
     hipError_t e = launch_zero_counters(a.counters, st);
     if (e != hipSuccess) return e;
     if ((e = launch_render_gen(a, st)) != hipSuccess) return e;
+    if (a.order && (e = launch_ray_order(a, w, st)) != hipSuccess) return e;
     switch (k) {
     case 1: e = go_render<1>(a, num_cu, st); break;
     case 2: e = go_render<2>(a, num_cu, st); break;
@@ -199,12 +269,13 @@ hipError_t launch_render(const RenderArgs &a, int k, int num_cu, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_render_backward(const RenderArgs &a, int k, int num_cu, hipStream_t st)
+hipError_t launch_render_backward(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st)
 {
     if ((int64_t)a.H * a.W <= 0) return hipSuccess;
     hipError_t e = launch_zero_counters(a.counters, st);
     if (e != hipSuccess) return e;
     if ((e = launch_render_gen(a, st)) != hipSuccess) return e;
+    if (a.order && (e = launch_ray_order(a, w, st)) != hipSuccess) return e;
     switch (k) {
     case 1: return go_render_bwd<1>(a, num_cu, st);
     case 2: return go_render_bwd<2>(a, num_cu, st);

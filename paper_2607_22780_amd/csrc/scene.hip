@@ -304,6 +304,21 @@ __global__ void k_refit(int n, const float *__restrict__ leaf_box, Node *nodes, 
     }
 }
 
+void launch_radix_sort(int n, int passes, uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, uint32_t *hist,
+                       hipStream_t st)
+{
+    const int sb = (int)sort_blocks(n);
+    uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
+    for (int pass = 0; pass < passes; ++pass) {
+        const int shift = 8 * pass;
+        hipLaunchKernelGGL(k_radix_hist, dim3(sb), dim3(kSortThreads), 0, st, n, ki, shift, hist);
+        hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, st, 256 * sb, hist);
+        hipLaunchKernelGGL(k_radix_scatter, dim3(sb), dim3(kSortThreads), 0, st, n, ki, vi, ko, vo, shift, hist);
+        uint32_t *t0 = ki, *t1 = vi;
+        ki = ko; vi = vo; ko = t0; vo = t1;
+    }
+}
+
 hipError_t launch_scene_build(const grt_surfels &s, float alpha_min, const SceneWS &w, hipStream_t st)
 {
     const int n = (int)s.n;
@@ -313,17 +328,8 @@ hipError_t launch_scene_build(const grt_surfels &s, float alpha_min, const Scene
     hipLaunchKernelGGL(k_boxes, dim3(gb), dim3(tb), 0, st, n, s.means, s.scales, s.quats, s.opacity, alpha_min,
                        w.box_tmp, w.bounds);
     hipLaunchKernelGGL(k_morton, dim3(gb), dim3(tb), 0, st, n, s.means, w.bounds, w.keys0, w.vals0);
-    const int sb = (int)sort_blocks(n);
-    uint32_t *ki = w.keys0, *vi = w.vals0, *ko = w.keys1, *vo = w.vals1;
-    for (int pass = 0; pass < 4; ++pass) {
-        int shift = 8 * pass;
-        hipLaunchKernelGGL(k_radix_hist, dim3(sb), dim3(kSortThreads), 0, st, n, ki, shift, w.hist);
-        hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, st, 256 * sb, w.hist);
-        hipLaunchKernelGGL(k_radix_scatter, dim3(sb), dim3(kSortThreads), 0, st, n, ki, vi, ko, vo, shift, w.hist);
-        uint32_t *t0 = ki, *t1 = vi;
-        ki = ko; vi = vo; ko = t0; vo = t1;
-    }
     // four passes: sorted codes/ids are back in keys0/vals0
+    launch_radix_sort(n, 4, w.keys0, w.vals0, w.keys1, w.vals1, w.hist, st);
     hipLaunchKernelGGL(k_records, dim3(gb), dim3(tb), 0, st, n, w.vals0, s.means, s.scales, s.quats, s.opacity, s.rgb,
                        alpha_min, w.box_tmp, w.rec, w.col, w.leaf_box);
     if (n > 1) {
