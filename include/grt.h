@@ -232,7 +232,14 @@ typedef struct {
  * t_min: self-intersection offset along the secondary ray (1e-3).
  * sample_dump: optional [npix, spp, 10] floats per sample: direction (3),
  *   mixture pdf q, weight f cos/q (3), incident radiance L_i (3); zeros for
- *   samples below the horizon or invalid pixels. */
+ *   samples below the horizon or invalid pixels.
+ * hit_list, hit_cap: optional stored hit lists (device memory of
+ *   grt_render_hit_list_bytes).  Layout: nray = npix * spp uint32 counts (the
+ *   number of hits sample r composited; 0 if not traced), then [nray][hit_cap]
+ *   uint32 record positions in compositing order (positions past hit_cap are
+ *   not stored).  grt_render_mis writes them; grt_render_mis_backward given
+ *   them differentiates from the stored lists instead of re-traversing, and
+ *   re-traverses only samples whose count exceeds hit_cap.  NULL: not used. */
 typedef struct {
     int n_cos, n_ggx, n_env;
     uint64_t seed;
@@ -241,7 +248,13 @@ typedef struct {
     float t_cut;
     int k;
     float *sample_dump;
+    uint32_t *hit_list;
+    int hit_cap;
 } grt_mis_opts;
+
+/* Bytes of a stored hit list for npix * spp samples (4 * nray * (1 + hit_cap)),
+ * 0 on bad arguments. */
+size_t grt_render_hit_list_bytes(int64_t npix, int spp, int hit_cap);
 
 /* Bytes of per-ray state the forward saves for grt_render_mis_backward. */
 size_t grt_render_saved_bytes(int64_t npix, int spp);

@@ -385,6 +385,12 @@ size_t grt_render_saved_bytes(int64_t npix, int spp)
     return (size_t)npix * (size_t)spp * 16u;
 }
 
+size_t grt_render_hit_list_bytes(int64_t npix, int spp, int hit_cap)
+{
+    if (npix < 0 || spp <= 0 || hit_cap < 0) return 0;
+    return (size_t)npix * (size_t)spp * 4u * (1u + (size_t)hit_cap);
+}
+
 size_t grt_render_workspace_bytes(int64_t npix, int spp)
 {
     if (npix < 0 || spp <= 0) return 0;
@@ -418,6 +424,12 @@ static int fill_render_args(const grt_scene *scene, const grt_env *env, const gr
     a.nc = o->n_cos; a.ng = o->n_ggx; a.ne = o->n_env;
     a.seed = o->seed; a.job = o->job;
     a.tmin = o->t_min; a.tcut = o->t_cut;
+    if (o->hit_list) {
+        if (o->hit_cap < 0 || o->hit_cap > 65536) return fail(GRT_ERR_INVALID, "hit_cap must be in 0..65536");
+        if (!aligned(o->hit_list, 4)) return fail(GRT_ERR_INVALID, "hit_list must be 4-byte aligned");
+        a.hits = o->hit_list;
+        a.hcap = o->hit_cap;
+    }
     return GRT_OK;
 }
 
@@ -466,9 +478,10 @@ int grt_render_mis_backward(const grt_scene *scene, const grt_env *env, const gr
     const grt::RenderWS w = grt::carve_render(workspace, (int64_t)g->H * g->W * spp);
     a.counters = w.counters;
     a.rays = w.rays;
-    a.order = a.S.n >= 2 ? w.v1 : nullptr;
+    a.order = a.S.n >= 2 && !a.hits ? w.v1 : nullptr;
     if ((rc = set_device(scene->ctx))) return rc;
-    hipError_t e = grt::launch_render_backward(a, w, opts->k, scene->ctx->num_cu, (hipStream_t)stream);
+    hipError_t e = a.hits ? grt::launch_render_backward_stored(a, w, opts->k, scene->ctx->num_cu, (hipStream_t)stream)
+                          : grt::launch_render_backward(a, w, opts->k, scene->ctx->num_cu, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "render backward launch");
     return GRT_OK;
 }

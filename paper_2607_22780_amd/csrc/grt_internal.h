@@ -157,6 +157,8 @@ struct RenderArgs {
     float4 *contrib;  // per sample f L_i cos / q, reduced per pixel afterwards
     float4 *rays;     // per sample record written by the generation kernel (3 x float4)
     const uint32_t *order;  // samples in traversal order (null: index order)
+    uint32_t *hits;         // stored hit lists: counts [nray], then [nray][hcap] (null: none)
+    int hcap;
     unsigned long long *counters;
     // backward
     const float *grad;
@@ -202,6 +204,8 @@ hipError_t launch_render_gen(const RenderArgs &a, hipStream_t st);
 hipError_t launch_ray_order(const RenderArgs &a, const RenderWS &w, hipStream_t st);
 hipError_t launch_render(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st);
 hipError_t launch_render_backward(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st);
+// Backward from stored hit lists (a.hits); re-traverses overflowing samples.
+hipError_t launch_render_backward_stored(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st);
 
 // Zero the per-launch counters; persistent grid size for a kernel.
 hipError_t launch_zero_counters(unsigned long long *c, hipStream_t st);

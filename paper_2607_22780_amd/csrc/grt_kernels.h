@@ -21,6 +21,8 @@ struct CompositeVisit {
     int32_t *did = nullptr;
     float *dtau = nullptr;
     int cap = 0;
+    uint32_t *hl = nullptr;  // stored hit list of the ray (record positions)
+    int hcap = 0;
 
     __device__ CompositeVisit() {}
     __device__ CompositeVisit(const SceneDev &S, float t_cut) : rec(S.rec), col(S.col), tcut(t_cut) {}
@@ -48,6 +50,7 @@ struct CompositeVisit {
         const float w = T * a;
         C.x += w * c.x; C.y += w * c.y; C.z += w * c.z;
         if (did && cnt < cap) { did[cnt] = (int32_t)id; dtau[cnt] = tau; }
+        if (hl && cnt < hcap) hl[cnt] = p;
         ++cnt;
         T = T * (1.0f - a);
         Td = trans_step(Td, hit_alpha(r1.w, crho2));

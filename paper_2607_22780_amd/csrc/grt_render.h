@@ -318,10 +318,16 @@ struct ShadeTrace {
         const float4 r0 = a.rays[3 * r];
         if (r0.w == 0.0f) {
             a.contrib[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (a.hits) a.hits[r] = 0u;
             return false;
         }
         const int spp = a.nc + a.ng + a.ne;
         const int64_t p = r / spp;
+        if (a.hits) {
+            const int64_t nray = (int64_t)a.H * a.W * spp;
+            v.hl = a.hits + nray + r * a.hcap;
+            v.hcap = a.hcap;
+        }
         const float3 x = make_float3(a.x[3 * p], a.x[3 * p + 1], a.x[3 * p + 2]);
         const float3 d = make_float3(r0.x, r0.y, r0.z);
         v.rec = S.rec;
@@ -342,6 +348,7 @@ struct ShadeTrace {
         const float3 Li = make_float3(v.C.x + v.T * r1.w, v.C.y + v.T * r2.x, v.C.z + v.T * r2.y);
         a.contrib[r] = make_float4(r1.x * Li.x, r1.y * Li.y, r1.z * Li.z, 0.0f);
         if (a.saved) a.saved[r] = make_float4(v.C.x, v.C.y, v.C.z, v.T);
+        if (a.hits) a.hits[r] = (uint32_t)v.cnt;
         if (a.dump) {
             float *dp = a.dump + r * 10;
             dp[7] = Li.x; dp[8] = Li.y; dp[9] = Li.z;

@@ -67,7 +67,7 @@ class grt_gbuffer(C.Structure):
 class grt_mis_opts(C.Structure):
     _fields_ = [("n_cos", C.c_int), ("n_ggx", C.c_int), ("n_env", C.c_int), ("seed", C.c_uint64),
                 ("job", C.c_uint32), ("t_min", C.c_float), ("t_cut", C.c_float), ("k", C.c_int),
-                ("sample_dump", VP)]
+                ("sample_dump", VP), ("hit_list", VP), ("hit_cap", C.c_int)]
 
 
 class grt_server_opts(C.Structure):
@@ -110,6 +110,7 @@ SIGNATURES = {
     "grt_render_mis": (C.c_int, [VP, VP, P(grt_gbuffer), P(grt_mis_opts), VP, VP, VP, C.c_size_t, VP]),
     "grt_render_mis_backward": (C.c_int, [VP, VP, P(grt_gbuffer), P(grt_mis_opts), VP, VP, P(grt_surfel_grads),
                                           VP, C.c_size_t, VP]),
+    "grt_render_hit_list_bytes": (C.c_size_t, [C.c_int64, C.c_int, C.c_int]),
     "grt_server_job_bytes": (C.c_size_t, [P(grt_job)]),
     "grt_server_create": (C.c_int, [VP, VP, P(grt_server_opts), P(VP)]),
     "grt_server_submit": (C.c_int, [VP, P(grt_job), P(C.c_uint64)]),
@@ -480,7 +481,7 @@ class GBuffer:
                            _ptr(self.rough), _ptr(self.metal), _ptr(self.valid))
 
 
-def make_mis_opts(split=(16, 8, 8), seed=0, job=0, t_min=1e-3, t_cut=1e-3, k=16, dump=None):
+def make_mis_opts(split=(16, 8, 8), seed=0, job=0, t_min=1e-3, t_cut=1e-3, k=16, dump=None, hits=None, hit_cap=0):
     o = grt_mis_opts()
     o.n_cos, o.n_ggx, o.n_env = split
     o.seed = seed
@@ -489,11 +490,23 @@ def make_mis_opts(split=(16, 8, 8), seed=0, job=0, t_min=1e-3, t_cut=1e-3, k=16,
     o.t_cut = t_cut
     o.k = k
     o.sample_dump = _ptr(dump)
+    o.hit_list = _ptr(hits)
+    o.hit_cap = int(hit_cap) if hits is not None else 0
     return o
 
 
+def grt_render_hit_list_bytes(npix: int, spp: int, hit_cap: int) -> int:
+    return int(load_library().grt_render_hit_list_bytes(npix, spp, hit_cap))
+
+
+def make_hit_list(npix: int, spp: int, hit_cap: int, device):
+    """Device buffer for stored hit lists: counts [nray] then [nray, hit_cap]."""
+    n = grt_render_hit_list_bytes(npix, spp, hit_cap) // 4
+    return torch.empty(n, dtype=torch.int32, device=device)
+
+
 def render_mis(scene: Scene, env: Env, gb: GBuffer, split=(16, 8, 8), seed=0, job=0, t_min=1e-3, t_cut=1e-3, k=16,
-               save=False, dump=False, workspace=None, stream=None):
+               save=False, dump=False, workspace=None, stream=None, hits=None, hit_cap=0):
     """c_pbr [npix,3]; with ``save`` also the per-ray state for the backward,
     with ``dump`` the per-sample record [npix, spp, 10]."""
     dev = gb.x.device
@@ -501,7 +514,7 @@ def render_mis(scene: Scene, env: Env, gb: GBuffer, split=(16, 8, 8), seed=0, jo
     out = torch.empty(gb.npix, 3, device=dev)
     saved = torch.empty(gb.npix * spp, 4, device=dev) if save else None
     dmp = torch.zeros(gb.npix, spp, 10, device=dev) if dump else None
-    opts = make_mis_opts(split, seed, job, t_min, t_cut, k, dmp)
+    opts = make_mis_opts(split, seed, job, t_min, t_cut, k, dmp, hits, hit_cap)
     need = grt_render_workspace_bytes(gb.npix, spp)
     if workspace is None or workspace.numel() < need:
         workspace = _workspace(need, dev)
@@ -515,10 +528,12 @@ def render_mis(scene: Scene, env: Env, gb: GBuffer, split=(16, 8, 8), seed=0, jo
 
 
 def render_mis_backward(scene: Scene, env: Env, gb: GBuffer, grad_rgb, saved, split=(16, 8, 8), seed=0, job=0,
-                        t_min=1e-3, t_cut=1e-3, k=16, grads=None, stream=None):
+                        t_min=1e-3, t_cut=1e-3, k=16, grads=None, stream=None, hits=None, hit_cap=0):
+    """Gradients into `grads` (+=).  With `hits` (the forward's stored hit
+    lists) the backward works from the lists instead of re-traversing."""
     if grads is None:
         grads = zero_grads(scene.n, gb.x.device)
-    opts = make_mis_opts(split, seed, job, t_min, t_cut, k)
+    opts = make_mis_opts(split, seed, job, t_min, t_cut, k, None, hits, hit_cap)
     ws = _workspace(grt_render_workspace_bytes(gb.npix, sum(split)), gb.x.device)
     grt_render_mis_backward(scene.handle, env.handle, gb.struct(), opts, grad_rgb.contiguous(), saved,
                             _grads_struct(grads), ws, stream)
@@ -556,19 +571,24 @@ class RenderMISFn(torch.autograd.Function):
     """c_pbr image as a function of the surfel parameters (Eq. mis)."""
 
     @staticmethod
-    def forward(ctx_, means, scales, quats, opacity, rgb, gctx, env, gb, split, seed, k, alpha_min):
+    def forward(ctx_, means, scales, quats, opacity, rgb, gctx, env, gb, split, seed, k, alpha_min, hit_cap=0):
+        """hit_cap > 0: store up to hit_cap hits per sample in the forward and
+        differentiate from the stored lists; 0: re-traverse in the backward."""
         scene = Scene(gctx, means.detach().contiguous(), scales.detach().contiguous(), quats.detach().contiguous(),
                       opacity.detach().contiguous(), rgb.detach().contiguous(), alpha_min)
-        res = render_mis(scene, env, gb, split=split, seed=seed, k=k, save=True)
-        ctx_.scene, ctx_.env, ctx_.gb, ctx_.cfg = scene, env, gb, (split, seed, k)
-        ctx_.saved_state = res["saved"]
+        hits = make_hit_list(gb.npix, sum(split), hit_cap, gb.x.device) if hit_cap > 0 else None
+        res = render_mis(scene, env, gb, split=split, seed=seed, k=k, save=True, hits=hits, hit_cap=hit_cap)
+        ctx_.scene, ctx_.env, ctx_.gb, ctx_.cfg = scene, env, gb, (split, seed, k, hit_cap)
+        ctx_.saved_state, ctx_.hits = res["saved"], hits
         return res["rgb"]
 
     @staticmethod
     def backward(ctx_, g_rgb):
-        split, seed, k = ctx_.cfg
-        g = render_mis_backward(ctx_.scene, ctx_.env, ctx_.gb, g_rgb, ctx_.saved_state, split=split, seed=seed, k=k)
-        return g["means"], g["scales"], g["quats"], g["opacity"], g["rgb"], None, None, None, None, None, None, None
+        split, seed, k, hit_cap = ctx_.cfg
+        g = render_mis_backward(ctx_.scene, ctx_.env, ctx_.gb, g_rgb, ctx_.saved_state, split=split, seed=seed, k=k,
+                                hits=ctx_.hits, hit_cap=hit_cap)
+        return (g["means"], g["scales"], g["quats"], g["opacity"], g["rgb"], None, None, None, None, None, None, None,
+                None)
 
 
 # --------------------------------------------------------------------------

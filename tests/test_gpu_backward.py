@@ -117,3 +117,96 @@ def test_render_autograd_matches_direct(grt_ctx):
     gg = grt.render_mis_backward(scene, E, G, w, fwd["saved"], split=(4, 2, 2), seed=11)
     for p, name in zip(params, ("means", "scales", "quats", "opacity", "rgb")):
         np.testing.assert_allclose(p.grad.cpu().numpy(), gg[name].cpu().numpy(), rtol=1e-4, atol=1e-6)
+
+
+def _small_render_case(grt, ctx):
+    from gpu_util import t, scene_tensors
+    s = W.scene1(n=20000, seed=0, s_lo=0.01, s_hi=0.06)
+    gb = W.gbuffer1(40, 37, seed=0)
+    env = W.envmap(64, 128, seed=0)
+    split = (16, 8, 8)
+    ref_f = O.render_mis(s, gb, env, split, 3, dump=True)
+    m = ref_f["margins"]
+    edge = ((m[..., 3] < 1e-5) | (m[..., 4] < 1e-9)).any(axis=1)
+    g = np.random.default_rng(4)
+    grad = (g.normal(0, 1, (gb.npix, 3)) * (~edge)[:, None]).astype(np.float32)
+    scene = grt.Scene(ctx, *scene_tensors(s))
+    E = grt.Env(ctx, t(env))
+    G = grt.GBuffer.from_numpy(gb, torch.device("cuda", 0))
+    return s, gb, env, split, grad, scene, E, G
+
+
+@pytest.mark.parametrize("cap", [2, 256])
+def test_render_backward_stored_lists(grt_ctx, cap):
+    """Stored-hit-list backward (the forward records each sample's hits):
+    equal to the oracle's gradient as the re-traversal backward is.  With a
+    capacity of 2 most samples overflow and are re-traversed; with 256 none
+    do.  The stored counts are the number of hits each sample composited."""
+    grt, ctx = grt_ctx
+    from gpu_util import t
+    s, gb, env, split, grad, scene, E, G = _small_render_case(grt, ctx)
+    ref = O.render_mis_backward(s, gb, env, split, 3, grad)
+    spp = sum(split)
+    hits = grt.make_hit_list(gb.npix, spp, cap, torch.device("cuda", 0))
+    fwd = grt.render_mis(scene, E, G, split=split, seed=3, save=True, dump=True, hits=hits, hit_cap=cap)
+    plain = grt.render_mis(scene, E, G, split=split, seed=3)
+    np.testing.assert_array_equal(fwd["rgb"].cpu().numpy(), plain["rgb"].cpu().numpy())
+    gg = grt.render_mis_backward(scene, E, G, t(grad), fwd["saved"], split=split, seed=3, hits=hits, hit_cap=cap)
+    torch.cuda.synchronize()
+    check_grads({k: v.cpu().numpy() for k, v in gg.items()}, ref)
+    counts = hits[: gb.npix * spp].cpu().numpy().astype(np.int64)
+    traced = fwd["dump"].reshape(-1, 10)[:, 3].cpu().numpy() > 0  # q > 0: the sample was traced
+    T = fwd["saved"][:, 3].cpu().numpy()
+    assert np.all(counts[~traced] == 0)
+    assert np.all((counts[traced] > 0) == (T[traced] < 1.0))  # a hit iff transmittance dropped
+    if cap == 2:
+        assert np.mean(counts > cap) > 0.2  # the overflow path is exercised
+    else:
+        assert counts.max() <= cap
+
+
+def test_stored_lists_hold_the_composited_hits(grt_ctx):
+    """The stored list of a sample names the surfels the plain trace
+    composites along the same ray, in the same order."""
+    grt, ctx = grt_ctx
+    from gpu_util import t
+    s, gb, env, split, grad, scene, E, G = _small_render_case(grt, ctx)
+    spp = sum(split)
+    cap = 128
+    hits = grt.make_hit_list(gb.npix, spp, cap, torch.device("cuda", 0))
+    res = grt.render_mis(scene, E, G, split=split, seed=3, save=True, dump=True, hits=hits, hit_cap=cap)
+    dump = res["dump"].reshape(-1, 10).cpu().numpy()
+    counts = hits[: gb.npix * spp].cpu().numpy()
+    lists = hits[gb.npix * spp:].reshape(-1, cap).cpu().numpy()
+    rec_ids = scene.arrays()["records"][:, 11].contiguous().view(torch.int32).cpu().numpy()
+    g = np.random.default_rng(9)
+    traced = np.nonzero(dump[:, 3] > 0)[0]
+    pick = np.sort(g.choice(traced, 256, replace=False))
+    pix = pick // spp
+    o = t(np.ascontiguousarray(gb.x[pix])); d = t(np.ascontiguousarray(dump[pick, 0:3]))
+    tr = grt.trace(scene, o, d, t_min=1e-3, dump_cap=cap)
+    ids = tr["ids"].cpu().numpy(); nh = tr["nhit"].cpu().numpy()
+    for k, r in enumerate(pick):
+        assert counts[r] == nh[k]
+        n = min(int(nh[k]), cap)
+        np.testing.assert_array_equal(rec_ids[lists[r, :n]], ids[k, :n])
+
+
+def test_render_autograd_stored_matches_retrace(grt_ctx):
+    """RenderMISFn with stored hit lists gives the re-traversal gradients."""
+    grt, ctx = grt_ctx
+    from gpu_util import t
+    s = W.scene1(n=8000, seed=5, s_lo=0.01, s_hi=0.05)
+    gb = W.gbuffer1(16, 16, seed=5)
+    env = W.envmap(32, 64, seed=5)
+    E = grt.Env(ctx, t(env))
+    G = grt.GBuffer.from_numpy(gb, torch.device("cuda", 0))
+    grads = []
+    for cap in (0, 64):
+        params = [t(a).requires_grad_(True) for a in s.arrays()]
+        img = grt.RenderMISFn.apply(*params, ctx, E, G, (4, 2, 2), 11, 16, 1.0 / 255.0, cap)
+        w = torch.from_numpy(np.random.default_rng(2).normal(0, 1, tuple(img.shape)).astype(np.float32)).cuda()
+        (img * w).sum().backward()
+        grads.append([p.grad.cpu().numpy() for p in params])
+    for a, b in zip(*grads):
+        np.testing.assert_allclose(a, b, rtol=1e-4, atol=1e-6)
