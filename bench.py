@@ -234,6 +234,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=384, help="pixels of the step the oracle times")
     ap.add_argument("--no-serve", action="store_true", help="skip the relighting-server leg")
+    ap.add_argument("--no-stored", action="store_true", help="skip the stored-hit-list backward leg")
+    ap.add_argument("--hit-cap", type=int, default=64, help="hits stored per sample in the stored-list leg")
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-rate", type=float, default=4.0, help="Poisson arrival rate, requests/s")
     ap.add_argument("--serve-slack", type=float, default=-1.0, help="server deadline seconds per ray (-1: default)")
@@ -306,6 +308,30 @@ def main():
         build_ms.append(eb0.elapsed_time(eb1)); fwd_ms.append(ef0.elapsed_time(ef1)); bwd_ms.append(eg0.elapsed_time(eg1))
     build_ms, fwd_ms, bwd_ms = (float(np.median(x)) for x in (build_ms, fwd_ms, bwd_ms))
 
+    stored = None
+    if not args.no_stored:
+        # the same step differentiated from stored hit lists instead of re-traversal
+        hits = grt.make_hit_list(gb.npix, spp, args.hit_cap, dev)
+        sf, sb = [], []
+        for _ in range(max(args.steps // 2, 2)):
+            ef0.record(st)
+            res = grt.render_mis(scene, E, G, split=SPLIT, seed=SEED, k=args.k, save=True, hits=hits,
+                                 hit_cap=args.hit_cap)
+            ef1.record(st)
+            eg0.record(st)
+            grt.render_mis_backward(scene, E, G, upstream, res["saved"], split=SPLIT, seed=SEED, k=args.k, hits=hits,
+                                    hit_cap=args.hit_cap)
+            eg1.record(st)
+            torch.cuda.synchronize()
+            sf.append(ef0.elapsed_time(ef1)); sb.append(eg0.elapsed_time(eg1))
+        cnt = hits[:gb.npix * spp].cpu().numpy()
+        stored = {"hit_cap": args.hit_cap, "list_gb": round(hits.numel() * 4 / 1e9, 3),
+                  "overflow_frac": round(float((cnt > args.hit_cap).mean()), 5),
+                  "mean_hits_per_sample": round(float(cnt.mean()), 3),
+                  "render_fwd_ms": round(float(np.median(sf)), 3), "render_bwd_ms": round(float(np.median(sb)), 3),
+                  "retrace_bwd_ms": round(bwd_ms, 3)}
+        del hits, res
+
     roofline = None
     if os.path.exists(WORKCOUNT):
         wc = json.load(open(WORKCOUNT))
@@ -362,6 +388,7 @@ def main():
         "fwd_mrays_s": round(rays / (fwd_ms * 1e-3) / 1e6, 2),
         "phase_ms": {"build": round(build_ms, 3), "render_fwd": round(fwd_ms, 3), "render_bwd": round(bwd_ms, 3)},
         "roofline": roofline,
+        "stored_hit_lists": stored,
         "relight_server": serve,
         "cpu_baseline": cpu,
     }

@@ -307,7 +307,9 @@ int grt_render_mis_backward(const grt_scene *scene, const grt_env *env, const gr
  *
  * mem_budget:    device bytes the server allocates for requests (its pool).
  * max_jobs:      requests resident at once (1..256).
- * epoch_rays:    rays per epoch across all requests (0 = 2,097,152).
+ * epoch_rays:    at most this many rays per epoch (0 = 134,217,728); an epoch
+ *                takes the rest of the earliest-deadline request, topped up
+ *                with the next requests while under 1,048,576 rays.
  * k:             k-buffer size, 4, 8 or 16.  t_min, t_cut as in grt_mis_opts.
  * slack_per_ray: seconds of deadline per ray (0 = arrival order only;
  *                negative = 4e-8, about twice a request's time alone). */

@@ -79,6 +79,7 @@ struct ServeJob {
         const ServeChunk ch = e.chunks[find_chunk(e, g)];
         a = &e.jobs[ch.slot];
         r = ch.begin + (g - ch.offset);
+        if (a->order) r = (int64_t)a->order[r];
         return t.begin(*a, S, r);
     }
 
@@ -101,11 +102,17 @@ struct ServeOneJob {
     ShadeTrace<K> t;
     int64_t r0;
 
-    __device__ ServeOneJob(const RenderArgs &a_, int64_t r0_) : a(a_), S(a_.S), r0(r0_) {}
+    int64_t r;
+
+    __device__ ServeOneJob(const RenderArgs &a_, int64_t r0_) : a(a_), S(a_.S), r0(r0_), r(0) {}
     __device__ __forceinline__ Walker<K> &walker() { return t.w; }
     __device__ __forceinline__ CompositeVisit &visit() { return t.v; }
-    __device__ __forceinline__ bool begin(int64_t g) { return t.begin(a, S, r0 + g); }
-    __device__ __forceinline__ void finish(int64_t g) { t.finish(a, r0 + g); }
+    __device__ __forceinline__ bool begin(int64_t g)
+    {
+        r = a.order ? (int64_t)a.order[r0 + g] : r0 + g;
+        return t.begin(a, S, r);
+    }
+    __device__ __forceinline__ void finish(int64_t) { t.finish(a, r); }
 };
 
 template <int K>
@@ -175,10 +182,12 @@ struct ServerJob {
     int state = kQueued;
     int status = GRT_OK;  // error code once failed or cancelled
     bool cancel = false;
+    bool pooled = false;  // holds [off, off + bytes) of the pool
     size_t bytes = 0, off = 0;
     int slot = -1;
     RenderArgs args{};
     EnvWS env{};
+    RenderWS sort{};  // sort keys/values and histogram (counters, rays, contrib unused)
     int64_t npix = 0, total = 0, next = 0;
     int inflight = 0;      // epochs in flight that hold rays of this job
     double deadline = 0;   // scheduling key
@@ -246,6 +255,13 @@ static size_t carve_job(ServerJob &j, char *base)
     a.rays = (float4 *)take(48 * nray);
     a.contrib = (float4 *)take(16 * nray);
     a.out = (float *)take(12 * npix);
+    // coherent traversal order of the request's samples, and its sort scratch
+    j.sort.k0 = (uint32_t *)take(4 * nray);
+    j.sort.v0 = (uint32_t *)take(4 * nray);
+    j.sort.k1 = (uint32_t *)take(4 * nray);
+    j.sort.v1 = (uint32_t *)take(4 * nray);
+    j.sort.hist = (uint32_t *)take(4 * 256 * (size_t)sort_blocks((int64_t)nray));
+    a.order = base ? j.sort.v1 : nullptr;
     return off;
 }
 
@@ -258,6 +274,8 @@ struct EpochSlot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     bool inflight = false;
+    int64_t rays = 0;       // rays of the epoch in flight
+    double t_launch = 0.0;  // when it was launched (server clock)
     std::vector<uint64_t> members, finishing;
 };
 
@@ -287,6 +305,7 @@ struct grt_server {
     std::vector<int> free_slots;
     hipStream_t copy = nullptr;
     grt::EpochSlot ep[2];
+    double rate = 5e7;  // traced rays per second, running estimate (launch gate)
     uint64_t next_id = 1;
     grt::Clock::time_point t0;
     // statistics
@@ -336,8 +355,10 @@ hipError_t upload(grt_server *s, ServerJob &j)
     for (const Cp &c : cps)
         if ((e = hipMemcpyAsync((void *)c.dst, c.src, c.n, hipMemcpyHostToDevice, s->copy)) != hipSuccess) return e;
     if ((e = grt::launch_env_build(a.E.rgb, q.env_H, q.env_W, j.env, s->copy)) != hipSuccess) return e;
-    // every sample's ray record up front, so epochs only trace
+    // every sample's ray record up front, so epochs only trace, and the
+    // samples' coherent traversal order
     if ((e = grt::launch_render_gen(a, s->copy)) != hipSuccess) return e;
+    if ((e = grt::launch_ray_order(a, j.sort, s->copy)) != hipSuccess) return e;
     if ((e = hipEventCreateWithFlags(&j.ready, hipEventDisableTiming)) != hipSuccess) return e;
     return hipEventRecord(j.ready, s->copy);
 }
@@ -346,6 +367,7 @@ void setup_args(grt_server *s, ServerJob &j)
 {
     grt::RenderArgs &a = j.args;
     a.S = s->S;
+    if (a.S.n < 2) a.order = nullptr;  // no hierarchy to order by: index order
     a.E.H = j.spec.env_H;
     a.E.W = j.spec.env_W;
     a.E.marg = j.env.marg;
@@ -368,8 +390,8 @@ void finish_job(grt_server *s, ServerJob &j, int status)
 {
     if (j.state == kDone) return;
     if (j.ready) { (void)hipEventDestroy(j.ready); j.ready = nullptr; }
-    if (j.bytes) s->alloc.release(j.off, j.bytes);
-    j.bytes = 0;
+    if (j.pooled) s->alloc.release(j.off, j.bytes);
+    j.pooled = false;
     if (j.slot >= 0) s->free_slots.push_back(j.slot);
     j.slot = -1;
     j.state = kDone;
@@ -402,6 +424,7 @@ void admit(grt_server *s, std::vector<uint64_t> &to_upload)
         size_t off;
         if (!s->alloc.alloc(j.bytes, off)) break;
         j.off = off;
+        j.pooled = true;
         j.slot = s->free_slots.back();
         s->free_slots.pop_back();
         grt::carve_job(j, s->pool + off);
@@ -417,6 +440,10 @@ void admit(grt_server *s, std::vector<uint64_t> &to_upload)
 // cancelled jobs with no epoch left in flight are dropped.
 void retire(grt_server *s, grt::EpochSlot &E)
 {
+    if (E.inflight && E.rays >= (1 << 20)) {
+        const double dt = s->now() - E.t_launch;
+        if (dt > 1e-4) s->rate = 0.7 * s->rate + 0.3 * (double)E.rays / dt;
+    }
     for (uint64_t id : E.members) --s->jobs[id].inflight;
     for (uint64_t id : E.finishing) {
         ServerJob &j = s->jobs[id];
@@ -450,6 +477,11 @@ void sweep(grt_server *s)
 
 // An epoch below this many rays also takes rays of the next requests.
 constexpr int64_t kFillRays = 1 << 20;
+// Launch gate: the estimated time left of the epoch in flight below which the
+// next epoch starts, and the share of its remaining rays below which a next
+// epoch counts as small and starts at once.
+constexpr double kTailSeconds = 0.010;
+constexpr double kSmallShare = 0.05;
 
 // Plan an epoch into slot E and launch it; false if no ray is left to trace.
 bool launch(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other, int64_t budget, hipError_t &err)
@@ -463,6 +495,21 @@ bool launch(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other, int64_t bud
     // earliest deadline first; the budget goes down the list
     std::stable_sort(run.begin(), run.end(),
                      [](const ServerJob *a, const ServerJob *b) { return a->deadline < b->deadline; });
+    // Launch gate: while the other epoch is in flight, the next one starts
+    // only in its tail (so its waves fill the CUs the tail leaves idle), or
+    // at once when it is small next to what the other epoch has left (so a
+    // small request passes a large one without slowing it noticeably).
+    if (other.inflight) {
+        int64_t want = 0;
+        for (ServerJob *j : run) {
+            if (want >= budget || (want > 0 && want >= kFillRays)) break;
+            want += std::min(j->total - j->next, budget - want);
+        }
+        const double left = (double)other.rays - s->rate * (s->now() - other.t_launch);
+        const bool tail = left <= s->rate * kTailSeconds;
+        const bool small = (double)want <= kSmallShare * left;
+        if (!tail && !small) return false;
+    }
     int nch = 0;
     int64_t off = 0;
     for (ServerJob *j : run) {
@@ -509,6 +556,8 @@ bool launch(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other, int64_t bud
     }
     if (err == hipSuccess) err = hipEventRecord(E.done, E.stream);
     E.inflight = true;
+    E.rays = off;
+    E.t_launch = s->now();
     s->rays_done += off;
     ++s->epochs;
     return true;
@@ -517,7 +566,7 @@ bool launch(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other, int64_t bud
 void scheduler(grt_server *s)
 {
     (void)hipSetDevice(s->ctx->device);
-    const int64_t budget = s->opts.epoch_rays > 0 ? s->opts.epoch_rays : (int64_t)1 << 26;
+    const int64_t budget = s->opts.epoch_rays > 0 ? s->opts.epoch_rays : (int64_t)1 << 27;
     std::vector<uint64_t> to_upload;
     std::unique_lock<std::mutex> lk(s->mu);
     while (!s->stop) {
