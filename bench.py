@@ -31,14 +31,18 @@ TRAFFIC = os.path.join(ROOT, "profiles", "traffic_room1m_1024px_32spp.json")
 CSRC = os.path.join(ROOT, "paper_2607_22780_amd", "csrc")
 
 
+# the sources the render kernels are built from
+KERNEL_SOURCES = ("render.hip", "grt_device.h", "grt_kernels.h", "grt_render.h", "grt_internal.h")
+
+
 def source_hash():
-    """Hash of the HIP sources: traffic counters are only valid for the kernels they were taken on."""
+    """Hash of the render kernels' sources: traffic counters are only valid
+    for the kernels they were taken on."""
     import hashlib
     h = hashlib.sha256()
-    for name in sorted(os.listdir(CSRC)):
-        if name.endswith((".hip", ".h")):
-            h.update(name.encode())
-            h.update(open(os.path.join(CSRC, name), "rb").read())
+    for name in KERNEL_SOURCES:
+        h.update(name.encode())
+        h.update(open(os.path.join(CSRC, name), "rb").read())
     return h.hexdigest()[:16]
 SPLIT = (16, 8, 8)
 SEED = 7

@@ -27,6 +27,13 @@ constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;
 
 inline int64_t sort_blocks(int64_t n) { return (n + kSortTile - 1) / kSortTile; }
+// Words of sort histogram for n keys: 256 per sort block, then the chunk
+// sums of the multi-block scan (one per 4096 histogram words).
+inline size_t sort_hist_words(int64_t n)
+{
+    const size_t total = 256 * (size_t)(sort_blocks(n) > 0 ? sort_blocks(n) : 1);
+    return total + (total + 4095) / 4096;
+}
 
 // Carving of a scene workspace; the same function sizes and places.
 struct SceneWS {
@@ -67,7 +74,7 @@ inline SceneWS carve_scene(void *base, int64_t n)
     w.parent_int = (int32_t *)take(4 * ni);
     w.parent_leaf = (int32_t *)take(4 * nn);
     w.flags = (uint32_t *)take(4 * ni);
-    w.hist = (uint32_t *)take(4 * 256 * (size_t)(sort_blocks(n) > 0 ? sort_blocks(n) : 1));
+    w.hist = (uint32_t *)take(4 * sort_hist_words(n));
     w.bounds = (int32_t *)take(4 * 8);
     w.bytes = off;
     return w;
@@ -191,7 +198,7 @@ inline RenderWS carve_render(void *base, int64_t nray)
     w.v0 = (uint32_t *)take(4 * n);
     w.k1 = (uint32_t *)take(4 * n);
     w.v1 = (uint32_t *)take(4 * n);
-    w.hist = (uint32_t *)take(4 * 256 * (size_t)sort_blocks((int64_t)n));
+    w.hist = (uint32_t *)take(4 * sort_hist_words((int64_t)n));
     w.bytes = off;
     return w;
 }

@@ -149,6 +149,56 @@ __global__ void __launch_bounds__(1024) k_radix_scan(int total, uint32_t *__rest
     }
 }
 
+// The same exclusive prefix sum for long histograms (the sort of a frame's
+// samples): per-chunk sums, a scan of the sums, then each chunk rescanned
+// from its offset.  kScanChunk entries per block, 16 per thread.
+constexpr int kScanChunk = 4096;
+
+__global__ void __launch_bounds__(256) k_scan_sums(int total, const uint32_t *__restrict__ hist,
+                                                   uint32_t *__restrict__ sums)
+{
+    __shared__ uint32_t part[256];
+    const int base = blockIdx.x * kScanChunk + threadIdx.x * 16;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        if (base + i < total) acc += hist[base + i];
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+        if (threadIdx.x < off) part[threadIdx.x] += part[threadIdx.x + off];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) sums[blockIdx.x] = part[0];
+}
+
+__global__ void __launch_bounds__(256) k_scan_apply(int total, uint32_t *__restrict__ hist,
+                                                    const uint32_t *__restrict__ sums)
+{
+    __shared__ uint32_t part[256];
+    const int base = blockIdx.x * kScanChunk + threadIdx.x * 16;
+    uint32_t v[16], acc = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        v[i] = base + i < total ? hist[base + i] : 0u;
+        acc += v[i];
+    }
+    part[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {  // inclusive scan of the thread sums
+        const uint32_t x = threadIdx.x >= off ? part[threadIdx.x - off] : 0u;
+        __syncthreads();
+        part[threadIdx.x] += x;
+        __syncthreads();
+    }
+    uint32_t run = sums[blockIdx.x] + part[threadIdx.x] - acc;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        if (base + i < total) hist[base + i] = run;
+        run += v[i];
+    }
+}
+
 // Scatter with ranks that follow the input order inside the tile: each round
 // of 256 keys is ranked per wavefront by matching digits bit by bit with
 // ballots, then across the four wavefronts of the block through LDS.
@@ -308,11 +358,21 @@ void launch_radix_sort(int n, int passes, uint32_t *k0, uint32_t *v0, uint32_t *
                        hipStream_t st)
 {
     const int sb = (int)sort_blocks(n);
+    const int total = 256 * sb;
+    // long histograms: chunk sums live after the histogram (scan_sum_words)
+    const int chunks = (total + kScanChunk - 1) / kScanChunk;
+    uint32_t *sums = hist + total;
     uint32_t *ki = k0, *vi = v0, *ko = k1, *vo = v1;
     for (int pass = 0; pass < passes; ++pass) {
         const int shift = 8 * pass;
         hipLaunchKernelGGL(k_radix_hist, dim3(sb), dim3(kSortThreads), 0, st, n, ki, shift, hist);
-        hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, st, 256 * sb, hist);
+        if (chunks > 16) {
+            hipLaunchKernelGGL(k_scan_sums, dim3(chunks), dim3(256), 0, st, total, hist, sums);
+            hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, st, chunks, sums);
+            hipLaunchKernelGGL(k_scan_apply, dim3(chunks), dim3(256), 0, st, total, hist, sums);
+        } else {
+            hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(1024), 0, st, total, hist);
+        }
         hipLaunchKernelGGL(k_radix_scatter, dim3(sb), dim3(kSortThreads), 0, st, n, ki, vi, ko, vo, shift, hist);
         uint32_t *t0 = ki, *t1 = vi;
         ki = ko; vi = vo; ko = t0; vo = t1;

@@ -260,7 +260,7 @@ static size_t carve_job(ServerJob &j, char *base)
     j.sort.v0 = (uint32_t *)take(4 * nray);
     j.sort.k1 = (uint32_t *)take(4 * nray);
     j.sort.v1 = (uint32_t *)take(4 * nray);
-    j.sort.hist = (uint32_t *)take(4 * 256 * (size_t)sort_blocks((int64_t)nray));
+    j.sort.hist = (uint32_t *)take(4 * sort_hist_words((int64_t)nray));
     a.order = base ? j.sort.v1 : nullptr;
     return off;
 }
