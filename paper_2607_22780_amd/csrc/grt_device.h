@@ -80,28 +80,6 @@ __device__ __forceinline__ void canon_geo(const float4 r0, const float4 r1, cons
     rho2 = u * u + v * v;
 }
 
-// Ray/surfel test: plane crossing tau = n.(mu - o) / n.d in (tmin, tmax],
-// then rho^2 = u^2 + v^2 of the crossing in units of the scales, against
-// the surfel's bound r2max = min(9, 2 ln(o / alpha_min)).
-__device__ __forceinline__ bool hit_test(const float4 r0, const float4 r1, const float4 r2, const float4 r3,
-                                         const float3 o, const float3 d, float tmin, float tmax, float &tau)
-{
-#pragma clang fp contract(off)
-    float m0 = r0.x - o.x, m1 = r0.y - o.y, m2 = r0.z - o.z;
-    float den = r1.x * d.x + r1.y * d.y + r1.z * d.z;
-    if (fabsf(den) < kGrazing) return false;
-    float num = r1.x * m0 + r1.y * m1 + r1.z * m2;
-    float t = num / den;
-    if (!(t > tmin && t <= tmax)) return false;
-    float dx = t * d.x - m0, dy = t * d.y - m1, dz = t * d.z - m2;
-    float u = r2.x * dx + r2.y * dy + r2.z * dz;
-    float v = r3.x * dx + r3.y * dy + r3.z * dz;
-    float rr = u * u + v * v;
-    if (!(rr <= r0.w)) return false;
-    tau = t;
-    return true;
-}
-
 // Value geometry of a hit: the same crossing evaluated in double from the
 // single-precision record (the in-plane offset D = tau d - m cancels badly in
 // single precision for small surfels seen from afar).
@@ -324,16 +302,16 @@ struct Walker {
 #endif
     }
 
-    __device__ __forceinline__ void test_leaf(const SceneDev &S, uint32_t p)
+    // Leaf test from the canonical crossing of surfel record p (den, tau,
+    // rho^2 as canon_geo computes them; r0.w is the bound r2max, r2.w the id):
+    // a hit goes into the k-buffer, or is deferred when beyond it.
+    __device__ __forceinline__ void test_leaf(uint32_t p, float den, float tau, float rho2, float r2max, float idbits)
     {
 #ifdef GRT_STATS
         ++st_leaves;
 #endif
-        const float4 *r = S.rec + 4 * (size_t)p;
-        float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
-        float t;
-        if (!hit_test(r0, r1, r2, r3, o, d, tmin, tmax, t)) return;
-        uint64_t k = make_key(t, __float_as_uint(r2.w));
+        if (fabsf(den) < kGrazing || !(tau > tmin && tau <= tmax) || !(rho2 <= r2max)) return;
+        uint64_t k = make_key(tau, __float_as_uint(idbits));
         if (k <= last) return;
         if (k >= key[K - 1]) {  // beyond the full buffer: next round
             defer(-(int)p - 1);
@@ -369,20 +347,20 @@ struct Walker {
     }
 
     // One item of the current round; true when the round's walk is complete.
-    __device__ __forceinline__ bool step(const SceneDev &S)
+    // One item of the current round's walk; `leaf` receives at most one leaf
+    // to test.  True when the round's walk is complete.
+    __device__ __forceinline__ bool step(const SceneDev &S, int &leaf)
     {
         if (cur == kNone) {
             if (F.walk.sp == 0) return true;
             cur = F.walk.pop();
         }
-        int leaf = kNone;
         if (cur < 0) {
             leaf = cur;
             cur = kNone;
         } else {
             walk_node(S, leaf);
         }
-        if (leaf != kNone) test_leaf(S, (uint32_t)(-leaf - 1));
         return false;
     }
 
@@ -401,7 +379,7 @@ struct Walker {
         hl = keep_child(cl, hl, tl);
         hr = keep_child(cr, hr, tr);
         // Kept children, nearer first.  A step tests at most one leaf, at the
-        // single site in step() (a wavefront then runs the leaf test once per
+        // single surfel site in advance() (a wavefront then runs it once per
         // step however its lanes' children are mixed); the other child
         // becomes the item in hand or goes on the walk stack.
         const bool lfirst = hl && (!hr || tl <= tr);
@@ -463,16 +441,34 @@ struct Walker {
     template <class Visit>
     __device__ __forceinline__ bool advance(const SceneDev &S, Visit &visit)
     {
-        if (ncomp == 0) {
-            if (!step(S)) return false;
-            const int m = cnt < K ? cnt : K;
-            if (m == 0) return true;
-            ncomp = m;
-            round_last = key[K - 1];
+        const bool comp = ncomp > 0;
+        uint32_t sp;  // record of this step's surfel work
+        if (!comp) {
+            int leaf = kNone;
+            if (step(S, leaf)) {  // the round's walk is complete
+                const int m = cnt < K ? cnt : K;
+                if (m == 0) return true;
+                ncomp = m;
+                round_last = key[K - 1];
+                return false;
+            }
+            if (leaf == kNone) return false;
+            sp = (uint32_t)(-leaf - 1);
+        } else {
+            sp = pos[0];
+        }
+        // One surfel site for leaf tests and composites: the record and its
+        // canonical crossing are shared by both kinds of lanes.
+        const float4 *r = S.rec + 4 * (size_t)sp;
+        const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+        float den, tau, rho2;
+        canon_geo(r0, r1, r2, r3, o, d, den, tau, rho2);
+        if (!comp) {
+            test_leaf(sp, den, tau, rho2, r0.w, r2.w);
             return false;
         }
-        const bool stop =
-            visit(pos[0], (uint32_t)(key[0] & 0xffffffffu), __uint_as_float((uint32_t)(key[0] >> 32)));
+        const bool stop = visit(sp, (uint32_t)(key[0] & 0xffffffffu), __uint_as_float((uint32_t)(key[0] >> 32)), r0,
+                                r1, r2, r3, rho2);
 #pragma unroll
         for (int i = 0; i < K - 1; ++i) { key[i] = key[i + 1]; pos[i] = pos[i + 1]; }
         key[K - 1] = ~0ull;

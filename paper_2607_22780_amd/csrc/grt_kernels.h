@@ -37,13 +37,12 @@ struct CompositeVisit {
         cnt = 0;
     }
 
-    __device__ __forceinline__ bool operator()(uint32_t p, uint32_t id, float tau)
+    // Hit p (record r0..r3, canonical rho^2 crho2) of the ray, in order;
+    // true when compositing stops after it.
+    __device__ __forceinline__ bool operator()(uint32_t p, uint32_t id, float tau, const float4 r0, const float4 r1,
+                                               const float4 r2, const float4 r3, float crho2)
     {
-        const float4 *r = rec + 4 * (size_t)p;
-        const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
         const float4 c = col[p];
-        float cden, ctau, crho2;
-        canon_geo(r0, r1, r2, r3, o, d, cden, ctau, crho2);
         HitGeo g;
         value_geo(r0, r1, r2, r3, o, d, g);
         const float a = r1.w * expf(-0.5f * g.rho2);
@@ -88,14 +87,11 @@ struct GradVisit {
         P = make_float3(0.f, 0.f, 0.f);
     }
 
-    __device__ __forceinline__ bool operator()(uint32_t p, uint32_t id, float tau)
+    __device__ __forceinline__ bool operator()(uint32_t p, uint32_t id, float tau, const float4 r0, const float4 r1,
+                                               const float4 r2, const float4 r3, float crho2)
     {
-        const float4 *r = rec + 4 * (size_t)p;
-        const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
         const float4 c = col[p];
         const float op = r1.w;
-        float cden, ctau, crho2;
-        canon_geo(r0, r1, r2, r3, o, d, cden, ctau, crho2);
         HitGeo hg;
         value_geo(r0, r1, r2, r3, o, d, hg);
         const float G = expf(-0.5f * hg.rho2);
@@ -161,5 +157,17 @@ struct GradVisit {
         return Td < tcut;
     }
 };
+
+// Hand hit p of the visit's ray to `visit` (record loaded, canonical rho^2
+// computed here): for callers that hold only the record position.
+template <class Visit>
+__device__ __forceinline__ bool visit_hit(Visit &visit, const float4 *rec, uint32_t p, float3 o, float3 d)
+{
+    const float4 *r = rec + 4 * (size_t)p;
+    const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
+    float den, tau, rho2;
+    canon_geo(r0, r1, r2, r3, o, d, den, tau, rho2);
+    return visit(p, __float_as_uint(r2.w), tau, r0, r1, r2, r3, rho2);
+}
 
 }  // namespace grt

@@ -178,10 +178,7 @@ __global__ void __launch_bounds__(256) k_render_bwd_stored(RenderArgs a)
     GradVisit v(a.S, a.tcut, a.g);
     v.reset(x, d, gC, gT, make_float3(sv.x, sv.y, sv.z), sv.w);
     const uint32_t *list = a.hits + nray + r * a.hcap;
-    for (uint32_t i = 0; i < nh; ++i) {
-        const uint32_t pos = list[i];
-        v(pos, __float_as_uint(a.S.rec[4 * (size_t)pos + 2].w), 0.0f);
-    }
+    for (uint32_t i = 0; i < nh; ++i) visit_hit(v, a.S.rec, list[i], x, d);
 }
 
 __global__ void k_render_reduce(int64_t npix, int spp, const float4 *__restrict__ contrib, float *__restrict__ out)
