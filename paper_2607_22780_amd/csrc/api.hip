@@ -478,7 +478,7 @@ int grt_render_mis_backward(const grt_scene *scene, const grt_env *env, const gr
     const grt::RenderWS w = grt::carve_render(workspace, (int64_t)g->H * g->W * spp);
     a.counters = w.counters;
     a.rays = w.rays;
-    a.order = a.S.n >= 2 && !a.hits ? w.v1 : nullptr;
+    a.order = a.S.n >= 2 ? w.v1 : nullptr;
     if ((rc = set_device(scene->ctx))) return rc;
     hipError_t e = a.hits ? grt::launch_render_backward_stored(a, w, opts->k, scene->ctx->num_cu, (hipStream_t)stream)
                           : grt::launch_render_backward(a, w, opts->k, scene->ctx->num_cu, (hipStream_t)stream);

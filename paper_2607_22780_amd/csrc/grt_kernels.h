@@ -59,6 +59,75 @@ struct CompositeVisit {
 
 __device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 
+// Per-workgroup LDS table that sums the 13 gradient terms of hits on the same
+// surfel before they reach global memory (device FP32 atomics run at a fixed
+// rate, so every hit folded in LDS is one global update fewer).  Slots are
+// claimed once (compare-and-swap) and keep their surfel until the flush; a
+// surfel that finds no slot within kAggProbe probes goes straight to global
+// atomics.
+constexpr int kAggSlots = 1024;
+constexpr int kAggProbe = 4;
+constexpr uint32_t kAggEmpty = 0xffffffffu;
+struct GradAgg {
+    uint32_t key[kAggSlots];
+    float val[13][kAggSlots];
+};
+
+// The 13 parameter-gradient terms of one hit into the gradient arrays (or the
+// aggregation table when there is one).
+__device__ __forceinline__ void grad_out(const GradPtrs &g, GradAgg *agg, uint32_t id, const float (&t)[13])
+{
+    if (agg) {
+        uint32_t h = (id * 2654435761u) & (kAggSlots - 1);
+        for (int k = 0; k < kAggProbe; ++k, h = (h + 1) & (kAggSlots - 1)) {
+            uint32_t cur = agg->key[h];
+            if (cur == kAggEmpty) cur = atomicCAS(&agg->key[h], kAggEmpty, id);
+            if (cur == kAggEmpty || cur == id) {
+#pragma unroll
+                for (int c = 0; c < 13; ++c) atomicAdd(&agg->val[c][h], t[c]);
+                return;
+            }
+        }
+    }
+    const size_t i = id;
+    unsafeAtomicAdd(&g.means[3 * i], t[0]);
+    unsafeAtomicAdd(&g.means[3 * i + 1], t[1]);
+    unsafeAtomicAdd(&g.means[3 * i + 2], t[2]);
+    unsafeAtomicAdd(&g.scales[2 * i], t[3]);
+    unsafeAtomicAdd(&g.scales[2 * i + 1], t[4]);
+    unsafeAtomicAdd(&g.quats[4 * i], t[5]);
+    unsafeAtomicAdd(&g.quats[4 * i + 1], t[6]);
+    unsafeAtomicAdd(&g.quats[4 * i + 2], t[7]);
+    unsafeAtomicAdd(&g.quats[4 * i + 3], t[8]);
+    unsafeAtomicAdd(&g.opacity[i], t[9]);
+    unsafeAtomicAdd(&g.rgb[3 * i], t[10]);
+    unsafeAtomicAdd(&g.rgb[3 * i + 1], t[11]);
+    unsafeAtomicAdd(&g.rgb[3 * i + 2], t[12]);
+}
+
+// Every thread of the workgroup: clear the table (before use) ...
+__device__ __forceinline__ void grad_agg_clear(GradAgg *agg)
+{
+    for (int h = threadIdx.x; h < kAggSlots; h += blockDim.x) {
+        agg->key[h] = kAggEmpty;
+#pragma unroll
+        for (int c = 0; c < 13; ++c) agg->val[c][h] = 0.0f;
+    }
+}
+
+// ... and move its sums to the gradient arrays (after use).
+__device__ __forceinline__ void grad_agg_flush(const GradPtrs &g, GradAgg *agg)
+{
+    for (int h = threadIdx.x; h < kAggSlots; h += blockDim.x) {
+        const uint32_t id = agg->key[h];
+        if (id == kAggEmpty) continue;
+        float t[13];
+#pragma unroll
+        for (int c = 0; c < 13; ++c) t[c] = agg->val[c][h];
+        grad_out(g, nullptr, id, t);
+    }
+}
+
 // Backward of g_C . C + g_T . T_fin through every composited hit, with the
 // hit set, order and stop index of the forward.
 struct GradVisit {
@@ -66,6 +135,7 @@ struct GradVisit {
     const float4 *col;
     float tcut;
     GradPtrs g;
+    GradAgg *agg = nullptr;  // optional per-workgroup aggregation table
     float3 o, d, gC, Cf;
     float gT, Tf;
     float T, Td;
@@ -137,20 +207,8 @@ struct GradVisit {
         dqw = (dqw - qw * proj) * iq; dqx = (dqx - qx * proj) * iq;
         dqy = (dqy - qy * proj) * iq; dqz = (dqz - qz * proj) * iq;
 
-        const size_t i = id;
-        unsafeAtomicAdd(&g.means[3 * i], dmu.x);
-        unsafeAtomicAdd(&g.means[3 * i + 1], dmu.y);
-        unsafeAtomicAdd(&g.means[3 * i + 2], dmu.z);
-        unsafeAtomicAdd(&g.scales[2 * i], dsu);
-        unsafeAtomicAdd(&g.scales[2 * i + 1], dsv);
-        unsafeAtomicAdd(&g.quats[4 * i], dqw);
-        unsafeAtomicAdd(&g.quats[4 * i + 1], dqx);
-        unsafeAtomicAdd(&g.quats[4 * i + 2], dqy);
-        unsafeAtomicAdd(&g.quats[4 * i + 3], dqz);
-        unsafeAtomicAdd(&g.opacity[i], G * dA);
-        unsafeAtomicAdd(&g.rgb[3 * i], w * gC.x);
-        unsafeAtomicAdd(&g.rgb[3 * i + 1], w * gC.y);
-        unsafeAtomicAdd(&g.rgb[3 * i + 2], w * gC.z);
+        const float terms[13] = {dmu.x, dmu.y, dmu.z, dsu, dsv, dqw, dqx, dqy, dqz, G * dA, w * gC.x, w * gC.y, w * gC.z};
+        grad_out(g, agg, id, terms);
 
         T = T * (1.0f - a);
         Td = trans_step(Td, hit_alpha(op, crho2));

@@ -157,28 +157,36 @@ __global__ void __launch_bounds__(256) GRT_OCCUPANCY k_render_bwd(RenderArgs a)
 // overflowed are left to the re-traversal kernel.
 __global__ void __launch_bounds__(256) k_render_bwd_stored(RenderArgs a)
 {
+    __shared__ GradAgg agg;
+    grad_agg_clear(&agg);
+    __syncthreads();
     const int spp = a.nc + a.ng + a.ne;
     const int64_t nray = (int64_t)a.H * a.W * spp;
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nray || a.S.n <= 0) return;
-    const uint32_t nh = a.hits[r];
-    if (nh == 0u || nh > (uint32_t)a.hcap) return;
-    const float4 r0 = a.rays[3 * r];
-    if (r0.w == 0.0f) return;
-    const int64_t p = r / spp;
-    const float inv = 1.0f / (float)spp;
-    const float3 gp = make_float3(a.grad[3 * p] * inv, a.grad[3 * p + 1] * inv, a.grad[3 * p + 2] * inv);
-    if (gp.x == 0.0f && gp.y == 0.0f && gp.z == 0.0f) return;
-    const float4 r1 = a.rays[3 * r + 1], r2 = a.rays[3 * r + 2];
-    const float3 gC = make_float3(r1.x * gp.x, r1.y * gp.y, r1.z * gp.z);
-    const float gT = gC.x * r1.w + gC.y * r2.x + gC.z * r2.y;
-    const float4 sv = a.saved[r];
-    const float3 x = make_float3(a.x[3 * p], a.x[3 * p + 1], a.x[3 * p + 2]);
-    const float3 d = make_float3(r0.x, r0.y, r0.z);
-    GradVisit v(a.S, a.tcut, a.g);
-    v.reset(x, d, gC, gT, make_float3(sv.x, sv.y, sv.z), sv.w);
-    const uint32_t *list = a.hits + nray + r * a.hcap;
-    for (uint32_t i = 0; i < nh; ++i) visit_hit(v, a.S.rec, list[i], x, d);
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // samples in traversal order: a workgroup's rays are neighbours and share surfels
+    const int64_t r = g < nray ? (a.order ? (int64_t)a.order[g] : g) : 0;
+    const uint32_t nh = g < nray && a.S.n > 0 ? a.hits[r] : 0u;
+    const float4 r0 = nh ? a.rays[3 * r] : make_float4(0.f, 0.f, 0.f, 0.f);
+    if (nh > 0u && nh <= (uint32_t)a.hcap && r0.w != 0.0f) {
+        const int64_t p = r / spp;
+        const float inv = 1.0f / (float)spp;
+        const float3 gp = make_float3(a.grad[3 * p] * inv, a.grad[3 * p + 1] * inv, a.grad[3 * p + 2] * inv);
+        if (gp.x != 0.0f || gp.y != 0.0f || gp.z != 0.0f) {
+            const float4 r1 = a.rays[3 * r + 1], r2 = a.rays[3 * r + 2];
+            const float3 gC = make_float3(r1.x * gp.x, r1.y * gp.y, r1.z * gp.z);
+            const float gT = gC.x * r1.w + gC.y * r2.x + gC.z * r2.y;
+            const float4 sv = a.saved[r];
+            const float3 x = make_float3(a.x[3 * p], a.x[3 * p + 1], a.x[3 * p + 2]);
+            const float3 d = make_float3(r0.x, r0.y, r0.z);
+            GradVisit v(a.S, a.tcut, a.g);
+            v.agg = &agg;
+            v.reset(x, d, gC, gT, make_float3(sv.x, sv.y, sv.z), sv.w);
+            const uint32_t *list = a.hits + nray + r * a.hcap;
+            for (uint32_t i = 0; i < nh; ++i) visit_hit(v, a.S.rec, list[i], x, d);
+        }
+    }
+    __syncthreads();
+    grad_agg_flush(a.g, &agg);
 }
 
 __global__ void k_render_reduce(int64_t npix, int spp, const float4 *__restrict__ contrib, float *__restrict__ out)
@@ -208,12 +216,12 @@ static hipError_t go_render_bwd(const RenderArgs &a, int num_cu, hipStream_t st)
 
 hipError_t launch_render_backward_stored(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st)
 {
-    (void)w;
     const int64_t nray = (int64_t)a.H * a.W * (a.nc + a.ng + a.ne);
     if (nray <= 0) return hipSuccess;
     hipError_t e = launch_zero_counters(a.counters, st);
     if (e != hipSuccess) return e;
     if ((e = launch_render_gen(a, st)) != hipSuccess) return e;
+    if (a.order && (e = launch_ray_order(a, w, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_render_bwd_stored, dim3((unsigned)((nray + 255) / 256)), dim3(256), 0, st, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // samples whose list overflowed: re-traverse (the others return at once)
