@@ -10,6 +10,8 @@
 // A child reference >= 0 is an internal node, < 0 is leaf -(pos+1).
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -188,9 +190,11 @@ __device__ __forceinline__ uint64_t make_key(float tau, uint32_t id)
 #define GRT_LDS_DEPTH 24
 #endif
 constexpr int kLdsDepth = GRT_LDS_DEPTH;  // LDS entries per lane and stack
+constexpr int kBwdLdsDepth = 12;          // backward kernels: their LDS also holds gradient tables
 constexpr int kStackCap = 160;  // logical capacity of a stack
 constexpr int kNone = 0x7fffffff;
 
+template <int D>
 struct SpillStack {
     int *lds;  // this lane's slot 0; slot i at lds[64 * i]
     int *mem;  // private overflow array [kStackCap]
@@ -200,10 +204,10 @@ struct SpillStack {
 
     __device__ __forceinline__ void push(int x)
     {
-        const int slot = sp % kLdsDepth;
-        if (sp >= kLdsDepth && sp - kLdsDepth >= spilled) {
-            mem[sp - kLdsDepth] = lds[64 * slot];
-            spilled = sp - kLdsDepth + 1;
+        const int slot = sp % D;
+        if (sp >= D && sp - D >= spilled) {
+            mem[sp - D] = lds[64 * slot];
+            spilled = sp - D + 1;
         }
         lds[64 * slot] = x;
         ++sp;
@@ -216,7 +220,7 @@ struct SpillStack {
             spilled = sp;
             return mem[sp];
         }
-        return lds[64 * (sp % kLdsDepth)];
+        return lds[64 * (sp % D)];
     }
 };
 
@@ -227,9 +231,10 @@ struct SpillStack {
 // tie-break), so it stays within kStackCap.
 constexpr int kMaxDeferred = kStackCap - 64;
 
+template <int D>
 struct Frontier {
-    SpillStack walk;  // the current round's walk stack
-    SpillStack def;   // deferrals for the next round
+    SpillStack<D> walk;  // the current round's walk stack
+    SpillStack<D> def;   // deferrals for the next round
 
     // the deferred list becomes the walk stack (descriptor fields swapped, no copy)
     __device__ __forceinline__ void swap_roles()
@@ -241,8 +246,9 @@ struct Frontier {
     }
 };
 
-template <int K>
+template <int K, int D = kLdsDepth>
 struct Walker {
+    static constexpr int kDepth = D;  // LDS entries per lane and stack
     float3 o, d, inv;
     float tmin, tmax;
     uint64_t last;
@@ -252,7 +258,7 @@ struct Walker {
     int cnt;
     int cur;              // item in hand: node >= 0, leaf -(pos+1), or kNone
     bool lost;            // deferred list dropped: next round restarts at the root
-    Frontier F;           // walk stack and deferred list (LDS + private spill)
+    Frontier<D> F;        // walk stack and deferred list (LDS + private spill)
     int ncomp;            // buffered hits still to composite (0 while walking)
     uint64_t round_last;  // largest key of the round's full buffer
 #ifdef GRT_STATS
@@ -495,7 +501,9 @@ struct Walker {
 //
 // Job: bool begin(int64_t ray)  -- set up the ray; false if it needs no trace
 //      (then it must already have written its result)
-//      Walker<K> &walker(), Visit &visit(), void finish(int64_t ray)
+//      Walker<K, D> &walker(), Visit &visit(), void finish(int64_t ray),
+//      void after_step() and void drain() -- run by every lane of the
+//      wavefront after each step and before it leaves
 // ---------------------------------------------------------------------------
 constexpr int kParts = 8;
 constexpr int kChunk = 64;
@@ -513,11 +521,13 @@ __device__ __forceinline__ void run_persistent(Job &job, unsigned long long *cou
     bool exhausted = false;               // wavefront-uniform
     bool active = false;
     int64_t ray = -1;
-    __shared__ int lds_stacks[4][2][kLdsDepth][64];  // [wave][stack][slot][lane]
+    using WalkerT = typename std::remove_reference<decltype(job.walker())>::type;
+    constexpr int D = WalkerT::kDepth;
+    __shared__ int lds_stacks[4][2][D][64];  // [wave][stack][slot][lane]
     int spill0[kStackCap], spill1[kStackCap];
     const int wave = (threadIdx.x >> 6) & 3;
     {
-        Frontier &F = job.walker().F;
+        auto &F = job.walker().F;
         F.walk.lds = &lds_stacks[wave][0][0][lane];
         F.def.lds = &lds_stacks[wave][1][0][lane];
         F.walk.mem = spill0;
@@ -557,7 +567,10 @@ __device__ __forceinline__ void run_persistent(Job &job, unsigned long long *cou
             }
         }
         if (!__ballot(active)) {
-            if (exhausted) break;
+            if (exhausted) {
+                job.drain();
+                break;
+            }
             continue;
         }
         if (active) {
@@ -566,6 +579,7 @@ __device__ __forceinline__ void run_persistent(Job &job, unsigned long long *cou
                 active = false;
             }
         }
+        job.after_step();  // wavefront-uniform point
     }
 }
 

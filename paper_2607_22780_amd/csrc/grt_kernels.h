@@ -59,36 +59,30 @@ struct CompositeVisit {
 
 __device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 
-// Per-workgroup LDS table that sums the 13 gradient terms of hits on the same
-// surfel before they reach global memory (device FP32 atomics run at a fixed
-// rate, so every hit folded in LDS is one global update fewer).  Slots are
-// claimed once (compare-and-swap) and keep their surfel until the flush; a
-// surfel that finds no slot within kAggProbe probes goes straight to global
-// atomics.
-constexpr int kAggSlots = 1024;
+// LDS tables that sum the 13 gradient terms of hits on the same surfel before
+// they reach global memory (device FP32 atomics run at a fixed rate, so every
+// hit folded in LDS is one global update fewer).  A slot is claimed by
+// compare-and-swap and keeps its surfel until the table is flushed; a surfel
+// that finds no slot within kAggProbe probes goes straight to global atomics.
+// The stored-list backward keeps one table per workgroup, flushed once; the
+// re-traversal backward keeps one per wavefront, flushed at wavefront-uniform
+// points once kWaveFlushAt slots are taken (no workgroup barrier needed).
 constexpr int kAggProbe = 4;
 constexpr uint32_t kAggEmpty = 0xffffffffu;
-struct GradAgg {
-    uint32_t key[kAggSlots];
-    float val[13][kAggSlots];
+template <int S>
+struct GradTable {
+    uint32_t key[S];
+    float val[13][S];
+    int claimed;
 };
+constexpr int kAggSlots = 1024;
+constexpr int kWaveSlots = 128;
+constexpr int kWaveFlushAt = 96;
+using GradAgg = GradTable<kAggSlots>;   // per workgroup
+using WaveAgg = GradTable<kWaveSlots>;  // per wavefront
 
-// The 13 parameter-gradient terms of one hit into the gradient arrays (or the
-// aggregation table when there is one).
-__device__ __forceinline__ void grad_out(const GradPtrs &g, GradAgg *agg, uint32_t id, const float (&t)[13])
+__device__ __forceinline__ void grad_global(const GradPtrs &g, uint32_t id, const float (&t)[13])
 {
-    if (agg) {
-        uint32_t h = (id * 2654435761u) & (kAggSlots - 1);
-        for (int k = 0; k < kAggProbe; ++k, h = (h + 1) & (kAggSlots - 1)) {
-            uint32_t cur = agg->key[h];
-            if (cur == kAggEmpty) cur = atomicCAS(&agg->key[h], kAggEmpty, id);
-            if (cur == kAggEmpty || cur == id) {
-#pragma unroll
-                for (int c = 0; c < 13; ++c) atomicAdd(&agg->val[c][h], t[c]);
-                return;
-            }
-        }
-    }
     const size_t i = id;
     unsafeAtomicAdd(&g.means[3 * i], t[0]);
     unsafeAtomicAdd(&g.means[3 * i + 1], t[1]);
@@ -105,27 +99,67 @@ __device__ __forceinline__ void grad_out(const GradPtrs &g, GradAgg *agg, uint32
     unsafeAtomicAdd(&g.rgb[3 * i + 2], t[12]);
 }
 
-// Every thread of the workgroup: clear the table (before use) ...
-__device__ __forceinline__ void grad_agg_clear(GradAgg *agg)
+// The 13 parameter-gradient terms of one hit into table t, else global.
+template <int S>
+__device__ __forceinline__ bool grad_table_add(GradTable<S> *t, uint32_t id, const float (&v)[13])
 {
-    for (int h = threadIdx.x; h < kAggSlots; h += blockDim.x) {
-        agg->key[h] = kAggEmpty;
+    uint32_t h = (id * 2654435761u) & (S - 1);
+    for (int k = 0; k < kAggProbe; ++k, h = (h + 1) & (S - 1)) {
+        uint32_t cur = t->key[h];
+        if (cur == kAggEmpty) {
+            cur = atomicCAS(&t->key[h], kAggEmpty, id);
+            if (cur == kAggEmpty) atomicAdd(&t->claimed, 1);
+        }
+        if (cur == kAggEmpty || cur == id) {
 #pragma unroll
-        for (int c = 0; c < 13; ++c) agg->val[c][h] = 0.0f;
+            for (int c = 0; c < 13; ++c) atomicAdd(&t->val[c][h], v[c]);
+            return true;
+        }
     }
+    return false;
 }
 
-// ... and move its sums to the gradient arrays (after use).
-__device__ __forceinline__ void grad_agg_flush(const GradPtrs &g, GradAgg *agg)
+// All threads of the table's owner (workgroup or wavefront): clear it.
+template <int S>
+__device__ __forceinline__ void grad_table_clear(GradTable<S> *t, int tid, int nthreads)
 {
-    for (int h = threadIdx.x; h < kAggSlots; h += blockDim.x) {
-        const uint32_t id = agg->key[h];
-        if (id == kAggEmpty) continue;
-        float t[13];
+    for (int h = tid; h < S; h += nthreads) {
+        t->key[h] = kAggEmpty;
 #pragma unroll
-        for (int c = 0; c < 13; ++c) t[c] = agg->val[c][h];
-        grad_out(g, nullptr, id, t);
+        for (int c = 0; c < 13; ++c) t->val[c][h] = 0.0f;
     }
+    if (tid == 0) t->claimed = 0;
+}
+
+// All threads of the owner: move the sums to the gradient arrays, then clear.
+template <int S>
+__device__ __forceinline__ void grad_table_flush(const GradPtrs &g, GradTable<S> *t, int tid, int nthreads)
+{
+    for (int h = tid; h < S; h += nthreads) {
+        const uint32_t id = t->key[h];
+        if (id == kAggEmpty) continue;
+        float v[13];
+#pragma unroll
+        for (int c = 0; c < 13; ++c) {
+            v[c] = t->val[c][h];
+            t->val[c][h] = 0.0f;
+        }
+        t->key[h] = kAggEmpty;
+        grad_global(g, id, v);
+    }
+    if (tid == 0) t->claimed = 0;
+}
+
+// Wavefront-uniform point of the re-traversal backward: flush the wavefront's
+// table once it is mostly taken (all of it when `all`).  The fences make the
+// lanes' LDS writes visible to each other (lanes hand slots over here).
+__device__ __forceinline__ void wave_table_sync(const GradPtrs &g, WaveAgg *t, bool all)
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const int taken = __builtin_amdgcn_readfirstlane(*(volatile int *)&t->claimed);
+    if (taken == 0 || (!all && taken < kWaveFlushAt)) return;
+    grad_table_flush(g, t, threadIdx.x & 63, 64);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
 // Backward of g_C . C + g_T . T_fin through every composited hit, with the
@@ -135,7 +169,8 @@ struct GradVisit {
     const float4 *col;
     float tcut;
     GradPtrs g;
-    GradAgg *agg = nullptr;  // optional per-workgroup aggregation table
+    GradAgg *agg = nullptr;   // optional per-workgroup aggregation table
+    WaveAgg *wagg = nullptr;  // optional per-wavefront aggregation table
     float3 o, d, gC, Cf;
     float gT, Tf;
     float T, Td;
@@ -208,7 +243,8 @@ struct GradVisit {
         dqy = (dqy - qy * proj) * iq; dqz = (dqz - qz * proj) * iq;
 
         const float terms[13] = {dmu.x, dmu.y, dmu.z, dsu, dsv, dqw, dqx, dqy, dqz, G * dA, w * gC.x, w * gC.y, w * gC.z};
-        grad_out(g, agg, id, terms);
+        if (!((wagg && grad_table_add(wagg, id, terms)) || (agg && grad_table_add(agg, id, terms))))
+            grad_global(g, id, terms);
 
         T = T * (1.0f - a);
         Td = trans_step(Td, hit_alpha(op, crho2));

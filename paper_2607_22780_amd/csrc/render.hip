@@ -99,18 +99,26 @@ struct RenderJob {
         return t.begin(a, S, r);
     }
     __device__ __forceinline__ void finish(int64_t) { t.finish(a, r); }
+    __device__ __forceinline__ void after_step() {}
+    __device__ __forceinline__ void drain() {}
 };
 
 template <int K>
 struct RenderBwdJob {
     const RenderArgs &a;
     SceneDev S;
-    Walker<K> w;
+    Walker<K, kBwdLdsDepth> w;
     GradVisit v;
     int spp;
 
-    __device__ RenderBwdJob(const RenderArgs &a_) : a(a_), S(a_.S), v(a_.S, a_.tcut, a_.g), spp(a_.nc + a_.ng + a_.ne) {}
-    __device__ __forceinline__ Walker<K> &walker() { return w; }
+    __device__ RenderBwdJob(const RenderArgs &a_, WaveAgg *t)
+        : a(a_), S(a_.S), v(a_.S, a_.tcut, a_.g), spp(a_.nc + a_.ng + a_.ne)
+    {
+        v.wagg = t;
+        grad_table_clear(t, threadIdx.x & 63, 64);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+    __device__ __forceinline__ Walker<K, kBwdLdsDepth> &walker() { return w; }
     __device__ __forceinline__ GradVisit &visit() { return v; }
 
     __device__ __forceinline__ bool begin(int64_t g)
@@ -136,6 +144,8 @@ struct RenderBwdJob {
     }
 
     __device__ __forceinline__ void finish(int64_t) {}
+    __device__ __forceinline__ void after_step() { wave_table_sync(a.g, v.wagg, false); }
+    __device__ __forceinline__ void drain() { wave_table_sync(a.g, v.wagg, true); }
 };
 
 template <int K>
@@ -148,7 +158,8 @@ __global__ void __launch_bounds__(256) GRT_OCCUPANCY k_render(RenderArgs a)
 template <int K>
 __global__ void __launch_bounds__(256) GRT_OCCUPANCY k_render_bwd(RenderArgs a)
 {
-    RenderBwdJob<K> job(a);
+    __shared__ WaveAgg tables[4];
+    RenderBwdJob<K> job(a, &tables[(threadIdx.x >> 6) & 3]);
     run_persistent<K>(job, a.counters, (int64_t)a.H * a.W * (a.nc + a.ng + a.ne));
 }
 
@@ -158,7 +169,7 @@ __global__ void __launch_bounds__(256) GRT_OCCUPANCY k_render_bwd(RenderArgs a)
 __global__ void __launch_bounds__(256) k_render_bwd_stored(RenderArgs a)
 {
     __shared__ GradAgg agg;
-    grad_agg_clear(&agg);
+    grad_table_clear(&agg, threadIdx.x, blockDim.x);
     __syncthreads();
     const int spp = a.nc + a.ng + a.ne;
     const int64_t nray = (int64_t)a.H * a.W * spp;
@@ -186,7 +197,7 @@ __global__ void __launch_bounds__(256) k_render_bwd_stored(RenderArgs a)
         }
     }
     __syncthreads();
-    grad_agg_flush(a.g, &agg);
+    grad_table_flush(a.g, &agg, threadIdx.x, blockDim.x);
 }
 
 __global__ void k_render_reduce(int64_t npix, int spp, const float4 *__restrict__ contrib, float *__restrict__ out)

@@ -83,7 +83,8 @@ struct ServeJob {
         return t.begin(*a, S, r);
     }
 
-    __device__ __forceinline__ void finish(int64_t) { t.finish(*a, r); }
+    __device__ __forceinline__ void finish(int64_t) { t.finish(*a, r); }    __device__ __forceinline__ void after_step() {}
+    __device__ __forceinline__ void drain() {}
 };
 
 template <int K>
@@ -112,7 +113,8 @@ struct ServeOneJob {
         r = a.order ? (int64_t)a.order[r0 + g] : r0 + g;
         return t.begin(a, S, r);
     }
-    __device__ __forceinline__ void finish(int64_t) { t.finish(a, r); }
+    __device__ __forceinline__ void finish(int64_t) { t.finish(a, r); }    __device__ __forceinline__ void after_step() {}
+    __device__ __forceinline__ void drain() {}
 };
 
 template <int K>

@@ -70,17 +70,24 @@ struct TraceJob {
         if (a.dump_id)
             for (int i = v.cnt; i < a.cap; ++i) { v.did[i] = -1; v.dtau[i] = 0.0f; }
     }
+    __device__ __forceinline__ void after_step() {}
+    __device__ __forceinline__ void drain() {}
 };
 
 template <int K>
 struct TraceBwdJob {
     const TraceBwdArgs &a;
     SceneDev S;
-    Walker<K> w;
+    Walker<K, kBwdLdsDepth> w;
     GradVisit v;
 
-    __device__ TraceBwdJob(const TraceBwdArgs &a_) : a(a_), S(a_.f.S), v(a_.f.S, a_.f.tcut, a_.g) {}
-    __device__ __forceinline__ Walker<K> &walker() { return w; }
+    __device__ TraceBwdJob(const TraceBwdArgs &a_, WaveAgg *t) : a(a_), S(a_.f.S), v(a_.f.S, a_.f.tcut, a_.g)
+    {
+        v.wagg = t;
+        grad_table_clear(t, threadIdx.x & 63, 64);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+    __device__ __forceinline__ Walker<K, kBwdLdsDepth> &walker() { return w; }
     __device__ __forceinline__ GradVisit &visit() { return v; }
 
     __device__ __forceinline__ bool begin(int64_t r)
@@ -100,6 +107,8 @@ struct TraceBwdJob {
     }
 
     __device__ __forceinline__ void finish(int64_t) {}
+    __device__ __forceinline__ void after_step() { wave_table_sync(a.g, v.wagg, false); }
+    __device__ __forceinline__ void drain() { wave_table_sync(a.g, v.wagg, true); }
 };
 
 template <int K>
@@ -112,7 +121,8 @@ __global__ void __launch_bounds__(256) GRT_OCCUPANCY k_trace(TraceArgs a)
 template <int K>
 __global__ void __launch_bounds__(256) GRT_OCCUPANCY k_trace_bwd(TraceBwdArgs a)
 {
-    TraceBwdJob<K> job(a);
+    __shared__ WaveAgg tables[4];
+    TraceBwdJob<K> job(a, &tables[(threadIdx.x >> 6) & 3]);
     run_persistent<K>(job, a.f.counters, a.f.n);
 }
 
