@@ -360,7 +360,9 @@ int grt_server_submit(grt_server *server, const grt_job *job, uint64_t *id);
 int grt_server_poll(grt_server *server, uint64_t id, int *state);
 
 /* Block until the request is done (returns its status) or timeout_s seconds
- * pass (GRT_ERR_TIMEOUT). */
+ * pass (GRT_ERR_TIMEOUT).  The server remembers the last 65,536 finished
+ * requests; older ids are unknown (GRT_ERR_INVALID) to poll, wait and
+ * job_times. */
 int grt_server_wait(grt_server *server, uint64_t id, double timeout_s);
 
 /* Cancel a request: removed if queued, dropped at the next epoch boundary if

@@ -191,6 +191,12 @@ __device__ __forceinline__ uint64_t make_key(float tau, uint32_t id)
 #endif
 constexpr int kLdsDepth = GRT_LDS_DEPTH;  // LDS entries per lane and stack
 constexpr int kBwdLdsDepth = 12;          // backward kernels: their LDS also holds gradient tables
+// Surfel steps run when at least kSurfelShare4 / 4 of a wavefront's active
+// lanes wait for one.
+#ifndef GRT_SURFEL_SHARE4
+#define GRT_SURFEL_SHARE4 2
+#endif
+constexpr int kSurfelShare4 = GRT_SURFEL_SHARE4;
 constexpr int kStackCap = 160;  // logical capacity of a stack
 constexpr int kNone = 0x7fffffff;
 
@@ -260,6 +266,7 @@ struct Walker {
     bool lost;            // deferred list dropped: next round restarts at the root
     Frontier<D> F;        // walk stack and deferred list (LDS + private spill)
     int ncomp;            // buffered hits still to composite (0 while walking)
+    int pend;             // leaf waiting for the next surfel step (record position), or kNone
     uint64_t round_last;  // largest key of the round's full buffer
 #ifdef GRT_STATS
     int st_nodes, st_leaves, st_rounds, st_lost, st_deferred;
@@ -283,6 +290,7 @@ struct Walker {
         last = 0;
         tlo = tmin;
         ncomp = 0;
+        pend = kNone;
         F.walk.reset();
         F.def.reset();
         lost = false;
@@ -444,25 +452,34 @@ struct Walker {
     // then shifts down).  Compositing a hit per call keeps a lane that ends
     // its round from holding the wavefront for K hits.  Returns true when the
     // ray is finished.
+    // One step of the lane.  Walking lanes step a node every call; a leaf they
+    // find waits (pend) for a surfel step, and so do buffered hits to
+    // composite.  Surfel steps -- the record, its canonical crossing, then the
+    // k-buffer insertion or the visitor -- run for the whole wavefront at
+    // once, when enough of its active lanes wait for one (or all do),
+    // so that block runs with many lanes (leaf tests postponed as in
+    // speculative while-while traversal).  Returns true when the ray is
+    // finished.  Every active lane of the wavefront calls it in the same step
+    // (the decision is a ballot over them).
     template <class Visit>
     __device__ __forceinline__ bool advance(const SceneDev &S, Visit &visit)
     {
-        const bool comp = ncomp > 0;
-        uint32_t sp;  // record of this step's surfel work
-        if (!comp) {
+        if (ncomp == 0 && pend == kNone) {
             int leaf = kNone;
             if (step(S, leaf)) {  // the round's walk is complete
                 const int m = cnt < K ? cnt : K;
                 if (m == 0) return true;
                 ncomp = m;
                 round_last = key[K - 1];
-                return false;
+            } else if (leaf != kNone) {
+                pend = -leaf - 1;
             }
-            if (leaf == kNone) return false;
-            sp = (uint32_t)(-leaf - 1);
-        } else {
-            sp = pos[0];
         }
+        const bool want = pend != kNone || ncomp > 0;
+        const int nwant = __popcll(__ballot(want)), nact = __popcll(__ballot(1));
+        if (!want || (4 * nwant < kSurfelShare4 * nact && nwant < nact)) return false;
+        const bool comp = ncomp > 0;
+        const uint32_t sp = comp ? pos[0] : (uint32_t)pend;
         // One surfel site for leaf tests and composites: the record and its
         // canonical crossing are shared by both kinds of lanes.
         const float4 *r = S.rec + 4 * (size_t)sp;
@@ -471,6 +488,7 @@ struct Walker {
         canon_geo(r0, r1, r2, r3, o, d, den, tau, rho2);
         if (!comp) {
             test_leaf(sp, den, tau, rho2, r0.w, r2.w);
+            pend = kNone;
             return false;
         }
         const bool stop = visit(sp, (uint32_t)(key[0] & 0xffffffffu), __uint_as_float((uint32_t)(key[0] >> 32)), r0,

@@ -303,6 +303,7 @@ struct grt_server {
     int error = GRT_OK;
     std::deque<uint64_t> pending;
     std::map<uint64_t, ServerJob> jobs;
+    std::deque<uint64_t> history;  // finished requests, oldest first (bounded)
     std::vector<uint64_t> resident;  // uploading or running, in admission order
     std::vector<int> free_slots;
     hipStream_t copy = nullptr;
@@ -320,6 +321,9 @@ struct grt_server {
 namespace {
 
 int sfail(int code, const char *msg) { return grt::set_error(code, msg); }
+
+// Finished requests the server keeps for poll, wait and job_times.
+constexpr size_t kHistory = 65536;
 
 size_t job_bytes(const grt_job &spec)
 {
@@ -399,6 +403,12 @@ void finish_job(grt_server *s, ServerJob &j, int status)
     j.state = kDone;
     j.status = status;
     j.t_done = s->now();
+    // remember a bounded number of finished requests (j itself is the newest)
+    s->history.push_back(j.id);
+    while (s->history.size() > kHistory) {
+        s->jobs.erase(s->history.front());
+        s->history.pop_front();
+    }
 }
 
 // Called with no epoch in flight (or after a device error, when nothing
@@ -749,14 +759,18 @@ int grt_server_wait(grt_server *s, uint64_t id, double timeout_s)
 {
     if (!s) return sfail(GRT_ERR_INVALID, "NULL argument");
     std::unique_lock<std::mutex> lk(s->mu);
-    auto it = s->jobs.find(id);
-    if (it == s->jobs.end()) return sfail(GRT_ERR_INVALID, "unknown job id");
     const auto deadline = grt::Clock::now() + std::chrono::duration<double>(timeout_s);
-    while (it->second.state != kDone) {
-        if (s->cv.wait_until(lk, deadline) == std::cv_status::timeout && it->second.state != kDone)
+    for (;;) {
+        // looked up after every wake: entries of old finished requests are dropped
+        auto it = s->jobs.find(id);
+        if (it == s->jobs.end()) return sfail(GRT_ERR_INVALID, "unknown job id");
+        if (it->second.state == kDone) return it->second.status;
+        if (s->cv.wait_until(lk, deadline) == std::cv_status::timeout) {
+            it = s->jobs.find(id);
+            if (it != s->jobs.end() && it->second.state == kDone) return it->second.status;
             return sfail(GRT_ERR_TIMEOUT, "wait timed out");
+        }
     }
-    return it->second.status;
 }
 
 int grt_server_cancel(grt_server *s, uint64_t id)
