@@ -197,7 +197,7 @@ constexpr int kBwdLdsDepth = 12;          // backward kernels: their LDS also ho
 #define GRT_SURFEL_SHARE4 2
 #endif
 constexpr int kSurfelShare4 = GRT_SURFEL_SHARE4;
-constexpr int kStackCap = 160;  // logical capacity of a stack
+constexpr int kStackCap = 256;  // logical capacity of a stack
 constexpr int kNone = 0x7fffffff;
 
 template <int D>
