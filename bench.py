@@ -234,7 +234,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--k", type=int, default=8)
+    ap.add_argument("--k", type=int, default=12, help="k-buffer size of the forward")
+    ap.add_argument("--k-bwd", type=int, default=8, help="k-buffer size of the backward")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=384, help="pixels of the step the oracle times")
     ap.add_argument("--no-serve", action="store_true", help="skip the relighting-server leg")
@@ -278,7 +279,7 @@ def main():
     def step(record=False):
         for p in params:
             p.grad = None
-        img = grt.RenderMISFn.apply(*params, ctx, E, G, SPLIT, SEED, args.k, 1.0 / 255.0)
+        img = grt.RenderMISFn.apply(*params, ctx, E, G, SPLIT, SEED, args.k, 1.0 / 255.0, 0, args.k_bwd)
         loss = (img * upstream).sum()
         loss.backward()
         return img
@@ -306,7 +307,7 @@ def main():
         res = grt.render_mis(scene, E, G, split=SPLIT, seed=SEED, k=args.k, save=True)
         ef1.record(st)
         eg0.record(st)
-        grt.render_mis_backward(scene, E, G, upstream, res["saved"], split=SPLIT, seed=SEED, k=args.k)
+        grt.render_mis_backward(scene, E, G, upstream, res["saved"], split=SPLIT, seed=SEED, k=args.k_bwd)
         eg1.record(st)
         torch.cuda.synchronize()
         build_ms.append(eb0.elapsed_time(eb1)); fwd_ms.append(ef0.elapsed_time(ef1)); bwd_ms.append(eg0.elapsed_time(eg1))
@@ -323,8 +324,8 @@ def main():
                                  hit_cap=args.hit_cap)
             ef1.record(st)
             eg0.record(st)
-            grt.render_mis_backward(scene, E, G, upstream, res["saved"], split=SPLIT, seed=SEED, k=args.k, hits=hits,
-                                    hit_cap=args.hit_cap)
+            grt.render_mis_backward(scene, E, G, upstream, res["saved"], split=SPLIT, seed=SEED, k=args.k_bwd,
+                                    hits=hits, hit_cap=args.hit_cap)
             eg1.record(st)
             torch.cuda.synchronize()
             sf.append(ef0.elapsed_time(ef1)); sb.append(eg0.elapsed_time(eg1))
@@ -388,7 +389,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "room scene, 1M surfels, 1024x1024 G-buffer, 32 spp (16/8/8 MIS), 256x512 env; "
                                "fwd+bwd training step", "surfels": s.n, "valid_pixels": npx_valid, "spp": spp,
-                   "rays_per_step": rays, "k": args.k},
+                   "rays_per_step": rays, "k": args.k, "k_bwd": args.k_bwd},
         "fwd_mrays_s": round(rays / (fwd_ms * 1e-3) / 1e6, 2),
         "phase_ms": {"build": round(build_ms, 3), "render_fwd": round(fwd_ms, 3), "render_bwd": round(bwd_ms, 3)},
         "roofline": roofline,

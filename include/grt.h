@@ -140,7 +140,7 @@ typedef struct {
     float t_max_all;
 } grt_rays;
 
-/* k: k-nearest hit buffer size per traversal round, one of 1,2,4,8,16,32
+/* k: k-nearest hit buffer size per traversal round, one of 1,2,4,8,12,16,32
  *    (results do not depend on k).
  * t_cut: transmittance cutoff (1e-3 in the workloads).
  * sky: radiance of escaped rays, L = c_rt + T sky.
@@ -308,9 +308,9 @@ int grt_render_mis_backward(const grt_scene *scene, const grt_env *env, const gr
  * mem_budget:    device bytes the server allocates for requests (its pool).
  * max_jobs:      requests resident at once (1..256).
  * epoch_rays:    at most this many rays per epoch (0 = 134,217,728); an epoch
- *                takes the rest of the earliest-deadline request, topped up
- *                with the next requests while under 1,048,576 rays.
- * k:             k-buffer size, 4, 8 or 16.  t_min, t_cut as in grt_mis_opts.
+ *                takes the rest of the earliest-deadline request, plus the
+ *                next requests while the epoch stays within 1,048,576 rays.
+ * k:             k-buffer size, 4, 8, 12 or 16.  t_min, t_cut as in grt_mis_opts.
  * slack_per_ray: seconds of deadline per ray (0 = arrival order only;
  *                negative = 4e-8, about twice a request's time alone). */
 typedef struct {

@@ -70,8 +70,8 @@ int check_rays(const grt_rays *r)
 
 int check_k(int k)
 {
-    if (k == 1 || k == 2 || k == 4 || k == 8 || k == 16 || k == 32) return GRT_OK;
-    return fail(GRT_ERR_INVALID, "k = %d is not one of 1,2,4,8,16,32", k);
+    if (k == 1 || k == 2 || k == 4 || k == 8 || k == 12 || k == 16 || k == 32) return GRT_OK;
+    return fail(GRT_ERR_INVALID, "k = %d is not one of 1,2,4,8,12,16,32", k);
 }
 
 int check_scene(const grt_scene *s)

@@ -155,6 +155,15 @@ __global__ void __launch_bounds__(256) GRT_OCCUPANCY k_render(RenderArgs a)
     run_persistent<K>(job, a.counters, (int64_t)a.H * a.W * (a.nc + a.ng + a.ne));
 }
 
+// The forward with a 12-hit buffer fits 3 wavefronts per SIMD (168 VGPRs)
+// when the compiler is held to it; it then beats K = 8 (fewer rounds).
+template <int K>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_render_w3(RenderArgs a)
+{
+    RenderJob<K> job(a);
+    run_persistent<K>(job, a.counters, (int64_t)a.H * a.W * (a.nc + a.ng + a.ne));
+}
+
 template <int K>
 __global__ void __launch_bounds__(256) GRT_OCCUPANCY k_render_bwd(RenderArgs a)
 {
@@ -211,8 +220,13 @@ template <int K>
 static hipError_t go_render(const RenderArgs &a, int num_cu, hipStream_t st)
 {
     const int64_t total = (int64_t)a.H * a.W * (a.nc + a.ng + a.ne);
-    const int nb = persistent_blocks(k_render<K>, num_cu, total);
-    hipLaunchKernelGGL(k_render<K>, dim3(nb), dim3(256), 0, st, a);
+    if constexpr (K == 12) {
+        const int nb = persistent_blocks(k_render_w3<K>, num_cu, total);
+        hipLaunchKernelGGL(k_render_w3<K>, dim3(nb), dim3(256), 0, st, a);
+    } else {
+        const int nb = persistent_blocks(k_render<K>, num_cu, total);
+        hipLaunchKernelGGL(k_render<K>, dim3(nb), dim3(256), 0, st, a);
+    }
     return hipGetLastError();
 }
 
@@ -243,6 +257,7 @@ hipError_t launch_render_backward_stored(const RenderArgs &a, const RenderWS &w,
     case 2: return go_render_bwd<2>(b, num_cu, st);
     case 4: return go_render_bwd<4>(b, num_cu, st);
     case 8: return go_render_bwd<8>(b, num_cu, st);
+    case 12: return go_render_bwd<12>(b, num_cu, st);
     case 16: return go_render_bwd<16>(b, num_cu, st);
     case 32: return go_render_bwd<32>(b, num_cu, st);
     default: return hipErrorInvalidValue;
@@ -332,6 +347,7 @@ hipError_t launch_render(const RenderArgs &a, const RenderWS &w, int k, int num_
     case 2: e = go_render<2>(a, num_cu, st); break;
     case 4: e = go_render<4>(a, num_cu, st); break;
     case 8: e = go_render<8>(a, num_cu, st); break;
+    case 12: e = go_render<12>(a, num_cu, st); break;
     case 16: e = go_render<16>(a, num_cu, st); break;
     case 32: e = go_render<32>(a, num_cu, st); break;
     default: return hipErrorInvalidValue;
@@ -354,6 +370,7 @@ hipError_t launch_render_backward(const RenderArgs &a, const RenderWS &w, int k,
     case 2: return go_render_bwd<2>(a, num_cu, st);
     case 4: return go_render_bwd<4>(a, num_cu, st);
     case 8: return go_render_bwd<8>(a, num_cu, st);
+    case 12: return go_render_bwd<12>(a, num_cu, st);
     case 16: return go_render_bwd<16>(a, num_cu, st);
     case 32: return go_render_bwd<32>(a, num_cu, st);
     default: return hipErrorInvalidValue;

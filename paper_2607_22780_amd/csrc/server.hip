@@ -125,6 +125,15 @@ __global__ void __launch_bounds__(256) GRT_OCCUPANCY
     run_persistent<K>(job, counters, n);
 }
 
+// K = 12 held to 3 wavefronts per SIMD, as the direct render's forward
+template <int K>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+    k_serve_one_w3(RenderArgs a, int64_t r0, int64_t n, unsigned long long *counters)
+{
+    ServeOneJob<K> job(a, r0);
+    run_persistent<K>(job, counters, n);
+}
+
 __global__ void k_serve_reduce(const RenderArgs *a, int64_t npix)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -144,8 +153,13 @@ template <int K>
 static hipError_t go_serve_one(const RenderArgs &a, int64_t r0, int64_t n, unsigned long long *counters, int num_cu,
                                hipStream_t st)
 {
-    const int nb = persistent_blocks(k_serve_one<K>, num_cu, n);
-    hipLaunchKernelGGL(k_serve_one<K>, dim3(nb), dim3(256), 0, st, a, r0, n, counters);
+    if constexpr (K == 12) {
+        const int nb = persistent_blocks(k_serve_one_w3<K>, num_cu, n);
+        hipLaunchKernelGGL(k_serve_one_w3<K>, dim3(nb), dim3(256), 0, st, a, r0, n, counters);
+    } else {
+        const int nb = persistent_blocks(k_serve_one<K>, num_cu, n);
+        hipLaunchKernelGGL(k_serve_one<K>, dim3(nb), dim3(256), 0, st, a, r0, n, counters);
+    }
     return hipGetLastError();
 }
 
@@ -159,6 +173,7 @@ static hipError_t launch_epoch(const ServeEpoch &e, const RenderArgs *one, int64
         switch (k) {
         case 4: return go_serve_one<4>(*one, r0, e.total, e.counters, num_cu, st);
         case 8: return go_serve_one<8>(*one, r0, e.total, e.counters, num_cu, st);
+        case 12: return go_serve_one<12>(*one, r0, e.total, e.counters, num_cu, st);
         case 16: return go_serve_one<16>(*one, r0, e.total, e.counters, num_cu, st);
         default: return hipErrorInvalidValue;
         }
@@ -166,6 +181,7 @@ static hipError_t launch_epoch(const ServeEpoch &e, const RenderArgs *one, int64
     switch (k) {
     case 4: return go_serve<4>(e, num_cu, st);
     case 8: return go_serve<8>(e, num_cu, st);
+    case 12: return go_serve<12>(e, num_cu, st);
     case 16: return go_serve<16>(e, num_cu, st);
     default: return hipErrorInvalidValue;
     }
@@ -487,7 +503,7 @@ void sweep(grt_server *s)
     s->resident.swap(keep);
 }
 
-// An epoch below this many rays also takes rays of the next requests.
+// Requests are batched into one epoch only while it stays within this many rays.
 constexpr int64_t kFillRays = 1 << 20;
 // Launch gate: the estimated time left of the epoch in flight below which the
 // next epoch starts, and the share of its remaining rays below which a next
@@ -514,8 +530,10 @@ bool launch(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other, int64_t bud
     if (other.inflight) {
         int64_t want = 0;
         for (ServerJob *j : run) {
-            if (want >= budget || (want > 0 && want >= kFillRays)) break;
-            want += std::min(j->total - j->next, budget - want);
+            const int64_t take = std::min(j->total - j->next, budget - want);
+            if (want > 0 && want + take > kFillRays) break;
+            want += take;
+            if (want >= budget) break;
         }
         const double left = (double)other.rays - s->rate * (s->now() - other.t_launch);
         const bool tail = left <= s->rate * kTailSeconds;
@@ -525,9 +543,12 @@ bool launch(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other, int64_t bud
     int nch = 0;
     int64_t off = 0;
     for (ServerJob *j : run) {
-        // an epoch is the head request's rest; small epochs are topped up
-        if (off >= budget || (nch > 0 && off >= kFillRays)) break;
+        // an epoch is the head request's rest, topped up with the next
+        // requests while the whole stays small (a small request is never
+        // held back by a large one sharing its epoch)
+        if (off >= budget) break;
         const int64_t take = std::min(j->total - j->next, budget - off);
+        if (nch > 0 && off + take > kFillRays) break;
         E.h_jobs[j->slot] = j->args;
         E.h_chunks[nch].slot = j->slot;
         E.h_chunks[nch].pad = 0;
@@ -677,7 +698,8 @@ int grt_server_create(grt_ctx *ctx, const grt_scene *scene, const grt_server_opt
     *out = nullptr;
     if (opts->max_jobs <= 0 || opts->max_jobs > 256) return sfail(GRT_ERR_INVALID, "max_jobs must be in 1..256");
     if (opts->mem_budget < ((size_t)1 << 20)) return sfail(GRT_ERR_INVALID, "mem_budget below 1 MiB");
-    if (!(opts->k == 4 || opts->k == 8 || opts->k == 16)) return sfail(GRT_ERR_INVALID, "server k must be 4, 8 or 16");
+    if (!(opts->k == 4 || opts->k == 8 || opts->k == 12 || opts->k == 16))
+        return sfail(GRT_ERR_INVALID, "server k must be 4, 8, 12 or 16");
     if (!(opts->t_min >= 0.0f) || !(opts->t_cut >= 0.0f && opts->t_cut < 1.0f))
         return sfail(GRT_ERR_INVALID, "bad t_min / t_cut");
     grt_server *s = new (std::nothrow) grt_server;

@@ -152,6 +152,7 @@ hipError_t launch_trace(const TraceArgs &a, int k, int num_cu, hipStream_t st)
     case 2: return go_trace<2>(a, num_cu, st);
     case 4: return go_trace<4>(a, num_cu, st);
     case 8: return go_trace<8>(a, num_cu, st);
+    case 12: return go_trace<12>(a, num_cu, st);
     case 16: return go_trace<16>(a, num_cu, st);
     case 32: return go_trace<32>(a, num_cu, st);
     default: return hipErrorInvalidValue;
@@ -168,6 +169,7 @@ hipError_t launch_trace_backward(const TraceBwdArgs &a, int k, int num_cu, hipSt
     case 2: return go_trace_bwd<2>(a, num_cu, st);
     case 4: return go_trace_bwd<4>(a, num_cu, st);
     case 8: return go_trace_bwd<8>(a, num_cu, st);
+    case 12: return go_trace_bwd<12>(a, num_cu, st);
     case 16: return go_trace_bwd<16>(a, num_cu, st);
     case 32: return go_trace_bwd<32>(a, num_cu, st);
     default: return hipErrorInvalidValue;

@@ -571,14 +571,17 @@ class RenderMISFn(torch.autograd.Function):
     """c_pbr image as a function of the surfel parameters (Eq. mis)."""
 
     @staticmethod
-    def forward(ctx_, means, scales, quats, opacity, rgb, gctx, env, gb, split, seed, k, alpha_min, hit_cap=0):
+    def forward(ctx_, means, scales, quats, opacity, rgb, gctx, env, gb, split, seed, k, alpha_min, hit_cap=0,
+                k_bwd=None):
         """hit_cap > 0: store up to hit_cap hits per sample in the forward and
-        differentiate from the stored lists; 0: re-traverse in the backward."""
+        differentiate from the stored lists; 0: re-traverse in the backward.
+        k_bwd: k-buffer size of the backward (default k; results do not
+        depend on either)."""
         scene = Scene(gctx, means.detach().contiguous(), scales.detach().contiguous(), quats.detach().contiguous(),
                       opacity.detach().contiguous(), rgb.detach().contiguous(), alpha_min)
         hits = make_hit_list(gb.npix, sum(split), hit_cap, gb.x.device) if hit_cap > 0 else None
         res = render_mis(scene, env, gb, split=split, seed=seed, k=k, save=True, hits=hits, hit_cap=hit_cap)
-        ctx_.scene, ctx_.env, ctx_.gb, ctx_.cfg = scene, env, gb, (split, seed, k, hit_cap)
+        ctx_.scene, ctx_.env, ctx_.gb, ctx_.cfg = scene, env, gb, (split, seed, k if k_bwd is None else k_bwd, hit_cap)
         ctx_.saved_state, ctx_.hits = res["saved"], hits
         return res["rgb"]
 
@@ -588,7 +591,7 @@ class RenderMISFn(torch.autograd.Function):
         g = render_mis_backward(ctx_.scene, ctx_.env, ctx_.gb, g_rgb, ctx_.saved_state, split=split, seed=seed, k=k,
                                 hits=ctx_.hits, hit_cap=hit_cap)
         return (g["means"], g["scales"], g["quats"], g["opacity"], g["rgb"], None, None, None, None, None, None, None,
-                None)
+                None, None)
 
 
 # --------------------------------------------------------------------------

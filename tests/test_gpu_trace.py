@@ -60,7 +60,7 @@ def test_config0_trace_parity(grt_ctx):
     compare(gpu, ref, 64)
 
 
-@pytest.mark.parametrize("k", [1, 2, 4, 8, 32])
+@pytest.mark.parametrize("k", [1, 2, 4, 8, 12, 32])
 def test_results_do_not_depend_on_k(grt_ctx, k):
     """k-buffer size changes rounds, not results: bitwise equal to k = 16."""
     grt, ctx = grt_ctx
