@@ -90,7 +90,8 @@ typedef struct {
 } grt_surfels;
 
 /* Bytes of device workspace a scene of n surfels needs (records, bounding
- * boxes, LBVH nodes, sort buffers).  256-byte aligned pointer required. */
+ * boxes, LBVH nodes, sort buffers, and 64 bytes per surfel in which the
+ * backward passes sum gradients).  256-byte aligned pointer required. */
 size_t grt_scene_workspace_bytes(int64_t n);
 
 /* Create a scene over borrowed surfel arrays and a caller-owned workspace of
@@ -183,7 +184,10 @@ typedef struct {
  * through the traced radiance): accumulates d/d(surfels) of
  *   sum_r grad_rgb[r] . c_rt(r) + grad_T[r] T(r)
  * given the forward's fwd_rgb/fwd_T.  grad_T may be NULL (zero).  Same
- * rays/opts as the forward (the dump fields are ignored). */
+ * rays/opts as the forward (the dump fields are ignored).  The terms are
+ * summed in the scene's workspace (float32 atomics, order not fixed) and then
+ * added to `grads`, so backward passes over one scene must not overlap in
+ * time (queue them on one stream). */
 int grt_trace_backward(const grt_scene *scene, const grt_rays *rays, const grt_trace_opts *opts,
                        const float *fwd_rgb, const float *fwd_T, const float *grad_rgb, const float *grad_T,
                        grt_surfel_grads *grads, void *workspace, size_t ws_bytes, void *stream);
@@ -279,9 +283,11 @@ int grt_render_mis(const grt_scene *scene, const grt_env *env, const grt_gbuffer
 
 /* Backward of grt_render_mis by re-traversal: regenerates every sample from
  * its counter, retraces, and accumulates d/d(surfels) of
- * sum_p grad_rgb[p] . c_pbr(p) into `grads` (atomic adds; the order of the
- * additions is not fixed).  `saved` must come from the forward with the same
- * scene build, environment, G-buffer and opts. */
+ * sum_p grad_rgb[p] . c_pbr(p) into `grads`.  As for grt_trace_backward,
+ * the terms are summed in the scene's workspace (atomic adds in no fixed
+ * order) and backward passes over one scene must not overlap in time.
+ * `saved` must come from the forward with the same scene build,
+ * environment, G-buffer and opts. */
 int grt_render_mis_backward(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g,
                             const grt_mis_opts *opts, const float *grad_rgb, const void *saved,
                             grt_surfel_grads *grads, void *workspace, size_t ws_bytes, void *stream);

@@ -94,6 +94,7 @@ grt::GradPtrs grad_ptrs(const grt_scene *s, const grt_surfel_grads *g)
     grt::GradPtrs p;
     p.means = g->means; p.scales = g->scales; p.quats = g->quats; p.opacity = g->opacity; p.rgb = g->rgb;
     p.order = nullptr;
+    p.acc = s->w.acc;
     p.p_scales = s->s.scales;
     p.p_quats = s->s.quats;
     return p;
@@ -323,7 +324,10 @@ int grt_trace_backward(const grt_scene *scene, const grt_rays *rays, const grt_t
     if ((rc = check_ws(workspace, ws_bytes, grt_trace_workspace_bytes(rays->n), "trace backward"))) return rc;
     b.f.counters = (unsigned long long *)workspace;
     if ((rc = set_device(scene->ctx))) return rc;
-    hipError_t e = grt::launch_trace_backward(b, opts->k, scene->ctx->num_cu, (hipStream_t)stream);
+    const hipStream_t st = (hipStream_t)stream;
+    hipError_t e = grt::launch_grad_lines_zero(b.g.acc, scene->s.n, st);
+    if (e == hipSuccess) e = grt::launch_trace_backward(b, opts->k, scene->ctx->num_cu, st);
+    if (e == hipSuccess) e = grt::launch_grad_lines_apply(b.g, scene->s.n, st);
     if (e != hipSuccess) return hip_fail(e, "trace backward launch");
     return GRT_OK;
 }
@@ -480,8 +484,12 @@ int grt_render_mis_backward(const grt_scene *scene, const grt_env *env, const gr
     a.rays = w.rays;
     a.order = a.S.n >= 2 ? w.v1 : nullptr;
     if ((rc = set_device(scene->ctx))) return rc;
-    hipError_t e = a.hits ? grt::launch_render_backward_stored(a, w, opts->k, scene->ctx->num_cu, (hipStream_t)stream)
-                          : grt::launch_render_backward(a, w, opts->k, scene->ctx->num_cu, (hipStream_t)stream);
+    const hipStream_t st = (hipStream_t)stream;
+    hipError_t e = grt::launch_grad_lines_zero(a.g.acc, scene->s.n, st);
+    if (e == hipSuccess)
+        e = a.hits ? grt::launch_render_backward_stored(a, w, opts->k, scene->ctx->num_cu, st)
+                   : grt::launch_render_backward(a, w, opts->k, scene->ctx->num_cu, st);
+    if (e == hipSuccess) e = grt::launch_grad_lines_apply(a.g, scene->s.n, st);
     if (e != hipSuccess) return hip_fail(e, "render backward launch");
     return GRT_OK;
 }

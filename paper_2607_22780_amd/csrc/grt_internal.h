@@ -48,6 +48,7 @@ struct SceneWS {
     uint32_t *flags;       // [n-1]
     uint32_t *hist;        // [256 * blocks]
     int32_t *bounds;       // [8]
+    float *acc;            // [n,16] gradient lines of the backward passes
     size_t bytes;
 };
 
@@ -76,6 +77,7 @@ inline SceneWS carve_scene(void *base, int64_t n)
     w.flags = (uint32_t *)take(4 * ni);
     w.hist = (uint32_t *)take(4 * sort_hist_words(n));
     w.bounds = (int32_t *)take(4 * 8);
+    w.acc = (float *)take(64 * nn);
     w.bytes = off;
     return w;
 }
@@ -129,6 +131,7 @@ hipError_t launch_trace(const TraceArgs &a, int k, int num_cu, hipStream_t st);
 
 struct GradPtrs {
     float *means, *scales, *quats, *opacity, *rgb;
+    float *acc;  // [n,16] per-surfel lines the kernels accumulate into
     const int32_t *order;  // unused by kernels (ids travel in records)
     const float *p_scales, *p_quats;
 };
@@ -138,6 +141,10 @@ struct TraceBwdArgs {
     GradPtrs g;
 };
 hipError_t launch_trace_backward(const TraceBwdArgs &a, int k, int num_cu, hipStream_t st);
+// Clear the scene's gradient lines (before a backward pass) and add them to
+// the caller's gradient arrays (after it).
+hipError_t launch_grad_lines_zero(float *acc, int64_t n, hipStream_t st);
+hipError_t launch_grad_lines_apply(const GradPtrs &g, int64_t n, hipStream_t st);
 
 // Environment and MIS (render.hip)
 struct EnvDev {

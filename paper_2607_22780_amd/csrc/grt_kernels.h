@@ -59,106 +59,61 @@ struct CompositeVisit {
 
 __device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 
-// LDS tables that sum the 13 gradient terms of hits on the same surfel before
-// they reach global memory (device FP32 atomics run at a fixed rate, so every
-// hit folded in LDS is one global update fewer).  A slot is claimed by
-// compare-and-swap and keeps its surfel until the table is flushed; a surfel
-// that finds no slot within kAggProbe probes goes straight to global atomics.
-// The stored-list backward keeps one table per workgroup, flushed once; the
-// re-traversal backward keeps one per wavefront, flushed at wavefront-uniform
-// points once kWaveFlushAt slots are taken (no workgroup barrier needed).
-constexpr int kAggProbe = 4;
-constexpr uint32_t kAggEmpty = 0xffffffffu;
-template <int S>
-struct GradTable {
-    uint32_t key[S];
-    float val[13][S];
-    int claimed;
+// Gradient terms reach global memory through per-wavefront LDS staging.
+// Device FP32 atomics are limited by the cache lines they touch (one line per
+// lane-atomic when lanes update unrelated surfels), not by the dwords: 16
+// lanes adding to the 16 floats of one line cost what one lane does.  So each
+// surfel owns a 16-float line of a scratch buffer (13 terms used), a hit's
+// terms are staged in LDS where it is composited (any subset of lanes), and a
+// flush has 16 lanes add one staged hit to its line in one instruction, four
+// hits per instruction.  Flushes run at wavefront-uniform points; a step
+// stages at most one hit per lane, so flushing whenever the list could not
+// take another full step keeps it from overflowing.
+constexpr int kStageCap = 128;
+constexpr int kStageStride = 14;  // 13 terms, then the surfel id
+struct WaveStage {
+    float v[kStageCap * kStageStride];
+    int count;
 };
-constexpr int kAggSlots = 1024;
-constexpr int kWaveSlots = 128;
-constexpr int kWaveFlushAt = 96;
-using GradAgg = GradTable<kAggSlots>;   // per workgroup
-using WaveAgg = GradTable<kWaveSlots>;  // per wavefront
 
-__device__ __forceinline__ void grad_global(const GradPtrs &g, uint32_t id, const float (&t)[13])
+// Active lanes: stage one hit each (13 terms of surfel id).
+__device__ __forceinline__ void stage_add(WaveStage *s, uint32_t id, const float (&t)[13])
 {
-    const size_t i = id;
-    unsafeAtomicAdd(&g.means[3 * i], t[0]);
-    unsafeAtomicAdd(&g.means[3 * i + 1], t[1]);
-    unsafeAtomicAdd(&g.means[3 * i + 2], t[2]);
-    unsafeAtomicAdd(&g.scales[2 * i], t[3]);
-    unsafeAtomicAdd(&g.scales[2 * i + 1], t[4]);
-    unsafeAtomicAdd(&g.quats[4 * i], t[5]);
-    unsafeAtomicAdd(&g.quats[4 * i + 1], t[6]);
-    unsafeAtomicAdd(&g.quats[4 * i + 2], t[7]);
-    unsafeAtomicAdd(&g.quats[4 * i + 3], t[8]);
-    unsafeAtomicAdd(&g.opacity[i], t[9]);
-    unsafeAtomicAdd(&g.rgb[3 * i], t[10]);
-    unsafeAtomicAdd(&g.rgb[3 * i + 1], t[11]);
-    unsafeAtomicAdd(&g.rgb[3 * i + 2], t[12]);
-}
-
-// The 13 parameter-gradient terms of one hit into table t, else global.
-template <int S>
-__device__ __forceinline__ bool grad_table_add(GradTable<S> *t, uint32_t id, const float (&v)[13])
-{
-    uint32_t h = (id * 2654435761u) & (S - 1);
-    for (int k = 0; k < kAggProbe; ++k, h = (h + 1) & (S - 1)) {
-        uint32_t cur = t->key[h];
-        if (cur == kAggEmpty) {
-            cur = atomicCAS(&t->key[h], kAggEmpty, id);
-            if (cur == kAggEmpty) atomicAdd(&t->claimed, 1);
-        }
-        if (cur == kAggEmpty || cur == id) {
+    const uint64_t m = __ballot(1);
+    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    volatile int *cnt = &s->count;
+    const int base = __builtin_amdgcn_readfirstlane(*cnt);
+    volatile float *e = &s->v[(base + rank) * kStageStride];
 #pragma unroll
-            for (int c = 0; c < 13; ++c) atomicAdd(&t->val[c][h], v[c]);
-            return true;
-        }
-    }
-    return false;
+    for (int c = 0; c < 13; ++c) e[c] = t[c];
+    reinterpret_cast<volatile uint32_t *>(e)[13] = id;
+    if (rank == 0) *cnt = base + __popcll(m);
 }
 
-// All threads of the table's owner (workgroup or wavefront): clear it.
-template <int S>
-__device__ __forceinline__ void grad_table_clear(GradTable<S> *t, int tid, int nthreads)
+// All 64 lanes of the wavefront: start with an empty list.
+__device__ __forceinline__ void stage_init(WaveStage *s)
 {
-    for (int h = tid; h < S; h += nthreads) {
-        t->key[h] = kAggEmpty;
-#pragma unroll
-        for (int c = 0; c < 13; ++c) t->val[c][h] = 0.0f;
-    }
-    if (tid == 0) t->claimed = 0;
+    if ((threadIdx.x & 63) == 0) *(volatile int *)&s->count = 0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
-// All threads of the owner: move the sums to the gradient arrays, then clear.
-template <int S>
-__device__ __forceinline__ void grad_table_flush(const GradPtrs &g, GradTable<S> *t, int tid, int nthreads)
-{
-    for (int h = tid; h < S; h += nthreads) {
-        const uint32_t id = t->key[h];
-        if (id == kAggEmpty) continue;
-        float v[13];
-#pragma unroll
-        for (int c = 0; c < 13; ++c) {
-            v[c] = t->val[c][h];
-            t->val[c][h] = 0.0f;
-        }
-        t->key[h] = kAggEmpty;
-        grad_global(g, id, v);
-    }
-    if (tid == 0) t->claimed = 0;
-}
-
-// Wavefront-uniform point of the re-traversal backward: flush the wavefront's
-// table once it is mostly taken (all of it when `all`).  The fences make the
-// lanes' LDS writes visible to each other (lanes hand slots over here).
-__device__ __forceinline__ void wave_table_sync(const GradPtrs &g, WaveAgg *t, bool all)
+// All 64 lanes of the wavefront, at a wavefront-uniform point: add the staged
+// hits to their surfels' lines once the list is past half full (all of it
+// when `all`), then empty it.
+__device__ __forceinline__ void stage_sync(float *acc, WaveStage *s, bool all)
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    const int taken = __builtin_amdgcn_readfirstlane(*(volatile int *)&t->claimed);
-    if (taken == 0 || (!all && taken < kWaveFlushAt)) return;
-    grad_table_flush(g, t, threadIdx.x & 63, 64);
+    const int n = __builtin_amdgcn_readfirstlane(*(volatile int *)&s->count);
+    if (n == 0 || (!all && n <= kStageCap - 64)) return;
+    const int lane = threadIdx.x & 63, c = lane & 15;
+    const volatile float *v = s->v;
+    if (c < 13)
+        for (int e = lane >> 4; e < n; e += 4) {
+            const uint32_t id = reinterpret_cast<const volatile uint32_t *>(v)[e * kStageStride + 13];
+            unsafeAtomicAdd(&acc[16 * (size_t)id + c], v[e * kStageStride + c]);
+        }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    if (lane == 0) *(volatile int *)&s->count = 0;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
 }
 
@@ -169,8 +124,7 @@ struct GradVisit {
     const float4 *col;
     float tcut;
     GradPtrs g;
-    GradAgg *agg = nullptr;   // optional per-workgroup aggregation table
-    WaveAgg *wagg = nullptr;  // optional per-wavefront aggregation table
+    WaveStage *stage = nullptr;  // the wavefront's staging list
     float3 o, d, gC, Cf;
     float gT, Tf;
     float T, Td;
@@ -243,8 +197,7 @@ struct GradVisit {
         dqy = (dqy - qy * proj) * iq; dqz = (dqz - qz * proj) * iq;
 
         const float terms[13] = {dmu.x, dmu.y, dmu.z, dsu, dsv, dqw, dqx, dqy, dqz, G * dA, w * gC.x, w * gC.y, w * gC.z};
-        if (!((wagg && grad_table_add(wagg, id, terms)) || (agg && grad_table_add(agg, id, terms))))
-            grad_global(g, id, terms);
+        stage_add(stage, id, terms);
 
         T = T * (1.0f - a);
         Td = trans_step(Td, hit_alpha(op, crho2));

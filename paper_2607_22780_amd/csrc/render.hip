@@ -111,12 +111,11 @@ struct RenderBwdJob {
     GradVisit v;
     int spp;
 
-    __device__ RenderBwdJob(const RenderArgs &a_, WaveAgg *t)
+    __device__ RenderBwdJob(const RenderArgs &a_, WaveStage *t)
         : a(a_), S(a_.S), v(a_.S, a_.tcut, a_.g), spp(a_.nc + a_.ng + a_.ne)
     {
-        v.wagg = t;
-        grad_table_clear(t, threadIdx.x & 63, 64);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        v.stage = t;
+        stage_init(t);
     }
     __device__ __forceinline__ Walker<K, kBwdLdsDepth> &walker() { return w; }
     __device__ __forceinline__ GradVisit &visit() { return v; }
@@ -144,8 +143,8 @@ struct RenderBwdJob {
     }
 
     __device__ __forceinline__ void finish(int64_t) {}
-    __device__ __forceinline__ void after_step() { wave_table_sync(a.g, v.wagg, false); }
-    __device__ __forceinline__ void drain() { wave_table_sync(a.g, v.wagg, true); }
+    __device__ __forceinline__ void after_step() { stage_sync(a.g.acc, v.stage, false); }
+    __device__ __forceinline__ void drain() { stage_sync(a.g.acc, v.stage, true); }
 };
 
 template <int K>
@@ -167,26 +166,33 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 template <int K>
 __global__ void __launch_bounds__(256) GRT_OCCUPANCY k_render_bwd(RenderArgs a)
 {
-    __shared__ WaveAgg tables[4];
-    RenderBwdJob<K> job(a, &tables[(threadIdx.x >> 6) & 3]);
+    __shared__ WaveStage stages[4];
+    RenderBwdJob<K> job(a, &stages[(threadIdx.x >> 6) & 3]);
     run_persistent<K>(job, a.counters, (int64_t)a.H * a.W * (a.nc + a.ng + a.ne));
 }
 
 // Backward from stored hit lists: one thread per sample runs the gradient of
 // its composited hits in order (no traversal).  Samples whose list
-// overflowed are left to the re-traversal kernel.
+// overflowed are left to the re-traversal kernel.  The wavefront steps
+// through the lists together, one hit per lane per step, so that its staged
+// terms are flushed at wavefront-uniform points.
 __global__ void __launch_bounds__(256) k_render_bwd_stored(RenderArgs a)
 {
-    __shared__ GradAgg agg;
-    grad_table_clear(&agg, threadIdx.x, blockDim.x);
-    __syncthreads();
+    __shared__ WaveStage stages[4];
+    WaveStage *stage = &stages[(threadIdx.x >> 6) & 3];
+    stage_init(stage);
     const int spp = a.nc + a.ng + a.ne;
     const int64_t nray = (int64_t)a.H * a.W * spp;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    // samples in traversal order: a workgroup's rays are neighbours and share surfels
+    // samples in traversal order: a wavefront's rays are neighbours and share surfels
     const int64_t r = g < nray ? (a.order ? (int64_t)a.order[g] : g) : 0;
     const uint32_t nh = g < nray && a.S.n > 0 ? a.hits[r] : 0u;
     const float4 r0 = nh ? a.rays[3 * r] : make_float4(0.f, 0.f, 0.f, 0.f);
+    GradVisit v(a.S, a.tcut, a.g);
+    v.stage = stage;
+    uint32_t cnt = 0;
+    float3 x = make_float3(0.f, 0.f, 0.f), d = x;
+    const uint32_t *list = a.hits + nray + r * a.hcap;
     if (nh > 0u && nh <= (uint32_t)a.hcap && r0.w != 0.0f) {
         const int64_t p = r / spp;
         const float inv = 1.0f / (float)spp;
@@ -196,17 +202,17 @@ __global__ void __launch_bounds__(256) k_render_bwd_stored(RenderArgs a)
             const float3 gC = make_float3(r1.x * gp.x, r1.y * gp.y, r1.z * gp.z);
             const float gT = gC.x * r1.w + gC.y * r2.x + gC.z * r2.y;
             const float4 sv = a.saved[r];
-            const float3 x = make_float3(a.x[3 * p], a.x[3 * p + 1], a.x[3 * p + 2]);
-            const float3 d = make_float3(r0.x, r0.y, r0.z);
-            GradVisit v(a.S, a.tcut, a.g);
-            v.agg = &agg;
+            x = make_float3(a.x[3 * p], a.x[3 * p + 1], a.x[3 * p + 2]);
+            d = make_float3(r0.x, r0.y, r0.z);
             v.reset(x, d, gC, gT, make_float3(sv.x, sv.y, sv.z), sv.w);
-            const uint32_t *list = a.hits + nray + r * a.hcap;
-            for (uint32_t i = 0; i < nh; ++i) visit_hit(v, a.S.rec, list[i], x, d);
+            cnt = nh;
         }
     }
-    __syncthreads();
-    grad_table_flush(a.g, &agg, threadIdx.x, blockDim.x);
+    for (uint32_t i = 0; __ballot(i < cnt); ++i) {
+        if (i < cnt) visit_hit(v, a.S.rec, list[i], x, d);
+        stage_sync(a.g.acc, stage, false);
+    }
+    stage_sync(a.g.acc, stage, true);
 }
 
 __global__ void k_render_reduce(int64_t npix, int spp, const float4 *__restrict__ contrib, float *__restrict__ out)

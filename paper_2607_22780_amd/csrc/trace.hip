@@ -11,7 +11,8 @@
 //   dL/dalpha_k = T_k (g_C . c_k) - [g_C . (C - P_k) + g_T T_fin] / (1 - alpha_k)
 // (P_k = colour composited through hit k), then chains alpha -> (o, u, v)
 // -> (s_u, s_v, mu, t_u, t_v, n) -> q, and adds the 13 parameter gradients of
-// the surfel with device atomics.
+// the surfel to its line of the scene's gradient buffer (device atomics,
+// staged per wavefront so that one instruction updates whole lines).
 //
 // Both kernels run persistent wavefronts that fetch rays dynamically.
 #include "grt_internal.h"
@@ -81,11 +82,10 @@ struct TraceBwdJob {
     Walker<K, kBwdLdsDepth> w;
     GradVisit v;
 
-    __device__ TraceBwdJob(const TraceBwdArgs &a_, WaveAgg *t) : a(a_), S(a_.f.S), v(a_.f.S, a_.f.tcut, a_.g)
+    __device__ TraceBwdJob(const TraceBwdArgs &a_, WaveStage *t) : a(a_), S(a_.f.S), v(a_.f.S, a_.f.tcut, a_.g)
     {
-        v.wagg = t;
-        grad_table_clear(t, threadIdx.x & 63, 64);
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        v.stage = t;
+        stage_init(t);
     }
     __device__ __forceinline__ Walker<K, kBwdLdsDepth> &walker() { return w; }
     __device__ __forceinline__ GradVisit &visit() { return v; }
@@ -107,8 +107,8 @@ struct TraceBwdJob {
     }
 
     __device__ __forceinline__ void finish(int64_t) {}
-    __device__ __forceinline__ void after_step() { wave_table_sync(a.g, v.wagg, false); }
-    __device__ __forceinline__ void drain() { wave_table_sync(a.g, v.wagg, true); }
+    __device__ __forceinline__ void after_step() { stage_sync(a.g.acc, v.stage, false); }
+    __device__ __forceinline__ void drain() { stage_sync(a.g.acc, v.stage, true); }
 };
 
 template <int K>
@@ -121,8 +121,8 @@ __global__ void __launch_bounds__(256) GRT_OCCUPANCY k_trace(TraceArgs a)
 template <int K>
 __global__ void __launch_bounds__(256) GRT_OCCUPANCY k_trace_bwd(TraceBwdArgs a)
 {
-    __shared__ WaveAgg tables[4];
-    TraceBwdJob<K> job(a, &tables[(threadIdx.x >> 6) & 3]);
+    __shared__ WaveStage stages[4];
+    TraceBwdJob<K> job(a, &stages[(threadIdx.x >> 6) & 3]);
     run_persistent<K>(job, a.f.counters, a.f.n);
 }
 
@@ -157,6 +157,51 @@ hipError_t launch_trace(const TraceArgs &a, int k, int num_cu, hipStream_t st)
     case 32: return go_trace<32>(a, num_cu, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+// Gradient lines: 16 floats per surfel, terms in the order
+// (mu xyz, s_u, s_v, q wxyz, opacity, rgb).
+__global__ void k_grad_lines_zero(float4 *acc, int64_t n4)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n4) acc[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+}
+
+__global__ void k_grad_lines_apply(GradPtrs g, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float4 *l = reinterpret_cast<const float4 *>(g.acc) + 4 * i;
+    const float4 a0 = l[0], a1 = l[1], a2 = l[2], a3 = l[3];
+    g.means[3 * i] += a0.x;
+    g.means[3 * i + 1] += a0.y;
+    g.means[3 * i + 2] += a0.z;
+    g.scales[2 * i] += a0.w;
+    g.scales[2 * i + 1] += a1.x;
+    g.quats[4 * i] += a1.y;
+    g.quats[4 * i + 1] += a1.z;
+    g.quats[4 * i + 2] += a1.w;
+    g.quats[4 * i + 3] += a2.x;
+    g.opacity[i] += a2.y;
+    g.rgb[3 * i] += a2.z;
+    g.rgb[3 * i + 1] += a2.w;
+    g.rgb[3 * i + 2] += a3.x;
+}
+
+hipError_t launch_grad_lines_zero(float *acc, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    const int64_t n4 = 4 * n;
+    hipLaunchKernelGGL(k_grad_lines_zero, dim3((unsigned)((n4 + 255) / 256)), dim3(256), 0, st,
+                       reinterpret_cast<float4 *>(acc), n4);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_lines_apply(const GradPtrs &g, int64_t n, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_grad_lines_apply, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g, n);
+    return hipGetLastError();
 }
 
 hipError_t launch_trace_backward(const TraceBwdArgs &a, int k, int num_cu, hipStream_t st)
