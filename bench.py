@@ -137,7 +137,7 @@ def serve_inputs(n, rate):
     return reqs, gbs, envs
 
 
-def serve_leg(ctx, scene, k, reqs, gbs, envs, slack=-1.0, epoch=0, detail=False):
+def serve_leg(ctx, scene, k, reqs, gbs, envs, slack=-1.0, epoch=0, detail=False, share=-1.0):
     """The persistent batched server versus one launch per request (upload,
     table build, render, copy back, in arrival order), on the same requests
     replayed at their arrival times and then all at once."""
@@ -156,8 +156,9 @@ def serve_leg(ctx, scene, k, reqs, gbs, envs, slack=-1.0, epoch=0, detail=False)
     req_srv, req_one = mk(), mk()
     rays = sum(r.rays for r in req_srv)
 
-    def run_server(replay):
-        srv = grt.Server(ctx, scene, mem_budget=48 << 30, max_jobs=16, k=k, slack_per_ray=slack, epoch_rays=epoch)
+    def run_server(replay, share=share):
+        srv = grt.Server(ctx, scene, mem_budget=48 << 30, max_jobs=16, k=k, slack_per_ray=slack, epoch_rays=epoch,
+                         preempt_share=share)
         warm = grt.Request(pinned[(reqs[0].res, reqs[0].cam)], pin(envs[0]), (1, 1, 1), 1, 1)
         srv.wait(srv.submit(warm))
         t0 = time.perf_counter()
@@ -208,19 +209,29 @@ def serve_leg(ctx, scene, k, reqs, gbs, envs, slack=-1.0, epoch=0, detail=False)
     lat_o, span_o = run_one(True)
     same = all(torch.equal(a.out, b.out) for a, b in zip(req_srv, req_one))
     log("bench: server leg (all at once)")
-    _, burst_s, _ = run_server(False)
+    blat_s, burst_s, bst = run_server(False)
     log("bench: per-request leg (all at once)")
-    _, burst_o = run_one(False)
+    blat_o, burst_o = run_one(False)
+    log("bench: server leg with preemption (replayed arrivals)")
+    plat_s, pspan_s, pst = run_server(True, share=0.25)
     res = {
         "workload": f"room scene resident; {len(reqs)} requests, Poisson {reqs[-1].arrival_s / max(len(reqs) - 1, 1):.3f}"
                     f" s mean gap, res in {{256,512,768,1024}}^2, spp in {{4..64}}, 128x256 env each",
         "rays": rays,
         "server": {"p50_s": round(pct(lat_s, 50), 4), "p99_s": round(pct(lat_s, 99), 4),
+                   "mean_s": round(float(np.mean(lat_s)), 4),
                    "mrays_s_replay": round(rays / span_s / 1e6, 2), "mrays_s_burst": round(rays / burst_s / 1e6, 2),
-                   "epochs": st["epochs"]},
+                   "burst_p50_s": round(pct(blat_s, 50), 4), "burst_p99_s": round(pct(blat_s, 99), 4),
+                   "epochs": st["epochs"], "stopped_epochs": st["stopped"]},
         "one_launch_per_request": {"p50_s": round(pct(lat_o, 50), 4), "p99_s": round(pct(lat_o, 99), 4),
+                                   "mean_s": round(float(np.mean(lat_o)), 4),
                                    "mrays_s_replay": round(rays / span_o / 1e6, 2),
-                                   "mrays_s_burst": round(rays / burst_o / 1e6, 2)},
+                                   "mrays_s_burst": round(rays / burst_o / 1e6, 2),
+                                   "burst_p50_s": round(pct(blat_o, 50), 4), "burst_p99_s": round(pct(blat_o, 99), 4)},
+        "server_preempt_share_0.25": {"p50_s": round(pct(plat_s, 50), 4), "p99_s": round(pct(plat_s, 99), 4),
+                                      "mean_s": round(float(np.mean(plat_s)), 4),
+                                      "mrays_s_replay": round(rays / pspan_s / 1e6, 2),
+                                      "stopped_epochs": pst["stopped"]},
         "images_identical": bool(same),
     }
     if detail:
@@ -242,7 +253,8 @@ def main():
     ap.add_argument("--no-stored", action="store_true", help="skip the stored-hit-list backward leg")
     ap.add_argument("--hit-cap", type=int, default=64, help="hits stored per sample in the stored-list leg")
     ap.add_argument("--serve-requests", type=int, default=32)
-    ap.add_argument("--serve-rate", type=float, default=4.0, help="Poisson arrival rate, requests/s")
+    ap.add_argument("--serve-rate", type=float, default=5.9,
+                    help="Poisson arrival rate, requests/s (5.9: 70%% load, 0.7 over the 0.119 s mean service time of one launch per request)")
     ap.add_argument("--serve-slack", type=float, default=-1.0, help="server deadline seconds per ray (-1: default)")
     ap.add_argument("--serve-epoch", type=int, default=0, help="server rays per epoch (0: default)")
     ap.add_argument("--count-work", action="store_true", help="recount per-ray work with the oracle and exit")

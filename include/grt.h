@@ -305,7 +305,11 @@ int grt_render_mis_backward(const grt_scene *scene, const grt_env *env, const gr
  * so small requests pass large ones while a large one is never starved), and
  * traces the rays of all of them in one persistent trace launch.  Two
  * epochs are in flight at once on two streams, so the waves of the next
- * epoch fill the tail of the current one.  Requests that complete are
+ * epoch fill the tail of the current one.  An epoch of one request's rays
+ * (at least 2,097,152) is stopped early when requests with earlier deadlines
+ * wait, if the work they add ahead of it stays within preempt_share of its
+ * own rays: its waves claim no more rays, and the rest runs after them.
+ * Requests that complete are
  * reduced per pixel and copied back.  A request's image equals
  * grt_render_mis with the same inputs and opts (seed, job) whatever it was
  * mixed with.  The scene must not be rebuilt or destroyed while the server
@@ -318,7 +322,11 @@ int grt_render_mis_backward(const grt_scene *scene, const grt_env *env, const gr
  *                next requests while the epoch stays within 1,048,576 rays.
  * k:             k-buffer size, 4, 8, 12 or 16.  t_min, t_cut as in grt_mis_opts.
  * slack_per_ray: seconds of deadline per ray (0 = arrival order only;
- *                negative = 4e-8, about twice a request's time alone). */
+ *                negative = 4e-8, about twice a request's time alone).
+ * preempt_share: rays that more urgent requests may run ahead of a started
+ *                request by stopping its epochs, as a share of its own rays
+ *                (0 or negative = never stop an epoch).  Stopping lowers the
+ *                mean latency under load and raises the largest ones. */
 typedef struct {
     size_t mem_budget;
     int max_jobs;
@@ -327,6 +335,7 @@ typedef struct {
     float t_min;
     float t_cut;
     double slack_per_ray;
+    double preempt_share;
 } grt_server_opts;
 
 /* A request.  All pointers are HOST memory, borrowed until the request is
@@ -379,8 +388,10 @@ int grt_server_cancel(grt_server *server, uint64_t id);
  * started running (-1 if not yet) and finished (-1 if not yet). */
 int grt_server_job_times(grt_server *server, uint64_t id, double *submit_s, double *start_s, double *done_s);
 
-/* Epochs run, rays traced, and free pool bytes. */
-int grt_server_stats(grt_server *server, uint64_t *epochs, int64_t *rays, size_t *pool_free);
+/* Epochs run, epochs stopped early for a more urgent request (their
+ * unclaimed rays ran in later epochs), rays traced, and free pool bytes.
+ * Any pointer may be NULL. */
+int grt_server_stats(grt_server *server, uint64_t *epochs, uint64_t *stopped, int64_t *rays, size_t *pool_free);
 
 /* Stop the scheduler (after its current epoch), cancel what is left, free
  * the pool. */

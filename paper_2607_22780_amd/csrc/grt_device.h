@@ -526,10 +526,15 @@ struct Walker {
 constexpr int kParts = 8;
 constexpr int kChunk = 64;
 
-__device__ __forceinline__ int64_t part_begin(int64_t total, int q) { return total * q / kParts; }
+__host__ __device__ __forceinline__ int64_t part_begin(int64_t total, int q) { return total * q / kParts; }
 
+// stop: optional flag in host memory; once it reads non-zero, wavefronts
+// claim no further chunks, finish the rays they hold and leave, so the claim
+// counters then say exactly which rays were traced (a prefix of each
+// partition).
 template <int K, class Job>
-__device__ __forceinline__ void run_persistent(Job &job, unsigned long long *counters, int64_t total)
+__device__ __forceinline__ void run_persistent(Job &job, unsigned long long *counters, int64_t total,
+                                               const int *stop = nullptr)
 {
     const int lane = threadIdx.x & 63;
     const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -561,8 +566,13 @@ __device__ __forceinline__ void run_persistent(Job &job, unsigned long long *cou
                 for (;;) {
                     const int64_t pb = part_begin(total, part), pe = part_begin(total, part + 1);
                     unsigned long long got = 0;
+                    int halt = 0;
                     const int leader = __ffsll((long long)idle) - 1;
-                    if (lane == leader) got = atomicAdd(&counters[part], (unsigned long long)kChunk);
+                    if (lane == leader) {
+                        if (stop) halt = __hip_atomic_load(stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                        if (!halt) got = atomicAdd(&counters[part], (unsigned long long)kChunk);
+                    }
+                    if (__shfl(halt, leader, 64)) { exhausted = true; break; }
                     got = __shfl(got, leader, 64);
                     if (pb + (int64_t)got < pe) {
                         pool_next = pb + (int64_t)got;

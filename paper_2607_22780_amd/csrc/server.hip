@@ -20,6 +20,7 @@
 // are done, so no kernel outlives the epoch.
 #include <string.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <deque>
@@ -49,15 +50,16 @@ struct ServeEpoch {
     int nchunks;
     int64_t total;
     unsigned long long *counters;
+    const int *stop;  // preemption flag (host memory) or null
     SceneDev S;
 };
 
-__device__ __forceinline__ int find_chunk(const ServeEpoch &e, int64_t g)
+__device__ __forceinline__ int find_chunk(const ServeChunk *chunks, int nchunks, int64_t g)
 {
-    int lo = 0, hi = e.nchunks - 1;
+    int lo = 0, hi = nchunks - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (e.chunks[mid].offset <= g) lo = mid; else hi = mid - 1;
+        if (chunks[mid].offset <= g) lo = mid; else hi = mid - 1;
     }
     return lo;
 }
@@ -76,7 +78,7 @@ struct ServeJob {
 
     __device__ __forceinline__ bool begin(int64_t g)
     {
-        const ServeChunk ch = e.chunks[find_chunk(e, g)];
+        const ServeChunk ch = e.chunks[find_chunk(e.chunks, e.nchunks, g)];
         a = &e.jobs[ch.slot];
         r = ch.begin + (g - ch.offset);
         if (a->order) r = (int64_t)a->order[r];
@@ -91,26 +93,43 @@ template <int K>
 __global__ void __launch_bounds__(256) GRT_OCCUPANCY k_serve(ServeEpoch e)
 {
     ServeJob<K> job(e);
-    run_persistent<K>(job, e.counters, e.total);
+    run_persistent<K>(job, e.counters, e.total, e.stop);
 }
 
-// An epoch holding a contiguous ray range of one request: the request's
-// arguments travel by value (uniform across the grid, as in a direct render).
+template <int K>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_serve_w3(ServeEpoch e)
+{
+    ServeJob<K> job(e);
+    run_persistent<K>(job, e.counters, e.total, e.stop);
+}
+
+// An epoch holding rays of one request only: its arguments travel by value
+// (uniform across the grid, as in a direct render); its rays are one range
+// of the request's sample order, or a few once a stopped epoch handed some
+// back (then each ray finds its range in the chunk table).
 template <int K>
 struct ServeOneJob {
     const RenderArgs &a;
     SceneDev S;
     ShadeTrace<K> t;
+    const ServeChunk *chunks;
+    int nchunks;
     int64_t r0;
 
     int64_t r;
 
-    __device__ ServeOneJob(const RenderArgs &a_, int64_t r0_) : a(a_), S(a_.S), r0(r0_), r(0) {}
+    __device__ ServeOneJob(const RenderArgs &a_, const ServeChunk *c, int nc, int64_t r0_)
+        : a(a_), S(a_.S), chunks(c), nchunks(nc), r0(r0_), r(0) {}
     __device__ __forceinline__ Walker<K> &walker() { return t.w; }
     __device__ __forceinline__ CompositeVisit &visit() { return t.v; }
     __device__ __forceinline__ bool begin(int64_t g)
     {
-        r = a.order ? (int64_t)a.order[r0 + g] : r0 + g;
+        int64_t q = r0 + g;
+        if (nchunks > 1) {
+            const ServeChunk ch = chunks[find_chunk(chunks, nchunks, g)];
+            q = ch.begin + (g - ch.offset);
+        }
+        r = a.order ? (int64_t)a.order[q] : q;
         return t.begin(a, S, r);
     }
     __device__ __forceinline__ void finish(int64_t) { t.finish(a, r); }    __device__ __forceinline__ void after_step() {}
@@ -119,51 +138,66 @@ struct ServeOneJob {
 
 template <int K>
 __global__ void __launch_bounds__(256) GRT_OCCUPANCY
-    k_serve_one(RenderArgs a, int64_t r0, int64_t n, unsigned long long *counters)
+    k_serve_one(RenderArgs a, const ServeChunk *chunks, int nchunks, int64_t r0, int64_t n,
+                unsigned long long *counters, const int *stop)
 {
-    ServeOneJob<K> job(a, r0);
-    run_persistent<K>(job, counters, n);
+    ServeOneJob<K> job(a, chunks, nchunks, r0);
+    run_persistent<K>(job, counters, n, stop);
 }
 
 // K = 12 held to 3 wavefronts per SIMD, as the direct render's forward
 template <int K>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
-    k_serve_one_w3(RenderArgs a, int64_t r0, int64_t n, unsigned long long *counters)
+    k_serve_one_w3(RenderArgs a, const ServeChunk *chunks, int nchunks, int64_t r0, int64_t n,
+                   unsigned long long *counters, const int *stop)
 {
-    ServeOneJob<K> job(a, r0);
-    run_persistent<K>(job, counters, n);
+    ServeOneJob<K> job(a, chunks, nchunks, r0);
+    run_persistent<K>(job, counters, n, stop);
 }
 
-__global__ void k_serve_reduce(const RenderArgs *a, int64_t npix)
+// counters/total: the claim counters of a preemptible epoch that held the
+// request's last rays; if the epoch was stopped before claiming them all, the
+// request is not complete and the reduction does nothing.
+__global__ void k_serve_reduce(const RenderArgs *a, int64_t npix, const unsigned long long *counters, int64_t total)
 {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= npix) return;
+    if (counters)
+        for (int q = 0; q < kParts; ++q)
+            if ((int64_t)counters[q] < part_begin(total, q + 1) - part_begin(total, q)) return;
     reduce_pixel(p, a->nc + a->ng + a->ne, a->contrib, a->out);
 }
 
 template <int K>
 static hipError_t go_serve(const ServeEpoch &e, int num_cu, hipStream_t st)
 {
-    const int nb = persistent_blocks(k_serve<K>, num_cu, e.total);
-    hipLaunchKernelGGL(k_serve<K>, dim3(nb), dim3(256), 0, st, e);
-    return hipGetLastError();
-}
-
-template <int K>
-static hipError_t go_serve_one(const RenderArgs &a, int64_t r0, int64_t n, unsigned long long *counters, int num_cu,
-                               hipStream_t st)
-{
     if constexpr (K == 12) {
-        const int nb = persistent_blocks(k_serve_one_w3<K>, num_cu, n);
-        hipLaunchKernelGGL(k_serve_one_w3<K>, dim3(nb), dim3(256), 0, st, a, r0, n, counters);
+        const int nb = persistent_blocks(k_serve_w3<K>, num_cu, e.total);
+        hipLaunchKernelGGL(k_serve_w3<K>, dim3(nb), dim3(256), 0, st, e);
     } else {
-        const int nb = persistent_blocks(k_serve_one<K>, num_cu, n);
-        hipLaunchKernelGGL(k_serve_one<K>, dim3(nb), dim3(256), 0, st, a, r0, n, counters);
+        const int nb = persistent_blocks(k_serve<K>, num_cu, e.total);
+        hipLaunchKernelGGL(k_serve<K>, dim3(nb), dim3(256), 0, st, e);
     }
     return hipGetLastError();
 }
 
-// one: the request of a single-request epoch (its chunk 0), else null
+template <int K>
+static hipError_t go_serve_one(const RenderArgs &a, const ServeEpoch &e, int64_t r0, int num_cu, hipStream_t st)
+{
+    if constexpr (K == 12) {
+        const int nb = persistent_blocks(k_serve_one_w3<K>, num_cu, e.total);
+        hipLaunchKernelGGL(k_serve_one_w3<K>, dim3(nb), dim3(256), 0, st, a, e.chunks, e.nchunks, r0, e.total,
+                           e.counters, e.stop);
+    } else {
+        const int nb = persistent_blocks(k_serve_one<K>, num_cu, e.total);
+        hipLaunchKernelGGL(k_serve_one<K>, dim3(nb), dim3(256), 0, st, a, e.chunks, e.nchunks, r0, e.total,
+                           e.counters, e.stop);
+    }
+    return hipGetLastError();
+}
+
+// one: the request when every chunk of the epoch is of that one request, else
+// null; r0: the first ray of chunk 0
 static hipError_t launch_epoch(const ServeEpoch &e, const RenderArgs *one, int64_t r0, int k, int num_cu,
                                hipStream_t st)
 {
@@ -171,10 +205,10 @@ static hipError_t launch_epoch(const ServeEpoch &e, const RenderArgs *one, int64
     if (err != hipSuccess) return err;
     if (one) {
         switch (k) {
-        case 4: return go_serve_one<4>(*one, r0, e.total, e.counters, num_cu, st);
-        case 8: return go_serve_one<8>(*one, r0, e.total, e.counters, num_cu, st);
-        case 12: return go_serve_one<12>(*one, r0, e.total, e.counters, num_cu, st);
-        case 16: return go_serve_one<16>(*one, r0, e.total, e.counters, num_cu, st);
+        case 4: return go_serve_one<4>(*one, e, r0, num_cu, st);
+        case 8: return go_serve_one<8>(*one, e, r0, num_cu, st);
+        case 12: return go_serve_one<12>(*one, e, r0, num_cu, st);
+        case 16: return go_serve_one<16>(*one, e, r0, num_cu, st);
         default: return hipErrorInvalidValue;
         }
     }
@@ -206,7 +240,15 @@ struct ServerJob {
     RenderArgs args{};
     EnvWS env{};
     RenderWS sort{};  // sort keys/values and histogram (counters, rays, contrib unused)
-    int64_t npix = 0, total = 0, next = 0;
+    int64_t npix = 0, total = 0;
+    // rays not yet handed to an epoch: ranges of the request's sample order
+    // (one range, until a stopped epoch hands back what it did not claim)
+    std::deque<std::pair<int64_t, int64_t>> left;
+    int64_t nleft = 0;
+    // with preemption on: rays other requests may still run ahead of it once
+    // it has started; at zero it goes first and its epochs are not stopped
+    int64_t passable = 0;
+    bool started = false;
     int inflight = 0;      // epochs in flight that hold rays of this job
     double deadline = 0;   // scheduling key
     hipEvent_t ready = nullptr;
@@ -289,9 +331,15 @@ struct EpochSlot {
     RenderArgs *d_jobs = nullptr, *h_jobs = nullptr;
     ServeChunk *d_chunks = nullptr, *h_chunks = nullptr;
     unsigned long long *counters = nullptr;
+    unsigned long long *h_counters = nullptr;  // the claim counters, copied back
+    int *stop_h = nullptr;                     // preemption flag (host memory) ...
+    int *stop_d = nullptr;                     // ... and its device address
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
     bool inflight = false;
+    bool preemptible = false;  // one request's rays: may be stopped early
+    bool stopped = false;      // the stop flag was raised
+    int nch = 0;
     int64_t rays = 0;       // rays of the epoch in flight
     double t_launch = 0.0;  // when it was launched (server clock)
     std::vector<uint64_t> members, finishing;
@@ -310,6 +358,7 @@ struct grt_server {
     grt::SceneDev S{};
     grt_server_opts opts{};
     double slack = 0;
+    double share = 0;  // preempt_share in effect
     char *pool = nullptr;
     grt::PoolAlloc alloc;
     std::mutex mu;
@@ -324,11 +373,13 @@ struct grt_server {
     std::vector<int> free_slots;
     hipStream_t copy = nullptr;
     grt::EpochSlot ep[2];
+    int chunk_cap = 0;  // chunk table entries per epoch
     double rate = 5e7;  // traced rays per second, running estimate (launch gate)
     uint64_t next_id = 1;
     grt::Clock::time_point t0;
     // statistics
     uint64_t epochs = 0;
+    uint64_t stopped = 0;  // epochs stopped before claiming all their rays
     int64_t rays_done = 0;
 
     double now() const { return std::chrono::duration<double>(grt::Clock::now() - t0).count(); }
@@ -464,11 +515,44 @@ void admit(grt_server *s, std::vector<uint64_t> &to_upload)
     }
 }
 
+// A stopped epoch has ended: the rays it did not claim (a suffix of each of
+// its partitions) go back, in order, to the front of its request's ranges,
+// and the request is not finishing after all.
+void give_back(grt_server *s, grt::EpochSlot &E)
+{
+    ServerJob &j = s->jobs[E.members[0]];
+    std::vector<std::pair<int64_t, int64_t>> back;
+    for (int q = 0; q < grt::kParts; ++q) {
+        const int64_t pb = grt::part_begin(E.rays, q), pe = grt::part_begin(E.rays, q + 1);
+        const int64_t a = pb + std::min((int64_t)E.h_counters[q], pe - pb);
+        for (int c = 0; c < E.nch && a < pe; ++c) {
+            const int64_t co = E.h_chunks[c].offset, ce = c + 1 < E.nch ? E.h_chunks[c + 1].offset : E.rays;
+            const int64_t lo = std::max(a, co), hi = std::min(pe, ce);
+            if (lo >= hi) continue;
+            const int64_t b0 = E.h_chunks[c].begin + (lo - co), b1 = E.h_chunks[c].begin + (hi - co);
+            if (!back.empty() && back.back().second == b0) back.back().second = b1;
+            else back.push_back({b0, b1});
+        }
+    }
+    if (back.empty()) return;
+    int64_t n = 0;
+    for (auto it = back.rbegin(); it != back.rend(); ++it) {
+        if (!j.left.empty() && j.left.front().first == it->second) j.left.front().first = it->first;
+        else j.left.push_front(*it);
+        n += it->second - it->first;
+    }
+    j.nleft += n;
+    s->rays_done -= n;
+    ++s->stopped;
+    E.finishing.clear();
+}
+
 // An epoch has completed on the device: its finishing jobs are done,
 // cancelled jobs with no epoch left in flight are dropped.
 void retire(grt_server *s, grt::EpochSlot &E)
 {
-    if (E.inflight && E.rays >= (1 << 20)) {
+    if (E.inflight && E.stopped) give_back(s, E);
+    if (E.inflight && !E.stopped && E.rays >= (1 << 20)) {
         const double dt = s->now() - E.t_launch;
         if (dt > 1e-4) s->rate = 0.7 * s->rate + 0.3 * (double)E.rays / dt;
     }
@@ -505,6 +589,11 @@ void sweep(grt_server *s)
 
 // Requests are batched into one epoch only while it stays within this many rays.
 constexpr int64_t kFillRays = 1 << 20;
+// A single-request epoch of at least this many rays can be stopped when a
+// request with an earlier deadline arrives, unless it is estimated to end
+// within kStopSeconds anyway.
+constexpr int64_t kPreemptRays = 1 << 21;
+constexpr double kStopSeconds = 0.015;
 // Launch gate: the estimated time left of the epoch in flight below which the
 // next epoch starts, and the share of its remaining rays below which a next
 // epoch counts as small and starts at once.
@@ -517,20 +606,33 @@ bool launch(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other, int64_t bud
     std::vector<ServerJob *> run;
     for (uint64_t id : s->resident) {
         ServerJob &j = s->jobs[id];
-        if (j.state == kRunning && !j.cancel && j.next < j.total) run.push_back(&j);
+        if (j.state == kRunning && !j.cancel && j.nleft > 0) run.push_back(&j);
     }
     if (run.empty()) return false;
-    // earliest deadline first; the budget goes down the list
-    std::stable_sort(run.begin(), run.end(),
-                     [](const ServerJob *a, const ServerJob *b) { return a->deadline < b->deadline; });
+    // earliest deadline first (protected requests before all others); the
+    // budget goes down the list
+    const bool budgets = s->share > 0.0;
+    auto guarded = [budgets](const ServerJob *j) { return budgets && j->started && j->passable <= 0; };
+    std::stable_sort(run.begin(), run.end(), [&](const ServerJob *a, const ServerJob *b) {
+        const bool pa = guarded(a), pb = guarded(b);
+        return pa != pb ? pa : a->deadline < b->deadline;
+    });
+    // With preemption on, an earlier-deadline request still uploading needs
+    // the CUs for its sampling and sort kernels first: a persistent epoch
+    // would hold them (without it, that request passes at the next epoch).
+    if (budgets && !guarded(run[0]))
+        for (uint64_t id : s->resident) {
+            const ServerJob &u = s->jobs[id];
+            if (u.state == kUploading && !u.cancel && u.deadline < run[0]->deadline) return false;
+        }
     // Launch gate: while the other epoch is in flight, the next one starts
     // only in its tail (so its waves fill the CUs the tail leaves idle), or
     // at once when it is small next to what the other epoch has left (so a
     // small request passes a large one without slowing it noticeably).
-    if (other.inflight) {
+    if (other.inflight && !other.stopped) {
         int64_t want = 0;
         for (ServerJob *j : run) {
-            const int64_t take = std::min(j->total - j->next, budget - want);
+            const int64_t take = std::min(j->nleft, budget - want);
             if (want > 0 && want + take > kFillRays) break;
             want += take;
             if (want >= budget) break;
@@ -546,35 +648,56 @@ bool launch(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other, int64_t bud
         // an epoch is the head request's rest, topped up with the next
         // requests while the whole stays small (a small request is never
         // held back by a large one sharing its epoch)
-        if (off >= budget) break;
-        const int64_t take = std::min(j->total - j->next, budget - off);
+        if (off >= budget || nch >= s->chunk_cap) break;
+        int64_t take = std::min(j->nleft, budget - off);
         if (nch > 0 && off + take > kFillRays) break;
         E.h_jobs[j->slot] = j->args;
-        E.h_chunks[nch].slot = j->slot;
-        E.h_chunks[nch].pad = 0;
-        E.h_chunks[nch].begin = j->next;
-        E.h_chunks[nch].offset = off;
-        ++nch;
-        off += take;
-        j->next += take;
+        while (take > 0 && nch < s->chunk_cap) {
+            std::pair<int64_t, int64_t> &rg = j->left.front();
+            const int64_t n = std::min(take, rg.second - rg.first);
+            E.h_chunks[nch].slot = j->slot;
+            E.h_chunks[nch].pad = 0;
+            E.h_chunks[nch].begin = rg.first;
+            E.h_chunks[nch].offset = off;
+            ++nch;
+            off += n;
+            take -= n;
+            j->nleft -= n;
+            rg.first += n;
+            if (rg.first == rg.second) j->left.pop_front();
+        }
         ++j->inflight;
+        j->started = true;
         E.members.push_back(j->id);
-        if (j->next >= j->total) E.finishing.push_back(j->id);
+        if (j->nleft == 0) E.finishing.push_back(j->id);
     }
+    // started requests this epoch passes are charged for its rays
+    for (ServerJob *j : run)
+        if (j->started && j->nleft > 0 && std::find(E.members.begin(), E.members.end(), j->id) == E.members.end())
+            j->passable -= off;
+    // an epoch of one request's rays may be stopped for a more urgent one
+    E.preemptible = s->share > 0.0 && E.members.size() == 1 && off >= kPreemptRays;
+    E.stopped = false;
+    E.nch = nch;
+    __atomic_store_n(E.stop_h, 0, __ATOMIC_RELEASE);
     grt::ServeEpoch e;
     e.jobs = E.d_jobs;
     e.chunks = E.d_chunks;
     e.nchunks = nch;
     e.total = off;
     e.counters = E.counters;
+    e.stop = E.preemptible ? E.stop_d : nullptr;
     e.S = s->S;
     err = hipMemcpyAsync(E.d_jobs, E.h_jobs, sizeof(grt::RenderArgs) * s->opts.max_jobs, hipMemcpyHostToDevice,
                          E.stream);
     if (err == hipSuccess)
         err = hipMemcpyAsync(E.d_chunks, E.h_chunks, sizeof(grt::ServeChunk) * nch, hipMemcpyHostToDevice, E.stream);
-    const grt::RenderArgs *one = nch == 1 ? &E.h_jobs[E.h_chunks[0].slot] : nullptr;
+    const grt::RenderArgs *one = E.members.size() == 1 ? &E.h_jobs[E.h_chunks[0].slot] : nullptr;
     if (err == hipSuccess)
         err = grt::launch_epoch(e, one, E.h_chunks[0].begin, s->opts.k, s->ctx->num_cu, E.stream);
+    if (err == hipSuccess && E.preemptible)
+        err = hipMemcpyAsync(E.h_counters, E.counters, grt::kParts * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                             E.stream);
     // a finishing job may still have rays in the other epoch
     if (err == hipSuccess && !E.finishing.empty() && other.inflight)
         err = hipStreamWaitEvent(E.stream, other.done, 0);
@@ -582,7 +705,7 @@ bool launch(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other, int64_t bud
         if (err != hipSuccess) break;
         ServerJob &j = s->jobs[id];
         hipLaunchKernelGGL(grt::k_serve_reduce, dim3((unsigned)((j.npix + 255) / 256)), dim3(256), 0, E.stream,
-                           E.d_jobs + j.slot, j.npix);
+                           E.d_jobs + j.slot, j.npix, E.preemptible ? E.counters : nullptr, off);
         err = hipGetLastError();
         if (err == hipSuccess)
             err = hipMemcpyAsync(j.spec.out_rgb, j.args.out, 12 * (size_t)j.npix, hipMemcpyDeviceToHost, E.stream);
@@ -594,6 +717,31 @@ bool launch(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other, int64_t bud
     s->rays_done += off;
     ++s->epochs;
     return true;
+}
+
+// Raise the stop flag of a preemptible epoch in flight when resident
+// requests with earlier deadlines wait (uploading, or ready with rays left),
+// the epoch is not about to end by itself, and the rays they would run ahead
+// of its request fit what that request still lets pass.  The request then
+// is charged for them when they launch.
+void preempt(grt_server *s)
+{
+    for (grt::EpochSlot &E : s->ep) {
+        if (!E.inflight || !E.preemptible || E.stopped) continue;
+        const double left = ((double)E.rays - s->rate * (s->now() - E.t_launch)) / s->rate;
+        if (left < kStopSeconds) continue;
+        ServerJob &J = s->jobs[E.members[0]];
+        int64_t ahead = 0;
+        for (uint64_t id : s->resident) {
+            const ServerJob &j = s->jobs[id];
+            if (j.cancel || j.id == J.id || j.nleft == 0 || j.deadline >= J.deadline) continue;
+            if (j.state != kUploading && j.state != kRunning) continue;
+            ahead += j.nleft;
+        }
+        if (ahead == 0 || ahead > J.passable) continue;
+        __atomic_store_n(E.stop_h, 1, __ATOMIC_RELEASE);
+        E.stopped = true;
+    }
 }
 
 void scheduler(grt_server *s)
@@ -634,6 +782,7 @@ void scheduler(grt_server *s)
             progressed = true;
         }
         sweep(s);
+        preempt(s);
         // fill free epoch slots
         for (int b = 0; b < 2; ++b) {
             grt::EpochSlot &E = s->ep[b];
@@ -674,6 +823,8 @@ void destroy_resources(grt_server *s)
         if (E.counters) (void)hipFree(E.counters);
         if (E.h_jobs) (void)hipHostFree(E.h_jobs);
         if (E.h_chunks) (void)hipHostFree(E.h_chunks);
+        if (E.h_counters) (void)hipHostFree(E.h_counters);
+        if (E.stop_h) (void)hipHostFree(E.stop_h);
         if (E.done) (void)hipEventDestroy(E.done);
         if (E.stream) (void)hipStreamDestroy(E.stream);
     }
@@ -713,15 +864,22 @@ int grt_server_create(grt_ctx *ctx, const grt_scene *scene, const grt_server_opt
     s->opts = *opts;
     s->t0 = grt::Clock::now();
     s->slack = opts->slack_per_ray < 0.0 ? 4e-8 : opts->slack_per_ray;
+    s->share = opts->preempt_share < 0.0 ? 0.0 : opts->preempt_share;
+    // a request's rays may come back from stopped epochs in up to 8 ranges
+    // per stop; an epoch takes as many as its table holds, the rest wait
+    s->chunk_cap = opts->max_jobs + 64;
     bool ok = hipSetDevice(ctx->device) == hipSuccess;
     ok = ok && hipMalloc((void **)&s->pool, opts->mem_budget) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) == hipSuccess;
     for (grt::EpochSlot &E : s->ep) {
         ok = ok && hipMalloc((void **)&E.d_jobs, sizeof(grt::RenderArgs) * opts->max_jobs) == hipSuccess;
-        ok = ok && hipMalloc((void **)&E.d_chunks, sizeof(grt::ServeChunk) * opts->max_jobs) == hipSuccess;
+        ok = ok && hipMalloc((void **)&E.d_chunks, sizeof(grt::ServeChunk) * s->chunk_cap) == hipSuccess;
         ok = ok && hipMalloc((void **)&E.counters, grt::kCounterBytes) == hipSuccess;
         ok = ok && hipHostMalloc((void **)&E.h_jobs, sizeof(grt::RenderArgs) * opts->max_jobs) == hipSuccess;
-        ok = ok && hipHostMalloc((void **)&E.h_chunks, sizeof(grt::ServeChunk) * opts->max_jobs) == hipSuccess;
+        ok = ok && hipHostMalloc((void **)&E.h_chunks, sizeof(grt::ServeChunk) * s->chunk_cap) == hipSuccess;
+        ok = ok && hipHostMalloc((void **)&E.h_counters, grt::kCounterBytes) == hipSuccess;
+        ok = ok && hipHostMalloc((void **)&E.stop_h, 64, hipHostMallocCoherent | hipHostMallocMapped) == hipSuccess;
+        ok = ok && hipHostGetDevicePointer((void **)&E.stop_d, E.stop_h, 0) == hipSuccess;
         ok = ok && hipStreamCreateWithFlags(&E.stream, hipStreamNonBlocking) == hipSuccess;
         ok = ok && hipEventCreateWithFlags(&E.done, hipEventDisableTiming) == hipSuccess;
         if (ok) memset(E.h_jobs, 0, sizeof(grt::RenderArgs) * opts->max_jobs);
@@ -759,6 +917,9 @@ int grt_server_submit(grt_server *s, const grt_job *job, uint64_t *id)
     j.bytes = bytes;
     j.npix = (int64_t)job->H * job->W;
     j.total = j.npix * (job->n_cos + job->n_ggx + job->n_env);
+    j.left.assign(1, {0, j.total});
+    j.nleft = j.total;
+    j.passable = (int64_t)(s->share * (double)j.total);
     j.t_submit = s->now();
     j.deadline = j.t_submit + s->slack * (double)j.total;
     s->pending.push_back(j.id);
@@ -826,11 +987,12 @@ int grt_server_job_times(grt_server *s, uint64_t id, double *submit_s, double *s
     return GRT_OK;
 }
 
-int grt_server_stats(grt_server *s, uint64_t *epochs, int64_t *rays, size_t *pool_free)
+int grt_server_stats(grt_server *s, uint64_t *epochs, uint64_t *stopped, int64_t *rays, size_t *pool_free)
 {
     if (!s) return sfail(GRT_ERR_INVALID, "NULL argument");
     std::lock_guard<std::mutex> lk(s->mu);
     if (epochs) *epochs = s->epochs;
+    if (stopped) *stopped = s->stopped;
     if (rays) *rays = s->rays_done;
     if (pool_free) {
         size_t f = 0;

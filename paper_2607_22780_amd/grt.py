@@ -72,7 +72,8 @@ class grt_mis_opts(C.Structure):
 
 class grt_server_opts(C.Structure):
     _fields_ = [("mem_budget", C.c_size_t), ("max_jobs", C.c_int), ("epoch_rays", C.c_int64), ("k", C.c_int),
-                ("t_min", C.c_float), ("t_cut", C.c_float), ("slack_per_ray", C.c_double)]
+                ("t_min", C.c_float), ("t_cut", C.c_float), ("slack_per_ray", C.c_double),
+                ("preempt_share", C.c_double)]
 
 
 class grt_job(C.Structure):
@@ -118,7 +119,7 @@ SIGNATURES = {
     "grt_server_wait": (C.c_int, [VP, C.c_uint64, C.c_double]),
     "grt_server_cancel": (C.c_int, [VP, C.c_uint64]),
     "grt_server_job_times": (C.c_int, [VP, C.c_uint64, P(C.c_double), P(C.c_double), P(C.c_double)]),
-    "grt_server_stats": (C.c_int, [VP, P(C.c_uint64), P(C.c_int64), P(C.c_size_t)]),
+    "grt_server_stats": (C.c_int, [VP, P(C.c_uint64), P(C.c_uint64), P(C.c_int64), P(C.c_size_t)]),
     "grt_server_destroy": (C.c_int, [VP]),
 }
 OPTIONAL = {}
@@ -631,9 +632,9 @@ def grt_server_job_times(server, jid: int):
 
 
 def grt_server_stats(server):
-    e, r, f = C.c_uint64(), C.c_int64(), C.c_size_t()
-    _check(load_library().grt_server_stats(server, C.byref(e), C.byref(r), C.byref(f)))
-    return dict(epochs=e.value, rays=r.value, pool_free=f.value)
+    e, st, r, f = C.c_uint64(), C.c_uint64(), C.c_int64(), C.c_size_t()
+    _check(load_library().grt_server_stats(server, C.byref(e), C.byref(st), C.byref(r), C.byref(f)))
+    return dict(epochs=e.value, stopped=st.value, rays=r.value, pool_free=f.value)
 
 
 def grt_server_destroy(server):
@@ -670,10 +671,10 @@ class Server:
     """Owns a grt_server over a built scene; submit Requests, wait, read times."""
 
     def __init__(self, ctx: Context, scene: Scene, mem_budget: int, max_jobs: int = 16, epoch_rays: int = 0, k=8,
-                 t_min=1e-3, t_cut=1e-3, slack_per_ray=-1.0):
+                 t_min=1e-3, t_cut=1e-3, slack_per_ray=-1.0, preempt_share=-1.0):
         self.ctx, self.scene = ctx, scene
         self.opts = grt_server_opts(int(mem_budget), int(max_jobs), int(epoch_rays), int(k), float(t_min),
-                                    float(t_cut), float(slack_per_ray))
+                                    float(t_cut), float(slack_per_ray), float(preempt_share))
         self.handle = grt_server_create(ctx.handle, scene.handle, self.opts)
         self.requests = {}
 

@@ -131,3 +131,36 @@ def test_small_request_overtakes_large(setup):
     assert srv.wait(b) == 0 and srv.wait(a) == 0
     assert srv.times(b)[2] < srv.times(a)[2]
     srv.close()
+
+
+def test_urgent_requests_stop_a_large_epoch(setup):
+    """A single-request epoch is stopped when more urgent requests arrive; the
+    rays it did not claim run in later epochs (possibly stopped again), and
+    every image still equals the direct render bit for bit."""
+    import time
+    grt, ctx, scene = setup
+    big_in = (W.gbuffer1(512, 512, seed=3), W.envmap(32, 64), (32, 16, 16), 5, 5)
+    small_in = [(W.gbuffer1(24, 24, seed=3, cam_stream=20 + i), W.envmap(32, 64, seed=3 + i), (4, 2, 2), 6 + i, 6 + i)
+                for i in range(3)]
+    srv = grt.Server(ctx, scene, mem_budget=1 << 32, max_jobs=8, preempt_share=0.25)
+    big = grt.Request(*big_in)
+    a = srv.submit(big)
+    t0 = time.time()
+    while 0 <= srv.poll(a) < 2 and time.time() - t0 < 60:
+        time.sleep(1e-4)
+    assert srv.poll(a) == 2
+    smalls = [grt.Request(*x) for x in small_in]
+    ids = []
+    for r in smalls:
+        time.sleep(0.005)
+        ids.append(srv.submit(r))
+    for b in ids:
+        assert srv.wait(b) == 0
+    assert srv.wait(a) == 0
+    assert all(srv.times(b)[2] < srv.times(a)[2] for b in ids)
+    st = srv.stats()
+    srv.close()
+    assert st["stopped"] >= 1
+    np.testing.assert_array_equal(big.out.numpy(), direct(grt, ctx, scene, *big_in))
+    for r, x in zip(smalls, small_in):
+        np.testing.assert_array_equal(r.out.numpy(), direct(grt, ctx, scene, *x))
