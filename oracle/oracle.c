@@ -390,6 +390,58 @@ int orc_trace(int64_t n, const float *means, const float *scales, const float *q
     return 0;
 }
 
+/* Attribute query of one ray per ray (Sec. 3.5.1, Eq. trace_attr, the
+ * Gaussian backend): along the same ordered, cut-off hit list as orc_trace,
+ * the material attributes of the composited surfels averaged with the
+ * normalized blending weights w_k = T_k a_k / sum_j T_j a_j (the weights of
+ * Eq. deferred_maps), and V = the final transmittance (visibility of the
+ * environment, 1 - o_rt).  A surfel's normal n = t_u x t_v enters facing the
+ * ray origin (negated when n . d > 0).  With no composited hit: V = 1 and
+ * every attribute 0.  Outputs (double): V [nr], albedo [nr,3], rough [nr],
+ * metal [nr], normal [nr,3] (the weighted average, not renormalized). */
+int orc_trace_attr(int64_t n, const float *means, const float *scales, const float *quats, const float *opacity,
+                   float alpha_min, const float *albedo, const float *rough, const float *metal,
+                   int64_t nr, const float *orig, const float *dirs, float tmin_s, float tmax_s, float t_cut,
+                   double *outV, double *outA, double *outR, double *outM, double *outN)
+{
+    Scene S;
+    if (scene_init(&S, n, means, scales, quats, opacity, NULL, alpha_min)) return -1;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < nr; ++r) {
+        const float *o = orig + 3 * r, *d = dirs + 3 * r;
+        RayResult R;
+        trace_ray(&S, o, d, tmin_s, tmax_s, t_cut, &R);
+        double T = 1.0, W = 0.0, A[3] = {0, 0, 0}, Rg = 0.0, M = 0.0, N[3] = {0, 0, 0};
+        for (int64_t k = 0; k < R.K; ++k) {
+            int64_t id = R.h[k].id;
+            const Surf64 *sf = &S.s64[id];
+            Geo64 g;
+            geo64(sf, o, d, &g);
+            double w = T * g.alpha;
+            double sgn = g.den > 0.0 ? -1.0 : 1.0;
+            W += w;
+            for (int c = 0; c < 3; ++c) {
+                A[c] += w * (double)albedo[3 * id + c];
+                N[c] += w * sgn * sf->n[c];
+            }
+            Rg += w * (double)rough[id];
+            M += w * (double)metal[id];
+            T *= 1.0 - g.alpha;
+        }
+        double inv = W > 0.0 ? 1.0 / W : 0.0;
+        outV[r] = R.T;
+        for (int c = 0; c < 3; ++c) {
+            outA[3 * r + c] = A[c] * inv;
+            outN[3 * r + c] = N[c] * inv;
+        }
+        outR[r] = Rg * inv;
+        outM[r] = M * inv;
+        free(R.h);
+    }
+    scene_free(&S);
+    return 0;
+}
+
 /* Gradient of sum_r (gC_r . c_rt(r) + gT_r T_fin(r)) w.r.t. the surfels.
  * g13 [n,13] is overwritten (mean 3, scale 2, quat 4, opacity 1, rgb 3). */
 int orc_trace_backward(int64_t n, const float *means, const float *scales, const float *quats,

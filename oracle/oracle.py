@@ -48,6 +48,8 @@ def lib():
         L.orc_render_mis_backward.restype = C.c_int
         L.orc_render_mis_backward.argtypes = ([I64, P, P, P, P, P, F] + [P] * 7 + [C.c_int, C.c_int, P, P, P] +
                                               [C.c_int, C.c_int, C.c_int, C.c_uint64, C.c_uint32, F, F, I64, P, P, P])
+        L.orc_trace_attr.restype = C.c_int
+        L.orc_trace_attr.argtypes = [I64, P, P, P, P, F, P, P, P, I64, P, P, F, F, F, P, P, P, P, P]
         if hasattr(L, "orc_count_work"):
             L.orc_count_work.restype = C.c_int
             L.orc_count_work.argtypes = [I64, P, P, P, P, P, F, F, I64, P, P, F, F, F, P, P, P]
@@ -101,6 +103,26 @@ def trace(s, origins, dirs, t_min=0.0, t_max=np.inf, t_cut=T_CUT, alpha_min=ALPH
     assert rc == 0
     if cap:
         out["ids"] = ids; out["tau"] = tau
+    return out
+
+
+def trace_attr(s, attrs, origins, dirs, t_min=0.0, t_max=np.inf, t_cut=T_CUT, alpha_min=ALPHA_MIN):
+    """Brute-force attribute query Trace_attr(x, w) for every ray (the
+    Gaussian backend): attrs = (albedo [n,3], rough [n], metal [n]).
+
+    Returns dict: V [R] (final transmittance), albedo [R,3], rough [R],
+    metal [R], normal [R,3]: normalized-blending-weight averages over the
+    composited hits (normals facing the ray origin; all 0 when nothing is hit).
+    """
+    means, scales, quats, opacity, _ = _scene(s)
+    alb, rough, metal = (_c(a) for a in attrs)
+    o = _c(origins); d = _c(dirs)
+    R = o.shape[0]
+    out = dict(V=np.zeros(R), albedo=np.zeros((R, 3)), rough=np.zeros(R), metal=np.zeros(R), normal=np.zeros((R, 3)))
+    rc = lib().orc_trace_attr(s.n, _p(means), _p(scales), _p(quats), _p(opacity), alpha_min, _p(alb), _p(rough),
+                              _p(metal), R, _p(o), _p(d), float(t_min), float(t_max), t_cut, _p(out["V"]),
+                              _p(out["albedo"]), _p(out["rough"]), _p(out["metal"]), _p(out["normal"]))
+    assert rc == 0
     return out
 
 
