@@ -180,6 +180,32 @@ typedef struct {
     float *rgb;
 } grt_surfel_grads;
 
+/* Per-surfel material attributes (device, float32, borrowed): albedo [n,3],
+ * roughness [n], metallic [n] -- the attributes a_i, r_i, m_i that the
+ * deferred maps blend (Sec. 3.3, Eq. deferred_maps). */
+typedef struct {
+    const float *albedo;
+    const float *rough;
+    const float *metal;
+} grt_surfel_attrs;
+
+/* Attribute query (Sec. 3.5.1, Eq. trace_attr; the Gaussian backend): for
+ * every ray, the same ordered hits and cut-off as grt_trace, returning
+ *   out_V [n]          visibility of the environment = the final
+ *                      transmittance (grt_trace's out_T, 1 - o_rt);
+ *   out_albedo [n,3], out_rough [n], out_metal [n], out_normal [n,3]
+ *                      the composited surfels' attributes averaged with the
+ *                      normalized blending weights T_k alpha_k / sum_j T_j
+ *                      alpha_j (as in Eq. deferred_maps); each surfel normal
+ *                      n = t_u x t_v enters turned toward the ray origin,
+ *                      and the averaged normal is not renormalized.
+ * A ray with no composited hit returns V = 1 and zero attributes.  Same
+ * rays/opts as grt_trace (sky and the dump fields are ignored); same
+ * workspace (grt_trace_workspace_bytes). */
+int grt_trace_attr(const grt_scene *scene, const grt_rays *rays, const grt_trace_opts *opts,
+                   const grt_surfel_attrs *attrs, float *out_V, float *out_albedo, float *out_rough, float *out_metal,
+                   float *out_normal, void *workspace, size_t ws_bytes, void *stream);
+
 /* Backward of grt_trace by re-traversal (Sec. 3.2: gradients backpropagate
  * through the traced radiance): accumulates d/d(surfels) of
  *   sum_r grad_rgb[r] . c_rt(r) + grad_T[r] T(r)

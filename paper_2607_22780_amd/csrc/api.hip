@@ -310,6 +310,29 @@ int grt_trace(const grt_scene *scene, const grt_rays *rays, const grt_trace_opts
     return GRT_OK;
 }
 
+int grt_trace_attr(const grt_scene *scene, const grt_rays *rays, const grt_trace_opts *opts,
+                   const grt_surfel_attrs *attrs, float *out_V, float *out_albedo, float *out_rough, float *out_metal,
+                   float *out_normal, void *workspace, size_t ws_bytes, void *stream)
+{
+    grt::TraceAttrArgs b;
+    int rc = fill_trace_args(scene, rays, opts, b.f);
+    if (rc) return rc;
+    if (!attrs) return fail(GRT_ERR_INVALID, "attrs is NULL");
+    if (scene->s.n > 0 && (!attrs->albedo || !attrs->rough || !attrs->metal))
+        return fail(GRT_ERR_INVALID, "an attribute array is NULL");
+    if (rays->n > 0 && (!out_V || !out_albedo || !out_rough || !out_metal || !out_normal))
+        return fail(GRT_ERR_INVALID, "an output array is NULL");
+    b.albedo = attrs->albedo; b.rough = attrs->rough; b.metal = attrs->metal;
+    b.out_V = out_V; b.out_albedo = out_albedo; b.out_rough = out_rough; b.out_metal = out_metal;
+    b.out_normal = out_normal;
+    if ((rc = check_ws(workspace, ws_bytes, grt_trace_workspace_bytes(rays->n), "trace_attr"))) return rc;
+    b.f.counters = (unsigned long long *)workspace;
+    if ((rc = set_device(scene->ctx))) return rc;
+    hipError_t e = grt::launch_trace_attr(b, opts->k, scene->ctx->num_cu, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "trace_attr launch");
+    return GRT_OK;
+}
+
 int grt_trace_backward(const grt_scene *scene, const grt_rays *rays, const grt_trace_opts *opts, const float *fwd_rgb,
                        const float *fwd_T, const float *grad_rgb, const float *grad_T, grt_surfel_grads *grads,
                        void *workspace, size_t ws_bytes, void *stream)

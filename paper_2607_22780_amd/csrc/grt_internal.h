@@ -129,6 +129,14 @@ struct TraceArgs {
 };
 hipError_t launch_trace(const TraceArgs &a, int k, int num_cu, hipStream_t st);
 
+// Attribute query over the rays of `f` (its radiance outputs unused).
+struct TraceAttrArgs {
+    TraceArgs f;
+    const float *albedo, *rough, *metal;
+    float *out_V, *out_albedo, *out_rough, *out_metal, *out_normal;
+};
+hipError_t launch_trace_attr(const TraceAttrArgs &a, int k, int num_cu, hipStream_t st);
+
 struct GradPtrs {
     float *means, *scales, *quats, *opacity, *rgb;
     float *acc;  // [n,16] per-surfel lines the kernels accumulate into

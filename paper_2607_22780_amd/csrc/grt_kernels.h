@@ -59,6 +59,55 @@ struct CompositeVisit {
 
 __device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
 
+// Attribute query of a ray (Eq. trace_attr, Gaussian backend): along the same
+// ordered hits and cut-off as the radiance trace, the material attributes of
+// the composited surfels summed with blending weights w = T alpha (Eq.
+// deferred_maps), each normal turned to face the ray origin; the caller
+// normalizes by the summed weight.  T ends as the visibility V of the
+// environment.
+struct AttrVisit {
+    const float4 *rec;
+    const float *albedo, *rough, *metal;  // per surfel id
+    float3 o, d;
+    float tcut;
+    float T, Td, W, R, M;
+    float3 A, N;
+
+    __device__ AttrVisit() {}
+    __device__ AttrVisit(const SceneDev &S, float t_cut, const float *al, const float *ro, const float *me)
+        : rec(S.rec), albedo(al), rough(ro), metal(me), tcut(t_cut) {}
+
+    __device__ __forceinline__ void reset(float3 o_, float3 d_)
+    {
+        o = o_;
+        d = d_;
+        T = 1.0f;
+        Td = 1.0f;
+        W = 0.0f; R = 0.0f; M = 0.0f;
+        A = make_float3(0.f, 0.f, 0.f);
+        N = make_float3(0.f, 0.f, 0.f);
+    }
+
+    __device__ __forceinline__ bool operator()(uint32_t p, uint32_t id, float tau, const float4 r0, const float4 r1,
+                                               const float4 r2, const float4 r3, float crho2)
+    {
+        HitGeo g;
+        value_geo(r0, r1, r2, r3, o, d, g);
+        const float a = r1.w * expf(-0.5f * g.rho2);
+        const float w = T * a;
+        const float wn = g.den > 0.0f ? -w : w;  // normal toward the ray origin
+        const size_t i = id;
+        W += w;
+        A.x += w * albedo[3 * i]; A.y += w * albedo[3 * i + 1]; A.z += w * albedo[3 * i + 2];
+        R += w * rough[i];
+        M += w * metal[i];
+        N.x += wn * r1.x; N.y += wn * r1.y; N.z += wn * r1.z;
+        T = T * (1.0f - a);
+        Td = trans_step(Td, hit_alpha(r1.w, crho2));
+        return Td < tcut;
+    }
+};
+
 // Gradient terms reach global memory through per-wavefront LDS staging.
 // Device FP32 atomics are limited by the cache lines they touch (one line per
 // lane-atomic when lanes update unrelated surfels), not by the dwords: 16

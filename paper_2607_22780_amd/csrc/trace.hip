@@ -118,6 +118,80 @@ __global__ void __launch_bounds__(256) GRT_OCCUPANCY k_trace(TraceArgs a)
     run_persistent<K>(job, a.counters, a.n);
 }
 
+// Attribute query (Eq. trace_attr): the trace's traversal with the attribute
+// payload; outputs the visibility and the normalized-weight attributes.
+template <int K>
+struct TraceAttrJob {
+    const TraceAttrArgs &a;
+    SceneDev S;
+    Walker<K> w;
+    AttrVisit v;
+
+    __device__ TraceAttrJob(const TraceAttrArgs &a_)
+        : a(a_), S(a_.f.S), v(a_.f.S, a_.f.tcut, a_.albedo, a_.rough, a_.metal) {}
+    __device__ __forceinline__ Walker<K> &walker() { return w; }
+    __device__ __forceinline__ AttrVisit &visit() { return v; }
+
+    __device__ __forceinline__ bool begin(int64_t r)
+    {
+        const float3 o = make_float3(a.f.o[3 * r], a.f.o[3 * r + 1], a.f.o[3 * r + 2]);
+        const float3 d = make_float3(a.f.d[3 * r], a.f.d[3 * r + 1], a.f.d[3 * r + 2]);
+        const float tmin = a.f.tmin_a ? a.f.tmin_a[r] : a.f.tmin;
+        const float tmax = a.f.tmax_a ? a.f.tmax_a[r] : a.f.tmax;
+        v.reset(o, d);
+        w.start(S, o, d, tmin, tmax);
+        if (S.n <= 0) {
+            finish(r);
+            return false;
+        }
+        return true;
+    }
+
+    __device__ __forceinline__ void finish(int64_t r)
+    {
+        const float inv = v.W > 0.0f ? 1.0f / v.W : 0.0f;
+        a.out_V[r] = v.T;
+        a.out_albedo[3 * r] = v.A.x * inv; a.out_albedo[3 * r + 1] = v.A.y * inv; a.out_albedo[3 * r + 2] = v.A.z * inv;
+        a.out_rough[r] = v.R * inv;
+        a.out_metal[r] = v.M * inv;
+        a.out_normal[3 * r] = v.N.x * inv; a.out_normal[3 * r + 1] = v.N.y * inv; a.out_normal[3 * r + 2] = v.N.z * inv;
+    }
+    __device__ __forceinline__ void after_step() {}
+    __device__ __forceinline__ void drain() {}
+};
+
+template <int K>
+__global__ void __launch_bounds__(256) GRT_OCCUPANCY k_trace_attr(TraceAttrArgs a)
+{
+    TraceAttrJob<K> job(a);
+    run_persistent<K>(job, a.f.counters, a.f.n);
+}
+
+template <int K>
+static hipError_t go_trace_attr(const TraceAttrArgs &a, int num_cu, hipStream_t st)
+{
+    const int nb = persistent_blocks(k_trace_attr<K>, num_cu, a.f.n);
+    hipLaunchKernelGGL(k_trace_attr<K>, dim3(nb), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_attr(const TraceAttrArgs &a, int k, int num_cu, hipStream_t st)
+{
+    if (a.f.n <= 0) return hipSuccess;
+    hipError_t e = launch_zero_counters(a.f.counters, st);
+    if (e != hipSuccess) return e;
+    switch (k) {
+    case 1: return go_trace_attr<1>(a, num_cu, st);
+    case 2: return go_trace_attr<2>(a, num_cu, st);
+    case 4: return go_trace_attr<4>(a, num_cu, st);
+    case 8: return go_trace_attr<8>(a, num_cu, st);
+    case 12: return go_trace_attr<12>(a, num_cu, st);
+    case 16: return go_trace_attr<16>(a, num_cu, st);
+    case 32: return go_trace_attr<32>(a, num_cu, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <int K>
 __global__ void __launch_bounds__(256) GRT_OCCUPANCY k_trace_bwd(TraceBwdArgs a)
 {

@@ -59,6 +59,10 @@ class grt_surfel_grads(C.Structure):
     _fields_ = [("means", VP), ("scales", VP), ("quats", VP), ("opacity", VP), ("rgb", VP)]
 
 
+class grt_surfel_attrs(C.Structure):
+    _fields_ = [("albedo", VP), ("rough", VP), ("metal", VP)]
+
+
 class grt_gbuffer(C.Structure):
     _fields_ = [("H", C.c_int), ("W", C.c_int), ("x", VP), ("n", VP), ("wo", VP), ("albedo", VP), ("rough", VP),
                 ("metal", VP), ("valid", VP)]
@@ -101,6 +105,8 @@ SIGNATURES = {
     "grt_trace": (C.c_int, [VP, P(grt_rays), P(grt_trace_opts), VP, VP, VP, VP, VP, C.c_size_t, VP]),
     "grt_trace_backward": (C.c_int, [VP, P(grt_rays), P(grt_trace_opts), VP, VP, VP, VP, P(grt_surfel_grads), VP,
                                      C.c_size_t, VP]),
+    "grt_trace_attr": (C.c_int, [VP, P(grt_rays), P(grt_trace_opts), P(grt_surfel_attrs), VP, VP, VP, VP, VP, VP,
+                                 C.c_size_t, VP]),
     "grt_env_workspace_bytes": (C.c_size_t, [C.c_int, C.c_int]),
     "grt_env_create": (C.c_int, [VP, VP, C.c_int, C.c_int, VP, C.c_size_t, P(VP)]),
     "grt_env_build": (C.c_int, [VP, VP]),
@@ -242,6 +248,13 @@ def grt_trace_workspace_bytes(n: int) -> int:
 def grt_trace(scene, rays: grt_rays, opts: grt_trace_opts, out_rgb, out_T, out_L, out_nhit, workspace, stream=None):
     _check(load_library().grt_trace(scene, C.byref(rays), C.byref(opts), _ptr(out_rgb), _ptr(out_T), _ptr(out_L),
                                     _ptr(out_nhit), _ptr(workspace), workspace.numel(), _stream(stream)))
+
+
+def grt_trace_attr(scene, rays: grt_rays, opts: grt_trace_opts, attrs: grt_surfel_attrs, out_V, out_albedo, out_rough,
+                   out_metal, out_normal, workspace, stream=None):
+    _check(load_library().grt_trace_attr(scene, C.byref(rays), C.byref(opts), C.byref(attrs), _ptr(out_V),
+                                         _ptr(out_albedo), _ptr(out_rough), _ptr(out_metal), _ptr(out_normal),
+                                         _ptr(workspace), workspace.numel(), _stream(stream)))
 
 
 def grt_trace_backward(scene, rays, opts, fwd_rgb, fwd_T, grad_rgb, grad_T, grads: grt_surfel_grads, workspace,
@@ -434,6 +447,26 @@ def trace(scene: Scene, origins, dirs, t_min=0.0, t_max=float("inf"), k=16, t_cu
     opts = make_trace_opts(k, t_cut, sky, ids, tau)
     ws = _workspace(grt_trace_workspace_bytes(R), dev)
     grt_trace(scene.handle, rays, opts, out["rgb"], out["T"], out["L"], out["nhit"], ws, stream)
+    return out
+
+
+def trace_attr(scene: Scene, albedo, rough, metal, origins, dirs, t_min=0.0, t_max=float("inf"), k=12, t_cut=1e-3,
+               stream=None):
+    """Attribute query (Eq. trace_attr, Gaussian backend) of every ray: dict
+    of V [R] (environment visibility), albedo [R,3], rough [R], metal [R],
+    normal [R,3] (normalized-weight averages over the composited hits)."""
+    dev = origins.device
+    R = origins.shape[0]
+    for a in (albedo, rough, metal):
+        assert a.is_contiguous() and a.dtype == torch.float32 and a.device == dev
+    out = dict(V=torch.empty(R, device=dev), albedo=torch.empty(R, 3, device=dev), rough=torch.empty(R, device=dev),
+               metal=torch.empty(R, device=dev), normal=torch.empty(R, 3, device=dev))
+    rays = make_rays(origins, dirs, t_min, t_max)
+    opts = make_trace_opts(k, t_cut, (0.0, 0.0, 0.0), None, None)
+    attrs = grt_surfel_attrs(_ptr(albedo), _ptr(rough), _ptr(metal))
+    ws = _workspace(grt_trace_workspace_bytes(R), dev)
+    grt_trace_attr(scene.handle, rays, opts, attrs, out["V"], out["albedo"], out["rough"], out["metal"],
+                   out["normal"], ws, stream)
     return out
 
 

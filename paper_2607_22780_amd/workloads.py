@@ -583,6 +583,17 @@ def envmap(H: int = 256, W: int = 512, seed: int = 0, stream: int = 3, config_id
 
 # --- loss target -------------------------------------------------------------
 
+def surfel_materials(n: int, seed: int = 0, config_id: int = 5):
+    """Per-surfel material attributes for the attribute query: albedo
+    U[0,1]^3, roughness U[0.05, 1], metallic Bernoulli(0.3) -- the G-buffer
+    material distribution.  Returns (albedo [n,3], rough [n], metal [n])."""
+    g = rng(config_id, 10 + seed)
+    albedo = g.uniform(0.0, 1.0, (n, 3))
+    rough = g.uniform(0.05, 1.0, n)
+    metal = (g.uniform(0.0, 1.0, n) < 0.3).astype(np.float64)
+    return _f32(albedo), _f32(rough), _f32(metal)
+
+
 def perturbed(s: Surfels, seed: int = 0, sigma: float = 0.05) -> Surfels:
     """Surfels with radiance and opacity perturbed by N(0, sigma^2) noise."""
     g = rng(2 + 100 * seed, 0)
