@@ -399,6 +399,39 @@ int orc_trace(int64_t n, const float *means, const float *scales, const float *q
  * ray origin (negated when n . d > 0).  With no composited hit: V = 1 and
  * every attribute 0.  Outputs (double): V [nr], albedo [nr,3], rough [nr],
  * metal [nr], normal [nr,3] (the weighted average, not renormalized). */
+typedef struct { const float *albedo, *rough, *metal; } Attrs;
+typedef struct { double V, a[3], r, m, n[3]; } AttrOut;
+
+static void attr_of_ray(const Scene *S, const Attrs *at, const float o[3], const float d[3], const RayResult *R,
+                        AttrOut *out)
+{
+    double T = 1.0, W = 0.0, A[3] = {0, 0, 0}, Rg = 0.0, M = 0.0, N[3] = {0, 0, 0};
+    for (int64_t k = 0; k < R->K; ++k) {
+        int64_t id = R->h[k].id;
+        const Surf64 *sf = &S->s64[id];
+        Geo64 g;
+        geo64(sf, o, d, &g);
+        double w = T * g.alpha;
+        double sgn = g.den > 0.0 ? -1.0 : 1.0;
+        W += w;
+        for (int c = 0; c < 3; ++c) {
+            A[c] += w * (double)at->albedo[3 * id + c];
+            N[c] += w * sgn * sf->n[c];
+        }
+        Rg += w * (double)at->rough[id];
+        M += w * (double)at->metal[id];
+        T *= 1.0 - g.alpha;
+    }
+    double inv = W > 0.0 ? 1.0 / W : 0.0;
+    out->V = R->T;
+    for (int c = 0; c < 3; ++c) {
+        out->a[c] = A[c] * inv;
+        out->n[c] = N[c] * inv;
+    }
+    out->r = Rg * inv;
+    out->m = M * inv;
+}
+
 int orc_trace_attr(int64_t n, const float *means, const float *scales, const float *quats, const float *opacity,
                    float alpha_min, const float *albedo, const float *rough, const float *metal,
                    int64_t nr, const float *orig, const float *dirs, float tmin_s, float tmax_s, float t_cut,
@@ -406,36 +439,21 @@ int orc_trace_attr(int64_t n, const float *means, const float *scales, const flo
 {
     Scene S;
     if (scene_init(&S, n, means, scales, quats, opacity, NULL, alpha_min)) return -1;
+    Attrs at = {albedo, rough, metal};
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t r = 0; r < nr; ++r) {
         const float *o = orig + 3 * r, *d = dirs + 3 * r;
         RayResult R;
         trace_ray(&S, o, d, tmin_s, tmax_s, t_cut, &R);
-        double T = 1.0, W = 0.0, A[3] = {0, 0, 0}, Rg = 0.0, M = 0.0, N[3] = {0, 0, 0};
-        for (int64_t k = 0; k < R.K; ++k) {
-            int64_t id = R.h[k].id;
-            const Surf64 *sf = &S.s64[id];
-            Geo64 g;
-            geo64(sf, o, d, &g);
-            double w = T * g.alpha;
-            double sgn = g.den > 0.0 ? -1.0 : 1.0;
-            W += w;
-            for (int c = 0; c < 3; ++c) {
-                A[c] += w * (double)albedo[3 * id + c];
-                N[c] += w * sgn * sf->n[c];
-            }
-            Rg += w * (double)rough[id];
-            M += w * (double)metal[id];
-            T *= 1.0 - g.alpha;
-        }
-        double inv = W > 0.0 ? 1.0 / W : 0.0;
-        outV[r] = R.T;
+        AttrOut q;
+        attr_of_ray(&S, &at, o, d, &R, &q);
+        outV[r] = q.V;
         for (int c = 0; c < 3; ++c) {
-            outA[3 * r + c] = A[c] * inv;
-            outN[3 * r + c] = N[c] * inv;
+            outA[3 * r + c] = q.a[c];
+            outN[3 * r + c] = q.n[c];
         }
-        outR[r] = Rg * inv;
-        outM[r] = M * inv;
+        outR[r] = q.r;
+        outM[r] = q.m;
         free(R.h);
     }
     scene_free(&S);
@@ -732,7 +750,188 @@ typedef struct {
 
 /* Sample j of pixel p: direction, weight f cos / q, incident radiance; and,
  * when traced, the ray's hit list (caller frees R->h). Returns 1 if traced. */
-static int mis_sample(const Scene *S, const Env *E, const MisOpts *op, uint32_t pix, int j,
+/* ------------------------------------------------------------------------ */
+/* Split-sum relighting (Sec. 3.5.1, Eq. relight_splitsum)                   */
+/* ------------------------------------------------------------------------ */
+
+/* The prefiltered representation E of an environment (piecewise constant over
+ * its texels; integrals are sums over texel centres weighted by each texel's
+ * exact solid angle), on a coarse equirectangular grid of PF_H x PF_W texel
+ * centres (same direction convention as the environment):
+ *   E_d(n)    = sum L(l) max(0, n.l) dW / sum max(0, n.l) dW       (diffuse)
+ *   E_s(R, r) = sum L(l) D(h) max(0, R.l) dW / sum D(h) max(0, R.l) dW,
+ *               h = normalize(R + l), D GGX with alpha = r^2       (specular)
+ * at roughness levels r = l / (PF_L - 1), l = 1 .. PF_L - 1; level 0 is the
+ * environment itself.  The DFG table holds, for n.v = mu and roughness r at
+ * LUT_N x LUT_N cell centres, the Schlick split of the specular lobe's
+ * directional albedo (F = 1):
+ *   A = int f_s/F (1 - (1 - v.h)^5) n.l dl,  B = int f_s/F (1 - v.h)^5 n.l dl
+ * integrated over half vectors h distributed as D(h) n.h (midpoint rule on
+ * LUT_Q x LUT_Q points of the inverse GGX distribution and the azimuth). */
+#define PF_H 16
+#define PF_W 32
+#define PF_L 6
+#define LUT_N 32
+#define LUT_Q 256
+
+static void texel_dir(int H, int W, int i, int j, double w[3])
+{
+    double th = ORC_PI * (i + 0.5) / H, ph = 2.0 * ORC_PI * (j + 0.5) / W;
+    w[0] = sin(th) * cos(ph); w[1] = cos(th); w[2] = sin(th) * sin(ph);
+}
+
+static double texel_omega(int H, int W, int i)
+{
+    return 2.0 * ORC_PI / W * (cos(ORC_PI * i / H) - cos(ORC_PI * (i + 1) / H));
+}
+
+int orc_env_prefilter(int H, int W, const float *rgb, double *Ed, double *Es)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int t = 0; t < PF_H * PF_W; ++t) {
+        double nt[3];
+        texel_dir(PF_H, PF_W, t / PF_W, t % PF_W, nt);
+        double sd[3] = {0, 0, 0}, wd = 0.0, ss[PF_L][3], ws[PF_L];
+        for (int l = 0; l < PF_L; ++l) { ss[l][0] = ss[l][1] = ss[l][2] = 0.0; ws[l] = 0.0; }
+        for (int i = 0; i < H; ++i) {
+            double om = texel_omega(H, W, i);
+            for (int j = 0; j < W; ++j) {
+                double lk[3];
+                texel_dir(H, W, i, j, lk);
+                double c = dot3(nt, lk);
+                if (!(c > 0.0)) continue;
+                const float *L = rgb + ((size_t)i * W + j) * 3;
+                double w = c * om;
+                for (int k = 0; k < 3; ++k) sd[k] += w * L[k];
+                wd += w;
+                double h[3] = {nt[0] + lk[0], nt[1] + lk[1], nt[2] + lk[2]};
+                normalize3(h);
+                double ndh = dot3(nt, h);
+                for (int l = 1; l < PF_L; ++l) {
+                    double r = (double)l / (PF_L - 1), a = r * r;
+                    double wl = ggx_D(ndh, a * a) * w;
+                    for (int k = 0; k < 3; ++k) ss[l][k] += wl * L[k];
+                    ws[l] += wl;
+                }
+            }
+        }
+        for (int k = 0; k < 3; ++k) Ed[3 * t + k] = wd > 0.0 ? sd[k] / wd : 0.0;
+        for (int l = 1; l < PF_L; ++l)
+            for (int k = 0; k < 3; ++k)
+                Es[((size_t)(l - 1) * PF_H * PF_W + t) * 3 + k] = ws[l] > 0.0 ? ss[l][k] / ws[l] : 0.0;
+    }
+    return 0;
+}
+
+int orc_dfg_lut(double *lut)
+{
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int i = 0; i < LUT_N; ++i)
+        for (int j = 0; j < LUT_N; ++j) {
+            double mu = (i + 0.5) / LUT_N, r = (j + 0.5) / LUT_N, a = r * r, a2 = a * a;
+            double v[3] = {sqrt(1.0 - mu * mu), 0.0, mu};
+            double A = 0.0, B = 0.0;
+            for (int s = 0; s < LUT_Q; ++s) {
+                double xi = (s + 0.5) / LUT_Q;
+                double c2 = (1.0 - xi) / (1.0 + (a2 - 1.0) * xi);
+                double ct = sqrt(c2), st = sqrt(1.0 - c2 > 0.0 ? 1.0 - c2 : 0.0);
+                for (int t = 0; t < LUT_Q; ++t) {
+                    double ph = 2.0 * ORC_PI * (t + 0.5) / LUT_Q;
+                    double h[3] = {st * cos(ph), st * sin(ph), ct};
+                    double vh = dot3(v, h);
+                    if (!(vh > 0.0)) continue;
+                    double nl = 2.0 * vh * h[2] - v[2];
+                    if (!(nl > 0.0)) continue;
+                    double g = smith_G1(nl, a2) * smith_G1(mu, a2) * vh / (mu * ct);
+                    double x = 1.0 - vh, fc = x * x * x * x * x;
+                    A += g * (1.0 - fc);
+                    B += g * fc;
+                }
+            }
+            lut[2 * (i * LUT_N + j)] = A / (LUT_Q * LUT_Q);
+            lut[2 * (i * LUT_N + j) + 1] = B / (LUT_Q * LUT_Q);
+        }
+    return 0;
+}
+
+/* Bilinear lookup of a PF_H x PF_W direction table (texel centres; wraps in
+ * the azimuth, clamps in the polar angle). */
+static void table_lookup(const double *T, const double w[3], double out[3])
+{
+    double y = w[1] < -1.0 ? -1.0 : (w[1] > 1.0 ? 1.0 : w[1]);
+    double th = acos(y), ph = atan2(w[2], w[0]);
+    if (ph < 0.0) ph += 2.0 * ORC_PI;
+    double x = ph / (2.0 * ORC_PI) * PF_W - 0.5, v = th / ORC_PI * PF_H - 0.5;
+    double fx0 = floor(x);
+    double fx = x - fx0;
+    int j0 = (int)fx0;
+    j0 = ((j0 % PF_W) + PF_W) % PF_W;
+    int j1 = (j0 + 1) % PF_W;
+    if (v < 0.0) v = 0.0;
+    if (v > PF_H - 1) v = PF_H - 1;
+    int i0 = (int)floor(v);
+    if (i0 > PF_H - 2) i0 = PF_H - 2;
+    double fy = v - i0;
+    for (int k = 0; k < 3; ++k) {
+        double a = T[((size_t)i0 * PF_W + j0) * 3 + k], b = T[((size_t)i0 * PF_W + j1) * 3 + k];
+        double c = T[((size_t)(i0 + 1) * PF_W + j0) * 3 + k], d = T[((size_t)(i0 + 1) * PF_W + j1) * 3 + k];
+        out[k] = (1.0 - fy) * ((1.0 - fx) * a + fx * b) + fy * ((1.0 - fx) * c + fx * d);
+    }
+}
+
+typedef struct {
+    Attrs at;
+    const double *Ed, *Es, *lut;
+} Relight;
+
+/* SplitSum(a, r, m, n, E) of the surface a secondary ray met, seen along -w
+ * (Eq. relight_splitsum: diffuse (1 - m) a E_d(n) plus specular
+ * E_s(R, r) (F0 A + B), F0 = 0.04 (1 - m) + m a, R the mirror of -w). */
+static void split_sum(const Env *E, const Relight *rl, const AttrOut *q, const double w[3], double out[3])
+{
+    double nr[3] = {q->n[0], q->n[1], q->n[2]};
+    double nl = sqrt(dot3(nr, nr));
+    double v[3] = {-w[0], -w[1], -w[2]};
+    if (nl > 0.0) { nr[0] /= nl; nr[1] /= nl; nr[2] /= nl; }
+    else { nr[0] = v[0]; nr[1] = v[1]; nr[2] = v[2]; }
+    double ndv = dot3(nr, v);
+    double R[3] = {2.0 * ndv * nr[0] - v[0], 2.0 * ndv * nr[1] - v[1], 2.0 * ndv * nr[2] - v[2]};
+    double mu = ndv < 0.0 ? 0.0 : (ndv > 1.0 ? 1.0 : ndv);
+    double r = q->r < 0.0 ? 0.0 : (q->r > 1.0 ? 1.0 : q->r);
+    double Ld[3], Ls[3], L0[3], L1[3];
+    table_lookup(rl->Ed, nr, Ld);
+    double xl = r * (PF_L - 1);
+    int l0 = (int)floor(xl);
+    if (l0 > PF_L - 2) l0 = PF_L - 2;
+    double tl = xl - l0;
+    if (l0 == 0) env_radiance(E, R, L0);
+    else table_lookup(rl->Es + (size_t)(l0 - 1) * PF_H * PF_W * 3, R, L0);
+    table_lookup(rl->Es + (size_t)l0 * PF_H * PF_W * 3, R, L1);
+    for (int k = 0; k < 3; ++k) Ls[k] = (1.0 - tl) * L0[k] + tl * L1[k];
+    /* DFG: bilinear over cell centres in (mu, r), clamped */
+    double xi = mu * LUT_N - 0.5, yj = r * LUT_N - 0.5;
+    if (xi < 0.0) xi = 0.0;
+    if (xi > LUT_N - 1) xi = LUT_N - 1;
+    if (yj < 0.0) yj = 0.0;
+    if (yj > LUT_N - 1) yj = LUT_N - 1;
+    int i0 = (int)floor(xi), j0 = (int)floor(yj);
+    if (i0 > LUT_N - 2) i0 = LUT_N - 2;
+    if (j0 > LUT_N - 2) j0 = LUT_N - 2;
+    double fi = xi - i0, fj = yj - j0, AB[2];
+    for (int k = 0; k < 2; ++k) {
+        double a = rl->lut[2 * (i0 * LUT_N + j0) + k], b = rl->lut[2 * (i0 * LUT_N + j0 + 1) + k];
+        double c = rl->lut[2 * ((i0 + 1) * LUT_N + j0) + k], d = rl->lut[2 * ((i0 + 1) * LUT_N + j0 + 1) + k];
+        AB[k] = (1.0 - fi) * ((1.0 - fj) * a + fj * b) + fi * ((1.0 - fj) * c + fj * d);
+    }
+    for (int k = 0; k < 3; ++k) {
+        double F0 = 0.04 * (1.0 - q->m) + q->m * q->a[k];
+        out[k] = (1.0 - q->m) * q->a[k] * Ld[k] + Ls[k] * (F0 * AB[0] + AB[1]);
+    }
+}
+
+/* One MIS sample of a pixel; with `rl`, the incident radiance is the
+ * relighting one (Eq. relight_splitsum) instead of c_rt + T L_env. */
+static int mis_sample(const Scene *S, const Env *E, const MisOpts *op, const Relight *rl, uint32_t pix, int j,
                       const double x[3], const double n[3], const double wo[3], const double alb[3],
                       double rough, double metal,
                       double w_out[3], double wt[3], double Li[3], double *q_out, RayResult *R, float df_out[3])
@@ -766,7 +965,15 @@ static int mis_sample(const Scene *S, const Env *E, const MisOpts *op, uint32_t 
     R->mg.texel = (float)texel;
     double Le[3];
     env_radiance(E, w, Le);
-    for (int c = 0; c < 3; ++c) Li[c] = R->C[c] + R->T * Le[c];
+    if (rl) {
+        AttrOut a;
+        attr_of_ray(S, &rl->at, of, df, R, &a);
+        double ss[3] = {0, 0, 0};
+        if (a.V < 1.0) split_sum(E, rl, &a, w, ss);
+        for (int c = 0; c < 3; ++c) Li[c] = a.V * Le[c] + (1.0 - a.V) * ss[c];
+    } else {
+        for (int c = 0; c < 3; ++c) Li[c] = R->C[c] + R->T * Le[c];
+    }
     if (q > 0.0) {
         double f[3];
         brdf(n, wo, w, alb, rough, metal, f);
@@ -797,20 +1004,12 @@ static void load_pixel(const float *gx, const float *gn, const float *gwo, const
  * texel margin being the angle from the sampled direction to the nearest
  * environment texel edge).
  */
-int orc_render_mis(int64_t n, const float *means, const float *scales, const float *quats, const float *opacity,
-                   const float *rgb, float alpha_min,
-                   const float *gx, const float *gn, const float *gwo, const float *galb, const float *grough,
-                   const float *gmetal, const uint8_t *gvalid,
-                   int eH, int eW, const float *env_rgb, const float *marg, const float *cond,
-                   int nc, int ng, int ne, uint64_t seed, uint32_t job, float tmin, float tcut,
-                   int64_t np, const int64_t *pix, double *out,
-                   float *s_dir, double *s_q, double *s_wt, double *s_Li, uint8_t *s_traced, float *s_margin)
+static void shade_pixels(const Scene *S, const Env *E, const MisOpts *op, const Relight *rl,
+                         const float *gx, const float *gn, const float *gwo, const float *galb, const float *grough,
+                         const float *gmetal, const uint8_t *gvalid, int64_t np, const int64_t *pix, double *out,
+                         float *s_dir, double *s_q, double *s_wt, double *s_Li, uint8_t *s_traced, float *s_margin)
 {
-    Scene S;
-    if (scene_init(&S, n, means, scales, quats, opacity, rgb, alpha_min)) return -1;
-    Env E = {eH, eW, env_rgb, marg, cond};
-    MisOpts op = {nc, ng, ne, seed, job, tmin, tcut};
-    int spp = nc + ng + ne;
+    int spp = op->nc + op->ng + op->ne;
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t k = 0; k < np; ++k) {
         int64_t p = pix[k];
@@ -828,7 +1027,7 @@ int orc_render_mis(int64_t n, const float *means, const float *scales, const flo
             R.tstop = INFINITY;
             int traced = 0;
             if (ok) {
-                traced = mis_sample(&S, &E, &op, (uint32_t)p, j, x, nn, wo, alb, grough[p], gmetal[p], w, wt, Li, &q,
+                traced = mis_sample(S, E, op, rl, (uint32_t)p, j, x, nn, wo, alb, grough[p], gmetal[p], w, wt, Li, &q,
                                     &R, df);
                 for (int c = 0; c < 3; ++c) acc[c] += wt[c] * Li[c];
             }
@@ -845,6 +1044,49 @@ int orc_render_mis(int64_t n, const float *means, const float *scales, const flo
         }
         for (int c = 0; c < 3; ++c) out[3 * k + c] = acc[c] / (double)spp;
     }
+}
+
+int orc_render_mis(int64_t n, const float *means, const float *scales, const float *quats, const float *opacity,
+                   const float *rgb, float alpha_min,
+                   const float *gx, const float *gn, const float *gwo, const float *galb, const float *grough,
+                   const float *gmetal, const uint8_t *gvalid,
+                   int eH, int eW, const float *env_rgb, const float *marg, const float *cond,
+                   int nc, int ng, int ne, uint64_t seed, uint32_t job, float tmin, float tcut,
+                   int64_t np, const int64_t *pix, double *out,
+                   float *s_dir, double *s_q, double *s_wt, double *s_Li, uint8_t *s_traced, float *s_margin)
+{
+    Scene S;
+    if (scene_init(&S, n, means, scales, quats, opacity, rgb, alpha_min)) return -1;
+    Env E = {eH, eW, env_rgb, marg, cond};
+    MisOpts op = {nc, ng, ne, seed, job, tmin, tcut};
+    shade_pixels(&S, &E, &op, NULL, gx, gn, gwo, galb, grough, gmetal, gvalid, np, pix, out, s_dir, s_q, s_wt, s_Li,
+                 s_traced, s_margin);
+    scene_free(&S);
+    return 0;
+}
+
+/* Relighting (Sec. 3.5.1): the same MIS estimator, with the incident
+ * radiance of Eq. relight_splitsum -- V L_env(w) + (1 - V) SplitSum of the
+ * attributes the ray's query returns -- from the environment's prefiltered
+ * tables Ed, Es (orc_env_prefilter) and the DFG table lut (orc_dfg_lut).
+ * Arguments as orc_render_mis, plus the per-surfel attributes. */
+int orc_render_relight(int64_t n, const float *means, const float *scales, const float *quats, const float *opacity,
+                       float alpha_min, const float *s_albedo, const float *s_rough, const float *s_metal,
+                       const float *gx, const float *gn, const float *gwo, const float *galb, const float *grough,
+                       const float *gmetal, const uint8_t *gvalid,
+                       int eH, int eW, const float *env_rgb, const float *marg, const float *cond,
+                       const double *Ed, const double *Es, const double *lut,
+                       int nc, int ng, int ne, uint64_t seed, uint32_t job, float tmin, float tcut,
+                       int64_t np, const int64_t *pix, double *out,
+                       float *s_dir, double *s_q, double *s_wt, double *s_Li, uint8_t *s_traced, float *s_margin)
+{
+    Scene S;
+    if (scene_init(&S, n, means, scales, quats, opacity, NULL, alpha_min)) return -1;
+    Env E = {eH, eW, env_rgb, marg, cond};
+    MisOpts op = {nc, ng, ne, seed, job, tmin, tcut};
+    Relight rl = {{s_albedo, s_rough, s_metal}, Ed, Es, lut};
+    shade_pixels(&S, &E, &op, &rl, gx, gn, gwo, galb, grough, gmetal, gvalid, np, pix, out, s_dir, s_q, s_wt, s_Li,
+                 s_traced, s_margin);
     scene_free(&S);
     return 0;
 }
@@ -876,7 +1118,7 @@ int orc_render_mis_backward(int64_t n, const float *means, const float *scales, 
             float df[3];
             RayResult R;
             R.h = NULL;
-            if (mis_sample(&S, &E, &op, (uint32_t)p, j, x, nn, wo, alb, grough[p], gmetal[p], w, wt, Li, &q, &R, df)) {
+            if (mis_sample(&S, &E, &op, NULL, (uint32_t)p, j, x, nn, wo, alb, grough[p], gmetal[p], w, wt, Li, &q, &R, df)) {
                 /* c_pbr += wt * (C + T L_env) / spp */
                 double gC[3], Le[3];
                 env_radiance(&E, w, Le);

@@ -48,6 +48,15 @@ def lib():
         L.orc_render_mis_backward.restype = C.c_int
         L.orc_render_mis_backward.argtypes = ([I64, P, P, P, P, P, F] + [P] * 7 + [C.c_int, C.c_int, P, P, P] +
                                               [C.c_int, C.c_int, C.c_int, C.c_uint64, C.c_uint32, F, F, I64, P, P, P])
+        L.orc_env_prefilter.restype = C.c_int
+        L.orc_env_prefilter.argtypes = [C.c_int, C.c_int, P, P, P]
+        L.orc_dfg_lut.restype = C.c_int
+        L.orc_dfg_lut.argtypes = [P]
+        L.orc_render_relight.restype = C.c_int
+        L.orc_render_relight.argtypes = ([I64, P, P, P, P, F, P, P, P] + [P] * 7 + [C.c_int, C.c_int, P, P, P] +
+                                         [P, P, P] +
+                                         [C.c_int, C.c_int, C.c_int, C.c_uint64, C.c_uint32, F, F, I64, P, P] +
+                                         [P] * 6)
         L.orc_trace_attr.restype = C.c_int
         L.orc_trace_attr.argtypes = [I64, P, P, P, P, F, P, P, P, I64, P, P, F, F, F, P, P, P, P, P]
         if hasattr(L, "orc_count_work"):
@@ -185,6 +194,64 @@ def render_mis(s, gb, env_rgb, split, seed, pix=None, job=0, t_min=1e-3, t_cut=T
                               _p(cond), nc, ng, ne, seed, job, t_min, t_cut, npx, _p(pix), _p(out),
                               _p(d.get("dir")), _p(d.get("q")), _p(d.get("wt")), _p(d.get("Li")),
                               _p(d.get("traced")), _p(d.get("margins")))
+    assert rc == 0
+    if dump:
+        d["rgb"] = out
+        return d
+    return out
+
+
+PF_H, PF_W, PF_L, LUT_N = 16, 32, 6, 32
+
+
+def env_prefilter(env_rgb):
+    """The prefiltered representation E of an environment (Eq.
+    relight_splitsum): diffuse Ed [16,32,3] and specular Es [5,16,32,3] at
+    roughness 0.2, 0.4, ..., 1.0 (level 0 is the environment itself)."""
+    e = _c(env_rgb)
+    Ed = np.zeros((PF_H, PF_W, 3)); Es = np.zeros((PF_L - 1, PF_H, PF_W, 3))
+    assert lib().orc_env_prefilter(e.shape[0], e.shape[1], _p(e), _p(Ed), _p(Es)) == 0
+    return Ed, Es
+
+
+def dfg_lut():
+    """The split-sum DFG table [32 (n.v), 32 (roughness), 2 (A, B)] at cell centres."""
+    lut = np.zeros((LUT_N, LUT_N, 2))
+    assert lib().orc_dfg_lut(_p(lut)) == 0
+    return lut
+
+
+def render_relight(s, attrs, gb, env_rgb, split, seed, pix=None, job=0, t_min=1e-3, t_cut=T_CUT,
+                   alpha_min=ALPHA_MIN, dump=False, tables=None):
+    """Relit c_pbr of the G-buffer pixels ``pix`` under env_rgb (Sec. 3.5.1):
+    the MIS estimator with L_i = V L_env + (1 - V) SplitSum(attributes the
+    query returns, prefiltered env).  attrs = (albedo [n,3], rough [n], metal
+    [n]); ``tables`` = (Ed, Es, lut) to reuse, else computed here."""
+    nc, ng, ne = split
+    spp = nc + ng + ne
+    means, scales, quats, opacity, _ = _scene(s)
+    alb, rough, metal = (_c(a) for a in attrs)
+    g = _gb(gb)
+    e = _c(env_rgb)
+    marg, cond = env_cdf(e)
+    if tables is None:
+        Ed, Es = env_prefilter(e)
+        lut = dfg_lut()
+    else:
+        Ed, Es, lut = (np.ascontiguousarray(a, np.float64) for a in tables)
+    pix = np.arange(gb.npix, dtype=np.int64) if pix is None else _c(pix, np.int64)
+    npx = len(pix)
+    out = np.zeros((npx, 3))
+    d = {}
+    if dump:
+        d = dict(dir=np.zeros((npx, spp, 3), np.float32), q=np.zeros((npx, spp)), wt=np.zeros((npx, spp, 3)),
+                 Li=np.zeros((npx, spp, 3)), traced=np.zeros((npx, spp), np.uint8),
+                 margins=np.zeros((npx, spp, 5), np.float32))
+    rc = lib().orc_render_relight(s.n, _p(means), _p(scales), _p(quats), _p(opacity), alpha_min, _p(alb), _p(rough),
+                                  _p(metal), *map(_p, g), e.shape[0], e.shape[1], _p(e), _p(marg), _p(cond),
+                                  _p(Ed), _p(Es), _p(lut), nc, ng, ne, seed, job, t_min, t_cut, npx, _p(pix),
+                                  _p(out), _p(d.get("dir")), _p(d.get("q")), _p(d.get("wt")), _p(d.get("Li")),
+                                  _p(d.get("traced")), _p(d.get("margins")))
     assert rc == 0
     if dump:
         d["rgb"] = out
