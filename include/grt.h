@@ -235,6 +235,25 @@ int grt_env_create(grt_ctx *ctx, const float *rgb, int H, int W, void *workspace
 int grt_env_build(grt_env *env, void *stream);
 /* Device pointers to the built tables: marg [H+1], cond [H, W+1]. */
 int grt_env_tables(const grt_env *env, const float **marg, const float **cond);
+
+/* Build the prefiltered representation E of the environment that split-sum
+ * relighting reads (Sec. 3.5.1, Eq. relight_splitsum), in the environment's
+ * workspace.  The map is taken as constant over each texel; every entry is a
+ * ratio of sums over all texels (centre direction l, exact solid angle dW),
+ * accumulated in double and stored as float:
+ *   Ed [16,32,3]   E_d(n) = sum L max(0,n.l) dW / sum max(0,n.l) dW
+ *   Es [5,16,32,3] E_s(R,r) = sum L D(h) max(0,R.l) dW / sum D(h) max(0,R.l) dW,
+ *                  h = normalize(R + l), GGX D with alpha = r^2, at
+ *                  r = 0.2, 0.4, ..., 1.0 (r = 0 is the map itself)
+ * on 16 x 32 direction grids (texel centres, the map's convention), and the
+ * DFG table lut [32 (n.v), 32 (r), 2] at cell centres: the Schlick split
+ *   A = int f_s/F (1 - (1 - v.h)^5) n.l dl,  B = int f_s/F (1 - v.h)^5 n.l dl
+ * of the specular directional albedo, integrated over half vectors drawn as
+ * D(h) n.h on a 256 x 256 midpoint grid.  Needs no grt_env_build. */
+int grt_env_prefilter(grt_env *env, void *stream);
+/* Device pointers to the prefiltered tables (layouts above);
+ * GRT_ERR_NOT_BUILT before grt_env_prefilter. */
+int grt_env_relight_tables(const grt_env *env, const float **Ed, const float **Es, const float **lut);
 int grt_env_destroy(grt_env *env);
 
 /* ------------------------------------------------------------ MIS render */
@@ -317,6 +336,25 @@ int grt_render_mis(const grt_scene *scene, const grt_env *env, const grt_gbuffer
 int grt_render_mis_backward(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g,
                             const grt_mis_opts *opts, const float *grad_rgb, const void *saved,
                             grt_surfel_grads *grads, void *workspace, size_t ws_bytes, void *stream);
+
+/* Relighting under the environment `env` (Sec. 3.5.1): the MIS estimator of
+ * grt_render_mis (same samples, same proposals and pdfs from env's tables),
+ * with the incident radiance of every traced sample replaced by
+ *   L_i = V L_env(w) + (1 - V) SplitSum(a, r, m, n, E)     (Eq. relight_splitsum)
+ * where (V, a, r, m, n) is the attribute query of the sample's ray (as
+ * grt_trace_attr, surfel attributes `attrs`) and, with v = -w, n the
+ * renormalized averaged normal (v if it vanished), R = 2 (n.v) n - v,
+ * mu = clamp(n.v, 0, 1), r clamped to [0, 1]:
+ *   SplitSum = (1 - m) a E_d(n) + E_s(R, r) (F0 A(mu, r) + B(mu, r)),
+ *   F0 = 0.04 (1 - m) + m a,
+ * E_d, E_s bilinear in direction over texel centres (wrapping in azimuth,
+ * clamped in the polar angle), linear between roughness levels, and A, B
+ * bilinear over the DFG table's cell centres (clamped).  env must be built
+ * and prefiltered.  opts as for grt_render_mis (no hit lists, no saved state:
+ * relighting has no backward).  Same workspace as grt_render_mis. */
+int grt_render_relight(const grt_scene *scene, const grt_env *env, const grt_surfel_attrs *attrs,
+                       const grt_gbuffer *g, const grt_mis_opts *opts, float *out_rgb, void *workspace,
+                       size_t ws_bytes, void *stream);
 
 /* ------------------------------------------------------- relighting server */
 

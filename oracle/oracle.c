@@ -862,13 +862,13 @@ static void table_lookup(const double *T, const double w[3], double out[3])
     double th = acos(y), ph = atan2(w[2], w[0]);
     if (ph < 0.0) ph += 2.0 * ORC_PI;
     double x = ph / (2.0 * ORC_PI) * PF_W - 0.5, v = th / ORC_PI * PF_H - 0.5;
+    x = x > -1.0 ? (x < (double)PF_W ? x : (double)PF_W) : -1.0;
     double fx0 = floor(x);
     double fx = x - fx0;
     int j0 = (int)fx0;
     j0 = ((j0 % PF_W) + PF_W) % PF_W;
     int j1 = (j0 + 1) % PF_W;
-    if (v < 0.0) v = 0.0;
-    if (v > PF_H - 1) v = PF_H - 1;
+    v = v > 0.0 ? (v < (double)(PF_H - 1) ? v : (double)(PF_H - 1)) : 0.0;
     int i0 = (int)floor(v);
     if (i0 > PF_H - 2) i0 = PF_H - 2;
     double fy = v - i0;
@@ -896,8 +896,8 @@ static void split_sum(const Env *E, const Relight *rl, const AttrOut *q, const d
     else { nr[0] = v[0]; nr[1] = v[1]; nr[2] = v[2]; }
     double ndv = dot3(nr, v);
     double R[3] = {2.0 * ndv * nr[0] - v[0], 2.0 * ndv * nr[1] - v[1], 2.0 * ndv * nr[2] - v[2]};
-    double mu = ndv < 0.0 ? 0.0 : (ndv > 1.0 ? 1.0 : ndv);
-    double r = q->r < 0.0 ? 0.0 : (q->r > 1.0 ? 1.0 : q->r);
+    double mu = ndv > 0.0 ? (ndv < 1.0 ? ndv : 1.0) : 0.0;
+    double r = q->r > 0.0 ? (q->r < 1.0 ? q->r : 1.0) : 0.0;
     double Ld[3], Ls[3], L0[3], L1[3];
     table_lookup(rl->Ed, nr, Ld);
     double xl = r * (PF_L - 1);

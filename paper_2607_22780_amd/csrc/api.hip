@@ -24,6 +24,7 @@ struct grt_env {
     int H, W;
     grt::EnvWS w;
     bool built;
+    bool prefiltered;
 };
 
 namespace {
@@ -377,6 +378,7 @@ int grt_env_create(grt_ctx *ctx, const float *rgb, int H, int W, void *workspace
     e->H = H; e->W = W;
     e->w = grt::carve_env(workspace, H, W);
     e->built = false;
+    e->prefiltered = false;
     *out = e;
     return GRT_OK;
 }
@@ -389,6 +391,27 @@ int grt_env_build(grt_env *env, void *stream)
     hipError_t e = grt::launch_env_build(env->rgb, env->H, env->W, env->w, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "env build launch");
     env->built = true;
+    return GRT_OK;
+}
+
+int grt_env_prefilter(grt_env *env, void *stream)
+{
+    if (!env) return fail(GRT_ERR_INVALID, "env is NULL");
+    int rc = set_device(env->ctx);
+    if (rc) return rc;
+    hipError_t e = grt::launch_env_prefilter(env->rgb, env->H, env->W, env->w, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "env prefilter launch");
+    env->prefiltered = true;
+    return GRT_OK;
+}
+
+int grt_env_relight_tables(const grt_env *env, const float **Ed, const float **Es, const float **lut)
+{
+    if (!env || !Ed || !Es || !lut) return fail(GRT_ERR_INVALID, "NULL argument");
+    if (!env->prefiltered) return fail(GRT_ERR_NOT_BUILT, "environment not prefiltered");
+    *Ed = env->w.Ed;
+    *Es = env->w.Es;
+    *lut = env->w.lut;
     return GRT_OK;
 }
 
@@ -457,6 +480,37 @@ static int fill_render_args(const grt_scene *scene, const grt_env *env, const gr
         a.hits = o->hit_list;
         a.hcap = o->hit_cap;
     }
+    return GRT_OK;
+}
+
+int grt_render_relight(const grt_scene *scene, const grt_env *env, const grt_surfel_attrs *attrs,
+                       const grt_gbuffer *g, const grt_mis_opts *opts, float *out_rgb, void *workspace, size_t ws_bytes,
+                       void *stream)
+{
+    grt::RenderArgs a;
+    int rc = fill_render_args(scene, env, g, opts, a);
+    if (rc) return rc;
+    if (!env->prefiltered) return fail(GRT_ERR_NOT_BUILT, "relighting needs grt_env_prefilter first");
+    if (!attrs) return fail(GRT_ERR_INVALID, "attrs is NULL");
+    if (scene->s.n > 0 && (!attrs->albedo || !attrs->rough || !attrs->metal))
+        return fail(GRT_ERR_INVALID, "an attribute array is NULL");
+    if ((int64_t)g->H * g->W > 0 && !out_rgb) return fail(GRT_ERR_INVALID, "out_rgb is NULL");
+    if (opts->hit_list) return fail(GRT_ERR_INVALID, "relighting stores no hit lists");
+    a.E.Ed = env->w.Ed; a.E.Es = env->w.Es; a.E.lut = env->w.lut;
+    a.sa_albedo = attrs->albedo; a.sa_rough = attrs->rough; a.sa_metal = attrs->metal;
+    a.out = out_rgb;
+    a.dump = opts->sample_dump;
+    const int spp = opts->n_cos + opts->n_ggx + opts->n_env;
+    if ((rc = check_ws(workspace, ws_bytes, grt_render_workspace_bytes((int64_t)g->H * g->W, spp), "relight")))
+        return rc;
+    const grt::RenderWS w = grt::carve_render(workspace, (int64_t)g->H * g->W * spp);
+    a.counters = w.counters;
+    a.contrib = w.contrib;
+    a.rays = w.rays;
+    a.order = a.S.n >= 2 ? w.v1 : nullptr;
+    if ((rc = set_device(scene->ctx))) return rc;
+    hipError_t e = grt::launch_render_relight(a, w, opts->k, scene->ctx->num_cu, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "relight launch");
     return GRT_OK;
 }
 

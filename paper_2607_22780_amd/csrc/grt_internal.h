@@ -82,10 +82,20 @@ inline SceneWS carve_scene(void *base, int64_t n)
     return w;
 }
 
+// Prefiltered representation of an environment for split-sum relighting:
+// kPfH x kPfW direction tables (texel centres, the environment's convention)
+// of the diffuse and of the specular average at roughness l / (kPfL - 1),
+// l = 1 .. kPfL - 1 (level 0 is the environment itself), and the DFG table
+// [kLutN (n.v)][kLutN (roughness)][A, B] integrated on kLutQ x kLutQ nodes.
+constexpr int kPfH = 16, kPfW = 32, kPfL = 6, kLutN = 32, kLutQ = 256;
+
 struct EnvWS {
     float *marg;   // [H+1]
     float *cond;   // [H,W+1]
     double *rows;  // [H]
+    float *Ed;     // [kPfH, kPfW, 3]
+    float *Es;     // [kPfL - 1, kPfH, kPfW, 3]
+    float *lut;    // [kLutN, kLutN, 2]
     size_t bytes;
 };
 
@@ -101,6 +111,9 @@ inline EnvWS carve_env(void *base, int H, int W)
     w.marg = (float *)take(4 * (size_t)(H + 1));
     w.cond = (float *)take(4 * (size_t)H * (size_t)(W + 1));
     w.rows = (double *)take(8 * (size_t)H);
+    w.Ed = (float *)take(4 * (size_t)kPfH * kPfW * 3);
+    w.Es = (float *)take(4 * (size_t)(kPfL - 1) * kPfH * kPfW * 3);
+    w.lut = (float *)take(4 * (size_t)kLutN * kLutN * 2);
     w.bytes = off;
     return w;
 }
@@ -160,8 +173,10 @@ struct EnvDev {
     const float *rgb;
     const float *marg;
     const float *cond;
+    const float *Ed, *Es, *lut;  // prefiltered tables (relighting), or null
 };
 hipError_t launch_env_build(const float *rgb, int H, int W, const EnvWS &w, hipStream_t st);
+hipError_t launch_env_prefilter(const float *rgb, int H, int W, const EnvWS &w, hipStream_t st);
 
 struct RenderArgs {
     SceneDev S;
@@ -182,6 +197,8 @@ struct RenderArgs {
     uint32_t *hits;         // stored hit lists: counts [nray], then [nray][hcap] (null: none)
     int hcap;
     unsigned long long *counters;
+    // relighting: per-surfel attributes (by id)
+    const float *sa_albedo, *sa_rough, *sa_metal;
     // backward
     const float *grad;
     GradPtrs g;
@@ -220,6 +237,9 @@ inline RenderWS carve_render(void *base, int64_t nray)
 
 // one ray record per sample of the whole G-buffer (sampling only, no trace)
 hipError_t launch_render_gen(const RenderArgs &a, hipStream_t st);
+// Split-sum relighting (needs a.E's prefiltered tables and a.sa_*): the
+// forward render with the attribute query and Eq. relight_splitsum.
+hipError_t launch_render_relight(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st);
 // Order the traced samples for coherent traversal: by direction bin, then by
 // the Morton code of the origin in the scene's root box (untraced last).
 // Sets nothing on the host; a.order must point at w.v1 afterwards.

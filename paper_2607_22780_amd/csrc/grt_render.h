@@ -227,6 +227,89 @@ __device__ __forceinline__ V3 brdf(V3 n, V3 wo, V3 wi, V3 alb, double rough, dou
     return v3(f[0], f[1], f[2]);
 }
 
+// ---------------------------------------------------------------------------
+// Split-sum relighting (Eq. relight_splitsum), in double: lookups of the
+// prefiltered tables and SplitSum(a, r, m, n, E) of a surface seen along -w.
+// ---------------------------------------------------------------------------
+// bilinear over texel centres; wraps in the azimuth, clamps in the polar angle
+__device__ __forceinline__ V3 table_lookup(const float *__restrict__ T, V3 w)
+{
+#pragma clang fp contract(off)
+    double y = w.y < -1.0 ? -1.0 : (w.y > 1.0 ? 1.0 : w.y);
+    double th = acos(y), ph = atan2(w.z, w.x);
+    if (ph < 0.0) ph += 2.0 * kPiD;
+    // clamps written so that a NaN lands on the lower bound (indices stay in range)
+    double x = ph / (2.0 * kPiD) * kPfW - 0.5, v = th / kPiD * kPfH - 0.5;
+    x = x > -1.0 ? (x < (double)kPfW ? x : (double)kPfW) : -1.0;
+    double fx0 = floor(x);
+    double fx = x - fx0;
+    int j0 = (int)fx0;
+    j0 = ((j0 % kPfW) + kPfW) % kPfW;
+    int j1 = (j0 + 1) % kPfW;
+    v = v > 0.0 ? (v < (double)(kPfH - 1) ? v : (double)(kPfH - 1)) : 0.0;
+    int i0 = (int)floor(v);
+    if (i0 > kPfH - 2) i0 = kPfH - 2;
+    double fy = v - i0;
+    double o[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double a = T[(i0 * kPfW + j0) * 3 + k], b = T[(i0 * kPfW + j1) * 3 + k];
+        double c = T[((i0 + 1) * kPfW + j0) * 3 + k], d = T[((i0 + 1) * kPfW + j1) * 3 + k];
+        o[k] = (1.0 - fy) * ((1.0 - fx) * a + fx * b) + fy * ((1.0 - fx) * c + fx * d);
+    }
+    return v3(o[0], o[1], o[2]);
+}
+
+// diffuse (1 - m) a E_d(n) plus specular E_s(R, r) (F0 A + B), F0 = 0.04 (1 - m)
+// + m a; n the query's averaged normal (renormalized; -w if it vanished), v = -w
+__device__ __forceinline__ V3 split_sum(const EnvDev &E, V3 alb, double rough, double metal, V3 nsum, V3 w)
+{
+#pragma clang fp contract(off)
+    V3 v = v3(-w.x, -w.y, -w.z);
+    double nl = sqrt(dot(nsum, nsum));
+    V3 n = nl > 0.0 ? v3(nsum.x / nl, nsum.y / nl, nsum.z / nl) : v;
+    double ndv = dot(n, v);
+    V3 R = v3(2.0 * ndv * n.x - v.x, 2.0 * ndv * n.y - v.y, 2.0 * ndv * n.z - v.z);
+    double mu = ndv > 0.0 ? (ndv < 1.0 ? ndv : 1.0) : 0.0;
+    double r = rough > 0.0 ? (rough < 1.0 ? rough : 1.0) : 0.0;
+    V3 Ld = table_lookup(E.Ed, n);
+    double xl = r * (kPfL - 1);
+    int l0 = (int)floor(xl);
+    if (l0 > kPfL - 2) l0 = kPfL - 2;
+    double tl = xl - l0;
+    V3 L0;
+    if (l0 == 0) {
+        float3 e = env_radiance(E, R);
+        L0 = v3(e.x, e.y, e.z);
+    } else {
+        L0 = table_lookup(E.Es + (size_t)(l0 - 1) * kPfH * kPfW * 3, R);
+    }
+    V3 L1 = table_lookup(E.Es + (size_t)l0 * kPfH * kPfW * 3, R);
+    V3 Ls = v3((1.0 - tl) * L0.x + tl * L1.x, (1.0 - tl) * L0.y + tl * L1.y, (1.0 - tl) * L0.z + tl * L1.z);
+    double xi = mu * kLutN - 0.5, yj = r * kLutN - 0.5;
+    if (xi < 0.0) xi = 0.0;
+    if (xi > kLutN - 1) xi = kLutN - 1;
+    if (yj < 0.0) yj = 0.0;
+    if (yj > kLutN - 1) yj = kLutN - 1;
+    int i0 = (int)floor(xi), j0 = (int)floor(yj);
+    if (i0 > kLutN - 2) i0 = kLutN - 2;
+    if (j0 > kLutN - 2) j0 = kLutN - 2;
+    double fi = xi - i0, fj = yj - j0, AB[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        double a = E.lut[2 * (i0 * kLutN + j0) + k], b = E.lut[2 * (i0 * kLutN + j0 + 1) + k];
+        double c = E.lut[2 * ((i0 + 1) * kLutN + j0) + k], d = E.lut[2 * ((i0 + 1) * kLutN + j0 + 1) + k];
+        AB[k] = (1.0 - fi) * ((1.0 - fj) * a + fj * b) + fi * ((1.0 - fj) * c + fj * d);
+    }
+    double al[3] = {alb.x, alb.y, alb.z}, Lds[3] = {Ld.x, Ld.y, Ld.z}, Lss[3] = {Ls.x, Ls.y, Ls.z}, o[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        double F0 = 0.04 * (1.0 - metal) + metal * al[k];
+        o[k] = (1.0 - metal) * al[k] * Lds[k] + Lss[k] * (F0 * AB[0] + AB[1]);
+    }
+    return v3(o[0], o[1], o[2]);
+}
+
 struct Shade {
     V3 n, wo, alb;
     float3 x;

@@ -71,6 +71,117 @@ hipError_t launch_env_build(const float *rgb, int H, int W, const EnvWS &w, hipS
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Prefiltered environment for split-sum relighting (Eq. relight_splitsum).
+// The environment is piecewise constant over its texels; each table entry is
+// a ratio of sums over all texels (centre direction l, exact solid angle dW)
+// accumulated in double:
+//   E_d(n)    = sum L max(0, n.l) dW / sum max(0, n.l) dW
+//   E_s(R, r) = sum L D(h) max(0, R.l) dW / sum D(h) max(0, R.l) dW,
+//               h = normalize(R + l), GGX D with alpha = r^2.
+// One wavefront per table texel: lanes split the environment's texels, then
+// a fixed-order tree in LDS sums the lanes.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(64) k_env_prefilter(int H, int W, const float *__restrict__ rgb,
+                                                      float *__restrict__ Ed, float *__restrict__ Es)
+{
+#pragma clang fp contract(off)
+    constexpr int kAcc = 4 + 4 * (kPfL - 1);  // diffuse (L, weight), then each level
+    __shared__ double part[kAcc][64];
+    const int t = blockIdx.x, lane = threadIdx.x;
+    const double tth = kPiD * ((t / kPfW) + 0.5) / kPfH, tph = 2.0 * kPiD * ((t % kPfW) + 0.5) / kPfW;
+    const V3 nt = v3(sin(tth) * cos(tph), cos(tth), sin(tth) * sin(tph));
+    double acc[kAcc];
+#pragma unroll
+    for (int q = 0; q < kAcc; ++q) acc[q] = 0.0;
+    for (int k = lane; k < H * W; k += 64) {
+        const int i = k / W, j = k - i * W;
+        const double th = kPiD * (i + 0.5) / H, ph = 2.0 * kPiD * (j + 0.5) / W;
+        const V3 l = v3(sin(th) * cos(ph), cos(th), sin(th) * sin(ph));
+        const double c = dot(nt, l);
+        if (!(c > 0.0)) continue;
+        const double om = 2.0 * kPiD / W * (cos(kPiD * i / H) - cos(kPiD * (i + 1) / H));
+        const float *L = rgb + (size_t)k * 3;
+        const double w = c * om;
+        acc[0] += w * L[0]; acc[1] += w * L[1]; acc[2] += w * L[2]; acc[3] += w;
+        const double ndh = dot(nt, normalized(v3(nt.x + l.x, nt.y + l.y, nt.z + l.z)));
+#pragma unroll
+        for (int lv = 1; lv < kPfL; ++lv) {
+            const double r = (double)lv / (kPfL - 1), al = r * r;
+            const double wl = ggx_D(ndh, al * al) * w;
+            double *s = acc + 4 * lv;
+            s[0] += wl * L[0]; s[1] += wl * L[1]; s[2] += wl * L[2]; s[3] += wl;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < kAcc; ++q) part[q][lane] = acc[q];
+    __syncthreads();
+    for (int half = 32; half > 0; half >>= 1) {
+        if (lane < half)
+            for (int q = 0; q < kAcc; ++q) part[q][lane] += part[q][lane + half];
+        __syncthreads();
+    }
+    if (lane < 3) {
+        Ed[t * 3 + lane] = part[3][0] > 0.0 ? (float)(part[lane][0] / part[3][0]) : 0.0f;
+        for (int lv = 1; lv < kPfL; ++lv) {
+            const double wsum = part[4 * lv + 3][0];
+            Es[((size_t)(lv - 1) * kPfH * kPfW + t) * 3 + lane] = wsum > 0.0 ? (float)(part[4 * lv + lane][0] / wsum) : 0.0f;
+        }
+    }
+}
+
+// DFG table: per cell (n.v = mu, roughness r at cell centres), the Schlick
+// split of the specular directional albedo (F = 1),
+//   A = E[g (1 - (1 - v.h)^5)],  B = E[g (1 - v.h)^5],  g = G (v.h) / (mu n.h),
+// over half vectors h distributed as D(h) n.h (the inverse GGX distribution
+// on a kLutQ x kLutQ midpoint grid of (xi, azimuth)), l = reflect(v, h) above
+// the horizon.  One workgroup per cell, one azimuth row per thread, a
+// fixed-order tree over the rows.
+__global__ void __launch_bounds__(256) k_dfg_lut(float *__restrict__ lut)
+{
+#pragma clang fp contract(off)
+    static_assert(kLutQ == 256, "one thread per quadrature row");
+    __shared__ double pa[256], pb[256];
+    const int cell = blockIdx.x, i = cell / kLutN, j = cell % kLutN, s = threadIdx.x;
+    const double mu = (i + 0.5) / kLutN, r = (j + 0.5) / kLutN, al = r * r, a2 = al * al;
+    const V3 v = v3(sqrt(1.0 - mu * mu), 0.0, mu);
+    const double xi = (s + 0.5) / kLutQ;
+    const double c2 = (1.0 - xi) / (1.0 + (a2 - 1.0) * xi);
+    const double ct = sqrt(c2), st = sqrt(1.0 - c2 > 0.0 ? 1.0 - c2 : 0.0);
+    const double g1v = smith_G1(mu, a2);
+    double A = 0.0, B = 0.0;
+    for (int t = 0; t < kLutQ; ++t) {
+        const double ph = 2.0 * kPiD * (t + 0.5) / kLutQ;
+        const V3 h = v3(st * cos(ph), st * sin(ph), ct);
+        const double vh = dot(v, h);
+        if (!(vh > 0.0)) continue;
+        const double nl = 2.0 * vh * h.z - v.z;
+        if (!(nl > 0.0)) continue;
+        const double g = smith_G1(nl, a2) * g1v * vh / (mu * ct);
+        const double x = 1.0 - vh, fc = x * x * x * x * x;
+        A += g * (1.0 - fc);
+        B += g * fc;
+    }
+    pa[s] = A;
+    pb[s] = B;
+    __syncthreads();
+    for (int half = 128; half > 0; half >>= 1) {
+        if (s < half) { pa[s] += pa[s + half]; pb[s] += pb[s + half]; }
+        __syncthreads();
+    }
+    if (s == 0) {
+        lut[2 * cell] = (float)(pa[0] / ((double)kLutQ * kLutQ));
+        lut[2 * cell + 1] = (float)(pb[0] / ((double)kLutQ * kLutQ));
+    }
+}
+
+hipError_t launch_env_prefilter(const float *rgb, int H, int W, const EnvWS &w, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_env_prefilter, dim3(kPfH * kPfW), dim3(64), 0, st, H, W, rgb, w.Ed, w.Es);
+    hipLaunchKernelGGL(k_dfg_lut, dim3(kLutN * kLutN), dim3(256), 0, st, w.lut);
+    return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(256) k_render_gen(RenderArgs a)
 {
     const int64_t total = (int64_t)a.H * a.W * (a.nc + a.ng + a.ne);
@@ -99,6 +210,62 @@ struct RenderJob {
         return t.begin(a, S, r);
     }
     __device__ __forceinline__ void finish(int64_t) { t.finish(a, r); }
+    __device__ __forceinline__ void after_step() {}
+    __device__ __forceinline__ void drain() {}
+};
+
+// Relighting (Sec. 3.5.1): the forward render's job with the attribute query
+// instead of the radiance trace; a sample's incident radiance is
+// V L_env(w) + (1 - V) SplitSum(attributes, prefiltered env) (Eq.
+// relight_splitsum), weighted by f cos / q from its ray record.
+template <int K>
+struct RelightJob {
+    const RenderArgs &a;
+    SceneDev S;
+    Walker<K> w;
+    AttrVisit v;
+    int64_t r;
+
+    __device__ RelightJob(const RenderArgs &a_)
+        : a(a_), S(a_.S), v(a_.S, a_.tcut, a_.sa_albedo, a_.sa_rough, a_.sa_metal), r(0) {}
+    __device__ __forceinline__ Walker<K> &walker() { return w; }
+    __device__ __forceinline__ AttrVisit &visit() { return v; }
+    __device__ __forceinline__ bool begin(int64_t g)
+    {
+        r = a.order ? (int64_t)a.order[g] : g;
+        const float4 r0 = a.rays[3 * r];
+        if (r0.w == 0.0f) {
+            a.contrib[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+            return false;
+        }
+        const int64_t p = r / (a.nc + a.ng + a.ne);
+        const float3 x = make_float3(a.x[3 * p], a.x[3 * p + 1], a.x[3 * p + 2]);
+        const float3 d = make_float3(r0.x, r0.y, r0.z);
+        v.reset(x, d);
+        w.start(S, x, d, a.tmin, INFINITY);
+        if (S.n <= 0) {
+            finish(g);
+            return false;
+        }
+        return true;
+    }
+    __device__ __forceinline__ void finish(int64_t)
+    {
+        const float4 r0 = a.rays[3 * r], r1 = a.rays[3 * r + 1], r2 = a.rays[3 * r + 2];
+        const double V = v.T;
+        V3 L = v3((double)r1.w * V, (double)r2.x * V, (double)r2.y * V);
+        if (V < 1.0) {
+            const double inv = v.W > 0.0f ? 1.0 / (double)v.W : 0.0;
+            const V3 ss = split_sum(a.E, v3(v.A.x * inv, v.A.y * inv, v.A.z * inv), v.R * inv, v.M * inv,
+                                    v3(v.N.x * inv, v.N.y * inv, v.N.z * inv), v3(r0.x, r0.y, r0.z));
+            L = v3(L.x + (1.0 - V) * ss.x, L.y + (1.0 - V) * ss.y, L.z + (1.0 - V) * ss.z);
+        }
+        a.contrib[r] = make_float4((float)(r1.x * L.x), (float)(r1.y * L.y), (float)(r1.z * L.z), 0.0f);
+        if (a.dump) {
+            float *dp = a.dump + r * 10;
+            dp[7] = (float)L.x; dp[8] = (float)L.y; dp[9] = (float)L.z;
+        }
+    }
     __device__ __forceinline__ void after_step() {}
     __device__ __forceinline__ void drain() {}
 };
@@ -160,6 +327,13 @@ template <int K>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_render_w3(RenderArgs a)
 {
     RenderJob<K> job(a);
+    run_persistent<K>(job, a.counters, (int64_t)a.H * a.W * (a.nc + a.ng + a.ne));
+}
+
+template <int K>
+__global__ void __launch_bounds__(256) GRT_OCCUPANCY k_render_relight(RenderArgs a)
+{
+    RelightJob<K> job(a);
     run_persistent<K>(job, a.counters, (int64_t)a.H * a.W * (a.nc + a.ng + a.ne));
 }
 
@@ -356,6 +530,39 @@ hipError_t launch_render(const RenderArgs &a, const RenderWS &w, int k, int num_
     case 12: e = go_render<12>(a, num_cu, st); break;
     case 16: e = go_render<16>(a, num_cu, st); break;
     case 32: e = go_render<32>(a, num_cu, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_render_reduce, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st, npix,
+                       a.nc + a.ng + a.ne, a.contrib, a.out);
+    return hipGetLastError();
+}
+
+template <int K>
+static hipError_t go_relight(const RenderArgs &a, int num_cu, hipStream_t st)
+{
+    const int64_t total = (int64_t)a.H * a.W * (a.nc + a.ng + a.ne);
+    const int nb = persistent_blocks(k_render_relight<K>, num_cu, total);
+    hipLaunchKernelGGL(k_render_relight<K>, dim3(nb), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_render_relight(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st)
+{
+    const int64_t npix = (int64_t)a.H * a.W;
+    if (npix <= 0) return hipSuccess;
+    hipError_t e = launch_zero_counters(a.counters, st);
+    if (e != hipSuccess) return e;
+    if ((e = launch_render_gen(a, st)) != hipSuccess) return e;
+    if (a.order && (e = launch_ray_order(a, w, st)) != hipSuccess) return e;
+    switch (k) {
+    case 1: e = go_relight<1>(a, num_cu, st); break;
+    case 2: e = go_relight<2>(a, num_cu, st); break;
+    case 4: e = go_relight<4>(a, num_cu, st); break;
+    case 8: e = go_relight<8>(a, num_cu, st); break;
+    case 12: e = go_relight<12>(a, num_cu, st); break;
+    case 16: e = go_relight<16>(a, num_cu, st); break;
+    case 32: e = go_relight<32>(a, num_cu, st); break;
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;

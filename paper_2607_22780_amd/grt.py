@@ -111,6 +111,10 @@ SIGNATURES = {
     "grt_env_create": (C.c_int, [VP, VP, C.c_int, C.c_int, VP, C.c_size_t, P(VP)]),
     "grt_env_build": (C.c_int, [VP, VP]),
     "grt_env_tables": (C.c_int, [VP, P(VP), P(VP)]),
+    "grt_env_prefilter": (C.c_int, [VP, VP]),
+    "grt_env_relight_tables": (C.c_int, [VP, P(VP), P(VP), P(VP)]),
+    "grt_render_relight": (C.c_int, [VP, VP, P(grt_surfel_attrs), P(grt_gbuffer), P(grt_mis_opts), VP, VP,
+                                     C.c_size_t, VP]),
     "grt_env_destroy": (C.c_int, [VP]),
     "grt_render_saved_bytes": (C.c_size_t, [C.c_int64, C.c_int]),
     "grt_render_workspace_bytes": (C.c_size_t, [C.c_int64, C.c_int]),
@@ -284,6 +288,22 @@ def grt_env_tables(env):
     return m.value, c.value
 
 
+def grt_env_prefilter(env, stream=None):
+    _check(load_library().grt_env_prefilter(env, _stream(stream)))
+
+
+def grt_env_relight_tables(env):
+    a, b, c = VP(), VP(), VP()
+    _check(load_library().grt_env_relight_tables(env, C.byref(a), C.byref(b), C.byref(c)))
+    return a.value, b.value, c.value
+
+
+def grt_render_relight(scene, env, attrs: grt_surfel_attrs, gbuf: grt_gbuffer, opts: grt_mis_opts, out_rgb,
+                       workspace, stream=None):
+    _check(load_library().grt_render_relight(scene, env, C.byref(attrs), C.byref(gbuf), C.byref(opts),
+                                             _ptr(out_rgb), _ptr(workspace), workspace.numel(), _stream(stream)))
+
+
 def grt_env_destroy(env):
     _check(load_library().grt_env_destroy(env))
 
@@ -396,6 +416,24 @@ class Env:
         marg = ws[mo:mo + 4 * (self.H + 1)].view(torch.float32)
         cond = ws[co:co + 4 * self.H * (self.W + 1)].view(torch.float32).view(self.H, self.W + 1)
         return marg, cond
+
+    def prefilter(self, stream=None):
+        """Build the prefiltered tables split-sum relighting reads."""
+        grt_env_prefilter(self.handle, stream)
+        return self
+
+    def relight_tables(self):
+        """(Ed [16,32,3], Es [5,16,32,3], lut [32,32,2]) viewing the workspace."""
+        base = self.workspace.data_ptr()
+        ws = self.workspace
+        out = []
+        for ptr, shape in zip(grt_env_relight_tables(self.handle), ((16, 32, 3), (5, 16, 32, 3), (32, 32, 2))):
+            n = 1
+            for x in shape:
+                n *= x
+            o = ptr - base
+            out.append(ws[o:o + 4 * n].view(torch.float32).view(*shape))
+        return tuple(out)
 
     def __del__(self):
         if getattr(self, "handle", None) and _LIB is not None:
@@ -556,6 +594,26 @@ def render_mis(scene: Scene, env: Env, gb: GBuffer, split=(16, 8, 8), seed=0, jo
     res = dict(rgb=out)
     if save:
         res["saved"] = saved
+    if dump:
+        res["dump"] = dmp
+    return res
+
+
+def render_relight(scene: Scene, env: Env, albedo, rough, metal, gb: GBuffer, split=(16, 8, 8), seed=0, job=0,
+                   t_min=1e-3, t_cut=1e-3, k=12, dump=False, workspace=None, stream=None):
+    """Relit c_pbr [npix,3] under the prefiltered `env` (Sec. 3.5.1, Eq.
+    relight_splitsum), surfel attributes albedo [n,3], rough [n], metal [n]."""
+    dev = gb.x.device
+    spp = sum(split)
+    out = torch.empty(gb.npix, 3, device=dev)
+    dmp = torch.zeros(gb.npix, spp, 10, device=dev) if dump else None
+    opts = make_mis_opts(split, seed, job, t_min, t_cut, k, dmp)
+    attrs = grt_surfel_attrs(_ptr(albedo), _ptr(rough), _ptr(metal))
+    need = grt_render_workspace_bytes(gb.npix, spp)
+    if workspace is None or workspace.numel() < need:
+        workspace = _workspace(need, dev)
+    grt_render_relight(scene.handle, env.handle, attrs, gb.struct(), opts, out, workspace, stream)
+    res = dict(rgb=out)
     if dump:
         res["dump"] = dmp
     return res
