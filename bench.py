@@ -251,6 +251,7 @@ def main():
     ap.add_argument("--cpu-pixels", type=int, default=384, help="pixels of the step the oracle times")
     ap.add_argument("--no-serve", action="store_true", help="skip the relighting-server leg")
     ap.add_argument("--no-stored", action="store_true", help="skip the stored-hit-list backward leg")
+    ap.add_argument("--no-relight", action="store_true", help="skip the split-sum relighting leg")
     ap.add_argument("--hit-cap", type=int, default=64, help="hits stored per sample in the stored-list leg")
     ap.add_argument("--serve-requests", type=int, default=32)
     ap.add_argument("--serve-rate", type=float, default=5.9,
@@ -349,6 +350,31 @@ def main():
                   "retrace_bwd_ms": round(bwd_ms, 3)}
         del hits, res
 
+    relight = None
+    if not args.no_relight:
+        # novel illumination: a fresh 128x256 map, prefiltered; the surfels
+        # carry seeded materials; the same G-buffer and samples per pixel
+        from paper_2607_22780_amd import workloads as W
+        log("bench: relighting leg")
+        env_new = W.envmap(128, 256, seed=11, stream=3, config_id=1)
+        mats = [t(a) for a in W.surfel_materials(s.n, seed=0)]
+        E2 = grt.Env(ctx, t(env_new))
+        pf, rf = [], []
+        ws = None
+        for _ in range(max(args.steps // 2, 3)):
+            ef0.record(st); E2.prefilter(); ef1.record(st)
+            eg0.record(st)
+            out = grt.render_relight(scene, E2, *mats, G, split=SPLIT, seed=SEED, k=args.k, workspace=ws)
+            eg1.record(st)
+            torch.cuda.synchronize()
+            pf.append(ef0.elapsed_time(ef1)); rf.append(eg0.elapsed_time(eg1))
+        frame = float(np.median(rf))
+        relight = {"env": "128x256, prefiltered to 16x32 tables at 6 roughness levels + 32x32 DFG",
+                   "prefilter_ms": round(float(np.median(pf)), 3), "frame_ms": round(frame, 3),
+                   "mrays_s": round(rays / (frame * 1e-3) / 1e6, 2),
+                   "radiance_fwd_ms": round(fwd_ms, 3)}
+        del out, E2
+
     roofline = None
     if os.path.exists(WORKCOUNT):
         wc = json.load(open(WORKCOUNT))
@@ -406,6 +432,7 @@ def main():
         "phase_ms": {"build": round(build_ms, 3), "render_fwd": round(fwd_ms, 3), "render_bwd": round(bwd_ms, 3)},
         "roofline": roofline,
         "stored_hit_lists": stored,
+        "relight_split_sum": relight,
         "relight_server": serve,
         "cpu_baseline": cpu,
     }

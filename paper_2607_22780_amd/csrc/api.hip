@@ -508,6 +508,11 @@ int grt_render_relight(const grt_scene *scene, const grt_env *env, const grt_sur
     a.contrib = w.contrib;
     a.rays = w.rays;
     a.order = a.S.n >= 2 ? w.v1 : nullptr;
+    // the sort's other buffers are dead once the order is built: the trace
+    // parks each sample's averaged normal there for the shading pass
+    a.rl_nx = reinterpret_cast<float *>(w.k0);
+    a.rl_ny = reinterpret_cast<float *>(w.v0);
+    a.rl_nz = reinterpret_cast<float *>(w.k1);
     if ((rc = set_device(scene->ctx))) return rc;
     hipError_t e = grt::launch_render_relight(a, w, opts->k, scene->ctx->num_cu, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "relight launch");

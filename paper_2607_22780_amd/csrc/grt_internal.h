@@ -197,8 +197,10 @@ struct RenderArgs {
     uint32_t *hits;         // stored hit lists: counts [nray], then [nray][hcap] (null: none)
     int hcap;
     unsigned long long *counters;
-    // relighting: per-surfel attributes (by id)
+    // relighting: per-surfel attributes (by id), and where the trace parks
+    // each sample's averaged normal for the shading pass (three float arrays)
     const float *sa_albedo, *sa_rough, *sa_metal;
+    float *rl_nx, *rl_ny, *rl_nz;
     // backward
     const float *grad;
     GradPtrs g;

@@ -214,10 +214,11 @@ struct RenderJob {
     __device__ __forceinline__ void drain() {}
 };
 
-// Relighting (Sec. 3.5.1): the forward render's job with the attribute query
-// instead of the radiance trace; a sample's incident radiance is
-// V L_env(w) + (1 - V) SplitSum(attributes, prefiltered env) (Eq.
-// relight_splitsum), weighted by f cos / q from its ray record.
+// Relighting (Sec. 3.5.1), first pass: the forward render's job with the
+// attribute query instead of the radiance trace.  It parks each traced
+// sample's query result for the shading pass: (V, albedo) in the sample's
+// contribution slot, (roughness, metallic) in the spare words of its ray
+// record, the averaged normal in rl_n*.
 template <int K>
 struct RelightJob {
     const RenderArgs &a;
@@ -251,24 +252,42 @@ struct RelightJob {
     }
     __device__ __forceinline__ void finish(int64_t)
     {
-        const float4 r0 = a.rays[3 * r], r1 = a.rays[3 * r + 1], r2 = a.rays[3 * r + 2];
-        const double V = v.T;
-        V3 L = v3((double)r1.w * V, (double)r2.x * V, (double)r2.y * V);
-        if (V < 1.0) {
-            const double inv = v.W > 0.0f ? 1.0 / (double)v.W : 0.0;
-            const V3 ss = split_sum(a.E, v3(v.A.x * inv, v.A.y * inv, v.A.z * inv), v.R * inv, v.M * inv,
-                                    v3(v.N.x * inv, v.N.y * inv, v.N.z * inv), v3(r0.x, r0.y, r0.z));
-            L = v3(L.x + (1.0 - V) * ss.x, L.y + (1.0 - V) * ss.y, L.z + (1.0 - V) * ss.z);
-        }
-        a.contrib[r] = make_float4((float)(r1.x * L.x), (float)(r1.y * L.y), (float)(r1.z * L.z), 0.0f);
-        if (a.dump) {
-            float *dp = a.dump + r * 10;
-            dp[7] = (float)L.x; dp[8] = (float)L.y; dp[9] = (float)L.z;
-        }
+        const float inv = v.W > 0.0f ? 1.0f / v.W : 0.0f;
+        a.contrib[r] = make_float4(v.T, v.A.x * inv, v.A.y * inv, v.A.z * inv);
+        float4 *r2 = a.rays + 3 * r + 2;
+        r2->z = v.R * inv;
+        r2->w = v.M * inv;
+        a.rl_nx[r] = v.N.x * inv;
+        a.rl_ny[r] = v.N.y * inv;
+        a.rl_nz[r] = v.N.z * inv;
     }
     __device__ __forceinline__ void after_step() {}
     __device__ __forceinline__ void drain() {}
 };
+
+// Relighting, second pass (one thread per sample): the incident radiance
+// V L_env(w) + (1 - V) SplitSum(a, r, m, n, E) (Eq. relight_splitsum) of each
+// traced sample from its parked query, weighted by f cos / q.
+__global__ void __launch_bounds__(256) k_relight_shade(RenderArgs a, int64_t total)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= total) return;
+    const float4 r0 = a.rays[3 * r];
+    if (r0.w == 0.0f) return;  // untraced: its contribution is already 0
+    const float4 r1 = a.rays[3 * r + 1], r2 = a.rays[3 * r + 2], q = a.contrib[r];
+    const double V = q.x;
+    V3 L = v3((double)r1.w * V, (double)r2.x * V, (double)r2.y * V);
+    if (V < 1.0) {
+        const V3 ss = split_sum(a.E, v3(q.y, q.z, q.w), r2.z, r2.w, v3(a.rl_nx[r], a.rl_ny[r], a.rl_nz[r]),
+                                v3(r0.x, r0.y, r0.z));
+        L = v3(L.x + (1.0 - V) * ss.x, L.y + (1.0 - V) * ss.y, L.z + (1.0 - V) * ss.z);
+    }
+    a.contrib[r] = make_float4((float)(r1.x * L.x), (float)(r1.y * L.y), (float)(r1.z * L.z), 0.0f);
+    if (a.dump) {
+        float *dp = a.dump + r * 10;
+        dp[7] = (float)L.x; dp[8] = (float)L.y; dp[9] = (float)L.z;
+    }
+}
 
 template <int K>
 struct RenderBwdJob {
@@ -332,6 +351,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 
 template <int K>
 __global__ void __launch_bounds__(256) GRT_OCCUPANCY k_render_relight(RenderArgs a)
+{
+    RelightJob<K> job(a);
+    run_persistent<K>(job, a.counters, (int64_t)a.H * a.W * (a.nc + a.ng + a.ne));
+}
+
+template <int K>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_render_relight_w3(RenderArgs a)
 {
     RelightJob<K> job(a);
     run_persistent<K>(job, a.counters, (int64_t)a.H * a.W * (a.nc + a.ng + a.ne));
@@ -542,8 +568,13 @@ template <int K>
 static hipError_t go_relight(const RenderArgs &a, int num_cu, hipStream_t st)
 {
     const int64_t total = (int64_t)a.H * a.W * (a.nc + a.ng + a.ne);
-    const int nb = persistent_blocks(k_render_relight<K>, num_cu, total);
-    hipLaunchKernelGGL(k_render_relight<K>, dim3(nb), dim3(256), 0, st, a);
+    if constexpr (K == 12) {
+        const int nb = persistent_blocks(k_render_relight_w3<K>, num_cu, total);
+        hipLaunchKernelGGL(k_render_relight_w3<K>, dim3(nb), dim3(256), 0, st, a);
+    } else {
+        const int nb = persistent_blocks(k_render_relight<K>, num_cu, total);
+        hipLaunchKernelGGL(k_render_relight<K>, dim3(nb), dim3(256), 0, st, a);
+    }
     return hipGetLastError();
 }
 
@@ -566,6 +597,8 @@ hipError_t launch_render_relight(const RenderArgs &a, const RenderWS &w, int k, 
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
+    const int64_t total = npix * (a.nc + a.ng + a.ne);
+    hipLaunchKernelGGL(k_relight_shade, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a, total);
     hipLaunchKernelGGL(k_render_reduce, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st, npix,
                        a.nc + a.ng + a.ne, a.contrib, a.out);
     return hipGetLastError();
