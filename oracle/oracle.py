@@ -259,6 +259,60 @@ def render_relight(s, attrs, gb, env_rgb, split, seed, pix=None, job=0, t_min=1e
     return out
 
 
+def denoise(rgb, depth, normal, valid, H, W, radius=3, sigma_s=2.0, sigma_d=1.0, sigma_n=128.0, eps_d=1e-2):
+    """Cross-bilateral denoiser (Sec. 3.4.2, "Denoising"), written out in
+    double: for each valid pixel p, over the valid pixels p' of the
+    (2 radius + 1)^2 window around it (inside the image),
+        B = exp(-|p - p'|^2 / (2 sigma_s^2))
+            * exp(-|D(p) - D(p')| / (sigma_d |grad D(p) . (p - p')| + eps_d))
+            * max(0, N(p) . N(p'))^sigma_n,
+        out(p) = sum B c(p') / sum B,
+    with N normalized per pixel and grad D(p) the screen-space depth gradient
+    by central differences (one-sided where a neighbour is outside the image
+    or invalid, 0 where both are).  Invalid pixels pass through unchanged.
+    rgb [H*W,3], depth [H*W], normal [H*W,3], valid [H*W]; returns [H*W,3]."""
+    c = np.asarray(rgb, np.float64).reshape(H, W, 3)
+    D = np.asarray(depth, np.float64).reshape(H, W)
+    n = np.asarray(normal, np.float64).reshape(H, W, 3)
+    v = np.asarray(valid).reshape(H, W).astype(bool)
+    ln = np.linalg.norm(n, axis=-1, keepdims=True)
+    n = np.where(ln > 0, n / np.where(ln > 0, ln, 1.0), 0.0)
+
+    def grad(axis):
+        g = np.zeros((H, W))
+        Dp = np.full((H, W), np.nan); Dm = np.full((H, W), np.nan)
+        if axis == 1:
+            Dp[:, :-1] = np.where(v[:, 1:], D[:, 1:], np.nan)
+            Dm[:, 1:] = np.where(v[:, :-1], D[:, :-1], np.nan)
+        else:
+            Dp[:-1, :] = np.where(v[1:, :], D[1:, :], np.nan)
+            Dm[1:, :] = np.where(v[:-1, :], D[:-1, :], np.nan)
+        hp, hm = ~np.isnan(Dp), ~np.isnan(Dm)
+        both = hp & hm
+        g[both] = (Dp[both] - Dm[both]) / 2.0
+        only_p = hp & ~hm
+        g[only_p] = Dp[only_p] - D[only_p]
+        only_m = hm & ~hp
+        g[only_m] = D[only_m] - Dm[only_m]
+        return g
+    gx, gy = grad(1), grad(0)
+    num = np.zeros((H, W, 3)); den = np.zeros((H, W))
+    for dy in range(-radius, radius + 1):
+        for dx in range(-radius, radius + 1):
+            # neighbour q = p + (dx, dy): shifted arrays, zero weight outside
+            ys = slice(max(0, -dy), min(H, H - dy)); xs = slice(max(0, -dx), min(W, W - dx))
+            yq = slice(max(0, dy), min(H, H + dy)); xq = slice(max(0, dx), min(W, W + dx))
+            ok = v[ys, xs] & v[yq, xq]
+            ws = np.exp(-(dx * dx + dy * dy) / (2.0 * sigma_s ** 2))
+            wd = np.exp(-np.abs(D[ys, xs] - D[yq, xq]) / (sigma_d * np.abs(gx[ys, xs] * dx + gy[ys, xs] * dy) + eps_d))
+            wn = np.maximum(0.0, np.einsum("ijk,ijk->ij", n[ys, xs], n[yq, xq])) ** sigma_n
+            B = np.where(ok, ws * wd * wn, 0.0)
+            num[ys, xs] += B[..., None] * c[yq, xq]
+            den[ys, xs] += B
+    out = np.where(v[..., None], num / np.where(den > 0, den, 1.0)[..., None], c)
+    return out.reshape(H * W, 3)
+
+
 def render_mis_backward(s, gb, env_rgb, split, seed, grad, pix=None, job=0, t_min=1e-3, t_cut=T_CUT,
                         alpha_min=ALPHA_MIN):
     """d/d(surfels) of sum_k grad[k] . c_pbr(pix[k]); returns [N,13] double."""

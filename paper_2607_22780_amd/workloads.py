@@ -372,6 +372,7 @@ class GBuffer:
     rough: np.ndarray   # [H*W]
     metal: np.ndarray   # [H*W]
     valid: np.ndarray   # [H*W] uint8
+    depth: np.ndarray = None  # [H*W] distance from the camera (0 where invalid), when known
 
     @property
     def npix(self):
@@ -407,14 +408,17 @@ def _materials(g, npx, valid):
     return albedo * valid[:, None], rough * valid, metal * valid
 
 
-def _finish_gbuffer(H, W, x, nrm, d, valid, g):
+def _finish_gbuffer(H, W, x, nrm, d, valid, g, o=None):
     valid = valid.astype(bool)
+    depth = None
+    if o is not None:
+        depth = _f32(np.where(valid, np.einsum("ij,ij->i", x - o, d), 0.0))
     x = np.where(valid[:, None], x, 0.0)
     nrm = np.where(valid[:, None], nrm, 0.0)
     wo = np.where(valid[:, None], -d, 0.0)
     albedo, rough, metal = _materials(g, H * W, valid)
     return GBuffer(H, W, _f32(x), _f32(nrm), _f32(wo), _f32(albedo), _f32(rough), _f32(metal),
-                   np.ascontiguousarray(valid.astype(np.uint8)))
+                   np.ascontiguousarray(valid.astype(np.uint8)), depth)
 
 
 def _sphere_trace(shapes, o, d, t_far=10.0, eps=1e-10, iters=2000):
@@ -454,7 +458,7 @@ def gbuffer1(H: int = 800, W: int = 800, seed: int = 0, cam_stream: int = 2) -> 
             break
     o, d = pinhole(3.5 * v, (0.0, 0.0, 0.0), 40.0, H, W)
     x, nrm, hit = _sphere_trace(shapes, o, d)
-    return _finish_gbuffer(H, W, x, nrm, d, hit, g)
+    return _finish_gbuffer(H, W, x, nrm, d, hit, g, o)
 
 
 # --- the room scene ----------------------------------------------------------
@@ -555,7 +559,7 @@ def gbuffer3(H: int = 1024, W: int = 1024, seed: int = 0, cam_stream: int = 2) -
     eye, target = camera3(g)
     o, d = pinhole(eye, target, 60.0, H, W)
     x, nrm, hit = _room_intersect(o, d, spheres, boxes)
-    return _finish_gbuffer(H, W, x, nrm, d, hit, g)
+    return _finish_gbuffer(H, W, x, nrm, d, hit, g, o)
 
 
 # --- environment maps ------------------------------------------------------
