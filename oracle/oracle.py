@@ -300,8 +300,10 @@ def denoise(rgb, depth, normal, valid, H, W, radius=3, sigma_s=2.0, sigma_d=1.0,
     for dy in range(-radius, radius + 1):
         for dx in range(-radius, radius + 1):
             # neighbour q = p + (dx, dy): shifted arrays, zero weight outside
-            ys = slice(max(0, -dy), min(H, H - dy)); xs = slice(max(0, -dx), min(W, W - dx))
-            yq = slice(max(0, dy), min(H, H + dy)); xq = slice(max(0, dx), min(W, W + dx))
+            if abs(dy) >= H or abs(dx) >= W:
+                continue  # every neighbour at this offset lies outside the image
+            ys = slice(max(0, -dy), H - max(0, dy)); xs = slice(max(0, -dx), W - max(0, dx))
+            yq = slice(max(0, dy), H - max(0, -dy)); xq = slice(max(0, dx), W - max(0, -dx))
             ok = v[ys, xs] & v[yq, xq]
             ws = np.exp(-(dx * dx + dy * dy) / (2.0 * sigma_s ** 2))
             wd = np.exp(-np.abs(D[ys, xs] - D[yq, xq]) / (sigma_d * np.abs(gx[ys, xs] * dx + gy[ys, xs] * dy) + eps_d))

@@ -91,3 +91,52 @@ def test_invalid_pixels_pass_through_and_never_contribute():
     c2 = c.copy(); c2[40] = 1e6  # an invalid pixel's colour must not leak
     out2 = O.denoise(c2, D, n, v, H, W)
     np.testing.assert_allclose(np.delete(out2, 40, 0), np.delete(out, 40, 0), rtol=1e-13)
+
+
+def _brute(c, D, n, v, H, W, R, ss, sd, sn, ed):
+    """Pixel by pixel, neighbour by neighbour, in plain Python."""
+    c = c.reshape(H, W, 3); D = D.reshape(H, W); n = n.reshape(H, W, 3); v = v.reshape(H, W)
+    nn = [[n[y, x] / np.linalg.norm(n[y, x]) for x in range(W)] for y in range(H)]
+
+    def g(y, x, oy, ox):
+        yp, xp, ym, xm = y + oy, x + ox, y - oy, x - ox
+        hp = 0 <= yp < H and 0 <= xp < W and v[yp, xp]
+        hm = 0 <= ym < H and 0 <= xm < W and v[ym, xm]
+        if hp and hm:
+            return (D[yp, xp] - D[ym, xm]) / 2
+        if hp:
+            return D[yp, xp] - D[y, x]
+        if hm:
+            return D[y, x] - D[ym, xm]
+        return 0.0
+    out = c.copy()
+    for y in range(H):
+        for x in range(W):
+            if not v[y, x]:
+                continue
+            gx, gy = g(y, x, 0, 1), g(y, x, 1, 0)
+            num = np.zeros(3); den = 0.0
+            for dy in range(-R, R + 1):
+                for dx in range(-R, R + 1):
+                    qy, qx = y + dy, x + dx
+                    if not (0 <= qy < H and 0 <= qx < W and v[qy, qx]):
+                        continue
+                    B = (np.exp(-(dx * dx + dy * dy) / (2 * ss * ss))
+                         * np.exp(-abs(D[y, x] - D[qy, qx]) / (sd * abs(gx * dx + gy * dy) + ed))
+                         * max(0.0, float(nn[y][x] @ nn[qy][qx])) ** sn)
+                    num += B * c[qy, qx]; den += B
+            out[y, x] = num / den
+    return out.reshape(H * W, 3)
+
+
+@pytest.mark.parametrize("H,W,R", [(2, 9, 3), (5, 4, 8), (1, 1, 2), (7, 6, 2)])
+def test_brute_force_on_tiny_images(H, W, R):
+    """Against a per-pixel loop, including windows larger than the image."""
+    g = np.random.default_rng(H * 100 + W)
+    c = g.uniform(0, 1, (H * W, 3)); D = g.uniform(1, 2, H * W)
+    n = g.standard_normal((H * W, 3)); n[:, 2] = np.abs(n[:, 2]) + 1.0
+    v = (g.uniform(0, 1, H * W) < 0.85).astype(np.uint8); v[0] = 1
+    kw = dict(radius=R, sigma_s=1.3, sigma_d=0.9, sigma_n=4.0, eps_d=0.05)
+    got = O.denoise(c, D, n, v, H, W, **kw)
+    want = _brute(c, D, n, v, H, W, R, 1.3, 0.9, 4.0, 0.05)
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-15)
