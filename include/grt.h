@@ -356,6 +356,32 @@ int grt_render_relight(const grt_scene *scene, const grt_env *env, const grt_sur
                        const grt_gbuffer *g, const grt_mis_opts *opts, float *out_rgb, void *workspace,
                        size_t ws_bytes, void *stream);
 
+/* Cross-bilateral denoiser for low-sample renders (Sec. 3.4.2,
+ * "Denoising"), on an H x W image with its guides (device arrays, row-major
+ * pixels): rgb [H*W,3] noisy colour, depth [H*W] distance from the camera,
+ * normal [H*W,3] (normalized here), valid [H*W] (uint8).  For each valid
+ * pixel p, over the valid pixels p' of the (2 radius + 1)^2 window inside the
+ * image,
+ *   B = exp(-|p-p'|^2 / (2 sigma_s^2))
+ *     * exp(-|D(p)-D(p')| / (sigma_d |grad D(p).(p-p')| + eps_d))
+ *     * max(0, N(p).N(p'))^sigma_n,
+ *   out(p) = sum B c(p') / sum B   (0 if the sum vanishes),
+ * with grad D the screen-space depth gradient by central differences
+ * (one-sided next to the border or an invalid pixel, 0 with neither
+ * neighbour).  Invalid pixels are copied unchanged.  radius 1..8 (pixels);
+ * sigma_s > 0 (pixels), sigma_d >= 0, sigma_n >= 0, eps_d > 0 (depth units).
+ * Workloads use radius 3, sigma_s 2, sigma_d 1, sigma_n 128, eps_d 0.01.
+ * out_rgb [H*W,3] must not overlap the inputs. */
+typedef struct {
+    int radius;
+    float sigma_s;
+    float sigma_d;
+    float sigma_n;
+    float eps_d;
+} grt_denoise_opts;
+int grt_denoise(grt_ctx *ctx, int H, int W, const float *rgb, const float *depth, const float *normal,
+                const uint8_t *valid, const grt_denoise_opts *opts, float *out_rgb, void *stream);
+
 /* ------------------------------------------------------- relighting server */
 
 /* A continuously batched relighting server over a resident built scene

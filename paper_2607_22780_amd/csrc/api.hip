@@ -483,6 +483,29 @@ static int fill_render_args(const grt_scene *scene, const grt_env *env, const gr
     return GRT_OK;
 }
 
+int grt_denoise(grt_ctx *ctx, int H, int W, const float *rgb, const float *depth, const float *normal,
+                const uint8_t *valid, const grt_denoise_opts *opts, float *out_rgb, void *stream)
+{
+    if (!ctx || !opts) return fail(GRT_ERR_INVALID, "ctx/opts is NULL");
+    if (H < 0 || W < 0 || (int64_t)H * W > 0x7fffffff) return fail(GRT_ERR_INVALID, "bad image size %dx%d", H, W);
+    if ((int64_t)H * W > 0 && (!rgb || !depth || !normal || !valid || !out_rgb))
+        return fail(GRT_ERR_INVALID, "an image array is NULL");
+    if (out_rgb && out_rgb == rgb) return fail(GRT_ERR_INVALID, "out_rgb must not alias rgb");
+    if (opts->radius < 1 || opts->radius > grt::kDenoiseMaxRadius)
+        return fail(GRT_ERR_INVALID, "radius must be in 1..%d", grt::kDenoiseMaxRadius);
+    if (!(opts->sigma_s > 0.0f) || !(opts->sigma_d >= 0.0f) || !(opts->sigma_n >= 0.0f) || !(opts->eps_d > 0.0f))
+        return fail(GRT_ERR_INVALID, "need sigma_s > 0, sigma_d >= 0, sigma_n >= 0, eps_d > 0");
+    grt::DenoiseArgs a;
+    a.H = H; a.W = W; a.radius = opts->radius;
+    a.sigma_s = opts->sigma_s; a.sigma_d = opts->sigma_d; a.sigma_n = opts->sigma_n; a.eps_d = opts->eps_d;
+    a.rgb = rgb; a.depth = depth; a.normal = normal; a.valid = valid; a.out = out_rgb;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    hipError_t e = grt::launch_denoise(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "denoise launch");
+    return GRT_OK;
+}
+
 int grt_render_relight(const grt_scene *scene, const grt_env *env, const grt_surfel_attrs *attrs,
                        const grt_gbuffer *g, const grt_mis_opts *opts, float *out_rgb, void *workspace, size_t ws_bytes,
                        void *stream)

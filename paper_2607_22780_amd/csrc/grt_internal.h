@@ -176,6 +176,17 @@ struct EnvDev {
     const float *Ed, *Es, *lut;  // prefiltered tables (relighting), or null
 };
 hipError_t launch_env_build(const float *rgb, int H, int W, const EnvWS &w, hipStream_t st);
+
+// Cross-bilateral denoiser (denoise.hip)
+constexpr int kDenoiseMaxRadius = 8;
+struct DenoiseArgs {
+    int H, W, radius;
+    float sigma_s, sigma_d, sigma_n, eps_d;
+    const float *rgb, *depth, *normal;
+    const uint8_t *valid;
+    float *out;
+};
+hipError_t launch_denoise(const DenoiseArgs &a, hipStream_t st);
 hipError_t launch_env_prefilter(const float *rgb, int H, int W, const EnvWS &w, hipStream_t st);
 
 struct RenderArgs {

@@ -59,6 +59,11 @@ class grt_surfel_grads(C.Structure):
     _fields_ = [("means", VP), ("scales", VP), ("quats", VP), ("opacity", VP), ("rgb", VP)]
 
 
+class grt_denoise_opts(C.Structure):
+    _fields_ = [("radius", C.c_int), ("sigma_s", C.c_float), ("sigma_d", C.c_float), ("sigma_n", C.c_float),
+                ("eps_d", C.c_float)]
+
+
 class grt_surfel_attrs(C.Structure):
     _fields_ = [("albedo", VP), ("rough", VP), ("metal", VP)]
 
@@ -112,6 +117,7 @@ SIGNATURES = {
     "grt_env_build": (C.c_int, [VP, VP]),
     "grt_env_tables": (C.c_int, [VP, P(VP), P(VP)]),
     "grt_env_prefilter": (C.c_int, [VP, VP]),
+    "grt_denoise": (C.c_int, [VP, C.c_int, C.c_int, VP, VP, VP, VP, P(grt_denoise_opts), VP, VP]),
     "grt_env_relight_tables": (C.c_int, [VP, P(VP), P(VP), P(VP)]),
     "grt_render_relight": (C.c_int, [VP, VP, P(grt_surfel_attrs), P(grt_gbuffer), P(grt_mis_opts), VP, VP,
                                      C.c_size_t, VP]),
@@ -617,6 +623,20 @@ def render_relight(scene: Scene, env: Env, albedo, rough, metal, gb: GBuffer, sp
     if dump:
         res["dump"] = dmp
     return res
+
+
+def denoise(ctx: Context, rgb, depth, normal, valid, H: int, W: int, radius=3, sigma_s=2.0, sigma_d=1.0,
+            sigma_n=128.0, eps_d=1e-2, stream=None):
+    """Cross-bilateral denoiser (Sec. 3.4.2): rgb [H*W,3] guided by depth
+    [H*W], normal [H*W,3] and valid [H*W] (uint8); returns the filtered image."""
+    dev = rgb.device
+    for a in (rgb, depth, normal, valid):
+        assert a.is_contiguous() and a.device == dev
+    out = torch.empty(H * W, 3, device=dev)
+    o = grt_denoise_opts(int(radius), float(sigma_s), float(sigma_d), float(sigma_n), float(eps_d))
+    _check(load_library().grt_denoise(ctx.handle, H, W, _ptr(rgb), _ptr(depth), _ptr(normal), _ptr(valid),
+                                      C.byref(o), _ptr(out), _stream(stream)))
+    return out
 
 
 def render_mis_backward(scene: Scene, env: Env, gb: GBuffer, grad_rgb, saved, split=(16, 8, 8), seed=0, job=0,
