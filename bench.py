@@ -369,10 +369,22 @@ def main():
             torch.cuda.synchronize()
             pf.append(ef0.elapsed_time(ef1)); rf.append(eg0.elapsed_time(eg1))
         frame = float(np.median(rf))
+        # cross-bilateral denoise of the relit frame (radius 3: 7x7 window)
+        dgb = [t(gb.depth), G.n, G.valid]
+        dn = []
+        for _ in range(5):
+            ef0.record(st)
+            grt.denoise(ctx, out["rgb"], *dgb, gb.H, gb.W)
+            ef1.record(st)
+            torch.cuda.synchronize()
+            dn.append(ef0.elapsed_time(ef1))
+        dn_ms = float(np.median(dn))
         relight = {"env": "128x256, prefiltered to 16x32 tables at 6 roughness levels + 32x32 DFG",
                    "prefilter_ms": round(float(np.median(pf)), 3), "frame_ms": round(frame, 3),
                    "mrays_s": round(rays / (frame * 1e-3) / 1e6, 2),
-                   "radiance_fwd_ms": round(fwd_ms, 3)}
+                   "radiance_fwd_ms": round(fwd_ms, 3),
+                   "denoise_ms": round(dn_ms, 4),
+                   "denoise_gb_s": round(gb.npix * 41 / (dn_ms * 1e-3) / 1e9, 1)}
         del out, E2
 
     roofline = None
