@@ -460,6 +460,66 @@ int orc_trace_attr(int64_t n, const float *means, const float *scales, const flo
     return 0;
 }
 
+/* Primary-ray G-buffer by 2DGRT (Sec. 3.3, Eq. deferred_maps, with the
+ * primary rays traced instead of rasterized): along each camera ray's
+ * ordered, cut-off hits, the deferred maps are the normalized-weight
+ * averages sum w_k {c_k, d_k, n_k, a_k, r_k, m_k}, w_k = T_k a_k / sum_j T_j a_j,
+ * d_k the depth tau_k of the hit, n_k facing the camera.  The pixel is
+ * covered (valid) when its accumulated opacity 1 - T reaches min_opacity;
+ * then the G-buffer holds x = o + D d, the unit normal N / |N|, wo = -d and
+ * the material maps; otherwise every entry is 0.  Outputs (double):
+ * x, n, wo, albedo [nr,3], rough, metal, depth [nr], rgb [nr,3] (C, the
+ * normalized radiance map, 0 where not covered), valid [nr] (uint8). */
+int orc_trace_gbuffer(int64_t n, const float *means, const float *scales, const float *quats, const float *opacity,
+                      const float *rgb, float alpha_min, const float *albedo, const float *rough, const float *metal,
+                      int64_t nr, const float *orig, const float *dirs, float tmin_s, float tmax_s, float t_cut,
+                      double min_opacity, double *ox, double *on, double *owo, double *oa, double *orough,
+                      double *ometal, double *odepth, double *orgb, uint8_t *ovalid)
+{
+    Scene S;
+    if (scene_init(&S, n, means, scales, quats, opacity, rgb, alpha_min)) return -1;
+    Attrs at = {albedo, rough, metal};
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < nr; ++r) {
+        const float *o = orig + 3 * r, *d = dirs + 3 * r;
+        RayResult R;
+        trace_ray(&S, o, d, tmin_s, tmax_s, t_cut, &R);
+        AttrOut q;
+        attr_of_ray(&S, &at, o, d, &R, &q);
+        /* depth and colour maps with the same weights */
+        double T = 1.0, W = 0.0, Dm = 0.0, C[3] = {0, 0, 0};
+        for (int64_t k = 0; k < R.K; ++k) {
+            const Surf64 *sf = &S.s64[R.h[k].id];
+            Geo64 g;
+            geo64(sf, o, d, &g);
+            double w = T * g.alpha;
+            W += w;
+            Dm += w * g.tau;
+            for (int c = 0; c < 3; ++c) C[c] += w * sf->c[c];
+            T *= 1.0 - g.alpha;
+        }
+        double inv = W > 0.0 ? 1.0 / W : 0.0;
+        int valid = 1.0 - q.V >= min_opacity && W > 0.0;
+        double nl = sqrt(q.n[0] * q.n[0] + q.n[1] * q.n[1] + q.n[2] * q.n[2]);
+        if (!(nl > 0.0)) valid = 0;
+        double D = Dm * inv;
+        for (int c = 0; c < 3; ++c) {
+            ox[3 * r + c] = valid ? (double)o[c] + D * (double)d[c] : 0.0;
+            on[3 * r + c] = valid ? q.n[c] / nl : 0.0;
+            owo[3 * r + c] = valid ? -(double)d[c] : 0.0;
+            oa[3 * r + c] = valid ? q.a[c] : 0.0;
+            orgb[3 * r + c] = valid ? C[c] * inv : 0.0;
+        }
+        orough[r] = valid ? q.r : 0.0;
+        ometal[r] = valid ? q.m : 0.0;
+        odepth[r] = valid ? D : 0.0;
+        ovalid[r] = (uint8_t)valid;
+        free(R.h);
+    }
+    scene_free(&S);
+    return 0;
+}
+
 /* Gradient of sum_r (gC_r . c_rt(r) + gT_r T_fin(r)) w.r.t. the surfels.
  * g13 [n,13] is overwritten (mean 3, scale 2, quat 4, opacity 1, rgb 3). */
 int orc_trace_backward(int64_t n, const float *means, const float *scales, const float *quats,

@@ -57,6 +57,8 @@ def lib():
                                          [P, P, P] +
                                          [C.c_int, C.c_int, C.c_int, C.c_uint64, C.c_uint32, F, F, I64, P, P] +
                                          [P] * 6)
+        L.orc_trace_gbuffer.restype = C.c_int
+        L.orc_trace_gbuffer.argtypes = ([I64, P, P, P, P, P, F, P, P, P, I64, P, P, F, F, F, C.c_double] + [P] * 9)
         L.orc_trace_attr.restype = C.c_int
         L.orc_trace_attr.argtypes = [I64, P, P, P, P, F, P, P, P, I64, P, P, F, F, F, P, P, P, P, P]
         if hasattr(L, "orc_count_work"):
@@ -131,6 +133,26 @@ def trace_attr(s, attrs, origins, dirs, t_min=0.0, t_max=np.inf, t_cut=T_CUT, al
     rc = lib().orc_trace_attr(s.n, _p(means), _p(scales), _p(quats), _p(opacity), alpha_min, _p(alb), _p(rough),
                               _p(metal), R, _p(o), _p(d), float(t_min), float(t_max), t_cut, _p(out["V"]),
                               _p(out["albedo"]), _p(out["rough"]), _p(out["metal"]), _p(out["normal"]))
+    assert rc == 0
+    return out
+
+
+def trace_gbuffer(s, attrs, origins, dirs, t_min=0.0, t_max=np.inf, t_cut=T_CUT, alpha_min=ALPHA_MIN,
+                  min_opacity=0.5):
+    """Primary-ray G-buffer by 2DGRT (Eq. deferred_maps on traced primary
+    rays): dict of x, n, wo, albedo [R,3], rough, metal, depth [R], rgb [R,3]
+    and valid [R] (uint8: accumulated opacity >= min_opacity)."""
+    arrs = _scene(s)
+    alb, rough, metal = (_c(a) for a in attrs)
+    o = _c(origins); d = _c(dirs)
+    R = o.shape[0]
+    out = dict(x=np.zeros((R, 3)), n=np.zeros((R, 3)), wo=np.zeros((R, 3)), albedo=np.zeros((R, 3)),
+               rough=np.zeros(R), metal=np.zeros(R), depth=np.zeros(R), rgb=np.zeros((R, 3)),
+               valid=np.zeros(R, np.uint8))
+    rc = lib().orc_trace_gbuffer(s.n, *map(_p, arrs), alpha_min, _p(alb), _p(rough), _p(metal), R, _p(o), _p(d),
+                                 float(t_min), float(t_max), t_cut, float(min_opacity),
+                                 *(_p(out[k]) for k in ("x", "n", "wo", "albedo", "rough", "metal", "depth", "rgb",
+                                                        "valid")))
     assert rc == 0
     return out
 
