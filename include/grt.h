@@ -206,6 +206,34 @@ int grt_trace_attr(const grt_scene *scene, const grt_rays *rays, const grt_trace
                    const grt_surfel_attrs *attrs, float *out_V, float *out_albedo, float *out_rough, float *out_metal,
                    float *out_normal, void *workspace, size_t ws_bytes, void *stream);
 
+/* Primary-ray G-buffer by 2DGRT (Sec. 3.3, Eq. deferred_maps with the
+ * camera rays traced instead of rasterized).  For every ray (camera origin o,
+ * unit direction d), the same ordered hits and cut-off as grt_trace; the
+ * deferred maps are the averages over the composited hits with normalized
+ * weights T_k alpha_k / sum_j T_j alpha_j of the hit depth tau_k, the surfel
+ * normal (turned toward the camera), colour and attributes.  A pixel is
+ * covered when its accumulated opacity 1 - T reaches min_opacity (0, 1] and
+ * the averaged normal N does not vanish; then
+ *   x = o + D d, n = N/|N|, wo = -d, albedo, rough, metal = the maps,
+ *   depth = D, rgb = the colour map, valid = 1,
+ * and every entry is 0 otherwise.  The arrays (device, [n,3] or [n]) form a
+ * grt_gbuffer that grt_render_mis and grt_render_relight take as is.  Same
+ * rays/opts/workspace as grt_trace (sky and dump ignored). */
+typedef struct {
+    float *x;
+    float *n;
+    float *wo;
+    float *albedo;
+    float *rough;
+    float *metal;
+    float *depth;
+    float *rgb;
+    uint8_t *valid;
+} grt_gbuffer_out;
+int grt_trace_gbuffer(const grt_scene *scene, const grt_rays *rays, const grt_trace_opts *opts,
+                      const grt_surfel_attrs *attrs, float min_opacity, grt_gbuffer_out *out, void *workspace,
+                      size_t ws_bytes, void *stream);
+
 /* Backward of grt_trace by re-traversal (Sec. 3.2: gradients backpropagate
  * through the traced radiance): accumulates d/d(surfels) of
  *   sum_r grad_rgb[r] . c_rt(r) + grad_T[r] T(r)

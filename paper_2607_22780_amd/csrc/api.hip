@@ -334,6 +334,32 @@ int grt_trace_attr(const grt_scene *scene, const grt_rays *rays, const grt_trace
     return GRT_OK;
 }
 
+int grt_trace_gbuffer(const grt_scene *scene, const grt_rays *rays, const grt_trace_opts *opts,
+                      const grt_surfel_attrs *attrs, float min_opacity, grt_gbuffer_out *out, void *workspace,
+                      size_t ws_bytes, void *stream)
+{
+    grt::TraceGBufArgs b;
+    int rc = fill_trace_args(scene, rays, opts, b.f);
+    if (rc) return rc;
+    if (!attrs || !out) return fail(GRT_ERR_INVALID, "attrs/out is NULL");
+    if (scene->s.n > 0 && (!attrs->albedo || !attrs->rough || !attrs->metal))
+        return fail(GRT_ERR_INVALID, "an attribute array is NULL");
+    if (rays->n > 0 && (!out->x || !out->n || !out->wo || !out->albedo || !out->rough || !out->metal ||
+                        !out->depth || !out->rgb || !out->valid))
+        return fail(GRT_ERR_INVALID, "an output array is NULL");
+    if (!(min_opacity > 0.0f && min_opacity <= 1.0f)) return fail(GRT_ERR_INVALID, "min_opacity must be in (0,1]");
+    b.albedo = attrs->albedo; b.rough = attrs->rough; b.metal = attrs->metal;
+    b.min_opacity = min_opacity;
+    b.x = out->x; b.n = out->n; b.wo = out->wo; b.out_albedo = out->albedo; b.out_rough = out->rough;
+    b.out_metal = out->metal; b.depth = out->depth; b.rgb = out->rgb; b.valid = out->valid;
+    if ((rc = check_ws(workspace, ws_bytes, grt_trace_workspace_bytes(rays->n), "trace_gbuffer"))) return rc;
+    b.f.counters = (unsigned long long *)workspace;
+    if ((rc = set_device(scene->ctx))) return rc;
+    hipError_t e = grt::launch_trace_gbuffer(b, opts->k, scene->ctx->num_cu, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "trace_gbuffer launch");
+    return GRT_OK;
+}
+
 int grt_trace_backward(const grt_scene *scene, const grt_rays *rays, const grt_trace_opts *opts, const float *fwd_rgb,
                        const float *fwd_T, const float *grad_rgb, const float *grad_T, grt_surfel_grads *grads,
                        void *workspace, size_t ws_bytes, void *stream)

@@ -150,6 +150,17 @@ struct TraceAttrArgs {
 };
 hipError_t launch_trace_attr(const TraceAttrArgs &a, int k, int num_cu, hipStream_t st);
 
+// Primary-ray G-buffer over the rays of `f`: a full G-buffer (x, n, wo,
+// albedo, rough, metal, valid) plus the depth and colour maps.
+struct TraceGBufArgs {
+    TraceArgs f;
+    const float *albedo, *rough, *metal;
+    float min_opacity;
+    float *x, *n, *wo, *out_albedo, *out_rough, *out_metal, *depth, *rgb;
+    uint8_t *valid;
+};
+hipError_t launch_trace_gbuffer(const TraceGBufArgs &a, int k, int num_cu, hipStream_t st);
+
 struct GradPtrs {
     float *means, *scales, *quats, *opacity, *rgb;
     float *acc;  // [n,16] per-surfel lines the kernels accumulate into

@@ -108,6 +108,39 @@ struct AttrVisit {
     }
 };
 
+// Primary-ray G-buffer (Eq. deferred_maps on traced camera rays): the
+// attribute sums plus the depth tau and the colour of each composited hit,
+// with the same weights.
+struct GBufVisit : AttrVisit {
+    const float4 *col;
+    float Dsum;
+    float3 Csum;
+
+    __device__ GBufVisit() {}
+    __device__ GBufVisit(const SceneDev &S, float t_cut, const float *al, const float *ro, const float *me)
+        : AttrVisit(S, t_cut, al, ro, me), col(S.col) {}
+
+    __device__ __forceinline__ void reset(float3 o_, float3 d_)
+    {
+        AttrVisit::reset(o_, d_);
+        Dsum = 0.0f;
+        Csum = make_float3(0.f, 0.f, 0.f);
+    }
+
+    __device__ __forceinline__ bool operator()(uint32_t p, uint32_t id, float tau, const float4 r0, const float4 r1,
+                                               const float4 r2, const float4 r3, float crho2)
+    {
+        HitGeo g;
+        value_geo(r0, r1, r2, r3, o, d, g);
+        const float a = r1.w * expf(-0.5f * g.rho2);
+        const float w = T * a;
+        const float4 c = col[p];
+        Dsum += w * tau;
+        Csum.x += w * c.x; Csum.y += w * c.y; Csum.z += w * c.z;
+        return AttrVisit::operator()(p, id, tau, r0, r1, r2, r3, crho2);
+    }
+};
+
 // Gradient terms reach global memory through per-wavefront LDS staging.
 // Device FP32 atomics are limited by the cache lines they touch (one line per
 // lane-atomic when lanes update unrelated surfels), not by the dwords: 16

@@ -160,6 +160,91 @@ struct TraceAttrJob {
     __device__ __forceinline__ void drain() {}
 };
 
+// Primary-ray G-buffer (Eq. deferred_maps by 2DGRT): the attribute query
+// with the depth and colour maps; a pixel is covered when its accumulated
+// opacity reaches min_opacity (and its averaged normal does not vanish).
+template <int K>
+struct TraceGBufJob {
+    const TraceGBufArgs &a;
+    SceneDev S;
+    Walker<K> w;
+    GBufVisit v;
+
+    __device__ TraceGBufJob(const TraceGBufArgs &a_)
+        : a(a_), S(a_.f.S), v(a_.f.S, a_.f.tcut, a_.albedo, a_.rough, a_.metal) {}
+    __device__ __forceinline__ Walker<K> &walker() { return w; }
+    __device__ __forceinline__ GBufVisit &visit() { return v; }
+
+    __device__ __forceinline__ bool begin(int64_t r)
+    {
+        const float3 o = make_float3(a.f.o[3 * r], a.f.o[3 * r + 1], a.f.o[3 * r + 2]);
+        const float3 d = make_float3(a.f.d[3 * r], a.f.d[3 * r + 1], a.f.d[3 * r + 2]);
+        const float tmin = a.f.tmin_a ? a.f.tmin_a[r] : a.f.tmin;
+        const float tmax = a.f.tmax_a ? a.f.tmax_a[r] : a.f.tmax;
+        v.reset(o, d);
+        w.start(S, o, d, tmin, tmax);
+        if (S.n <= 0) {
+            finish(r);
+            return false;
+        }
+        return true;
+    }
+
+    __device__ __forceinline__ void finish(int64_t r)
+    {
+        const float inv = v.W > 0.0f ? 1.0f / v.W : 0.0f;
+        const float3 N = make_float3(v.N.x * inv, v.N.y * inv, v.N.z * inv);
+        const float nl = sqrtf(N.x * N.x + N.y * N.y + N.z * N.z);
+        const bool ok = v.W > 0.0f && 1.0f - v.T >= a.min_opacity && nl > 0.0f;
+        const float in = ok ? 1.0f / nl : 0.0f, D = ok ? v.Dsum * inv : 0.0f, m = ok ? inv : 0.0f;
+        a.x[3 * r] = ok ? v.o.x + D * v.d.x : 0.0f;
+        a.x[3 * r + 1] = ok ? v.o.y + D * v.d.y : 0.0f;
+        a.x[3 * r + 2] = ok ? v.o.z + D * v.d.z : 0.0f;
+        a.n[3 * r] = N.x * in; a.n[3 * r + 1] = N.y * in; a.n[3 * r + 2] = N.z * in;
+        a.wo[3 * r] = ok ? -v.d.x : 0.0f; a.wo[3 * r + 1] = ok ? -v.d.y : 0.0f; a.wo[3 * r + 2] = ok ? -v.d.z : 0.0f;
+        a.out_albedo[3 * r] = v.A.x * m; a.out_albedo[3 * r + 1] = v.A.y * m; a.out_albedo[3 * r + 2] = v.A.z * m;
+        a.out_rough[r] = v.R * m;
+        a.out_metal[r] = v.M * m;
+        a.depth[r] = D;
+        a.rgb[3 * r] = v.Csum.x * m; a.rgb[3 * r + 1] = v.Csum.y * m; a.rgb[3 * r + 2] = v.Csum.z * m;
+        a.valid[r] = ok ? 1 : 0;
+    }
+    __device__ __forceinline__ void after_step() {}
+    __device__ __forceinline__ void drain() {}
+};
+
+template <int K>
+__global__ void __launch_bounds__(256) GRT_OCCUPANCY k_trace_gbuffer(TraceGBufArgs a)
+{
+    TraceGBufJob<K> job(a);
+    run_persistent<K>(job, a.f.counters, a.f.n);
+}
+
+template <int K>
+static hipError_t go_trace_gbuffer(const TraceGBufArgs &a, int num_cu, hipStream_t st)
+{
+    const int nb = persistent_blocks(k_trace_gbuffer<K>, num_cu, a.f.n);
+    hipLaunchKernelGGL(k_trace_gbuffer<K>, dim3(nb), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_gbuffer(const TraceGBufArgs &a, int k, int num_cu, hipStream_t st)
+{
+    if (a.f.n <= 0) return hipSuccess;
+    hipError_t e = launch_zero_counters(a.f.counters, st);
+    if (e != hipSuccess) return e;
+    switch (k) {
+    case 1: return go_trace_gbuffer<1>(a, num_cu, st);
+    case 2: return go_trace_gbuffer<2>(a, num_cu, st);
+    case 4: return go_trace_gbuffer<4>(a, num_cu, st);
+    case 8: return go_trace_gbuffer<8>(a, num_cu, st);
+    case 12: return go_trace_gbuffer<12>(a, num_cu, st);
+    case 16: return go_trace_gbuffer<16>(a, num_cu, st);
+    case 32: return go_trace_gbuffer<32>(a, num_cu, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
 template <int K>
 __global__ void __launch_bounds__(256) GRT_OCCUPANCY k_trace_attr(TraceAttrArgs a)
 {

@@ -59,6 +59,11 @@ class grt_surfel_grads(C.Structure):
     _fields_ = [("means", VP), ("scales", VP), ("quats", VP), ("opacity", VP), ("rgb", VP)]
 
 
+class grt_gbuffer_out(C.Structure):
+    _fields_ = [("x", VP), ("n", VP), ("wo", VP), ("albedo", VP), ("rough", VP), ("metal", VP), ("depth", VP),
+                ("rgb", VP), ("valid", VP)]
+
+
 class grt_denoise_opts(C.Structure):
     _fields_ = [("radius", C.c_int), ("sigma_s", C.c_float), ("sigma_d", C.c_float), ("sigma_n", C.c_float),
                 ("eps_d", C.c_float)]
@@ -112,6 +117,8 @@ SIGNATURES = {
                                      C.c_size_t, VP]),
     "grt_trace_attr": (C.c_int, [VP, P(grt_rays), P(grt_trace_opts), P(grt_surfel_attrs), VP, VP, VP, VP, VP, VP,
                                  C.c_size_t, VP]),
+    "grt_trace_gbuffer": (C.c_int, [VP, P(grt_rays), P(grt_trace_opts), P(grt_surfel_attrs), C.c_float,
+                                    P(grt_gbuffer_out), VP, C.c_size_t, VP]),
     "grt_env_workspace_bytes": (C.c_size_t, [C.c_int, C.c_int]),
     "grt_env_create": (C.c_int, [VP, VP, C.c_int, C.c_int, VP, C.c_size_t, P(VP)]),
     "grt_env_build": (C.c_int, [VP, VP]),
@@ -512,6 +519,32 @@ def trace_attr(scene: Scene, albedo, rough, metal, origins, dirs, t_min=0.0, t_m
     grt_trace_attr(scene.handle, rays, opts, attrs, out["V"], out["albedo"], out["rough"], out["metal"],
                    out["normal"], ws, stream)
     return out
+
+
+def trace_gbuffer(scene: Scene, albedo, rough, metal, origins, dirs, H: int, W: int, min_opacity=0.5, k=12,
+                  t_cut=1e-3, stream=None):
+    """Primary-ray G-buffer by 2DGRT of H x W camera rays (row-major): dict
+    with a GBuffer ("gbuffer", usable by render_mis / render_relight), and the
+    depth [H*W] and colour [H*W,3] maps."""
+    dev = origins.device
+    R = origins.shape[0]
+    assert R == H * W
+    for a in (albedo, rough, metal):
+        assert a.is_contiguous() and a.dtype == torch.float32 and a.device == dev
+    e3 = lambda: torch.empty(R, 3, device=dev)
+    e1 = lambda: torch.empty(R, device=dev)
+    o = dict(x=e3(), n=e3(), wo=e3(), albedo=e3(), rough=e1(), metal=e1(), depth=e1(), rgb=e3(),
+             valid=torch.empty(R, dtype=torch.uint8, device=dev))
+    st = grt_gbuffer_out(*(_ptr(o[k_]) for k_ in ("x", "n", "wo", "albedo", "rough", "metal", "depth", "rgb",
+                                                  "valid")))
+    rays = make_rays(origins, dirs, 0.0, float("inf"))
+    opts = make_trace_opts(k, t_cut, (0.0, 0.0, 0.0), None, None)
+    attrs = grt_surfel_attrs(_ptr(albedo), _ptr(rough), _ptr(metal))
+    ws = _workspace(grt_trace_workspace_bytes(R), dev)
+    _check(load_library().grt_trace_gbuffer(scene.handle, C.byref(rays), C.byref(opts), C.byref(attrs),
+                                            float(min_opacity), C.byref(st), _ptr(ws), ws.numel(), _stream(stream)))
+    o["gbuffer"] = GBuffer(H, W, o["x"], o["n"], o["wo"], o["albedo"], o["rough"], o["metal"], o["valid"])
+    return o
 
 
 def zero_grads(n: int, device):
