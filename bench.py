@@ -379,7 +379,20 @@ def main():
             torch.cuda.synchronize()
             dn.append(ef0.elapsed_time(ef1))
         dn_ms = float(np.median(dn))
+        # primary-ray G-buffer by 2DGRT of a 1024^2 camera inside the room
+        cam_o, cam_d = W.pinhole(*W.camera3(W.rng(3, 2)), 60.0, gb.H, gb.W)
+        co, cd = t(cam_o.astype(np.float32)), t(cam_d.astype(np.float32))
+        gt = []
+        for _ in range(5):
+            ef0.record(st)
+            gbt = grt.trace_gbuffer(scene, *mats, co, cd, gb.H, gb.W, k=args.k)
+            ef1.record(st)
+            torch.cuda.synchronize()
+            gt.append(ef0.elapsed_time(ef1))
+        covered = float(gbt["valid"].float().mean().item())
+        del gbt
         relight = {"env": "128x256, prefiltered to 16x32 tables at 6 roughness levels + 32x32 DFG",
+                   "gbuffer_trace_ms": round(float(np.median(gt)), 3), "gbuffer_covered": round(covered, 4),
                    "prefilter_ms": round(float(np.median(pf)), 3), "frame_ms": round(frame, 3),
                    "mrays_s": round(rays / (frame * 1e-3) / 1e6, 2),
                    "radiance_fwd_ms": round(fwd_ms, 3),
