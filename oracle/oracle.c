@@ -1274,3 +1274,73 @@ int orc_trace_extent(int64_t n, const float *means, const float *scales, const f
     scene_free(&S);
     return 0;
 }
+
+/* Mesh backend of the attribute query (Sec. 3.5.2, "Mesh-based ray
+ * tracing"): the closest triangle hit by each ray with t_min < t <= t_max
+ * (two-sided, Moller-Trumbore, in double; equal t: the lower triangle id).
+ * A miss returns V = 1 and zero attributes; a hit V = 0 and the per-vertex
+ * albedo, roughness, metallic and normal interpolated with the barycentric
+ * weights (1 - u - v, u, v) of the hit, the normal turned toward the ray
+ * origin (not renormalized).  Margins per ray: [0] the hit's barycentric
+ * margin min(u, v, 1 - u - v), [1] the relative gap in t to the next
+ * triangle met (inf if none). */
+int orc_mesh_trace_attr(int64_t nv, const float *verts, int64_t nf, const int32_t *tris, const float *albedo,
+                        const float *rough, const float *metal, const float *vnormal, int64_t nr, const float *orig,
+                        const float *dirs, float tmin_s, float tmax_s, double *outV, double *outA, double *outR,
+                        double *outM, double *outN, double *margins)
+{
+    (void)nv;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < nr; ++r) {
+        double o[3] = {orig[3 * r], orig[3 * r + 1], orig[3 * r + 2]};
+        double d[3] = {dirs[3 * r], dirs[3 * r + 1], dirs[3 * r + 2]};
+        double best = INFINITY, second = INFINITY, bu = 0.0, bv = 0.0;
+        int64_t bf = -1;
+        for (int64_t f = 0; f < nf; ++f) {
+            const float *a = verts + 3 * (int64_t)tris[3 * f], *b = verts + 3 * (int64_t)tris[3 * f + 1],
+                        *c = verts + 3 * (int64_t)tris[3 * f + 2];
+            double v0[3] = {a[0], a[1], a[2]};
+            double e1[3] = {b[0] - v0[0], b[1] - v0[1], b[2] - v0[2]}, e2[3] = {c[0] - v0[0], c[1] - v0[1], c[2] - v0[2]};
+            double p[3] = {d[1] * e2[2] - d[2] * e2[1], d[2] * e2[0] - d[0] * e2[2], d[0] * e2[1] - d[1] * e2[0]};
+            double det = dot3(e1, p);
+            if (fabs(det) < 1e-12) continue;
+            double inv = 1.0 / det;
+            double sv[3] = {o[0] - v0[0], o[1] - v0[1], o[2] - v0[2]};
+            double u = dot3(sv, p) * inv;
+            if (u < 0.0 || u > 1.0) continue;
+            double q[3] = {sv[1] * e1[2] - sv[2] * e1[1], sv[2] * e1[0] - sv[0] * e1[2], sv[0] * e1[1] - sv[1] * e1[0]};
+            double v = dot3(d, q) * inv;
+            if (v < 0.0 || u + v > 1.0) continue;
+            double t = dot3(e2, q) * inv;
+            if (!(t > tmin_s && t <= tmax_s)) continue;
+            if (t < best) { second = best; best = t; bf = f; bu = u; bv = v; }
+            else if (t < second) second = t;
+        }
+        double A[3] = {0, 0, 0}, Rg = 0.0, M = 0.0, N[3] = {0, 0, 0};
+        if (bf >= 0) {
+            double w[3] = {1.0 - bu - bv, bu, bv};
+            for (int k = 0; k < 3; ++k) {
+                int64_t vi = tris[3 * bf + k];
+                for (int c = 0; c < 3; ++c) {
+                    A[c] += w[k] * (double)albedo[3 * vi + c];
+                    N[c] += w[k] * (double)vnormal[3 * vi + c];
+                }
+                Rg += w[k] * (double)rough[vi];
+                M += w[k] * (double)metal[vi];
+            }
+            if (dot3(N, d) > 0.0) { N[0] = -N[0]; N[1] = -N[1]; N[2] = -N[2]; }
+        }
+        outV[r] = bf >= 0 ? 0.0 : 1.0;
+        for (int c = 0; c < 3; ++c) { outA[3 * r + c] = A[c]; outN[3 * r + c] = N[c]; }
+        outR[r] = Rg;
+        outM[r] = M;
+        if (margins) {
+            double bm = 1.0 - bu - bv;
+            if (bu < bm) bm = bu;
+            if (bv < bm) bm = bv;
+            margins[2 * r] = bf >= 0 ? bm : INFINITY;
+            margins[2 * r + 1] = bf >= 0 && second < INFINITY ? (second - best) / best : INFINITY;
+        }
+    }
+    return 0;
+}

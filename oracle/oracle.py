@@ -57,6 +57,8 @@ def lib():
                                          [P, P, P] +
                                          [C.c_int, C.c_int, C.c_int, C.c_uint64, C.c_uint32, F, F, I64, P, P] +
                                          [P] * 6)
+        L.orc_mesh_trace_attr.restype = C.c_int
+        L.orc_mesh_trace_attr.argtypes = [I64, P, I64, P, P, P, P, P, I64, P, P, F, F, P, P, P, P, P, P]
         L.orc_trace_gbuffer.restype = C.c_int
         L.orc_trace_gbuffer.argtypes = ([I64, P, P, P, P, P, F, P, P, P, I64, P, P, F, F, F, C.c_double] + [P] * 9)
         L.orc_trace_attr.restype = C.c_int
@@ -133,6 +135,22 @@ def trace_attr(s, attrs, origins, dirs, t_min=0.0, t_max=np.inf, t_cut=T_CUT, al
     rc = lib().orc_trace_attr(s.n, _p(means), _p(scales), _p(quats), _p(opacity), alpha_min, _p(alb), _p(rough),
                               _p(metal), R, _p(o), _p(d), float(t_min), float(t_max), t_cut, _p(out["V"]),
                               _p(out["albedo"]), _p(out["rough"]), _p(out["metal"]), _p(out["normal"]))
+    assert rc == 0
+    return out
+
+
+def mesh_trace_attr(m, origins, dirs, t_min=0.0, t_max=np.inf):
+    """Mesh backend of Trace_attr: closest-hit V [R], albedo [R,3], rough,
+    metal [R], normal [R,3] (barycentric, facing the origin) and margins
+    [R,2] (barycentric margin, relative t gap to the next triangle)."""
+    o = _c(origins); d = _c(dirs)
+    R = o.shape[0]
+    out = dict(V=np.zeros(R), albedo=np.zeros((R, 3)), rough=np.zeros(R), metal=np.zeros(R), normal=np.zeros((R, 3)),
+               margins=np.zeros((R, 2)))
+    tris = _c(m.tris, np.int32)
+    rc = lib().orc_mesh_trace_attr(m.nv, _p(_c(m.verts)), m.nf, _p(tris), _p(_c(m.albedo)), _p(_c(m.rough)),
+                                   _p(_c(m.metal)), _p(_c(m.normal)), R, _p(o), _p(d), float(t_min), float(t_max),
+                                   *(_p(out[k]) for k in ("V", "albedo", "rough", "metal", "normal", "margins")))
     assert rc == 0
     return out
 

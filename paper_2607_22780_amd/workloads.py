@@ -562,6 +562,103 @@ def gbuffer3(H: int = 1024, W: int = 1024, seed: int = 0, cam_stream: int = 2) -
     return _finish_gbuffer(H, W, x, nrm, d, hit, g, o)
 
 
+# --- triangle meshes (the mesh backend's input) ----------------------------
+
+@dataclass
+class Mesh:
+    """A triangle mesh with per-vertex material attributes and normals."""
+    verts: np.ndarray   # [V,3]
+    tris: np.ndarray    # [F,3] int32 vertex indices
+    albedo: np.ndarray  # [V,3]
+    rough: np.ndarray   # [V]
+    metal: np.ndarray   # [V]
+    normal: np.ndarray  # [V,3] unit
+
+    @property
+    def nv(self):
+        return self.verts.shape[0]
+
+    @property
+    def nf(self):
+        return self.tris.shape[0]
+
+
+def _grid(p0, eu, ev, res):
+    """(res+1)^2 vertices over the parallelogram p0 + s eu + t ev, 2 res^2 triangles."""
+    s, t = np.meshgrid(np.linspace(0.0, 1.0, res + 1), np.linspace(0.0, 1.0, res + 1), indexing="ij")
+    v = p0[None, :] + s.reshape(-1, 1) * eu[None, :] + t.reshape(-1, 1) * ev[None, :]
+    i, j = np.meshgrid(np.arange(res), np.arange(res), indexing="ij")
+    a = (i * (res + 1) + j).reshape(-1)
+    b, c, d = a + (res + 1), a + 1, a + res + 2
+    return v, np.concatenate([np.stack([a, b, d], 1), np.stack([a, d, c], 1)])
+
+
+def _with_materials(g, parts):
+    verts, tris, nrm, base = [], [], [], 0
+    for v, f, n in parts:
+        verts.append(v); tris.append(f + base); nrm.append(n); base += v.shape[0]
+    verts = np.concatenate(verts); tris = np.concatenate(tris); nrm = _normalize(np.concatenate(nrm))
+    nv = verts.shape[0]
+    albedo = g.uniform(0.0, 1.0, (nv, 3)); rough = g.uniform(0.05, 1.0, nv)
+    metal = (g.uniform(0.0, 1.0, nv) < 0.3).astype(np.float64)
+    return Mesh(_f32(verts), np.ascontiguousarray(tris.astype(np.int32)), _f32(albedo), _f32(rough), _f32(metal),
+                _f32(nrm))
+
+
+def mesh3(seed: int = 0, wall_res: int = 48, segments: int = 48) -> Mesh:
+    """The room as triangles: floor and four walls (normals inward, open
+    ceiling) as grids, the 10 spheres as UV spheres and the 10 boxes with
+    their yaw -- stand-ins for a mesh extracted from optimized surfels."""
+    spheres, boxes = objects3(seed)
+    g = rng(6 + 100 * seed, 0)
+    parts = []
+    lo, hi = ROOM_LO, ROOM_HI
+    ext = hi - lo
+    X, Y, Z = np.eye(3)
+    for p0, eu, ev, n in ((lo, ext[0] * X, ext[2] * Z, Y),
+                          (lo, ext[1] * Y, ext[2] * Z, X), (np.array([hi[0], lo[1], lo[2]]), ext[1] * Y, ext[2] * Z, -X),
+                          (lo, ext[0] * X, ext[1] * Y, Z), (np.array([lo[0], lo[1], hi[2]]), ext[0] * X, ext[1] * Y, -Z)):
+        v, f = _grid(p0, eu, ev, wall_res)
+        parts.append((v, f, np.tile(n, (v.shape[0], 1))))
+    for sp in spheres:
+        th, ph = np.meshgrid(np.linspace(0.0, math.pi, segments // 2 + 1), np.linspace(0.0, 2 * math.pi, segments + 1),
+                             indexing="ij")
+        n = np.stack([np.sin(th) * np.cos(ph), np.cos(th), np.sin(th) * np.sin(ph)], -1).reshape(-1, 3)
+        rows, cols = segments // 2, segments
+        i, j = np.meshgrid(np.arange(rows), np.arange(cols), indexing="ij")
+        a = (i * (cols + 1) + j).reshape(-1)
+        b, c, d = a + (cols + 1), a + 1, a + cols + 2
+        f = np.concatenate([np.stack([a, b, d], 1), np.stack([a, d, c], 1)])
+        parts.append((sp.c + sp.r * n, f, n))
+    for bx in boxes:
+        R = bx.rot
+        for axis in range(3):
+            o1, o2 = [b for b in range(3) if b != axis]
+            for sgn in (-1.0, 1.0):
+                nl = np.zeros(3); nl[axis] = sgn
+                corners = []
+                for s1, s2 in ((-1, -1), (1, -1), (1, 1), (-1, 1)):
+                    pl = np.zeros(3); pl[axis] = sgn * bx.half[axis]
+                    pl[o1] = s1 * bx.half[o1]; pl[o2] = s2 * bx.half[o2]
+                    corners.append(bx.c + pl @ R)
+                v = np.array(corners)
+                f = np.array([[0, 1, 2], [0, 2, 3]])
+                parts.append((v, f, np.tile(nl @ R, (4, 1))))
+    return _with_materials(g, parts)
+
+
+def tri_soup(n: int = 2000, seed: int = 0) -> Mesh:
+    """n random triangles in [-1,1]^3 (edges 0.05..0.3), per-vertex attributes
+    and random unit normals."""
+    g = rng(7 + 100 * seed, 0)
+    c = g.uniform(-1.0, 1.0, (n, 3))
+    e1 = random_unit_vectors(g, n) * g.uniform(0.05, 0.3, (n, 1))
+    e2 = random_unit_vectors(g, n) * g.uniform(0.05, 0.3, (n, 1))
+    v = np.stack([c, c + e1, c + e2], 1).reshape(-1, 3)
+    f = np.arange(3 * n).reshape(n, 3)
+    return _with_materials(g, [(v, f, random_unit_vectors(g, 3 * n))])
+
+
 # --- environment maps ------------------------------------------------------
 
 def envmap(H: int = 256, W: int = 512, seed: int = 0, stream: int = 3, config_id: int = 1) -> np.ndarray:
