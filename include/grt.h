@@ -384,6 +384,43 @@ int grt_render_relight(const grt_scene *scene, const grt_env *env, const grt_sur
                        const grt_gbuffer *g, const grt_mis_opts *opts, float *out_rgb, void *workspace,
                        size_t ws_bytes, void *stream);
 
+/* Mesh backend of the attribute query (Sec. 3.5.2, "Mesh-based ray
+ * tracing"): a triangle mesh answers Eq. trace_attr by a closest-hit query.
+ *   verts [nv,3], tris [nf,3] int32 vertex indices (device, borrowed, not to
+ *   change after grt_mesh_build; a triangle with an index outside [0, nv) is
+ *   ignored).  0 <= nf <= 2^29.  Workspace: grt_mesh_workspace_bytes(nf),
+ *   256-byte aligned (LBVH over the triangles' boxes). */
+typedef struct {
+    int64_t nv;
+    const float *verts;
+    int64_t nf;
+    const int32_t *tris;
+} grt_mesh_desc;
+typedef struct grt_mesh grt_mesh;
+size_t grt_mesh_workspace_bytes(int64_t nf);
+int grt_mesh_create(grt_ctx *ctx, const grt_mesh_desc *mesh, void *workspace, size_t ws_bytes, grt_mesh **out);
+int grt_mesh_build(grt_mesh *mesh, void *stream);
+int grt_mesh_destroy(grt_mesh *mesh);
+
+/* Per-vertex attributes (device, float32): albedo [nv,3], rough [nv],
+ * metal [nv], normal [nv,3]. */
+typedef struct {
+    const float *albedo;
+    const float *rough;
+    const float *metal;
+    const float *normal;
+} grt_vertex_attrs;
+
+/* For every ray (scalar t_min/t_max only), the closest triangle hit with
+ * t_min < t <= t_max (two-sided, Moller-Trumbore in float; equal t: the
+ * lower triangle index).  A miss: out_V = 1 and zero attributes.  A hit:
+ * out_V = 0 and the vertex attributes interpolated with the hit's
+ * barycentric weights (1 - u - v, u, v), the normal turned toward the ray
+ * origin (not renormalized).  Same outputs as grt_trace_attr, so either
+ * backend can answer the query. */
+int grt_mesh_trace_attr(const grt_mesh *mesh, const grt_rays *rays, const grt_vertex_attrs *attrs, float *out_V,
+                        float *out_albedo, float *out_rough, float *out_metal, float *out_normal, void *stream);
+
 /* Cross-bilateral denoiser for low-sample renders (Sec. 3.4.2,
  * "Denoising"), on an H x W image with its guides (device arrays, row-major
  * pixels): rgb [H*W,3] noisy colour, depth [H*W] distance from the camera,

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgrt.so")
-SOURCES = ["api.hip", "scene.hip", "trace.hip", "render.hip", "server.hip", "denoise.hip"]
+SOURCES = ["api.hip", "scene.hip", "trace.hip", "render.hip", "server.hip", "denoise.hip", "mesh.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

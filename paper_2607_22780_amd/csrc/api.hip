@@ -18,6 +18,13 @@ struct grt_scene {
     bool built;
 };
 
+struct grt_mesh {
+    grt_ctx *ctx;
+    grt_mesh_desc m;
+    grt::MeshWS w;
+    bool built;
+};
+
 struct grt_env {
     grt_ctx *ctx;
     const float *rgb;
@@ -506,6 +513,76 @@ static int fill_render_args(const grt_scene *scene, const grt_env *env, const gr
         a.hits = o->hit_list;
         a.hcap = o->hit_cap;
     }
+    return GRT_OK;
+}
+
+size_t grt_mesh_workspace_bytes(int64_t nf)
+{
+    if (nf < 0) return 0;
+    return grt::carve_mesh(nullptr, nf).bytes;
+}
+
+int grt_mesh_create(grt_ctx *ctx, const grt_mesh_desc *m, void *workspace, size_t ws_bytes, grt_mesh **out)
+{
+    if (!ctx || !m || !out) return fail(GRT_ERR_INVALID, "NULL argument");
+    *out = nullptr;
+    if (m->nv < 0 || m->nv > 0x7fffffff || m->nf < 0 || m->nf > (1 << 29))
+        return fail(GRT_ERR_INVALID, "mesh size out of range (nv %lld, nf %lld)", (long long)m->nv, (long long)m->nf);
+    if (m->nf > 0 && (!m->verts || !m->tris)) return fail(GRT_ERR_INVALID, "verts/tris is NULL");
+    const size_t need = grt_mesh_workspace_bytes(m->nf);
+    if (!workspace || ws_bytes < need) return fail(GRT_ERR_OOM, "mesh workspace of %zu bytes < %zu needed", ws_bytes, need);
+    if (!aligned(workspace, 256)) return fail(GRT_ERR_INVALID, "workspace must be 256-byte aligned");
+    grt_mesh *h = new (std::nothrow) grt_mesh;
+    if (!h) return fail(GRT_ERR_OOM, "host allocation failed");
+    h->ctx = ctx;
+    h->m = *m;
+    h->w = grt::carve_mesh(workspace, m->nf);
+    h->built = false;
+    *out = h;
+    return GRT_OK;
+}
+
+int grt_mesh_build(grt_mesh *mesh, void *stream)
+{
+    if (!mesh) return fail(GRT_ERR_INVALID, "mesh is NULL");
+    int rc = set_device(mesh->ctx);
+    if (rc) return rc;
+    hipError_t e = grt::launch_mesh_build((int)mesh->m.nv, mesh->m.verts, (int)mesh->m.nf, mesh->m.tris, mesh->w,
+                                         (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mesh build launch");
+    mesh->built = true;
+    return GRT_OK;
+}
+
+int grt_mesh_trace_attr(const grt_mesh *mesh, const grt_rays *rays, const grt_vertex_attrs *attrs, float *out_V,
+                        float *out_albedo, float *out_rough, float *out_metal, float *out_normal, void *stream)
+{
+    if (!mesh || !rays || !attrs) return fail(GRT_ERR_INVALID, "NULL argument");
+    if (!mesh->built) return fail(GRT_ERR_NOT_BUILT, "mesh used before grt_mesh_build");
+    int rc = check_rays(rays);
+    if (rc) return rc;
+    if (rays->t_min || rays->t_max) return fail(GRT_ERR_INVALID, "the mesh query takes scalar t_min/t_max only");
+    if (mesh->m.nf > 0 && (!attrs->albedo || !attrs->rough || !attrs->metal || !attrs->normal))
+        return fail(GRT_ERR_INVALID, "a vertex attribute array is NULL");
+    if (rays->n > 0 && (!out_V || !out_albedo || !out_rough || !out_metal || !out_normal))
+        return fail(GRT_ERR_INVALID, "an output array is NULL");
+    grt::MeshTraceArgs a;
+    a.n = rays->n;
+    a.nv = (int)mesh->m.nv; a.nf = (int)mesh->m.nf;
+    a.rec = mesh->w.rec; a.nodes = mesh->w.nodes; a.tris = mesh->m.tris;
+    a.o = rays->origins; a.d = rays->dirs; a.tmin = rays->t_min_all; a.tmax = rays->t_max_all;
+    a.albedo = attrs->albedo; a.rough = attrs->rough; a.metal = attrs->metal; a.vnormal = attrs->normal;
+    a.out_V = out_V; a.out_albedo = out_albedo; a.out_rough = out_rough; a.out_metal = out_metal;
+    a.out_normal = out_normal;
+    if ((rc = set_device(mesh->ctx))) return rc;
+    hipError_t e = grt::launch_mesh_trace_attr(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mesh trace launch");
+    return GRT_OK;
+}
+
+int grt_mesh_destroy(grt_mesh *mesh)
+{
+    delete mesh;
     return GRT_OK;
 }
 

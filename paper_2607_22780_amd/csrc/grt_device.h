@@ -143,6 +143,14 @@ __device__ __forceinline__ bool slab(float lx, float ly, float lz, float hx, flo
     return tn <= tf * 1.0000005f + 1e-30f;
 }
 
+// order-preserving float <-> int maps (atomic min/max of floats)
+__device__ __forceinline__ int f2o(float f)
+{
+    int i = __float_as_int(f);
+    return i >= 0 ? i : i ^ 0x7fffffff;
+}
+__device__ __forceinline__ float o2f(int i) { return __int_as_float(i >= 0 ? i : i ^ 0x7fffffff); }
+
 __device__ __forceinline__ float safe_inv(float d)
 {
     return 1.0f / (fabsf(d) > 1e-30f ? d : copysignf(1e-30f, d));

@@ -188,6 +188,70 @@ struct EnvDev {
 };
 hipError_t launch_env_build(const float *rgb, int H, int W, const EnvWS &w, hipStream_t st);
 
+// LBVH pieces shared by the surfel scene and the triangle mesh (scene.hip)
+hipError_t launch_bounds_reset(int32_t *bounds, hipStream_t st);
+hipError_t launch_morton_sort(int n, const float *centres, const int32_t *bounds, uint32_t *keys0, uint32_t *vals0,
+                              uint32_t *keys1, uint32_t *vals1, uint32_t *hist, hipStream_t st);
+hipError_t launch_hierarchy_refit(int n, const uint32_t *keys, const float *leaf_box, Node *nodes, int32_t *parent_int,
+                                  int32_t *parent_leaf, uint32_t *flags, hipStream_t st);
+
+// Triangle mesh for the mesh backend of the attribute query (mesh.hip):
+// records in Morton order, 48 B each: (v0, triangle id bits), (e1, 0), (e2, 0).
+struct MeshWS {
+    float4 *rec;
+    Node *nodes;
+    float *leaf_box;  // [nf,6] sorted order
+    float *box_tmp;   // [nf,6] triangle order
+    float *centre;    // [nf,3]
+    uint32_t *keys0, *keys1, *vals0, *vals1;
+    int32_t *parent_int, *parent_leaf;
+    uint32_t *flags, *hist;
+    int32_t *bounds;
+    size_t bytes;
+};
+
+inline MeshWS carve_mesh(void *base, int64_t nf)
+{
+    MeshWS w{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? (char *)base + off : nullptr;
+        off += align256(bytes);
+        return p;
+    };
+    size_t n = (size_t)(nf > 0 ? nf : 1), ni = (size_t)(nf > 1 ? nf - 1 : 1);
+    w.rec = (float4 *)take(48 * n);
+    w.nodes = (Node *)take(sizeof(Node) * ni);
+    w.leaf_box = (float *)take(24 * n);
+    w.box_tmp = (float *)take(24 * n);
+    w.centre = (float *)take(12 * n);
+    w.keys0 = (uint32_t *)take(4 * n);
+    w.keys1 = (uint32_t *)take(4 * n);
+    w.vals0 = (uint32_t *)take(4 * n);
+    w.vals1 = (uint32_t *)take(4 * n);
+    w.parent_int = (int32_t *)take(4 * ni);
+    w.parent_leaf = (int32_t *)take(4 * n);
+    w.flags = (uint32_t *)take(4 * ni);
+    w.hist = (uint32_t *)take(4 * sort_hist_words((int64_t)n));
+    w.bounds = (int32_t *)take(4 * 8);
+    w.bytes = off;
+    return w;
+}
+
+struct MeshTraceArgs {
+    int64_t n;                       // rays
+    int nv, nf;
+    const float4 *rec;
+    const Node *nodes;
+    const int32_t *tris;             // [nf,3]
+    const float *o, *d;
+    float tmin, tmax;
+    const float *albedo, *rough, *metal, *vnormal;  // per vertex
+    float *out_V, *out_albedo, *out_rough, *out_metal, *out_normal;
+};
+hipError_t launch_mesh_build(int nv, const float *verts, int nf, const int32_t *tris, const MeshWS &w, hipStream_t st);
+hipError_t launch_mesh_trace_attr(const MeshTraceArgs &a, hipStream_t st);
+
 // Cross-bilateral denoiser (denoise.hip)
 constexpr int kDenoiseMaxRadius = 8;
 struct DenoiseArgs {

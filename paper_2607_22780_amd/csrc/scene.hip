@@ -14,12 +14,6 @@
 
 namespace grt {
 
-__device__ __forceinline__ int f2o(float f)
-{
-    int i = __float_as_int(f);
-    return i >= 0 ? i : i ^ 0x7fffffff;
-}
-__device__ __forceinline__ float o2f(int i) { return __int_as_float(i >= 0 ? i : i ^ 0x7fffffff); }
 
 // support bound rho^2 <= min(9, 2 ln(o / alpha_min)), evaluated in double and
 // rounded once, so it does not depend on the math library's last ulp
@@ -377,6 +371,35 @@ void launch_radix_sort(int n, int passes, uint32_t *k0, uint32_t *v0, uint32_t *
         uint32_t *t0 = ki, *t1 = vi;
         ki = ko; vi = vo; ko = t0; vo = t1;
     }
+}
+
+// Pieces of the LBVH build shared with the triangle mesh: reset the centre
+// bounds; Morton codes of centres [n,3] within the bounds and their sort
+// (sorted codes / original indices back in keys0 / vals0); the hierarchy over
+// the sorted codes and the refit from leaf boxes in sorted order.
+hipError_t launch_bounds_reset(int32_t *bounds, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, st, bounds);
+    return hipGetLastError();
+}
+
+hipError_t launch_morton_sort(int n, const float *centres, const int32_t *bounds, uint32_t *keys0, uint32_t *vals0,
+                              uint32_t *keys1, uint32_t *vals1, uint32_t *hist, hipStream_t st)
+{
+    const int tb = 256, gb = (n + tb - 1) / tb;
+    hipLaunchKernelGGL(k_morton, dim3(gb), dim3(tb), 0, st, n, centres, bounds, keys0, vals0);
+    launch_radix_sort(n, 4, keys0, vals0, keys1, vals1, hist, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_hierarchy_refit(int n, const uint32_t *keys, const float *leaf_box, Node *nodes, int32_t *parent_int,
+                                  int32_t *parent_leaf, uint32_t *flags, hipStream_t st)
+{
+    if (n <= 1) return hipSuccess;
+    const int tb = 256, gb = (n + tb - 1) / tb, gi = (n - 1 + tb - 1) / tb;
+    hipLaunchKernelGGL(k_hierarchy, dim3(gi), dim3(tb), 0, st, n, keys, nodes, parent_int, parent_leaf, flags);
+    hipLaunchKernelGGL(k_refit, dim3(gb), dim3(tb), 0, st, n, leaf_box, nodes, parent_int, parent_leaf, flags);
+    return hipGetLastError();
 }
 
 hipError_t launch_scene_build(const grt_surfels &s, float alpha_min, const SceneWS &w, hipStream_t st)

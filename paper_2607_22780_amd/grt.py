@@ -64,6 +64,14 @@ class grt_gbuffer_out(C.Structure):
                 ("rgb", VP), ("valid", VP)]
 
 
+class grt_mesh_desc(C.Structure):
+    _fields_ = [("nv", C.c_int64), ("verts", VP), ("nf", C.c_int64), ("tris", VP)]
+
+
+class grt_vertex_attrs(C.Structure):
+    _fields_ = [("albedo", VP), ("rough", VP), ("metal", VP), ("normal", VP)]
+
+
 class grt_denoise_opts(C.Structure):
     _fields_ = [("radius", C.c_int), ("sigma_s", C.c_float), ("sigma_d", C.c_float), ("sigma_n", C.c_float),
                 ("eps_d", C.c_float)]
@@ -124,6 +132,11 @@ SIGNATURES = {
     "grt_env_build": (C.c_int, [VP, VP]),
     "grt_env_tables": (C.c_int, [VP, P(VP), P(VP)]),
     "grt_env_prefilter": (C.c_int, [VP, VP]),
+    "grt_mesh_workspace_bytes": (C.c_size_t, [C.c_int64]),
+    "grt_mesh_create": (C.c_int, [VP, P(grt_mesh_desc), VP, C.c_size_t, P(VP)]),
+    "grt_mesh_build": (C.c_int, [VP, VP]),
+    "grt_mesh_destroy": (C.c_int, [VP]),
+    "grt_mesh_trace_attr": (C.c_int, [VP, P(grt_rays), P(grt_vertex_attrs), VP, VP, VP, VP, VP, VP]),
     "grt_denoise": (C.c_int, [VP, C.c_int, C.c_int, VP, VP, VP, VP, P(grt_denoise_opts), VP, VP]),
     "grt_env_relight_tables": (C.c_int, [VP, P(VP), P(VP), P(VP)]),
     "grt_render_relight": (C.c_int, [VP, VP, P(grt_surfel_attrs), P(grt_gbuffer), P(grt_mis_opts), VP, VP,
@@ -656,6 +669,47 @@ def render_relight(scene: Scene, env: Env, albedo, rough, metal, gb: GBuffer, sp
     if dump:
         res["dump"] = dmp
     return res
+
+
+class Mesh:
+    """A triangle mesh (verts [V,3] float32, tris [F,3] int32, device) with its
+    LBVH, for the mesh backend of the attribute query."""
+
+    def __init__(self, ctx: Context, verts: torch.Tensor, tris: torch.Tensor, stream=None):
+        assert verts.is_contiguous() and verts.dtype == torch.float32
+        assert tris.is_contiguous() and tris.dtype == torch.int32
+        self.ctx, self.verts, self.tris = ctx, verts, tris
+        self.nv, self.nf = int(verts.shape[0]), int(tris.shape[0])
+        self.workspace = _workspace(int(load_library().grt_mesh_workspace_bytes(self.nf)), verts.device)
+        self.desc = grt_mesh_desc(self.nv, _ptr(verts), self.nf, _ptr(tris))
+        h = VP()
+        _check(load_library().grt_mesh_create(ctx.handle, C.byref(self.desc), _ptr(self.workspace),
+                                              self.workspace.numel(), C.byref(h)))
+        self.handle = h.value
+        _check(load_library().grt_mesh_build(self.handle, _stream(stream)))
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _LIB is not None:
+            _LIB.grt_mesh_destroy(self.handle)
+            self.handle = None
+
+
+def mesh_trace_attr(mesh: Mesh, albedo, rough, metal, normal, origins, dirs, t_min=0.0, t_max=float("inf"),
+                    stream=None):
+    """Mesh backend of Trace_attr: dict of V [R], albedo [R,3], rough [R],
+    metal [R], normal [R,3] (barycentric, facing the ray origin)."""
+    dev = origins.device
+    R = origins.shape[0]
+    for a in (albedo, rough, metal, normal):
+        assert a.is_contiguous() and a.dtype == torch.float32 and a.device == dev
+    out = dict(V=torch.empty(R, device=dev), albedo=torch.empty(R, 3, device=dev), rough=torch.empty(R, device=dev),
+               metal=torch.empty(R, device=dev), normal=torch.empty(R, 3, device=dev))
+    rays = make_rays(origins, dirs, t_min, t_max)
+    va = grt_vertex_attrs(_ptr(albedo), _ptr(rough), _ptr(metal), _ptr(normal))
+    _check(load_library().grt_mesh_trace_attr(mesh.handle, C.byref(rays), C.byref(va), _ptr(out["V"]),
+                                              _ptr(out["albedo"]), _ptr(out["rough"]), _ptr(out["metal"]),
+                                              _ptr(out["normal"]), _stream(stream)))
+    return out
 
 
 def denoise(ctx: Context, rgb, depth, normal, valid, H: int, W: int, radius=3, sigma_s=2.0, sigma_d=1.0,
