@@ -939,9 +939,13 @@ static void table_lookup(const double *T, const double w[3], double out[3])
     }
 }
 
+struct MeshRefS;
+static void mesh_query(const struct MeshRefS *m, const double o[3], const double d[3], double tmin, double tmax,
+                       AttrOut *q, double mg[2]);
 typedef struct {
     Attrs at;
     const double *Ed, *Es, *lut;
+    const struct MeshRefS *mesh;  /* the mesh backend answers the query, or NULL: the surfels */
 } Relight;
 
 /* SplitSum(a, r, m, n, E) of the surface a secondary ray met, seen along -w
@@ -1027,7 +1031,14 @@ static int mis_sample(const Scene *S, const Env *E, const MisOpts *op, const Rel
     env_radiance(E, w, Le);
     if (rl) {
         AttrOut a;
-        attr_of_ray(S, &rl->at, of, df, R, &a);
+        if (rl->mesh) {
+            double od[3] = {of[0], of[1], of[2]}, dd[3] = {df[0], df[1], df[2]}, mg[2];
+            mesh_query(rl->mesh, od, dd, op->tmin, INFINITY, &a, mg);
+            R->mg.r2 = (float)mg[0];
+            R->mg.den = (float)mg[1];
+        } else {
+            attr_of_ray(S, &rl->at, of, df, R, &a);
+        }
         double ss[3] = {0, 0, 0};
         if (a.V < 1.0) split_sum(E, rl, &a, w, ss);
         for (int c = 0; c < 3; ++c) Li[c] = a.V * Le[c] + (1.0 - a.V) * ss[c];
@@ -1144,7 +1155,7 @@ int orc_render_relight(int64_t n, const float *means, const float *scales, const
     if (scene_init(&S, n, means, scales, quats, opacity, NULL, alpha_min)) return -1;
     Env E = {eH, eW, env_rgb, marg, cond};
     MisOpts op = {nc, ng, ne, seed, job, tmin, tcut};
-    Relight rl = {{s_albedo, s_rough, s_metal}, Ed, Es, lut};
+    Relight rl = {{s_albedo, s_rough, s_metal}, Ed, Es, lut, NULL};
     shade_pixels(&S, &E, &op, &rl, gx, gn, gwo, galb, grough, gmetal, gvalid, np, pix, out, s_dir, s_q, s_wt, s_Li,
                  s_traced, s_margin);
     scene_free(&S);
@@ -1276,71 +1287,118 @@ int orc_trace_extent(int64_t n, const float *means, const float *scales, const f
 }
 
 /* Mesh backend of the attribute query (Sec. 3.5.2, "Mesh-based ray
- * tracing"): the closest triangle hit by each ray with t_min < t <= t_max
+ * tracing"): the closest triangle hit by the ray with t_min < t <= t_max
  * (two-sided, Moller-Trumbore, in double; equal t: the lower triangle id).
  * A miss returns V = 1 and zero attributes; a hit V = 0 and the per-vertex
  * albedo, roughness, metallic and normal interpolated with the barycentric
  * weights (1 - u - v, u, v) of the hit, the normal turned toward the ray
- * origin (not renormalized).  Margins per ray: [0] the hit's barycentric
- * margin min(u, v, 1 - u - v), [1] the relative gap in t to the next
- * triangle met (inf if none). */
+ * origin (not renormalized).  Margins: [0] the hit's barycentric margin
+ * min(u, v, 1 - u - v), [1] the relative gap in t to the next triangle met
+ * (inf if none). */
+typedef struct MeshRefS {
+    int64_t nf;
+    const float *verts;
+    const int32_t *tris;
+    const float *albedo, *rough, *metal, *normal;
+} MeshRef;
+
+static void mesh_query(const struct MeshRefS *m, const double o[3], const double d[3], double tmin, double tmax,
+                       AttrOut *q, double mg[2])
+{
+    double best = INFINITY, second = INFINITY, bu = 0.0, bv = 0.0;
+    int64_t bf = -1;
+    for (int64_t f = 0; f < m->nf; ++f) {
+        const float *a = m->verts + 3 * (int64_t)m->tris[3 * f], *b = m->verts + 3 * (int64_t)m->tris[3 * f + 1],
+                    *c = m->verts + 3 * (int64_t)m->tris[3 * f + 2];
+        double v0[3] = {a[0], a[1], a[2]};
+        double e1[3] = {b[0] - v0[0], b[1] - v0[1], b[2] - v0[2]}, e2[3] = {c[0] - v0[0], c[1] - v0[1], c[2] - v0[2]};
+        double p[3] = {d[1] * e2[2] - d[2] * e2[1], d[2] * e2[0] - d[0] * e2[2], d[0] * e2[1] - d[1] * e2[0]};
+        double det = dot3(e1, p);
+        if (fabs(det) < 1e-12) continue;
+        double inv = 1.0 / det;
+        double sv[3] = {o[0] - v0[0], o[1] - v0[1], o[2] - v0[2]};
+        double u = dot3(sv, p) * inv;
+        if (u < 0.0 || u > 1.0) continue;
+        double qq[3] = {sv[1] * e1[2] - sv[2] * e1[1], sv[2] * e1[0] - sv[0] * e1[2], sv[0] * e1[1] - sv[1] * e1[0]};
+        double v = dot3(d, qq) * inv;
+        if (v < 0.0 || u + v > 1.0) continue;
+        double t = dot3(e2, qq) * inv;
+        if (!(t > tmin && t <= tmax)) continue;
+        if (t < best) { second = best; best = t; bf = f; bu = u; bv = v; }
+        else if (t < second) second = t;
+    }
+    double A[3] = {0, 0, 0}, Rg = 0.0, M = 0.0, N[3] = {0, 0, 0};
+    if (bf >= 0) {
+        double w[3] = {1.0 - bu - bv, bu, bv};
+        for (int k = 0; k < 3; ++k) {
+            int64_t vi = m->tris[3 * bf + k];
+            for (int c = 0; c < 3; ++c) {
+                A[c] += w[k] * (double)m->albedo[3 * vi + c];
+                N[c] += w[k] * (double)m->normal[3 * vi + c];
+            }
+            Rg += w[k] * (double)m->rough[vi];
+            M += w[k] * (double)m->metal[vi];
+        }
+        if (dot3(N, d) > 0.0) { N[0] = -N[0]; N[1] = -N[1]; N[2] = -N[2]; }
+    }
+    q->V = bf >= 0 ? 0.0 : 1.0;
+    for (int c = 0; c < 3; ++c) { q->a[c] = A[c]; q->n[c] = N[c]; }
+    q->r = Rg;
+    q->m = M;
+    if (mg) {
+        double bm = 1.0 - bu - bv;
+        if (bu < bm) bm = bu;
+        if (bv < bm) bm = bv;
+        mg[0] = bf >= 0 ? bm : INFINITY;
+        mg[1] = bf >= 0 && second < INFINITY ? (second - best) / best : INFINITY;
+    }
+}
+
 int orc_mesh_trace_attr(int64_t nv, const float *verts, int64_t nf, const int32_t *tris, const float *albedo,
                         const float *rough, const float *metal, const float *vnormal, int64_t nr, const float *orig,
                         const float *dirs, float tmin_s, float tmax_s, double *outV, double *outA, double *outR,
                         double *outM, double *outN, double *margins)
 {
     (void)nv;
+    MeshRef m = {nf, verts, tris, albedo, rough, metal, vnormal};
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t r = 0; r < nr; ++r) {
         double o[3] = {orig[3 * r], orig[3 * r + 1], orig[3 * r + 2]};
         double d[3] = {dirs[3 * r], dirs[3 * r + 1], dirs[3 * r + 2]};
-        double best = INFINITY, second = INFINITY, bu = 0.0, bv = 0.0;
-        int64_t bf = -1;
-        for (int64_t f = 0; f < nf; ++f) {
-            const float *a = verts + 3 * (int64_t)tris[3 * f], *b = verts + 3 * (int64_t)tris[3 * f + 1],
-                        *c = verts + 3 * (int64_t)tris[3 * f + 2];
-            double v0[3] = {a[0], a[1], a[2]};
-            double e1[3] = {b[0] - v0[0], b[1] - v0[1], b[2] - v0[2]}, e2[3] = {c[0] - v0[0], c[1] - v0[1], c[2] - v0[2]};
-            double p[3] = {d[1] * e2[2] - d[2] * e2[1], d[2] * e2[0] - d[0] * e2[2], d[0] * e2[1] - d[1] * e2[0]};
-            double det = dot3(e1, p);
-            if (fabs(det) < 1e-12) continue;
-            double inv = 1.0 / det;
-            double sv[3] = {o[0] - v0[0], o[1] - v0[1], o[2] - v0[2]};
-            double u = dot3(sv, p) * inv;
-            if (u < 0.0 || u > 1.0) continue;
-            double q[3] = {sv[1] * e1[2] - sv[2] * e1[1], sv[2] * e1[0] - sv[0] * e1[2], sv[0] * e1[1] - sv[1] * e1[0]};
-            double v = dot3(d, q) * inv;
-            if (v < 0.0 || u + v > 1.0) continue;
-            double t = dot3(e2, q) * inv;
-            if (!(t > tmin_s && t <= tmax_s)) continue;
-            if (t < best) { second = best; best = t; bf = f; bu = u; bv = v; }
-            else if (t < second) second = t;
-        }
-        double A[3] = {0, 0, 0}, Rg = 0.0, M = 0.0, N[3] = {0, 0, 0};
-        if (bf >= 0) {
-            double w[3] = {1.0 - bu - bv, bu, bv};
-            for (int k = 0; k < 3; ++k) {
-                int64_t vi = tris[3 * bf + k];
-                for (int c = 0; c < 3; ++c) {
-                    A[c] += w[k] * (double)albedo[3 * vi + c];
-                    N[c] += w[k] * (double)vnormal[3 * vi + c];
-                }
-                Rg += w[k] * (double)rough[vi];
-                M += w[k] * (double)metal[vi];
-            }
-            if (dot3(N, d) > 0.0) { N[0] = -N[0]; N[1] = -N[1]; N[2] = -N[2]; }
-        }
-        outV[r] = bf >= 0 ? 0.0 : 1.0;
-        for (int c = 0; c < 3; ++c) { outA[3 * r + c] = A[c]; outN[3 * r + c] = N[c]; }
-        outR[r] = Rg;
-        outM[r] = M;
-        if (margins) {
-            double bm = 1.0 - bu - bv;
-            if (bu < bm) bm = bu;
-            if (bv < bm) bm = bv;
-            margins[2 * r] = bf >= 0 ? bm : INFINITY;
-            margins[2 * r + 1] = bf >= 0 && second < INFINITY ? (second - best) / best : INFINITY;
-        }
+        AttrOut q;
+        double mg[2];
+        mesh_query(&m, o, d, tmin_s, tmax_s, &q, mg);
+        outV[r] = q.V;
+        for (int c = 0; c < 3; ++c) { outA[3 * r + c] = q.a[c]; outN[3 * r + c] = q.n[c]; }
+        outR[r] = q.r;
+        outM[r] = q.m;
+        if (margins) { margins[2 * r] = mg[0]; margins[2 * r + 1] = mg[1]; }
     }
+    return 0;
+}
+
+/* Relighting with the mesh backend answering the attribute query (Sec.
+ * 3.5.2 leaves Eq. relight_splitsum unchanged): as orc_render_relight, the
+ * secondary rays queried against the triangle mesh instead of the surfels.
+ * Sample margins [np,spp,5] carry the mesh query's barycentric margin and
+ * depth gap in [0] and [1], the texel margin in [4]. */
+int orc_render_relight_mesh(int64_t nv, const float *verts, int64_t nf, const int32_t *tris, const float *v_albedo,
+                            const float *v_rough, const float *v_metal, const float *v_normal,
+                            const float *gx, const float *gn, const float *gwo, const float *galb, const float *grough,
+                            const float *gmetal, const uint8_t *gvalid,
+                            int eH, int eW, const float *env_rgb, const float *marg, const float *cond,
+                            const double *Ed, const double *Es, const double *lut,
+                            int nc, int ng, int ne, uint64_t seed, uint32_t job, float tmin,
+                            int64_t np, const int64_t *pix, double *out,
+                            float *s_dir, double *s_q, double *s_wt, double *s_Li, uint8_t *s_traced, float *s_margin)
+{
+    (void)nv;
+    Scene S = {0, NULL, NULL};
+    Env E = {eH, eW, env_rgb, marg, cond};
+    MisOpts op = {nc, ng, ne, seed, job, tmin, 1e-3f};
+    MeshRef m = {nf, verts, tris, v_albedo, v_rough, v_metal, v_normal};
+    Relight rl = {{NULL, NULL, NULL}, Ed, Es, lut, &m};
+    shade_pixels(&S, &E, &op, &rl, gx, gn, gwo, galb, grough, gmetal, gvalid, np, pix, out, s_dir, s_q, s_wt, s_Li,
+                 s_traced, s_margin);
     return 0;
 }

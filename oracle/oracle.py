@@ -59,6 +59,10 @@ def lib():
                                          [P] * 6)
         L.orc_mesh_trace_attr.restype = C.c_int
         L.orc_mesh_trace_attr.argtypes = [I64, P, I64, P, P, P, P, P, I64, P, P, F, F, P, P, P, P, P, P]
+        L.orc_render_relight_mesh.restype = C.c_int
+        L.orc_render_relight_mesh.argtypes = ([I64, P, I64, P, P, P, P, P] + [P] * 7 + [C.c_int, C.c_int, P, P, P] +
+                                              [P, P, P] + [C.c_int, C.c_int, C.c_int, C.c_uint64, C.c_uint32, F,
+                                                           I64, P, P] + [P] * 6)
         L.orc_trace_gbuffer.restype = C.c_int
         L.orc_trace_gbuffer.argtypes = ([I64, P, P, P, P, P, F, P, P, P, I64, P, P, F, F, F, C.c_double] + [P] * 9)
         L.orc_trace_attr.restype = C.c_int
@@ -353,6 +357,42 @@ def denoise(rgb, depth, normal, valid, H, W, radius=3, sigma_s=2.0, sigma_d=1.0,
             den[ys, xs] += B
     out = np.where(v[..., None], num / np.where(den > 0, den, 1.0)[..., None], c)
     return out.reshape(H * W, 3)
+
+
+def render_relight_mesh(m, gb, env_rgb, split, seed, pix=None, job=0, t_min=1e-3, dump=False, tables=None):
+    """Relit c_pbr with the mesh backend answering the attribute query
+    (mesh m with per-vertex attributes; otherwise as render_relight).  With
+    ``dump`` the margins carry the mesh query's barycentric margin [..., 0]
+    and depth gap [..., 1]."""
+    nc, ng, ne = split
+    spp = nc + ng + ne
+    g = _gb(gb)
+    e = _c(env_rgb)
+    marg, cond = env_cdf(e)
+    if tables is None:
+        Ed, Es = env_prefilter(e)
+        lut = dfg_lut()
+    else:
+        Ed, Es, lut = (np.ascontiguousarray(a, np.float64) for a in tables)
+    pix = np.arange(gb.npix, dtype=np.int64) if pix is None else _c(pix, np.int64)
+    npx = len(pix)
+    out = np.zeros((npx, 3))
+    d = {}
+    if dump:
+        d = dict(dir=np.zeros((npx, spp, 3), np.float32), q=np.zeros((npx, spp)), wt=np.zeros((npx, spp, 3)),
+                 Li=np.zeros((npx, spp, 3)), traced=np.zeros((npx, spp), np.uint8),
+                 margins=np.zeros((npx, spp, 5), np.float32))
+    tris = _c(m.tris, np.int32)
+    rc = lib().orc_render_relight_mesh(m.nv, _p(_c(m.verts)), m.nf, _p(tris), _p(_c(m.albedo)), _p(_c(m.rough)),
+                                       _p(_c(m.metal)), _p(_c(m.normal)), *map(_p, g), e.shape[0], e.shape[1], _p(e),
+                                       _p(marg), _p(cond), _p(Ed), _p(Es), _p(lut), nc, ng, ne, seed, job, t_min, npx,
+                                       _p(pix), _p(out), _p(d.get("dir")), _p(d.get("q")), _p(d.get("wt")),
+                                       _p(d.get("Li")), _p(d.get("traced")), _p(d.get("margins")))
+    assert rc == 0
+    if dump:
+        d["rgb"] = out
+        return d
+    return out
 
 
 def render_mis_backward(s, gb, env_rgb, split, seed, grad, pix=None, job=0, t_min=1e-3, t_cut=T_CUT,

@@ -88,3 +88,39 @@ def test_triangle_order_does_not_matter():
     assert (a["V"] < 1).sum() > 30
     for k in ("V", "albedo", "rough", "metal", "normal"):
         np.testing.assert_allclose(b[k], a[k], rtol=1e-12, atol=1e-15)
+
+
+def test_relight_through_an_empty_mesh_is_the_radiance_estimator():
+    """No triangles: every secondary ray sees the environment (V = 1), so the
+    mesh-backed relit image equals the radiance render with no geometry."""
+    gb = W.gbuffer1(16, 16, seed=2)
+    env = W.envmap(32, 64, seed=4)
+    z = np.zeros
+    m = W.Mesh(z((3, 3), np.float32), z((0, 3), np.int32), z((3, 3), np.float32), z(3, np.float32),
+               z(3, np.float32), z((3, 3), np.float32))
+    s = W.Surfels(z((0, 3), np.float32), z((0, 2), np.float32), z((0, 4), np.float32), z(0, np.float32),
+                  z((0, 3), np.float32))
+    np.testing.assert_array_equal(O.render_relight_mesh(m, gb, env, (4, 2, 2), seed=5),
+                                  O.render_mis(s, gb, env, (4, 2, 2), seed=5))
+
+
+def test_relight_under_a_mesh_ceiling():
+    """A pixel under a large two-triangle ceiling that every upward ray hits
+    (V = 0): with a constant environment L0 and metallic 1, L_i = L0 (a A + B)
+    for the interpolated albedo a, within the DFG table's range."""
+    L0 = 0.6
+    env = np.full((32, 64, 3), L0, np.float32)
+    v = np.float32([[-50, -50, 1], [50, -50, 1], [50, 50, 1], [-50, 50, 1]])
+    f = np.int32([[0, 1, 2], [0, 2, 3]])
+    m = W.Mesh(v, f, np.full((4, 3), 0.7, np.float32), np.full(4, 0.4, np.float32), np.ones(4, np.float32),
+               np.tile(np.float32([0, 0, -1]), (4, 1)))
+    gb = W.GBuffer(1, 1, np.float32([[0, 0, 0]]), np.float32([[0, 0, 1]]), np.float32([[0, 0.6, 0.8]]),
+                   np.float32([[0.5, 0.5, 0.5]]), np.float32([0.5]), np.float32([0.0]), np.uint8([1]))
+    d = O.render_relight_mesh(m, gb, env, (8, 4, 4), seed=3, dump=True)
+    lut = O.dfg_lut()
+    tr = d["traced"][0].astype(bool)
+    Li = d["Li"][0][tr]
+    assert tr.sum() > 8
+    lo, hi = L0 * (0.7 * lut[..., 0] + lut[..., 1]).min(), L0 * (0.7 * lut[..., 0] + lut[..., 1]).max()
+    assert (Li >= lo - 1e-9).all() and (Li <= hi + 1e-9).all()
+    assert np.allclose(Li[:, 0], Li[:, 1]) and np.allclose(Li[:, 1], Li[:, 2])  # grey albedo, grey light
