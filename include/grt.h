@@ -421,6 +421,15 @@ typedef struct {
 int grt_mesh_trace_attr(const grt_mesh *mesh, const grt_rays *rays, const grt_vertex_attrs *attrs, float *out_V,
                         float *out_albedo, float *out_rough, float *out_metal, float *out_normal, void *stream);
 
+/* Relighting with the mesh backend answering the attribute query (Sec.
+ * 3.5.2: Eq. relight_splitsum unchanged, only the query's backend differs):
+ * as grt_render_relight, each traced sample's (V, a, r, m, n) coming from
+ * grt_mesh_trace_attr's closest-hit query of its ray (t > t_min) against
+ * `mesh` with per-vertex `attrs`.  Same opts, workspace and env needs. */
+int grt_render_relight_mesh(const grt_mesh *mesh, const grt_env *env, const grt_vertex_attrs *attrs,
+                            const grt_gbuffer *g, const grt_mis_opts *opts, float *out_rgb, void *workspace,
+                            size_t ws_bytes, void *stream);
+
 /* Cross-bilateral denoiser for low-sample renders (Sec. 3.4.2,
  * "Denoising"), on an H x W image with its guides (device arrays, row-major
  * pixels): rgb [H*W,3] noisy colour, depth [H*W] distance from the camera,

@@ -480,11 +480,22 @@ size_t grt_render_workspace_bytes(int64_t npix, int spp)
     return grt::carve_render(nullptr, npix * spp).bytes;
 }
 
+static int fill_render_common(const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *o, grt::RenderArgs &a);
+
 static int fill_render_args(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *o,
                             grt::RenderArgs &a)
 {
     int rc = check_scene(scene);
     if (rc) return rc;
+    if ((rc = fill_render_common(env, g, o, a))) return rc;
+    a.S = scene_dev(scene);
+    return GRT_OK;
+}
+
+// everything of a render but the scene (a.S left empty)
+static int fill_render_common(const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *o, grt::RenderArgs &a)
+{
+    int rc;
     if (!env) return fail(GRT_ERR_INVALID, "env is NULL");
     if (!env->built) return fail(GRT_ERR_NOT_BUILT, "environment used before grt_env_build");
     if (!g || !o) return fail(GRT_ERR_INVALID, "gbuffer/opts is NULL");
@@ -500,7 +511,6 @@ static int fill_render_args(const grt_scene *scene, const grt_env *env, const gr
     if (!(o->t_min >= 0.0f)) return fail(GRT_ERR_INVALID, "t_min must be >= 0");
     if (!(o->t_cut >= 0.0f && o->t_cut < 1.0f)) return fail(GRT_ERR_INVALID, "t_cut must be in [0,1)");
     memset(&a, 0, sizeof(a));
-    a.S = scene_dev(scene);
     a.E.H = env->H; a.E.W = env->W; a.E.rgb = env->rgb; a.E.marg = env->w.marg; a.E.cond = env->w.cond;
     a.H = g->H; a.W = g->W;
     a.x = g->x; a.n = g->n; a.wo = g->wo; a.alb = g->albedo; a.rough = g->rough; a.metal = g->metal; a.valid = g->valid;
@@ -642,6 +652,44 @@ int grt_render_relight(const grt_scene *scene, const grt_env *env, const grt_sur
     if ((rc = set_device(scene->ctx))) return rc;
     hipError_t e = grt::launch_render_relight(a, w, opts->k, scene->ctx->num_cu, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "relight launch");
+    return GRT_OK;
+}
+
+int grt_render_relight_mesh(const grt_mesh *mesh, const grt_env *env, const grt_vertex_attrs *attrs,
+                            const grt_gbuffer *g, const grt_mis_opts *opts, float *out_rgb, void *workspace,
+                            size_t ws_bytes, void *stream)
+{
+    if (!mesh || !attrs) return fail(GRT_ERR_INVALID, "mesh/attrs is NULL");
+    if (!mesh->built) return fail(GRT_ERR_NOT_BUILT, "mesh used before grt_mesh_build");
+    grt::RenderArgs a;
+    int rc = fill_render_common(env, g, opts, a);
+    if (rc) return rc;
+    if (!env->prefiltered) return fail(GRT_ERR_NOT_BUILT, "relighting needs grt_env_prefilter first");
+    if (mesh->m.nf > 0 && (!attrs->albedo || !attrs->rough || !attrs->metal || !attrs->normal))
+        return fail(GRT_ERR_INVALID, "a vertex attribute array is NULL");
+    if ((int64_t)g->H * g->W > 0 && !out_rgb) return fail(GRT_ERR_INVALID, "out_rgb is NULL");
+    if (opts->hit_list) return fail(GRT_ERR_INVALID, "relighting stores no hit lists");
+    a.E.Ed = env->w.Ed; a.E.Es = env->w.Es; a.E.lut = env->w.lut;
+    a.out = out_rgb;
+    a.dump = opts->sample_dump;
+    const int spp = opts->n_cos + opts->n_ggx + opts->n_env;
+    if ((rc = check_ws(workspace, ws_bytes, grt_render_workspace_bytes((int64_t)g->H * g->W, spp), "relight")))
+        return rc;
+    const grt::RenderWS w = grt::carve_render(workspace, (int64_t)g->H * g->W * spp);
+    a.counters = w.counters;
+    a.contrib = w.contrib;
+    a.rays = w.rays;
+    a.order = nullptr;
+    a.rl_nx = reinterpret_cast<float *>(w.k0);
+    a.rl_ny = reinterpret_cast<float *>(w.v0);
+    a.rl_nz = reinterpret_cast<float *>(w.k1);
+    grt::MeshTraceArgs m{};
+    m.nv = (int)mesh->m.nv; m.nf = (int)mesh->m.nf;
+    m.rec = mesh->w.rec; m.nodes = mesh->w.nodes; m.tris = mesh->m.tris;
+    m.albedo = attrs->albedo; m.rough = attrs->rough; m.metal = attrs->metal; m.vnormal = attrs->normal;
+    if ((rc = set_device(mesh->ctx))) return rc;
+    hipError_t e = grt::launch_render_relight_mesh(a, m, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "mesh relight launch");
     return GRT_OK;
 }
 

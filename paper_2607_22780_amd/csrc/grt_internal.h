@@ -328,6 +328,10 @@ hipError_t launch_render_gen(const RenderArgs &a, hipStream_t st);
 // Split-sum relighting (needs a.E's prefiltered tables and a.sa_*): the
 // forward render with the attribute query and Eq. relight_splitsum.
 hipError_t launch_render_relight(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st);
+// relighting through the mesh: the query pass over a render's ray records
+// (m's ray fields unused), then the surfel relight's shading pass
+hipError_t launch_mesh_relight_query(const RenderArgs &a, const MeshTraceArgs &m, hipStream_t st);
+hipError_t launch_render_relight_mesh(const RenderArgs &a, const MeshTraceArgs &m, hipStream_t st);
 // Order the traced samples for coherent traversal: by direction bin, then by
 // the Morton code of the origin in the scene's root box (untraced last).
 // Sets nothing on the host; a.order must point at w.v1 afterwards.

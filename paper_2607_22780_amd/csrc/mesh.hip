@@ -121,33 +121,33 @@ __device__ __forceinline__ bool tri_hit(const float4 r0, const float4 r1, const 
 
 constexpr int kMeshStack = 64;  // LBVH depth <= 63: one far child per level
 
-__global__ void __launch_bounds__(256) k_mesh_trace_attr(MeshTraceArgs a)
+// Closest hit of one ray: triangle id (0xffffffff: miss) and barycentrics.
+__device__ __forceinline__ void mesh_closest(const float4 *__restrict__ rec, const Node *__restrict__ nodes, int nf,
+                                             float3 o, float3 d, float tmin, float tmax, uint32_t &bid, float &bu,
+                                             float &bv)
 {
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= a.n) return;
-    const float3 o = make_float3(a.o[3 * r], a.o[3 * r + 1], a.o[3 * r + 2]);
-    const float3 d = make_float3(a.d[3 * r], a.d[3 * r + 1], a.d[3 * r + 2]);
     const float3 inv = make_float3(safe_inv(d.x), safe_inv(d.y), safe_inv(d.z));
-    float best = a.tmax, bu = 0.0f, bv = 0.0f;
-    uint32_t bid = 0xffffffffu;
+    float best = tmax;
+    bu = 0.0f; bv = 0.0f;
+    bid = 0xffffffffu;
     int stack[kMeshStack];
     int sp = 0;
-    int cur = a.nf <= 0 ? kNone : (a.nf == 1 ? -1 : 0);
+    int cur = nf <= 0 ? kNone : (nf == 1 ? -1 : 0);
     while (cur != kNone) {
         if (cur < 0) {  // leaf: triangle record -(cur + 1)
-            const float4 *rr = a.rec + 3 * (size_t)(-cur - 1);
+            const float4 *rr = rec + 3 * (size_t)(-cur - 1);
             const float4 r0 = rr[0], r1 = rr[1], r2 = rr[2];
             float t, u, v;
-            if (tri_hit(r0, r1, r2, o, d, a.tmin, best, bid, t, u, v)) {
+            if (tri_hit(r0, r1, r2, o, d, tmin, best, bid, t, u, v)) {
                 best = t; bu = u; bv = v; bid = __float_as_uint(r0.w);
             }
             cur = sp > 0 ? stack[--sp] : kNone;
             continue;
         }
-        const Node nd = a.nodes[cur];
+        const Node nd = nodes[cur];
         float tl, tr;
-        const bool hl = slab(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, o, inv, a.tmin, best, tl);
-        const bool hr = slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, o, inv, a.tmin, best, tr);
+        const bool hl = slab(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, o, inv, tmin, best, tl);
+        const bool hr = slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, o, inv, tmin, best, tr);
         if (hl && hr) {
             const bool lf = tl <= tr;
             if (sp < kMeshStack) stack[sp++] = lf ? nd.d.y : nd.d.x;
@@ -160,28 +160,88 @@ __global__ void __launch_bounds__(256) k_mesh_trace_attr(MeshTraceArgs a)
             cur = sp > 0 ? stack[--sp] : kNone;
         }
     }
-    float V = 1.0f, A[3] = {0.f, 0.f, 0.f}, R = 0.0f, M = 0.0f, N[3] = {0.f, 0.f, 0.f};
-    if (bid != 0xffffffffu && bid < (uint32_t)a.nf) {
-        V = 0.0f;
-        const float w[3] = {1.0f - bu - bv, bu, bv};
+}
+
+// Barycentric vertex attributes of the hit (the normal facing the ray
+// origin); V = 1 and zeros on a miss.
+struct MeshHitAttrs {
+    float V, A[3], R, M, N[3];
+};
+__device__ __forceinline__ MeshHitAttrs mesh_attrs(const int32_t *__restrict__ tris, int nf, const float *albedo,
+                                                   const float *rough, const float *metal, const float *vnormal,
+                                                   uint32_t bid, float bu, float bv, float3 d)
+{
+    MeshHitAttrs h = {1.0f, {0.f, 0.f, 0.f}, 0.0f, 0.0f, {0.f, 0.f, 0.f}};
+    if (bid == 0xffffffffu || bid >= (uint32_t)nf) return h;
+    h.V = 0.0f;
+    const float w[3] = {1.0f - bu - bv, bu, bv};
 #pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const int vi = a.tris[3 * (size_t)bid + k];  // valid: degenerate triangles are never hit
+    for (int k = 0; k < 3; ++k) {
+        const int vi = tris[3 * (size_t)bid + k];  // valid: degenerate triangles are never hit
 #pragma unroll
-            for (int c = 0; c < 3; ++c) {
-                A[c] += w[k] * a.albedo[3 * (size_t)vi + c];
-                N[c] += w[k] * a.vnormal[3 * (size_t)vi + c];
-            }
-            R += w[k] * a.rough[vi];
-            M += w[k] * a.metal[vi];
+        for (int c = 0; c < 3; ++c) {
+            h.A[c] += w[k] * albedo[3 * (size_t)vi + c];
+            h.N[c] += w[k] * vnormal[3 * (size_t)vi + c];
         }
-        if (N[0] * d.x + N[1] * d.y + N[2] * d.z > 0.0f) { N[0] = -N[0]; N[1] = -N[1]; N[2] = -N[2]; }
+        h.R += w[k] * rough[vi];
+        h.M += w[k] * metal[vi];
     }
-    a.out_V[r] = V;
+    if (h.N[0] * d.x + h.N[1] * d.y + h.N[2] * d.z > 0.0f) { h.N[0] = -h.N[0]; h.N[1] = -h.N[1]; h.N[2] = -h.N[2]; }
+    return h;
+}
+
+__global__ void __launch_bounds__(256) k_mesh_trace_attr(MeshTraceArgs a)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= a.n) return;
+    const float3 o = make_float3(a.o[3 * r], a.o[3 * r + 1], a.o[3 * r + 2]);
+    const float3 d = make_float3(a.d[3 * r], a.d[3 * r + 1], a.d[3 * r + 2]);
+    uint32_t bid;
+    float bu, bv;
+    mesh_closest(a.rec, a.nodes, a.nf, o, d, a.tmin, a.tmax, bid, bu, bv);
+    const MeshHitAttrs h = mesh_attrs(a.tris, a.nf, a.albedo, a.rough, a.metal, a.vnormal, bid, bu, bv, d);
+    a.out_V[r] = h.V;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) { a.out_albedo[3 * r + c] = A[c]; a.out_normal[3 * r + c] = N[c]; }
-    a.out_rough[r] = R;
-    a.out_metal[r] = M;
+    for (int c = 0; c < 3; ++c) { a.out_albedo[3 * r + c] = h.A[c]; a.out_normal[3 * r + c] = h.N[c]; }
+    a.out_rough[r] = h.R;
+    a.out_metal[r] = h.M;
+}
+
+// Relighting through the mesh, query pass: for every traced sample of the
+// render's ray records, the mesh query parked for the shading pass as the
+// surfel relight parks it ((V, albedo) in the contribution slot, (r, m) in
+// the ray record's spare words, the normal in rl_n*).
+__global__ void __launch_bounds__(256) k_mesh_relight_query(RenderArgs a, MeshTraceArgs m, int64_t total)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= total) return;
+    const float4 r0 = a.rays[3 * r];
+    if (r0.w == 0.0f) {
+        a.contrib[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+        return;
+    }
+    const int64_t p = r / (a.nc + a.ng + a.ne);
+    const float3 x = make_float3(a.x[3 * p], a.x[3 * p + 1], a.x[3 * p + 2]);
+    const float3 d = make_float3(r0.x, r0.y, r0.z);
+    uint32_t bid;
+    float bu, bv;
+    mesh_closest(m.rec, m.nodes, m.nf, x, d, a.tmin, INFINITY, bid, bu, bv);
+    const MeshHitAttrs h = mesh_attrs(m.tris, m.nf, m.albedo, m.rough, m.metal, m.vnormal, bid, bu, bv, d);
+    a.contrib[r] = make_float4(h.V, h.A[0], h.A[1], h.A[2]);
+    float4 *r2 = a.rays + 3 * r + 2;
+    r2->z = h.R;
+    r2->w = h.M;
+    a.rl_nx[r] = h.N[0];
+    a.rl_ny[r] = h.N[1];
+    a.rl_nz[r] = h.N[2];
+}
+
+hipError_t launch_mesh_relight_query(const RenderArgs &a, const MeshTraceArgs &m, hipStream_t st)
+{
+    const int64_t total = (int64_t)a.H * a.W * (a.nc + a.ng + a.ne);
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_mesh_relight_query, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a, m, total);
+    return hipGetLastError();
 }
 
 hipError_t launch_mesh_trace_attr(const MeshTraceArgs &a, hipStream_t st)

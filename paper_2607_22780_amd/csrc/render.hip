@@ -604,6 +604,20 @@ hipError_t launch_render_relight(const RenderArgs &a, const RenderWS &w, int k, 
     return hipGetLastError();
 }
 
+hipError_t launch_render_relight_mesh(const RenderArgs &a, const MeshTraceArgs &m, hipStream_t st)
+{
+    const int64_t npix = (int64_t)a.H * a.W;
+    if (npix <= 0) return hipSuccess;
+    hipError_t e = launch_render_gen(a, st);
+    if (e != hipSuccess) return e;
+    if ((e = launch_mesh_relight_query(a, m, st)) != hipSuccess) return e;
+    const int64_t total = npix * (a.nc + a.ng + a.ne);
+    hipLaunchKernelGGL(k_relight_shade, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a, total);
+    hipLaunchKernelGGL(k_render_reduce, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st, npix,
+                       a.nc + a.ng + a.ne, a.contrib, a.out);
+    return hipGetLastError();
+}
+
 hipError_t launch_render_backward(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st)
 {
     if ((int64_t)a.H * a.W <= 0) return hipSuccess;

@@ -137,6 +137,8 @@ SIGNATURES = {
     "grt_mesh_build": (C.c_int, [VP, VP]),
     "grt_mesh_destroy": (C.c_int, [VP]),
     "grt_mesh_trace_attr": (C.c_int, [VP, P(grt_rays), P(grt_vertex_attrs), VP, VP, VP, VP, VP, VP]),
+    "grt_render_relight_mesh": (C.c_int, [VP, VP, P(grt_vertex_attrs), P(grt_gbuffer), P(grt_mis_opts), VP, VP,
+                                          C.c_size_t, VP]),
     "grt_denoise": (C.c_int, [VP, C.c_int, C.c_int, VP, VP, VP, VP, P(grt_denoise_opts), VP, VP]),
     "grt_env_relight_tables": (C.c_int, [VP, P(VP), P(VP), P(VP)]),
     "grt_render_relight": (C.c_int, [VP, VP, P(grt_surfel_attrs), P(grt_gbuffer), P(grt_mis_opts), VP, VP,
@@ -710,6 +712,28 @@ def mesh_trace_attr(mesh: Mesh, albedo, rough, metal, normal, origins, dirs, t_m
                                               _ptr(out["albedo"]), _ptr(out["rough"]), _ptr(out["metal"]),
                                               _ptr(out["normal"]), _stream(stream)))
     return out
+
+
+def render_relight_mesh(mesh: Mesh, env: Env, albedo, rough, metal, normal, gb, split=(16, 8, 8), seed=0, job=0,
+                        t_min=1e-3, dump=False, workspace=None, stream=None):
+    """Relit c_pbr [npix,3] under the prefiltered `env` with the mesh backend
+    answering the attribute query (per-vertex albedo, rough, metal, normal)."""
+    dev = gb.x.device
+    spp = sum(split)
+    out = torch.empty(gb.npix, 3, device=dev)
+    dmp = torch.zeros(gb.npix, spp, 10, device=dev) if dump else None
+    opts = make_mis_opts(split, seed, job, t_min, 1e-3, 12, dmp)
+    va = grt_vertex_attrs(_ptr(albedo), _ptr(rough), _ptr(metal), _ptr(normal))
+    need = grt_render_workspace_bytes(gb.npix, spp)
+    if workspace is None or workspace.numel() < need:
+        workspace = _workspace(need, dev)
+    _check(load_library().grt_render_relight_mesh(mesh.handle, env.handle, C.byref(va), C.byref(gb.struct()),
+                                                  C.byref(opts), _ptr(out), _ptr(workspace), workspace.numel(),
+                                                  _stream(stream)))
+    res = dict(rgb=out)
+    if dump:
+        res["dump"] = dmp
+    return res
 
 
 def denoise(ctx: Context, rgb, depth, normal, valid, H: int, W: int, radius=3, sigma_s=2.0, sigma_d=1.0,

@@ -89,3 +89,35 @@ def test_bad_indices_are_ignored_and_empty_mesh(grt_ctx):
     empty = W.Mesh(m.verts, np.zeros((0, 3), np.int32), m.albedo, m.rough, m.metal, m.normal)
     out = run(grt, ctx, empty, o, d)
     assert (out["V"] == 1).all() and not out["albedo"].any()
+
+
+def test_relight_through_the_mesh(grt_ctx):
+    """Relighting with the mesh backend on the room mesh and a 32x32 room
+    G-buffer: per-sample incident radiance and pixels against the oracle;
+    samples whose mesh query sits on a knife edge (barycentric margin or depth
+    gap below 1e-5, or a texel edge) are excused."""
+    grt, ctx = grt_ctx
+    from gpu_util import t
+    m = W.mesh3()
+    gb = W.gbuffer3(32, 32)
+    env = W.envmap(32, 64, seed=8)
+    mesh = grt.Mesh(ctx, t(m.verts), t(m.tris))
+    E = grt.Env(ctx, t(env)).prefilter()
+    G = grt.GBuffer.from_numpy(gb, torch.device("cuda", 0))
+    res = grt.render_relight_mesh(mesh, E, t(m.albedo), t(m.rough), t(m.metal), t(m.normal), G, split=(4, 2, 2),
+                                  seed=7, dump=True)
+    torch.cuda.synchronize()
+    gpu = {k: v.cpu().numpy() for k, v in res.items()}
+    ref = O.render_relight_mesh(m, gb, env, (4, 2, 2), seed=7, dump=True)
+    d = gpu["dump"]
+    traced = ref["traced"].astype(bool)
+    same_dir = np.all(d[..., 0:3] == ref["dir"], axis=-1)
+    assert same_dir.mean() >= 0.9999
+    mg = ref["margins"]
+    edge = (mg[..., 0] < 1e-5) | (mg[..., 1] < 1e-5) | (mg[..., 4] < 1e-9) | ~same_dir
+    ok = traced & ~edge & (d[..., 3] > 0)
+    np.testing.assert_allclose(d[..., 7:10][ok], ref["Li"][ok], rtol=1e-4, atol=1e-5)
+    assert edge[traced].mean() < 0.01
+    bad_px = edge.any(axis=1)
+    np.testing.assert_allclose(gpu["rgb"][~bad_px], ref["rgb"][~bad_px], rtol=1e-3, atol=1e-5)
+    assert ok.sum() > 2000
