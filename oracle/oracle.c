@@ -280,6 +280,62 @@ static void trace_ray(const Scene *S, const float o[3], const float d[3], float 
  * p = r_o + tau r_d, tau = n.(mu - r_o)/(n.r_d), and the quaternion frame.
  * Gradients are accumulated into g (13 doubles per surfel:
  * mean 3, scale 2, quat 4, opacity 1, rgb 3). */
+/* Chain rule of one composited hit (the hit's alpha through rho^2 = u^2 + v^2
+ * of the tangent-plane crossing, Sec. 3.1): from dL/dalpha (dA), dL/dtau
+ * (dtau, the hit's depth along the ray) and a direct dL/dn (dnx, NULL = none)
+ * to the stored parameters, out[10] = (mean 3, scale 2, quaternion 4,
+ * opacity).  The crossing point is x = o + tau d with
+ * tau = n.(mu - o) / n.d, so tau moves with mu and n. */
+static void hit_chain(const Surf64 *s, const float d[3], const Geo64 *g, double dA, double dtau,
+                      const double dnx[3], double out[10])
+{
+    double a = g->alpha;
+    double gamma = -0.5 * a * dA;            /* dL/d(rho^2) */
+    double du = 2.0 * g->u * gamma, dv = 2.0 * g->v * gamma;
+    double dsu = -(g->u / s->su) * du, dsv = -(g->v / s->sv) * dv;
+    double gD[3], dtu[3], dtv[3], dn[3], dmu[3];
+    for (int i = 0; i < 3; ++i) gD[i] = du * s->tu[i] / s->su + dv * s->tv[i] / s->sv;
+    /* total dL/dtau: through the crossing point, plus the direct term */
+    double gDd = (gD[0] * d[0] + gD[1] * d[1] + gD[2] * d[2] + dtau) / g->den;
+    for (int i = 0; i < 3; ++i) {
+        dmu[i] = gDd * s->n[i] - gD[i];
+        dtu[i] = du * g->D[i] / s->su;
+        dtv[i] = dv * g->D[i] / s->sv;
+        dn[i] = -gDd * g->D[i] + (dnx ? dnx[i] : 0.0);
+    }
+    /* columns of R(q) -> unit quaternion (w,x,y,z) */
+    double qw = s->qhat[0], qx = s->qhat[1], qy = s->qhat[2], qz = s->qhat[3];
+    double dq[4];
+    dq[0] = dtu[1] * (2 * qz) + dtu[2] * (-2 * qy)
+          + dtv[0] * (-2 * qz) + dtv[2] * (2 * qx)
+          + dn[0] * (2 * qy) + dn[1] * (-2 * qx);
+    dq[1] = dtu[1] * (2 * qy) + dtu[2] * (2 * qz)
+          + dtv[0] * (2 * qy) + dtv[1] * (-4 * qx) + dtv[2] * (2 * qw)
+          + dn[0] * (2 * qz) + dn[1] * (-2 * qw) + dn[2] * (-4 * qx);
+    dq[2] = dtu[0] * (-4 * qy) + dtu[1] * (2 * qx) + dtu[2] * (-2 * qw)
+          + dtv[0] * (2 * qx) + dtv[2] * (2 * qz)
+          + dn[0] * (2 * qw) + dn[1] * (2 * qz) + dn[2] * (-4 * qy);
+    dq[3] = dtu[0] * (-4 * qz) + dtu[1] * (2 * qw) + dtu[2] * (2 * qx)
+          + dtv[0] * (-2 * qw) + dtv[1] * (-4 * qz) + dtv[2] * (2 * qy)
+          + dn[0] * (2 * qx) + dn[1] * (2 * qy);
+    /* unit quaternion -> stored quaternion: (I - qhat qhat^T) / |q| */
+    double proj = qw * dq[0] + qx * dq[1] + qy * dq[2] + qz * dq[3];
+    out[0] = dmu[0]; out[1] = dmu[1]; out[2] = dmu[2];
+    out[3] = dsu; out[4] = dsv;
+    for (int i = 0; i < 4; ++i) out[5 + i] = (dq[i] - s->qhat[i] * proj) / s->qlen;
+    out[9] = g->G * dA;
+}
+
+static void add_grads(double *dst, const double *src, int m)
+{
+    for (int i = 0; i < m; ++i) {
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+        dst[i] += src[i];
+    }
+}
+
 static void backward_ray(const Scene *S, const float o[3], const float d[3], const RayResult *R,
                          const double gC[3], double gT, double *g13)
 {
@@ -297,48 +353,10 @@ static void backward_ray(const Scene *S, const float o[3], const float d[3], con
             double behind = gC[0] * (R->C[0] - P[0]) + gC[1] * (R->C[1] - P[1]) + gC[2] * (R->C[2] - P[2]) + gT * R->T;
             dA -= behind / (1.0 - a);
         }
-        double drgb[3] = {w * gC[0], w * gC[1], w * gC[2]};
-        double dop = g.G * dA;
-        double gamma = -0.5 * a * dA;            /* dL/d(rho^2) */
-        double du = 2.0 * g.u * gamma, dv = 2.0 * g.v * gamma;
-        double dsu = -(g.u / s->su) * du, dsv = -(g.v / s->sv) * dv;
-        double gD[3], dtu[3], dtv[3], dn[3], dmu[3];
-        for (int i = 0; i < 3; ++i) gD[i] = du * s->tu[i] / s->su + dv * s->tv[i] / s->sv;
-        double gDd = (gD[0] * d[0] + gD[1] * d[1] + gD[2] * d[2]) / g.den;
-        for (int i = 0; i < 3; ++i) {
-            dmu[i] = gDd * s->n[i] - gD[i];
-            dtu[i] = du * g.D[i] / s->su;
-            dtv[i] = dv * g.D[i] / s->sv;
-            dn[i] = -gDd * g.D[i];
-        }
-        /* columns of R(q) -> unit quaternion (w,x,y,z) */
-        double qw = s->qhat[0], qx = s->qhat[1], qy = s->qhat[2], qz = s->qhat[3];
-        double dq[4];
-        dq[0] = dtu[1] * (2 * qz) + dtu[2] * (-2 * qy)
-              + dtv[0] * (-2 * qz) + dtv[2] * (2 * qx)
-              + dn[0] * (2 * qy) + dn[1] * (-2 * qx);
-        dq[1] = dtu[1] * (2 * qy) + dtu[2] * (2 * qz)
-              + dtv[0] * (2 * qy) + dtv[1] * (-4 * qx) + dtv[2] * (2 * qw)
-              + dn[0] * (2 * qz) + dn[1] * (-2 * qw) + dn[2] * (-4 * qx);
-        dq[2] = dtu[0] * (-4 * qy) + dtu[1] * (2 * qx) + dtu[2] * (-2 * qw)
-              + dtv[0] * (2 * qx) + dtv[2] * (2 * qz)
-              + dn[0] * (2 * qw) + dn[1] * (2 * qz) + dn[2] * (-4 * qy);
-        dq[3] = dtu[0] * (-4 * qz) + dtu[1] * (2 * qw) + dtu[2] * (2 * qx)
-              + dtv[0] * (-2 * qw) + dtv[1] * (-4 * qz) + dtv[2] * (2 * qy)
-              + dn[0] * (2 * qx) + dn[1] * (2 * qy);
-        /* unit quaternion -> stored quaternion: (I - qhat qhat^T) / |q| */
-        double proj = qw * dq[0] + qx * dq[1] + qy * dq[2] + qz * dq[3];
-        double dqs[4] = {(dq[0] - qw * proj) / s->qlen, (dq[1] - qx * proj) / s->qlen,
-                         (dq[2] - qy * proj) / s->qlen, (dq[3] - qz * proj) / s->qlen};
-        double *gg = g13 + 13 * id;
-        double add[13] = {dmu[0], dmu[1], dmu[2], dsu, dsv, dqs[0], dqs[1], dqs[2], dqs[3], dop,
-                          drgb[0], drgb[1], drgb[2]};
-        for (int i = 0; i < 13; ++i) {
-#ifdef _OPENMP
-#pragma omp atomic
-#endif
-            gg[i] += add[i];
-        }
+        double add[13];
+        hit_chain(s, d, &g, dA, 0.0, NULL, add);
+        for (int c = 0; c < 3; ++c) add[10 + c] = w * gC[c];
+        add_grads(g13 + 13 * id, add, 13);
         T *= 1.0 - a;
     }
 }
@@ -514,6 +532,123 @@ int orc_trace_gbuffer(int64_t n, const float *means, const float *scales, const 
         ometal[r] = valid ? q.m : 0.0;
         odepth[r] = valid ? D : 0.0;
         ovalid[r] = (uint8_t)valid;
+        free(R.h);
+    }
+    scene_free(&S);
+    return 0;
+}
+
+/* Gradient of the primary-ray G-buffer of orc_trace_gbuffer (Eq.
+ * deferred_maps on traced camera rays):
+ *   L = sum over covered pixels of gx.x + gn.n + ga.albedo + gr rough
+ *       + gm metal + gd depth + gc.rgb
+ * with upstream gradients gx, gn, ga, gc [R,3] and gr, gm, gd [R] (double,
+ * NULL = zero).  An uncovered pixel's maps are constant zeros, and the
+ * coverage test itself is not differentiated.  g13 [n,13] (as
+ * orc_trace_backward) and gattr [n,5] (albedo 3, roughness, metallic) are
+ * overwritten.
+ * Written from the definitions: every map is a ratio S_f / W of blended sums
+ * S_f = sum_k w_k f_k, W = sum_k w_k, w_k = T_k alpha_k, and
+ * n = N / |N| with N = sum_k w_k s_k n_k (s_k turns the surfel normal toward
+ * the camera).  With the hits' values held fixed, dL/dw_k = e_k, and
+ * w_i depends on alpha_k through T_i for i > k:
+ *   dw_k/dalpha_k = T_k,  dw_i/dalpha_k = -alpha_i prod_{j<i, j!=k} (1 - alpha_j).
+ * The hit's depth tau_k, normal n_k, colour and attributes get their direct
+ * terms w_k dL/dS_f. */
+int orc_trace_gbuffer_backward(int64_t n, const float *means, const float *scales, const float *quats,
+                               const float *opacity, const float *rgb, float alpha_min, const float *albedo,
+                               const float *rough, const float *metal, int64_t nr, const float *orig,
+                               const float *dirs, float tmin_s, float tmax_s, float t_cut, double min_opacity,
+                               const double *gx, const double *gn, const double *ga, const double *gr,
+                               const double *gm, const double *gd, const double *gc, double *g13, double *gattr)
+{
+    Scene S;
+    if (scene_init(&S, n, means, scales, quats, opacity, rgb, alpha_min)) return -1;
+    memset(g13, 0, sizeof(double) * 13 * (size_t)n);
+    memset(gattr, 0, sizeof(double) * 5 * (size_t)n);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < nr; ++r) {
+        const float *o = orig + 3 * r, *d = dirs + 3 * r;
+        RayResult R;
+        trace_ray(&S, o, d, tmin_s, tmax_s, t_cut, &R);
+        int64_t K = R.K;
+        Geo64 *geo = (Geo64 *)malloc(sizeof(Geo64) * (size_t)(K > 0 ? K : 1));
+        double *Tk = (double *)malloc(sizeof(double) * (size_t)(K > 0 ? K : 1));
+        double *e = (double *)malloc(sizeof(double) * (size_t)(K > 0 ? K : 1));
+        /* forward sums */
+        double T = 1.0, W = 0.0, SD = 0.0, SA[3] = {0, 0, 0}, SR = 0.0, SM = 0.0, SC[3] = {0, 0, 0};
+        double N[3] = {0, 0, 0};
+        for (int64_t k = 0; k < K; ++k) {
+            int64_t id = R.h[k].id;
+            const Surf64 *sf = &S.s64[id];
+            geo64(sf, o, d, &geo[k]);
+            Tk[k] = T;
+            double w = T * geo[k].alpha;
+            double sgn = geo[k].den > 0.0 ? -1.0 : 1.0;
+            W += w;
+            SD += w * geo[k].tau;
+            for (int c = 0; c < 3; ++c) {
+                SA[c] += w * (double)albedo[3 * id + c];
+                SC[c] += w * sf->c[c];
+                N[c] += w * sgn * sf->n[c];
+            }
+            SR += w * (double)rough[id];
+            SM += w * (double)metal[id];
+            T *= 1.0 - geo[k].alpha;
+        }
+        double nbar = W > 0.0 ? sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]) / W : 0.0;
+        int valid = 1.0 - R.T >= min_opacity && W > 0.0 && nbar > 0.0;
+        if (valid) {
+            double D = SD / W, A[3], C[3], Rm = SR / W, Mm = SM / W;
+            double nl = sqrt(N[0] * N[0] + N[1] * N[1] + N[2] * N[2]), nh[3];
+            for (int c = 0; c < 3; ++c) {
+                A[c] = SA[c] / W;
+                C[c] = SC[c] / W;
+                nh[c] = N[c] / nl;
+            }
+            const double zero3[3] = {0, 0, 0};
+            const double *pgx = gx ? gx + 3 * r : zero3, *pgn = gn ? gn + 3 * r : zero3;
+            const double *pga = ga ? ga + 3 * r : zero3, *pgc = gc ? gc + 3 * r : zero3;
+            double grr = gr ? gr[r] : 0.0, gmm = gm ? gm[r] : 0.0;
+            /* x = o + D d: the hit-point map moves with the depth only */
+            double gD = (gd ? gd[r] : 0.0) + pgx[0] * d[0] + pgx[1] * d[1] + pgx[2] * d[2];
+            /* d(N/|N|)/dN applied to gn */
+            double ndg = nh[0] * pgn[0] + nh[1] * pgn[1] + nh[2] * pgn[2], gN[3];
+            for (int c = 0; c < 3; ++c) gN[c] = (pgn[c] - nh[c] * ndg) / nl;
+            for (int64_t k = 0; k < K; ++k) {
+                int64_t id = R.h[k].id;
+                const Surf64 *sf = &S.s64[id];
+                double sgn = geo[k].den > 0.0 ? -1.0 : 1.0, ek = gD * (geo[k].tau - D);
+                for (int c = 0; c < 3; ++c)
+                    ek += pga[c] * ((double)albedo[3 * id + c] - A[c]) + pgc[c] * (sf->c[c] - C[c]);
+                ek += grr * ((double)rough[id] - Rm) + gmm * ((double)metal[id] - Mm);
+                e[k] = ek / W + sgn * (sf->n[0] * gN[0] + sf->n[1] * gN[1] + sf->n[2] * gN[2]);
+            }
+            for (int64_t k = 0; k < K; ++k) {
+                int64_t id = R.h[k].id;
+                const Surf64 *sf = &S.s64[id];
+                double dA = e[k] * Tk[k], prod = Tk[k];
+                for (int64_t i = k + 1; i < K; ++i) {
+                    dA -= e[i] * geo[i].alpha * prod;
+                    prod *= 1.0 - geo[i].alpha;
+                }
+                double w = Tk[k] * geo[k].alpha, sgn = geo[k].den > 0.0 ? -1.0 : 1.0;
+                double dnx[3] = {w * sgn * gN[0], w * sgn * gN[1], w * sgn * gN[2]};
+                double add[13], at[5];
+                hit_chain(sf, d, &geo[k], dA, w * gD / W, dnx, add);
+                for (int c = 0; c < 3; ++c) {
+                    add[10 + c] = w * pgc[c] / W;
+                    at[c] = w * pga[c] / W;
+                }
+                at[3] = w * grr / W;
+                at[4] = w * gmm / W;
+                add_grads(g13 + 13 * id, add, 13);
+                add_grads(gattr + 5 * id, at, 5);
+            }
+        }
+        free(geo);
+        free(Tk);
+        free(e);
         free(R.h);
     }
     scene_free(&S);

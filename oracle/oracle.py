@@ -65,6 +65,9 @@ def lib():
                                                            I64, P, P] + [P] * 6)
         L.orc_trace_gbuffer.restype = C.c_int
         L.orc_trace_gbuffer.argtypes = ([I64, P, P, P, P, P, F, P, P, P, I64, P, P, F, F, F, C.c_double] + [P] * 9)
+        L.orc_trace_gbuffer_backward.restype = C.c_int
+        L.orc_trace_gbuffer_backward.argtypes = ([I64, P, P, P, P, P, F, P, P, P, I64, P, P, F, F, F, C.c_double]
+                                                 + [P] * 9)
         L.orc_trace_attr.restype = C.c_int
         L.orc_trace_attr.argtypes = [I64, P, P, P, P, F, P, P, P, I64, P, P, F, F, F, P, P, P, P, P]
         if hasattr(L, "orc_count_work"):
@@ -177,6 +180,31 @@ def trace_gbuffer(s, attrs, origins, dirs, t_min=0.0, t_max=np.inf, t_cut=T_CUT,
                                                         "valid")))
     assert rc == 0
     return out
+
+
+GBUF_GRAD_KEYS = ("x", "n", "albedo", "rough", "metal", "depth", "rgb")
+
+
+def trace_gbuffer_backward(s, attrs, origins, dirs, grads, t_min=0.0, t_max=np.inf, t_cut=T_CUT,
+                           alpha_min=ALPHA_MIN, min_opacity=0.5):
+    """d/d(surfels, attributes) of the sum over covered pixels of
+    grads[k] . map_k for the maps of trace_gbuffer (keys x, n, albedo, rough,
+    metal, depth, rgb; missing keys are zero).  Returns (g13 [N,13] as
+    trace_backward, gattr [N,5] = albedo 3, roughness, metallic)."""
+    arrs = _scene(s)
+    alb, rough, metal = (_c(a) for a in attrs)
+    o = _c(origins); d = _c(dirs)
+    R = o.shape[0]
+    shape = dict(x=(R, 3), n=(R, 3), albedo=(R, 3), rgb=(R, 3), rough=(R,), metal=(R,), depth=(R,))
+    gp = {k: (_c(grads[k], np.float64).reshape(shape[k]) if grads.get(k) is not None else None)
+          for k in GBUF_GRAD_KEYS}
+    g13 = np.zeros((s.n, 13)); ga = np.zeros((s.n, 5))
+    rc = lib().orc_trace_gbuffer_backward(s.n, *map(_p, arrs), alpha_min, _p(alb), _p(rough), _p(metal), R, _p(o),
+                                          _p(d), float(t_min), float(t_max), t_cut, float(min_opacity),
+                                          *(_p(gp[k]) for k in ("x", "n", "albedo", "rough", "metal", "depth",
+                                                                "rgb")), _p(g13), _p(ga))
+    assert rc == 0
+    return g13, ga
 
 
 def trace_backward(s, origins, dirs, gC, gT, t_min=0.0, t_max=np.inf, t_cut=T_CUT, alpha_min=ALPHA_MIN):
