@@ -390,7 +390,21 @@ def main():
             torch.cuda.synchronize()
             gt.append(ef0.elapsed_time(ef1))
         covered = float(gbt["valid"].float().mean().item())
-        del gbt
+        # its backward by re-traversal, seeded upstream gradients on every map
+        gen = torch.Generator(device=dev).manual_seed(SEED)
+        gup = {kk: torch.randn(gbt[kk].shape, generator=gen, device=dev)
+               for kk in ("x", "n", "albedo", "rough", "metal", "depth", "rgb")}
+        gzs = grt.zero_grads(scene.n, dev)
+        gza = dict(albedo=torch.zeros(scene.n, 3, device=dev), rough=torch.zeros(scene.n, device=dev),
+                   metal=torch.zeros(scene.n, device=dev))
+        gbw = []
+        for _ in range(3):
+            ef0.record(st)
+            grt.trace_gbuffer_backward(scene, *mats, co, cd, gbt, gup, k=args.k, grads=gzs, attr_grads=gza)
+            ef1.record(st)
+            torch.cuda.synchronize()
+            gbw.append(ef0.elapsed_time(ef1))
+        del gbt, gup, gzs, gza
         # the same relit frame with the mesh backend answering the query
         # (the room as 46k triangles with per-vertex materials)
         mesh3 = W.mesh3()
@@ -416,6 +430,7 @@ def main():
                                     "frame_ms": round(mesh_frame, 3),
                                     "mrays_s": round(rays / (mesh_frame * 1e-3) / 1e6, 2)},
                    "gbuffer_trace_ms": round(float(np.median(gt)), 3), "gbuffer_covered": round(covered, 4),
+                   "gbuffer_backward_ms": round(float(np.median(gbw)), 3),
                    "prefilter_ms": round(float(np.median(pf)), 3), "frame_ms": round(frame, 3),
                    "mrays_s": round(rays / (frame * 1e-3) / 1e6, 2),
                    "radiance_fwd_ms": round(fwd_ms, 3),

@@ -218,7 +218,11 @@ int grt_trace_attr(const grt_scene *scene, const grt_rays *rays, const grt_trace
  *   depth = D, rgb = the colour map, valid = 1,
  * and every entry is 0 otherwise.  The arrays (device, [n,3] or [n]) form a
  * grt_gbuffer that grt_render_mis and grt_render_relight take as is.  Same
- * rays/opts/workspace as grt_trace (sky and dump ignored). */
+ * rays/opts/workspace as grt_trace (sky and dump ignored).
+ * weight and nlen are optional (NULL: not written) and are what
+ * grt_trace_gbuffer_backward needs besides the maps: weight [n] = W, the sum
+ * of the blending weights sum_k T_k alpha_k, and nlen [n] = |N| of the
+ * averaged normal before renormalization; both 0 on uncovered pixels. */
 typedef struct {
     float *x;
     float *n;
@@ -229,10 +233,53 @@ typedef struct {
     float *depth;
     float *rgb;
     uint8_t *valid;
+    float *weight;
+    float *nlen;
 } grt_gbuffer_out;
 int grt_trace_gbuffer(const grt_scene *scene, const grt_rays *rays, const grt_trace_opts *opts,
                       const grt_surfel_attrs *attrs, float min_opacity, grt_gbuffer_out *out, void *workspace,
                       size_t ws_bytes, void *stream);
+
+/* Upstream gradients of the primary-ray G-buffer's maps (device, float32,
+ * borrowed; x, n, albedo, rgb [n,3], rough, metal, depth [n]; any NULL =
+ * zero).  wo and valid have none. */
+typedef struct {
+    const float *x;
+    const float *n;
+    const float *albedo;
+    const float *rough;
+    const float *metal;
+    const float *depth;
+    const float *rgb;
+} grt_gbuffer_grad;
+
+/* Gradient accumulators of the per-surfel attributes (device, float32, ADDED
+ * to, by surfel id: albedo [n,3], rough [n], metal [n]; any NULL = not
+ * computed). */
+typedef struct {
+    float *albedo;
+    float *rough;
+    float *metal;
+} grt_attr_grads;
+
+/* Backward of grt_trace_gbuffer by re-traversal (Sec. 3.3, Eq. deferred_maps:
+ * gradients reach the surfels through the deferred maps of the primary
+ * rays): accumulates d/d(surfels) into `grads` and d/d(attributes) into
+ * `agrads` (NULL: none) of
+ *   L = sum over covered pixels of grad.x . x + grad.n . n + ... + grad.rgb . rgb.
+ * Every map is a ratio of blended sums over W = sum_k T_k alpha_k, and
+ * n = N/|N|; x = o + depth d, so grad.x reaches the surfels through the depth.
+ * Uncovered pixels contribute nothing (their maps are constant) and the
+ * coverage test is not differentiated.  `fwd` holds the forward's outputs
+ * with the same scene, rays, opts and attributes, including weight and nlen
+ * (x and wo are not read).  The surfel terms are summed in the scene's
+ * workspace, so backward passes over one scene must not overlap in time; the
+ * attribute terms are float32 atomics in no fixed order.  Same workspace as
+ * grt_trace. */
+int grt_trace_gbuffer_backward(const grt_scene *scene, const grt_rays *rays, const grt_trace_opts *opts,
+                               const grt_surfel_attrs *attrs, const grt_gbuffer_out *fwd,
+                               const grt_gbuffer_grad *grad, grt_surfel_grads *grads, grt_attr_grads *agrads,
+                               void *workspace, size_t ws_bytes, void *stream);
 
 /* Backward of grt_trace by re-traversal (Sec. 3.2: gradients backpropagate
  * through the traced radiance): accumulates d/d(surfels) of

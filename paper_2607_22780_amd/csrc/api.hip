@@ -359,11 +359,48 @@ int grt_trace_gbuffer(const grt_scene *scene, const grt_rays *rays, const grt_tr
     b.min_opacity = min_opacity;
     b.x = out->x; b.n = out->n; b.wo = out->wo; b.out_albedo = out->albedo; b.out_rough = out->rough;
     b.out_metal = out->metal; b.depth = out->depth; b.rgb = out->rgb; b.valid = out->valid;
+    b.weight = out->weight; b.nlen = out->nlen;
     if ((rc = check_ws(workspace, ws_bytes, grt_trace_workspace_bytes(rays->n), "trace_gbuffer"))) return rc;
     b.f.counters = (unsigned long long *)workspace;
     if ((rc = set_device(scene->ctx))) return rc;
     hipError_t e = grt::launch_trace_gbuffer(b, opts->k, scene->ctx->num_cu, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "trace_gbuffer launch");
+    return GRT_OK;
+}
+
+int grt_trace_gbuffer_backward(const grt_scene *scene, const grt_rays *rays, const grt_trace_opts *opts,
+                               const grt_surfel_attrs *attrs, const grt_gbuffer_out *fwd,
+                               const grt_gbuffer_grad *grad, grt_surfel_grads *grads, grt_attr_grads *agrads,
+                               void *workspace, size_t ws_bytes, void *stream)
+{
+    grt::TraceGBufBwdArgs b;
+    int rc = fill_trace_args(scene, rays, opts, b.f);
+    if (rc) return rc;
+    if (!attrs || !fwd || !grad) return fail(GRT_ERR_INVALID, "attrs/fwd/grad is NULL");
+    if (scene->s.n > 0 && (!attrs->albedo || !attrs->rough || !attrs->metal))
+        return fail(GRT_ERR_INVALID, "an attribute array is NULL");
+    if (rays->n > 0 && (!fwd->n || !fwd->albedo || !fwd->rough || !fwd->metal || !fwd->depth || !fwd->rgb ||
+                        !fwd->valid || !fwd->weight || !fwd->nlen))
+        return fail(GRT_ERR_INVALID, "a forward map (n, albedo, rough, metal, depth, rgb, valid, weight, nlen) is NULL");
+    if ((rc = check_grads(grads, scene->s.n))) return rc;
+    b.albedo = attrs->albedo; b.rough = attrs->rough; b.metal = attrs->metal;
+    b.fwd_n = fwd->n; b.fwd_albedo = fwd->albedo; b.fwd_rough = fwd->rough; b.fwd_metal = fwd->metal;
+    b.fwd_depth = fwd->depth; b.fwd_rgb = fwd->rgb; b.fwd_weight = fwd->weight; b.fwd_nlen = fwd->nlen;
+    b.fwd_valid = fwd->valid;
+    b.g_x = grad->x; b.g_n = grad->n; b.g_albedo = grad->albedo; b.g_rough = grad->rough; b.g_metal = grad->metal;
+    b.g_depth = grad->depth; b.g_rgb = grad->rgb;
+    b.g = grad_ptrs(scene, grads);
+    b.ga_albedo = agrads ? agrads->albedo : nullptr;
+    b.ga_rough = agrads ? agrads->rough : nullptr;
+    b.ga_metal = agrads ? agrads->metal : nullptr;
+    if ((rc = check_ws(workspace, ws_bytes, grt_trace_workspace_bytes(rays->n), "trace_gbuffer backward"))) return rc;
+    b.f.counters = (unsigned long long *)workspace;
+    if ((rc = set_device(scene->ctx))) return rc;
+    const hipStream_t st = (hipStream_t)stream;
+    hipError_t e = grt::launch_grad_lines_zero(b.g.acc, scene->s.n, st);
+    if (e == hipSuccess) e = grt::launch_trace_gbuffer_backward(b, opts->k, scene->ctx->num_cu, st);
+    if (e == hipSuccess) e = grt::launch_grad_lines_apply(b.g, scene->s.n, st);
+    if (e != hipSuccess) return hip_fail(e, "trace_gbuffer backward launch");
     return GRT_OK;
 }
 

@@ -158,6 +158,7 @@ struct TraceGBufArgs {
     float min_opacity;
     float *x, *n, *wo, *out_albedo, *out_rough, *out_metal, *depth, *rgb;
     uint8_t *valid;
+    float *weight, *nlen;  // saved for the backward (NULL: not written)
 };
 hipError_t launch_trace_gbuffer(const TraceGBufArgs &a, int k, int num_cu, hipStream_t st);
 
@@ -173,6 +174,18 @@ struct TraceBwdArgs {
     GradPtrs g;
 };
 hipError_t launch_trace_backward(const TraceBwdArgs &a, int k, int num_cu, hipStream_t st);
+// Backward of the primary-ray G-buffer: the forward's maps (fwd_*), upstream
+// gradients (g_*, NULL = zero) and attribute gradients (ga_*, NULL = skipped).
+struct TraceGBufBwdArgs {
+    TraceArgs f;
+    const float *albedo, *rough, *metal;
+    const float *fwd_n, *fwd_albedo, *fwd_rough, *fwd_metal, *fwd_depth, *fwd_rgb, *fwd_weight, *fwd_nlen;
+    const uint8_t *fwd_valid;
+    const float *g_x, *g_n, *g_albedo, *g_rough, *g_metal, *g_depth, *g_rgb;
+    GradPtrs g;
+    float *ga_albedo, *ga_rough, *ga_metal;
+};
+hipError_t launch_trace_gbuffer_backward(const TraceGBufBwdArgs &a, int k, int num_cu, hipStream_t st);
 // Clear the scene's gradient lines (before a backward pass) and add them to
 // the caller's gradient arrays (after it).
 hipError_t launch_grad_lines_zero(float *acc, int64_t n, hipStream_t st);

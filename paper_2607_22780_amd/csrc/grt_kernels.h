@@ -201,6 +201,55 @@ __device__ __forceinline__ void stage_sync(float *acc, WaveStage *s, bool all)
 
 // Backward of g_C . C + g_T . T_fin through every composited hit, with the
 // hit set, order and stop index of the forward.
+// Chain rule of one composited hit: from dL/dalpha (dA) -- and, for callers
+// that also read the hit's depth tau and normal n, a direct dL/dtau (dtau)
+// and dL/dn (dnx) -- to the surfel's stored parameters, out[0..9] = (mu xyz,
+// s_u, s_v, q wxyz, opacity).  alpha = o G(u, v) at the tangent-plane
+// crossing x = o + tau d, tau = n.(mu - o) / n.d, so tau moves with mu and n.
+template <bool kDirect>
+__device__ __forceinline__ void hit_param_grads(const HitGeo &hg, const float4 r1, const float4 r2, const float4 r3,
+                                                float3 d, float a, float G, float dA, float dtau, float3 dnx,
+                                                const GradPtrs &g, uint32_t id, float out[10])
+{
+    const float3 n = make_float3(r1.x, r1.y, r1.z);
+    const float den = hg.den;
+    const float3 D = hg.D;
+    const float3 au = make_float3(r2.x, r2.y, r2.z), av = make_float3(r3.x, r3.y, r3.z);
+    const float u = hg.u, v = hg.v;
+    const float gamma = -0.5f * a * dA;  // dL/d(rho^2)
+    const float du = 2.0f * u * gamma, dv = 2.0f * v * gamma;
+    // parameters of the surfel in its stored form
+    const float4 q = reinterpret_cast<const float4 *>(g.p_quats)[id];
+    const float su = g.p_scales[2 * (size_t)id], sv = g.p_scales[2 * (size_t)id + 1];
+    const float ql = sqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
+    const float iq = 1.0f / ql;
+    const float qw = q.x * iq, qx = q.y * iq, qy = q.z * iq, qz = q.w * iq;
+    const float dsu = -(u / su) * du, dsv = -(v / sv) * dv;
+    const float3 gD = make_float3(du * au.x + dv * av.x, du * au.y + dv * av.y, du * au.z + dv * av.z);
+    const float gDd = kDirect ? (dot3(gD, d) + dtau) / den : dot3(gD, d) / den;
+    const float3 dmu = make_float3(gDd * n.x - gD.x, gDd * n.y - gD.y, gDd * n.z - gD.z);
+    const float ku = du / su, kv = dv / sv;
+    const float3 dtu = make_float3(ku * D.x, ku * D.y, ku * D.z);
+    const float3 dtv = make_float3(kv * D.x, kv * D.y, kv * D.z);
+    float3 dn = make_float3(-gDd * D.x, -gDd * D.y, -gDd * D.z);
+    if (kDirect) { dn.x += dnx.x; dn.y += dnx.y; dn.z += dnx.z; }
+    // d(columns of R)/d(unit quaternion)
+    float dqw = 2.f * (dtu.y * qz - dtu.z * qy - dtv.x * qz + dtv.z * qx + dn.x * qy - dn.y * qx);
+    float dqx = 2.f * (dtu.y * qy + dtu.z * qz + dtv.x * qy - 2.f * dtv.y * qx + dtv.z * qw + dn.x * qz - dn.y * qw -
+                       2.f * dn.z * qx);
+    float dqy = 2.f * (-2.f * dtu.x * qy + dtu.y * qx - dtu.z * qw + dtv.x * qx + dtv.z * qz + dn.x * qw +
+                       dn.y * qz - 2.f * dn.z * qy);
+    float dqz = 2.f * (-2.f * dtu.x * qz + dtu.y * qw + dtu.z * qx - dtv.x * qw - 2.f * dtv.y * qz + dtv.z * qy +
+                       dn.x * qx + dn.y * qy);
+    const float proj = qw * dqw + qx * dqx + qy * dqy + qz * dqz;
+    dqw = (dqw - qw * proj) * iq; dqx = (dqx - qx * proj) * iq;
+    dqy = (dqy - qy * proj) * iq; dqz = (dqz - qz * proj) * iq;
+    out[0] = dmu.x; out[1] = dmu.y; out[2] = dmu.z;
+    out[3] = dsu; out[4] = dsv;
+    out[5] = dqw; out[6] = dqx; out[7] = dqy; out[8] = dqz;
+    out[9] = G * dA;
+}
+
 struct GradVisit {
     const float4 *rec;
     const float4 *col;
@@ -245,41 +294,83 @@ struct GradVisit {
             float behind = gC.x * (Cf.x - P.x) + gC.y * (Cf.y - P.y) + gC.z * (Cf.z - P.z) + gT * Tf;
             dA -= behind / om;
         }
-        const float3 n = make_float3(r1.x, r1.y, r1.z);
-        const float den = hg.den;
-        const float3 D = hg.D;
-        const float3 au = make_float3(r2.x, r2.y, r2.z), av = make_float3(r3.x, r3.y, r3.z);
-        const float u = hg.u, v = hg.v;
-        const float gamma = -0.5f * a * dA;  // dL/d(rho^2)
-        const float du = 2.0f * u * gamma, dv = 2.0f * v * gamma;
-        // parameters of the surfel in its stored form
-        const float4 q = reinterpret_cast<const float4 *>(g.p_quats)[id];
-        const float su = g.p_scales[2 * (size_t)id], sv = g.p_scales[2 * (size_t)id + 1];
-        const float ql = sqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
-        const float iq = 1.0f / ql;
-        const float qw = q.x * iq, qx = q.y * iq, qy = q.z * iq, qz = q.w * iq;
-        const float dsu = -(u / su) * du, dsv = -(v / sv) * dv;
-        const float3 gD = make_float3(du * au.x + dv * av.x, du * au.y + dv * av.y, du * au.z + dv * av.z);
-        const float gDd = dot3(gD, d) / den;
-        const float3 dmu = make_float3(gDd * n.x - gD.x, gDd * n.y - gD.y, gDd * n.z - gD.z);
-        const float ku = du / su, kv = dv / sv;
-        const float3 dtu = make_float3(ku * D.x, ku * D.y, ku * D.z);
-        const float3 dtv = make_float3(kv * D.x, kv * D.y, kv * D.z);
-        const float3 dn = make_float3(-gDd * D.x, -gDd * D.y, -gDd * D.z);
-        // d(columns of R)/d(unit quaternion)
-        float dqw = 2.f * (dtu.y * qz - dtu.z * qy - dtv.x * qz + dtv.z * qx + dn.x * qy - dn.y * qx);
-        float dqx = 2.f * (dtu.y * qy + dtu.z * qz + dtv.x * qy - 2.f * dtv.y * qx + dtv.z * qw + dn.x * qz - dn.y * qw -
-                           2.f * dn.z * qx);
-        float dqy = 2.f * (-2.f * dtu.x * qy + dtu.y * qx - dtu.z * qw + dtv.x * qx + dtv.z * qz + dn.x * qw +
-                           dn.y * qz - 2.f * dn.z * qy);
-        float dqz = 2.f * (-2.f * dtu.x * qz + dtu.y * qw + dtu.z * qx - dtv.x * qw - 2.f * dtv.y * qz + dtv.z * qy +
-                           dn.x * qx + dn.y * qy);
-        const float proj = qw * dqw + qx * dqx + qy * dqy + qz * dqz;
-        dqw = (dqw - qw * proj) * iq; dqx = (dqx - qx * proj) * iq;
-        dqy = (dqy - qy * proj) * iq; dqz = (dqz - qz * proj) * iq;
-
-        const float terms[13] = {dmu.x, dmu.y, dmu.z, dsu, dsv, dqw, dqx, dqy, dqz, G * dA, w * gC.x, w * gC.y, w * gC.z};
+        float terms[13];
+        hit_param_grads<false>(hg, r1, r2, r3, d, a, G, dA, 0.0f, make_float3(0.f, 0.f, 0.f), g, id, terms);
+        terms[10] = w * gC.x; terms[11] = w * gC.y; terms[12] = w * gC.z;
         stage_add(stage, id, terms);
+
+        T = T * (1.0f - a);
+        Td = trans_step(Td, hit_alpha(op, crho2));
+        return Td < tcut;
+    }
+};
+
+// Backward of the primary-ray G-buffer (Eq. deferred_maps on traced camera
+// rays).  Every map is a ratio S_f / W of blended sums S_f = sum_k w_k f_k,
+// W = sum_k w_k, w_k = T_k alpha_k, and the normal map is N / |N| with
+// N = sum_k w_k s_k n_k.  Holding the hits' values fixed, dL/dw_k is
+//   e_k = sum_f g_f (f_k - F_f) / W + s_k n_k . (I - n n^T) g_n / |N|,
+// and sum_k w_k e_k = 0 (every map is invariant to a common scale of the
+// weights), so the part of the loss behind hit k is -(e_1 w_1 + ... + e_k w_k).
+// The per-ray constants come from the forward's maps, W and |N| / W.
+struct GBufGradVisit {
+    const float4 *rec;
+    const float4 *col;
+    const float *albedo, *rough, *metal;  // per surfel id
+    float *ga_albedo, *ga_rough, *ga_metal;  // attribute gradients (NULL: skipped)
+    float tcut;
+    GradPtrs g;
+    WaveStage *stage = nullptr;
+    float3 o, d;
+    float kD, kR, kM, e0;  // upstream gradients over W, and sum_f g_f F_f / W
+    float3 kA, kC, kN;
+    float T, Td, P;
+
+    __device__ GBufGradVisit() {}
+    __device__ GBufGradVisit(const SceneDev &S, float t_cut, const GradPtrs &gp)
+        : rec(S.rec), col(S.col), tcut(t_cut), g(gp) {}
+
+    __device__ __forceinline__ void reset(float3 o_, float3 d_)
+    {
+        o = o_;
+        d = d_;
+        T = 1.0f;
+        Td = 1.0f;
+        P = 0.0f;
+    }
+
+    __device__ __forceinline__ bool operator()(uint32_t p, uint32_t id, float tau, const float4 r0, const float4 r1,
+                                               const float4 r2, const float4 r3, float crho2)
+    {
+        const float4 c = col[p];
+        const float op = r1.w;
+        HitGeo hg;
+        value_geo(r0, r1, r2, r3, o, d, hg);
+        const float G = expf(-0.5f * hg.rho2);
+        const float a = op * G;
+        const float w = T * a;
+        const float side = hg.den > 0.0f ? -1.0f : 1.0f;  // normal toward the camera
+        const size_t i = id;
+        const float3 al = make_float3(albedo[3 * i], albedo[3 * i + 1], albedo[3 * i + 2]);
+        const float e = kD * tau + kA.x * al.x + kA.y * al.y + kA.z * al.z + kR * rough[i] + kM * metal[i] +
+                        kC.x * c.x + kC.y * c.y + kC.z * c.z - e0 + side * (r1.x * kN.x + r1.y * kN.y + r1.z * kN.z);
+        P += w * e;
+        float dA = T * e;
+        const float om = 1.0f - a;
+        if (om >= 1e-6f) dA += P / om;
+        const float sw = side * w;
+        float terms[13];
+        hit_param_grads<true>(hg, r1, r2, r3, d, a, G, dA, w * kD, make_float3(sw * kN.x, sw * kN.y, sw * kN.z), g,
+                              id, terms);
+        terms[10] = w * kC.x; terms[11] = w * kC.y; terms[12] = w * kC.z;
+        stage_add(stage, id, terms);
+        if (ga_albedo) {
+            atomicAdd(ga_albedo + 3 * i, w * kA.x);
+            atomicAdd(ga_albedo + 3 * i + 1, w * kA.y);
+            atomicAdd(ga_albedo + 3 * i + 2, w * kA.z);
+        }
+        if (ga_rough) atomicAdd(ga_rough + i, w * kR);
+        if (ga_metal) atomicAdd(ga_metal + i, w * kM);
 
         T = T * (1.0f - a);
         Td = trans_step(Td, hit_alpha(op, crho2));

@@ -208,6 +208,8 @@ struct TraceGBufJob {
         a.depth[r] = D;
         a.rgb[3 * r] = v.Csum.x * m; a.rgb[3 * r + 1] = v.Csum.y * m; a.rgb[3 * r + 2] = v.Csum.z * m;
         a.valid[r] = ok ? 1 : 0;
+        if (a.weight) a.weight[r] = ok ? v.W : 0.0f;
+        if (a.nlen) a.nlen[r] = ok ? nl : 0.0f;
     }
     __device__ __forceinline__ void after_step() {}
     __device__ __forceinline__ void drain() {}
@@ -241,6 +243,99 @@ hipError_t launch_trace_gbuffer(const TraceGBufArgs &a, int k, int num_cu, hipSt
     case 12: return go_trace_gbuffer<12>(a, num_cu, st);
     case 16: return go_trace_gbuffer<16>(a, num_cu, st);
     case 32: return go_trace_gbuffer<32>(a, num_cu, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// Backward of the primary-ray G-buffer by re-traversal: the same hits as the
+// forward, with the per-ray constants of GBufGradVisit from the forward's
+// maps; uncovered pixels (constant maps) are skipped.
+template <int K>
+struct TraceGBufBwdJob {
+    const TraceGBufBwdArgs &a;
+    SceneDev S;
+    Walker<K, kBwdLdsDepth> w;
+    GBufGradVisit v;
+
+    __device__ TraceGBufBwdJob(const TraceGBufBwdArgs &a_, WaveStage *t) : a(a_), S(a_.f.S), v(a_.f.S, a_.f.tcut, a_.g)
+    {
+        v.albedo = a.albedo; v.rough = a.rough; v.metal = a.metal;
+        v.ga_albedo = a.ga_albedo; v.ga_rough = a.ga_rough; v.ga_metal = a.ga_metal;
+        v.stage = t;
+        stage_init(t);
+    }
+    __device__ __forceinline__ Walker<K, kBwdLdsDepth> &walker() { return w; }
+    __device__ __forceinline__ GBufGradVisit &visit() { return v; }
+
+    static __device__ __forceinline__ float3 ld3(const float *p, int64_t r)
+    {
+        return p ? make_float3(p[3 * r], p[3 * r + 1], p[3 * r + 2]) : make_float3(0.f, 0.f, 0.f);
+    }
+
+    __device__ __forceinline__ bool begin(int64_t r)
+    {
+        if (S.n <= 0 || !a.fwd_valid[r]) return false;
+        const float Wt = a.fwd_weight[r], nl = a.fwd_nlen[r];
+        if (!(Wt > 0.0f) || !(nl > 0.0f)) return false;
+        const float3 o = make_float3(a.f.o[3 * r], a.f.o[3 * r + 1], a.f.o[3 * r + 2]);
+        const float3 d = make_float3(a.f.d[3 * r], a.f.d[3 * r + 1], a.f.d[3 * r + 2]);
+        const float3 gx = ld3(a.g_x, r), gn = ld3(a.g_n, r), gA = ld3(a.g_albedo, r), gC = ld3(a.g_rgb, r);
+        const float gR = a.g_rough ? a.g_rough[r] : 0.0f, gM = a.g_metal ? a.g_metal[r] : 0.0f;
+        // x = o + D d: the hit-point map moves with the depth only
+        const float gD = (a.g_depth ? a.g_depth[r] : 0.0f) + dot3(gx, d);
+        if (gD == 0.0f && gR == 0.0f && gM == 0.0f && gn.x == 0.0f && gn.y == 0.0f && gn.z == 0.0f &&
+            gA.x == 0.0f && gA.y == 0.0f && gA.z == 0.0f && gC.x == 0.0f && gC.y == 0.0f && gC.z == 0.0f)
+            return false;
+        const float iW = 1.0f / Wt;
+        v.kD = gD * iW; v.kR = gR * iW; v.kM = gM * iW;
+        v.kA = make_float3(gA.x * iW, gA.y * iW, gA.z * iW);
+        v.kC = make_float3(gC.x * iW, gC.y * iW, gC.z * iW);
+        const float3 A = ld3(a.fwd_albedo, r), C = ld3(a.fwd_rgb, r), nh = ld3(a.fwd_n, r);
+        v.e0 = v.kD * a.fwd_depth[r] + dot3(v.kA, A) + v.kR * a.fwd_rough[r] + v.kM * a.fwd_metal[r] + dot3(v.kC, C);
+        // d(N/|N|)/dN applied to g_n, with |N| = W |N / W|
+        const float ndg = dot3(nh, gn), iN = iW / nl;
+        v.kN = make_float3((gn.x - nh.x * ndg) * iN, (gn.y - nh.y * ndg) * iN, (gn.z - nh.z * ndg) * iN);
+        const float tmin = a.f.tmin_a ? a.f.tmin_a[r] : a.f.tmin;
+        const float tmax = a.f.tmax_a ? a.f.tmax_a[r] : a.f.tmax;
+        v.reset(o, d);
+        w.start(S, o, d, tmin, tmax);
+        return true;
+    }
+
+    __device__ __forceinline__ void finish(int64_t) {}
+    __device__ __forceinline__ void after_step() { stage_sync(a.g.acc, v.stage, false); }
+    __device__ __forceinline__ void drain() { stage_sync(a.g.acc, v.stage, true); }
+};
+
+template <int K>
+__global__ void __launch_bounds__(256) GRT_OCCUPANCY k_trace_gbuffer_bwd(TraceGBufBwdArgs a)
+{
+    __shared__ WaveStage stages[4];
+    TraceGBufBwdJob<K> job(a, &stages[(threadIdx.x >> 6) & 3]);
+    run_persistent<K>(job, a.f.counters, a.f.n);
+}
+
+template <int K>
+static hipError_t go_trace_gbuffer_bwd(const TraceGBufBwdArgs &a, int num_cu, hipStream_t st)
+{
+    const int nb = persistent_blocks(k_trace_gbuffer_bwd<K>, num_cu, a.f.n);
+    hipLaunchKernelGGL(k_trace_gbuffer_bwd<K>, dim3(nb), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_trace_gbuffer_backward(const TraceGBufBwdArgs &a, int k, int num_cu, hipStream_t st)
+{
+    if (a.f.n <= 0) return hipSuccess;
+    hipError_t e = launch_zero_counters(a.f.counters, st);
+    if (e != hipSuccess) return e;
+    switch (k) {
+    case 1: return go_trace_gbuffer_bwd<1>(a, num_cu, st);
+    case 2: return go_trace_gbuffer_bwd<2>(a, num_cu, st);
+    case 4: return go_trace_gbuffer_bwd<4>(a, num_cu, st);
+    case 8: return go_trace_gbuffer_bwd<8>(a, num_cu, st);
+    case 12: return go_trace_gbuffer_bwd<12>(a, num_cu, st);
+    case 16: return go_trace_gbuffer_bwd<16>(a, num_cu, st);
+    case 32: return go_trace_gbuffer_bwd<32>(a, num_cu, st);
     default: return hipErrorInvalidValue;
     }
 }

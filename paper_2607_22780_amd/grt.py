@@ -61,7 +61,15 @@ class grt_surfel_grads(C.Structure):
 
 class grt_gbuffer_out(C.Structure):
     _fields_ = [("x", VP), ("n", VP), ("wo", VP), ("albedo", VP), ("rough", VP), ("metal", VP), ("depth", VP),
-                ("rgb", VP), ("valid", VP)]
+                ("rgb", VP), ("valid", VP), ("weight", VP), ("nlen", VP)]
+
+
+class grt_gbuffer_grad(C.Structure):
+    _fields_ = [("x", VP), ("n", VP), ("albedo", VP), ("rough", VP), ("metal", VP), ("depth", VP), ("rgb", VP)]
+
+
+class grt_attr_grads(C.Structure):
+    _fields_ = [("albedo", VP), ("rough", VP), ("metal", VP)]
 
 
 class grt_mesh_desc(C.Structure):
@@ -127,6 +135,9 @@ SIGNATURES = {
                                  C.c_size_t, VP]),
     "grt_trace_gbuffer": (C.c_int, [VP, P(grt_rays), P(grt_trace_opts), P(grt_surfel_attrs), C.c_float,
                                     P(grt_gbuffer_out), VP, C.c_size_t, VP]),
+    "grt_trace_gbuffer_backward": (C.c_int, [VP, P(grt_rays), P(grt_trace_opts), P(grt_surfel_attrs),
+                                             P(grt_gbuffer_out), P(grt_gbuffer_grad), P(grt_surfel_grads),
+                                             P(grt_attr_grads), VP, C.c_size_t, VP]),
     "grt_env_workspace_bytes": (C.c_size_t, [C.c_int, C.c_int]),
     "grt_env_create": (C.c_int, [VP, VP, C.c_int, C.c_int, VP, C.c_size_t, P(VP)]),
     "grt_env_build": (C.c_int, [VP, VP]),
@@ -536,11 +547,21 @@ def trace_attr(scene: Scene, albedo, rough, metal, origins, dirs, t_min=0.0, t_m
     return out
 
 
+GBUFFER_OUT_KEYS = ("x", "n", "wo", "albedo", "rough", "metal", "depth", "rgb", "valid", "weight", "nlen")
+GBUFFER_GRAD_KEYS = ("x", "n", "albedo", "rough", "metal", "depth", "rgb")
+
+
+def _gbuffer_out_struct(o):
+    return grt_gbuffer_out(*(_ptr(o[k_]) if o.get(k_) is not None else None for k_ in GBUFFER_OUT_KEYS))
+
+
 def trace_gbuffer(scene: Scene, albedo, rough, metal, origins, dirs, H: int, W: int, min_opacity=0.5, k=12,
                   t_cut=1e-3, stream=None):
     """Primary-ray G-buffer by 2DGRT of H x W camera rays (row-major): dict
-    with a GBuffer ("gbuffer", usable by render_mis / render_relight), and the
-    depth [H*W] and colour [H*W,3] maps."""
+    with a GBuffer ("gbuffer", usable by render_mis / render_relight), the
+    depth [H*W] and colour [H*W,3] maps, and what the backward needs besides
+    the maps (weight = the sum of the blending weights, nlen = the averaged
+    normal's length before renormalization)."""
     dev = origins.device
     R = origins.shape[0]
     assert R == H * W
@@ -549,9 +570,8 @@ def trace_gbuffer(scene: Scene, albedo, rough, metal, origins, dirs, H: int, W: 
     e3 = lambda: torch.empty(R, 3, device=dev)
     e1 = lambda: torch.empty(R, device=dev)
     o = dict(x=e3(), n=e3(), wo=e3(), albedo=e3(), rough=e1(), metal=e1(), depth=e1(), rgb=e3(),
-             valid=torch.empty(R, dtype=torch.uint8, device=dev))
-    st = grt_gbuffer_out(*(_ptr(o[k_]) for k_ in ("x", "n", "wo", "albedo", "rough", "metal", "depth", "rgb",
-                                                  "valid")))
+             valid=torch.empty(R, dtype=torch.uint8, device=dev), weight=e1(), nlen=e1())
+    st = _gbuffer_out_struct(o)
     rays = make_rays(origins, dirs, 0.0, float("inf"))
     opts = make_trace_opts(k, t_cut, (0.0, 0.0, 0.0), None, None)
     attrs = grt_surfel_attrs(_ptr(albedo), _ptr(rough), _ptr(metal))
@@ -560,6 +580,43 @@ def trace_gbuffer(scene: Scene, albedo, rough, metal, origins, dirs, H: int, W: 
                                             float(min_opacity), C.byref(st), _ptr(ws), ws.numel(), _stream(stream)))
     o["gbuffer"] = GBuffer(H, W, o["x"], o["n"], o["wo"], o["albedo"], o["rough"], o["metal"], o["valid"])
     return o
+
+
+def trace_gbuffer_backward(scene: Scene, albedo, rough, metal, origins, dirs, fwd, grad, k=12, t_cut=1e-3,
+                           grads=None, attr_grads=None, stream=None):
+    """Backward of trace_gbuffer (same scene, rays, attributes, k and t_cut;
+    ``fwd`` is its output dict): accumulates d/d(surfels) and d/d(albedo,
+    rough, metal) of the sum over covered pixels of grad[key] . map[key]
+    (keys x, n, albedo, rough, metal, depth, rgb; missing keys are zero).
+    Returns (grads, attr_grads)."""
+    dev = origins.device
+    R = origins.shape[0]
+    for a in (albedo, rough, metal):
+        assert a.is_contiguous() and a.dtype == torch.float32 and a.device == dev
+    if grads is None:
+        grads = zero_grads(scene.n, dev)
+    if attr_grads is None:
+        attr_grads = dict(albedo=torch.zeros(scene.n, 3, device=dev), rough=torch.zeros(scene.n, device=dev),
+                          metal=torch.zeros(scene.n, device=dev))
+    gin = {}
+    for key in GBUFFER_GRAD_KEYS:
+        g = grad.get(key)
+        if g is not None:
+            g = g.contiguous()
+            assert g.dtype == torch.float32 and g.device == dev and g.numel() == R * (3 if fwd[key].dim() == 2 else 1)
+        gin[key] = g
+    gst = grt_gbuffer_grad(*(_ptr(gin[key]) if gin[key] is not None else None for key in GBUFFER_GRAD_KEYS))
+    ast = grt_attr_grads(*(_ptr(attr_grads[key]) if attr_grads.get(key) is not None else None
+                           for key in ("albedo", "rough", "metal")))
+    rays = make_rays(origins, dirs, 0.0, float("inf"))
+    opts = make_trace_opts(k, t_cut, (0.0, 0.0, 0.0), None, None)
+    attrs = grt_surfel_attrs(_ptr(albedo), _ptr(rough), _ptr(metal))
+    ws = _workspace(grt_trace_workspace_bytes(R), dev)
+    _check(load_library().grt_trace_gbuffer_backward(scene.handle, C.byref(rays), C.byref(opts), C.byref(attrs),
+                                                     C.byref(_gbuffer_out_struct(fwd)), C.byref(gst),
+                                                     C.byref(_grads_struct(grads)), C.byref(ast), _ptr(ws),
+                                                     ws.numel(), _stream(stream)))
+    return grads, attr_grads
 
 
 def zero_grads(n: int, device):
