@@ -380,7 +380,9 @@ typedef struct {
  * 0 on bad arguments. */
 size_t grt_render_hit_list_bytes(int64_t npix, int spp, int hit_cap);
 
-/* Bytes of per-ray state the forward saves for grt_render_mis_backward. */
+/* Bytes of per-sample state the forward saves for grt_render_mis_backward:
+ * the composite (c_rt, T) of every sample, then the depth of its last
+ * composited hit (the backward's re-traversal stops there). */
 size_t grt_render_saved_bytes(int64_t npix, int spp);
 
 /* Bytes of device workspace grt_render_mis and grt_render_mis_backward need:

@@ -502,7 +502,7 @@ int grt_env_destroy(grt_env *env)
 size_t grt_render_saved_bytes(int64_t npix, int spp)
 {
     if (npix < 0 || spp <= 0) return 0;
-    return (size_t)npix * (size_t)spp * 16u;
+    return (size_t)npix * (size_t)spp * 20u;
 }
 
 size_t grt_render_hit_list_bytes(int64_t npix, int spp, int hit_cap)
@@ -740,6 +740,8 @@ int grt_render_mis(const grt_scene *scene, const grt_env *env, const grt_gbuffer
     if (saved && !aligned(saved, 16)) return fail(GRT_ERR_INVALID, "saved must be 16-byte aligned");
     a.out = out_rgb;
     a.saved = reinterpret_cast<float4 *>(saved);
+    a.saved_t = saved ? reinterpret_cast<float *>(a.saved + (int64_t)g->H * g->W * (opts->n_cos + opts->n_ggx + opts->n_env))
+                      : nullptr;
     a.dump = opts->sample_dump;
     const int spp = opts->n_cos + opts->n_ggx + opts->n_env;
     if ((rc = check_ws(workspace, ws_bytes, grt_render_workspace_bytes((int64_t)g->H * g->W, spp), "render")))
@@ -767,6 +769,7 @@ int grt_render_mis_backward(const grt_scene *scene, const grt_env *env, const gr
     if ((rc = check_grads(grads, scene->s.n))) return rc;
     a.grad = grad_rgb;
     a.saved = const_cast<float4 *>(reinterpret_cast<const float4 *>(saved));
+    a.saved_t = reinterpret_cast<float *>(a.saved + (int64_t)g->H * g->W * (opts->n_cos + opts->n_ggx + opts->n_env));
     a.g = grad_ptrs(scene, grads);
     const int spp = opts->n_cos + opts->n_ggx + opts->n_env;
     if ((rc = check_ws(workspace, ws_bytes, grt_render_workspace_bytes((int64_t)g->H * g->W, spp),

@@ -265,7 +265,7 @@ struct Walker {
     static constexpr int kDepth = D;  // LDS entries per lane and stack
     float3 o, d, inv;
     float tmin, tmax;
-    uint64_t last;
+    uint64_t last;        // start key of the round; while compositing, the last composited hit
     float tlo, thi;
     uint64_t key[K];
     uint32_t pos[K];
@@ -450,6 +450,10 @@ struct Walker {
         }
     }
 
+    // Depth of the last composited hit once the ray is finished (0 when none
+    // was): a re-traversal bounded there meets the same composited hits.
+    __device__ __forceinline__ float stop_depth() const { return __uint_as_float((uint32_t)(last >> 32)); }
+
     __device__ __forceinline__ bool deferred_empty() const
     {
         return !lost && F.def.sp == 0;
@@ -501,6 +505,7 @@ struct Walker {
         }
         const bool stop = visit(sp, (uint32_t)(key[0] & 0xffffffffu), __uint_as_float((uint32_t)(key[0] >> 32)), r0,
                                 r1, r2, r3, rho2);
+        last = key[0];  // the last composited hit (next_round resets it)
 #pragma unroll
         for (int i = 0; i < K - 1; ++i) { key[i] = key[i + 1]; pos[i] = pos[i + 1]; }
         key[K - 1] = ~0ull;

@@ -289,6 +289,7 @@ struct RenderArgs {
     float tmin, tcut;
     float *out;
     float4 *saved;
+    float *saved_t;  // the forward's stop depth per sample (after the saved (C, T) records)
     float *dump;
     float4 *contrib;  // per sample f L_i cos / q, reduced per pixel afterwards
     float4 *rays;     // per sample record written by the generation kernel (3 x float4)

@@ -430,7 +430,10 @@ struct ShadeTrace {
         const float4 r1 = a.rays[3 * r + 1], r2 = a.rays[3 * r + 2];
         const float3 Li = make_float3(v.C.x + v.T * r1.w, v.C.y + v.T * r2.x, v.C.z + v.T * r2.y);
         a.contrib[r] = make_float4(r1.x * Li.x, r1.y * Li.y, r1.z * Li.z, 0.0f);
-        if (a.saved) a.saved[r] = make_float4(v.C.x, v.C.y, v.C.z, v.T);
+        if (a.saved) {
+            a.saved[r] = make_float4(v.C.x, v.C.y, v.C.z, v.T);
+            a.saved_t[r] = w.stop_depth();
+        }
         if (a.hits) a.hits[r] = (uint32_t)v.cnt;
         if (a.dump) {
             float *dp = a.dump + r * 10;

@@ -455,6 +455,7 @@ void setup_args(grt_server *s, ServerJob &j)
     a.tmin = s->opts.t_min;
     a.tcut = s->opts.t_cut;
     a.saved = nullptr;
+    a.saved_t = nullptr;
     a.dump = nullptr;
     a.grad = nullptr;
 }

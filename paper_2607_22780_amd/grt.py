@@ -690,12 +690,14 @@ def make_hit_list(npix: int, spp: int, hit_cap: int, device):
 
 def render_mis(scene: Scene, env: Env, gb: GBuffer, split=(16, 8, 8), seed=0, job=0, t_min=1e-3, t_cut=1e-3, k=16,
                save=False, dump=False, workspace=None, stream=None, hits=None, hit_cap=0):
-    """c_pbr [npix,3]; with ``save`` also the per-ray state for the backward,
+    """c_pbr [npix,3]; with ``save`` also the per-sample state for the
+    backward ("saved", flat; views "saved_ct" [nray,4] = (c_rt, T) and
+    "saved_stop" [nray] = the depth of the last composited hit, 0 if none),
     with ``dump`` the per-sample record [npix, spp, 10]."""
     dev = gb.x.device
     spp = sum(split)
     out = torch.empty(gb.npix, 3, device=dev)
-    saved = torch.empty(gb.npix * spp, 4, device=dev) if save else None
+    saved = torch.empty(grt_render_saved_bytes(gb.npix, spp) // 4, device=dev) if save else None
     dmp = torch.zeros(gb.npix, spp, 10, device=dev) if dump else None
     opts = make_mis_opts(split, seed, job, t_min, t_cut, k, dmp, hits, hit_cap)
     need = grt_render_workspace_bytes(gb.npix, spp)
@@ -704,7 +706,10 @@ def render_mis(scene: Scene, env: Env, gb: GBuffer, split=(16, 8, 8), seed=0, jo
     grt_render_mis(scene.handle, env.handle, gb.struct(), opts, out, saved, workspace, stream)
     res = dict(rgb=out)
     if save:
+        nray = gb.npix * spp
         res["saved"] = saved
+        res["saved_ct"] = saved[: 4 * nray].view(nray, 4)
+        res["saved_stop"] = saved[4 * nray: 5 * nray]
     if dump:
         res["dump"] = dmp
     return res

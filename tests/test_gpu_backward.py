@@ -156,9 +156,14 @@ def test_render_backward_stored_lists(grt_ctx, cap):
     check_grads({k: v.cpu().numpy() for k, v in gg.items()}, ref)
     counts = hits[: gb.npix * spp].cpu().numpy().astype(np.int64)
     traced = fwd["dump"].reshape(-1, 10)[:, 3].cpu().numpy() > 0  # q > 0: the sample was traced
-    T = fwd["saved"][:, 3].cpu().numpy()
+    T = fwd["saved_ct"][:, 3].cpu().numpy()
+    stop = fwd["saved_stop"].cpu().numpy()
     assert np.all(counts[~traced] == 0)
     assert np.all((counts[traced] > 0) == (T[traced] < 1.0))  # a hit iff transmittance dropped
+    # the saved stop depth of a traced sample: 0 without a composited hit,
+    # past t_min with one (untraced samples save nothing)
+    assert np.all((stop[traced] > 1e-3) == (counts[traced] > 0))
+    assert np.all(stop[traced & (counts == 0)] == 0)
     if cap == 2:
         assert np.mean(counts > cap) > 0.2  # the overflow path is exercised
     else:
