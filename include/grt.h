@@ -146,7 +146,14 @@ typedef struct {
  * t_cut: transmittance cutoff (1e-3 in the workloads).
  * sky: radiance of escaped rays, L = c_rt + T sky.
  * hit_ids/hit_tau: optional [n, hit_cap] dump of the composited hits in
- *    order (surfel id, depth), -1 / 0 padded; NULL to skip. */
+ *    order (surfel id, depth), -1 / 0 padded; NULL to skip.
+ * stop_depth: optional [n] (device, float32).  grt_trace and
+ *    grt_trace_gbuffer write the depth of each ray's last composited hit
+ *    (0 when none); grt_trace_backward and grt_trace_gbuffer_backward, given
+ *    the opts of that forward, end their re-traversal there (every hit they
+ *    composite lies at or before it), which saves the walk beyond.  It must
+ *    then hold that forward's values for the same rays; NULL: the backward
+ *    walks the whole ray range. */
 typedef struct {
     int k;
     float t_cut;
@@ -154,6 +161,7 @@ typedef struct {
     int32_t *hit_ids;
     float *hit_tau;
     int hit_cap;
+    float *stop_depth;
 } grt_trace_opts;
 
 /* Bytes of device workspace grt_trace / grt_trace_backward need (the

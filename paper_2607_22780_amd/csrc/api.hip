@@ -283,6 +283,7 @@ static int fill_trace_args(const grt_scene *scene, const grt_rays *rays, const g
     a.tmin = rays->t_min_all; a.tmax = rays->t_max_all;
     a.tcut = opts->t_cut;
     for (int c = 0; c < 3; ++c) a.sky[c] = opts->sky[c];
+    a.stop_depth = opts->stop_depth;
     return GRT_OK;
 }
 

@@ -519,6 +519,17 @@ struct Walker {
     }
 };
 
+// Upper end of a backward's re-traversal: the depth of the forward's last
+// composited hit when it was saved (every hit the backward composites lies at
+// or before it, and ties there come after the hit that ended the forward),
+// with a margin that keeps node culling clear of rounding.
+__device__ __forceinline__ float stop_bound(const float *stop_depth, int64_t r, float tmax)
+{
+    if (!stop_depth) return tmax;
+    const float ts = stop_depth[r];
+    return fminf(tmax, ts + 1e-6f * ts + 1e-6f);
+}
+
 // ---------------------------------------------------------------------------
 // Persistent wavefronts with dynamic ray fetching.
 //

@@ -138,6 +138,7 @@ struct TraceArgs {
     int32_t *dump_id;
     float *dump_tau;
     int cap;
+    float *stop_depth;  // written by the forwards, read by the backwards (NULL: unused)
     unsigned long long *counters;
 };
 hipError_t launch_trace(const TraceArgs &a, int k, int num_cu, hipStream_t st);

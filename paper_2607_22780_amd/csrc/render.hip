@@ -324,10 +324,7 @@ struct RenderBwdJob {
         const float3 x = make_float3(a.x[3 * p], a.x[3 * p + 1], a.x[3 * p + 2]);
         const float3 d = make_float3(r0.x, r0.y, r0.z);
         v.reset(x, d, gC, gT, make_float3(sv.x, sv.y, sv.z), sv.w);
-        // nothing beyond the forward's last composited hit is composited
-        // again; the margin only keeps node culling clear of rounding
-        const float ts = a.saved_t[r];
-        w.start(S, x, d, a.tmin, ts + 1e-6f * ts + 1e-6f);
+        w.start(S, x, d, a.tmin, stop_bound(a.saved_t, r, INFINITY));
         return true;
     }
 

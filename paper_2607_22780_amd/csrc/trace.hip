@@ -68,6 +68,7 @@ struct TraceJob {
             a.out_L[3 * r + 2] = v.C.z + v.T * a.sky[2];
         }
         if (a.out_nhit) a.out_nhit[r] = v.cnt;
+        if (a.stop_depth) a.stop_depth[r] = w.stop_depth();
         if (a.dump_id)
             for (int i = v.cnt; i < a.cap; ++i) { v.did[i] = -1; v.dtau[i] = 0.0f; }
     }
@@ -102,7 +103,7 @@ struct TraceBwdJob {
         const float tmax = a.f.tmax_a ? a.f.tmax_a[r] : a.f.tmax;
         const float3 C = make_float3(a.fwd_rgb[3 * r], a.fwd_rgb[3 * r + 1], a.fwd_rgb[3 * r + 2]);
         v.reset(o, d, gC, gT, C, a.fwd_T[r]);
-        w.start(S, o, d, tmin, tmax);
+        w.start(S, o, d, tmin, stop_bound(a.f.stop_depth, r, tmax));
         return true;
     }
 
@@ -210,6 +211,7 @@ struct TraceGBufJob {
         a.valid[r] = ok ? 1 : 0;
         if (a.weight) a.weight[r] = ok ? v.W : 0.0f;
         if (a.nlen) a.nlen[r] = ok ? nl : 0.0f;
+        if (a.f.stop_depth) a.f.stop_depth[r] = w.stop_depth();
     }
     __device__ __forceinline__ void after_step() {}
     __device__ __forceinline__ void drain() {}
@@ -298,7 +300,7 @@ struct TraceGBufBwdJob {
         const float tmin = a.f.tmin_a ? a.f.tmin_a[r] : a.f.tmin;
         const float tmax = a.f.tmax_a ? a.f.tmax_a[r] : a.f.tmax;
         v.reset(o, d);
-        w.start(S, o, d, tmin, tmax);
+        w.start(S, o, d, tmin, stop_bound(a.f.stop_depth, r, tmax));
         return true;
     }
 

@@ -52,7 +52,7 @@ class grt_rays(C.Structure):
 
 class grt_trace_opts(C.Structure):
     _fields_ = [("k", C.c_int), ("t_cut", C.c_float), ("sky", C.c_float * 3), ("hit_ids", VP), ("hit_tau", VP),
-                ("hit_cap", C.c_int)]
+                ("hit_cap", C.c_int), ("stop_depth", VP)]
 
 
 class grt_surfel_grads(C.Structure):
@@ -495,7 +495,7 @@ def make_rays(origins, dirs, t_min=0.0, t_max=float("inf")):
     return r
 
 
-def make_trace_opts(k=16, t_cut=1e-3, sky=(0.5, 0.5, 0.5), hit_ids=None, hit_tau=None):
+def make_trace_opts(k=16, t_cut=1e-3, sky=(0.5, 0.5, 0.5), hit_ids=None, hit_tau=None, stop=None):
     o = grt_trace_opts()
     o.k = k
     o.t_cut = t_cut
@@ -504,13 +504,16 @@ def make_trace_opts(k=16, t_cut=1e-3, sky=(0.5, 0.5, 0.5), hit_ids=None, hit_tau
     o.hit_ids = _ptr(hit_ids)
     o.hit_tau = _ptr(hit_tau)
     o.hit_cap = int(hit_ids.shape[1]) if hit_ids is not None else 0
+    o.stop_depth = _ptr(stop)
     return o
 
 
 def trace(scene: Scene, origins, dirs, t_min=0.0, t_max=float("inf"), k=16, t_cut=1e-3, sky=(0.5, 0.5, 0.5),
-          dump_cap=0, stream=None):
+          dump_cap=0, save_stop=False, stream=None):
     """Trace every ray; returns dict of rgb [R,3], T [R], L [R,3], nhit [R]
-    (and ids/tau [R,dump_cap] when dump_cap > 0)."""
+    (and ids/tau [R,dump_cap] when dump_cap > 0; with ``save_stop`` also
+    stop [R], the depth of each ray's last composited hit, which
+    trace_backward takes to bound its re-traversal)."""
     dev = origins.device
     R = origins.shape[0]
     out = dict(rgb=torch.empty(R, 3, device=dev), T=torch.empty(R, device=dev), L=torch.empty(R, 3, device=dev),
@@ -520,8 +523,10 @@ def trace(scene: Scene, origins, dirs, t_min=0.0, t_max=float("inf"), k=16, t_cu
         ids = torch.empty(R, dump_cap, dtype=torch.int32, device=dev)
         tau = torch.empty(R, dump_cap, dtype=torch.float32, device=dev)
         out["ids"], out["tau"] = ids, tau
+    if save_stop:
+        out["stop"] = torch.empty(R, device=dev)
     rays = make_rays(origins, dirs, t_min, t_max)
-    opts = make_trace_opts(k, t_cut, sky, ids, tau)
+    opts = make_trace_opts(k, t_cut, sky, ids, tau, out.get("stop"))
     ws = _workspace(grt_trace_workspace_bytes(R), dev)
     grt_trace(scene.handle, rays, opts, out["rgb"], out["T"], out["L"], out["nhit"], ws, stream)
     return out
@@ -561,7 +566,8 @@ def trace_gbuffer(scene: Scene, albedo, rough, metal, origins, dirs, H: int, W: 
     with a GBuffer ("gbuffer", usable by render_mis / render_relight), the
     depth [H*W] and colour [H*W,3] maps, and what the backward needs besides
     the maps (weight = the sum of the blending weights, nlen = the averaged
-    normal's length before renormalization)."""
+    normal's length before renormalization, stop = the depth of the last
+    composited hit)."""
     dev = origins.device
     R = origins.shape[0]
     assert R == H * W
@@ -570,10 +576,10 @@ def trace_gbuffer(scene: Scene, albedo, rough, metal, origins, dirs, H: int, W: 
     e3 = lambda: torch.empty(R, 3, device=dev)
     e1 = lambda: torch.empty(R, device=dev)
     o = dict(x=e3(), n=e3(), wo=e3(), albedo=e3(), rough=e1(), metal=e1(), depth=e1(), rgb=e3(),
-             valid=torch.empty(R, dtype=torch.uint8, device=dev), weight=e1(), nlen=e1())
+             valid=torch.empty(R, dtype=torch.uint8, device=dev), weight=e1(), nlen=e1(), stop=e1())
     st = _gbuffer_out_struct(o)
     rays = make_rays(origins, dirs, 0.0, float("inf"))
-    opts = make_trace_opts(k, t_cut, (0.0, 0.0, 0.0), None, None)
+    opts = make_trace_opts(k, t_cut, (0.0, 0.0, 0.0), None, None, o["stop"])
     attrs = grt_surfel_attrs(_ptr(albedo), _ptr(rough), _ptr(metal))
     ws = _workspace(grt_trace_workspace_bytes(R), dev)
     _check(load_library().grt_trace_gbuffer(scene.handle, C.byref(rays), C.byref(opts), C.byref(attrs),
@@ -609,7 +615,7 @@ def trace_gbuffer_backward(scene: Scene, albedo, rough, metal, origins, dirs, fw
     ast = grt_attr_grads(*(_ptr(attr_grads[key]) if attr_grads.get(key) is not None else None
                            for key in ("albedo", "rough", "metal")))
     rays = make_rays(origins, dirs, 0.0, float("inf"))
-    opts = make_trace_opts(k, t_cut, (0.0, 0.0, 0.0), None, None)
+    opts = make_trace_opts(k, t_cut, (0.0, 0.0, 0.0), None, None, fwd.get("stop"))
     attrs = grt_surfel_attrs(_ptr(albedo), _ptr(rough), _ptr(metal))
     ws = _workspace(grt_trace_workspace_bytes(R), dev)
     _check(load_library().grt_trace_gbuffer_backward(scene.handle, C.byref(rays), C.byref(opts), C.byref(attrs),
@@ -631,12 +637,14 @@ def _grads_struct(g):
 
 
 def trace_backward(scene: Scene, origins, dirs, fwd_rgb, fwd_T, grad_rgb, grad_T=None, t_min=0.0,
-                   t_max=float("inf"), k=16, t_cut=1e-3, grads=None, stream=None):
-    """Accumulate d/d(surfels) of sum grad_rgb . c_rt + grad_T . T into ``grads``."""
+                   t_max=float("inf"), k=16, t_cut=1e-3, grads=None, stop=None, stream=None):
+    """Accumulate d/d(surfels) of sum grad_rgb . c_rt + grad_T . T into
+    ``grads``; ``stop`` (the forward's, from trace(save_stop=True)) bounds the
+    re-traversal."""
     if grads is None:
         grads = zero_grads(scene.n, origins.device)
     rays = make_rays(origins, dirs, t_min, t_max)
-    opts = make_trace_opts(k, t_cut)
+    opts = make_trace_opts(k, t_cut, stop=stop)
     ws = _workspace(grt_trace_workspace_bytes(origins.shape[0]), origins.device)
     grt_trace_backward(scene.handle, rays, opts, fwd_rgb, fwd_T, grad_rgb.contiguous(),
                        None if grad_T is None else grad_T.contiguous(), _grads_struct(grads), ws, stream)
@@ -836,19 +844,19 @@ class TraceFn(torch.autograd.Function):
     def forward(ctx_, means, scales, quats, opacity, rgb, origins, dirs, gctx, t_min, k, t_cut, alpha_min):
         scene = Scene(gctx, means.detach().contiguous(), scales.detach().contiguous(), quats.detach().contiguous(),
                       opacity.detach().contiguous(), rgb.detach().contiguous(), alpha_min)
-        out = trace(scene, origins, dirs, t_min=t_min, k=k, t_cut=t_cut)
+        out = trace(scene, origins, dirs, t_min=t_min, k=k, t_cut=t_cut, save_stop=True)
         ctx_.scene = scene
         ctx_.cfg = (t_min, k, t_cut)
-        ctx_.save_for_backward(origins, dirs, out["rgb"], out["T"])
+        ctx_.save_for_backward(origins, dirs, out["rgb"], out["T"], out["stop"])
         return out["rgb"], out["T"]
 
     @staticmethod
     def backward(ctx_, g_rgb, g_T):
-        origins, dirs, rgb, T = ctx_.saved_tensors
+        origins, dirs, rgb, T, stop = ctx_.saved_tensors
         t_min, k, t_cut = ctx_.cfg
         g = trace_backward(ctx_.scene, origins, dirs, rgb, T,
                            torch.zeros_like(rgb) if g_rgb is None else g_rgb,
-                           None if g_T is None else g_T, t_min=t_min, k=k, t_cut=t_cut)
+                           None if g_T is None else g_T, t_min=t_min, k=k, t_cut=t_cut, stop=stop)
         return g["means"], g["scales"], g["quats"], g["opacity"], g["rgb"], None, None, None, None, None, None, None
 
 

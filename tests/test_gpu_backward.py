@@ -38,22 +38,31 @@ def check_grads(g, ref13, rel=1e-3, floor=1e-2):
         assert l2 < rel, (name, l2)
 
 
-def test_trace_backward_config0(grt_ctx):
+@pytest.mark.parametrize("bounded", [False, True])
+def test_trace_backward_config0(grt_ctx, bounded):
+    """Re-traversal over the whole ray range, or bounded by the forward's
+    saved stop depth: the same gradients."""
     grt, ctx = grt_ctx
     from gpu_util import t, scene_tensors
     s = W.scene0(); r = W.rays0()
     g = np.random.default_rng(0)
-    ref_f = O.trace(s, r.origins, r.dirs)
+    ref_f = O.trace(s, r.origins, r.dirs, cap=64)
     keep = ref_f["margins"][:, 3] >= 1e-5  # cutoff knife edges carry no gradient in either side
     gC = (g.normal(0, 1, (r.n, 3)) * keep[:, None]).astype(np.float32)
     gT = (g.normal(0, 1, r.n) * keep).astype(np.float32)
     ref = O.trace_backward(s, r.origins, r.dirs, gC, gT)
     scene = grt.Scene(ctx, *scene_tensors(s))
     o, d = t(r.origins), t(r.dirs)
-    fwd = grt.trace(scene, o, d)
-    gg = grt.trace_backward(scene, o, d, fwd["rgb"], fwd["T"], t(gC), t(gT))
+    fwd = grt.trace(scene, o, d, save_stop=bounded)
+    gg = grt.trace_backward(scene, o, d, fwd["rgb"], fwd["T"], t(gC), t(gT), stop=fwd.get("stop"))
     torch.cuda.synchronize()
     check_grads({k: v.cpu().numpy() for k, v in gg.items()}, ref)
+    if bounded:  # the stop depth is the depth of the last composited hit
+        nh = ref_f["nhit"]
+        last = np.where(nh > 0, ref_f["tau"][np.arange(r.n), np.maximum(nh - 1, 0)], 0.0)
+        stop = fwd["stop"].cpu().numpy()
+        ok = keep & (nh <= 64)
+        np.testing.assert_allclose(stop[ok], last[ok], rtol=1e-5, atol=1e-6)
 
 
 def test_trace_autograd_function(grt_ctx):

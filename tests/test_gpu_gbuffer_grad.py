@@ -111,9 +111,10 @@ def test_gbuffer_backward_each_map(grt_ctx, keys):
 
 
 def test_gbuffer_backward_k_and_nothing_upstream(grt_ctx):
-    """K only changes the order of float atomics; zero upstream gradients,
-    or gradients only on uncovered pixels, add exactly nothing; attribute
-    gradients may be left out."""
+    """K, and bounding the re-traversal by the saved stop depth, only change
+    the order of float atomics; zero upstream gradients, or gradients only on
+    uncovered pixels, add exactly nothing; attribute gradients may be left
+    out."""
     grt, ctx = grt_ctx
     from gpu_util import t, DEV
     s = W.scene1(n=10000, seed=1, s_lo=0.01, s_hi=0.06)
@@ -122,6 +123,13 @@ def test_gbuffer_backward_k_and_nothing_upstream(grt_ctx):
     up, _ = upstream(s, at, o, d, 0.5, seed=4)
     gg12, ga12, fwd, scene = run_gpu(grt, ctx, s, at, o, d, 32, 24, up, 0.5, k=12)
     mats = [t(a) for a in at]
+    # unbounded re-traversal (no saved stop depth) gives the same gradients
+    fwd_nostop = {kk: v for kk, v in fwd.items() if kk != "stop"}
+    gu, gau = grt.trace_gbuffer_backward(scene, *mats, t(o), t(d), fwd_nostop, {kk: t(v) for kk, v in up.items()})
+    for name in BLOCKS:
+        close(gu[name].cpu().numpy(), gg12[name].cpu().numpy().astype(np.float64), f"{name} unbounded", rel=1e-4)
+    for name in ABLOCKS:
+        close(gau[name].cpu().numpy(), ga12[name].cpu().numpy().astype(np.float64), f"{name} unbounded", rel=1e-4)
     for k in (1, 32):
         gk, gak, _, _ = run_gpu(grt, ctx, s, at, o, d, 32, 24, up, 0.5, k=k, scene=scene)
         for name in BLOCKS:
