@@ -248,6 +248,27 @@ int grt_trace_gbuffer(const grt_scene *scene, const grt_rays *rays, const grt_tr
                       const grt_surfel_attrs *attrs, float min_opacity, grt_gbuffer_out *out, void *workspace,
                       size_t ws_bytes, void *stream);
 
+/* A pinhole camera (double): the eye, a point it looks at, the up direction
+ * and the vertical field of view in degrees. */
+typedef struct {
+    double eye[3];
+    double target[3];
+    double up[3];
+    double vfov_deg;
+} grt_camera;
+
+/* Primary rays of an H x W image, one through each pixel centre, row-major
+ * with row 0 at the top (the camera rays grt_trace_gbuffer takes):
+ *   f = normalize(target - eye), r = normalize(f x up), u = r x f,
+ *   t = tan(vfov_deg * pi/180 * 0.5),
+ *   sx = ((j + 0.5) / W * 2 - 1) * t * (W / H), sy = (1 - (i + 0.5) / H * 2) * t,
+ *   d(i, j) = normalize(f + sx r + sy u),  o = eye,
+ * each evaluated in double, left to right as written, with no fused
+ * multiply-add, then rounded to float.  out_o, out_d [H*W, 3] device float32.
+ * GRT_ERR_INVALID for a degenerate camera (eye = target, up parallel to the
+ * view direction, vfov outside (0, 180)) or an empty image. */
+int grt_camera_rays(grt_ctx *ctx, const grt_camera *cam, int H, int W, float *out_o, float *out_d, void *stream);
+
 /* Upstream gradients of the primary-ray G-buffer's maps (device, float32,
  * borrowed; x, n, albedo, rgb [n,3], rough, metal, depth [n]; any NULL =
  * zero).  wo and valid have none. */
@@ -547,7 +568,10 @@ int grt_denoise(grt_ctx *ctx, int H, int W, const float *rgb, const float *depth
  * preempt_share: rays that more urgent requests may run ahead of a started
  *                request by stopping its epochs, as a share of its own rays
  *                (0 or negative = never stop an epoch).  Stopping lowers the
- *                mean latency under load and raises the largest ones. */
+ *                mean latency under load and raises the largest ones.
+ * attrs:         per-surfel materials (device, borrowed for the server's
+ *                life) for camera requests; all NULL = camera requests are
+ *                refused. */
 typedef struct {
     size_t mem_budget;
     int max_jobs;
@@ -557,13 +581,20 @@ typedef struct {
     float t_cut;
     double slack_per_ray;
     double preempt_share;
+    grt_surfel_attrs attrs;
 } grt_server_opts;
 
 /* A request.  All pointers are HOST memory, borrowed until the request is
  * done (pinned memory lets uploads overlap compute).  G-buffer arrays as in
  * grt_gbuffer; env_rgb [env_H, env_W, 3] as in grt_env_create; sample
  * allocation and random identity as in grt_mis_opts; out_rgb [H*W*3]
- * receives c_pbr. */
+ * receives c_pbr.
+ * Camera request (camera_request != 0): the G-buffer pointers are ignored
+ * (may be NULL).  The server traces the request's G-buffer from `camera` on
+ * its upload stream, as grt_camera_rays followed by grt_trace_gbuffer (the
+ * server's attrs, k and t_cut, coverage at min_opacity in (0, 1]), and then
+ * renders it like an uploaded one: the image equals grt_render_mis on that
+ * traced G-buffer. */
 typedef struct {
     int H, W;
     const float *x;
@@ -579,6 +610,9 @@ typedef struct {
     uint64_t seed;
     uint32_t job;
     float *out_rgb;
+    int camera_request;
+    grt_camera camera;
+    float min_opacity;
 } grt_job;
 
 /* Pool bytes a request occupies while resident (0 if malformed). */

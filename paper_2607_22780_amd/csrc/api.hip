@@ -634,6 +634,20 @@ int grt_mesh_destroy(grt_mesh *mesh)
     return GRT_OK;
 }
 
+int grt_camera_rays(grt_ctx *ctx, const grt_camera *cam, int H, int W, float *out_o, float *out_d, void *stream)
+{
+    if (!ctx || !cam || !out_o || !out_d) return fail(GRT_ERR_INVALID, "NULL argument");
+    if (H <= 0 || W <= 0 || (int64_t)H * W > 0x7fffffff) return fail(GRT_ERR_INVALID, "bad image size %dx%d", H, W);
+    grt::PinholeDev c;
+    if (!grt::make_pinhole(cam->eye, cam->target, cam->up, cam->vfov_deg, H, W, c))
+        return fail(GRT_ERR_INVALID, "degenerate camera");
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    hipError_t e = grt::launch_camera_rays(c, H, W, out_o, out_d, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "camera rays launch");
+    return GRT_OK;
+}
+
 int grt_denoise(grt_ctx *ctx, int H, int W, const float *rgb, const float *depth, const float *normal,
                 const uint8_t *valid, const grt_denoise_opts *opts, float *out_rgb, void *stream)
 {

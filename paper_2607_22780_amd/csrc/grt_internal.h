@@ -175,6 +175,16 @@ struct TraceBwdArgs {
     GradPtrs g;
 };
 hipError_t launch_trace_backward(const TraceBwdArgs &a, int k, int num_cu, hipStream_t st);
+// Pinhole camera rays (grt_camera_rays): the camera frame in double, set up
+// on the host, and one ray per pixel centre.
+struct PinholeDev {
+    double eye[3], f[3], r[3], u[3];
+    double t, aspect;
+};
+bool make_pinhole(const double eye[3], const double target[3], const double up[3], double vfov_deg, int H, int W,
+                  PinholeDev &c);
+hipError_t launch_camera_rays(const PinholeDev &c, int H, int W, float *o, float *d, hipStream_t st);
+
 // Backward of the primary-ray G-buffer: the forward's maps (fwd_*), upstream
 // gradients (g_*, NULL = zero) and attribute gradients (ga_*, NULL = skipped).
 struct TraceGBufBwdArgs {

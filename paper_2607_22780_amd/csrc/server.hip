@@ -372,6 +372,7 @@ struct grt_server {
     std::vector<uint64_t> resident;  // uploading or running, in admission order
     std::vector<int> free_slots;
     hipStream_t copy = nullptr;
+    unsigned long long *copy_counters = nullptr;  // ray fetch of G-buffer traces on the copy stream
     grt::EpochSlot ep[2];
     int chunk_cap = 0;  // chunk table entries per epoch
     double rate = 5e7;  // traced rays per second, running estimate (launch gate)
@@ -406,9 +407,58 @@ int check_job(const grt_job *j)
     if (j->env_H <= 0 || j->env_W <= 0 || (int64_t)j->env_H * j->env_W > (1 << 24)) return GRT_ERR_INVALID;
     const int spp = j->n_cos + j->n_ggx + j->n_env;
     if (j->n_cos < 0 || j->n_ggx < 0 || j->n_env < 0 || spp <= 0 || spp > 4096) return GRT_ERR_INVALID;
-    if (!j->x || !j->n || !j->wo || !j->albedo || !j->rough || !j->metal || !j->valid || !j->env_rgb || !j->out_rgb)
+    if (!j->env_rgb || !j->out_rgb) return GRT_ERR_INVALID;
+    if (j->camera_request) {
+        grt::PinholeDev c;
+        if (!(j->min_opacity > 0.0f && j->min_opacity <= 1.0f)) return GRT_ERR_INVALID;
+        if (!grt::make_pinhole(j->camera.eye, j->camera.target, j->camera.up, j->camera.vfov_deg, j->H, j->W, c))
+            return GRT_ERR_INVALID;
+    } else if (!j->x || !j->n || !j->wo || !j->albedo || !j->rough || !j->metal || !j->valid) {
         return GRT_ERR_INVALID;
+    }
     return GRT_OK;
+}
+
+// The G-buffer of a camera request, traced on the copy stream into the
+// request's G-buffer area (as grt_camera_rays + grt_trace_gbuffer).  The
+// camera rays borrow the request's ray-record area (24 of its >= 48 bytes per
+// pixel) and the depth and colour maps its contribution area (16 of >= 16
+// bytes per pixel); both are written only later, on the same stream.
+hipError_t trace_request_gbuffer(grt_server *s, ServerJob &j)
+{
+    const grt_job &q = j.spec;
+    const int64_t npix = (int64_t)q.H * q.W;
+    grt::RenderArgs &a = j.args;
+    grt::PinholeDev c;
+    if (!grt::make_pinhole(q.camera.eye, q.camera.target, q.camera.up, q.camera.vfov_deg, q.H, q.W, c))
+        return hipErrorInvalidValue;  // checked at submission
+    float *o = reinterpret_cast<float *>(a.rays), *d = o + 3 * npix;
+    hipError_t e = grt::launch_camera_rays(c, q.H, q.W, o, d, s->copy);
+    if (e != hipSuccess) return e;
+    grt::TraceGBufArgs b;
+    memset(&b, 0, sizeof(b));
+    b.f.S = s->S;
+    b.f.n = npix;
+    b.f.o = o;
+    b.f.d = d;
+    b.f.tmin = 0.0f;
+    b.f.tmax = INFINITY;
+    b.f.tcut = s->opts.t_cut;
+    b.f.counters = s->copy_counters;
+    b.albedo = s->opts.attrs.albedo;
+    b.rough = s->opts.attrs.rough;
+    b.metal = s->opts.attrs.metal;
+    b.min_opacity = q.min_opacity;
+    b.x = const_cast<float *>(a.x);
+    b.n = const_cast<float *>(a.n);
+    b.wo = const_cast<float *>(a.wo);
+    b.out_albedo = const_cast<float *>(a.alb);
+    b.out_rough = const_cast<float *>(a.rough);
+    b.out_metal = const_cast<float *>(a.metal);
+    b.valid = const_cast<uint8_t *>(a.valid);
+    b.depth = reinterpret_cast<float *>(a.contrib);
+    b.rgb = b.depth + npix;
+    return grt::launch_trace_gbuffer(b, s->opts.k, s->ctx->num_cu, s->copy);
 }
 
 // Upload a job's inputs and build its tables on the copy stream.
@@ -422,11 +472,16 @@ hipError_t upload(grt_server *s, ServerJob &j)
         const void *dst;
         const void *src;
         size_t n;
-    } cps[] = {{a.x, q.x, 12 * npix},       {a.n, q.n, 12 * npix},         {a.wo, q.wo, 12 * npix},
-               {a.alb, q.albedo, 12 * npix}, {a.rough, q.rough, 4 * npix},  {a.metal, q.metal, 4 * npix},
-               {a.valid, q.valid, npix},     {a.E.rgb, q.env_rgb, 12 * (size_t)q.env_H * q.env_W}};
-    for (const Cp &c : cps)
-        if ((e = hipMemcpyAsync((void *)c.dst, c.src, c.n, hipMemcpyHostToDevice, s->copy)) != hipSuccess) return e;
+    } cps[] = {{a.E.rgb, q.env_rgb, 12 * (size_t)q.env_H * q.env_W}, {a.x, q.x, 12 * npix},
+               {a.n, q.n, 12 * npix},         {a.wo, q.wo, 12 * npix},    {a.alb, q.albedo, 12 * npix},
+               {a.rough, q.rough, 4 * npix},  {a.metal, q.metal, 4 * npix}, {a.valid, q.valid, npix}};
+    // a camera request uploads only its environment and traces its G-buffer
+    const int ncp = q.camera_request ? 1 : (int)(sizeof(cps) / sizeof(cps[0]));
+    for (int i = 0; i < ncp; ++i)
+        if ((e = hipMemcpyAsync((void *)cps[i].dst, cps[i].src, cps[i].n, hipMemcpyHostToDevice, s->copy)) !=
+            hipSuccess)
+            return e;
+    if (q.camera_request && (e = trace_request_gbuffer(s, j)) != hipSuccess) return e;
     if ((e = grt::launch_env_build(a.E.rgb, q.env_H, q.env_W, j.env, s->copy)) != hipSuccess) return e;
     // every sample's ray record up front, so epochs only trace, and the
     // samples' coherent traversal order
@@ -830,6 +885,7 @@ void destroy_resources(grt_server *s)
         if (E.stream) (void)hipStreamDestroy(E.stream);
     }
     if (s->copy) (void)hipStreamSynchronize(s->copy);
+    if (s->copy_counters) (void)hipFree(s->copy_counters);
     if (s->pool) (void)hipFree(s->pool);
     if (s->copy) (void)hipStreamDestroy(s->copy);
 }
@@ -872,6 +928,7 @@ int grt_server_create(grt_ctx *ctx, const grt_scene *scene, const grt_server_opt
     bool ok = hipSetDevice(ctx->device) == hipSuccess;
     ok = ok && hipMalloc((void **)&s->pool, opts->mem_budget) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) == hipSuccess;
+    ok = ok && hipMalloc((void **)&s->copy_counters, grt::kCounterBytes) == hipSuccess;
     for (grt::EpochSlot &E : s->ep) {
         ok = ok && hipMalloc((void **)&E.d_jobs, sizeof(grt::RenderArgs) * opts->max_jobs) == hipSuccess;
         ok = ok && hipMalloc((void **)&E.d_chunks, sizeof(grt::ServeChunk) * s->chunk_cap) == hipSuccess;
@@ -907,6 +964,9 @@ int grt_server_submit(grt_server *s, const grt_job *job, uint64_t *id)
 {
     if (!s || !id) return sfail(GRT_ERR_INVALID, "NULL argument");
     if (check_job(job) != GRT_OK) return sfail(GRT_ERR_INVALID, "malformed job");
+    if (job->camera_request && s->S.n > 0 &&
+        (!s->opts.attrs.albedo || !s->opts.attrs.rough || !s->opts.attrs.metal))
+        return sfail(GRT_ERR_INVALID, "camera requests need the server's surfel attributes");
     const size_t bytes = job_bytes(*job);
     if (bytes > (s->opts.mem_budget & ~(size_t)255)) return sfail(GRT_ERR_ADMISSION, "job exceeds the memory budget");
     std::lock_guard<std::mutex> lk(s->mu);

@@ -15,6 +15,8 @@
 // staged per wavefront so that one instruction updates whole lines).
 //
 // Both kernels run persistent wavefronts that fetch rays dynamically.
+#include <cmath>
+
 #include "grt_internal.h"
 #include "grt_kernels.h"
 
@@ -247,6 +249,70 @@ hipError_t launch_trace_gbuffer(const TraceGBufArgs &a, int k, int num_cu, hipSt
     case 32: return go_trace_gbuffer<32>(a, num_cu, st);
     default: return hipErrorInvalidValue;
     }
+}
+
+// ---- pinhole camera rays ----------------------------------------------------
+// Every quantity is formed in double in the order the ABI states, with
+// contraction off, so the rays equal that formula evaluated on any IEEE
+// machine and rounded to float.
+
+static bool normalize3(const double v[3], double out[3])
+{
+#pragma clang fp contract(off)
+    const double l = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    if (!(l > 0.0) || !std::isfinite(l)) return false;
+    for (int c = 0; c < 3; ++c) out[c] = v[c] / l;
+    return true;
+}
+
+static void cross3(const double a[3], const double b[3], double out[3])
+{
+#pragma clang fp contract(off)
+    out[0] = a[1] * b[2] - a[2] * b[1];
+    out[1] = a[2] * b[0] - a[0] * b[2];
+    out[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+bool make_pinhole(const double eye[3], const double target[3], const double up[3], double vfov_deg, int H, int W,
+                  PinholeDev &c)
+{
+#pragma clang fp contract(off)
+    if (H <= 0 || W <= 0 || !(vfov_deg > 0.0 && vfov_deg < 180.0)) return false;
+    const double v[3] = {target[0] - eye[0], target[1] - eye[1], target[2] - eye[2]};
+    double rr[3];
+    if (!normalize3(v, c.f)) return false;
+    cross3(c.f, up, rr);
+    if (!normalize3(rr, c.r)) return false;
+    cross3(c.r, c.f, c.u);
+    for (int k = 0; k < 3; ++k) c.eye[k] = eye[k];
+    c.t = tan(vfov_deg * (M_PI / 180.0) * 0.5);
+    c.aspect = (double)W / (double)H;
+    return true;
+}
+
+__global__ void k_camera_rays(PinholeDev c, int H, int W, float *o, float *d)
+{
+#pragma clang fp contract(off)
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (int64_t)H * W) return;
+    const int i = (int)(p / W), j = (int)(p % W);
+    const double sx = (((double)j + 0.5) / (double)W * 2.0 - 1.0) * c.t * c.aspect;
+    const double sy = (1.0 - ((double)i + 0.5) / (double)H * 2.0) * c.t;
+    double v[3];
+    for (int k = 0; k < 3; ++k) v[k] = c.f[k] + sx * c.r[k] + sy * c.u[k];
+    const double l = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    for (int k = 0; k < 3; ++k) {
+        d[3 * p + k] = (float)(v[k] / l);
+        o[3 * p + k] = (float)c.eye[k];
+    }
+}
+
+hipError_t launch_camera_rays(const PinholeDev &c, int H, int W, float *o, float *d, hipStream_t st)
+{
+    const int64_t n = (int64_t)H * W;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_camera_rays, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, c, H, W, o, d);
+    return hipGetLastError();
 }
 
 // Backward of the primary-ray G-buffer by re-traversal: the same hits as the

@@ -103,14 +103,27 @@ class grt_mis_opts(C.Structure):
 class grt_server_opts(C.Structure):
     _fields_ = [("mem_budget", C.c_size_t), ("max_jobs", C.c_int), ("epoch_rays", C.c_int64), ("k", C.c_int),
                 ("t_min", C.c_float), ("t_cut", C.c_float), ("slack_per_ray", C.c_double),
-                ("preempt_share", C.c_double)]
+                ("preempt_share", C.c_double), ("attrs", grt_surfel_attrs)]
+
+
+class grt_camera(C.Structure):
+    _fields_ = [("eye", C.c_double * 3), ("target", C.c_double * 3), ("up", C.c_double * 3), ("vfov_deg", C.c_double)]
+
+
+def make_camera(eye, target, vfov_deg, up=(0.0, 1.0, 0.0)) -> grt_camera:
+    c = grt_camera()
+    for i in range(3):
+        c.eye[i], c.target[i], c.up[i] = float(eye[i]), float(target[i]), float(up[i])
+    c.vfov_deg = float(vfov_deg)
+    return c
 
 
 class grt_job(C.Structure):
     _fields_ = [("H", C.c_int), ("W", C.c_int), ("x", VP), ("n", VP), ("wo", VP), ("albedo", VP), ("rough", VP),
                 ("metal", VP), ("valid", VP), ("env_rgb", VP), ("env_H", C.c_int), ("env_W", C.c_int),
                 ("n_cos", C.c_int), ("n_ggx", C.c_int), ("n_env", C.c_int), ("seed", C.c_uint64),
-                ("job", C.c_uint32), ("out_rgb", VP)]
+                ("job", C.c_uint32), ("out_rgb", VP), ("camera_request", C.c_int), ("camera", grt_camera),
+                ("min_opacity", C.c_float)]
 
 
 # every symbol include/grt.h declares, with (restype, argtypes)
@@ -135,6 +148,7 @@ SIGNATURES = {
                                  C.c_size_t, VP]),
     "grt_trace_gbuffer": (C.c_int, [VP, P(grt_rays), P(grt_trace_opts), P(grt_surfel_attrs), C.c_float,
                                     P(grt_gbuffer_out), VP, C.c_size_t, VP]),
+    "grt_camera_rays": (C.c_int, [VP, P(grt_camera), C.c_int, C.c_int, VP, VP, VP]),
     "grt_trace_gbuffer_backward": (C.c_int, [VP, P(grt_rays), P(grt_trace_opts), P(grt_surfel_attrs),
                                              P(grt_gbuffer_out), P(grt_gbuffer_grad), P(grt_surfel_grads),
                                              P(grt_attr_grads), VP, C.c_size_t, VP]),
@@ -560,6 +574,17 @@ def _gbuffer_out_struct(o):
     return grt_gbuffer_out(*(_ptr(o[k_]) if o.get(k_) is not None else None for k_ in GBUFFER_OUT_KEYS))
 
 
+def camera_rays(ctx: Context, camera: grt_camera, H: int, W: int, stream=None):
+    """Primary rays of an H x W pinhole camera (row-major, row 0 at the top):
+    (origins [H*W,3], dirs [H*W,3]) on the context's device."""
+    dev = ctx.device
+    o = torch.empty(H * W, 3, device=dev)
+    d = torch.empty(H * W, 3, device=dev)
+    _check(load_library().grt_camera_rays(ctx.handle, C.byref(camera), int(H), int(W), _ptr(o), _ptr(d),
+                                          _stream(stream)))
+    return o, d
+
+
 def trace_gbuffer(scene: Scene, albedo, rough, metal, origins, dirs, H: int, W: int, min_opacity=0.5, k=12,
                   t_cut=1e-3, stream=None):
     """Primary-ray G-buffer by 2DGRT of H x W camera rays (row-major): dict
@@ -939,23 +964,34 @@ def grt_server_job_bytes(job: grt_job) -> int:
 
 class Request:
     """A relighting request over host tensors (pinned when ``pin``), kept
-    alive until the server is done with it."""
+    alive until the server is done with it.  ``gb`` is a host G-buffer, or
+    ``camera`` (a grt_camera, with H and W) asks the server to trace the
+    G-buffer itself, coverage at ``min_opacity``."""
 
-    def __init__(self, gb, env_rgb, split=(16, 8, 8), seed=0, job=0, pin=True):
+    def __init__(self, gb, env_rgb, split=(16, 8, 8), seed=0, job=0, pin=True, camera=None, H=None, W=None,
+                 min_opacity=0.5):
         def host(a):
             t = torch.from_numpy(a) if not isinstance(a, torch.Tensor) else a
             t = t.contiguous()
             return t.pin_memory() if pin else t
-        self.arrays = [host(a) for a in (gb.x, gb.n, gb.wo, gb.albedo, gb.rough, gb.metal, gb.valid)]
         self.env = host(env_rgb)
-        self.out = torch.zeros(gb.H * gb.W, 3)
+        if camera is None:
+            self.arrays = [host(a) for a in (gb.x, gb.n, gb.wo, gb.albedo, gb.rough, gb.metal, gb.valid)]
+            self.H, self.W = int(gb.H), int(gb.W)
+        else:
+            self.arrays = [None] * 7
+            self.H, self.W = int(H), int(W)
+        self.out = torch.zeros(self.H * self.W, 3)
         if pin:
             self.out = self.out.pin_memory()
-        self.H, self.W = int(gb.H), int(gb.W)
         x, n, wo, alb, rough, metal, valid = self.arrays
         self.struct = grt_job(self.H, self.W, _ptr(x), _ptr(n), _ptr(wo), _ptr(alb), _ptr(rough), _ptr(metal),
                               _ptr(valid), _ptr(self.env), int(self.env.shape[0]), int(self.env.shape[1]),
                               split[0], split[1], split[2], seed, job, _ptr(self.out))
+        if camera is not None:
+            self.struct.camera_request = 1
+            self.struct.camera = camera
+            self.struct.min_opacity = float(min_opacity)
         self.rays = self.H * self.W * sum(split)
 
 
@@ -963,10 +999,14 @@ class Server:
     """Owns a grt_server over a built scene; submit Requests, wait, read times."""
 
     def __init__(self, ctx: Context, scene: Scene, mem_budget: int, max_jobs: int = 16, epoch_rays: int = 0, k=8,
-                 t_min=1e-3, t_cut=1e-3, slack_per_ray=-1.0, preempt_share=-1.0):
+                 t_min=1e-3, t_cut=1e-3, slack_per_ray=-1.0, preempt_share=-1.0, attrs=None):
+        """attrs: (albedo, rough, metal) device tensors for camera requests,
+        kept alive with the server."""
         self.ctx, self.scene = ctx, scene
+        self.attrs = attrs
+        at = grt_surfel_attrs(*(_ptr(a) for a in attrs)) if attrs is not None else grt_surfel_attrs()
         self.opts = grt_server_opts(int(mem_budget), int(max_jobs), int(epoch_rays), int(k), float(t_min),
-                                    float(t_cut), float(slack_per_ray), float(preempt_share))
+                                    float(t_cut), float(slack_per_ray), float(preempt_share), at)
         self.handle = grt_server_create(ctx.handle, scene.handle, self.opts)
         self.requests = {}
 

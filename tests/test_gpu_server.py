@@ -164,3 +164,66 @@ def test_urgent_requests_stop_a_large_epoch(setup):
     np.testing.assert_array_equal(big.out.numpy(), direct(grt, ctx, scene, *big_in))
     for r, x in zip(smalls, small_in):
         np.testing.assert_array_equal(r.out.numpy(), direct(grt, ctx, scene, *x))
+
+
+CAMERAS = [((3.5, 0.4, 0.2), (0.0, 0.0, 0.0), 40.0, (0.0, 1.0, 0.0)),
+           ((0.3, 1.8, -3.2), (0.1, -0.2, 0.4), 55.0, (0.0, 1.0, 0.0)),
+           ((2.0, 2.0, 2.0), (0.0, 0.0, 0.0), 25.0, (0.3, 1.0, -0.2))]
+
+
+def test_camera_rays_match_the_pinhole(setup):
+    """grt_camera_rays is the pinhole formula in double, rounded once: bit for
+    bit the seeded generator's rays, on ragged sizes; degenerate cameras are
+    refused."""
+    grt, ctx, _ = setup
+    for (eye, tgt, fov, up), (H, Wd) in zip(CAMERAS, [(48, 40), (33, 17), (1, 7)]):
+        o, d = grt.camera_rays(ctx, grt.make_camera(eye, tgt, fov, up), H, Wd)
+        wo, wd = W.pinhole(eye, tgt, fov, H, Wd, up=up)
+        np.testing.assert_array_equal(d.cpu().numpy(), wd.astype(np.float32))
+        np.testing.assert_array_equal(o.cpu().numpy(), wo.astype(np.float32))
+    for cam in (grt.make_camera((0, 0, 0), (0, 0, 0), 40.0), grt.make_camera((0, 0, 1), (0, 0, 0), 40.0, up=(0, 0, 1)),
+                grt.make_camera((0, 0, 1), (0, 0, 0), 180.0)):
+        with pytest.raises(grt.GrtError):
+            grt.camera_rays(ctx, cam, 4, 4)
+
+
+def test_camera_requests_match_the_traced_gbuffer_render(setup):
+    """A camera request's image equals grt_render_mis on the G-buffer that
+    grt_trace_gbuffer traces from the same camera, mixed with uploaded
+    requests; a server without surfel attributes refuses camera requests."""
+    grt, ctx, scene = setup
+    from gpu_util import t
+    at = [t(a) for a in W.surfel_materials(scene.n, seed=4)]
+    cams = []
+    for i, ((eye, tgt, fov, up), (H, Wd)) in enumerate(zip(CAMERAS, [(40, 32), (33, 17), (24, 24)])):
+        cams.append((grt.make_camera(eye, tgt, fov, up), H, Wd, W.envmap(32, 64, seed=20 + i),
+                     W.mis_split([8, 16, 4][i]), 300 + i, 40 + i, [0.5, 0.3, 0.9][i]))
+    refs = []
+    for cam, H, Wd, env, split, seed, job, mo in cams:
+        o, d = grt.camera_rays(ctx, cam, H, Wd)
+        g = grt.trace_gbuffer(scene, *at, o, d, H, Wd, min_opacity=mo, k=12)
+        E = grt.Env(ctx, t(env))
+        refs.append(grt.render_mis(scene, E, g["gbuffer"], split=split, seed=seed, job=job, k=8)["rgb"].cpu().numpy())
+        torch.cuda.synchronize()
+        assert g["valid"].float().mean().item() > 0.05
+    up = requests(2, seed=5)
+    up_refs = [direct(grt, ctx, scene, gb, env, split, seed, job) for gb, env, split, seed, job in up]
+    srv = grt.Server(ctx, scene, mem_budget=1 << 30, max_jobs=8, epoch_rays=1 << 15, attrs=at)
+    rs = [grt.Request(None, env, split, seed, job, camera=cam, H=H, W=Wd, min_opacity=mo)
+          for cam, H, Wd, env, split, seed, job, mo in cams]
+    ru = [grt.Request(gb, env, split, seed, job) for gb, env, split, seed, job in up]
+    order = [rs[0], ru[0], rs[1], ru[1], rs[2]]
+    ids = [srv.submit(r) for r in order]
+    for jid in ids:
+        assert srv.wait(jid) == 0
+    for r, want in zip(rs, refs):
+        np.testing.assert_array_equal(r.out.numpy(), want)
+    for r, want in zip(ru, up_refs):
+        np.testing.assert_array_equal(r.out.numpy(), want)
+    assert srv.stats()["pool_free"] == (1 << 30)
+    srv.close()
+    bare = grt.Server(ctx, scene, mem_budget=1 << 28, max_jobs=2)
+    cam, H, Wd, env, split, seed, job, mo = cams[0]
+    with pytest.raises(grt.GrtError):
+        bare.submit(grt.Request(None, env, split, seed, job, camera=cam, H=H, W=Wd, min_opacity=mo))
+    bare.close()
