@@ -155,15 +155,23 @@ def serve_leg(ctx, scene, k, reqs, gbs, envs, slack=-1.0, epoch=0, detail=False,
                   for i, q in enumerate(reqs)]
     req_srv, req_one = mk(), mk()
     rays = sum(r.rays for r in req_srv)
+    # the same requests as cameras: the server traces each G-buffer itself
+    # (2DGRT primary rays with the surfels' materials) and uploads only the
+    # environment
+    cams = {q.cam: grt.make_camera(*W.camera3(W.rng(3, 10 + q.cam)), 60.0) for q in reqs}
+    mats = [torch.from_numpy(a).to(dev) for a in W.surfel_materials(scene.n, seed=0)]
+    req_cam = [grt.Request(None, pin(envs[i]), splits[i], q.seed, q.rid, camera=cams[q.cam], H=q.res, W=q.res)
+               for i, q in enumerate(reqs)]
 
-    def run_server(replay, share=share):
+    def run_server(replay, share=share, rlist=None):
+        rlist = req_srv if rlist is None else rlist
         srv = grt.Server(ctx, scene, mem_budget=48 << 30, max_jobs=16, k=k, slack_per_ray=slack, epoch_rays=epoch,
-                         preempt_share=share)
+                         preempt_share=share, attrs=mats)
         warm = grt.Request(pinned[(reqs[0].res, reqs[0].cam)], pin(envs[0]), (1, 1, 1), 1, 1)
         srv.wait(srv.submit(warm))
         t0 = time.perf_counter()
         ids = []
-        for q, r in zip(reqs, req_srv):
+        for q, r in zip(reqs, rlist):
             if replay:
                 dt = t0 + q.arrival_s - time.perf_counter()
                 if dt > 0:
@@ -214,6 +222,8 @@ def serve_leg(ctx, scene, k, reqs, gbs, envs, slack=-1.0, epoch=0, detail=False,
     blat_o, burst_o = run_one(False)
     log("bench: server leg with preemption (replayed arrivals)")
     plat_s, pspan_s, pst = run_server(True, share=0.25)
+    log("bench: server leg with camera requests (replayed arrivals)")
+    clat_s, cspan_s, _ = run_server(True, rlist=req_cam)
     res = {
         "workload": f"room scene resident; {len(reqs)} requests, Poisson {reqs[-1].arrival_s / max(len(reqs) - 1, 1):.3f}"
                     f" s mean gap, res in {{256,512,768,1024}}^2, spp in {{4..64}}, 128x256 env each",
@@ -232,6 +242,10 @@ def serve_leg(ctx, scene, k, reqs, gbs, envs, slack=-1.0, epoch=0, detail=False,
                                       "mean_s": round(float(np.mean(plat_s)), 4),
                                       "mrays_s_replay": round(rays / pspan_s / 1e6, 2),
                                       "stopped_epochs": pst["stopped"]},
+        "server_camera_requests": {"p50_s": round(pct(clat_s, 50), 4), "p99_s": round(pct(clat_s, 99), 4),
+                                   "mean_s": round(float(np.mean(clat_s)), 4),
+                                   "mrays_s_replay": round(rays / cspan_s / 1e6, 2),
+                                   "upload_per_request": "environment only (G-buffer traced by the server)"},
         "images_identical": bool(same),
     }
     if detail:
