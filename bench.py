@@ -461,13 +461,14 @@ def main():
         per_ray = bb if dominant == "bwd" else bf
         achieved = per_ray * rays / (ms * 1e-3) / 1e9
         kname = "k_render_bwd" if dominant == "bwd" else "k_render"
-        traffic = None
+        traffic = l2_hit = None
         if os.path.exists(TRAFFIC):
             tr = json.load(open(TRAFFIC))
             if tr.get("source_hash") == source_hash() and kname in tr.get("kernels", {}):
                 traffic = tr["kernels"][kname]["hbm_bytes"]
+                l2_hit = tr["kernels"][kname].get("l2_hit")
         roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, kernel=kname,
+                        frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, l2_hit=l2_hit, kernel=kname,
                         bytes_per_ray=round(per_ray, 1), kernel_ms=round(ms, 3))
 
     if args.calib_copy:
