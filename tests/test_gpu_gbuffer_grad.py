@@ -187,3 +187,41 @@ def test_gbuffer_backward_room_1024_sampled(grt_ctx):
     ref13, refa = O.trace_gbuffer_backward(s, at, o[pix], d[pix], {k: v.astype(np.float64) for k, v in up_s.items()})
     assert np.count_nonzero(ref13[:, 0]) >= 64
     check(gg, ga, ref13, refa)
+
+
+def test_gbuffer_backward_edge_cases(grt_ctx):
+    """An empty scene covers nothing and gets no gradient; no rays is a
+    no-op; a single pixel matches the oracle; a forward without its saved
+    weight is refused."""
+    grt, ctx = grt_ctx
+    from gpu_util import t, scene_tensors, DEV
+    z = lambda *sh: np.zeros(sh, np.float32)
+    scene0 = grt.Scene(ctx, *scene_tensors(W.Surfels(z(0, 3), z(0, 2), z(0, 4), z(0), z(0, 3))))
+    mats0 = [t(z(0, 3)), t(z(0)), t(z(0))]
+    o, d = camera(4, 3, seed=1)
+    fwd = grt.trace_gbuffer(scene0, *mats0, t(o), t(d), 4, 3)
+    assert not fwd["valid"].any()
+    up = {k: torch.ones_like(fwd[k]) for k in DIM}
+    gg, ga = grt.trace_gbuffer_backward(scene0, *mats0, t(o), t(d), fwd, up)
+    torch.cuda.synchronize()
+    assert all(v.numel() == 0 for v in gg.values()) and all(v.numel() == 0 for v in ga.values())
+    s = W.scene1(n=20000, seed=0, s_lo=0.01, s_hi=0.06)
+    at = W.surfel_materials(s.n, seed=7)
+    scene = grt.Scene(ctx, *scene_tensors(s))
+    mats = [t(a) for a in at]
+    e3 = torch.empty(0, 3, device=DEV)
+    f0 = grt.trace_gbuffer(scene, *mats, e3, e3.clone(), 0, 0)
+    g0, a0 = grt.trace_gbuffer_backward(scene, *mats, e3, e3.clone(), f0, {})
+    torch.cuda.synchronize()
+    assert not any(v.any() for v in g0.values()) and not any(v.any() for v in a0.values())
+    o1, d1 = camera(1, 1, seed=1)
+    up1, keep = upstream(s, at, o1, d1, 0.5, seed=3)
+    assert keep.all()
+    gg1, ga1, fw1, _ = run_gpu(grt, ctx, s, at, o1, d1, 1, 1, up1, 0.5, scene=scene)
+    ref13, refa = O.trace_gbuffer_backward(s, at, o1, d1, {k: v.astype(np.float64) for k, v in up1.items()},
+                                           min_opacity=0.5)
+    assert np.count_nonzero(ref13[:, 0]) >= 10
+    check(gg1, ga1, ref13, refa)
+    bad = {k: v for k, v in fw1.items() if k != "weight"}
+    with pytest.raises(grt.GrtError):
+        grt.trace_gbuffer_backward(scene, *mats, t(o1), t(d1), bad, {k: t(v) for k, v in up1.items()})

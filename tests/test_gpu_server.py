@@ -227,3 +227,22 @@ def test_camera_requests_match_the_traced_gbuffer_render(setup):
     with pytest.raises(grt.GrtError):
         bare.submit(grt.Request(None, env, split, seed, job, camera=cam, H=H, W=Wd, min_opacity=mo))
     bare.close()
+
+
+def test_single_pixel_camera_request(setup):
+    """A 1x1 camera request (the smallest image) equals the render of its
+    traced G-buffer."""
+    grt, ctx, scene = setup
+    from gpu_util import t
+    at = [t(a) for a in W.surfel_materials(scene.n, seed=4)]
+    cam = grt.make_camera(*CAMERAS[0][:3], CAMERAS[0][3])
+    env = W.envmap(16, 32, seed=9)
+    o, d = grt.camera_rays(ctx, cam, 1, 1)
+    g = grt.trace_gbuffer(scene, *at, o, d, 1, 1, min_opacity=0.5, k=12)
+    want = grt.render_mis(scene, grt.Env(ctx, t(env)), g["gbuffer"], split=(2, 1, 1), seed=5, job=3,
+                          k=8)["rgb"].cpu().numpy()
+    srv = grt.Server(ctx, scene, mem_budget=1 << 26, max_jobs=2, attrs=at)
+    r = grt.Request(None, env, (2, 1, 1), 5, 3, camera=cam, H=1, W=1)
+    assert srv.wait(srv.submit(r)) == 0
+    np.testing.assert_array_equal(r.out.numpy(), want)
+    srv.close()
