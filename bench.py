@@ -113,7 +113,13 @@ def cpu_baseline(s, gb, env, npx: int = 384):
     t2 = time.time()
     rays = npx * sum(SPLIT)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=rays / (t2 - t0) / 1e6, unit="Mrays/s", cores=cores, kind="oracle",
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+    except OSError:
+        pass
+    return dict(value=rays / (t2 - t0) / 1e6, unit="Mrays/s", cores=cores, kind="oracle", cpu=model,
                 sample=f"{npx} valid pixels x {sum(SPLIT)} spp ({rays} rays) of the same step, forward "
                        f"{t1 - t0:.2f}s + backward {t2 - t1:.2f}s, scene/G-buffer generation excluded")
 
@@ -469,7 +475,9 @@ def main():
                 l2_hit = tr["kernels"][kname].get("l2_hit")
         roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                         frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, l2_hit=l2_hit, kernel=kname,
-                        bytes_per_ray=round(per_ray, 1), kernel_ms=round(ms, 3))
+                        bytes_per_ray=round(per_ray, 1), kernel_ms=round(ms, 3),
+                        traffic_gbs=round(traffic / (ms * 1e-3) / 1e9, 1) if traffic else None,
+                        traced_fraction=round(wc["traced_fraction"], 4))
 
     if args.calib_copy:
         a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
