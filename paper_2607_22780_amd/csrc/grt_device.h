@@ -199,6 +199,10 @@ __device__ __forceinline__ uint64_t make_key(float tau, uint32_t id)
 #endif
 constexpr int kLdsDepth = GRT_LDS_DEPTH;  // LDS entries per lane and stack
 constexpr int kBwdLdsDepth = 12;          // backward kernels: their LDS also holds gradient tables
+// Backward kernels composite a hit (running the gradient chain) only in
+// surfel steps where at least 3/16 of the wavefront's active lanes have one to
+// composite, or no lane is still walking (measured best of 1/16 .. 6/16).
+constexpr int kBwdCompShare16 = 3;
 // Surfel steps run when at least kSurfelShare4 / 4 of a wavefront's active
 // lanes wait for one.
 #ifndef GRT_SURFEL_SHARE4
@@ -260,7 +264,12 @@ struct Frontier {
     }
 };
 
-template <int K, int D = kLdsDepth>
+// kCompShare16 > 0: lanes with buffered hits join a surfel step only when at
+// least kCompShare16/16 of the active lanes have one, or when no lane is still
+// walking, so an expensive visitor runs with more lanes at once.  Each lane's
+// own sequence of steps is unchanged, and every call either walks some lane
+// or runs the step for all of them.  0: they join every surfel step.
+template <int K, int D = kLdsDepth, int kCompShare16 = 0>
 struct Walker {
     static constexpr int kDepth = D;  // LDS entries per lane and stack
     float3 o, d, inv;
@@ -487,9 +496,23 @@ struct Walker {
                 pend = -leaf - 1;
             }
         }
-        const bool want = pend != kNone || ncomp > 0;
-        const int nwant = __popcll(__ballot(want)), nact = __popcll(__ballot(1));
-        if (!want || (4 * nwant < kSurfelShare4 * nact && nwant < nact)) return false;
+        const bool wl = pend != kNone, wc = ncomp > 0;
+        bool want = wl || wc;
+        int nwant, nact;
+        bool all;
+        if (kCompShare16 == 0) {
+            nwant = __popcll(__ballot(want));
+            nact = __popcll(__ballot(1));
+            all = nwant == nact;
+        } else {
+            const int nl = __popcll(__ballot(wl)), nc = __popcll(__ballot(wc));
+            nact = __popcll(__ballot(1));
+            all = nl + nc == nact;
+            const bool comp_ok = 16 * nc >= kCompShare16 * nact || all;
+            want = wl || (wc && comp_ok);
+            nwant = nl + (comp_ok ? nc : 0);
+        }
+        if (!want || (4 * nwant < kSurfelShare4 * nact && !all)) return false;
         const bool comp = ncomp > 0;
         const uint32_t sp = comp ? pos[0] : (uint32_t)pend;
         // One surfel site for leaf tests and composites: the record and its
