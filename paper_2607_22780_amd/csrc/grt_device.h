@@ -201,8 +201,11 @@ constexpr int kLdsDepth = GRT_LDS_DEPTH;  // LDS entries per lane and stack
 constexpr int kBwdLdsDepth = 12;          // backward kernels: their LDS also holds gradient tables
 // Backward kernels composite a hit (running the gradient chain) only in
 // surfel steps where at least 3/16 of the wavefront's active lanes have one to
-// composite, or no lane is still walking (measured best of 1/16 .. 6/16).
+// composite, or no lane is still walking, and run surfel steps once 3/8 of
+// the active lanes wait for one (measured best of composite shares 1/16 ..
+// 6/16 and step shares 1/4 .. 5/8).
 constexpr int kBwdCompShare16 = 3;
+constexpr int kBwdSiteShare8 = 3;
 // Surfel steps run when at least kSurfelShare4 / 4 of a wavefront's active
 // lanes wait for one.
 #ifndef GRT_SURFEL_SHARE4
@@ -269,7 +272,9 @@ struct Frontier {
 // walking, so an expensive visitor runs with more lanes at once.  Each lane's
 // own sequence of steps is unchanged, and every call either walks some lane
 // or runs the step for all of them.  0: they join every surfel step.
-template <int K, int D = kLdsDepth, int kCompShare16 = 0>
+// kSiteShare8 > 0: surfel steps run once kSiteShare8/8 of the active lanes
+// wait for one (0: kSurfelShare4/4).
+template <int K, int D = kLdsDepth, int kCompShare16 = 0, int kSiteShare8 = 0>
 struct Walker {
     static constexpr int kDepth = D;  // LDS entries per lane and stack
     float3 o, d, inv;
@@ -512,7 +517,8 @@ struct Walker {
             want = wl || (wc && comp_ok);
             nwant = nl + (comp_ok ? nc : 0);
         }
-        if (!want || (4 * nwant < kSurfelShare4 * nact && !all)) return false;
+        const bool few = kSiteShare8 ? 8 * nwant < kSiteShare8 * nact : 4 * nwant < kSurfelShare4 * nact;
+        if (!want || (few && !all)) return false;
         const bool comp = ncomp > 0;
         const uint32_t sp = comp ? pos[0] : (uint32_t)pend;
         // One surfel site for leaf tests and composites: the record and its
@@ -541,6 +547,10 @@ struct Walker {
         return false;
     }
 };
+
+// The walker of the backward kernels (see kBwdCompShare16, kBwdSiteShare8).
+template <int K>
+using BwdWalker = Walker<K, kBwdLdsDepth, kBwdCompShare16, kBwdSiteShare8>;
 
 // Upper end of a backward's re-traversal: the depth of the forward's last
 // composited hit when it was saved (every hit the backward composites lies at

@@ -293,7 +293,7 @@ template <int K>
 struct RenderBwdJob {
     const RenderArgs &a;
     SceneDev S;
-    Walker<K, kBwdLdsDepth, kBwdCompShare16> w;
+    BwdWalker<K> w;
     GradVisit v;
     int spp;
 
@@ -303,7 +303,7 @@ struct RenderBwdJob {
         v.stage = t;
         stage_init(t);
     }
-    __device__ __forceinline__ Walker<K, kBwdLdsDepth, kBwdCompShare16> &walker() { return w; }
+    __device__ __forceinline__ BwdWalker<K> &walker() { return w; }
     __device__ __forceinline__ GradVisit &visit() { return v; }
 
     __device__ __forceinline__ bool begin(int64_t g)

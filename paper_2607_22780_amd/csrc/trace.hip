@@ -82,7 +82,7 @@ template <int K>
 struct TraceBwdJob {
     const TraceBwdArgs &a;
     SceneDev S;
-    Walker<K, kBwdLdsDepth, kBwdCompShare16> w;
+    BwdWalker<K> w;
     GradVisit v;
 
     __device__ TraceBwdJob(const TraceBwdArgs &a_, WaveStage *t) : a(a_), S(a_.f.S), v(a_.f.S, a_.f.tcut, a_.g)
@@ -90,7 +90,7 @@ struct TraceBwdJob {
         v.stage = t;
         stage_init(t);
     }
-    __device__ __forceinline__ Walker<K, kBwdLdsDepth, kBwdCompShare16> &walker() { return w; }
+    __device__ __forceinline__ BwdWalker<K> &walker() { return w; }
     __device__ __forceinline__ GradVisit &visit() { return v; }
 
     __device__ __forceinline__ bool begin(int64_t r)
@@ -322,7 +322,7 @@ template <int K>
 struct TraceGBufBwdJob {
     const TraceGBufBwdArgs &a;
     SceneDev S;
-    Walker<K, kBwdLdsDepth, kBwdCompShare16> w;
+    BwdWalker<K> w;
     GBufGradVisit v;
 
     __device__ TraceGBufBwdJob(const TraceGBufBwdArgs &a_, WaveStage *t) : a(a_), S(a_.f.S), v(a_.f.S, a_.f.tcut, a_.g)
@@ -332,7 +332,7 @@ struct TraceGBufBwdJob {
         v.stage = t;
         stage_init(t);
     }
-    __device__ __forceinline__ Walker<K, kBwdLdsDepth, kBwdCompShare16> &walker() { return w; }
+    __device__ __forceinline__ BwdWalker<K> &walker() { return w; }
     __device__ __forceinline__ GBufGradVisit &visit() { return v; }
 
     static __device__ __forceinline__ float3 ld3(const float *p, int64_t r)
