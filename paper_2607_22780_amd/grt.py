@@ -912,6 +912,32 @@ class RenderMISFn(torch.autograd.Function):
                 None, None)
 
 
+class GBufferFn(torch.autograd.Function):
+    """The primary-ray G-buffer's deferred maps (Eq. deferred_maps on traced
+    camera rays) as functions of the surfel parameters and their attributes:
+    returns (x, n, albedo, rough, metal, depth, rgb, valid); valid is not
+    differentiable, and wo (= -d) is left out."""
+
+    @staticmethod
+    def forward(ctx_, means, scales, quats, opacity, rgb, albedo, rough, metal, gctx, origins, dirs, H, W,
+                min_opacity=0.5, k=12, alpha_min=1.0 / 255.0):
+        scene = Scene(gctx, means.detach().contiguous(), scales.detach().contiguous(), quats.detach().contiguous(),
+                      opacity.detach().contiguous(), rgb.detach().contiguous(), alpha_min)
+        mats = [a.detach().contiguous() for a in (albedo, rough, metal)]
+        fwd = trace_gbuffer(scene, *mats, origins, dirs, H, W, min_opacity=min_opacity, k=k)
+        ctx_.scene, ctx_.mats, ctx_.fwd, ctx_.rays, ctx_.k = scene, mats, fwd, (origins, dirs), k
+        ctx_.mark_non_differentiable(fwd["valid"])
+        ctx_.set_materialize_grads(False)
+        return tuple(fwd[key] for key in GBUFFER_GRAD_KEYS) + (fwd["valid"],)
+
+    @staticmethod
+    def backward(ctx_, *grads):
+        grad = {key: g for key, g in zip(GBUFFER_GRAD_KEYS, grads[:len(GBUFFER_GRAD_KEYS)])}
+        gs, ga = trace_gbuffer_backward(ctx_.scene, *ctx_.mats, *ctx_.rays, ctx_.fwd, grad, k=ctx_.k)
+        return ((gs["means"], gs["scales"], gs["quats"], gs["opacity"], gs["rgb"], ga["albedo"], ga["rough"],
+                 ga["metal"]) + (None,) * 8)
+
+
 # --------------------------------------------------------------------------
 # Relighting server
 # --------------------------------------------------------------------------

@@ -225,3 +225,33 @@ def test_gbuffer_backward_edge_cases(grt_ctx):
     bad = {k: v for k, v in fw1.items() if k != "weight"}
     with pytest.raises(grt.GrtError):
         grt.trace_gbuffer_backward(scene, *mats, t(o1), t(d1), bad, {k: t(v) for k, v in up1.items()})
+
+
+def test_gbuffer_autograd_function(grt_ctx):
+    """GBufferFn: torch.autograd drives the same forward and backward kernels
+    (maps, then grads of sum_k g_k . map_k for surfels and attributes)."""
+    grt, ctx = grt_ctx
+    from gpu_util import t, scene_tensors
+    s = W.scene1(n=10000, seed=4, s_lo=0.01, s_hi=0.06)
+    at = W.surfel_materials(s.n, seed=5)
+    o, d = camera(24, 20, seed=3)
+    up, _ = upstream(s, at, o, d, 0.5, seed=8)
+    params = [t(a).requires_grad_(True) for a in s.arrays()]
+    mats = [t(a).requires_grad_(True) for a in at]
+    outs = grt.GBufferFn.apply(*params, *mats, ctx, t(o), t(d), 24, 20)
+    maps = dict(zip(("x", "n", "albedo", "rough", "metal", "depth", "rgb"), outs[:7]))
+    assert outs[7].dtype == torch.uint8 and not outs[7].requires_grad
+    loss = sum((maps[k] * t(v).reshape(maps[k].shape)).sum() for k, v in up.items())
+    loss.backward()
+    torch.cuda.synchronize()
+    scene = grt.Scene(ctx, *scene_tensors(s))
+    mt = [t(a) for a in at]
+    fwd = grt.trace_gbuffer(scene, *mt, t(o), t(d), 24, 20)
+    gg, ga = grt.trace_gbuffer_backward(scene, *mt, t(o), t(d), fwd, {k: t(v) for k, v in up.items()})
+    torch.cuda.synchronize()
+    for p, name in zip(params, BLOCKS):
+        close(p.grad.cpu().numpy(), gg[name].cpu().numpy().astype(np.float64), name, rel=1e-4)
+    for m, name in zip(mats, ABLOCKS):
+        close(m.grad.cpu().numpy(), ga[name].cpu().numpy().astype(np.float64), name, rel=1e-4)
+    for k in ("x", "n", "albedo", "depth", "rgb"):
+        np.testing.assert_array_equal(maps[k].detach().cpu().numpy(), fwd[k].cpu().numpy())
