@@ -89,25 +89,33 @@ struct ServeJob {
     __device__ __forceinline__ void drain() {}
 };
 
-template <int K>
+// kStop: the epoch may be stopped (e.stop set).  Without it the persistent
+// loop carries no stop test, as a direct render's does.
+template <int K, bool kStop>
 __global__ void __launch_bounds__(256) GRT_OCCUPANCY k_serve(ServeEpoch e)
 {
     ServeJob<K> job(e);
-    run_persistent<K>(job, e.counters, e.total, e.stop);
+    if (kStop)
+        run_persistent<K>(job, e.counters, e.total, e.stop);
+    else
+        run_persistent<K>(job, e.counters, e.total);
 }
 
-template <int K>
+template <int K, bool kStop>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_serve_w3(ServeEpoch e)
 {
     ServeJob<K> job(e);
-    run_persistent<K>(job, e.counters, e.total, e.stop);
+    if (kStop)
+        run_persistent<K>(job, e.counters, e.total, e.stop);
+    else
+        run_persistent<K>(job, e.counters, e.total);
 }
 
 // An epoch holding rays of one request only: its arguments travel by value
 // (uniform across the grid, as in a direct render); its rays are one range
 // of the request's sample order, or a few once a stopped epoch handed some
 // back (then each ray finds its range in the chunk table).
-template <int K>
+template <int K, bool kPlain>
 struct ServeOneJob {
     const RenderArgs &a;
     SceneDev S;
@@ -125,7 +133,7 @@ struct ServeOneJob {
     __device__ __forceinline__ bool begin(int64_t g)
     {
         int64_t q = r0 + g;
-        if (nchunks > 1) {
+        if (!kPlain && nchunks > 1) {
             const ServeChunk ch = chunks[find_chunk(chunks, nchunks, g)];
             q = ch.begin + (g - ch.offset);
         }
@@ -136,23 +144,32 @@ struct ServeOneJob {
     __device__ __forceinline__ void drain() {}
 };
 
-template <int K>
+// kPlain: one range of rays and no stop flag (every epoch while preemption
+// is off), so the kernel is the direct render's loop with the request's
+// arguments; otherwise it handles a range table and a stop flag.
+template <int K, bool kPlain>
 __global__ void __launch_bounds__(256) GRT_OCCUPANCY
     k_serve_one(RenderArgs a, const ServeChunk *chunks, int nchunks, int64_t r0, int64_t n,
                 unsigned long long *counters, const int *stop)
 {
-    ServeOneJob<K> job(a, chunks, nchunks, r0);
-    run_persistent<K>(job, counters, n, stop);
+    ServeOneJob<K, kPlain> job(a, chunks, nchunks, r0);
+    if (kPlain)
+        run_persistent<K>(job, counters, n);
+    else
+        run_persistent<K>(job, counters, n, stop);
 }
 
 // K = 12 held to 3 wavefronts per SIMD, as the direct render's forward
-template <int K>
+template <int K, bool kPlain>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
     k_serve_one_w3(RenderArgs a, const ServeChunk *chunks, int nchunks, int64_t r0, int64_t n,
                    unsigned long long *counters, const int *stop)
 {
-    ServeOneJob<K> job(a, chunks, nchunks, r0);
-    run_persistent<K>(job, counters, n, stop);
+    ServeOneJob<K, kPlain> job(a, chunks, nchunks, r0);
+    if (kPlain)
+        run_persistent<K>(job, counters, n);
+    else
+        run_persistent<K>(job, counters, n, stop);
 }
 
 // counters/total: the claim counters of a preemptible epoch that held the
@@ -168,15 +185,36 @@ __global__ void k_serve_reduce(const RenderArgs *a, int64_t npix, const unsigned
     reduce_pixel(p, a->nc + a->ng + a->ne, a->contrib, a->out);
 }
 
+template <int K, bool kStop>
+static hipError_t go_serve_as(const ServeEpoch &e, int num_cu, hipStream_t st)
+{
+    if constexpr (K == 12) {
+        const int nb = persistent_blocks(k_serve_w3<K, kStop>, num_cu, e.total);
+        hipLaunchKernelGGL((k_serve_w3<K, kStop>), dim3(nb), dim3(256), 0, st, e);
+    } else {
+        const int nb = persistent_blocks(k_serve<K, kStop>, num_cu, e.total);
+        hipLaunchKernelGGL((k_serve<K, kStop>), dim3(nb), dim3(256), 0, st, e);
+    }
+    return hipGetLastError();
+}
+
 template <int K>
 static hipError_t go_serve(const ServeEpoch &e, int num_cu, hipStream_t st)
 {
+    return e.stop ? go_serve_as<K, true>(e, num_cu, st) : go_serve_as<K, false>(e, num_cu, st);
+}
+
+template <int K, bool kPlain>
+static hipError_t go_serve_one_as(const RenderArgs &a, const ServeEpoch &e, int64_t r0, int num_cu, hipStream_t st)
+{
     if constexpr (K == 12) {
-        const int nb = persistent_blocks(k_serve_w3<K>, num_cu, e.total);
-        hipLaunchKernelGGL(k_serve_w3<K>, dim3(nb), dim3(256), 0, st, e);
+        const int nb = persistent_blocks(k_serve_one_w3<K, kPlain>, num_cu, e.total);
+        hipLaunchKernelGGL((k_serve_one_w3<K, kPlain>), dim3(nb), dim3(256), 0, st, a, e.chunks, e.nchunks, r0,
+                           e.total, e.counters, e.stop);
     } else {
-        const int nb = persistent_blocks(k_serve<K>, num_cu, e.total);
-        hipLaunchKernelGGL(k_serve<K>, dim3(nb), dim3(256), 0, st, e);
+        const int nb = persistent_blocks(k_serve_one<K, kPlain>, num_cu, e.total);
+        hipLaunchKernelGGL((k_serve_one<K, kPlain>), dim3(nb), dim3(256), 0, st, a, e.chunks, e.nchunks, r0,
+                           e.total, e.counters, e.stop);
     }
     return hipGetLastError();
 }
@@ -184,16 +222,8 @@ static hipError_t go_serve(const ServeEpoch &e, int num_cu, hipStream_t st)
 template <int K>
 static hipError_t go_serve_one(const RenderArgs &a, const ServeEpoch &e, int64_t r0, int num_cu, hipStream_t st)
 {
-    if constexpr (K == 12) {
-        const int nb = persistent_blocks(k_serve_one_w3<K>, num_cu, e.total);
-        hipLaunchKernelGGL(k_serve_one_w3<K>, dim3(nb), dim3(256), 0, st, a, e.chunks, e.nchunks, r0, e.total,
-                           e.counters, e.stop);
-    } else {
-        const int nb = persistent_blocks(k_serve_one<K>, num_cu, e.total);
-        hipLaunchKernelGGL(k_serve_one<K>, dim3(nb), dim3(256), 0, st, a, e.chunks, e.nchunks, r0, e.total,
-                           e.counters, e.stop);
-    }
-    return hipGetLastError();
+    return (!e.stop && e.nchunks <= 1) ? go_serve_one_as<K, true>(a, e, r0, num_cu, st)
+                                       : go_serve_one_as<K, false>(a, e, r0, num_cu, st);
 }
 
 // one: the request when every chunk of the epoch is of that one request, else
