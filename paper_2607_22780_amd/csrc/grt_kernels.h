@@ -9,7 +9,10 @@ namespace grt {
 // Forward compositing (Sec. 3.2, Eq. trace; Eq. alpha_blending along the ray).
 // Where to stop is decided on the transmittance of the canonical
 // single-precision alphas (Td); the composited values use alphas from the
-// double-precision crossing.
+// double-precision crossing.  kHitList: the visitor also records the record
+// positions of the composited hits in the ray's stored hit list (hl); the
+// plain forward carries no list pointer at all.
+template <bool kHitList>
 struct CompositeVisit {
     const float4 *rec;
     const float4 *col;
@@ -49,7 +52,7 @@ struct CompositeVisit {
         const float w = T * a;
         C.x += w * c.x; C.y += w * c.y; C.z += w * c.z;
         if (did && cnt < cap) { did[cnt] = (int32_t)id; dtau[cnt] = tau; }
-        if (hl && cnt < hcap) hl[cnt] = p;
+        if (kHitList && hl && cnt < hcap) hl[cnt] = p;
         ++cnt;
         T = T * (1.0f - a);
         Td = trans_step(Td, hit_alpha(r1.w, crho2));

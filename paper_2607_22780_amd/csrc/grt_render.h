@@ -390,11 +390,12 @@ __device__ __forceinline__ void gen_ray(const RenderArgs &a, int64_t r)
 
 // The persistent-loop job of the forward render: begin loads the ray record
 // (skipping untraced samples), finish writes f L_i cos / q and the saved
-// (C, T).  `a` may differ per lane (the server mixes jobs).
-template <int K>
+// (C, T).  `a` may differ per lane (the server mixes jobs).  kHitList: the
+// launch stores hit lists (a.hits); only then does the visitor carry one.
+template <int K, bool kHitList = false>
 struct ShadeTrace {
     Walker<K> w;
-    CompositeVisit v;
+    CompositeVisit<kHitList> v;
 
     __device__ __forceinline__ bool begin(const RenderArgs &a, const SceneDev &S, int64_t r)
     {
@@ -406,7 +407,7 @@ struct ShadeTrace {
         }
         const int spp = a.nc + a.ng + a.ne;
         const int64_t p = r / spp;
-        if (a.hits) {
+        if (kHitList && a.hits) {
             const int64_t nray = (int64_t)a.H * a.W * spp;
             v.hl = a.hits + nray + r * a.hcap;
             v.hcap = a.hcap;

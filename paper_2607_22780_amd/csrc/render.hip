@@ -194,16 +194,16 @@ __global__ void __launch_bounds__(256) k_render_gen(RenderArgs a)
 // Jobs for the persistent loop.  Ray index order keeps a wavefront's chunk on
 // neighbouring pixels (shared origins, nearby surfaces).
 // ---------------------------------------------------------------------------
-template <int K>
+template <int K, bool kHitList>
 struct RenderJob {
     const RenderArgs &a;
     SceneDev S;
-    ShadeTrace<K> t;
+    ShadeTrace<K, kHitList> t;
     int64_t r;  // sample index of the lane's ray
 
     __device__ RenderJob(const RenderArgs &a_) : a(a_), S(a_.S), r(0) {}
     __device__ __forceinline__ Walker<K> &walker() { return t.w; }
-    __device__ __forceinline__ CompositeVisit &visit() { return t.v; }
+    __device__ __forceinline__ decltype(t.v) &visit() { return t.v; }
     __device__ __forceinline__ bool begin(int64_t g)
     {
         r = a.order ? (int64_t)a.order[g] : g;
@@ -333,19 +333,21 @@ struct RenderBwdJob {
     __device__ __forceinline__ void drain() { stage_sync(a.g.acc, v.stage, true); }
 };
 
-template <int K>
+// kHitList: the launch stores hit lists (a.hits set); a separate kernel, so
+// that the plain forward carries no list pointer in its registers.
+template <int K, bool kHitList>
 __global__ void __launch_bounds__(256) GRT_OCCUPANCY k_render(RenderArgs a)
 {
-    RenderJob<K> job(a);
+    RenderJob<K, kHitList> job(a);
     run_persistent<K>(job, a.counters, (int64_t)a.H * a.W * (a.nc + a.ng + a.ne));
 }
 
 // The forward with a 12-hit buffer fits 3 wavefronts per SIMD (168 VGPRs)
 // when the compiler is held to it; it then beats K = 8 (fewer rounds).
-template <int K>
+template <int K, bool kHitList>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_render_w3(RenderArgs a)
 {
-    RenderJob<K> job(a);
+    RenderJob<K, kHitList> job(a);
     run_persistent<K>(job, a.counters, (int64_t)a.H * a.W * (a.nc + a.ng + a.ne));
 }
 
@@ -422,18 +424,24 @@ __global__ void k_render_reduce(int64_t npix, int spp, const float4 *__restrict_
     reduce_pixel(p, spp, contrib, out);
 }
 
-template <int K>
-static hipError_t go_render(const RenderArgs &a, int num_cu, hipStream_t st)
+template <int K, bool kHitList>
+static hipError_t go_render_as(const RenderArgs &a, int num_cu, hipStream_t st)
 {
     const int64_t total = (int64_t)a.H * a.W * (a.nc + a.ng + a.ne);
     if constexpr (K == 12) {
-        const int nb = persistent_blocks(k_render_w3<K>, num_cu, total);
-        hipLaunchKernelGGL(k_render_w3<K>, dim3(nb), dim3(256), 0, st, a);
+        const int nb = persistent_blocks(k_render_w3<K, kHitList>, num_cu, total);
+        hipLaunchKernelGGL((k_render_w3<K, kHitList>), dim3(nb), dim3(256), 0, st, a);
     } else {
-        const int nb = persistent_blocks(k_render<K>, num_cu, total);
-        hipLaunchKernelGGL(k_render<K>, dim3(nb), dim3(256), 0, st, a);
+        const int nb = persistent_blocks(k_render<K, kHitList>, num_cu, total);
+        hipLaunchKernelGGL((k_render<K, kHitList>), dim3(nb), dim3(256), 0, st, a);
     }
     return hipGetLastError();
+}
+
+template <int K>
+static hipError_t go_render(const RenderArgs &a, int num_cu, hipStream_t st)
+{
+    return a.hits ? go_render_as<K, true>(a, num_cu, st) : go_render_as<K, false>(a, num_cu, st);
 }
 
 template <int K>

@@ -74,7 +74,7 @@ struct ServeJob {
 
     __device__ ServeJob(const ServeEpoch &e_) : e(e_), S(e_.S), a(nullptr), r(0) {}
     __device__ __forceinline__ Walker<K> &walker() { return t.w; }
-    __device__ __forceinline__ CompositeVisit &visit() { return t.v; }
+    __device__ __forceinline__ decltype(t.v) &visit() { return t.v; }
 
     __device__ __forceinline__ bool begin(int64_t g)
     {
@@ -129,7 +129,7 @@ struct ServeOneJob {
     __device__ ServeOneJob(const RenderArgs &a_, const ServeChunk *c, int nc, int64_t r0_)
         : a(a_), S(a_.S), chunks(c), nchunks(nc), r0(r0_), r(0) {}
     __device__ __forceinline__ Walker<K> &walker() { return t.w; }
-    __device__ __forceinline__ CompositeVisit &visit() { return t.v; }
+    __device__ __forceinline__ decltype(t.v) &visit() { return t.v; }
     __device__ __forceinline__ bool begin(int64_t g)
     {
         int64_t q = r0 + g;

@@ -38,11 +38,11 @@ struct TraceJob {
     const TraceArgs &a;
     SceneDev S;
     Walker<K> w;
-    CompositeVisit v;
+    CompositeVisit<false> v;
 
     __device__ TraceJob(const TraceArgs &a_) : a(a_), S(a_.S), v(a_.S, a_.tcut) {}
     __device__ __forceinline__ Walker<K> &walker() { return w; }
-    __device__ __forceinline__ CompositeVisit &visit() { return v; }
+    __device__ __forceinline__ CompositeVisit<false> &visit() { return v; }
 
     __device__ __forceinline__ bool begin(int64_t r)
     {
