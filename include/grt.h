@@ -89,9 +89,9 @@ typedef struct {
     const float *rgb;
 } grt_surfels;
 
-/* Bytes of device workspace a scene of n surfels needs (records, bounding
- * boxes, LBVH nodes, sort buffers, and 64 bytes per surfel in which the
- * backward passes sum gradients).  256-byte aligned pointer required. */
+/* Bytes of device workspace a scene of n surfels needs (records and stored
+ * quaternions in LBVH order, bounding boxes, LBVH nodes, sort buffers, and 64
+ * bytes per surfel in which the backward passes sum gradients).  256-byte aligned pointer required. */
 size_t grt_scene_workspace_bytes(int64_t n);
 
 /* Create a scene over borrowed surfel arrays and a caller-owned workspace of

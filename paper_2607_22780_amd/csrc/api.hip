@@ -61,6 +61,7 @@ grt::SceneDev scene_dev(const grt_scene *s)
     d.rec = s->w.rec;
     d.col = s->w.col;
     d.nodes = s->w.nodes;
+    d.quat = s->w.quat;
     d.n = (int32_t)s->s.n;
     return d;
 }
@@ -103,8 +104,6 @@ grt::GradPtrs grad_ptrs(const grt_scene *s, const grt_surfel_grads *g)
     p.means = g->means; p.scales = g->scales; p.quats = g->quats; p.opacity = g->opacity; p.rgb = g->rgb;
     p.order = nullptr;
     p.acc = s->w.acc;
-    p.p_scales = s->s.scales;
-    p.p_quats = s->s.quats;
     return p;
 }
 

@@ -3,9 +3,13 @@
 // Scene layout in the caller's workspace (all in Morton order of the surfel
 // bounding-box centres, so neighbouring surfels sit in neighbouring lines):
 //   rec  [n][4] float4   r0 = (mu.xyz, r2max)      r1 = (n.xyz, opacity)
-//                        r2 = (a_u.xyz, id bits)   r3 = (a_v.xyz, 0)
+//                        r2 = (a_u.xyz, id bits)   r3 = (a_v.xyz, s_u)
 //                        with a_u = t_u / s_u, a_v = t_v / s_v      (64 B)
-//   col  [n]    float4   (rgb, 0)                                    (16 B)
+//   col  [n]    float4   (rgb, s_v)                                  (16 B)
+//   quat [n]    float4   the stored quaternion (w, x, y, z)          (16 B)
+// The backward's chain rule reads the stored scales and quaternion of each
+// composited hit from these, by record position, not from the caller's arrays
+// by surfel id, which would cost a random line per hit.
 //   node [n-1]  Node     both child boxes + child references        (64 B)
 // A child reference >= 0 is an internal node, < 0 is leaf -(pos+1).
 #pragma once
@@ -42,6 +46,7 @@ struct SceneDev {
     const float4 *rec;
     const float4 *col;
     const Node *nodes;
+    const float4 *quat;  // stored quaternions in record order
     int32_t n;
 };
 

@@ -49,6 +49,7 @@ struct SceneWS {
     uint32_t *hist;        // [256 * blocks]
     int32_t *bounds;       // [8]
     float *acc;            // [n,16] gradient lines of the backward passes
+    float4 *quat;          // [n] stored quaternions in record order
     size_t bytes;
 };
 
@@ -78,6 +79,7 @@ inline SceneWS carve_scene(void *base, int64_t n)
     w.hist = (uint32_t *)take(4 * sort_hist_words(n));
     w.bounds = (int32_t *)take(4 * 8);
     w.acc = (float *)take(64 * nn);
+    w.quat = (float4 *)take(16 * nn);
     w.bytes = off;
     return w;
 }
@@ -167,7 +169,6 @@ struct GradPtrs {
     float *means, *scales, *quats, *opacity, *rgb;
     float *acc;  // [n,16] per-surfel lines the kernels accumulate into
     const int32_t *order;  // unused by kernels (ids travel in records)
-    const float *p_scales, *p_quats;
 };
 struct TraceBwdArgs {
     TraceArgs f;

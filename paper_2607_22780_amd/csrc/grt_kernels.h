@@ -212,7 +212,7 @@ __device__ __forceinline__ void stage_sync(float *acc, WaveStage *s, bool all)
 template <bool kDirect>
 __device__ __forceinline__ void hit_param_grads(const HitGeo &hg, const float4 r1, const float4 r2, const float4 r3,
                                                 float3 d, float a, float G, float dA, float dtau, float3 dnx,
-                                                const GradPtrs &g, uint32_t id, float out[10])
+                                                float4 q, float su, float sv, float out[10])
 {
     const float3 n = make_float3(r1.x, r1.y, r1.z);
     const float den = hg.den;
@@ -221,9 +221,7 @@ __device__ __forceinline__ void hit_param_grads(const HitGeo &hg, const float4 r
     const float u = hg.u, v = hg.v;
     const float gamma = -0.5f * a * dA;  // dL/d(rho^2)
     const float du = 2.0f * u * gamma, dv = 2.0f * v * gamma;
-    // parameters of the surfel in its stored form
-    const float4 q = reinterpret_cast<const float4 *>(g.p_quats)[id];
-    const float su = g.p_scales[2 * (size_t)id], sv = g.p_scales[2 * (size_t)id + 1];
+    // parameters of the surfel in its stored form (q, su, sv from the record order)
     const float ql = sqrtf(q.x * q.x + q.y * q.y + q.z * q.z + q.w * q.w);
     const float iq = 1.0f / ql;
     const float qw = q.x * iq, qx = q.y * iq, qy = q.z * iq, qz = q.w * iq;
@@ -265,7 +263,9 @@ struct GradVisit {
     float3 P;
 
     __device__ GradVisit() {}
-    __device__ GradVisit(const SceneDev &S, float t_cut, const GradPtrs &gp) : rec(S.rec), col(S.col), tcut(t_cut), g(gp) {}
+    const float4 *quat;
+    __device__ GradVisit(const SceneDev &S, float t_cut, const GradPtrs &gp)
+        : rec(S.rec), col(S.col), tcut(t_cut), g(gp), quat(S.quat) {}
 
     __device__ __forceinline__ void reset(float3 o_, float3 d_, float3 gC_, float gT_, float3 Cf_, float Tf_)
     {
@@ -298,7 +298,8 @@ struct GradVisit {
             dA -= behind / om;
         }
         float terms[13];
-        hit_param_grads<false>(hg, r1, r2, r3, d, a, G, dA, 0.0f, make_float3(0.f, 0.f, 0.f), g, id, terms);
+        hit_param_grads<false>(hg, r1, r2, r3, d, a, G, dA, 0.0f, make_float3(0.f, 0.f, 0.f), quat[p], r3.w, c.w,
+                               terms);
         terms[10] = w * gC.x; terms[11] = w * gC.y; terms[12] = w * gC.z;
         stage_add(stage, id, terms);
 
@@ -330,8 +331,9 @@ struct GBufGradVisit {
     float T, Td, P;
 
     __device__ GBufGradVisit() {}
+    const float4 *quat;
     __device__ GBufGradVisit(const SceneDev &S, float t_cut, const GradPtrs &gp)
-        : rec(S.rec), col(S.col), tcut(t_cut), g(gp) {}
+        : rec(S.rec), col(S.col), tcut(t_cut), g(gp), quat(S.quat) {}
 
     __device__ __forceinline__ void reset(float3 o_, float3 d_)
     {
@@ -363,8 +365,8 @@ struct GBufGradVisit {
         if (om >= 1e-6f) dA += P / om;
         const float sw = side * w;
         float terms[13];
-        hit_param_grads<true>(hg, r1, r2, r3, d, a, G, dA, w * kD, make_float3(sw * kN.x, sw * kN.y, sw * kN.z), g,
-                              id, terms);
+        hit_param_grads<true>(hg, r1, r2, r3, d, a, G, dA, w * kD, make_float3(sw * kN.x, sw * kN.y, sw * kN.z),
+                              quat[p], r3.w, c.w, terms);
         terms[10] = w * kC.x; terms[11] = w * kC.y; terms[12] = w * kC.z;
         stage_add(stage, id, terms);
         if (ga_albedo) {

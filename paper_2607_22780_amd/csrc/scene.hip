@@ -245,7 +245,7 @@ __global__ void k_records(int n, const uint32_t *__restrict__ order, const float
                           const float *__restrict__ scales, const float *__restrict__ quats,
                           const float *__restrict__ opacity, const float *__restrict__ rgb, float alpha_min,
                           const float *__restrict__ box_tmp, float4 *__restrict__ rec, float4 *__restrict__ col,
-                          float *__restrict__ leaf_box)
+                          float *__restrict__ leaf_box, float4 *__restrict__ qrec)
 {
 #pragma clang fp contract(off)
     int p = blockIdx.x * blockDim.x + threadIdx.x;
@@ -258,8 +258,9 @@ __global__ void k_records(int n, const uint32_t *__restrict__ order, const float
     rec[4 * (size_t)p + 0] = make_float4(means[3 * id], means[3 * id + 1], means[3 * id + 2], support_r2(op, alpha_min));
     rec[4 * (size_t)p + 1] = make_float4(nn.x, nn.y, nn.z, op);
     rec[4 * (size_t)p + 2] = make_float4(tu.x / su, tu.y / su, tu.z / su, __uint_as_float(id));
-    rec[4 * (size_t)p + 3] = make_float4(tv.x / sv, tv.y / sv, tv.z / sv, 0.0f);
-    col[p] = make_float4(rgb[3 * id], rgb[3 * id + 1], rgb[3 * id + 2], 0.0f);
+    rec[4 * (size_t)p + 3] = make_float4(tv.x / sv, tv.y / sv, tv.z / sv, su);
+    col[p] = make_float4(rgb[3 * id], rgb[3 * id + 1], rgb[3 * id + 2], sv);
+    qrec[p] = make_float4(quats[4 * id], quats[4 * id + 1], quats[4 * id + 2], quats[4 * id + 3]);
 #pragma unroll
     for (int a = 0; a < 6; ++a) leaf_box[6 * (size_t)p + a] = box_tmp[6 * (size_t)id + a];
 }
@@ -414,7 +415,7 @@ hipError_t launch_scene_build(const grt_surfels &s, float alpha_min, const Scene
     // four passes: sorted codes/ids are back in keys0/vals0
     launch_radix_sort(n, 4, w.keys0, w.vals0, w.keys1, w.vals1, w.hist, st);
     hipLaunchKernelGGL(k_records, dim3(gb), dim3(tb), 0, st, n, w.vals0, s.means, s.scales, s.quats, s.opacity, s.rgb,
-                       alpha_min, w.box_tmp, w.rec, w.col, w.leaf_box);
+                       alpha_min, w.box_tmp, w.rec, w.col, w.leaf_box, w.quat);
     if (n > 1) {
         int gi = (n - 1 + tb - 1) / tb;
         hipLaunchKernelGGL(k_hierarchy, dim3(gi), dim3(tb), 0, st, n, w.keys0, w.nodes, w.parent_int, w.parent_leaf,
