@@ -114,16 +114,18 @@ int grt_scene_set_surfels(grt_scene *scene, const grt_surfels *surfels);
 int grt_scene_destroy(grt_scene *scene);
 
 /* Device pointers into the built scene, for inspection by tests:
- * records [n,16] float (sorted order; word 11 holds the surfel id as bits),
- * nodes [max(n-1,0),16] (child boxes lo/hi as floats 0..11, children as
- * int32 words 12,13: >= 0 internal node, < 0 leaf -(pos+1)), order [n]
- * int32 (sorted position -> surfel id). */
+ * records [n,16] float (sorted order; word 11 holds the surfel id as bits,
+ * word 15 the stored scale s_u), nodes [max(n-1,0),16] (child boxes lo/hi as
+ * floats 0..11, children as int32 words 12,13: >= 0 internal node, < 0 leaf
+ * -(pos+1)), order [n] int32 (sorted position -> surfel id). */
 typedef struct {
     int64_t n;
     const float *records;
     const float *nodes;
     const int32_t *order;
     const float *leaf_boxes; /* [n,6] lo.xyz, hi.xyz in sorted order */
+    const float *colours;    /* [n,4] rgb and the stored scale s_v, sorted order */
+    const float *quats;      /* [n,4] the stored quaternion (w first), sorted order */
 } grt_scene_view;
 int grt_scene_view_get(const grt_scene *scene, grt_scene_view *out);
 

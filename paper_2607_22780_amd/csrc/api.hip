@@ -262,6 +262,8 @@ int grt_scene_view_get(const grt_scene *scene, grt_scene_view *out)
     out->nodes = reinterpret_cast<const float *>(scene->w.nodes);
     out->order = reinterpret_cast<const int32_t *>(scene->w.vals0);
     out->leaf_boxes = scene->w.leaf_box;
+    out->colours = reinterpret_cast<const float *>(scene->w.col);
+    out->quats = reinterpret_cast<const float *>(scene->w.quat);
     return GRT_OK;
 }
 

@@ -42,7 +42,8 @@ class grt_surfels(C.Structure):
 
 
 class grt_scene_view(C.Structure):
-    _fields_ = [("n", C.c_int64), ("records", VP), ("nodes", VP), ("order", VP), ("leaf_boxes", VP)]
+    _fields_ = [("n", C.c_int64), ("records", VP), ("nodes", VP), ("order", VP), ("leaf_boxes", VP),
+                ("colours", VP), ("quats", VP)]
 
 
 class grt_rays(C.Structure):
@@ -427,7 +428,8 @@ class Scene:
 
     def arrays(self):
         """Torch views into the built scene: records [n,16], nodes [n-1,16]
-        (float32; children as int32 in words 12-13), leaf boxes [n,6], order [n]."""
+        (float32; children as int32 in words 12-13), leaf boxes [n,6], order [n],
+        colours [n,4] (rgb, s_v) and stored quaternions [n,4], all in sorted order."""
         v = self.view()
         base = self.workspace.data_ptr()
 
@@ -439,7 +441,9 @@ class Scene:
         return dict(records=sl(v.records, 16 * n, torch.float32).view(n, 16),
                     nodes=sl(v.nodes, 16 * max(n - 1, 0), torch.float32).view(max(n - 1, 0), 16),
                     leaf_boxes=sl(v.leaf_boxes, 6 * n, torch.float32).view(n, 6),
-                    order=sl(v.order, n, torch.int32))
+                    order=sl(v.order, n, torch.int32),
+                    colours=sl(v.colours, 4 * n, torch.float32).view(n, 4),
+                    quats=sl(v.quats, 4 * n, torch.float32).view(n, 4))
 
     def __del__(self):
         if getattr(self, "handle", None) and _LIB is not None:

@@ -120,7 +120,9 @@ def test_stacked_and_occluded(grt_ctx):
 
 def test_bvh_structure(grt_ctx):
     """The LBVH is a binary tree over all leaves; every node's child boxes
-    contain their subtrees' leaf boxes; records hold a permutation of ids."""
+    contain their subtrees' leaf boxes; records hold a permutation of ids, and
+    the stored parameters the backward reads by record position (centre,
+    opacity, s_u, s_v, quaternion, colour) are the caller's, bit for bit."""
     grt, ctx = grt_ctx
     from gpu_util import scene_tensors
     s = W.scene1(n=20000, seed=0)
@@ -131,6 +133,14 @@ def test_bvh_structure(grt_ctx):
     rec, nd, lb = arr["records"], arr["nodes"], arr["leaf_boxes"]
     ids = rec[:, 11].view(np.uint32)
     assert np.array_equal(np.sort(ids), np.arange(n, dtype=np.uint32))
+    assert np.array_equal(arr["order"].view(np.uint32), ids)
+    means, scales, quats, opac, rgb = (np.asarray(a, np.float32) for a in s.arrays())
+    np.testing.assert_array_equal(rec[:, 0:3], means[ids])
+    np.testing.assert_array_equal(rec[:, 7], opac.reshape(-1)[ids])
+    np.testing.assert_array_equal(rec[:, 15], scales[ids, 0])
+    np.testing.assert_array_equal(arr["colours"][:, 3], scales[ids, 1])
+    np.testing.assert_array_equal(arr["colours"][:, 0:3], rgb[ids])
+    np.testing.assert_array_equal(arr["quats"], quats[ids])
     ch = nd[:, 12:14].view(np.int32)
     seen_leaf = np.zeros(n, bool)
     seen_node = np.zeros(n - 1, bool)
