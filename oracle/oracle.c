@@ -326,18 +326,25 @@ static void hit_chain(const Surf64 *s, const float d[3], const Geo64 *g, double 
     out[9] = g->G * dA;
 }
 
-static void add_grads(double *dst, const double *src, int m)
+/* dst += src; with dst_abs (may be NULL) also dst_abs += |src|. */
+static void add_grads(double *dst, double *dst_abs, const double *src, int m)
 {
     for (int i = 0; i < m; ++i) {
 #ifdef _OPENMP
 #pragma omp atomic
 #endif
         dst[i] += src[i];
+        if (dst_abs) {
+#ifdef _OPENMP
+#pragma omp atomic
+#endif
+            dst_abs[i] += fabs(src[i]);
+        }
     }
 }
 
 static void backward_ray(const Scene *S, const float o[3], const float d[3], const RayResult *R,
-                         const double gC[3], double gT, double *g13)
+                         const double gC[3], double gT, double *g13, double *g13_abs)
 {
     double T = 1.0, P[3] = {0, 0, 0};
     for (int64_t k = 0; k < R->K; ++k) {
@@ -356,7 +363,22 @@ static void backward_ray(const Scene *S, const float o[3], const float d[3], con
         double add[13];
         hit_chain(s, d, &g, dA, 0.0, NULL, add);
         for (int c = 0; c < 3; ++c) add[10 + c] = w * gC[c];
-        add_grads(g13 + 13 * id, add, 13);
+        add_grads(g13 + 13 * id, NULL, add, 13);
+        if (g13_abs) {
+            /* error scale: each term's own magnitude, plus the chain applied
+             * to the magnitudes dL/dalpha is formed from (a single-precision
+             * path forms C - P_k as a difference of running sums) */
+            double dAs = T * (fabs(gC[0] * s->c[0]) + fabs(gC[1] * s->c[1]) + fabs(gC[2] * s->c[2]));
+            if (1.0 - a >= 1e-6) {
+                double m = fabs(gT * R->T);
+                for (int c = 0; c < 3; ++c) m += fabs(gC[c]) * (fabs(R->C[c]) + fabs(P[c]));
+                dAs += m / (1.0 - a);
+            }
+            double sc[13];
+            hit_chain(s, d, &g, dAs, 0.0, NULL, sc);
+            for (int i = 0; i < 13; ++i) sc[i] = fabs(add[i]) + (i < 10 ? fabs(sc[i]) : 0.0);
+            add_grads(g13_abs + 13 * id, NULL, sc, 13);
+        }
         T *= 1.0 - a;
     }
 }
@@ -384,6 +406,7 @@ int orc_trace(int64_t n, const float *means, const float *scales, const float *q
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t r = 0; r < nr; ++r) {
         float tmin = tmin_a ? tmin_a[r] : tmin_s, tmax = tmax_a ? tmax_a[r] : tmax_s;
+        if (!(tmin >= 0.0f)) tmin = 0.0f; /* a ray starts at its origin: negative t_min is 0 */
         RayResult R;
         trace_ray(&S, orig + 3 * r, dirs + 3 * r, tmin, tmax, t_cut, &R);
         for (int c = 0; c < 3; ++c) {
@@ -560,12 +583,15 @@ int orc_trace_gbuffer_backward(int64_t n, const float *means, const float *scale
                                const float *rough, const float *metal, int64_t nr, const float *orig,
                                const float *dirs, float tmin_s, float tmax_s, float t_cut, double min_opacity,
                                const double *gx, const double *gn, const double *ga, const double *gr,
-                               const double *gm, const double *gd, const double *gc, double *g13, double *gattr)
+                               const double *gm, const double *gd, const double *gc, double *g13, double *gattr,
+                               double *g13_abs, double *gattr_abs)
 {
     Scene S;
     if (scene_init(&S, n, means, scales, quats, opacity, rgb, alpha_min)) return -1;
     memset(g13, 0, sizeof(double) * 13 * (size_t)n);
     memset(gattr, 0, sizeof(double) * 5 * (size_t)n);
+    if (g13_abs) memset(g13_abs, 0, sizeof(double) * 13 * (size_t)n);
+    if (gattr_abs) memset(gattr_abs, 0, sizeof(double) * 5 * (size_t)n);
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t r = 0; r < nr; ++r) {
         const float *o = orig + 3 * r, *d = dirs + 3 * r;
@@ -575,6 +601,7 @@ int orc_trace_gbuffer_backward(int64_t n, const float *means, const float *scale
         Geo64 *geo = (Geo64 *)malloc(sizeof(Geo64) * (size_t)(K > 0 ? K : 1));
         double *Tk = (double *)malloc(sizeof(double) * (size_t)(K > 0 ? K : 1));
         double *e = (double *)malloc(sizeof(double) * (size_t)(K > 0 ? K : 1));
+        double *es = (double *)malloc(sizeof(double) * (size_t)(K > 0 ? K : 1));
         /* forward sums */
         double T = 1.0, W = 0.0, SD = 0.0, SA[3] = {0, 0, 0}, SR = 0.0, SM = 0.0, SC[3] = {0, 0, 0};
         double N[3] = {0, 0, 0};
@@ -623,7 +650,16 @@ int orc_trace_gbuffer_backward(int64_t n, const float *means, const float *scale
                     ek += pga[c] * ((double)albedo[3 * id + c] - A[c]) + pgc[c] * (sf->c[c] - C[c]);
                 ek += grr * ((double)rough[id] - Rm) + gmm * ((double)metal[id] - Mm);
                 e[k] = ek / W + sgn * (sf->n[0] * gN[0] + sf->n[1] * gN[1] + sf->n[2] * gN[2]);
+                /* magnitudes of the summands of e_k (the error scale of a
+                 * single-precision e_k) */
+                double m = fabs(gD * geo[k].tau) + fabs(gD * D) + fabs(grr * (double)rough[id]) + fabs(grr * Rm) +
+                           fabs(gmm * (double)metal[id]) + fabs(gmm * Mm);
+                for (int c = 0; c < 3; ++c)
+                    m += fabs(pga[c] * (double)albedo[3 * id + c]) + fabs(pga[c] * A[c]) + fabs(pgc[c] * sf->c[c]) +
+                         fabs(pgc[c] * C[c]);
+                es[k] = m / W + fabs(sf->n[0] * gN[0]) + fabs(sf->n[1] * gN[1]) + fabs(sf->n[2] * gN[2]);
             }
+            double Ps = 0.0;
             for (int64_t k = 0; k < K; ++k) {
                 int64_t id = R.h[k].id;
                 const Surf64 *sf = &S.s64[id];
@@ -642,13 +678,26 @@ int orc_trace_gbuffer_backward(int64_t n, const float *means, const float *scale
                 }
                 at[3] = w * grr / W;
                 at[4] = w * gmm / W;
-                add_grads(g13 + 13 * id, add, 13);
-                add_grads(gattr + 5 * id, at, 5);
+                add_grads(g13 + 13 * id, NULL, add, 13);
+                add_grads(gattr + 5 * id, gattr_abs ? gattr_abs + 5 * id : NULL, at, 5);
+                if (g13_abs) {
+                    /* error scale: the terms' magnitudes, plus the chain
+                     * applied to the magnitudes dL/dalpha_k is formed from
+                     * (a single-precision path forms the part behind hit k
+                     * as minus the running sum of w_i e_i in front of it) */
+                    Ps += w * es[k];
+                    double dAs = Tk[k] * es[k] + (1.0 - geo[k].alpha >= 1e-6 ? Ps / (1.0 - geo[k].alpha) : 0.0);
+                    double sc[13];
+                    hit_chain(sf, d, &geo[k], dAs, 0.0, NULL, sc);
+                    for (int i = 0; i < 13; ++i) sc[i] = fabs(add[i]) + (i < 10 ? fabs(sc[i]) : 0.0);
+                    add_grads(g13_abs + 13 * id, NULL, sc, 13);
+                }
             }
         }
         free(geo);
         free(Tk);
         free(e);
+        free(es);
         free(R.h);
     }
     scene_free(&S);
@@ -661,17 +710,19 @@ int orc_trace_backward(int64_t n, const float *means, const float *scales, const
                        const float *opacity, const float *rgb, float alpha_min,
                        int64_t nr, const float *orig, const float *dirs, const float *tmin_a, const float *tmax_a,
                        float tmin_s, float tmax_s, float t_cut,
-                       const double *gC, const double *gT, double *g13)
+                       const double *gC, const double *gT, double *g13, double *g13_abs)
 {
     Scene S;
     if (scene_init(&S, n, means, scales, quats, opacity, rgb, alpha_min)) return -1;
     memset(g13, 0, sizeof(double) * 13 * (size_t)n);
+    if (g13_abs) memset(g13_abs, 0, sizeof(double) * 13 * (size_t)n);
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t r = 0; r < nr; ++r) {
         float tmin = tmin_a ? tmin_a[r] : tmin_s, tmax = tmax_a ? tmax_a[r] : tmax_s;
+        if (!(tmin >= 0.0f)) tmin = 0.0f; /* a ray starts at its origin: negative t_min is 0 */
         RayResult R;
         trace_ray(&S, orig + 3 * r, dirs + 3 * r, tmin, tmax, t_cut, &R);
-        backward_ray(&S, orig + 3 * r, dirs + 3 * r, &R, gC + 3 * r, gT[r], g13);
+        backward_ray(&S, orig + 3 * r, dirs + 3 * r, &R, gC + 3 * r, gT[r], g13, g13_abs);
         free(R.h);
     }
     scene_free(&S);
@@ -1305,11 +1356,12 @@ int orc_render_mis_backward(int64_t n, const float *means, const float *scales, 
                             const float *grough, const float *gmetal, const uint8_t *gvalid,
                             int eH, int eW, const float *env_rgb, const float *marg, const float *cond,
                             int nc, int ng, int ne, uint64_t seed, uint32_t job, float tmin, float tcut,
-                            int64_t np, const int64_t *pix, const double *grad, double *g13)
+                            int64_t np, const int64_t *pix, const double *grad, double *g13, double *g13_abs)
 {
     Scene S;
     if (scene_init(&S, n, means, scales, quats, opacity, rgb, alpha_min)) return -1;
     memset(g13, 0, sizeof(double) * 13 * (size_t)n);
+    if (g13_abs) memset(g13_abs, 0, sizeof(double) * 13 * (size_t)n);
     Env E = {eH, eW, env_rgb, marg, cond};
     MisOpts op = {nc, ng, ne, seed, job, tmin, tcut};
     int spp = nc + ng + ne;
@@ -1334,7 +1386,7 @@ int orc_render_mis_backward(int64_t n, const float *means, const float *scales, 
                     gT += gC[c] * Le[c];
                 }
                 float of[3] = {(float)x[0], (float)x[1], (float)x[2]};
-                backward_ray(&S, of, df, &R, gC, gT, g13);
+                backward_ray(&S, of, df, &R, gC, gT, g13, g13_abs);
             }
             free(R.h);
         }
@@ -1536,4 +1588,25 @@ int orc_render_relight_mesh(int64_t nv, const float *verts, int64_t nf, const in
     shade_pixels(&S, &E, &op, &rl, gx, gn, gwo, galb, grough, gmetal, gvalid, np, pix, out, s_dir, s_q, s_wt, s_Li,
                  s_traced, s_margin);
     return 0;
+}
+
+/* SplitSum(a, r, m, n, E) (Eq. relight_splitsum) of m query results with
+ * caller-supplied prefiltered tables (Ed [PF_H,PF_W,3], Es [PF_L-1,PF_H,PF_W,3],
+ * lut [LUT_N,LUT_N,2]) and environment (level 0 of the specular lookup):
+ * the same function the relit estimator calls, exposed so that its table
+ * lookups can be checked against tables of known content. */
+void orc_split_sum(int eH, int eW, const float *env_rgb, const double *Ed, const double *Es, const double *lut,
+                   int64_t m, const double *albedo, const double *rough, const double *metal, const double *nsum,
+                   const double *w, double *out)
+{
+    Env E = {eH, eW, env_rgb, NULL, NULL};
+    Relight rl = {{NULL, NULL, NULL}, Ed, Es, lut, NULL};
+    for (int64_t k = 0; k < m; ++k) {
+        AttrOut q;
+        q.V = 0.0;
+        for (int c = 0; c < 3; ++c) { q.a[c] = albedo[3 * k + c]; q.n[c] = nsum[3 * k + c]; }
+        q.r = rough[k];
+        q.m = metal[k];
+        split_sum(&E, &rl, &q, w + 3 * k, out + 3 * k);
+    }
 }

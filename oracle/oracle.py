@@ -37,7 +37,7 @@ def lib():
         L.orc_trace.restype = C.c_int
         L.orc_trace.argtypes = [I64, P, P, P, P, P, F, I64, P, P, P, P, F, F, F, P, P, P, P, P, I64, P, P, P]
         L.orc_trace_backward.restype = C.c_int
-        L.orc_trace_backward.argtypes = [I64, P, P, P, P, P, F, I64, P, P, P, P, F, F, F, P, P, P]
+        L.orc_trace_backward.argtypes = [I64, P, P, P, P, P, F, I64, P, P, P, P, F, F, F, P, P, P, P]
         L.orc_env_cdf.restype = C.c_int
         L.orc_env_cdf.argtypes = [C.c_int, C.c_int, P, P, P]
         L.orc_philox.restype = None
@@ -47,7 +47,7 @@ def lib():
                                      [C.c_int, C.c_int, C.c_int, C.c_uint64, C.c_uint32, F, F, I64, P, P] + [P] * 6)
         L.orc_render_mis_backward.restype = C.c_int
         L.orc_render_mis_backward.argtypes = ([I64, P, P, P, P, P, F] + [P] * 7 + [C.c_int, C.c_int, P, P, P] +
-                                              [C.c_int, C.c_int, C.c_int, C.c_uint64, C.c_uint32, F, F, I64, P, P, P])
+                                              [C.c_int, C.c_int, C.c_int, C.c_uint64, C.c_uint32, F, F, I64, P, P, P, P])
         L.orc_env_prefilter.restype = C.c_int
         L.orc_env_prefilter.argtypes = [C.c_int, C.c_int, P, P, P]
         L.orc_dfg_lut.restype = C.c_int
@@ -67,7 +67,7 @@ def lib():
         L.orc_trace_gbuffer.argtypes = ([I64, P, P, P, P, P, F, P, P, P, I64, P, P, F, F, F, C.c_double] + [P] * 9)
         L.orc_trace_gbuffer_backward.restype = C.c_int
         L.orc_trace_gbuffer_backward.argtypes = ([I64, P, P, P, P, P, F, P, P, P, I64, P, P, F, F, F, C.c_double]
-                                                 + [P] * 9)
+                                                 + [P] * 11)
         L.orc_trace_attr.restype = C.c_int
         L.orc_trace_attr.argtypes = [I64, P, P, P, P, F, P, P, P, I64, P, P, F, F, F, P, P, P, P, P]
         if hasattr(L, "orc_count_work"):
@@ -186,11 +186,14 @@ GBUF_GRAD_KEYS = ("x", "n", "albedo", "rough", "metal", "depth", "rgb")
 
 
 def trace_gbuffer_backward(s, attrs, origins, dirs, grads, t_min=0.0, t_max=np.inf, t_cut=T_CUT,
-                           alpha_min=ALPHA_MIN, min_opacity=0.5):
+                           alpha_min=ALPHA_MIN, min_opacity=0.5, with_abs=False):
     """d/d(surfels, attributes) of the sum over covered pixels of
     grads[k] . map_k for the maps of trace_gbuffer (keys x, n, albedo, rough,
     metal, depth, rgb; missing keys are zero).  Returns (g13 [N,13] as
-    trace_backward, gattr [N,5] = albedo 3, roughness, metallic)."""
+    trace_backward, gattr [N,5] = albedo 3, roughness, metallic); with
+    ``with_abs`` also each element's error scale (g13_abs, gattr_abs): the
+    magnitudes of its per-hit terms plus the chain rule applied to the
+    magnitudes of what each hit's dL/dalpha sums (see orc_trace_gbuffer_backward)."""
     arrs = _scene(s)
     alb, rough, metal = (_c(a) for a in attrs)
     o = _c(origins); d = _c(dirs)
@@ -199,17 +202,22 @@ def trace_gbuffer_backward(s, attrs, origins, dirs, grads, t_min=0.0, t_max=np.i
     gp = {k: (_c(grads[k], np.float64).reshape(shape[k]) if grads.get(k) is not None else None)
           for k in GBUF_GRAD_KEYS}
     g13 = np.zeros((s.n, 13)); ga = np.zeros((s.n, 5))
+    g13a = np.zeros((s.n, 13)) if with_abs else None
+    gaa = np.zeros((s.n, 5)) if with_abs else None
     rc = lib().orc_trace_gbuffer_backward(s.n, *map(_p, arrs), alpha_min, _p(alb), _p(rough), _p(metal), R, _p(o),
                                           _p(d), float(t_min), float(t_max), t_cut, float(min_opacity),
                                           *(_p(gp[k]) for k in ("x", "n", "albedo", "rough", "metal", "depth",
-                                                                "rgb")), _p(g13), _p(ga))
+                                                                "rgb")), _p(g13), _p(ga), _p(g13a), _p(gaa))
     assert rc == 0
-    return g13, ga
+    return (g13, ga, g13a, gaa) if with_abs else (g13, ga)
 
 
-def trace_backward(s, origins, dirs, gC, gT, t_min=0.0, t_max=np.inf, t_cut=T_CUT, alpha_min=ALPHA_MIN):
+def trace_backward(s, origins, dirs, gC, gT, t_min=0.0, t_max=np.inf, t_cut=T_CUT, alpha_min=ALPHA_MIN,
+                   with_abs=False):
     """d/d(surfels) of sum_r gC_r . c_rt + gT_r T_fin; returns [N,13] double
-    (mean 3, scale 2, quat 4, opacity 1, rgb 3)."""
+    (mean 3, scale 2, quat 4, opacity 1, rgb 3); with ``with_abs`` also each
+    element's error scale: the magnitudes of its per-hit terms plus the chain
+    rule applied to the magnitudes of what each hit's dL/dalpha sums."""
     arrs = _scene(s)
     o = _c(origins); d = _c(dirs)
     R = o.shape[0]
@@ -217,11 +225,13 @@ def trace_backward(s, origins, dirs, gC, gT, t_min=0.0, t_max=np.inf, t_cut=T_CU
     tmax_a = _c(t_max) if np.ndim(t_max) else None
     gC = _c(gC, np.float64).reshape(R, 3); gT = _c(gT, np.float64).reshape(R)
     g = np.zeros((s.n, 13))
+    ga = np.zeros((s.n, 13)) if with_abs else None
     rc = lib().orc_trace_backward(s.n, *map(_p, arrs), alpha_min, R, _p(o), _p(d), _p(tmin_a), _p(tmax_a),
                                   float(0.0 if tmin_a is not None else t_min),
-                                  float(np.inf if tmax_a is not None else t_max), t_cut, _p(gC), _p(gT), _p(g))
+                                  float(np.inf if tmax_a is not None else t_max), t_cut, _p(gC), _p(gT), _p(g),
+                                  _p(ga))
     assert rc == 0
-    return g
+    return (g, ga) if with_abs else g
 
 
 def env_cdf(env_rgb):
@@ -424,8 +434,9 @@ def render_relight_mesh(m, gb, env_rgb, split, seed, pix=None, job=0, t_min=1e-3
 
 
 def render_mis_backward(s, gb, env_rgb, split, seed, grad, pix=None, job=0, t_min=1e-3, t_cut=T_CUT,
-                        alpha_min=ALPHA_MIN):
-    """d/d(surfels) of sum_k grad[k] . c_pbr(pix[k]); returns [N,13] double."""
+                        alpha_min=ALPHA_MIN, with_abs=False):
+    """d/d(surfels) of sum_k grad[k] . c_pbr(pix[k]); returns [N,13] double
+    (with ``with_abs`` also each element's error scale, as trace_backward)."""
     nc, ng, ne = split
     arrs = _scene(s)
     g = _gb(gb)
@@ -434,11 +445,12 @@ def render_mis_backward(s, gb, env_rgb, split, seed, grad, pix=None, job=0, t_mi
     pix = np.arange(gb.npix, dtype=np.int64) if pix is None else _c(pix, np.int64)
     grad = _c(grad, np.float64).reshape(len(pix), 3)
     out = np.zeros((s.n, 13))
+    oabs = np.zeros((s.n, 13)) if with_abs else None
     rc = lib().orc_render_mis_backward(s.n, *map(_p, arrs), alpha_min, *map(_p, g), e.shape[0], e.shape[1], _p(e),
                                        _p(marg), _p(cond), nc, ng, ne, seed, job, t_min, t_cut, len(pix), _p(pix),
-                                       _p(grad), _p(out))
+                                       _p(grad), _p(out), _p(oabs))
     assert rc == 0
-    return out
+    return (out, oabs) if with_abs else out
 
 
 def split_grads(g13):
@@ -515,4 +527,39 @@ def env_lookup(env_rgb, w):
     w = _d(w).reshape(-1, 3)
     out = np.zeros((len(w), 3))
     L.orc_env_lookup(e.shape[0], e.shape[1], _p(e), len(w), _p(w), _p(out))
+    return out
+
+
+def trace_extent(s, origins, dirs, t_min=0.0, t_max=np.inf, t_cut=T_CUT, alpha_min=ALPHA_MIN):
+    """Per ray: the depth where compositing ended (the last composited hit's
+    depth if the ray was cut off, else t_max) and the composited hit count,
+    the segment the work counter prices."""
+    L = lib()
+    L.orc_trace_extent.restype = C.c_int
+    L.orc_trace_extent.argtypes = [I64, P, P, P, P, F, I64, P, P, F, F, F, P, P]
+    means, scales, quats, opacity, _ = _scene(s)
+    o = _c(origins); d = _c(dirs)
+    R = o.shape[0]
+    t_term = np.zeros(R, np.float32); nhit = np.zeros(R, np.int64)
+    rc = L.orc_trace_extent(s.n, _p(means), _p(scales), _p(quats), _p(opacity), alpha_min, R, _p(o), _p(d),
+                            float(t_min), float(t_max), t_cut, _p(t_term), _p(nhit))
+    assert rc == 0
+    return t_term, nhit
+
+
+def split_sum(env_rgb, Ed, Es, lut, albedo, rough, metal, nsum, w):
+    """SplitSum of Eq. relight_splitsum for query results (albedo [m,3],
+    rough [m], metal [m], summed normal nsum [m,3]) of secondary rays w [m,3],
+    with the given tables Ed [16,32,3], Es [5,16,32,3], lut [32,32,2] and the
+    environment env_rgb [H,W,3] (level 0 of the specular lookup)."""
+    L = lib()
+    L.orc_split_sum.restype = None
+    L.orc_split_sum.argtypes = [C.c_int, C.c_int, P, P, P, P, I64, P, P, P, P, P, P]
+    e = _c(env_rgb)
+    albedo = _d(albedo).reshape(-1, 3)
+    m = len(albedo)
+    out = np.zeros((m, 3))
+    L.orc_split_sum(e.shape[0], e.shape[1], _p(e), _p(_d(Ed)), _p(_d(Es)), _p(_d(lut)), m, _p(albedo),
+                    _p(_d(rough).reshape(m)), _p(_d(metal).reshape(m)), _p(_d(nsum).reshape(m, 3)),
+                    _p(_d(w).reshape(m, 3)), _p(out))
     return out

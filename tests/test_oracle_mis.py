@@ -219,3 +219,38 @@ def test_occluder_blocks_environment():
     assert tr.sum() > 0
     np.testing.assert_allclose(d["Li"][tr], np.broadcast_to(np.float32([0.25, 0.5, 0.75]), d["Li"][tr].shape),
                                rtol=1e-6)
+
+
+def test_brdf_fresnel_and_lobe_closed_forms():
+    """Two geometries where D, G and F reduce to hand-derived constants (Sec.
+    3.1 Eq. brdf_specular with the readings alpha_g = r^2, GGX D, separable
+    Smith G1(x) = 2x / (x + sqrt(a2 + (1 - a2) x^2)), Schlick F on wi.h).
+    Roughness 0.5, so a2 = alpha_g^2 = 1/16 and G1(1/2) = 8 / (4 + sqrt 19),
+    G1(1) = 1.
+
+    A: wo, wi at 60 degrees either side of n: h = n, n.h = 1, wi.h = 1/2,
+       D = 1 / (pi a2) = 16 / pi, G = G1(1/2)^2, F = F0 + (1 - F0) / 32;
+       m = 1 (F0 = a, no diffuse): f = D F G / (4 * 1/2 * 1/2) = D F G.
+    B: wo = n, wi at 60 degrees: h at 30 degrees, n.h = wi.h = sqrt(3)/2,
+       D = (1/16) / (pi (1 - 45/64)^2) = 256 / (361 pi), G = G1(1/2),
+       F = F0 + (1 - F0)(1 - sqrt(3)/2)^5; m = 0.4 (F0 = 0.024 + 0.4 a):
+       f = 0.6 a / pi + D F G / (4 * 1/2 * 1).
+    A wrong Fresnel exponent, F taken on n.wi or n.h, or a lost factor fails."""
+    n = np.array([0.0, 0.0, 1.0])
+    s3 = math.sqrt(3.0)
+    a = np.array([0.9, 0.5, 0.2])
+    g1h = 8.0 / (4.0 + math.sqrt(19.0))
+    wo = np.array([s3 / 2, 0.0, 0.5]); wi = np.array([-s3 / 2, 0.0, 0.5])
+    fA = O.brdf(n, wo, a, 0.5, 1.0, wi[None])[0]
+    wantA = (16.0 / math.pi) * g1h ** 2 * (a + (1.0 - a) / 32.0)
+    np.testing.assert_allclose(fA, wantA, rtol=1e-12)
+    wi = np.array([s3 / 2, 0.0, 0.5])
+    fB = O.brdf(n, n, a, 0.5, 0.4, wi[None])[0]
+    F0 = 0.024 + 0.4 * a
+    FB = F0 + (1.0 - F0) * (1.0 - s3 / 2) ** 5
+    wantB = 0.6 * a / math.pi + (256.0 / (361.0 * math.pi)) * g1h * FB / 2.0
+    np.testing.assert_allclose(fB, wantB, rtol=1e-12)
+    # the same geometries rotated: the BRDF depends on angles only
+    R = np.linalg.qr(np.random.default_rng(9).standard_normal((3, 3)))[0]
+    fR = O.brdf(R @ n, R @ n, a, 0.5, 0.4, (R @ wi)[None])[0]
+    np.testing.assert_allclose(fR, wantB, rtol=1e-10)

@@ -158,3 +158,124 @@ def test_relight_behind_an_opaque_wall():
         hi = L0 * (F0 * lut[..., 0] + lut[..., 1]).max()
         assert (Li >= lo - 1e-6).all() and (Li <= hi + 1e-6).all()
         assert (Li <= L0 + 1e-9).all()
+
+
+# --------------------------------------------------------------------------
+# SplitSum's table lookups, on tables of known content.  A direction table
+# filled with a function that is bilinear in its texel coordinates
+# (x = phi / 2pi * 32 - 1/2, v = theta / pi * 16 - 1/2, integers at texel
+# centres) is reproduced exactly by bilinear interpolation between centres,
+# at any direction away from the azimuth seam and the poles; likewise a DFG
+# table bilinear in (mu * 32 - 1/2, r * 32 - 1/2).  So the relit radiance at
+# any query has a closed form:
+#   (1 - m) a Ed(n) + [(1 - t) Es_l(R) + t Es_{l+1}(R)] (F0 A(mu, r) + B(mu, r))
+# with n the renormalized query normal, v = -w, R = 2 (n.v) n - v, mu = n.v,
+# r * 5 = l + t, F0 = 0.04 (1 - m) + m a (reading of Eq. relight_splitsum);
+# level 0 is the environment at R's nearest texel.
+# --------------------------------------------------------------------------
+
+def _tex_coords(w):
+    th = np.arccos(np.clip(w[:, 1], -1, 1))
+    ph = np.mod(np.arctan2(w[:, 2], w[:, 0]), 2 * np.pi)
+    return ph / (2 * np.pi) * O.PF_W - 0.5, th / np.pi * O.PF_H - 0.5
+
+
+def _bilinear_table(c):
+    """[16, 32, 3] table with T[i, j] = c0 + c1 j + c2 i + c3 i j per channel."""
+    i, j = np.meshgrid(np.arange(O.PF_H), np.arange(O.PF_W), indexing="ij")
+    return np.stack([c[k, 0] + c[k, 1] * j + c[k, 2] * i + c[k, 3] * i * j for k in range(3)], -1)
+
+
+def _eval_bilinear(c, x, v):
+    return np.stack([c[k, 0] + c[k, 1] * x + c[k, 2] * v + c[k, 3] * x * v for k in range(3)], -1)
+
+
+def _tables(g):
+    cd = g.uniform(0.2, 1.0, (3, 4)) * np.float64([1, 0.05, 0.07, 0.01])
+    cs = [g.uniform(0.2, 1.0, (3, 4)) * np.float64([1, 0.05, 0.07, 0.01]) + 3.0 * lv for lv in range(5)]
+    Ed = _bilinear_table(cd)
+    Es = np.stack([_bilinear_table(c) for c in cs])
+    ca = np.float64([0.5, 0.011, -0.007, 0.0003])
+    cb = np.float64([0.1, -0.002, 0.004, 0.0001])
+    i, j = np.meshgrid(np.arange(O.LUT_N), np.arange(O.LUT_N), indexing="ij")
+    lut = np.stack([ca[0] + ca[1] * i + ca[2] * j + ca[3] * i * j, cb[0] + cb[1] * i + cb[2] * j + cb[3] * i * j], -1)
+    return cd, cs, Ed, Es, ca, cb, lut
+
+
+def _interior_dirs(g, m):
+    """Unit directions with theta in [0.2, pi - 0.2] and phi in [0.4, 2pi - 0.4]."""
+    th = g.uniform(0.2, np.pi - 0.2, m)
+    ph = g.uniform(0.4, 2 * np.pi - 0.4, m)
+    return np.stack([np.sin(th) * np.cos(ph), np.cos(th), np.sin(th) * np.sin(ph)], -1)
+
+
+def _queries(g, m):
+    """Normals n and mirror directions R, both interior, with n.R in [0.1, 0.95];
+    the ray direction is w = -v with v = 2 (n.R) n - R (so R mirrors v)."""
+    ns, Rs = [], []
+    while len(ns) < m:
+        n = _interior_dirs(g, 1)[0]
+        R = _interior_dirs(g, 1)[0]
+        c = n @ R
+        if 0.1 < c < 0.95:
+            ns.append(n); Rs.append(R)
+    n, R = np.array(ns), np.array(Rs)
+    v = 2 * (n * R).sum(1, keepdims=True) * n - R
+    return n, R, -v
+
+
+@pytest.mark.parametrize("metal", [0.0, 1.0, 0.35])
+def test_split_sum_lookups_closed_form(metal):
+    """Diffuse (m = 0, a > 0), specular (m = 1) and mixed queries at rough-
+    ness between the prefiltered levels: E_d is read at n (not R), E_s at R
+    between the two levels around r, and the DFG terms at (n.v, r)."""
+    g = np.random.default_rng(int(metal * 100) + 1)
+    cd, cs, Ed, Es, ca, cb, lut = _tables(g)
+    m = 64
+    n, R, w = _queries(g, m)
+    a = g.uniform(0.1, 1.0, (m, 3))
+    r = g.uniform(0.21, 0.98, m)  # DFG cells span r in [1/64, 63/64]
+    nsum = n * g.uniform(0.3, 2.0, (m, 1))  # the query's summed normal, renormalized inside
+    env = np.ones((8, 16, 3), np.float32)
+    got = O.split_sum(env, Ed, Es, lut, a, r, np.full(m, metal), nsum, w)
+    xn, vn = _tex_coords(n)
+    xr, vr = _tex_coords(R)
+    Ld = _eval_bilinear(cd, xn, vn)
+    lv = r * 5
+    l0 = np.floor(lv).astype(int)
+    t = (lv - l0)[:, None]
+    Ls = np.stack([(1 - t[k]) * _eval_bilinear(cs[l0[k] - 1], xr[k:k + 1], vr[k:k + 1])[0] +
+                   t[k] * _eval_bilinear(cs[l0[k]], xr[k:k + 1], vr[k:k + 1])[0] for k in range(m)])
+    mu = (n * -w).sum(1)
+    xi, yj = mu * O.LUT_N - 0.5, r * O.LUT_N - 0.5
+    A = ca[0] + ca[1] * xi + ca[2] * yj + ca[3] * xi * yj
+    B = cb[0] + cb[1] * xi + cb[2] * yj + cb[3] * xi * yj
+    F0 = 0.04 * (1 - metal) + metal * a
+    want = (1 - metal) * a * Ld + Ls * (F0 * A[:, None] + B[:, None])
+    np.testing.assert_allclose(got, want, rtol=1e-10)
+
+
+def test_split_sum_level_zero_reads_the_environment():
+    """Below the first prefiltered roughness the specular lookup blends the
+    environment itself at R's nearest texel with the first table."""
+    g = np.random.default_rng(21)
+    cd, cs, Ed, Es, ca, cb, lut = _tables(g)
+    H, Wd = 8, 16
+    env = g.uniform(0.5, 4.0, (H, Wd, 3)).astype(np.float32)
+    m = 48
+    n, R, w = _queries(g, m)
+    a = g.uniform(0.1, 1.0, (m, 3))
+    r = g.uniform(0.05, 0.19, m)
+    got = O.split_sum(env, Ed, Es, lut, a, r, np.ones(m), n, w)
+    th = np.arccos(np.clip(R[:, 1], -1, 1))
+    ph = np.mod(np.arctan2(R[:, 2], R[:, 0]), 2 * np.pi)
+    texel = env[np.minimum((th / np.pi * H).astype(int), H - 1), np.minimum((ph / (2 * np.pi) * Wd).astype(int), Wd - 1)]
+    t = (r * 5)[:, None]
+    xr, vr = _tex_coords(R)
+    Ls = (1 - t) * texel + t * _eval_bilinear(cs[0], xr, vr)
+    mu = (n * -w).sum(1)
+    xi, yj = mu * O.LUT_N - 0.5, r * O.LUT_N - 0.5
+    A = ca[0] + ca[1] * xi + ca[2] * yj + ca[3] * xi * yj
+    B = cb[0] + cb[1] * xi + cb[2] * yj + cb[3] * xi * yj
+    want = Ls * (a * A[:, None] + B[:, None])
+    np.testing.assert_allclose(got, want, rtol=1e-10)

@@ -196,3 +196,18 @@ def test_work_counts_bound_hits():
     assert np.all(nc >= nh)
     assert np.all((nn >= 1) | (nc == 0))
     assert nh.sum() > 0
+
+
+def test_negative_per_ray_t_min_is_zero():
+    """A ray starts at its origin: a negative (or NaN) per-ray t_min admits
+    no hit behind it and gives exactly the t_min = 0 result."""
+    s = W.scene0(n=1500, seed=8)
+    r = W.rays0(res=10, per=4, seed=8)
+    base = O.trace(s, r.origins, r.dirs, t_min=0.0, cap=32)
+    tm = np.random.default_rng(0).uniform(-2.0, -1e-3, r.n).astype(np.float32)
+    tm[::7] = np.nan
+    got = O.trace(s, r.origins, r.dirs, t_min=tm, t_max=np.full(r.n, np.inf, np.float32), cap=32)
+    for k in ("C", "T", "nhit", "ids", "tau"):
+        np.testing.assert_array_equal(got[k], base[k])
+    # and the same rays with the origins moved back: now hits behind count
+    assert (O.trace(s, r.origins - 0.5 * r.dirs, r.dirs, t_min=0.0)["nhit"] >= base["nhit"]).all()
