@@ -132,7 +132,11 @@ int grt_scene_view_get(const grt_scene *scene, grt_scene_view *out);
 /* ------------------------------------------------------------------ trace */
 
 /* Rays (Sec. 3.2, r_o + tau r_d).  origins/dirs [n,3]; dirs unit length.
- * t_min/t_max per ray [n] or NULL to use the scalars; 0 <= t_min < t_max. */
+ * t_min/t_max per ray [n] or NULL to use the scalars; 0 <= t_min < t_max.
+ * The scalar t_min_all must be >= 0 (GRT_ERR_INVALID otherwise); a negative
+ * or NaN per-ray t_min is read as 0 (a ray starts at its origin, and depth
+ * keys order depths by their bit patterns, which is monotone for tau >= 0
+ * only), so hits behind the origin are never admitted. */
 typedef struct {
     int64_t n;
     const float *origins;

@@ -48,7 +48,7 @@ struct TraceJob {
     {
         const float3 o = make_float3(a.o[3 * r], a.o[3 * r + 1], a.o[3 * r + 2]);
         const float3 d = make_float3(a.d[3 * r], a.d[3 * r + 1], a.d[3 * r + 2]);
-        const float tmin = a.tmin_a ? a.tmin_a[r] : a.tmin;
+        const float tmin = a.tmin_a ? fmaxf(a.tmin_a[r], 0.0f) : a.tmin;  // negative: 0
         const float tmax = a.tmax_a ? a.tmax_a[r] : a.tmax;
         v.reset(o, d);
         if (a.dump_id) { v.did = a.dump_id + r * a.cap; v.dtau = a.dump_tau + r * a.cap; v.cap = a.cap; }
@@ -101,7 +101,7 @@ struct TraceBwdJob {
         if (gC.x == 0.0f && gC.y == 0.0f && gC.z == 0.0f && gT == 0.0f) return false;
         const float3 o = make_float3(a.f.o[3 * r], a.f.o[3 * r + 1], a.f.o[3 * r + 2]);
         const float3 d = make_float3(a.f.d[3 * r], a.f.d[3 * r + 1], a.f.d[3 * r + 2]);
-        const float tmin = a.f.tmin_a ? a.f.tmin_a[r] : a.f.tmin;
+        const float tmin = a.f.tmin_a ? fmaxf(a.f.tmin_a[r], 0.0f) : a.f.tmin;  // negative: 0
         const float tmax = a.f.tmax_a ? a.f.tmax_a[r] : a.f.tmax;
         const float3 C = make_float3(a.fwd_rgb[3 * r], a.fwd_rgb[3 * r + 1], a.fwd_rgb[3 * r + 2]);
         v.reset(o, d, gC, gT, C, a.fwd_T[r]);
@@ -139,7 +139,7 @@ struct TraceAttrJob {
     {
         const float3 o = make_float3(a.f.o[3 * r], a.f.o[3 * r + 1], a.f.o[3 * r + 2]);
         const float3 d = make_float3(a.f.d[3 * r], a.f.d[3 * r + 1], a.f.d[3 * r + 2]);
-        const float tmin = a.f.tmin_a ? a.f.tmin_a[r] : a.f.tmin;
+        const float tmin = a.f.tmin_a ? fmaxf(a.f.tmin_a[r], 0.0f) : a.f.tmin;  // negative: 0
         const float tmax = a.f.tmax_a ? a.f.tmax_a[r] : a.f.tmax;
         v.reset(o, d);
         w.start(S, o, d, tmin, tmax);
@@ -182,7 +182,7 @@ struct TraceGBufJob {
     {
         const float3 o = make_float3(a.f.o[3 * r], a.f.o[3 * r + 1], a.f.o[3 * r + 2]);
         const float3 d = make_float3(a.f.d[3 * r], a.f.d[3 * r + 1], a.f.d[3 * r + 2]);
-        const float tmin = a.f.tmin_a ? a.f.tmin_a[r] : a.f.tmin;
+        const float tmin = a.f.tmin_a ? fmaxf(a.f.tmin_a[r], 0.0f) : a.f.tmin;  // negative: 0
         const float tmax = a.f.tmax_a ? a.f.tmax_a[r] : a.f.tmax;
         v.reset(o, d);
         w.start(S, o, d, tmin, tmax);
@@ -363,7 +363,7 @@ struct TraceGBufBwdJob {
         // d(N/|N|)/dN applied to g_n, with |N| = W |N / W|
         const float ndg = dot3(nh, gn), iN = iW / nl;
         v.kN = make_float3((gn.x - nh.x * ndg) * iN, (gn.y - nh.y * ndg) * iN, (gn.z - nh.z * ndg) * iN);
-        const float tmin = a.f.tmin_a ? a.f.tmin_a[r] : a.f.tmin;
+        const float tmin = a.f.tmin_a ? fmaxf(a.f.tmin_a[r], 0.0f) : a.f.tmin;  // negative: 0
         const float tmax = a.f.tmax_a ? a.f.tmax_a[r] : a.f.tmax;
         v.reset(o, d);
         w.start(S, o, d, tmin, stop_bound(a.f.stop_depth, r, tmax));

@@ -46,7 +46,8 @@ def compare(gpu, ref, edge):
     np.testing.assert_array_equal(gpu["valid"][ok], ref["valid"][ok])
     for k in MAPS:
         np.testing.assert_allclose(gpu[k][ok], ref[k][ok], rtol=RTOL, atol=ATOL, err_msg=k)
-    assert edge.mean() < 0.002
+    print(f"  excused {edge.mean():.2e}", flush=True)
+    assert edge.mean() <= 0.001
 
 
 @pytest.mark.parametrize("H,Wd,thr", [(48, 40, 0.5), (33, 17, 0.2), (1, 7, 0.9)])
@@ -88,4 +89,4 @@ def test_traced_gbuffer_feeds_the_render(grt_ctx):
                                                                     "valid")))
     want = O.render_mis(s, gb, env, (4, 2, 2), seed=4)
     assert gb.valid.mean() > 0.1
-    np.testing.assert_allclose(img, want, rtol=1e-3, atol=1e-4)
+    np.testing.assert_allclose(img, want, rtol=1e-4, atol=1e-5)

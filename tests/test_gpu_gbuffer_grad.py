@@ -29,24 +29,18 @@ def grt_ctx():
     return grt, grt.Context(0)
 
 
-def close(got, want, name, rel=1e-3, floor=1e-2):
-    got = got.reshape(want.shape).astype(np.float64)
-    scale = np.abs(want).max()
-    if scale == 0:
-        assert np.abs(got).max() == 0, name
-        return
-    tol = rel * np.maximum(np.abs(want), floor * scale)
-    bad = np.abs(got - want) > tol
-    assert bad.mean() < 1e-3, (name, bad.sum(), np.abs(got - want).max(), scale)
-    l2 = np.linalg.norm(got - want) / np.linalg.norm(want)
-    assert l2 < rel, (name, l2)
+def close(got, want, name, rel=1e-3, floor=1e-2, want_abs=None):
+    from gpu_util import grad_close
+    grad_close(got, want, name, want_abs, rel=rel, floor=floor)
 
 
-def check(gg, ga, ref13, refa, **kw):
+def check(gg, ga, ref13, refa, ref13_abs=None, refa_abs=None, **kw):
     for name, (a, b) in BLOCKS.items():
-        close(gg[name].cpu().numpy(), ref13[:, a:b], name, **kw)
+        close(gg[name].cpu().numpy(), ref13[:, a:b], name,
+              want_abs=None if ref13_abs is None else ref13_abs[:, a:b], **kw)
     for name, (a, b) in ABLOCKS.items():
-        close(ga[name].cpu().numpy(), refa[:, a:b], name, **kw)
+        close(ga[name].cpu().numpy(), refa[:, a:b], name,
+              want_abs=None if refa_abs is None else refa_abs[:, a:b], **kw)
 
 
 def camera(H, Wd, seed=0):
@@ -90,10 +84,10 @@ def test_gbuffer_backward_parity(grt_ctx, H, Wd, thr):
     up, keep = upstream(s, at, o, d, thr, seed=H + 1)
     gg, ga, fwd, _ = run_gpu(grt, ctx, s, at, o, d, H, Wd, up, thr)
     assert fwd["valid"].float().mean().item() > 0.1
-    ref13, refa = O.trace_gbuffer_backward(s, at, o, d, {k: v.astype(np.float64) for k, v in up.items()},
-                                           min_opacity=thr)
+    ref13, refa, ref13_abs, refa_abs = O.trace_gbuffer_backward(s, at, o, d, {k: v.astype(np.float64) for k, v in up.items()},
+                                           min_opacity=thr, with_abs=True)
     assert np.count_nonzero(ref13[:, 0]) >= 100
-    check(gg, ga, ref13, refa)
+    check(gg, ga, ref13, refa, ref13_abs, refa_abs)
 
 
 @pytest.mark.parametrize("keys", [("n",), ("depth", "x"), ("albedo", "rough", "metal"), ("rgb",)])
@@ -105,9 +99,9 @@ def test_gbuffer_backward_each_map(grt_ctx, keys):
     o, d = camera(24, 24, seed=5)
     up, _ = upstream(s, at, o, d, 0.5, seed=11, keys=keys)
     gg, ga, _, _ = run_gpu(grt, ctx, s, at, o, d, 24, 24, up, 0.5)
-    ref13, refa = O.trace_gbuffer_backward(s, at, o, d, {k: v.astype(np.float64) for k, v in up.items()},
-                                           min_opacity=0.5)
-    check(gg, ga, ref13, refa)
+    ref13, refa, ref13_abs, refa_abs = O.trace_gbuffer_backward(s, at, o, d, {k: v.astype(np.float64) for k, v in up.items()},
+                                           min_opacity=0.5, with_abs=True)
+    check(gg, ga, ref13, refa, ref13_abs, refa_abs)
 
 
 def test_gbuffer_backward_k_and_nothing_upstream(grt_ctx):
@@ -184,9 +178,9 @@ def test_gbuffer_backward_room_1024_sampled(grt_ctx):
         up[k] = t(full)
     gg, ga = grt.trace_gbuffer_backward(scene, *mats, t(o), t(d), fwd, up)
     torch.cuda.synchronize()
-    ref13, refa = O.trace_gbuffer_backward(s, at, o[pix], d[pix], {k: v.astype(np.float64) for k, v in up_s.items()})
+    ref13, refa, ref13_abs, refa_abs = O.trace_gbuffer_backward(s, at, o[pix], d[pix], {k: v.astype(np.float64) for k, v in up_s.items()}, with_abs=True)
     assert np.count_nonzero(ref13[:, 0]) >= 64
-    check(gg, ga, ref13, refa)
+    check(gg, ga, ref13, refa, ref13_abs, refa_abs)
 
 
 def test_gbuffer_backward_edge_cases(grt_ctx):
@@ -218,10 +212,10 @@ def test_gbuffer_backward_edge_cases(grt_ctx):
     up1, keep = upstream(s, at, o1, d1, 0.5, seed=3)
     assert keep.all()
     gg1, ga1, fw1, _ = run_gpu(grt, ctx, s, at, o1, d1, 1, 1, up1, 0.5, scene=scene)
-    ref13, refa = O.trace_gbuffer_backward(s, at, o1, d1, {k: v.astype(np.float64) for k, v in up1.items()},
-                                           min_opacity=0.5)
+    ref13, refa, ref13_abs, refa_abs = O.trace_gbuffer_backward(s, at, o1, d1, {k: v.astype(np.float64) for k, v in up1.items()},
+                                           min_opacity=0.5, with_abs=True)
     assert np.count_nonzero(ref13[:, 0]) >= 10
-    check(gg1, ga1, ref13, refa)
+    check(gg1, ga1, ref13, refa, ref13_abs, refa_abs)
     bad = {k: v for k, v in fw1.items() if k != "weight"}
     with pytest.raises(grt.GrtError):
         grt.trace_gbuffer_backward(scene, *mats, t(o1), t(d1), bad, {k: t(v) for k, v in up1.items()})

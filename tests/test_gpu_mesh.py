@@ -117,7 +117,8 @@ def test_relight_through_the_mesh(grt_ctx):
     edge = (mg[..., 0] < 1e-5) | (mg[..., 1] < 1e-5) | (mg[..., 4] < 1e-9) | ~same_dir
     ok = traced & ~edge & (d[..., 3] > 0)
     np.testing.assert_allclose(d[..., 7:10][ok], ref["Li"][ok], rtol=1e-4, atol=1e-5)
-    assert edge[traced].mean() < 0.01
+    print(f"  excused {edge[traced].mean():.2e} of traced samples", flush=True)
+    assert edge[traced].mean() <= 0.001
     bad_px = edge.any(axis=1)
-    np.testing.assert_allclose(gpu["rgb"][~bad_px], ref["rgb"][~bad_px], rtol=1e-3, atol=1e-5)
+    np.testing.assert_allclose(gpu["rgb"][~bad_px], ref["rgb"][~bad_px], rtol=1e-4, atol=1e-5)
     assert ok.sum() > 2000

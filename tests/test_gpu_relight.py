@@ -64,9 +64,10 @@ def compare(gpu, ref, max_excused):
     ok = traced & ~edge & (d[..., 3] > 0)
     np.testing.assert_allclose(d[..., 4:7][ok], ref["wt"][ok], rtol=1e-5, atol=1e-7)
     np.testing.assert_allclose(d[..., 7:10][ok], ref["Li"][ok], rtol=RTOL, atol=ATOL)
+    print(f"  excused {edge[traced].mean():.2e} of traced samples", flush=True)
     assert edge[traced].mean() <= max_excused
     bad_px = edge.any(axis=1)
-    np.testing.assert_allclose(gpu["rgb"][~bad_px], ref["rgb"][~bad_px], rtol=1e-3, atol=1e-5)
+    np.testing.assert_allclose(gpu["rgb"][~bad_px], ref["rgb"][~bad_px], rtol=1e-4, atol=1e-5)
     assert bad_px.mean() < 0.05
     return ok
 
@@ -80,7 +81,7 @@ def test_relight_per_sample_and_pixel_parity(grt_ctx):
     gb = W.gbuffer1(40, 37, seed=0)
     env = W.envmap(64, 128, seed=5)
     gpu, ref = relight_both(grt, ctx, s, at, gb, env, (16, 8, 8), seed=3)
-    ok = compare(gpu, ref, max_excused=0.002)
+    ok = compare(gpu, ref, max_excused=0.001)
     # the samples that hit geometry exercise the split-sum term
     assert ok.sum() > 1000
 
@@ -93,7 +94,7 @@ def test_relight_allocations_and_k(grt_ctx, split, k):
     gb = W.gbuffer1(24, 21, seed=2)
     env = W.envmap(32, 64, seed=6)
     gpu, ref = relight_both(grt, ctx, s, at, gb, env, split, seed=11, k=k)
-    compare(gpu, ref, max_excused=0.01)
+    compare(gpu, ref, max_excused=0.001)
 
 
 def test_relight_is_k_invariant_and_empty_scene(grt_ctx):
