@@ -689,10 +689,14 @@ constexpr double kSmallShare = 0.05;
 // Plan an epoch into slot E and launch it; false if no ray is left to trace.
 bool launch(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other, int64_t budget, hipError_t &err)
 {
+    // A request whose rays are in the other epoch while that one may still be
+    // stopped waits for it: a stop hands unclaimed rays back to the request,
+    // which must then not be finishing in this epoch already.
+    const uint64_t held = other.inflight && other.preemptible && !other.members.empty() ? other.members[0] : 0;
     std::vector<ServerJob *> run;
     for (uint64_t id : s->resident) {
         ServerJob &j = s->jobs[id];
-        if (j.state == kRunning && !j.cancel && j.nleft > 0) run.push_back(&j);
+        if (j.state == kRunning && !j.cancel && j.nleft > 0 && j.id != held) run.push_back(&j);
     }
     if (run.empty()) return false;
     // earliest deadline first (protected requests before all others); the

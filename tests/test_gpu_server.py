@@ -166,6 +166,34 @@ def test_urgent_requests_stop_a_large_epoch(setup):
         np.testing.assert_array_equal(r.out.numpy(), direct(grt, ctx, scene, *x))
 
 
+def test_stopped_epochs_with_small_epoch_budget(setup):
+    """Preemption with epochs smaller than the large request (so its rays
+    span several epochs and two can be in flight): a request is never
+    finished by one epoch while another epoch that may still be stopped
+    holds some of its rays, so every image equals the direct render."""
+    import time
+    grt, ctx, scene = setup
+    big_in = (W.gbuffer1(512, 512, seed=3), W.envmap(32, 64), (32, 16, 16), 5, 5)
+    small_in = [(W.gbuffer1(32, 32, seed=3, cam_stream=30 + i), W.envmap(32, 64, seed=9 + i), (8, 4, 4), 16 + i,
+                 16 + i) for i in range(4)]
+    srv = grt.Server(ctx, scene, mem_budget=1 << 32, max_jobs=8, preempt_share=0.5, epoch_rays=1 << 22)
+    big = grt.Request(*big_in)
+    a = srv.submit(big)
+    smalls = [grt.Request(*x) for x in small_in]
+    ids = []
+    for r in smalls:
+        time.sleep(0.01)
+        ids.append(srv.submit(r))
+    for b in ids + [a]:
+        assert srv.wait(b) == 0
+    st = srv.stats()
+    srv.close()
+    assert st["epochs"] >= 4
+    np.testing.assert_array_equal(big.out.numpy(), direct(grt, ctx, scene, *big_in))
+    for r, x in zip(smalls, small_in):
+        np.testing.assert_array_equal(r.out.numpy(), direct(grt, ctx, scene, *x))
+
+
 CAMERAS = [((3.5, 0.4, 0.2), (0.0, 0.0, 0.0), 40.0, (0.0, 1.0, 0.0)),
            ((0.3, 1.8, -3.2), (0.1, -0.2, 0.4), 55.0, (0.0, 1.0, 0.0)),
            ((2.0, 2.0, 2.0), (0.0, 0.0, 0.0), 25.0, (0.3, 1.0, -0.2))]
