@@ -438,6 +438,24 @@ size_t grt_render_workspace_bytes(int64_t npix, int spp);
 int grt_render_mis(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *opts,
                    float *out_rgb, void *saved, void *workspace, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * render as grt_render_mis, with its scratch (ray-fetch counters, ray
+ * records, contributions, sort buffers: grt_render_workspace_bytes) taken
+ * from a fixed device array of GRT_NOALLOC_SCRATCH_BYTES that the library
+ * holds per device until the process ends, instead of a workspace argument.
+ * It calls no hipMalloc, hipFree or allocating routine.  The caller still
+ * passes out_rgb [npix,3] and `saved` (or NULL) as for grt_render_mis; the
+ * result is the same bit for bit.  GRT_ERR_INVALID (with the sizes in
+ * grt_last_error) when grt_render_workspace_bytes(npix, spp) exceeds the
+ * array, i.e. above about 1.6M samples (H * W * spp).  Every call on one GPU
+ * shares that GPU's array: calls that overlap in time on one GPU (other
+ * streams, other threads) race and must be serialized by the caller.  The
+ * counters that must start at zero are cleared by the call itself. */
+#define GRT_NOALLOC_SCRATCH_BYTES ((size_t)128 << 20)
+int grt_render_mis_noalloc(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g,
+                           const grt_mis_opts *opts, float *out_rgb, void *saved, void *stream);
+
 /* Backward of grt_render_mis by re-traversal: regenerates every sample from
  * its counter, retraces, and accumulates d/d(surfels) of
  * sum_p grad_rgb[p] . c_pbr(p) into `grads`.  As for grt_trace_backward,

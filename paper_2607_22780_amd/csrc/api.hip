@@ -4,9 +4,25 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 
 #include "grt_internal.h"
+
+// Scratch of grt_render_mis_noalloc (ray-fetch counters, per-sample ray
+// records, contributions and sort buffers): a file-scope device array, so
+// that call allocates nothing.  Every device the library runs on holds its
+// own copy until the process ends.  Host code never uses this name as a
+// device address: grt_ctx_create looks each device's copy up once with
+// hipGetSymbolAddress and keeps that address in the context.
+static __device__ __align__(256) unsigned char scratch[GRT_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+// device address of `scratch` per device, looked up once per device
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_dev[kMaxDevices] = {};
+}  // namespace
 
 struct grt_scene {
     grt_ctx *ctx;
@@ -170,10 +186,27 @@ int grt_ctx_create(int device, grt_ctx **out)
     hipDeviceProp_t prop;
     e = hipGetDeviceProperties(&prop, device);
     if (e != hipSuccess) return hip_fail(e, "hipGetDeviceProperties");
+    void *scr = nullptr;
+    if (device < kMaxDevices) {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_dev[device]) {
+            int prev = 0;
+            if ((e = hipGetDevice(&prev)) != hipSuccess) return hip_fail(e, "hipGetDevice");
+            if ((e = hipSetDevice(device)) != hipSuccess) return hip_fail(e, "hipSetDevice");
+            void *p = nullptr;
+            e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+            const hipError_t e2 = hipSetDevice(prev);
+            if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+            if (e2 != hipSuccess) return hip_fail(e2, "hipSetDevice");
+            g_scratch_dev[device] = p;
+        }
+        scr = g_scratch_dev[device];
+    }
     grt_ctx *c = new (std::nothrow) grt_ctx;
     if (!c) return fail(GRT_ERR_OOM, "host allocation failed");
     c->device = device;
     c->num_cu = prop.multiProcessorCount;
+    c->scratch = scr;
     *out = c;
     return GRT_OK;
 }
@@ -771,6 +804,27 @@ int grt_render_mis(const grt_scene *scene, const grt_env *env, const grt_gbuffer
     hipError_t e = grt::launch_render(a, w, opts->k, scene->ctx->num_cu, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "render launch");
     return GRT_OK;
+}
+
+int grt_render_mis_noalloc(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *opts,
+                           float *out_rgb, void *saved, void *stream)
+{
+    if (!scene) return fail(GRT_ERR_INVALID, "scene is NULL");
+    if (!g || !opts) return fail(GRT_ERR_INVALID, "gbuffer/opts is NULL");
+    if (g->H < 0 || g->W < 0) return fail(GRT_ERR_INVALID, "G-buffer size %d x %d", g->H, g->W);
+    const int spp = opts->n_cos + opts->n_ggx + opts->n_env;
+    if (opts->n_cos < 0 || opts->n_ggx < 0 || opts->n_env < 0 || spp <= 0)
+        return fail(GRT_ERR_INVALID, "sample allocation %d/%d/%d", opts->n_cos, opts->n_ggx, opts->n_env);
+    const size_t need = grt_render_workspace_bytes((int64_t)g->H * g->W, spp);
+    if (need > GRT_NOALLOC_SCRATCH_BYTES)
+        return fail(GRT_ERR_INVALID,
+                    "grt_render_mis_noalloc: %d x %d pixels x %d spp need %zu bytes of scratch, more than its "
+                    "fixed %zu (about %zu samples); use grt_render_mis with a workspace",
+                    g->H, g->W, spp, need, (size_t)GRT_NOALLOC_SCRATCH_BYTES,
+                    (size_t)GRT_NOALLOC_SCRATCH_BYTES / 81u);
+    if (!scene->ctx->scratch) return fail(GRT_ERR_DEVICE, "no scratch on device %d", scene->ctx->device);
+    return grt_render_mis(scene, env, g, opts, out_rgb, saved, scene->ctx->scratch, GRT_NOALLOC_SCRATCH_BYTES,
+                          stream);
 }
 
 int grt_render_mis_backward(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *opts,

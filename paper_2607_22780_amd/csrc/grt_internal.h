@@ -12,6 +12,7 @@
 struct grt_ctx {
     int device;
     int num_cu;
+    void *scratch;  // this device's copy of grt_render_mis_noalloc's scratch (device address)
 };
 
 

@@ -173,6 +173,7 @@ SIGNATURES = {
     "grt_render_saved_bytes": (C.c_size_t, [C.c_int64, C.c_int]),
     "grt_render_workspace_bytes": (C.c_size_t, [C.c_int64, C.c_int]),
     "grt_render_mis": (C.c_int, [VP, VP, P(grt_gbuffer), P(grt_mis_opts), VP, VP, VP, C.c_size_t, VP]),
+    "grt_render_mis_noalloc": (C.c_int, [VP, VP, P(grt_gbuffer), P(grt_mis_opts), VP, VP, VP]),
     "grt_render_mis_backward": (C.c_int, [VP, VP, P(grt_gbuffer), P(grt_mis_opts), VP, VP, P(grt_surfel_grads),
                                           VP, C.c_size_t, VP]),
     "grt_render_hit_list_bytes": (C.c_size_t, [C.c_int64, C.c_int, C.c_int]),
@@ -373,6 +374,11 @@ def grt_render_workspace_bytes(npix: int, spp: int) -> int:
 def grt_render_mis(scene, env, gbuf: grt_gbuffer, opts: grt_mis_opts, out_rgb, saved, workspace, stream=None):
     _check(load_library().grt_render_mis(scene, env, C.byref(gbuf), C.byref(opts), _ptr(out_rgb), _ptr(saved),
                                          _ptr(workspace), workspace.numel(), _stream(stream)))
+
+
+def grt_render_mis_noalloc(scene, env, gbuf: grt_gbuffer, opts: grt_mis_opts, out_rgb, saved, stream=None):
+    _check(load_library().grt_render_mis_noalloc(scene, env, C.byref(gbuf), C.byref(opts), _ptr(out_rgb),
+                                                 _ptr(saved), _stream(stream)))
 
 
 def grt_render_mis_backward(scene, env, gbuf, opts, grad_rgb, saved, grads: grt_surfel_grads, workspace,
