@@ -126,6 +126,14 @@ typedef struct {
     const float *leaf_boxes; /* [n,6] lo.xyz, hi.xyz in sorted order */
     const float *colours;    /* [n,4] rgb and the stored scale s_v, sorted order */
     const float *quats;      /* [n,4] the stored quaternion (w first), sorted order */
+    /* The 4-wide hierarchy the traversal walks, collapsed from `nodes`:
+     * nodes4 [max(n-1,0),32] (floats 0..23 the four child boxes as lo.x[4],
+     * lo.y[4], lo.z[4], hi.x[4], hi.y[4], hi.z[4]; int32 words 24..27 the
+     * children: >= 0 a 4-wide node, < 0 leaf -(pos+1), 0x7fffffff unused;
+     * word 28 the child count), of which the first *nodes4_count are used
+     * (node 0 the root; device int32, valid once the build has run). */
+    const float *nodes4;
+    const int32_t *nodes4_count;
 } grt_scene_view;
 int grt_scene_view_get(const grt_scene *scene, grt_scene_view *out);
 
@@ -150,7 +158,11 @@ typedef struct {
 /* k: k-nearest hit buffer size per traversal round, one of 1,2,4,8,12,16,32
  *    (results do not depend on k).
  * t_cut: transmittance cutoff (1e-3 in the workloads).
- * sky: radiance of escaped rays, L = c_rt + T sky.
+ * sky: radiance of escaped rays, L = c_rt + T sky (when env is NULL).
+ * env: optional built environment (grt_env_build); then L = c_rt + T L_env(d)
+ *    with the environment at the nearest texel of the ray direction, as the
+ *    MIS render looks it up (Sec. 3.3 Eq. lighting_decompose).  It must stay
+ *    alive until the trace has run on its stream.
  * hit_ids/hit_tau: optional [n, hit_cap] dump of the composited hits in
  *    order (surfel id, depth), -1 / 0 padded; NULL to skip.
  * stop_depth: optional [n] (device, float32).  grt_trace and
@@ -168,6 +180,7 @@ typedef struct {
     float *hit_tau;
     int hit_cap;
     float *stop_depth;
+    const grt_env *env;
 } grt_trace_opts;
 
 /* Bytes of device workspace grt_trace / grt_trace_backward need (the
@@ -581,7 +594,7 @@ int grt_denoise(grt_ctx *ctx, int H, int W, const float *rgb, const float *depth
  * mixed with.  The scene must not be rebuilt or destroyed while the server
  * exists.
  *
- * mem_budget:    device bytes the server allocates for requests (its pool).
+ * mem_budget:    device bytes of the request pool (inside the workspace).
  * max_jobs:      requests resident at once (1..256).
  * epoch_rays:    at most this many rays per epoch (0 = 134,217,728); an epoch
  *                takes the rest of the earliest-deadline request, plus the
@@ -594,8 +607,14 @@ int grt_denoise(grt_ctx *ctx, int H, int W, const float *rgb, const float *depth
  *                (0 or negative = never stop an epoch).  Stopping lowers the
  *                mean latency under load and raises the largest ones.
  * attrs:         per-surfel materials (device, borrowed for the server's
- *                life) for camera requests; all NULL = camera requests are
- *                refused. */
+ *                life) for camera and relighting requests; all NULL = such
+ *                requests are refused.
+ * workspace:     device memory the caller owns (e.g. a torch tensor), 256-byte
+ *                aligned, at least grt_server_workspace_bytes(opts) bytes,
+ *                borrowed until grt_server_destroy returns: the request pool,
+ *                the epochs' job and chunk tables and their claim counters
+ *                all live there (the server allocates no device memory; it
+ *                holds a few pinned host buffers of tables and flags). */
 typedef struct {
     size_t mem_budget;
     int max_jobs;
@@ -606,13 +625,28 @@ typedef struct {
     double slack_per_ray;
     double preempt_share;
     grt_surfel_attrs attrs;
+    void *workspace;
+    size_t ws_bytes;
 } grt_server_opts;
 
-/* A request.  All pointers are HOST memory, borrowed until the request is
- * done (pinned memory lets uploads overlap compute).  G-buffer arrays as in
- * grt_gbuffer; env_rgb [env_H, env_W, 3] as in grt_env_create; sample
- * allocation and random identity as in grt_mis_opts; out_rgb [H*W*3]
- * receives c_pbr.
+/* Device bytes grt_server_create needs in opts->workspace for these opts
+ * (mem_budget plus the epoch tables); 0 if max_jobs or mem_budget is out of
+ * range. */
+size_t grt_server_workspace_bytes(const grt_server_opts *opts);
+
+/* A request.  Pointers may be host or device memory, borrowed until the
+ * request is done (pinned host memory lets uploads overlap compute).
+ * G-buffer arrays as in grt_gbuffer; env_rgb [env_H, env_W, 3] as in
+ * grt_env_create; sample allocation and random identity as in grt_mis_opts;
+ * out_rgb [H*W*3] (host or device) receives c_pbr.
+ * relight = 0: the radiance estimator of grt_render_mis under the request's
+ * environment (the surfels' stored radiance, L_i = c_rt + T L_env).
+ * relight != 0: relighting under the request's environment (Sec. 3.5.1):
+ * the attribute query of the server's surfel materials and the split-sum
+ * shading of Eq. relight_splitsum, as grt_render_relight; the image equals
+ * grt_render_relight with the same inputs and opts whatever it was mixed
+ * with.  An epoch holds requests of one kind, and relighting epochs are never
+ * stopped early.
  * Camera request (camera_request != 0): the G-buffer pointers are ignored
  * (may be NULL).  The server traces the request's G-buffer from `camera` on
  * its upload stream, as grt_camera_rays followed by grt_trace_gbuffer (the
@@ -637,6 +671,7 @@ typedef struct {
     int camera_request;
     grt_camera camera;
     float min_opacity;
+    int relight;
 } grt_job;
 
 /* Pool bytes a request occupies while resident (0 if malformed). */

@@ -1610,3 +1610,27 @@ void orc_split_sum(int eH, int eW, const float *env_rgb, const double *Ed, const
         split_sum(&E, &rl, &q, w + 3 * k, out + 3 * k);
     }
 }
+
+/* Trace with an environment map instead of a constant sky (Sec. 3.3 Eq.
+ * lighting_decompose): L = c_rt + T_fin L_env(d), the environment looked up
+ * at the nearest texel of the ray direction (the render's lookup).  Rays as
+ * in orc_trace with scalar t_min/t_max; outL [nr,3]. */
+int orc_trace_env(int64_t n, const float *means, const float *scales, const float *quats, const float *opacity,
+                  const float *rgb, float alpha_min, int64_t nr, const float *orig, const float *dirs, float tmin,
+                  float tmax, float t_cut, int eH, int eW, const float *env_rgb, double *outL)
+{
+    Scene S;
+    if (scene_init(&S, n, means, scales, quats, opacity, rgb, alpha_min)) return -1;
+    Env E = {eH, eW, env_rgb, NULL, NULL};
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t r = 0; r < nr; ++r) {
+        RayResult R;
+        trace_ray(&S, orig + 3 * r, dirs + 3 * r, tmin, tmax, t_cut, &R);
+        double w[3] = {dirs[3 * r], dirs[3 * r + 1], dirs[3 * r + 2]}, Le[3];
+        env_radiance(&E, w, Le);
+        for (int c = 0; c < 3; ++c) outL[3 * r + c] = R.C[c] + R.T * Le[c];
+        free(R.h);
+    }
+    scene_free(&S);
+    return 0;
+}

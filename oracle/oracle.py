@@ -126,6 +126,22 @@ def trace(s, origins, dirs, t_min=0.0, t_max=np.inf, t_cut=T_CUT, alpha_min=ALPH
     return out
 
 
+def trace_env(s, origins, dirs, env_rgb, t_min=0.0, t_max=np.inf, t_cut=T_CUT, alpha_min=ALPHA_MIN):
+    """L [R,3] = c_rt + T_fin L_env(d) of every ray under an environment map
+    (nearest texel of the ray direction) instead of a constant sky."""
+    L = lib()
+    L.orc_trace_env.restype = C.c_int
+    L.orc_trace_env.argtypes = [I64, P, P, P, P, P, F, I64, P, P, F, F, F, C.c_int, C.c_int, P, P]
+    arrs = _scene(s)
+    o = _c(origins); d = _c(dirs); e = _c(env_rgb)
+    R = o.shape[0]
+    out = np.zeros((R, 3))
+    rc = L.orc_trace_env(s.n, *map(_p, arrs), alpha_min, R, _p(o), _p(d), float(t_min), float(t_max), t_cut,
+                         e.shape[0], e.shape[1], _p(e), _p(out))
+    assert rc == 0
+    return out
+
+
 def trace_attr(s, attrs, origins, dirs, t_min=0.0, t_max=np.inf, t_cut=T_CUT, alpha_min=ALPHA_MIN):
     """Brute-force attribute query Trace_attr(x, w) for every ray (the
     Gaussian backend): attrs = (albedo [n,3], rough [n], metal [n]).

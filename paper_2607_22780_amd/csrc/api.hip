@@ -78,6 +78,7 @@ grt::SceneDev scene_dev(const grt_scene *s)
     d.col = s->w.col;
     d.nodes = s->w.nodes;
     d.quat = s->w.quat;
+    d.nodes4 = s->w.nodes4;
     d.n = (int32_t)s->s.n;
     return d;
 }
@@ -297,6 +298,8 @@ int grt_scene_view_get(const grt_scene *scene, grt_scene_view *out)
     out->leaf_boxes = scene->w.leaf_box;
     out->colours = reinterpret_cast<const float *>(scene->w.col);
     out->quats = reinterpret_cast<const float *>(scene->w.quat);
+    out->nodes4 = reinterpret_cast<const float *>(scene->w.nodes4);
+    out->nodes4_count = scene->w.ctl4 + 2;
     return GRT_OK;
 }
 
@@ -318,6 +321,12 @@ static int fill_trace_args(const grt_scene *scene, const grt_rays *rays, const g
     a.tcut = opts->t_cut;
     for (int c = 0; c < 3; ++c) a.sky[c] = opts->sky[c];
     a.stop_depth = opts->stop_depth;
+    if (opts->env) {
+        if (!opts->env->built) return fail(GRT_ERR_NOT_BUILT, "trace environment used before grt_env_build");
+        a.env_rgb = opts->env->rgb;
+        a.env_H = opts->env->H;
+        a.env_W = opts->env->W;
+    }
     return GRT_OK;
 }
 

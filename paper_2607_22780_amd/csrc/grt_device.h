@@ -12,6 +12,11 @@
 // by surfel id, which would cost a random line per hit.
 //   node [n-1]  Node     both child boxes + child references        (64 B)
 // A child reference >= 0 is an internal node, < 0 is leaf -(pos+1).
+//   node4 [<= n-1] Node4 the same hierarchy collapsed to 4 children per
+//                        node (boxes as structure of arrays, references as
+//                        above, >= 0 now a 4-wide node)           (128 B)
+// The traversal walks the 4-wide nodes: half the node steps of the binary
+// tree, each testing up to four boxes from one 128-byte line.
 #pragma once
 
 #include <type_traits>
@@ -42,11 +47,22 @@ struct alignas(16) Node {
     int4 d;    // left, right, unused, unused
 };
 
+// Unused child slots of a 4-wide node hold this reference (and a zero box).
+constexpr int kNoChild = 0x7fffffff;
+
+struct alignas(16) Node4 {
+    float4 lx, ly, lz;  // lower corners of the four child boxes
+    float4 hx, hy, hz;  // upper corners
+    int4 ch;            // child references (kNoChild: unused slot)
+    int4 pad;
+};
+
 struct SceneDev {
     const float4 *rec;
     const float4 *col;
     const Node *nodes;
     const float4 *quat;  // stored quaternions in record order
+    const Node4 *nodes4;
     int32_t n;
 };
 
@@ -203,21 +219,29 @@ __device__ __forceinline__ uint64_t make_key(float tau, uint32_t id)
 #define GRT_LDS_DEPTH 24
 #endif
 constexpr int kLdsDepth = GRT_LDS_DEPTH;  // LDS entries per lane and stack
-constexpr int kBwdLdsDepth = 12;          // backward kernels: their LDS also holds gradient tables
+#ifndef GRT_BWD_LDS_DEPTH
+#define GRT_BWD_LDS_DEPTH 12
+#endif
+constexpr int kBwdLdsDepth = GRT_BWD_LDS_DEPTH;  // backward kernels: their LDS also holds gradient tables
 // Backward kernels composite a hit (running the gradient chain) only in
-// surfel steps where at least 3/16 of the wavefront's active lanes have one to
-// composite, or no lane is still walking, and run surfel steps once 3/8 of
-// the active lanes wait for one (measured best of composite shares 1/16 ..
-// 6/16 and step shares 1/4 .. 5/8).
-constexpr int kBwdCompShare16 = 3;
-constexpr int kBwdSiteShare8 = 3;
+// surfel steps where at least kBwdCompShare16/16 of the wavefront's active
+// lanes have one to composite, or no lane is still walking, and run surfel
+// steps once kBwdSiteShare8/8 of the active lanes wait for one.
+#ifndef GRT_BWD_COMP_SHARE16
+#define GRT_BWD_COMP_SHARE16 3
+#endif
+#ifndef GRT_BWD_SITE_SHARE8
+#define GRT_BWD_SITE_SHARE8 3
+#endif
+constexpr int kBwdCompShare16 = GRT_BWD_COMP_SHARE16;
+constexpr int kBwdSiteShare8 = GRT_BWD_SITE_SHARE8;
 // Surfel steps run when at least kSurfelShare4 / 4 of a wavefront's active
 // lanes wait for one.
 #ifndef GRT_SURFEL_SHARE4
 #define GRT_SURFEL_SHARE4 2
 #endif
 constexpr int kSurfelShare4 = GRT_SURFEL_SHARE4;
-constexpr int kStackCap = 256;  // logical capacity of a stack
+constexpr int kStackCap = 384;  // logical capacity of a stack
 constexpr int kNone = 0x7fffffff;
 
 template <int D>
@@ -252,10 +276,14 @@ struct SpillStack {
 
 // The walk stack and the deferred list of a lane; their roles swap each
 // round (the deferred list becomes the next round's walk stack).  A round's
-// stack starts with at most kMaxDeferred items and grows by at most one entry
-// per tree level below them (LBVH depth <= 63: 30-bit codes + position
-// tie-break), so it stays within kStackCap.
-constexpr int kMaxDeferred = kStackCap - 64;
+// stack starts with at most kMaxDeferred items; below them, a node step pops
+// one item and pushes at most three, so the stack holds at most three
+// siblings for each 4-wide level of the current path.  The 4-wide tree is no
+// deeper than the binary LBVH (each of its edges spans at least one binary
+// edge), whose depth is at most 63 (30-bit codes, then the position breaking
+// ties), so the stack stays within kMaxDeferred + 3 * 63 <= kStackCap.
+constexpr int kMaxDeferred = 192;
+static_assert(kMaxDeferred + 3 * 63 <= kStackCap, "walk stack bound");
 
 template <int D>
 struct Frontier {
@@ -405,47 +433,61 @@ struct Walker {
         return false;
     }
 
-    // Test the two children of node `cur`; sets the next item and at most one
-    // leaf to test.
+    // Test the children of 4-wide node `cur`; sets the next item and at most
+    // one leaf to test.  Kept children (met within thi) are taken nearest
+    // entry first: a leaf among them goes to the single surfel site in
+    // advance() (a wavefront then runs it once per step however its lanes'
+    // children are mixed), the nearest other child becomes the item in hand,
+    // and the rest go on the walk stack, farthest first.
     __device__ __forceinline__ void walk_node(const SceneDev &S, int &leaf)
     {
 #ifdef GRT_STATS
         ++st_nodes;
 #endif
-        const Node nd = S.nodes[cur];
-        float tl, tr;
-        bool hl = slab(nd.a.x, nd.a.y, nd.a.z, nd.a.w, nd.b.x, nd.b.y, o, inv, tlo, tmax, tl);
-        bool hr = slab(nd.b.z, nd.b.w, nd.c.x, nd.c.y, nd.c.z, nd.c.w, o, inv, tlo, tmax, tr);
-        const int cl = nd.d.x, cr = nd.d.y;
-        hl = keep_child(cl, hl, tl);
-        hr = keep_child(cr, hr, tr);
-        // Kept children, nearer first.  A step tests at most one leaf, at the
-        // single surfel site in advance() (a wavefront then runs it once per
-        // step however its lanes' children are mixed); the other child
-        // becomes the item in hand or goes on the walk stack.
-        const bool lfirst = hl && (!hr || tl <= tr);
-        const int near = lfirst ? cl : cr, far = lfirst ? cr : cl;
-        if (hl && hr) {
-            if (near < 0) {
-                leaf = near;
-                cur = far;
-            } else if (far < 0) {
-                leaf = far;
-                cur = near;
-            } else {
-                F.walk.push(far);
-                cur = near;
-            }
-        } else if (hl || hr) {
-            if (near < 0) {
-                leaf = near;
-                cur = kNone;
-            } else {
-                cur = near;
-            }
-        } else {
-            cur = kNone;
+        const Node4 *nd = S.nodes4 + cur;
+        const float4 lx = nd->lx, ly = nd->ly, lz = nd->lz, hx = nd->hx, hy = nd->hy, hz = nd->hz;
+        const int4 ch = nd->ch;
+        float t0 = 0.0f, t1 = 0.0f, t2 = 0.0f, t3 = 0.0f;
+        bool k0 = ch.x != kNoChild && slab(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, o, inv, tlo, tmax, t0);
+        bool k1 = ch.y != kNoChild && slab(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, o, inv, tlo, tmax, t1);
+        bool k2 = ch.z != kNoChild && slab(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, o, inv, tlo, tmax, t2);
+        bool k3 = ch.w != kNoChild && slab(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, o, inv, tlo, tmax, t3);
+        k0 = keep_child(ch.x, k0, t0);
+        k1 = keep_child(ch.y, k1, t1);
+        k2 = keep_child(ch.z, k2, t2);
+        k3 = keep_child(ch.w, k3, t3);
+        const int m = (int)k0 + (int)k1 + (int)k2 + (int)k3;
+        // kept children first, by entry depth (a five-exchange sorting network)
+        float s0 = k0 ? t0 : INFINITY, s1 = k1 ? t1 : INFINITY, s2 = k2 ? t2 : INFINITY, s3 = k3 ? t3 : INFINITY;
+        int c0 = k0 ? ch.x : kNone, c1 = k1 ? ch.y : kNone, c2 = k2 ? ch.z : kNone, c3 = k3 ? ch.w : kNone;
+        auto xch = [](float &sa, int &ca, float &sb, int &cb) {
+            const bool sw = sb < sa;
+            const float ts = sw ? sb : sa;
+            const int tc = sw ? cb : ca;
+            sb = sw ? sa : sb;
+            cb = sw ? ca : cb;
+            sa = ts;
+            ca = tc;
+        };
+        xch(s0, c0, s1, c1);
+        xch(s2, c2, s3, c3);
+        xch(s0, c0, s2, c2);
+        xch(s1, c1, s3, c3);
+        xch(s1, c1, s2, c2);
+        // the nearest kept leaf, if any, is the step's leaf; the others in order
+        const int li = (m > 0 && c0 < 0) ? 0 : (m > 1 && c1 < 0) ? 1 : (m > 2 && c2 < 0) ? 2 : (m > 3 && c3 < 0) ? 3 : -1;
+        int o0 = c0, o1 = c1, o2 = c2, o3 = c3, no = m;
+        if (li >= 0) {
+            leaf = li == 0 ? c0 : li == 1 ? c1 : li == 2 ? c2 : c3;
+            o0 = li == 0 ? c1 : c0;
+            o1 = li <= 1 ? c2 : c1;
+            o2 = li <= 2 ? c3 : c2;
+            no = m - 1;
         }
+        cur = no >= 1 ? o0 : kNone;
+        if (no >= 4) F.walk.push(o3);
+        if (no >= 3) F.walk.push(o2);
+        if (no >= 2) F.walk.push(o1);
     }
 
     // Set up the next round from the deferred frontier (or the root).

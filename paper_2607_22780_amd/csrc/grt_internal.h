@@ -51,6 +51,9 @@ struct SceneWS {
     int32_t *bounds;       // [8]
     float *acc;            // [n,16] gradient lines of the backward passes
     float4 *quat;          // [n] stored quaternions in record order
+    Node4 *nodes4;         // [n-1] the 4-wide hierarchy (node 0 the root)
+    int32_t *f4;           // [n-1] binary node each 4-wide node was collapsed from
+    int32_t *ctl4;         // [4] collapse state: level range [lo, hi), node count
     size_t bytes;
 };
 
@@ -81,6 +84,9 @@ inline SceneWS carve_scene(void *base, int64_t n)
     w.bounds = (int32_t *)take(4 * 8);
     w.acc = (float *)take(64 * nn);
     w.quat = (float4 *)take(16 * nn);
+    w.nodes4 = (Node4 *)take(sizeof(Node4) * ni);
+    w.f4 = (int32_t *)take(4 * ni);
+    w.ctl4 = (int32_t *)take(16);
     w.bytes = off;
     return w;
 }
@@ -143,6 +149,8 @@ struct TraceArgs {
     int cap;
     float *stop_depth;  // written by the forwards, read by the backwards (NULL: unused)
     unsigned long long *counters;
+    const float *env_rgb;  // environment [env_H, env_W, 3] for L, or NULL: the constant sky
+    int env_H, env_W;
 };
 hipError_t launch_trace(const TraceArgs &a, int k, int num_cu, hipStream_t st);
 
@@ -355,6 +363,9 @@ hipError_t launch_render_gen(const RenderArgs &a, hipStream_t st);
 // Split-sum relighting (needs a.E's prefiltered tables and a.sa_*): the
 // forward render with the attribute query and Eq. relight_splitsum.
 hipError_t launch_render_relight(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st);
+// Relighting's shading pass alone, over every sample of a.H x a.W x spp whose
+// attribute query has run (the server runs it once a request's rays are done).
+hipError_t launch_relight_shade(const RenderArgs &a, hipStream_t st);
 // relighting through the mesh: the query pass over a render's ray records
 // (m's ray fields unused), then the surfel relight's shading pass
 hipError_t launch_mesh_relight_query(const RenderArgs &a, const MeshTraceArgs &m, hipStream_t st);

@@ -447,6 +447,54 @@ struct ShadeTrace {
     }
 };
 
+// The persistent-loop job of the relighting trace (Sec. 3.5.1, Eq.
+// trace_attr): begin loads the ray record (skipping untraced samples), and
+// finish parks the attribute query's result for the shading pass: (V,
+// albedo) in the sample's contribution slot, (roughness, metallic) in the
+// spare words of its ray record, the averaged normal in rl_n*.  `a` may
+// differ per lane (the server mixes requests).
+template <int K>
+struct RelightTrace {
+    Walker<K> w;
+    AttrVisit v;
+
+    __device__ __forceinline__ bool begin(const RenderArgs &a, const SceneDev &S, int64_t r)
+    {
+        const float4 r0 = a.rays[3 * r];
+        if (r0.w == 0.0f) {
+            a.contrib[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+            return false;
+        }
+        const int64_t p = r / (a.nc + a.ng + a.ne);
+        const float3 x = make_float3(a.x[3 * p], a.x[3 * p + 1], a.x[3 * p + 2]);
+        const float3 d = make_float3(r0.x, r0.y, r0.z);
+        v.rec = S.rec;
+        v.albedo = a.sa_albedo;
+        v.rough = a.sa_rough;
+        v.metal = a.sa_metal;
+        v.tcut = a.tcut;
+        v.reset(x, d);
+        w.start(S, x, d, a.tmin, INFINITY);
+        if (S.n <= 0) {
+            finish(a, r);
+            return false;
+        }
+        return true;
+    }
+
+    __device__ __forceinline__ void finish(const RenderArgs &a, int64_t r)
+    {
+        const float inv = v.W > 0.0f ? 1.0f / v.W : 0.0f;
+        a.contrib[r] = make_float4(v.T, v.A.x * inv, v.A.y * inv, v.A.z * inv);
+        float4 *r2 = a.rays + 3 * r + 2;
+        r2->z = v.R * inv;
+        r2->w = v.M * inv;
+        a.rl_nx[r] = v.N.x * inv;
+        a.rl_ny[r] = v.N.y * inv;
+        a.rl_nz[r] = v.N.z * inv;
+    }
+};
+
 // c_pbr = (1/N_r) sum_j contrib[p, j], summed in sample order
 __device__ __forceinline__ void reduce_pixel(int64_t p, int spp, const float4 *__restrict__ contrib,
                                              float *__restrict__ out)

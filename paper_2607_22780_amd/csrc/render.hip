@@ -215,52 +215,24 @@ struct RenderJob {
 };
 
 // Relighting (Sec. 3.5.1), first pass: the forward render's job with the
-// attribute query instead of the radiance trace.  It parks each traced
-// sample's query result for the shading pass: (V, albedo) in the sample's
-// contribution slot, (roughness, metallic) in the spare words of its ray
-// record, the averaged normal in rl_n*.
+// attribute query instead of the radiance trace (RelightTrace parks each
+// traced sample's query result for the shading pass).
 template <int K>
 struct RelightJob {
     const RenderArgs &a;
     SceneDev S;
-    Walker<K> w;
-    AttrVisit v;
+    RelightTrace<K> t;
     int64_t r;
 
-    __device__ RelightJob(const RenderArgs &a_)
-        : a(a_), S(a_.S), v(a_.S, a_.tcut, a_.sa_albedo, a_.sa_rough, a_.sa_metal), r(0) {}
-    __device__ __forceinline__ Walker<K> &walker() { return w; }
-    __device__ __forceinline__ AttrVisit &visit() { return v; }
+    __device__ RelightJob(const RenderArgs &a_) : a(a_), S(a_.S), r(0) {}
+    __device__ __forceinline__ Walker<K> &walker() { return t.w; }
+    __device__ __forceinline__ AttrVisit &visit() { return t.v; }
     __device__ __forceinline__ bool begin(int64_t g)
     {
         r = a.order ? (int64_t)a.order[g] : g;
-        const float4 r0 = a.rays[3 * r];
-        if (r0.w == 0.0f) {
-            a.contrib[r] = make_float4(0.f, 0.f, 0.f, 0.f);
-            return false;
-        }
-        const int64_t p = r / (a.nc + a.ng + a.ne);
-        const float3 x = make_float3(a.x[3 * p], a.x[3 * p + 1], a.x[3 * p + 2]);
-        const float3 d = make_float3(r0.x, r0.y, r0.z);
-        v.reset(x, d);
-        w.start(S, x, d, a.tmin, INFINITY);
-        if (S.n <= 0) {
-            finish(g);
-            return false;
-        }
-        return true;
+        return t.begin(a, S, r);
     }
-    __device__ __forceinline__ void finish(int64_t)
-    {
-        const float inv = v.W > 0.0f ? 1.0f / v.W : 0.0f;
-        a.contrib[r] = make_float4(v.T, v.A.x * inv, v.A.y * inv, v.A.z * inv);
-        float4 *r2 = a.rays + 3 * r + 2;
-        r2->z = v.R * inv;
-        r2->w = v.M * inv;
-        a.rl_nx[r] = v.N.x * inv;
-        a.rl_ny[r] = v.N.y * inv;
-        a.rl_nz[r] = v.N.z * inv;
-    }
+    __device__ __forceinline__ void finish(int64_t) { t.finish(a, r); }
     __device__ __forceinline__ void after_step() {}
     __device__ __forceinline__ void drain() {}
 };
@@ -609,6 +581,14 @@ hipError_t launch_render_relight(const RenderArgs &a, const RenderWS &w, int k, 
     hipLaunchKernelGGL(k_relight_shade, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a, total);
     hipLaunchKernelGGL(k_render_reduce, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st, npix,
                        a.nc + a.ng + a.ne, a.contrib, a.out);
+    return hipGetLastError();
+}
+
+hipError_t launch_relight_shade(const RenderArgs &a, hipStream_t st)
+{
+    const int64_t total = (int64_t)a.H * a.W * (a.nc + a.ng + a.ne);
+    if (total <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_relight_shade, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, a, total);
     return hipGetLastError();
 }
 

@@ -10,6 +10,8 @@
 //   3. stable LSD radix sort, 4 passes x 8 bit (k_radix_hist/scan/scatter)
 //   4. records in sorted order                 (k_records)
 //   5. Karras hierarchy, then bottom-up refit  (k_hierarchy, k_refit)
+#include <algorithm>
+
 #include "grt_internal.h"
 
 namespace grt {
@@ -349,6 +351,108 @@ __global__ void k_refit(int n, const float *__restrict__ leaf_box, Node *nodes, 
     }
 }
 
+// ---------------------------------------------------------------------------
+// The 4-wide hierarchy the traversal walks, collapsed top down from the
+// binary LBVH, one level of 4-wide nodes per launch.  A 4-wide node starts
+// from a binary node's two children and twice opens the internal child of
+// largest surface area (replacing it by its two children), so it has 2..4
+// children.  Its internal children become the 4-wide nodes of the next level:
+// each takes the next index from a counter and records which binary node it
+// collapses.  Level ranges and the counter live in device memory, so the
+// host launches a fixed number of levels without reading anything back.
+// ---------------------------------------------------------------------------
+constexpr int kCollapseLevels = 64;  // >= the LBVH's depth bound (63) + 1
+
+__device__ __forceinline__ float box_area(const float *b)
+{
+    const float dx = b[3] - b[0], dy = b[4] - b[1], dz = b[5] - b[2];
+    return dx * dy + dy * dz + dz * dx;
+}
+
+__global__ void k_collapse_init(int32_t *__restrict__ ctl, int32_t *__restrict__ f4)
+{
+    if (threadIdx.x == 0) {
+        ctl[0] = 0;  // level range [lo, hi)
+        ctl[1] = 1;
+        ctl[2] = 1;  // nodes allocated
+        f4[0] = 0;   // the root collapses binary node 0
+    }
+}
+
+__global__ void k_collapse_next(int32_t *__restrict__ ctl)
+{
+    if (threadIdx.x == 0) {
+        ctl[0] = ctl[1];
+        ctl[1] = ctl[2];
+    }
+}
+
+__global__ void __launch_bounds__(256) k_collapse(const Node *__restrict__ bin, Node4 *__restrict__ out,
+                                                   int32_t *__restrict__ f4, int32_t *ctl)
+{
+    const int lo = ctl[0], hi = ctl[1];
+    for (int i = lo + (int)(blockIdx.x * blockDim.x + threadIdx.x); i < hi; i += (int)(gridDim.x * blockDim.x)) {
+        float box[4][6];
+        int ref[4];
+        const float *w = reinterpret_cast<const float *>(&bin[f4[i]]);
+        const int4 c = bin[f4[i]].d;
+#pragma unroll
+        for (int a = 0; a < 6; ++a) { box[0][a] = w[a]; box[1][a] = w[6 + a]; }
+        ref[0] = c.x;
+        ref[1] = c.y;
+        int m = 2;
+        for (int e = 0; e < 2; ++e) {
+            int best = -1;
+            float ba = -1.0f;
+            for (int j = 0; j < m; ++j)
+                if (ref[j] >= 0) {
+                    const float ar = box_area(box[j]);
+                    if (ar > ba) { ba = ar; best = j; }
+                }
+            if (best < 0) break;
+            const Node &nd = bin[ref[best]];
+            const float *v = reinterpret_cast<const float *>(&nd);
+            const int4 d = nd.d;
+#pragma unroll
+            for (int a = 0; a < 6; ++a) { box[best][a] = v[a]; box[m][a] = v[6 + a]; }
+            ref[best] = d.x;
+            ref[m] = d.y;
+            ++m;
+        }
+        Node4 o;
+        float *lo4 = reinterpret_cast<float *>(&o.lx);  // lx, ly, lz, hx, hy, hz: 6 x 4 floats
+        int *ch = reinterpret_cast<int *>(&o.ch);
+        for (int j = 0; j < 4; ++j) {
+            int r = kNoChild;
+            if (j < m) {
+                r = ref[j];
+                if (r >= 0) {
+                    const int k = atomicAdd(&ctl[2], 1);
+                    f4[k] = r;
+                    r = k;
+                }
+            }
+            ch[j] = r;
+#pragma unroll
+            for (int a = 0; a < 6; ++a) lo4[4 * a + j] = j < m ? box[j][a] : 0.0f;
+        }
+        o.pad = make_int4(m, 0, 0, 0);
+        out[i] = o;
+    }
+}
+
+hipError_t launch_collapse4(int n, const Node *nodes, Node4 *nodes4, int32_t *f4, int32_t *ctl, hipStream_t st)
+{
+    if (n <= 1) return hipSuccess;
+    const int blocks = (int)std::min<int64_t>(1024, ((int64_t)n / 2 + 255) / 256);
+    hipLaunchKernelGGL(k_collapse_init, dim3(1), dim3(64), 0, st, ctl, f4);
+    for (int l = 0; l < kCollapseLevels; ++l) {
+        hipLaunchKernelGGL(k_collapse, dim3(blocks), dim3(256), 0, st, nodes, nodes4, f4, ctl);
+        hipLaunchKernelGGL(k_collapse_next, dim3(1), dim3(64), 0, st, ctl);
+    }
+    return hipGetLastError();
+}
+
 void launch_radix_sort(int n, int passes, uint32_t *k0, uint32_t *v0, uint32_t *k1, uint32_t *v1, uint32_t *hist,
                        hipStream_t st)
 {
@@ -422,6 +526,7 @@ hipError_t launch_scene_build(const grt_surfels &s, float alpha_min, const Scene
                            w.flags);
         hipLaunchKernelGGL(k_refit, dim3(gb), dim3(tb), 0, st, n, w.leaf_box, w.nodes, w.parent_int, w.parent_leaf,
                            w.flags);
+        return launch_collapse4(n, w.nodes, w.nodes4, w.f4, w.ctl4, st);
     }
     return hipGetLastError();
 }

@@ -64,11 +64,14 @@ __device__ __forceinline__ int find_chunk(const ServeChunk *chunks, int nchunks,
     return lo;
 }
 
-template <int K>
+// Trace: ShadeTrace<K> (the radiance trace of Eq. mis) or RelightTrace<K>
+// (the attribute query of relighting, Eq. trace_attr); an epoch holds
+// requests of one kind.
+template <int K, class Trace>
 struct ServeJob {
     const ServeEpoch &e;
     SceneDev S;
-    ShadeTrace<K> t;
+    Trace t;
     const RenderArgs *a;
     int64_t r;
 
@@ -85,26 +88,27 @@ struct ServeJob {
         return t.begin(*a, S, r);
     }
 
-    __device__ __forceinline__ void finish(int64_t) { t.finish(*a, r); }    __device__ __forceinline__ void after_step() {}
+    __device__ __forceinline__ void finish(int64_t) { t.finish(*a, r); }
+    __device__ __forceinline__ void after_step() {}
     __device__ __forceinline__ void drain() {}
 };
 
 // kStop: the epoch may be stopped (e.stop set).  Without it the persistent
 // loop carries no stop test, as a direct render's does.
-template <int K, bool kStop>
+template <int K, class Trace, bool kStop>
 __global__ void __launch_bounds__(256) GRT_OCCUPANCY k_serve(ServeEpoch e)
 {
-    ServeJob<K> job(e);
+    ServeJob<K, Trace> job(e);
     if (kStop)
         run_persistent<K>(job, e.counters, e.total, e.stop);
     else
         run_persistent<K>(job, e.counters, e.total);
 }
 
-template <int K, bool kStop>
+template <int K, class Trace, bool kStop>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_serve_w3(ServeEpoch e)
 {
-    ServeJob<K> job(e);
+    ServeJob<K, Trace> job(e);
     if (kStop)
         run_persistent<K>(job, e.counters, e.total, e.stop);
     else
@@ -115,11 +119,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
 // (uniform across the grid, as in a direct render); its rays are one range
 // of the request's sample order, or a few once a stopped epoch handed some
 // back (then each ray finds its range in the chunk table).
-template <int K, bool kPlain>
+template <int K, class Trace, bool kPlain>
 struct ServeOneJob {
     const RenderArgs &a;
     SceneDev S;
-    ShadeTrace<K> t;
+    Trace t;
     const ServeChunk *chunks;
     int nchunks;
     int64_t r0;
@@ -140,19 +144,21 @@ struct ServeOneJob {
         r = a.order ? (int64_t)a.order[q] : q;
         return t.begin(a, S, r);
     }
-    __device__ __forceinline__ void finish(int64_t) { t.finish(a, r); }    __device__ __forceinline__ void after_step() {}
+    __device__ __forceinline__ void finish(int64_t) { t.finish(a, r); }
+    __device__ __forceinline__ void after_step() {}
     __device__ __forceinline__ void drain() {}
 };
 
 // kPlain: one range of rays and no stop flag (every epoch while preemption
-// is off), so the kernel is the direct render's loop with the request's
-// arguments; otherwise it handles a range table and a stop flag.
-template <int K, bool kPlain>
+// is off, and every relighting epoch), so the kernel is the direct render's
+// loop with the request's arguments; otherwise it handles a range table and
+// a stop flag.
+template <int K, class Trace, bool kPlain>
 __global__ void __launch_bounds__(256) GRT_OCCUPANCY
     k_serve_one(RenderArgs a, const ServeChunk *chunks, int nchunks, int64_t r0, int64_t n,
                 unsigned long long *counters, const int *stop)
 {
-    ServeOneJob<K, kPlain> job(a, chunks, nchunks, r0);
+    ServeOneJob<K, Trace, kPlain> job(a, chunks, nchunks, r0);
     if (kPlain)
         run_persistent<K>(job, counters, n);
     else
@@ -160,12 +166,12 @@ __global__ void __launch_bounds__(256) GRT_OCCUPANCY
 }
 
 // K = 12 held to 3 wavefronts per SIMD, as the direct render's forward
-template <int K, bool kPlain>
+template <int K, class Trace, bool kPlain>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
     k_serve_one_w3(RenderArgs a, const ServeChunk *chunks, int nchunks, int64_t r0, int64_t n,
                    unsigned long long *counters, const int *stop)
 {
-    ServeOneJob<K, kPlain> job(a, chunks, nchunks, r0);
+    ServeOneJob<K, Trace, kPlain> job(a, chunks, nchunks, r0);
     if (kPlain)
         run_persistent<K>(job, counters, n);
     else
@@ -185,68 +191,62 @@ __global__ void k_serve_reduce(const RenderArgs *a, int64_t npix, const unsigned
     reduce_pixel(p, a->nc + a->ng + a->ne, a->contrib, a->out);
 }
 
-template <int K, bool kStop>
+template <int K, class Trace, bool kStop>
 static hipError_t go_serve_as(const ServeEpoch &e, int num_cu, hipStream_t st)
 {
     if constexpr (K == 12) {
-        const int nb = persistent_blocks(k_serve_w3<K, kStop>, num_cu, e.total);
-        hipLaunchKernelGGL((k_serve_w3<K, kStop>), dim3(nb), dim3(256), 0, st, e);
+        const int nb = persistent_blocks(k_serve_w3<K, Trace, kStop>, num_cu, e.total);
+        hipLaunchKernelGGL((k_serve_w3<K, Trace, kStop>), dim3(nb), dim3(256), 0, st, e);
     } else {
-        const int nb = persistent_blocks(k_serve<K, kStop>, num_cu, e.total);
-        hipLaunchKernelGGL((k_serve<K, kStop>), dim3(nb), dim3(256), 0, st, e);
+        const int nb = persistent_blocks(k_serve<K, Trace, kStop>, num_cu, e.total);
+        hipLaunchKernelGGL((k_serve<K, Trace, kStop>), dim3(nb), dim3(256), 0, st, e);
     }
     return hipGetLastError();
 }
 
-template <int K>
-static hipError_t go_serve(const ServeEpoch &e, int num_cu, hipStream_t st)
-{
-    return e.stop ? go_serve_as<K, true>(e, num_cu, st) : go_serve_as<K, false>(e, num_cu, st);
-}
-
-template <int K, bool kPlain>
+template <int K, class Trace, bool kPlain>
 static hipError_t go_serve_one_as(const RenderArgs &a, const ServeEpoch &e, int64_t r0, int num_cu, hipStream_t st)
 {
     if constexpr (K == 12) {
-        const int nb = persistent_blocks(k_serve_one_w3<K, kPlain>, num_cu, e.total);
-        hipLaunchKernelGGL((k_serve_one_w3<K, kPlain>), dim3(nb), dim3(256), 0, st, a, e.chunks, e.nchunks, r0,
-                           e.total, e.counters, e.stop);
+        const int nb = persistent_blocks(k_serve_one_w3<K, Trace, kPlain>, num_cu, e.total);
+        hipLaunchKernelGGL((k_serve_one_w3<K, Trace, kPlain>), dim3(nb), dim3(256), 0, st, a, e.chunks, e.nchunks,
+                           r0, e.total, e.counters, e.stop);
     } else {
-        const int nb = persistent_blocks(k_serve_one<K, kPlain>, num_cu, e.total);
-        hipLaunchKernelGGL((k_serve_one<K, kPlain>), dim3(nb), dim3(256), 0, st, a, e.chunks, e.nchunks, r0,
+        const int nb = persistent_blocks(k_serve_one<K, Trace, kPlain>, num_cu, e.total);
+        hipLaunchKernelGGL((k_serve_one<K, Trace, kPlain>), dim3(nb), dim3(256), 0, st, a, e.chunks, e.nchunks, r0,
                            e.total, e.counters, e.stop);
     }
     return hipGetLastError();
 }
 
+// Radiance epochs may be stopped; relighting epochs never are.
 template <int K>
-static hipError_t go_serve_one(const RenderArgs &a, const ServeEpoch &e, int64_t r0, int num_cu, hipStream_t st)
+static hipError_t go_epoch(const ServeEpoch &e, const RenderArgs *one, int64_t r0, bool relight, int num_cu,
+                           hipStream_t st)
 {
-    return (!e.stop && e.nchunks <= 1) ? go_serve_one_as<K, true>(a, e, r0, num_cu, st)
-                                       : go_serve_one_as<K, false>(a, e, r0, num_cu, st);
+    if (relight)
+        return one ? go_serve_one_as<K, RelightTrace<K>, true>(*one, e, r0, num_cu, st)
+                   : go_serve_as<K, RelightTrace<K>, false>(e, num_cu, st);
+    if (one)
+        return (!e.stop && e.nchunks <= 1) ? go_serve_one_as<K, ShadeTrace<K>, true>(*one, e, r0, num_cu, st)
+                                           : go_serve_one_as<K, ShadeTrace<K>, false>(*one, e, r0, num_cu, st);
+    return e.stop ? go_serve_as<K, ShadeTrace<K>, true>(e, num_cu, st)
+                  : go_serve_as<K, ShadeTrace<K>, false>(e, num_cu, st);
 }
 
 // one: the request when every chunk of the epoch is of that one request, else
-// null; r0: the first ray of chunk 0
-static hipError_t launch_epoch(const ServeEpoch &e, const RenderArgs *one, int64_t r0, int k, int num_cu,
+// null; r0: the first ray of chunk 0; relight: the epoch's requests are
+// relighting requests (the attribute query)
+static hipError_t launch_epoch(const ServeEpoch &e, const RenderArgs *one, int64_t r0, bool relight, int k, int num_cu,
                                hipStream_t st)
 {
     const hipError_t err = launch_zero_counters(e.counters, st);
     if (err != hipSuccess) return err;
-    if (one) {
-        switch (k) {
-        case 4: return go_serve_one<4>(*one, e, r0, num_cu, st);
-        case 8: return go_serve_one<8>(*one, e, r0, num_cu, st);
-        case 12: return go_serve_one<12>(*one, e, r0, num_cu, st);
-        case 16: return go_serve_one<16>(*one, e, r0, num_cu, st);
-        default: return hipErrorInvalidValue;
-        }
-    }
     switch (k) {
-    case 4: return go_serve<4>(e, num_cu, st);
-    case 8: return go_serve<8>(e, num_cu, st);
-    case 12: return go_serve<12>(e, num_cu, st);
-    case 16: return go_serve<16>(e, num_cu, st);
+    case 4: return go_epoch<4>(e, one, r0, relight, num_cu, st);
+    case 8: return go_epoch<8>(e, one, r0, relight, num_cu, st);
+    case 12: return go_epoch<12>(e, one, r0, relight, num_cu, st);
+    case 16: return go_epoch<16>(e, one, r0, relight, num_cu, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -271,6 +271,7 @@ struct ServerJob {
     EnvWS env{};
     RenderWS sort{};  // sort keys/values and histogram (counters, rays, contrib unused)
     int64_t npix = 0, total = 0;
+    bool relight = false;  // a relighting request (Eq. relight_splitsum), else radiance (Eq. mis)
     // rays not yet handed to an epoch: ranges of the request's sample order
     // (one range, until a stopped epoch hands back what it did not claim)
     std::deque<std::pair<int64_t, int64_t>> left;
@@ -345,6 +346,11 @@ static size_t carve_job(ServerJob &j, char *base)
     a.rays = (float4 *)take(48 * nray);
     a.contrib = (float4 *)take(16 * nray);
     a.out = (float *)take(12 * npix);
+    if (j.spec.relight) {  // where the attribute query parks each sample's averaged normal
+        a.rl_nx = (float *)take(4 * nray);
+        a.rl_ny = (float *)take(4 * nray);
+        a.rl_nz = (float *)take(4 * nray);
+    }
     // coherent traversal order of the request's samples, and its sort scratch
     j.sort.k0 = (uint32_t *)take(4 * nray);
     j.sort.v0 = (uint32_t *)take(4 * nray);
@@ -368,6 +374,7 @@ struct EpochSlot {
     hipEvent_t done = nullptr;
     bool inflight = false;
     bool preemptible = false;  // one request's rays: may be stopped early
+    bool relight = false;      // an epoch of relighting requests
     bool stopped = false;      // the stop flag was raised
     int nch = 0;
     int64_t rays = 0;       // rays of the epoch in flight
@@ -508,11 +515,14 @@ hipError_t upload(grt_server *s, ServerJob &j)
     // a camera request uploads only its environment and traces its G-buffer
     const int ncp = q.camera_request ? 1 : (int)(sizeof(cps) / sizeof(cps[0]));
     for (int i = 0; i < ncp; ++i)
-        if ((e = hipMemcpyAsync((void *)cps[i].dst, cps[i].src, cps[i].n, hipMemcpyHostToDevice, s->copy)) !=
+        if ((e = hipMemcpyAsync((void *)cps[i].dst, cps[i].src, cps[i].n, hipMemcpyDefault, s->copy)) !=
             hipSuccess)
             return e;
     if (q.camera_request && (e = trace_request_gbuffer(s, j)) != hipSuccess) return e;
     if ((e = grt::launch_env_build(a.E.rgb, q.env_H, q.env_W, j.env, s->copy)) != hipSuccess) return e;
+    // relighting: the prefiltered environment and the DFG table (Eq. relight_splitsum)
+    if (j.relight && (e = grt::launch_env_prefilter(a.E.rgb, q.env_H, q.env_W, j.env, s->copy)) != hipSuccess)
+        return e;
     // every sample's ray record up front, so epochs only trace, and the
     // samples' coherent traversal order
     if ((e = grt::launch_render_gen(a, s->copy)) != hipSuccess) return e;
@@ -543,6 +553,15 @@ void setup_args(grt_server *s, ServerJob &j)
     a.saved_t = nullptr;
     a.dump = nullptr;
     a.grad = nullptr;
+    a.hits = nullptr;
+    if (j.relight) {
+        a.E.Ed = j.env.Ed;
+        a.E.Es = j.env.Es;
+        a.E.lut = j.env.lut;
+        a.sa_albedo = s->opts.attrs.albedo;
+        a.sa_rough = s->opts.attrs.rough;
+        a.sa_metal = s->opts.attrs.metal;
+    }
 }
 
 void finish_job(grt_server *s, ServerJob &j, int status)
@@ -707,6 +726,10 @@ bool launch(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other, int64_t bud
         const bool pa = guarded(a), pb = guarded(b);
         return pa != pb ? pa : a->deadline < b->deadline;
     });
+    // an epoch holds requests of the head request's kind (one trace per kernel)
+    const bool relight = run[0]->relight;
+    run.erase(std::remove_if(run.begin(), run.end(), [relight](const ServerJob *j) { return j->relight != relight; }),
+              run.end());
     // With preemption on, an earlier-deadline request still uploading needs
     // the CUs for its sampling and sort kernels first: a persistent epoch
     // would hold them (without it, that request passes at the next epoch).
@@ -765,8 +788,10 @@ bool launch(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other, int64_t bud
     for (ServerJob *j : run)
         if (j->started && j->nleft > 0 && std::find(E.members.begin(), E.members.end(), j->id) == E.members.end())
             j->passable -= off;
-    // an epoch of one request's rays may be stopped for a more urgent one
-    E.preemptible = s->share > 0.0 && E.members.size() == 1 && off >= kPreemptRays;
+    // an epoch of one request's radiance rays may be stopped for a more
+    // urgent one (relighting epochs run to their end)
+    E.relight = relight;
+    E.preemptible = !relight && s->share > 0.0 && E.members.size() == 1 && off >= kPreemptRays;
     E.stopped = false;
     E.nch = nch;
     __atomic_store_n(E.stop_h, 0, __ATOMIC_RELEASE);
@@ -784,7 +809,7 @@ bool launch(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other, int64_t bud
         err = hipMemcpyAsync(E.d_chunks, E.h_chunks, sizeof(grt::ServeChunk) * nch, hipMemcpyHostToDevice, E.stream);
     const grt::RenderArgs *one = E.members.size() == 1 ? &E.h_jobs[E.h_chunks[0].slot] : nullptr;
     if (err == hipSuccess)
-        err = grt::launch_epoch(e, one, E.h_chunks[0].begin, s->opts.k, s->ctx->num_cu, E.stream);
+        err = grt::launch_epoch(e, one, E.h_chunks[0].begin, relight, s->opts.k, s->ctx->num_cu, E.stream);
     if (err == hipSuccess && E.preemptible)
         err = hipMemcpyAsync(E.h_counters, E.counters, grt::kParts * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                              E.stream);
@@ -794,11 +819,13 @@ bool launch(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other, int64_t bud
     for (uint64_t id : E.finishing) {
         if (err != hipSuccess) break;
         ServerJob &j = s->jobs[id];
+        // relighting: the shading pass over the request's parked query results
+        if (j.relight && (err = grt::launch_relight_shade(j.args, E.stream)) != hipSuccess) break;
         hipLaunchKernelGGL(grt::k_serve_reduce, dim3((unsigned)((j.npix + 255) / 256)), dim3(256), 0, E.stream,
                            E.d_jobs + j.slot, j.npix, E.preemptible ? E.counters : nullptr, off);
         err = hipGetLastError();
         if (err == hipSuccess)
-            err = hipMemcpyAsync(j.spec.out_rgb, j.args.out, 12 * (size_t)j.npix, hipMemcpyDeviceToHost, E.stream);
+            err = hipMemcpyAsync(j.spec.out_rgb, j.args.out, 12 * (size_t)j.npix, hipMemcpyDefault, E.stream);
     }
     if (err == hipSuccess) err = hipEventRecord(E.done, E.stream);
     E.inflight = true;
@@ -908,9 +935,6 @@ void destroy_resources(grt_server *s)
 {
     for (grt::EpochSlot &E : s->ep) {
         if (E.stream) (void)hipStreamSynchronize(E.stream);
-        if (E.d_jobs) (void)hipFree(E.d_jobs);
-        if (E.d_chunks) (void)hipFree(E.d_chunks);
-        if (E.counters) (void)hipFree(E.counters);
         if (E.h_jobs) (void)hipHostFree(E.h_jobs);
         if (E.h_chunks) (void)hipHostFree(E.h_chunks);
         if (E.h_counters) (void)hipHostFree(E.h_counters);
@@ -919,14 +943,60 @@ void destroy_resources(grt_server *s)
         if (E.stream) (void)hipStreamDestroy(E.stream);
     }
     if (s->copy) (void)hipStreamSynchronize(s->copy);
-    if (s->copy_counters) (void)hipFree(s->copy_counters);
-    if (s->pool) (void)hipFree(s->pool);
     if (s->copy) (void)hipStreamDestroy(s->copy);
+}
+
+// The server's device memory, all in the caller's workspace: per epoch slot
+// the job table, the chunk table and the claim counters, the copy stream's
+// counters, then the request pool.
+struct ServerWS {
+    grt::RenderArgs *d_jobs[2];
+    grt::ServeChunk *d_chunks[2];
+    unsigned long long *counters[2];
+    unsigned long long *copy_counters;
+    char *pool;
+    size_t pool_bytes;
+    size_t bytes;
+};
+
+ServerWS carve_server(void *base, const grt_server_opts &o)
+{
+    ServerWS w{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *p = base ? (char *)base + off : nullptr;
+        off += grt::align256(bytes);
+        return p;
+    };
+    const int chunk_cap = o.max_jobs + 64;
+    for (int b = 0; b < 2; ++b) {
+        w.d_jobs[b] = (grt::RenderArgs *)take(sizeof(grt::RenderArgs) * (size_t)o.max_jobs);
+        w.d_chunks[b] = (grt::ServeChunk *)take(sizeof(grt::ServeChunk) * (size_t)chunk_cap);
+        w.counters[b] = (unsigned long long *)take(grt::kCounterBytes);
+    }
+    w.copy_counters = (unsigned long long *)take(grt::kCounterBytes);
+    w.pool_bytes = o.mem_budget & ~(size_t)255;
+    w.pool = take(w.pool_bytes);
+    w.bytes = off;
+    return w;
+}
+
+int check_opts(const grt_server_opts *opts)
+{
+    if (opts->max_jobs <= 0 || opts->max_jobs > 256) return sfail(GRT_ERR_INVALID, "max_jobs must be in 1..256");
+    if (opts->mem_budget < ((size_t)1 << 20)) return sfail(GRT_ERR_INVALID, "mem_budget below 1 MiB");
+    return GRT_OK;
 }
 
 }  // namespace
 
 extern "C" {
+
+size_t grt_server_workspace_bytes(const grt_server_opts *opts)
+{
+    if (!opts || opts->max_jobs <= 0 || opts->max_jobs > 256 || opts->mem_budget < ((size_t)1 << 20)) return 0;
+    return carve_server(nullptr, *opts).bytes;
+}
 
 size_t grt_server_job_bytes(const grt_job *job)
 {
@@ -938,8 +1008,11 @@ int grt_server_create(grt_ctx *ctx, const grt_scene *scene, const grt_server_opt
 {
     if (!ctx || !scene || !opts || !out) return sfail(GRT_ERR_INVALID, "NULL argument");
     *out = nullptr;
-    if (opts->max_jobs <= 0 || opts->max_jobs > 256) return sfail(GRT_ERR_INVALID, "max_jobs must be in 1..256");
-    if (opts->mem_budget < ((size_t)1 << 20)) return sfail(GRT_ERR_INVALID, "mem_budget below 1 MiB");
+    if (int rc = check_opts(opts)) return rc;
+    const ServerWS need = carve_server(nullptr, *opts);
+    if (!opts->workspace || opts->ws_bytes < need.bytes)
+        return sfail(GRT_ERR_OOM, "server workspace missing or below grt_server_workspace_bytes");
+    if (((uintptr_t)opts->workspace & 255u) != 0) return sfail(GRT_ERR_INVALID, "server workspace must be 256-byte aligned");
     if (!(opts->k == 4 || opts->k == 8 || opts->k == 12 || opts->k == 16))
         return sfail(GRT_ERR_INVALID, "server k must be 4, 8, 12 or 16");
     if (!(opts->t_min >= 0.0f) || !(opts->t_cut >= 0.0f && opts->t_cut < 1.0f))
@@ -959,14 +1032,16 @@ int grt_server_create(grt_ctx *ctx, const grt_scene *scene, const grt_server_opt
     // a request's rays may come back from stopped epochs in up to 8 ranges
     // per stop; an epoch takes as many as its table holds, the rest wait
     s->chunk_cap = opts->max_jobs + 64;
+    const ServerWS w = carve_server(opts->workspace, *opts);
+    s->pool = w.pool;
+    s->copy_counters = w.copy_counters;
     bool ok = hipSetDevice(ctx->device) == hipSuccess;
-    ok = ok && hipMalloc((void **)&s->pool, opts->mem_budget) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) == hipSuccess;
-    ok = ok && hipMalloc((void **)&s->copy_counters, grt::kCounterBytes) == hipSuccess;
-    for (grt::EpochSlot &E : s->ep) {
-        ok = ok && hipMalloc((void **)&E.d_jobs, sizeof(grt::RenderArgs) * opts->max_jobs) == hipSuccess;
-        ok = ok && hipMalloc((void **)&E.d_chunks, sizeof(grt::ServeChunk) * s->chunk_cap) == hipSuccess;
-        ok = ok && hipMalloc((void **)&E.counters, grt::kCounterBytes) == hipSuccess;
+    for (int b = 0; b < 2; ++b) {
+        grt::EpochSlot &E = s->ep[b];
+        E.d_jobs = w.d_jobs[b];
+        E.d_chunks = w.d_chunks[b];
+        E.counters = w.counters[b];
         ok = ok && hipHostMalloc((void **)&E.h_jobs, sizeof(grt::RenderArgs) * opts->max_jobs) == hipSuccess;
         ok = ok && hipHostMalloc((void **)&E.h_chunks, sizeof(grt::ServeChunk) * s->chunk_cap) == hipSuccess;
         ok = ok && hipHostMalloc((void **)&E.h_counters, grt::kCounterBytes) == hipSuccess;
@@ -979,9 +1054,9 @@ int grt_server_create(grt_ctx *ctx, const grt_scene *scene, const grt_server_opt
     if (!ok) {
         destroy_resources(s);
         delete s;
-        return sfail(GRT_ERR_OOM, "device allocation for the server failed");
+        return sfail(GRT_ERR_OOM, "host allocation for the server failed");
     }
-    s->alloc.init(opts->mem_budget & ~(size_t)255);
+    s->alloc.init(w.pool_bytes);
     for (int i = opts->max_jobs - 1; i >= 0; --i) s->free_slots.push_back(i);
     try {
         s->th = std::thread(scheduler, s);
@@ -998,9 +1073,9 @@ int grt_server_submit(grt_server *s, const grt_job *job, uint64_t *id)
 {
     if (!s || !id) return sfail(GRT_ERR_INVALID, "NULL argument");
     if (check_job(job) != GRT_OK) return sfail(GRT_ERR_INVALID, "malformed job");
-    if (job->camera_request && s->S.n > 0 &&
+    if ((job->camera_request || job->relight) && s->S.n > 0 &&
         (!s->opts.attrs.albedo || !s->opts.attrs.rough || !s->opts.attrs.metal))
-        return sfail(GRT_ERR_INVALID, "camera requests need the server's surfel attributes");
+        return sfail(GRT_ERR_INVALID, "camera and relighting requests need the server's surfel attributes");
     const size_t bytes = job_bytes(*job);
     if (bytes > (s->opts.mem_budget & ~(size_t)255)) return sfail(GRT_ERR_ADMISSION, "job exceeds the memory budget");
     std::lock_guard<std::mutex> lk(s->mu);
@@ -1009,6 +1084,7 @@ int grt_server_submit(grt_server *s, const grt_job *job, uint64_t *id)
     ServerJob &j = s->jobs[s->next_id];
     j.id = s->next_id++;
     j.spec = *job;
+    j.relight = job->relight != 0;
     j.bytes = bytes;
     j.npix = (int64_t)job->H * job->W;
     j.total = j.npix * (job->n_cos + job->n_ggx + job->n_env);

@@ -19,6 +19,7 @@
 
 #include "grt_internal.h"
 #include "grt_kernels.h"
+#include "grt_render.h"
 
 namespace grt {
 
@@ -65,9 +66,15 @@ struct TraceJob {
         a.out_rgb[3 * r] = v.C.x; a.out_rgb[3 * r + 1] = v.C.y; a.out_rgb[3 * r + 2] = v.C.z;
         a.out_T[r] = v.T;
         if (a.out_L) {
-            a.out_L[3 * r] = v.C.x + v.T * a.sky[0];
-            a.out_L[3 * r + 1] = v.C.y + v.T * a.sky[1];
-            a.out_L[3 * r + 2] = v.C.z + v.T * a.sky[2];
+            float3 Le = make_float3(a.sky[0], a.sky[1], a.sky[2]);
+            if (a.env_rgb) {  // L_env at the nearest texel of the direction (Eq. lighting_decompose)
+                EnvDev E{};
+                E.H = a.env_H; E.W = a.env_W; E.rgb = a.env_rgb;
+                Le = env_radiance(E, v3(a.d[3 * r], a.d[3 * r + 1], a.d[3 * r + 2]));
+            }
+            a.out_L[3 * r] = v.C.x + v.T * Le.x;
+            a.out_L[3 * r + 1] = v.C.y + v.T * Le.y;
+            a.out_L[3 * r + 2] = v.C.z + v.T * Le.z;
         }
         if (a.out_nhit) a.out_nhit[r] = v.cnt;
         if (a.stop_depth) a.stop_depth[r] = w.stop_depth();

@@ -43,7 +43,7 @@ class grt_surfels(C.Structure):
 
 class grt_scene_view(C.Structure):
     _fields_ = [("n", C.c_int64), ("records", VP), ("nodes", VP), ("order", VP), ("leaf_boxes", VP),
-                ("colours", VP), ("quats", VP)]
+                ("colours", VP), ("quats", VP), ("nodes4", VP), ("nodes4_count", VP)]
 
 
 class grt_rays(C.Structure):
@@ -53,7 +53,7 @@ class grt_rays(C.Structure):
 
 class grt_trace_opts(C.Structure):
     _fields_ = [("k", C.c_int), ("t_cut", C.c_float), ("sky", C.c_float * 3), ("hit_ids", VP), ("hit_tau", VP),
-                ("hit_cap", C.c_int), ("stop_depth", VP)]
+                ("hit_cap", C.c_int), ("stop_depth", VP), ("env", VP)]
 
 
 class grt_surfel_grads(C.Structure):
@@ -104,7 +104,8 @@ class grt_mis_opts(C.Structure):
 class grt_server_opts(C.Structure):
     _fields_ = [("mem_budget", C.c_size_t), ("max_jobs", C.c_int), ("epoch_rays", C.c_int64), ("k", C.c_int),
                 ("t_min", C.c_float), ("t_cut", C.c_float), ("slack_per_ray", C.c_double),
-                ("preempt_share", C.c_double), ("attrs", grt_surfel_attrs)]
+                ("preempt_share", C.c_double), ("attrs", grt_surfel_attrs), ("workspace", VP),
+                ("ws_bytes", C.c_size_t)]
 
 
 class grt_camera(C.Structure):
@@ -124,7 +125,7 @@ class grt_job(C.Structure):
                 ("metal", VP), ("valid", VP), ("env_rgb", VP), ("env_H", C.c_int), ("env_W", C.c_int),
                 ("n_cos", C.c_int), ("n_ggx", C.c_int), ("n_env", C.c_int), ("seed", C.c_uint64),
                 ("job", C.c_uint32), ("out_rgb", VP), ("camera_request", C.c_int), ("camera", grt_camera),
-                ("min_opacity", C.c_float)]
+                ("min_opacity", C.c_float), ("relight", C.c_int)]
 
 
 # every symbol include/grt.h declares, with (restype, argtypes)
@@ -178,6 +179,7 @@ SIGNATURES = {
                                           VP, C.c_size_t, VP]),
     "grt_render_hit_list_bytes": (C.c_size_t, [C.c_int64, C.c_int, C.c_int]),
     "grt_server_job_bytes": (C.c_size_t, [P(grt_job)]),
+    "grt_server_workspace_bytes": (C.c_size_t, [P(grt_server_opts)]),
     "grt_server_create": (C.c_int, [VP, VP, P(grt_server_opts), P(VP)]),
     "grt_server_submit": (C.c_int, [VP, P(grt_job), P(C.c_uint64)]),
     "grt_server_poll": (C.c_int, [VP, C.c_uint64, P(C.c_int)]),
@@ -435,7 +437,9 @@ class Scene:
     def arrays(self):
         """Torch views into the built scene: records [n,16], nodes [n-1,16]
         (float32; children as int32 in words 12-13), leaf boxes [n,6], order [n],
-        colours [n,4] (rgb, s_v) and stored quaternions [n,4], all in sorted order."""
+        colours [n,4] (rgb, s_v) and stored quaternions [n,4], all in sorted order;
+        nodes4 [n-1,32] (the 4-wide hierarchy: boxes as structure of arrays in
+        words 0-23, children as int32 in words 24-27) and nodes4_count [1]."""
         v = self.view()
         base = self.workspace.data_ptr()
 
@@ -449,7 +453,9 @@ class Scene:
                     leaf_boxes=sl(v.leaf_boxes, 6 * n, torch.float32).view(n, 6),
                     order=sl(v.order, n, torch.int32),
                     colours=sl(v.colours, 4 * n, torch.float32).view(n, 4),
-                    quats=sl(v.quats, 4 * n, torch.float32).view(n, 4))
+                    quats=sl(v.quats, 4 * n, torch.float32).view(n, 4),
+                    nodes4=sl(v.nodes4, 32 * max(n - 1, 0), torch.float32).view(max(n - 1, 0), 32),
+                    nodes4_count=sl(v.nodes4_count, 1, torch.int32))
 
     def __del__(self):
         if getattr(self, "handle", None) and _LIB is not None:
@@ -519,8 +525,9 @@ def make_rays(origins, dirs, t_min=0.0, t_max=float("inf")):
     return r
 
 
-def make_trace_opts(k=16, t_cut=1e-3, sky=(0.5, 0.5, 0.5), hit_ids=None, hit_tau=None, stop=None):
+def make_trace_opts(k=16, t_cut=1e-3, sky=(0.5, 0.5, 0.5), hit_ids=None, hit_tau=None, stop=None, env=None):
     o = grt_trace_opts()
+    o.env = env.handle if env is not None else None
     o.k = k
     o.t_cut = t_cut
     for i in range(3):
@@ -533,8 +540,9 @@ def make_trace_opts(k=16, t_cut=1e-3, sky=(0.5, 0.5, 0.5), hit_ids=None, hit_tau
 
 
 def trace(scene: Scene, origins, dirs, t_min=0.0, t_max=float("inf"), k=16, t_cut=1e-3, sky=(0.5, 0.5, 0.5),
-          dump_cap=0, save_stop=False, stream=None):
+          dump_cap=0, save_stop=False, stream=None, env=None):
     """Trace every ray; returns dict of rgb [R,3], T [R], L [R,3], nhit [R]
+    (L = rgb + T sky, or rgb + T L_env(d) under a built Env ``env``)
     (and ids/tau [R,dump_cap] when dump_cap > 0; with ``save_stop`` also
     stop [R], the depth of each ray's last composited hit, which
     trace_backward takes to bound its re-traversal)."""
@@ -550,7 +558,7 @@ def trace(scene: Scene, origins, dirs, t_min=0.0, t_max=float("inf"), k=16, t_cu
     if save_stop:
         out["stop"] = torch.empty(R, device=dev)
     rays = make_rays(origins, dirs, t_min, t_max)
-    opts = make_trace_opts(k, t_cut, sky, ids, tau, out.get("stop"))
+    opts = make_trace_opts(k, t_cut, sky, ids, tau, out.get("stop"), env)
     ws = _workspace(grt_trace_workspace_bytes(R), dev)
     grt_trace(scene.handle, rays, opts, out["rgb"], out["T"], out["L"], out["nhit"], ws, stream)
     return out
@@ -998,18 +1006,25 @@ def grt_server_job_bytes(job: grt_job) -> int:
     return int(load_library().grt_server_job_bytes(C.byref(job)))
 
 
+def grt_server_workspace_bytes(opts: grt_server_opts) -> int:
+    return int(load_library().grt_server_workspace_bytes(C.byref(opts)))
+
+
 class Request:
-    """A relighting request over host tensors (pinned when ``pin``), kept
-    alive until the server is done with it.  ``gb`` is a host G-buffer, or
-    ``camera`` (a grt_camera, with H and W) asks the server to trace the
-    G-buffer itself, coverage at ``min_opacity``."""
+    """A relighting request, kept alive until the server is done with it.
+    Inputs are host tensors (pinned when ``pin``) or, given as device
+    tensors, used in place.  ``gb`` is a G-buffer, or ``camera`` (a
+    grt_camera, with H and W) asks the server to trace the G-buffer itself,
+    coverage at ``min_opacity``.  ``relight``: split-sum relighting of the
+    server's surfel materials (Eq. relight_splitsum) instead of the radiance
+    estimator.  ``out_device``: the image is written to a device tensor."""
 
     def __init__(self, gb, env_rgb, split=(16, 8, 8), seed=0, job=0, pin=True, camera=None, H=None, W=None,
-                 min_opacity=0.5):
+                 min_opacity=0.5, relight=False, out_device=None):
         def host(a):
             t = torch.from_numpy(a) if not isinstance(a, torch.Tensor) else a
             t = t.contiguous()
-            return t.pin_memory() if pin else t
+            return t.pin_memory() if pin and not t.is_cuda else t
         self.env = host(env_rgb)
         if camera is None:
             self.arrays = [host(a) for a in (gb.x, gb.n, gb.wo, gb.albedo, gb.rough, gb.metal, gb.valid)]
@@ -1017,9 +1032,12 @@ class Request:
         else:
             self.arrays = [None] * 7
             self.H, self.W = int(H), int(W)
-        self.out = torch.zeros(self.H * self.W, 3)
-        if pin:
-            self.out = self.out.pin_memory()
+        if out_device is not None:
+            self.out = torch.zeros(self.H * self.W, 3, device=out_device)
+        else:
+            self.out = torch.zeros(self.H * self.W, 3)
+            if pin:
+                self.out = self.out.pin_memory()
         x, n, wo, alb, rough, metal, valid = self.arrays
         self.struct = grt_job(self.H, self.W, _ptr(x), _ptr(n), _ptr(wo), _ptr(alb), _ptr(rough), _ptr(metal),
                               _ptr(valid), _ptr(self.env), int(self.env.shape[0]), int(self.env.shape[1]),
@@ -1028,6 +1046,7 @@ class Request:
             self.struct.camera_request = 1
             self.struct.camera = camera
             self.struct.min_opacity = float(min_opacity)
+        self.struct.relight = 1 if relight else 0
         self.rays = self.H * self.W * sum(split)
 
 
@@ -1036,13 +1055,20 @@ class Server:
 
     def __init__(self, ctx: Context, scene: Scene, mem_budget: int, max_jobs: int = 16, epoch_rays: int = 0, k=8,
                  t_min=1e-3, t_cut=1e-3, slack_per_ray=-1.0, preempt_share=-1.0, attrs=None):
-        """attrs: (albedo, rough, metal) device tensors for camera requests,
-        kept alive with the server."""
+        """attrs: (albedo, rough, metal) device tensors for camera and
+        relighting requests, kept alive with the server.  The server's device
+        memory (pool and tables) is a torch tensor owned here."""
         self.ctx, self.scene = ctx, scene
         self.attrs = attrs
         at = grt_surfel_attrs(*(_ptr(a) for a in attrs)) if attrs is not None else grt_surfel_attrs()
         self.opts = grt_server_opts(int(mem_budget), int(max_jobs), int(epoch_rays), int(k), float(t_min),
                                     float(t_cut), float(slack_per_ray), float(preempt_share), at)
+        need = grt_server_workspace_bytes(self.opts)
+        if need == 0:
+            raise GrtError(ERR_INVALID, "bad server options")
+        self.workspace = _workspace(need, ctx.device)
+        self.opts.workspace = _ptr(self.workspace)
+        self.opts.ws_bytes = self.workspace.numel()
         self.handle = grt_server_create(ctx.handle, scene.handle, self.opts)
         self.requests = {}
 

@@ -274,3 +274,99 @@ def test_single_pixel_camera_request(setup):
     assert srv.wait(srv.submit(r)) == 0
     np.testing.assert_array_equal(r.out.numpy(), want)
     srv.close()
+
+
+def direct_relight(grt, ctx, scene, mats, gb, env, split, seed, job):
+    from gpu_util import t
+    E = grt.Env(ctx, t(env)).prefilter()
+    G = grt.GBuffer.from_numpy(gb, torch.device("cuda", 0))
+    out = grt.render_relight(scene, E, *mats, G, split=split, seed=seed, job=job, k=8)["rgb"].cpu().numpy()
+    torch.cuda.synchronize()
+    return out
+
+
+KINDS = [True, False, True, True, False, True]
+
+
+def test_relight_requests_alone_and_mixed(setup):
+    """Relighting requests (the attribute query and Eq. relight_splitsum)
+    served alone and mixed with radiance requests: each image equals the
+    direct grt_render_relight / grt_render_mis bit for bit."""
+    grt, ctx, scene = setup
+    from gpu_util import t
+    mats = [t(a) for a in W.surfel_materials(scene.n, seed=2)]
+    reqs = requests(6, seed=5)
+    ref = [direct_relight(grt, ctx, scene, mats, *q) if rl else direct(grt, ctx, scene, *q)
+           for q, rl in zip(reqs, KINDS)]
+    srv = grt.Server(ctx, scene, mem_budget=1 << 30, max_jobs=8, epoch_rays=1 << 16, attrs=mats)
+    for (gb, env, split, seed, job), rl, want in zip(reqs, KINDS, ref):
+        r = grt.Request(gb, env, split, seed, job, relight=rl)
+        assert srv.wait(srv.submit(r)) == 0
+        np.testing.assert_array_equal(r.out.numpy(), want)
+    rs = [grt.Request(gb, env, split, seed, job, relight=rl) for (gb, env, split, seed, job), rl in zip(reqs, KINDS)]
+    ids = [srv.submit(r) for r in rs]
+    for jid, r, want in zip(ids, rs, ref):
+        assert srv.wait(jid) == 0
+        np.testing.assert_array_equal(r.out.numpy(), want)
+    st = srv.stats()
+    srv.close()
+    assert st["pool_free"] == (1 << 30)
+
+
+def test_mixed_run_against_the_oracle(setup):
+    """Sampled pixels of a mixed run (relighting and radiance requests) match
+    the oracle's relit and radiance estimators at 1e-4 / 1e-5."""
+    grt, ctx, scene = setup
+    from gpu_util import t
+    from oracle import oracle as O
+    s = W.scene1(n=40000, seed=3, s_lo=0.005, s_hi=0.03)
+    at = W.surfel_materials(s.n, seed=2)
+    mats = [t(a) for a in at]
+    reqs = requests(4, seed=6)
+    kinds = [True, False, True, False]
+    srv = grt.Server(ctx, scene, mem_budget=1 << 30, max_jobs=8, epoch_rays=1 << 16, attrs=mats)
+    rs = [grt.Request(gb, env, split, seed, job, relight=rl) for (gb, env, split, seed, job), rl in zip(reqs, kinds)]
+    ids = [srv.submit(r) for r in rs]
+    for jid in ids:
+        assert srv.wait(jid) == 0
+    srv.close()
+    checked = 0
+    for (gb, env, split, seed, job), rl, r in zip(reqs, kinds, rs):
+        valid = np.nonzero(gb.valid)[0]
+        pix = np.sort(np.random.default_rng(job).choice(valid, 10, replace=False))
+        if rl:
+            ref = O.render_relight(s, at, gb, env, split, seed, pix=pix, job=job, dump=True)
+        else:
+            ref = O.render_mis(s, gb, env, split, seed, pix=pix, job=job, dump=True)
+        m = ref["margins"]
+        clean = ~((m[..., 3] < 1e-5) | (m[..., 4] < 1e-9)).any(axis=1)
+        got = r.out.numpy()[pix]
+        np.testing.assert_allclose(got[clean], ref["rgb"][clean], rtol=1e-4, atol=1e-5)
+        checked += int(clean.sum())
+    assert checked >= 32
+
+
+def test_device_memory_requests_and_workspace(setup):
+    """Inputs and output in device memory; the server's own device memory is
+    the caller's workspace, and a short one is refused."""
+    grt, ctx, scene = setup
+    from types import SimpleNamespace
+    from gpu_util import t
+    gb, env, split, seed, job = requests(1, seed=7)[0]
+    want = direct(grt, ctx, scene, gb, env, split, seed, job)
+    dgb = SimpleNamespace(H=gb.H, W=gb.W, x=t(gb.x), n=t(gb.n), wo=t(gb.wo), albedo=t(gb.albedo),
+                          rough=t(gb.rough), metal=t(gb.metal), valid=t(gb.valid))
+    srv = grt.Server(ctx, scene, mem_budget=1 << 28, max_jobs=2)
+    r = grt.Request(dgb, t(env), split, seed, job, out_device=torch.device("cuda", 0))
+    assert srv.wait(srv.submit(r)) == 0
+    np.testing.assert_array_equal(r.out.cpu().numpy(), want)
+    srv.close()
+    opts = grt.grt_server_opts(1 << 28, 2, 0, 8, 1e-3, 1e-3, -1.0, -1.0, grt.grt_surfel_attrs())
+    need = grt.grt_server_workspace_bytes(opts)
+    assert need > (1 << 28)
+    ws = torch.empty(need - 256, dtype=torch.uint8, device="cuda")
+    opts.workspace = ws.data_ptr()
+    opts.ws_bytes = ws.numel()
+    with pytest.raises(grt.GrtError) as ei:
+        grt.grt_server_create(ctx.handle, scene.handle, opts)
+    assert ei.value.code == grt.ERR_OOM

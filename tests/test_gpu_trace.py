@@ -202,3 +202,70 @@ def test_negative_per_ray_t_min_is_zero(grt_ctx):
         np.testing.assert_array_equal(a[k].cpu().numpy(), b[k].cpu().numpy())
     ref = O.trace(s, r.origins, r.dirs, t_min=tm, t_max=np.full(r.n, np.inf, np.float32), cap=32)
     compare({kk: v.cpu().numpy() for kk, v in b.items()}, ref, 32)
+
+
+def test_trace_under_an_environment(grt_ctx):
+    """grt_trace_opts.env: L = c_rt + T L_env(d) against the oracle."""
+    grt, ctx = grt_ctx
+    from gpu_util import t, scene_tensors
+    s = W.scene0(); r = W.rays0()
+    env = W.envmap(64, 128, seed=6)
+    scene = grt.Scene(ctx, *scene_tensors(s))
+    E = grt.Env(ctx, t(env))
+    out = grt.trace(scene, t(r.origins), t(r.dirs), env=E)
+    torch.cuda.synchronize()
+    ref = O.trace(s, r.origins, r.dirs)
+    L = O.trace_env(s, r.origins, r.dirs, env)
+    ok = ref["margins"][:, 3] >= 1e-5
+    np.testing.assert_allclose(out["L"].cpu().numpy()[ok], L[ok], rtol=RTOL, atol=ATOL)
+    np.testing.assert_allclose(out["T"].cpu().numpy()[ok], ref["T"][ok], rtol=RTOL, atol=ATOL)
+    assert ok.mean() > 0.999
+
+
+@pytest.mark.parametrize("n", [2, 3, 5, 257, 20000])
+def test_wide_bvh_structure(grt_ctx, n):
+    """The 4-wide hierarchy the traversal walks: every node has 2..4
+    children, every leaf is reached exactly once, every node is used once,
+    and each child box is exactly the union of its subtree's leaf boxes (the
+    binary LBVH's boxes, regrouped)."""
+    grt, ctx = grt_ctx
+    from gpu_util import scene_tensors
+    s = W.scene1(n=max(n, 2), seed=1).subset(np.arange(n))
+    scene = grt.Scene(ctx, *scene_tensors(s))
+    torch.cuda.synchronize()
+    arr = {k: v.cpu().numpy() for k, v in scene.arrays().items()}
+    lb, n4 = arr["leaf_boxes"], int(arr["nodes4_count"][0])
+    nd4 = arr["nodes4"][:n4]
+    assert 1 <= n4 <= n - 1
+    boxes = nd4[:, :24].reshape(n4, 6, 4)  # [node, lo.x..hi.z, child]
+    ch = nd4[:, 24:28].view(np.int32)
+    cnt = nd4[:, 28].view(np.int32)
+    seen_leaf = np.zeros(n, bool)
+    seen_node = np.zeros(n4, bool)
+
+    def walk(i):
+        assert not seen_node[i]
+        seen_node[i] = True
+        assert 2 <= cnt[i] <= 4
+        lo = np.full(3, np.inf, np.float32); hi = np.full(3, -np.inf, np.float32)
+        for j in range(4):
+            c = ch[i, j]
+            if j >= cnt[i]:
+                assert c == 0x7fffffff
+                continue
+            if c < 0:
+                p = -c - 1
+                assert not seen_leaf[p]
+                seen_leaf[p] = True
+                sub_lo, sub_hi = lb[p, :3], lb[p, 3:]
+            else:
+                sub_lo, sub_hi = walk(c)
+            np.testing.assert_array_equal(boxes[i, :3, j], sub_lo)
+            np.testing.assert_array_equal(boxes[i, 3:, j], sub_hi)
+            lo = np.minimum(lo, sub_lo); hi = np.maximum(hi, sub_hi)
+        return lo, hi
+
+    import sys
+    sys.setrecursionlimit(10000)
+    walk(0)
+    assert seen_leaf.all() and seen_node.all()

@@ -211,3 +211,22 @@ def test_negative_per_ray_t_min_is_zero():
         np.testing.assert_array_equal(got[k], base[k])
     # and the same rays with the origins moved back: now hits behind count
     assert (O.trace(s, r.origins - 0.5 * r.dirs, r.dirs, t_min=0.0)["nhit"] >= base["nhit"]).all()
+
+
+def test_trace_under_an_environment():
+    """L = c_rt + T L_env(d) (Sec. 3.3 Eq. lighting_decompose): a constant
+    environment gives the constant-sky trace, an empty scene gives the
+    environment at the ray direction's texel, and any map gives C + T L_env
+    from the trace's own C and T."""
+    s = W.scene0(n=1500, seed=9)
+    r = W.rays0(res=10, per=4, seed=9)
+    const = np.full((8, 16, 3), 0.25, np.float32)
+    np.testing.assert_allclose(O.trace_env(s, r.origins, r.dirs, const),
+                               O.trace(s, r.origins, r.dirs, sky=(0.25, 0.25, 0.25))["L"], rtol=1e-15, atol=0)
+    env = W.envmap(16, 32, seed=2)
+    z = lambda *sh: np.zeros(sh, np.float32)
+    empty = W.Surfels(z(0, 3), z(0, 2), z(0, 4), z(0), z(0, 3))
+    np.testing.assert_array_equal(O.trace_env(empty, r.origins, r.dirs, env), O.env_lookup(env, r.dirs))
+    tr = O.trace(s, r.origins, r.dirs)
+    want = tr["C"] + tr["T"][:, None] * O.env_lookup(env, r.dirs)
+    np.testing.assert_allclose(O.trace_env(s, r.origins, r.dirs, env), want, rtol=1e-15, atol=1e-15)
