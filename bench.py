@@ -10,7 +10,13 @@ floor of a 4x3x4 room, 300k on 10 spheres and 10 boxes), a 1024x1024
 G-buffer from a camera inside the room, 32 samples per pixel split 16/8/8
 (cosine / GGX / environment) against a 256x512 environment map.
 
-Prints ONE JSON line.  Mrays/s counts rays as valid pixels x spp.
+Beside the headline the line carries the other measured workloads: the plain
+trace of 4,096 surfels, the 300k-surfel forward and its differentiable step
+(re-traversal against stored hit lists), split-sum relighting of the room,
+and the relighting server against one launch per request.
+
+Prints ONE JSON line.  Mrays/s counts rays as valid pixels x spp (or rays,
+for the plain trace).
 """
 from __future__ import annotations
 
@@ -18,6 +24,7 @@ import argparse
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -26,10 +33,11 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-WORKCOUNT = os.path.join(ROOT, "profiles", "workcount_room1m_1024px_32spp.json")
-TRAFFIC = os.path.join(ROOT, "profiles", "traffic_room1m_1024px_32spp.json")
+PROFILES = os.path.join(ROOT, "profiles")
+WORKCOUNT = {name: os.path.join(PROFILES, f"workcount_{name}.json")
+             for name in ("room1m_1024px_32spp", "shapes300k_800px_32spp", "plain4k_32768rays")}
+TRAFFIC = os.path.join(PROFILES, "traffic_room1m_1024px_32spp.json")
 CSRC = os.path.join(ROOT, "paper_2607_22780_amd", "csrc")
-
 
 # the sources the render kernels are built from
 KERNEL_SOURCES = ("render.hip", "grt_device.h", "grt_kernels.h", "grt_render.h", "grt_internal.h")
@@ -44,10 +52,13 @@ def source_hash():
         h.update(name.encode())
         h.update(open(os.path.join(CSRC, name), "rb").read())
     return h.hexdigest()[:16]
+
+
 SPLIT = (16, 8, 8)
 SEED = 7
 HBM_PEAK_GBS = 8000.0
 RES = 1024
+WORK_RAYS = 65536  # sampled rays per work count (2,048 pixels x 32 spp)
 
 
 def log(msg):
@@ -62,66 +73,249 @@ def make_inputs():
     return s, gb, env
 
 
-def count_work(nsample_px: int = 256):
-    """Per-ray algorithmic work (N_node, N_cand, N_hit) of the room workload,
-    counted by the oracle on a reference LBVH over a seeded pixel sample,
-    written to profiles/ for the roofline (measurement infrastructure)."""
+def shapes_inputs():
+    from paper_2607_22780_amd import workloads as W
+    return W.scene1(), W.gbuffer1(), W.envmap()
+
+
+# --------------------------------------------------------------------------
+# Algorithmic work per ray (the oracle's reference LBVH), for the rooflines
+# --------------------------------------------------------------------------
+
+def _count_render(name, s, gb, env, npx):
     from oracle import oracle as O
-    s, gb, env = make_inputs()
     valid = np.nonzero(gb.valid)[0]
-    pix = np.sort(np.random.default_rng(1).choice(valid, nsample_px, replace=False))
+    pix = np.sort(np.random.default_rng(1).choice(valid, npx, replace=False))
     t0 = time.time()
     d = O.render_mis(s, gb, env, SPLIT, SEED, pix=pix, dump=True)
     tr = d["traced"].astype(bool)
     org = np.repeat(gb.x[pix][:, None, :], sum(SPLIT), axis=1)[tr]
-    dirs = d["dir"][tr]
-    nc, nn, nh = O.count_work(s, org.astype(np.float32), dirs.astype(np.float32), t_min=1e-3)
-    spp = sum(SPLIT)
-    out = dict(workload="room 1M surfels, 1024x1024 G-buffer, 32 spp (16/8/8), 256x512 env",
-               sample_pixels=int(nsample_px), sample_rays=int(nsample_px * spp), traced_rays=int(tr.sum()),
-               traced_fraction=float(tr.mean()), mean_n_node=float(nn.mean()), mean_n_cand=float(nc.mean()),
-               mean_n_hit=float(nh.mean()), seconds=time.time() - t0)
-    os.makedirs(os.path.dirname(WORKCOUNT), exist_ok=True)
-    with open(WORKCOUNT, "w") as f:
-        json.dump(out, f, indent=1)
+    nc, nn, nh = O.count_work(s, org.astype(np.float32), d["dir"][tr].astype(np.float32), t_min=1e-3)
+    return dict(sample_pixels=int(npx), sample_rays=int(npx * sum(SPLIT)), traced_rays=int(tr.sum()),
+                traced_fraction=float(tr.mean()), mean_n_node=float(nn.mean()), mean_n_cand=float(nc.mean()),
+                mean_n_hit=float(nh.mean()), seconds=round(time.time() - t0, 1))
+
+
+def count_work():
+    """Per-ray algorithmic work (N_node, N_cand, N_hit) of each workload,
+    counted by the oracle on its reference LBVH over 65,536 seeded sample
+    rays (all 32,768 rays of the plain trace), written to profiles/
+    (measurement infrastructure)."""
+    from oracle import oracle as O
+    from paper_2607_22780_amd import workloads as W
+    out = {}
+    s0, r0 = W.scene0(), W.rays0()
+    t0 = time.time()
+    nc, nn, nh = O.count_work(s0, r0.origins, r0.dirs, t_min=0.0)
+    out["plain4k_32768rays"] = dict(workload="plain trace, 4,096 surfels, 32,768 rays", sample_rays=int(r0.n),
+                                    traced_rays=int(r0.n), traced_fraction=1.0, mean_n_node=float(nn.mean()),
+                                    mean_n_cand=float(nc.mean()), mean_n_hit=float(nh.mean()),
+                                    seconds=round(time.time() - t0, 1))
+    npx = WORK_RAYS // sum(SPLIT)
+    s1, g1, e1 = shapes_inputs()
+    out["shapes300k_800px_32spp"] = dict(workload="shapes, 300k surfels, 800x800 G-buffer, 32 spp (16/8/8), "
+                                                  "256x512 env", **_count_render("shapes", s1, g1, e1, npx))
+    s3, g3, e3 = make_inputs()
+    out["room1m_1024px_32spp"] = dict(workload="room 1M surfels, 1024x1024 G-buffer, 32 spp (16/8/8), 256x512 env",
+                                      **_count_render("room", s3, g3, e3, npx))
+    os.makedirs(PROFILES, exist_ok=True)
+    for name, d in out.items():
+        with open(WORKCOUNT[name], "w") as f:
+            json.dump(d, f, indent=1)
     return out
+
+
+def load_work(name):
+    p = WORKCOUNT[name]
+    return json.load(open(p)) if os.path.exists(p) else None
+
+
+def trace_bytes(wc):
+    """Algorithmic bytes of one traced ray: the ray (32), its output (16), one
+    64-byte line per reference-LBVH node and per candidate surfel."""
+    return 32 + 16 + 64 * wc["mean_n_node"] + 64 * wc["mean_n_cand"]
 
 
 def bytes_per_ray(wc, env_hw=(256, 512)):
     """Algorithmic bytes per sample ray (forward and backward), from the counts."""
     spp = sum(SPLIT)
     tf = wc["traced_fraction"]
-    trace_fwd = 32 + 16 + 64 * wc["mean_n_node"] + 64 * wc["mean_n_cand"]
     env_lookup = 12 + (SPLIT[2] / spp) * 4 * (math.log2(env_hw[0]) + math.log2(env_hw[1]))
     shade = (56 + 12) / spp + env_lookup
-    fwd = shade + tf * (trace_fwd + 16)            # + 16 B saved per traced ray
-    bwd = shade + 12 / spp + tf * (trace_fwd + 16 + 52 * wc["mean_n_hit"])
+    fwd = shade + tf * (trace_bytes(wc) + 16)            # + 16 B saved per traced ray
+    bwd = shade + 12 / spp + tf * (trace_bytes(wc) + 16 + 52 * wc["mean_n_hit"])
     return fwd, bwd
 
 
-def cpu_baseline(s, gb, env, npx: int = 384):
-    """The oracle (brute force, OpenMP) on a bounded sample of the same step."""
+def roofline(bytes_per, units, ms):
+    achieved = bytes_per * units / (ms * 1e-3) / 1e9
+    return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(achieved / HBM_PEAK_GBS, 4), bytes_per_unit=round(bytes_per, 1), kernel_ms=round(ms, 3))
+
+
+# --------------------------------------------------------------------------
+# The oracle on the host
+# --------------------------------------------------------------------------
+
+def cpu_model():
+    """The host CPU as lscpu reports it: the model name (a virtual machine
+    may shorten it) with the family/model/stepping, the logical CPUs and the
+    clock, so that the identification does not rest on the name alone."""
+    keys = {"Model name": "model_name", "Vendor ID": "vendor", "CPU family": "family", "Model": "model",
+            "Stepping": "stepping", "CPU(s)": "cpus", "Thread(s) per core": "threads_per_core",
+            "Socket(s)": "sockets", "CPU max MHz": "max_mhz", "L3 cache": "l3"}
+    info = {}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            k, _, v = ln.partition(":")
+            if k.strip() in keys and v.strip():
+                info[keys[k.strip()]] = v.strip()
+    except Exception:
+        pass
+    if "model_name" not in info:
+        try:
+            with open("/proc/cpuinfo") as f:
+                name = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
+            if name:
+                info["model_name"] = name
+        except OSError:
+            pass
+    return info or None
+
+
+def cpu_baseline(s, gb, env, npx: int = 192, runs: int = 3):
+    """The oracle (brute force, OpenMP) on a bounded sample of the same step,
+    forward + backward, median of `runs` runs."""
     from oracle import oracle as O
     valid = np.nonzero(gb.valid)[0]
     pix = np.sort(np.random.default_rng(2).choice(valid, npx, replace=False))
     grad = np.random.default_rng(3).normal(0, 1, (npx, 3))
     O.lib()
-    t0 = time.time()
-    O.render_mis(s, gb, env, SPLIT, SEED, pix=pix)
-    t1 = time.time()
-    O.render_mis_backward(s, gb, env, SPLIT, SEED, grad, pix=pix)
-    t2 = time.time()
+    fw, bw = [], []
+    for _ in range(runs):
+        t0 = time.time()
+        O.render_mis(s, gb, env, SPLIT, SEED, pix=pix)
+        t1 = time.time()
+        O.render_mis_backward(s, gb, env, SPLIT, SEED, grad, pix=pix)
+        t2 = time.time()
+        fw.append(t1 - t0)
+        bw.append(t2 - t1)
+    f, b = float(np.median(fw)), float(np.median(bw))
     rays = npx * sum(SPLIT)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    model = None
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), None)
-    except OSError:
-        pass
-    return dict(value=rays / (t2 - t0) / 1e6, unit="Mrays/s", cores=cores, kind="oracle", cpu=model,
-                sample=f"{npx} valid pixels x {sum(SPLIT)} spp ({rays} rays) of the same step, forward "
-                       f"{t1 - t0:.2f}s + backward {t2 - t1:.2f}s, scene/G-buffer generation excluded")
+    return dict(value=round(rays / (f + b) / 1e6, 6), unit="Mrays/s", cores=cores, kind="oracle", cpu=cpu_model(),
+                sample=f"{npx} valid pixels x {sum(SPLIT)} spp ({rays} rays) of the same step, forward + backward, "
+                       f"median of {runs} runs (forward {f:.2f}s, backward {b:.2f}s), scene/G-buffer generation "
+                       f"excluded")
+
+
+# --------------------------------------------------------------------------
+# Further workloads
+# --------------------------------------------------------------------------
+
+def _events(n):
+    import torch
+    return [torch.cuda.Event(enable_timing=True) for _ in range(n)]
+
+
+def _median_ms(fn, reps):
+    import torch
+    st = torch.cuda.current_stream()
+    e0, e1 = _events(2)
+    ts = []
+    for _ in range(reps):
+        e0.record(st)
+        fn()
+        e1.record(st)
+        torch.cuda.synchronize()
+        ts.append(e0.elapsed_time(e1))
+    return float(np.median(ts))
+
+
+def leg_plain(ctx, k):
+    """The plain trace: 4,096 surfels, 32,768 rays (grt_trace)."""
+    import torch
+    from paper_2607_22780_amd import grt
+    from paper_2607_22780_amd import workloads as W
+    dev = torch.device("cuda", 0)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    s, r = W.scene0(), W.rays0()
+    scene = grt.Scene(ctx, *(t(a) for a in s.arrays()))
+    o, d = t(r.origins), t(r.dirs)
+    grt.trace(scene, o, d, k=k)
+    build_ms = _median_ms(scene.build, 5)
+    ms = _median_ms(lambda: grt.trace(scene, o, d, k=k), 10)
+    out = dict(workload="4,096 surfels, 32,768 rays from 64x64 points, 8 hemisphere rays each",
+               build_ms=round(build_ms, 3), trace_ms=round(ms, 4), mrays_s=round(r.n / (ms * 1e-3) / 1e6, 1))
+    wc = load_work("plain4k_32768rays")
+    if wc:
+        out["roofline"] = roofline(trace_bytes(wc), r.n, ms)
+    return out
+
+
+def leg_shapes(ctx, k, k_bwd, hit_cap):
+    """The 300k-surfel scene at 800x800, 32 spp: the MIS forward, and the
+    differentiable step (loss against a target from perturbed radiance and
+    opacity) by re-traversal and from stored hit lists."""
+    import torch
+    from paper_2607_22780_amd import grt
+    from paper_2607_22780_amd import workloads as W
+    dev = torch.device("cuda", 0)
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    s, gb, env = shapes_inputs()
+    rays = int(gb.valid.sum()) * sum(SPLIT)
+    E = grt.Env(ctx, t(env))
+    G = grt.GBuffer.from_numpy(gb, dev)
+    tgt_scene = grt.Scene(ctx, *(t(a) for a in W.perturbed(s).arrays()))
+    target = grt.render_mis(tgt_scene, E, G, split=SPLIT, seed=SEED, k=k)["rgb"]
+    del tgt_scene
+    scene = grt.Scene(ctx, *(t(a) for a in s.arrays()))
+    build_ms = _median_ms(scene.build, 5)
+    state = {}
+
+    def fwd():
+        state["f"] = grt.render_mis(scene, E, G, split=SPLIT, seed=SEED, k=k, save=True)
+
+    def bwd():
+        up = 2.0 * (state["f"]["rgb"] - target)
+        grt.render_mis_backward(scene, E, G, up, state["f"]["saved"], split=SPLIT, seed=SEED, k=k_bwd)
+
+    fwd()
+    fwd_ms = _median_ms(fwd, 5)
+    bwd_ms = _median_ms(bwd, 5)
+    hits = grt.make_hit_list(gb.npix, sum(SPLIT), hit_cap, dev)
+
+    def fwd_s():
+        state["f"] = grt.render_mis(scene, E, G, split=SPLIT, seed=SEED, k=k, save=True, hits=hits, hit_cap=hit_cap)
+
+    def bwd_s():
+        up = 2.0 * (state["f"]["rgb"] - target)
+        grt.render_mis_backward(scene, E, G, up, state["f"]["saved"], split=SPLIT, seed=SEED, k=k_bwd, hits=hits,
+                                hit_cap=hit_cap)
+
+    fwd_s()
+    sf_ms = _median_ms(fwd_s, 3)
+    sb_ms = _median_ms(bwd_s, 3)
+    cnt = hits[:gb.npix * sum(SPLIT)].cpu().numpy()
+    out = dict(workload="300k surfels on 3 spheres + 2 tori, 800x800 G-buffer, 32 spp (16/8/8), 256x512 env",
+               rays=rays, build_ms=round(build_ms, 3), fwd_ms=round(fwd_ms, 3),
+               fwd_mrays_s=round(rays / (fwd_ms * 1e-3) / 1e6, 1),
+               step={"loss": "L2 against perturbed radiance and opacity (sigma 0.05)",
+                     "retrace": {"fwd_ms": round(fwd_ms, 3), "bwd_ms": round(bwd_ms, 3),
+                                 "mrays_s": round(rays / ((fwd_ms + bwd_ms) * 1e-3) / 1e6, 1)},
+                     "stored": {"hit_cap": hit_cap, "list_gb": round(hits.numel() * 4 / 1e9, 3),
+                                "overflow_frac": round(float((cnt > hit_cap).mean()), 5),
+                                "fwd_ms": round(sf_ms, 3), "bwd_ms": round(sb_ms, 3),
+                                "mrays_s": round(rays / ((sf_ms + sb_ms) * 1e-3) / 1e6, 1)},
+                     "saved_state_gb": round(grt.grt_render_saved_bytes(gb.npix, sum(SPLIT)) / 1e9, 3)})
+    wc = load_work("shapes300k_800px_32spp")
+    if wc:
+        bf, bb = bytes_per_ray(wc)
+        out["roofline_fwd"] = roofline(bf, rays, fwd_ms)
+        out["roofline_bwd"] = roofline(bb, rays, bwd_ms)
+    del hits, state
+    return out
 
 
 def _gbuffer_task(key):
@@ -143,38 +337,34 @@ def serve_inputs(n, rate):
     return reqs, gbs, envs
 
 
-def serve_leg(ctx, scene, k, reqs, gbs, envs, slack=-1.0, epoch=0, detail=False, share=-1.0):
-    """The persistent batched server versus one launch per request (upload,
-    table build, render, copy back, in arrival order), on the same requests
-    replayed at their arrival times and then all at once."""
+def serve_leg(ctx, scene, k, reqs, gbs, envs, warm, slack=-1.0, epoch=0, extra=False):
+    """The persistent batched server against one launch per request (upload,
+    tables, render, copy back, in arrival order), on the same relighting
+    requests (the attribute query and split-sum shading under each request's
+    own environment) replayed at their arrival times and then all at once.
+    The first `warm` requests of each run warm the system and are left out of
+    the latency statistics."""
     import torch
     from paper_2607_22780_amd import grt
     from paper_2607_22780_amd import workloads as W
-    dev = torch.device("cuda", 0)
     from types import SimpleNamespace
+    dev = torch.device("cuda", 0)
     splits = [W.mis_split(q.spp) for q in reqs]
     pin = lambda a: torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
     pinned = {key: SimpleNamespace(H=g.H, W=g.W, x=pin(g.x), n=pin(g.n), wo=pin(g.wo), albedo=pin(g.albedo),
                                    rough=pin(g.rough), metal=pin(g.metal), valid=pin(g.valid))
               for key, g in gbs.items()}
-    mk = lambda: [grt.Request(pinned[(q.res, q.cam)], pin(envs[i]), splits[i], q.seed, q.rid)
+    mats = [torch.from_numpy(a).to(dev) for a in W.surfel_materials(scene.n, seed=0)]
+    mk = lambda: [grt.Request(pinned[(q.res, q.cam)], pin(envs[i]), splits[i], q.seed, q.rid, relight=True)
                   for i, q in enumerate(reqs)]
     req_srv, req_one = mk(), mk()
-    rays = sum(r.rays for r in req_srv)
-    # the same requests as cameras: the server traces each G-buffer itself
-    # (2DGRT primary rays with the surfels' materials) and uploads only the
-    # environment
-    cams = {q.cam: grt.make_camera(*W.camera3(W.rng(3, 10 + q.cam)), 60.0) for q in reqs}
-    mats = [torch.from_numpy(a).to(dev) for a in W.surfel_materials(scene.n, seed=0)]
-    req_cam = [grt.Request(None, pin(envs[i]), splits[i], q.seed, q.rid, camera=cams[q.cam], H=q.res, W=q.res)
-               for i, q in enumerate(reqs)]
+    measured = slice(warm, len(reqs))
+    rays_m = sum(r.rays for r in req_srv[measured])
 
-    def run_server(replay, share=share, rlist=None):
+    def run_server(replay, share=-1.0, rlist=None):
         rlist = req_srv if rlist is None else rlist
         srv = grt.Server(ctx, scene, mem_budget=48 << 30, max_jobs=16, k=k, slack_per_ray=slack, epoch_rays=epoch,
                          preempt_share=share, attrs=mats)
-        warm = grt.Request(pinned[(reqs[0].res, reqs[0].cam)], pin(envs[0]), (1, 1, 1), 1, 1)
-        srv.wait(srv.submit(warm))
         t0 = time.perf_counter()
         ids = []
         for q, r in zip(reqs, rlist):
@@ -188,16 +378,16 @@ def serve_leg(ctx, scene, k, reqs, gbs, envs, slack=-1.0, epoch=0, detail=False,
             if st != 0:
                 raise grt.GrtError(st, "server request failed")
         times = [srv.times(j) for j in ids]
-        lat = [d - s for s, _, d in times]
-        span = max(d for _, _, d in times) - min(s for s, _, _ in times)
-        stats = srv.stats()
         srv.close()
-        return lat, span, stats
+        lat = [d - s for s, _, d in times][measured]
+        tm = times[measured]
+        span = max(d for _, _, d in tm) - min(s for s, _, _ in tm)
+        return lat, span
 
     def run_one(replay):
         stream = torch.cuda.current_stream()
         t0 = time.perf_counter()
-        lat = []
+        lat, marks = [], []
         for q, r in zip(reqs, req_one):
             if replay:
                 dt = t0 + q.arrival_s - time.perf_counter()
@@ -206,58 +396,64 @@ def serve_leg(ctx, scene, k, reqs, gbs, envs, slack=-1.0, epoch=0, detail=False,
             arrive = t0 + q.arrival_s if replay else t0
             x, n, wo, alb, rough, metal, valid = (a.to(dev, non_blocking=True) for a in r.arrays)
             G = grt.GBuffer(r.H, r.W, x, n, wo, alb, rough, metal, valid)
-            E = grt.Env(ctx, r.env.to(dev, non_blocking=True))
+            E = grt.Env(ctx, r.env.to(dev, non_blocking=True)).prefilter()
             sp = (r.struct.n_cos, r.struct.n_ggx, r.struct.n_env)
-            out = grt.render_mis(scene, E, G, split=sp, seed=r.struct.seed, job=r.struct.job, k=k)["rgb"]
+            out = grt.render_relight(scene, E, *mats, G, split=sp, seed=r.struct.seed, job=r.struct.job, k=k)["rgb"]
             r.out.copy_(out, non_blocking=True)
             stream.synchronize()
-            lat.append(time.perf_counter() - arrive)
+            done = time.perf_counter()
+            lat.append(done - arrive)
+            marks.append((arrive, done))
             del E
-        return lat, time.perf_counter() - t0
+        tm = marks[measured]
+        return lat[measured], max(d for _, d in tm) - min(a for a, _ in tm)
 
     pct = lambda a, p: float(np.percentile(np.asarray(a), p))
-    res = {}
+    summary = lambda lat, span: {"p50_s": round(pct(lat, 50), 4), "p99_s": round(pct(lat, 99), 4),
+                                 "mean_s": round(float(np.mean(lat)), 4), "mrays_s": round(rays_m / span / 1e6, 2)}
     log("bench: server leg (replayed arrivals)")
-    lat_s, span_s, st = run_server(True)
+    s_rep = run_server(True)
     log("bench: per-request leg (replayed arrivals)")
-    lat_o, span_o = run_one(True)
+    o_rep = run_one(True)
     same = all(torch.equal(a.out, b.out) for a, b in zip(req_srv, req_one))
     log("bench: server leg (all at once)")
-    blat_s, burst_s, bst = run_server(False)
+    s_bur = run_server(False)
     log("bench: per-request leg (all at once)")
-    blat_o, burst_o = run_one(False)
-    log("bench: server leg with preemption (replayed arrivals)")
-    plat_s, pspan_s, pst = run_server(True, share=0.25)
-    log("bench: server leg with camera requests (replayed arrivals)")
-    clat_s, cspan_s, _ = run_server(True, rlist=req_cam)
+    o_bur = run_one(False)
+    gap = reqs[-1].arrival_s / max(len(reqs) - 1, 1)
     res = {
-        "workload": f"room scene resident; {len(reqs)} requests, Poisson {reqs[-1].arrival_s / max(len(reqs) - 1, 1):.3f}"
-                    f" s mean gap, res in {{256,512,768,1024}}^2, spp in {{4..64}}, 128x256 env each",
-        "rays": rays,
-        "server": {"p50_s": round(pct(lat_s, 50), 4), "p99_s": round(pct(lat_s, 99), 4),
-                   "mean_s": round(float(np.mean(lat_s)), 4),
-                   "mrays_s_replay": round(rays / span_s / 1e6, 2), "mrays_s_burst": round(rays / burst_s / 1e6, 2),
-                   "burst_p50_s": round(pct(blat_s, 50), 4), "burst_p99_s": round(pct(blat_s, 99), 4),
-                   "epochs": st["epochs"], "stopped_epochs": st["stopped"]},
-        "one_launch_per_request": {"p50_s": round(pct(lat_o, 50), 4), "p99_s": round(pct(lat_o, 99), 4),
-                                   "mean_s": round(float(np.mean(lat_o)), 4),
-                                   "mrays_s_replay": round(rays / span_o / 1e6, 2),
-                                   "mrays_s_burst": round(rays / burst_o / 1e6, 2),
-                                   "burst_p50_s": round(pct(blat_o, 50), 4), "burst_p99_s": round(pct(blat_o, 99), 4)},
-        "server_preempt_share_0.25": {"p50_s": round(pct(plat_s, 50), 4), "p99_s": round(pct(plat_s, 99), 4),
-                                      "mean_s": round(float(np.mean(plat_s)), 4),
-                                      "mrays_s_replay": round(rays / pspan_s / 1e6, 2),
-                                      "stopped_epochs": pst["stopped"]},
-        "server_camera_requests": {"p50_s": round(pct(clat_s, 50), 4), "p99_s": round(pct(clat_s, 99), 4),
-                                   "mean_s": round(float(np.mean(clat_s)), 4),
-                                   "mrays_s_replay": round(rays / cspan_s / 1e6, 2),
-                                   "upload_per_request": "environment only (G-buffer traced by the server)"},
+        "workload": f"room scene resident; relighting (attribute query + split-sum) of {len(reqs)} requests, "
+                    f"the first {warm} as warm-up, {len(reqs) - warm} measured; Poisson {gap:.3f} s mean gap; "
+                    f"res in {{256,512,768,1024}}^2, spp in {{4..64}}, 128x256 env each",
+        "measured_rays": rays_m,
+        "server": {"replay": summary(*s_rep), "burst": summary(*s_bur)},
+        "one_launch_per_request": {"replay": summary(*o_rep), "burst": summary(*o_bur)},
         "images_identical": bool(same),
     }
-    if detail:
-        res["latency_s"] = [dict(res=q.res, spp=q.spp, arrival=round(q.arrival_s, 3), server=round(a, 4),
-                                 one_launch=round(b, 4)) for q, a, b in zip(reqs, lat_s, lat_o)]
+    if extra:
+        log("bench: server leg with preemption (radiance requests, replayed arrivals)")
+        rad = [grt.Request(pinned[(q.res, q.cam)], pin(envs[i]), splits[i], q.seed, q.rid) for i, q in enumerate(reqs)]
+        res["server_radiance_preempt_share_0.25"] = summary(*run_server(True, share=0.25, rlist=rad))
+        log("bench: server leg with camera requests (replayed arrivals)")
+        cams = {q.cam: grt.make_camera(*W.camera3(W.rng(3, 10 + q.cam)), 60.0) for q in reqs}
+        rc = [grt.Request(None, pin(envs[i]), splits[i], q.seed, q.rid, camera=cams[q.cam], H=q.res, W=q.res,
+                          relight=True) for i, q in enumerate(reqs)]
+        res["server_camera_requests"] = summary(*run_server(True, rlist=rc))
     return res
+
+
+def calib_copy():
+    """A plain 1 GiB device copy (2 GiB moved): the achieved bandwidth beside
+    the 8 TB/s peak, and the kernel the byte counters are scaled by."""
+    import torch
+    a = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ms = _median_ms(lambda: b.copy_(a), 10)
+    gbs = 2 * a.numel() * 4 / (ms * 1e-3) / 1e9
+    del a, b
+    return {"bytes_moved": 2 << 30, "ms": round(ms, 3), "achieved_gbs": round(gbs, 1), "peak_gbs": HBM_PEAK_GBS,
+            "frac_of_peak": round(gbs / HBM_PEAK_GBS, 3)}
 
 
 def main():
@@ -268,19 +464,22 @@ def main():
     ap.add_argument("--k", type=int, default=12, help="k-buffer size of the forward")
     ap.add_argument("--k-bwd", type=int, default=8, help="k-buffer size of the backward")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-pixels", type=int, default=384, help="pixels of the step the oracle times")
+    ap.add_argument("--cpu-pixels", type=int, default=192, help="pixels of the step the oracle times per run")
     ap.add_argument("--no-serve", action="store_true", help="skip the relighting-server leg")
-    ap.add_argument("--no-stored", action="store_true", help="skip the stored-hit-list backward leg")
+    ap.add_argument("--serve-extra", action="store_true",
+                    help="also replay the server with preemption and with camera requests")
+    ap.add_argument("--no-legs", action="store_true", help="skip the plain-trace and 300k-surfel legs")
+    ap.add_argument("--room-stored", action="store_true", help="also time stored hit lists on the room")
     ap.add_argument("--no-relight", action="store_true", help="skip the split-sum relighting leg")
-    ap.add_argument("--hit-cap", type=int, default=64, help="hits stored per sample in the stored-list leg")
-    ap.add_argument("--serve-requests", type=int, default=32)
+    ap.add_argument("--hit-cap", type=int, default=64, help="hits stored per sample in the stored-list legs")
+    ap.add_argument("--serve-requests", type=int, default=220)
+    ap.add_argument("--serve-warm", type=int, default=20)
     ap.add_argument("--serve-rate", type=float, default=5.9,
-                    help="Poisson arrival rate, requests/s (5.9: 70%% load, 0.7 over the 0.119 s mean service time of one launch per request)")
+                    help="Poisson arrival rate, requests/s (5.9: about 70%% load for one launch per request)")
     ap.add_argument("--serve-slack", type=float, default=-1.0, help="server deadline seconds per ray (-1: default)")
     ap.add_argument("--serve-epoch", type=int, default=0, help="server rays per epoch (0: default)")
     ap.add_argument("--count-work", action="store_true", help="recount per-ray work with the oracle and exit")
-    ap.add_argument("--calib-copy", action="store_true",
-                    help="also run a plain 1 GiB device copy (calibrates the HBM byte counters)")
+    ap.add_argument("--calib-copy", action="store_true", help="only time a plain 1 GiB device copy and exit")
     args = ap.parse_args()
 
     if args.count_work:
@@ -293,6 +492,10 @@ def main():
 
     import torch
     from paper_2607_22780_amd import grt
+
+    if args.calib_copy:
+        print(json.dumps(calib_copy()))
+        return
 
     dev = torch.device("cuda", 0)
     log("bench: generating inputs")
@@ -307,9 +510,7 @@ def main():
     params = [t(a).requires_grad_(True) for a in s.arrays()]
     upstream = t(np.random.default_rng(0).normal(0, 1, (gb.npix, 3)).astype(np.float32))
 
-    ev = {}
-
-    def step(record=False):
+    def step():
         for p in params:
             p.grad = None
         img = grt.RenderMISFn.apply(*params, ctx, E, G, SPLIT, SEED, args.k, 1.0 / 255.0, 0, args.k_bwd)
@@ -332,7 +533,7 @@ def main():
     # per-kernel timing with events on the launch stream (torch's current one)
     st = torch.cuda.current_stream()
     scene = grt.Scene(ctx, *(p.detach() for p in params))
-    eb0, eb1, ef0, ef1, eg0, eg1 = (torch.cuda.Event(enable_timing=True) for _ in range(6))
+    eb0, eb1, ef0, ef1, eg0, eg1 = _events(6)
     build_ms, fwd_ms, bwd_ms = [], [], []
     for _ in range(max(args.steps, 1)):
         eb0.record(st); scene.build(); eb1.record(st)
@@ -345,9 +546,10 @@ def main():
         torch.cuda.synchronize()
         build_ms.append(eb0.elapsed_time(eb1)); fwd_ms.append(ef0.elapsed_time(ef1)); bwd_ms.append(eg0.elapsed_time(eg1))
     build_ms, fwd_ms, bwd_ms = (float(np.median(x)) for x in (build_ms, fwd_ms, bwd_ms))
+    del res
 
     stored = None
-    if not args.no_stored:
+    if args.room_stored:
         # the same step differentiated from stored hit lists instead of re-traversal
         hits = grt.make_hit_list(gb.npix, spp, args.hit_cap, dev)
         sf, sb = [], []
@@ -370,6 +572,13 @@ def main():
                   "retrace_bwd_ms": round(bwd_ms, 3)}
         del hits, res
 
+    legs = None
+    if not args.no_legs:
+        log("bench: plain-trace leg (4,096 surfels)")
+        legs = {"plain_trace_4k": leg_plain(ctx, 16)}
+        log("bench: 300k-surfel leg (forward; differentiable step, re-traversal and stored lists)")
+        legs["shapes_300k"] = leg_shapes(ctx, args.k, args.k_bwd, args.hit_cap)
+
     relight = None
     if not args.no_relight:
         # novel illumination: a fresh 128x256 map, prefiltered; the surfels
@@ -380,35 +589,27 @@ def main():
         mats = [t(a) for a in W.surfel_materials(s.n, seed=0)]
         E2 = grt.Env(ctx, t(env_new))
         pf, rf = [], []
-        ws = None
-        for _ in range(max(args.steps // 2, 3)):
+        for _ in range(3):
             ef0.record(st); E2.prefilter(); ef1.record(st)
             eg0.record(st)
-            out = grt.render_relight(scene, E2, *mats, G, split=SPLIT, seed=SEED, k=args.k, workspace=ws)
+            out = grt.render_relight(scene, E2, *mats, G, split=SPLIT, seed=SEED, k=args.k)
             eg1.record(st)
             torch.cuda.synchronize()
             pf.append(ef0.elapsed_time(ef1)); rf.append(eg0.elapsed_time(eg1))
         frame = float(np.median(rf))
         # cross-bilateral denoise of the relit frame (radius 3: 7x7 window)
         dgb = [t(gb.depth), G.n, G.valid]
-        dn = []
-        for _ in range(5):
-            ef0.record(st)
-            grt.denoise(ctx, out["rgb"], *dgb, gb.H, gb.W)
-            ef1.record(st)
-            torch.cuda.synchronize()
-            dn.append(ef0.elapsed_time(ef1))
-        dn_ms = float(np.median(dn))
+        dn_ms = _median_ms(lambda: grt.denoise(ctx, out["rgb"], *dgb, gb.H, gb.W), 5)
         # primary-ray G-buffer by 2DGRT of a 1024^2 camera inside the room
         cam_o, cam_d = W.pinhole(*W.camera3(W.rng(3, 2)), 60.0, gb.H, gb.W)
         co, cd = t(cam_o.astype(np.float32)), t(cam_d.astype(np.float32))
-        gt = []
-        for _ in range(5):
-            ef0.record(st)
-            gbt = grt.trace_gbuffer(scene, *mats, co, cd, gb.H, gb.W, k=args.k)
-            ef1.record(st)
-            torch.cuda.synchronize()
-            gt.append(ef0.elapsed_time(ef1))
+        holder = {}
+
+        def gtrace():
+            holder["g"] = grt.trace_gbuffer(scene, *mats, co, cd, gb.H, gb.W, k=args.k)
+
+        gt_ms = _median_ms(gtrace, 5)
+        gbt = holder.pop("g")
         covered = float(gbt["valid"].float().mean().item())
         # its backward by re-traversal, seeded upstream gradients on every map
         gen = torch.Generator(device=dev).manual_seed(SEED)
@@ -417,40 +618,28 @@ def main():
         gzs = grt.zero_grads(scene.n, dev)
         gza = dict(albedo=torch.zeros(scene.n, 3, device=dev), rough=torch.zeros(scene.n, device=dev),
                    metal=torch.zeros(scene.n, device=dev))
-        gbw = []
-        for _ in range(3):
-            ef0.record(st)
-            grt.trace_gbuffer_backward(scene, *mats, co, cd, gbt, gup, k=args.k, grads=gzs, attr_grads=gza)
-            ef1.record(st)
-            torch.cuda.synchronize()
-            gbw.append(ef0.elapsed_time(ef1))
+        gbw_ms = _median_ms(lambda: grt.trace_gbuffer_backward(scene, *mats, co, cd, gbt, gup, k=args.k, grads=gzs,
+                                                               attr_grads=gza), 3)
         del gbt, gup, gzs, gza
         # the same relit frame with the mesh backend answering the query
         # (the room as 46k triangles with per-vertex materials)
         mesh3 = W.mesh3()
         mt = [t(a) for a in (mesh3.verts, mesh3.tris)]
         ma = [t(a) for a in (mesh3.albedo, mesh3.rough, mesh3.metal, mesh3.normal)]
-        em0, em1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        em0, em1 = _events(2)
         em0.record(st)
         M = grt.Mesh(ctx, *mt)
         em1.record(st)
         torch.cuda.synchronize()
         mesh_build_ms = em0.elapsed_time(em1)
-        mf = []
-        for _ in range(3):
-            em0.record(st)
-            grt.render_relight_mesh(M, E2, *ma, G, split=SPLIT, seed=SEED)
-            em1.record(st)
-            torch.cuda.synchronize()
-            mf.append(em0.elapsed_time(em1))
-        mesh_frame = float(np.median(mf))
+        mesh_frame = _median_ms(lambda: grt.render_relight_mesh(M, E2, *ma, G, split=SPLIT, seed=SEED), 3)
         del M
         relight = {"env": "128x256, prefiltered to 16x32 tables at 6 roughness levels + 32x32 DFG",
                    "mesh_backend": {"triangles": int(mesh3.nf), "build_ms": round(mesh_build_ms, 3),
                                     "frame_ms": round(mesh_frame, 3),
                                     "mrays_s": round(rays / (mesh_frame * 1e-3) / 1e6, 2)},
-                   "gbuffer_trace_ms": round(float(np.median(gt)), 3), "gbuffer_covered": round(covered, 4),
-                   "gbuffer_backward_ms": round(float(np.median(gbw)), 3),
+                   "gbuffer_trace_ms": round(gt_ms, 3), "gbuffer_covered": round(covered, 4),
+                   "gbuffer_backward_ms": round(gbw_ms, 3),
                    "prefilter_ms": round(float(np.median(pf)), 3), "frame_ms": round(frame, 3),
                    "mrays_s": round(rays / (frame * 1e-3) / 1e6, 2),
                    "radiance_fwd_ms": round(fwd_ms, 3),
@@ -458,14 +647,13 @@ def main():
                    "denoise_gb_s": round(gb.npix * 41 / (dn_ms * 1e-3) / 1e9, 1)}
         del out, E2
 
-    roofline = None
-    if os.path.exists(WORKCOUNT):
-        wc = json.load(open(WORKCOUNT))
+    roof = None
+    wc = load_work("room1m_1024px_32spp")
+    if wc:
         bf, bb = bytes_per_ray(wc)
         dominant = "bwd" if bwd_ms >= fwd_ms else "fwd"
         ms = bwd_ms if dominant == "bwd" else fwd_ms
         per_ray = bb if dominant == "bwd" else bf
-        achieved = per_ray * rays / (ms * 1e-3) / 1e9
         kname = "k_render_bwd" if dominant == "bwd" else "k_render"
         traffic = l2_hit = None
         if os.path.exists(TRAFFIC):
@@ -473,24 +661,22 @@ def main():
             if tr.get("source_hash") == source_hash() and kname in tr.get("kernels", {}):
                 traffic = tr["kernels"][kname]["hbm_bytes"]
                 l2_hit = tr["kernels"][kname].get("l2_hit")
-        roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                        frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic, l2_hit=l2_hit, kernel=kname,
-                        bytes_per_ray=round(per_ray, 1), kernel_ms=round(ms, 3),
-                        traffic_gbs=round(traffic / (ms * 1e-3) / 1e9, 1) if traffic else None,
-                        traced_fraction=round(wc["traced_fraction"], 4))
+        r = roofline(per_ray, rays, ms)
+        roof = dict(bound="hbm", achieved=r["achieved"], peak=HBM_PEAK_GBS, unit="GB/s", frac=r["frac"],
+                    traffic=traffic, l2_hit=l2_hit, kernel=kname, bytes_per_ray=round(per_ray, 1),
+                    kernel_ms=round(ms, 3), traffic_gbs=round(traffic / (ms * 1e-3) / 1e9, 1) if traffic else None,
+                    traced_fraction=round(wc["traced_fraction"], 4), work_sample_rays=wc.get("sample_rays"),
+                    fwd_frac=roofline(bf, rays, fwd_ms)["frac"])
 
-    if args.calib_copy:
-        a = torch.empty(1 << 28, dtype=torch.float32, device=dev)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
+    log("bench: device copy (achieved bandwidth)")
+    copy = calib_copy()
 
     serve = None
     if not args.no_serve:
         log("bench: generating relighting requests")
         reqs, gbs, envs = serve_inputs(args.serve_requests, args.serve_rate)
-        serve = serve_leg(ctx, scene, args.k, reqs, gbs, envs, args.serve_slack, args.serve_epoch)
+        serve = serve_leg(ctx, scene, args.k, reqs, gbs, envs, args.serve_warm, args.serve_slack, args.serve_epoch,
+                          extra=args.serve_extra)
         del reqs, gbs, envs
 
     cpu = None
@@ -516,8 +702,10 @@ def main():
                    "rays_per_step": rays, "k": args.k, "k_bwd": args.k_bwd},
         "fwd_mrays_s": round(rays / (fwd_ms * 1e-3) / 1e6, 2),
         "phase_ms": {"build": round(build_ms, 3), "render_fwd": round(fwd_ms, 3), "render_bwd": round(bwd_ms, 3)},
-        "roofline": roofline,
-        "stored_hit_lists": stored,
+        "roofline": roof,
+        "copy_bandwidth": copy,
+        "legs": legs,
+        "stored_hit_lists_room": stored,
         "relight_split_sum": relight,
         "relight_server": serve,
         "cpu_baseline": cpu,

@@ -164,6 +164,22 @@ __device__ __forceinline__ bool slab(float lx, float ly, float lz, float hx, flo
     return tn <= tf * 1.0000005f + 1e-30f;
 }
 
+// The same test with each plane's entry depth as one fused multiply-add,
+// l inv + (-o inv), noi = -o inv formed once per node: within an ulp of the
+// subtract-then-multiply form, far inside the boxes' 1e-5 padding and the
+// test's relative slack, so it still never rejects a box the ray enters.
+__device__ __forceinline__ bool slab_fma(float lx, float ly, float lz, float hx, float hy, float hz, const float3 inv,
+                                         const float3 noi, float t0, float t1, float &tnear)
+{
+    float ax = fmaf(lx, inv.x, noi.x), bx = fmaf(hx, inv.x, noi.x);
+    float ay = fmaf(ly, inv.y, noi.y), by = fmaf(hy, inv.y, noi.y);
+    float az = fmaf(lz, inv.z, noi.z), bz = fmaf(hz, inv.z, noi.z);
+    float tn = fmaxf(fmaxf(fminf(ax, bx), fminf(ay, by)), fmaxf(fminf(az, bz), t0));
+    float tf = fminf(fminf(fmaxf(ax, bx), fmaxf(ay, by)), fminf(fmaxf(az, bz), t1));
+    tnear = tn;
+    return tn <= tf * 1.0000005f + 1e-30f;
+}
+
 // order-preserving float <-> int maps (atomic min/max of floats)
 __device__ __forceinline__ int f2o(float f)
 {
@@ -307,7 +323,10 @@ struct Frontier {
 // or runs the step for all of them.  0: they join every surfel step.
 // kSiteShare8 > 0: surfel steps run once kSiteShare8/8 of the active lanes
 // wait for one (0: kSurfelShare4/4).
-template <int K, int D = kLdsDepth, int kCompShare16 = 0, int kSiteShare8 = 0>
+#ifndef GRT_FWD_COMP_SHARE16
+#define GRT_FWD_COMP_SHARE16 0
+#endif
+template <int K, int D = kLdsDepth, int kCompShare16 = GRT_FWD_COMP_SHARE16, int kSiteShare8 = 0>
 struct Walker {
     static constexpr int kDepth = D;  // LDS entries per lane and stack
     float3 o, d, inv;
@@ -447,11 +466,25 @@ struct Walker {
         const Node4 *nd = S.nodes4 + cur;
         const float4 lx = nd->lx, ly = nd->ly, lz = nd->lz, hx = nd->hx, hy = nd->hy, hz = nd->hz;
         const int4 ch = nd->ch;
-        float t0 = 0.0f, t1 = 0.0f, t2 = 0.0f, t3 = 0.0f;
-        bool k0 = ch.x != kNoChild && slab(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, o, inv, tlo, tmax, t0);
-        bool k1 = ch.y != kNoChild && slab(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, o, inv, tlo, tmax, t1);
-        bool k2 = ch.z != kNoChild && slab(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, o, inv, tlo, tmax, t2);
-        bool k3 = ch.w != kNoChild && slab(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, o, inv, tlo, tmax, t3);
+        // all four boxes tested without branches (an unused slot's zero box
+        // is masked by its reference)
+        float t0, t1, t2, t3;
+#ifdef GRT_SLAB_FMA
+        const float3 noi = make_float3(-o.x * inv.x, -o.y * inv.y, -o.z * inv.z);
+        bool k0 = slab_fma(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, inv, noi, tlo, tmax, t0);
+        bool k1 = slab_fma(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, inv, noi, tlo, tmax, t1);
+        bool k2 = slab_fma(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, inv, noi, tlo, tmax, t2);
+        bool k3 = slab_fma(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, inv, noi, tlo, tmax, t3);
+#else
+        bool k0 = slab(lx.x, ly.x, lz.x, hx.x, hy.x, hz.x, o, inv, tlo, tmax, t0);
+        bool k1 = slab(lx.y, ly.y, lz.y, hx.y, hy.y, hz.y, o, inv, tlo, tmax, t1);
+        bool k2 = slab(lx.z, ly.z, lz.z, hx.z, hy.z, hz.z, o, inv, tlo, tmax, t2);
+        bool k3 = slab(lx.w, ly.w, lz.w, hx.w, hy.w, hz.w, o, inv, tlo, tmax, t3);
+#endif
+        k0 = k0 & (ch.x != kNoChild);
+        k1 = k1 & (ch.y != kNoChild);
+        k2 = k2 & (ch.z != kNoChild);
+        k3 = k3 & (ch.w != kNoChild);
         k0 = keep_child(ch.x, k0, t0);
         k1 = keep_child(ch.y, k1, t1);
         k2 = keep_child(ch.z, k2, t2);
