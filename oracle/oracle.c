@@ -344,7 +344,8 @@ static void add_grads(double *dst, double *dst_abs, const double *src, int m)
 }
 
 static void backward_ray(const Scene *S, const float o[3], const float d[3], const RayResult *R,
-                         const double gC[3], double gT, double *g13, double *g13_abs)
+                         const double gC[3], double gT, double *g13, double *g13_abs, double *dmu_sum,
+                         double *dmu_abs)
 {
     double T = 1.0, P[3] = {0, 0, 0};
     for (int64_t k = 0; k < R->K; ++k) {
@@ -364,6 +365,8 @@ static void backward_ray(const Scene *S, const float o[3], const float d[3], con
         hit_chain(s, d, &g, dA, 0.0, NULL, add);
         for (int c = 0; c < 3; ++c) add[10 + c] = w * gC[c];
         add_grads(g13 + 13 * id, NULL, add, 13);
+        if (dmu_sum)
+            for (int c = 0; c < 3; ++c) dmu_sum[c] += add[c];
         if (g13_abs) {
             /* error scale: each term's own magnitude, plus the chain applied
              * to the magnitudes dL/dalpha is formed from (a single-precision
@@ -378,6 +381,8 @@ static void backward_ray(const Scene *S, const float o[3], const float d[3], con
             hit_chain(s, d, &g, dAs, 0.0, NULL, sc);
             for (int i = 0; i < 13; ++i) sc[i] = fabs(add[i]) + (i < 10 ? fabs(sc[i]) : 0.0);
             add_grads(g13_abs + 13 * id, NULL, sc, 13);
+            if (dmu_abs)
+                for (int c = 0; c < 3; ++c) dmu_abs[c] += sc[c];
         }
         T *= 1.0 - a;
     }
@@ -722,7 +727,7 @@ int orc_trace_backward(int64_t n, const float *means, const float *scales, const
         if (!(tmin >= 0.0f)) tmin = 0.0f; /* a ray starts at its origin: negative t_min is 0 */
         RayResult R;
         trace_ray(&S, orig + 3 * r, dirs + 3 * r, tmin, tmax, t_cut, &R);
-        backward_ray(&S, orig + 3 * r, dirs + 3 * r, &R, gC + 3 * r, gT[r], g13, g13_abs);
+        backward_ray(&S, orig + 3 * r, dirs + 3 * r, &R, gC + 3 * r, gT[r], g13, g13_abs, NULL, NULL);
         free(R.h);
     }
     scene_free(&S);
@@ -858,6 +863,70 @@ static void brdf(const double n[3], const double wo[3], const double wi[3], cons
         double F0 = 0.04 * (1.0 - metal) + metal * alb[c];
         double F = F0 + (1.0 - F0) * x5;
         f[c] = (1.0 - metal) * alb[c] / ORC_PI + D * F * G / (4.0 * ndi * ndo);
+    }
+}
+
+/* f(wo, wi) of brdf() and its partial derivatives with respect to its
+ * arguments taken as free vectors and scalars (Sec. 3.1 Eq. brdf_specular,
+ * differentiated by hand): dn[c][i] = df_c/dn_i, dwo[c][i] = df_c/dwo_i,
+ * da[c] = df_c/da_c, dr[c] = df_c/d(roughness), dm[c] = df_c/d(metallic).
+ * With h = (wi + wo)/|wi + wo|, a2 = r^4, t = (n.h)^2 (a2 - 1) + 1,
+ * S = D F G1(n.wi) G1(n.wo) / (4 n.wi n.wo):
+ *   dD/d(n.h) = -4 a2 (n.h)(a2 - 1) / (pi t^3),  dD/da2 = 1/(pi t^2) - 2 a2 (n.h)^2/(pi t^3)
+ *   G1(v) = 2v/(v + s), s = sqrt(a2 + (1 - a2) v^2): dG1/dv = 2 (s - v ds/dv)/(v + s)^2,
+ *   ds/dv = (1 - a2) v / s, dG1/da2 = -2 v (ds/da2)/(v + s)^2, ds/da2 = (1 - v^2)/(2 s)
+ *   dF/d(wi.h) = -5 (1 - F0) (1 - wi.h)^4,  dh/dwo = (I - h h^T)/|wi + wo|. */
+static void brdf_partials(const double n[3], const double wo[3], const double wi[3], const double alb[3],
+                          double rough, double metal, double f[3], double dn[3][3], double dwo[3][3], double da[3],
+                          double dr[3], double dm[3])
+{
+    double ndi = dot3(n, wi), ndo = dot3(n, wo);
+    double hs[3] = {wi[0] + wo[0], wi[1] + wo[1], wi[2] + wo[2]};
+    double hl = sqrt(dot3(hs, hs));
+    double h[3] = {hs[0] / hl, hs[1] / hl, hs[2] / hl};
+    double ndh = dot3(n, h), idh = dot3(wi, h);
+    double a = rough * rough, a2 = a * a;
+    double t = ndh * ndh * (a2 - 1.0) + 1.0;
+    double D = a2 / (ORC_PI * t * t);
+    double dD_dnh = -4.0 * a2 * ndh * (a2 - 1.0) / (ORC_PI * t * t * t);
+    double dD_da2 = 1.0 / (ORC_PI * t * t) - 2.0 * a2 * ndh * ndh / (ORC_PI * t * t * t);
+    double vs[2] = {ndi, ndo}, G1[2], dG1[2], dG1a[2];
+    for (int k = 0; k < 2; ++k) {
+        double v = vs[k], sq = sqrt(a2 + (1.0 - a2) * v * v);
+        double ds_dv = (1.0 - a2) * v / sq, ds_da = (1.0 - v * v) / (2.0 * sq);
+        G1[k] = 2.0 * v / (v + sq);
+        dG1[k] = 2.0 * (sq - v * ds_dv) / ((v + sq) * (v + sq));
+        dG1a[k] = -2.0 * v * ds_da / ((v + sq) * (v + sq));
+    }
+    double G = G1[0] * G1[1];
+    double x = 1.0 - idh;
+    if (x < 0.0) x = 0.0;
+    double x4 = x * x * x * x, x5 = x4 * x;
+    double den = 4.0 * ndi * ndo;
+    double dnh_dwo[3], dih_dwo[3];
+    for (int i = 0; i < 3; ++i) {
+        dnh_dwo[i] = (n[i] - h[i] * ndh) / hl;
+        dih_dwo[i] = (wi[i] - h[i] * idh) / hl;
+    }
+    for (int c = 0; c < 3; ++c) {
+        double F0 = 0.04 * (1.0 - metal) + metal * alb[c];
+        double F = F0 + (1.0 - F0) * x5;
+        double S = D * F * G / den;
+        f[c] = (1.0 - metal) * alb[c] / ORC_PI + S;
+        double dF_dih = x > 0.0 ? -5.0 * (1.0 - F0) * x4 : 0.0;
+        /* S through n.wi and n.wo (numerator G1 and the denominator) */
+        double dS_dni = D * F * G1[1] / (4.0 * ndo) * (dG1[0] * ndi - G1[0]) / (ndi * ndi);
+        double dS_dno = D * F * G1[0] / (4.0 * ndi) * (dG1[1] * ndo - G1[1]) / (ndo * ndo);
+        double dS_dnh = dD_dnh * F * G / den;
+        double dS_dih = D * dF_dih * G / den;
+        for (int i = 0; i < 3; ++i) {
+            dn[c][i] = dS_dni * wi[i] + dS_dno * wo[i] + dS_dnh * h[i];
+            dwo[c][i] = dS_dno * n[i] + dS_dnh * dnh_dwo[i] + dS_dih * dih_dwo[i];
+        }
+        double dG_da2 = dG1a[0] * G1[1] + G1[0] * dG1a[1];
+        dr[c] = (dD_da2 * F * G + D * F * dG_da2) / den * 4.0 * rough * rough * rough;
+        da[c] = (1.0 - metal) / ORC_PI + D * G / den * (1.0 - x5) * metal;
+        dm[c] = -alb[c] / ORC_PI + D * G / den * (1.0 - x5) * (alb[c] - 0.04);
     }
 }
 
@@ -1356,12 +1425,16 @@ int orc_render_mis_backward(int64_t n, const float *means, const float *scales, 
                             const float *grough, const float *gmetal, const uint8_t *gvalid,
                             int eH, int eW, const float *env_rgb, const float *marg, const float *cond,
                             int nc, int ng, int ne, uint64_t seed, uint32_t job, float tmin, float tcut,
-                            int64_t np, const int64_t *pix, const double *grad, double *g13, double *g13_abs)
+                            int64_t np, const int64_t *pix, const double *grad, double *g13, double *g13_abs,
+                            double *g_shade, double *g_shade_abs)
 {
     Scene S;
     if (scene_init(&S, n, means, scales, quats, opacity, rgb, alpha_min)) return -1;
     memset(g13, 0, sizeof(double) * 13 * (size_t)n);
     if (g13_abs) memset(g13_abs, 0, sizeof(double) * 13 * (size_t)n);
+    if (g_shade) memset(g_shade, 0, sizeof(double) * 14 * (size_t)np);
+    if (!(g_shade && g13_abs)) g_shade_abs = NULL;
+    if (g_shade_abs) memset(g_shade_abs, 0, sizeof(double) * 14 * (size_t)np);
     Env E = {eH, eW, env_rgb, marg, cond};
     MisOpts op = {nc, ng, ne, seed, job, tmin, tcut};
     int spp = nc + ng + ne;
@@ -1371,6 +1444,13 @@ int orc_render_mis_backward(int64_t n, const float *means, const float *scales, 
         double x[3], nn[3], wo[3], alb[3];
         load_pixel(gx, gn, gwo, galb, p, x, nn, wo, alb);
         if (!(gvalid[p] && dot3(nn, wo) > 0.0)) continue;
+        /* d/d(shading state) with each sample's direction and pdf held fixed
+         * (reading 36): x (through the secondary rays' origin), the unit
+         * normal and view direction, albedo, roughness, metallic */
+        double Gx[3] = {0, 0, 0}, Gn[3] = {0, 0, 0}, Go[3] = {0, 0, 0}, Ga[3] = {0, 0, 0}, Gr = 0.0, Gm = 0.0;
+        /* error scales: the terms' magnitudes (x: with the chain of magnitudes
+         * of the surfel gradients' error scale) */
+        double Ax[3] = {0, 0, 0}, An[3] = {0, 0, 0}, Ao[3] = {0, 0, 0}, Aa[3] = {0, 0, 0}, Ar = 0.0, Am = 0.0;
         for (int j = 0; j < spp; ++j) {
             double w[3], wt[3], Li[3], q;
             float df[3];
@@ -1386,9 +1466,67 @@ int orc_render_mis_backward(int64_t n, const float *means, const float *scales, 
                     gT += gC[c] * Le[c];
                 }
                 float of[3] = {(float)x[0], (float)x[1], (float)x[2]};
-                backward_ray(&S, of, df, &R, gC, gT, g13, g13_abs);
+                double dmu[3] = {0, 0, 0};
+                backward_ray(&S, of, df, &R, gC, gT, g13, g13_abs, g_shade ? dmu : NULL, g_shade_abs ? Ax : NULL);
+                if (g_shade && q > 0.0) {
+                    /* the secondary ray leaves from x: every hit's geometry
+                     * depends on (mu - x), so d/dx = -d/dmu summed over hits */
+                    for (int c = 0; c < 3; ++c) Gx[c] -= dmu[c];
+                    double f[3], dn[3][3], dwo[3][3], da[3], dr[3], dm[3];
+                    brdf_partials(nn, wo, w, alb, grough[p], gmetal[p], f, dn, dwo, da, dr, dm);
+                    double ndi = dot3(nn, w);
+                    for (int c = 0; c < 3; ++c) {
+                        /* g_c = f_c (n.w) / q; its weight in the loss */
+                        double u = grad[3 * k + c] * Li[c] / (double)spp / q;
+                        for (int i = 0; i < 3; ++i) {
+                            Gn[i] += u * (dn[c][i] * ndi + f[c] * w[i]);
+                            Go[i] += u * dwo[c][i] * ndi;
+                        }
+                        Ga[c] += u * da[c] * ndi;
+                        Gr += u * dr[c] * ndi;
+                        Gm += u * dm[c] * ndi;
+                        if (g_shade_abs) {
+                            double ua = fabs(u) * ndi;
+                            for (int i = 0; i < 3; ++i) {
+                                An[i] += ua * fabs(dn[c][i]) + fabs(u * f[c] * w[i]);
+                                Ao[i] += ua * fabs(dwo[c][i]);
+                            }
+                            Aa[c] += ua * fabs(da[c]);
+                            Ar += ua * fabs(dr[c]);
+                            Am += ua * fabs(dm[c]);
+                        }
+                    }
+                }
             }
             free(R.h);
+        }
+        if (g_shade) {
+            /* through the normalisations n / |n| and wo / |wo| of the stored values */
+            double nr[3] = {gn[3 * p], gn[3 * p + 1], gn[3 * p + 2]}, orw[3] = {gwo[3 * p], gwo[3 * p + 1], gwo[3 * p + 2]};
+            double ln = sqrt(dot3(nr, nr)), lo = sqrt(dot3(orw, orw));
+            double pn = dot3(nn, Gn), po = dot3(wo, Go);
+            double *o = g_shade + 14 * k;
+            for (int i = 0; i < 3; ++i) {
+                o[i] = Gx[i];
+                o[3 + i] = (Gn[i] - nn[i] * pn) / ln;
+                o[6 + i] = (Go[i] - wo[i] * po) / lo;
+                o[9 + i] = Ga[i];
+            }
+            o[12] = Gr;
+            o[13] = Gm;
+            if (g_shade_abs) {
+                double *oa = g_shade_abs + 14 * k;
+                double sn = fabs(nn[0]) * An[0] + fabs(nn[1]) * An[1] + fabs(nn[2]) * An[2];
+                double so = fabs(wo[0]) * Ao[0] + fabs(wo[1]) * Ao[1] + fabs(wo[2]) * Ao[2];
+                for (int i = 0; i < 3; ++i) {
+                    oa[i] = Ax[i];
+                    oa[3 + i] = (An[i] + fabs(nn[i]) * sn) / ln;
+                    oa[6 + i] = (Ao[i] + fabs(wo[i]) * so) / lo;
+                    oa[9 + i] = Aa[i];
+                }
+                oa[12] = Ar;
+                oa[13] = Am;
+            }
         }
     }
     scene_free(&S);

@@ -47,7 +47,8 @@ def lib():
                                      [C.c_int, C.c_int, C.c_int, C.c_uint64, C.c_uint32, F, F, I64, P, P] + [P] * 6)
         L.orc_render_mis_backward.restype = C.c_int
         L.orc_render_mis_backward.argtypes = ([I64, P, P, P, P, P, F] + [P] * 7 + [C.c_int, C.c_int, P, P, P] +
-                                              [C.c_int, C.c_int, C.c_int, C.c_uint64, C.c_uint32, F, F, I64, P, P, P, P])
+                                              [C.c_int, C.c_int, C.c_int, C.c_uint64, C.c_uint32, F, F, I64, P, P, P, P, P,
+                                               P])
         L.orc_env_prefilter.restype = C.c_int
         L.orc_env_prefilter.argtypes = [C.c_int, C.c_int, P, P, P]
         L.orc_dfg_lut.restype = C.c_int
@@ -450,9 +451,14 @@ def render_relight_mesh(m, gb, env_rgb, split, seed, pix=None, job=0, t_min=1e-3
 
 
 def render_mis_backward(s, gb, env_rgb, split, seed, grad, pix=None, job=0, t_min=1e-3, t_cut=T_CUT,
-                        alpha_min=ALPHA_MIN, with_abs=False):
+                        alpha_min=ALPHA_MIN, with_abs=False, shading=False):
     """d/d(surfels) of sum_k grad[k] . c_pbr(pix[k]); returns [N,13] double
-    (with ``with_abs`` also each element's error scale, as trace_backward)."""
+    (with ``with_abs`` also each element's error scale, as trace_backward).
+    With ``shading`` also d/d(shading state) of the listed pixels, with every
+    sample's direction and pdf held fixed: [len(pix), 14] = x 3, n 3, wo 3
+    (the stored, unnormalised vectors), albedo 3, roughness, metallic;
+    returned last (with ``with_abs`` followed by its error scales, the same
+    shape: the terms' magnitudes, and for x the mean terms' error scales)."""
     nc, ng, ne = split
     arrs = _scene(s)
     g = _gb(gb)
@@ -462,11 +468,15 @@ def render_mis_backward(s, gb, env_rgb, split, seed, grad, pix=None, job=0, t_mi
     grad = _c(grad, np.float64).reshape(len(pix), 3)
     out = np.zeros((s.n, 13))
     oabs = np.zeros((s.n, 13)) if with_abs else None
+    shade = np.zeros((len(pix), 14)) if shading else None
+    sabs = np.zeros((len(pix), 14)) if shading and with_abs else None
     rc = lib().orc_render_mis_backward(s.n, *map(_p, arrs), alpha_min, *map(_p, g), e.shape[0], e.shape[1], _p(e),
                                        _p(marg), _p(cond), nc, ng, ne, seed, job, t_min, t_cut, len(pix), _p(pix),
-                                       _p(grad), _p(out), _p(oabs))
+                                       _p(grad), _p(out), _p(oabs), _p(shade), _p(sabs))
     assert rc == 0
-    return (out, oabs) if with_abs else out
+    res = (out,) + ((oabs,) if with_abs else ()) + ((shade,) if shading else ()) + \
+        ((sabs,) if sabs is not None else ())
+    return res if len(res) > 1 else out
 
 
 def split_grads(g13):
