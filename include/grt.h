@@ -480,6 +480,38 @@ int grt_render_mis_backward(const grt_scene *scene, const grt_env *env, const gr
                             const grt_mis_opts *opts, const float *grad_rgb, const void *saved,
                             grt_surfel_grads *grads, void *workspace, size_t ws_bytes, void *stream);
 
+/* Gradients of a loss on the MIS render with respect to the shading state
+ * of each pixel (Sec. 3.3, Eq. deferred_maps), so that they can flow on into
+ * the G-buffer's own backward (grt_trace_gbuffer_backward).  Each sample's
+ * direction and mixture pdf are held fixed, as its hit set is: the estimator
+ * is differentiated through the weights f(wo, w) (w . n) / q and through the
+ * secondary rays' common origin x, not through the proposals.  Device
+ * float32 arrays, [npix,3] or [npix]; every pixel is written (0 where the
+ * pixel is invalid or wo . n <= 0); a NULL member is not written.
+ *   x:      d/dx of the secondary rays' origin (the hits' geometry moves
+ *           with mu - x: minus the sum of their mean gradients)
+ *   n, wo:  d/d the stored vectors (they are normalised before use, so the
+ *           gradient is orthogonal to them and scales with 1/|n|, 1/|wo|)
+ *   albedo, rough, metal: d/d the material maps */
+typedef struct {
+    float *x;
+    float *n;
+    float *wo;
+    float *albedo;
+    float *rough;
+    float *metal;
+} grt_shading_grads;
+
+/* grt_render_mis_backward (the surfel gradients, accumulated into `grads`
+ * exactly as there) plus the shading-state gradients `shade` (overwritten).
+ * Same arguments and workspace otherwise; GRT_ERR_INVALID if shade is NULL.
+ * With stored hit lists (opts->hit_list) the origin gradients come from the
+ * lists, and from the re-traversal for samples whose list overflowed. */
+int grt_render_mis_backward_shading(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g,
+                                    const grt_mis_opts *opts, const float *grad_rgb, const void *saved,
+                                    grt_surfel_grads *grads, const grt_shading_grads *shade, void *workspace,
+                                    size_t ws_bytes, void *stream);
+
 /* Relighting under the environment `env` (Sec. 3.5.1): the MIS estimator of
  * grt_render_mis (same samples, same proposals and pdfs from env's tables),
  * with the incident radiance of every traced sample replaced by

@@ -836,9 +836,10 @@ int grt_render_mis_noalloc(const grt_scene *scene, const grt_env *env, const grt
                           stream);
 }
 
-int grt_render_mis_backward(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *opts,
-                            const float *grad_rgb, const void *saved, grt_surfel_grads *grads, void *workspace,
-                            size_t ws_bytes, void *stream)
+static int render_backward(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g,
+                           const grt_mis_opts *opts, const float *grad_rgb, const void *saved,
+                           grt_surfel_grads *grads, const grt_shading_grads *shade, void *workspace,
+                           size_t ws_bytes, void *stream)
 {
     grt::RenderArgs a;
     int rc = fill_render_args(scene, env, g, opts, a);
@@ -858,6 +859,9 @@ int grt_render_mis_backward(const grt_scene *scene, const grt_env *env, const gr
     a.counters = w.counters;
     a.rays = w.rays;
     a.order = a.S.n >= 2 ? w.v1 : nullptr;
+    // the backward does not use the contribution slots: they hold the
+    // per-sample origin gradients when the shading state is differentiated
+    a.gorig = shade ? w.contrib : nullptr;
     if ((rc = set_device(scene->ctx))) return rc;
     const hipStream_t st = (hipStream_t)stream;
     hipError_t e = grt::launch_grad_lines_zero(a.g.acc, scene->s.n, st);
@@ -865,8 +869,28 @@ int grt_render_mis_backward(const grt_scene *scene, const grt_env *env, const gr
         e = a.hits ? grt::launch_render_backward_stored(a, w, opts->k, scene->ctx->num_cu, st)
                    : grt::launch_render_backward(a, w, opts->k, scene->ctx->num_cu, st);
     if (e == hipSuccess) e = grt::launch_grad_lines_apply(a.g, scene->s.n, st);
+    if (e == hipSuccess && shade) {
+        const grt::ShadeGradOut o{shade->x, shade->n, shade->wo, shade->albedo, shade->rough, shade->metal};
+        e = grt::launch_render_shade_grad(a, o, st);
+    }
     if (e != hipSuccess) return hip_fail(e, "render backward launch");
     return GRT_OK;
+}
+
+int grt_render_mis_backward(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *opts,
+                            const float *grad_rgb, const void *saved, grt_surfel_grads *grads, void *workspace,
+                            size_t ws_bytes, void *stream)
+{
+    return render_backward(scene, env, g, opts, grad_rgb, saved, grads, nullptr, workspace, ws_bytes, stream);
+}
+
+int grt_render_mis_backward_shading(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g,
+                                    const grt_mis_opts *opts, const float *grad_rgb, const void *saved,
+                                    grt_surfel_grads *grads, const grt_shading_grads *shade, void *workspace,
+                                    size_t ws_bytes, void *stream)
+{
+    if (!shade) return fail(GRT_ERR_INVALID, "shade is NULL");
+    return render_backward(scene, env, g, opts, grad_rgb, saved, grads, shade, workspace, ws_bytes, stream);
 }
 
 }  // extern "C"

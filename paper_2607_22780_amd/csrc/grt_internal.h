@@ -325,6 +325,9 @@ struct RenderArgs {
     // backward
     const float *grad;
     GradPtrs g;
+    // backward with the shading state: per sample, the loss's gradient with
+    // respect to its ray's origin (xyz; null: not formed)
+    float4 *gorig;
 };
 // Render workspace: counters | contributions (16 B/sample) | ray records
 // (48 B/sample) | sort keys and values (2 x 2 x 4 B/sample) | sort histogram.
@@ -378,6 +381,12 @@ hipError_t launch_render(const RenderArgs &a, const RenderWS &w, int k, int num_
 hipError_t launch_render_backward(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st);
 // Backward from stored hit lists (a.hits); re-traverses overflowing samples.
 hipError_t launch_render_backward_stored(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st);
+// After a backward with a.gorig set: the gradients with respect to each
+// pixel's shading state (null outputs are not written).
+struct ShadeGradOut {
+    float *x, *n, *wo, *alb, *rough, *metal;
+};
+hipError_t launch_render_shade_grad(const RenderArgs &a, const ShadeGradOut &o, hipStream_t st);
 
 // Zero the per-launch counters; persistent grid size for a kernel.
 hipError_t launch_zero_counters(unsigned long long *c, hipStream_t st);

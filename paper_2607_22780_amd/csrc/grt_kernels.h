@@ -154,15 +154,18 @@ struct GBufVisit : AttrVisit {
 // hits per instruction.  Flushes run at wavefront-uniform points; a step
 // stages at most one hit per lane, so flushing whenever the list could not
 // take another full step keeps it from overflowing.
-constexpr int kStageCap = 128;
 constexpr int kStageStride = 14;  // 13 terms, then the surfel id
-struct WaveStage {
-    float v[kStageCap * kStageStride];
+template <int Cap>
+struct WaveStageN {
+    static constexpr int kCap = Cap;
+    float v[Cap * kStageStride];
     int count;
 };
+using WaveStage = WaveStageN<128>;
 
 // Active lanes: stage one hit each (13 terms of surfel id).
-__device__ __forceinline__ void stage_add(WaveStage *s, uint32_t id, const float (&t)[13])
+template <class Stage>
+__device__ __forceinline__ void stage_add(Stage *s, uint32_t id, const float (&t)[13])
 {
     const uint64_t m = __ballot(1);
     const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
@@ -176,7 +179,8 @@ __device__ __forceinline__ void stage_add(WaveStage *s, uint32_t id, const float
 }
 
 // All 64 lanes of the wavefront: start with an empty list.
-__device__ __forceinline__ void stage_init(WaveStage *s)
+template <class Stage>
+__device__ __forceinline__ void stage_init(Stage *s)
 {
     if ((threadIdx.x & 63) == 0) *(volatile int *)&s->count = 0;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -185,11 +189,12 @@ __device__ __forceinline__ void stage_init(WaveStage *s)
 // All 64 lanes of the wavefront, at a wavefront-uniform point: add the staged
 // hits to their surfels' lines once the list is past half full (all of it
 // when `all`), then empty it.
-__device__ __forceinline__ void stage_sync(float *acc, WaveStage *s, bool all)
+template <class Stage>
+__device__ __forceinline__ void stage_sync(float *acc, Stage *s, bool all)
 {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     const int n = __builtin_amdgcn_readfirstlane(*(volatile int *)&s->count);
-    if (n == 0 || (!all && n <= kStageCap - 64)) return;
+    if (n == 0 || (!all && n <= Stage::kCap - 64)) return;
     const int lane = threadIdx.x & 63, c = lane & 15;
     const volatile float *v = s->v;
     if (c < 13)
@@ -251,7 +256,11 @@ __device__ __forceinline__ void hit_param_grads(const HitGeo &hg, const float4 r
     out[9] = G * dA;
 }
 
-struct GradVisit {
+// kOrigin: also sum the hits' mean terms per ray.  Every hit's geometry is a
+// function of mu - o, so the loss's gradient with respect to the ray origin
+// is minus that sum (kept in `gmu`).
+template <bool kOrigin = false>
+struct GradVisitT {
     const float4 *rec;
     const float4 *col;
     float tcut;
@@ -261,10 +270,11 @@ struct GradVisit {
     float gT, Tf;
     float T, Td;
     float3 P;
+    float3 gmu;
 
-    __device__ GradVisit() {}
+    __device__ GradVisitT() {}
     const float4 *quat;
-    __device__ GradVisit(const SceneDev &S, float t_cut, const GradPtrs &gp)
+    __device__ GradVisitT(const SceneDev &S, float t_cut, const GradPtrs &gp)
         : rec(S.rec), col(S.col), tcut(t_cut), g(gp), quat(S.quat) {}
 
     __device__ __forceinline__ void reset(float3 o_, float3 d_, float3 gC_, float gT_, float3 Cf_, float Tf_)
@@ -278,6 +288,7 @@ struct GradVisit {
         T = 1.0f;
         Td = 1.0f;
         P = make_float3(0.f, 0.f, 0.f);
+        gmu = make_float3(0.f, 0.f, 0.f);
     }
 
     __device__ __forceinline__ bool operator()(uint32_t p, uint32_t id, float tau, const float4 r0, const float4 r1,
@@ -302,7 +313,106 @@ struct GradVisit {
                                terms);
         terms[10] = w * gC.x; terms[11] = w * gC.y; terms[12] = w * gC.z;
         stage_add(stage, id, terms);
+        if constexpr (kOrigin) {
+            gmu.x += terms[0]; gmu.y += terms[1]; gmu.z += terms[2];
+        }
 
+        T = T * (1.0f - a);
+        Td = trans_step(Td, hit_alpha(op, crho2));
+        return Td < tcut;
+    }
+};
+
+using GradVisit = GradVisitT<false>;
+
+// The radiance backward with each hit's chain rule taken off the traversal.
+// Compositing a hit in a step runs on the lanes that have one to composite,
+// often a few of the wavefront; only what must follow the ray in order stays
+// there (alpha, the running sum P, T and dL/dalpha).  The hit is queued per
+// wavefront -- record position, sample index, dL/dalpha and its weight T
+// alpha -- and the chain to the surfel's parameters runs later for 64 queued
+// hits at once, one per lane, at a wavefront-uniform point.  The result is
+// the same terms as GradVisit's; only the order of the atomic adds differs.
+constexpr int kQueueCap = 128;  // a power of two; >= 63 + 64 (a drain leaves < 64, a step adds <= 64)
+struct GradQueue {
+    uint32_t p[kQueueCap];
+    uint32_t r[kQueueCap];
+    float dA[kQueueCap];
+    float w[kQueueCap];
+    int head, count;
+};
+
+__device__ __forceinline__ void queue_init(GradQueue *q)
+{
+    if ((threadIdx.x & 63) == 0) {
+        *(volatile int *)&q->head = 0;
+        *(volatile int *)&q->count = 0;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+}
+
+// Active lanes: queue one hit each.
+__device__ __forceinline__ void queue_push(GradQueue *q, uint32_t p, uint32_t r, float dA, float w)
+{
+    const uint64_t m = __ballot(1);
+    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    volatile int *cnt = &q->count;
+    const int n = __builtin_amdgcn_readfirstlane(*cnt);
+    const int head = __builtin_amdgcn_readfirstlane(*(volatile int *)&q->head);
+    const int e = (head + n + rank) & (kQueueCap - 1);
+    reinterpret_cast<volatile uint32_t *>(q->p)[e] = p;
+    reinterpret_cast<volatile uint32_t *>(q->r)[e] = r;
+    reinterpret_cast<volatile float *>(q->dA)[e] = dA;
+    reinterpret_cast<volatile float *>(q->w)[e] = w;
+    if (rank == 0) *cnt = n + __popcll(m);
+}
+
+struct GradVisitQ {
+    const float4 *col;
+    float tcut;
+    GradQueue *q = nullptr;
+    uint32_t r;  // the lane's sample
+    float3 o, d, gC, Cf;
+    float gT, Tf;
+    float T, Td;
+    float3 P;
+
+    __device__ GradVisitQ() {}
+    __device__ GradVisitQ(const SceneDev &S, float t_cut) : col(S.col), tcut(t_cut) {}
+
+    __device__ __forceinline__ void reset(float3 o_, float3 d_, float3 gC_, float gT_, float3 Cf_, float Tf_,
+                                          uint32_t r_)
+    {
+        o = o_;
+        d = d_;
+        gC = gC_;
+        gT = gT_;
+        Cf = Cf_;
+        Tf = Tf_;
+        r = r_;
+        T = 1.0f;
+        Td = 1.0f;
+        P = make_float3(0.f, 0.f, 0.f);
+    }
+
+    __device__ __forceinline__ bool operator()(uint32_t p, uint32_t id, float tau, const float4 r0, const float4 r1,
+                                               const float4 r2, const float4 r3, float crho2)
+    {
+        const float4 c = col[p];
+        const float op = r1.w;
+        HitGeo hg;
+        value_geo(r0, r1, r2, r3, o, d, hg);
+        const float G = expf(-0.5f * hg.rho2);
+        const float a = op * G;
+        const float w = T * a;
+        P.x += w * c.x; P.y += w * c.y; P.z += w * c.z;
+        float dA = T * (gC.x * c.x + gC.y * c.y + gC.z * c.z);
+        const float om = 1.0f - a;
+        if (om >= 1e-6f) {
+            float behind = gC.x * (Cf.x - P.x) + gC.y * (Cf.y - P.y) + gC.z * (Cf.z - P.z) + gT * Tf;
+            dA -= behind / om;
+        }
+        queue_push(q, p, r, dA, w);
         T = T * (1.0f - a);
         Td = trans_step(Td, hit_alpha(op, crho2));
         return Td < tcut;

@@ -227,6 +227,75 @@ __device__ __forceinline__ V3 brdf(V3 n, V3 wo, V3 wi, V3 alb, double rough, dou
     return v3(f[0], f[1], f[2]);
 }
 
+// Backward of the BRDF times the cosine, sum_c u_c f_c(wo, wi) (n.wi), with
+// wi held fixed: accumulates the derivatives with respect to the unit normal
+// n, the unit view direction wo, albedo, roughness and metallic.  The
+// specular part of f_c is K F_c, K = D G1(n.wi) G1(n.wo) / (4 (n.wi)(n.wo)),
+// and everything that moves K enters through its logarithm:
+//   d ln K / d(n.wi) = -(1 + s'(n.wi)) / (n.wi + s(n.wi))  (G1's 1/v and the
+//     denominator's cancel; s(v) = sqrt(a2 + (1 - a2) v^2), s' = ds/dv),
+//   the same in n.wo,  d ln K / d(n.h) = -4 (n.h)(a2 - 1) / t,
+//   t = (n.h)^2 (a2 - 1) + 1,  with h = (wi + wo) / |wi + wo|;
+// the roughness (a2 = r^4) enters D directly and G1 through s:
+//   dD/da2 = (1 - 2 a2 (n.h)^2 / t) / (pi t^2),  d ln G1 / da2 = -(ds/da2) / (v + s).
+// F_c = F0_c + (1 - F0_c) x^5, x = max(0, 1 - wi.h), F0_c = 0.04 (1 - m) + m a_c.
+struct ShadeGrad {
+    V3 n, wo, alb;
+    double rough, metal;
+};
+
+__device__ __forceinline__ void brdf_cos_backward(V3 n, V3 wo, V3 wi, V3 alb, double rough, double metal,
+                                                  const double u[3], ShadeGrad &g)
+{
+#pragma clang fp contract(off)
+    const double ndi = dot(n, wi), ndo = dot(n, wo);
+    const V3 hs = v3(wi.x + wo.x, wi.y + wo.y, wi.z + wo.z);
+    const double hl = sqrt(dot(hs, hs));
+    const V3 h = v3(hs.x / hl, hs.y / hl, hs.z / hl);
+    const double ndh = dot(n, h), idh = dot(wi, h);
+    const double r2 = rough * rough, a2 = r2 * r2;
+    const double t = ndh * ndh * (a2 - 1.0) + 1.0;
+    const double D = a2 / (kPiD * t * t);
+    const double si = sqrt(a2 + (1.0 - a2) * ndi * ndi), so = sqrt(a2 + (1.0 - a2) * ndo * ndo);
+    const double G1i = 2.0 * ndi / (ndi + si), G1o = 2.0 * ndo / (ndo + so);
+    const double den = 4.0 * ndi * ndo;
+    const double K = D * G1i * G1o / den;
+    double x = 1.0 - idh;
+    if (x < 0.0) x = 0.0;
+    const double x4 = x * x * x * x, x5 = x4 * x;
+    const double al[3] = {alb.x, alb.y, alb.z};
+    // channel sums: sum u f, sum u F, sum u dF/d(wi.h), and the albedo/metal terms
+    double uf = 0.0, uF = 0.0, udF = 0.0, um = 0.0, ga[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const double F0 = 0.04 * (1.0 - metal) + metal * al[c];
+        const double F = F0 + (1.0 - F0) * x5;
+        uf += u[c] * ((1.0 - metal) * al[c] / kPiD + K * F);
+        uF += u[c] * F;
+        udF += u[c] * (x > 0.0 ? -5.0 * (1.0 - F0) * x4 : 0.0);
+        ga[c] = u[c] * ndi * ((1.0 - metal) / kPiD + K * metal * (1.0 - x5));
+        um += u[c] * (-al[c] / kPiD + K * (al[c] - 0.04) * (1.0 - x5));
+    }
+    const double KuF = K * uF;
+    const double Li = -(1.0 + (1.0 - a2) * ndi / si) / (ndi + si);
+    const double Lo = -(1.0 + (1.0 - a2) * ndo / so) / (ndo + so);
+    const double Lh = -4.0 * ndh * (a2 - 1.0) / t;
+    // d/dn of (n.wi), (n.wo), (n.h); d/dwo of (n.wo), (n.h), (wi.h)
+    const double cn_i = ndi * KuF * Li + uf, cn_o = ndi * KuF * Lo, cn_h = ndi * KuF * Lh;
+    g.n = v3(g.n.x + cn_i * wi.x + cn_o * wo.x + cn_h * h.x, g.n.y + cn_i * wi.y + cn_o * wo.y + cn_h * h.y,
+             g.n.z + cn_i * wi.z + cn_o * wo.z + cn_h * h.z);
+    const double cw_h = cn_h / hl, cw_i = ndi * K * udF / hl;
+    g.wo = v3(g.wo.x + cn_o * n.x + cw_h * (n.x - h.x * ndh) + cw_i * (wi.x - h.x * idh),
+              g.wo.y + cn_o * n.y + cw_h * (n.y - h.y * ndh) + cw_i * (wi.y - h.y * idh),
+              g.wo.z + cn_o * n.z + cw_h * (n.z - h.z * ndh) + cw_i * (wi.z - h.z * idh));
+    g.alb = v3(g.alb.x + ga[0], g.alb.y + ga[1], g.alb.z + ga[2]);
+    g.metal += ndi * um;
+    const double dD = (1.0 - 2.0 * a2 * ndh * ndh / t) / (kPiD * t * t);
+    const double dlnG = -(1.0 - ndi * ndi) / (2.0 * si * (ndi + si)) - (1.0 - ndo * ndo) / (2.0 * so * (ndo + so));
+    const double dK = dD * G1i * G1o / den + K * dlnG;
+    g.rough += ndi * uF * dK * 4.0 * r2 * rough;
+}
+
 // ---------------------------------------------------------------------------
 // Split-sum relighting (Eq. relight_splitsum), in double: lookups of the
 // prefiltered tables and SplitSum(a, r, m, n, E) of a surface seen along -w.

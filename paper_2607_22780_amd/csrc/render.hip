@@ -261,12 +261,15 @@ __global__ void __launch_bounds__(256) k_relight_shade(RenderArgs a, int64_t tot
     }
 }
 
-template <int K>
+// kOrigin: also write each sample's origin gradient to a.gorig (zero for a
+// sample that contributes nothing; samples done from stored hit lists are
+// left to that kernel).
+template <int K, bool kOrigin>
 struct RenderBwdJob {
     const RenderArgs &a;
     SceneDev S;
     BwdWalker<K> w;
-    GradVisit v;
+    GradVisitT<kOrigin> v;
     int spp;
 
     __device__ RenderBwdJob(const RenderArgs &a_, WaveStage *t)
@@ -276,7 +279,84 @@ struct RenderBwdJob {
         stage_init(t);
     }
     __device__ __forceinline__ BwdWalker<K> &walker() { return w; }
-    __device__ __forceinline__ GradVisit &visit() { return v; }
+    __device__ __forceinline__ GradVisitT<kOrigin> &visit() { return v; }
+
+    __device__ __forceinline__ bool skip(int64_t r)
+    {
+        if constexpr (kOrigin) a.gorig[r] = make_float4(0.f, 0.f, 0.f, 0.f);
+        return false;
+    }
+
+    __device__ __forceinline__ bool begin(int64_t g)
+    {
+        const int64_t r = a.order ? (int64_t)a.order[g] : g;
+        if (S.n <= 0) return skip(r);
+        const float4 r0 = a.rays[3 * r];
+        if (r0.w == 0.0f) return skip(r);
+        if (a.hits && a.hits[r] <= (uint32_t)a.hcap) return false;  // done from its stored list
+        const int64_t p = r / spp;
+        const float inv = 1.0f / (float)spp;
+        const float3 gp = make_float3(a.grad[3 * p] * inv, a.grad[3 * p + 1] * inv, a.grad[3 * p + 2] * inv);
+        if (gp.x == 0.0f && gp.y == 0.0f && gp.z == 0.0f) return skip(r);
+        const float4 r1 = a.rays[3 * r + 1], r2 = a.rays[3 * r + 2];
+        const float3 gC = make_float3(r1.x * gp.x, r1.y * gp.y, r1.z * gp.z);
+        const float gT = gC.x * r1.w + gC.y * r2.x + gC.z * r2.y;
+        const float4 sv = a.saved[r];
+        const float3 x = make_float3(a.x[3 * p], a.x[3 * p + 1], a.x[3 * p + 2]);
+        const float3 d = make_float3(r0.x, r0.y, r0.z);
+        v.reset(x, d, gC, gT, make_float3(sv.x, sv.y, sv.z), sv.w);
+        w.start(S, x, d, a.tmin, stop_bound(a.saved_t, r, INFINITY));
+        if constexpr (kOrigin) cur = r;
+        return true;
+    }
+
+    __device__ __forceinline__ void finish(int64_t)
+    {
+        if constexpr (kOrigin) a.gorig[cur] = make_float4(-v.gmu.x, -v.gmu.y, -v.gmu.z, 0.0f);
+    }
+    __device__ __forceinline__ void after_step() { stage_sync(a.g.acc, v.stage, false); }
+    __device__ __forceinline__ void drain() { stage_sync(a.g.acc, v.stage, true); }
+
+    int64_t cur = 0;  // the lane's sample (kOrigin)
+};
+
+#ifndef GRT_BWD_QUEUE
+#define GRT_BWD_QUEUE 0
+#endif
+#ifndef GRT_BWDQ_WAVES
+#define GRT_BWDQ_WAVES 3
+#endif
+
+// The benchmarked backward: RenderBwdJob's work with each hit's chain rule
+// queued (GradVisitQ) and run 64 hits at a time at the wavefront-uniform
+// point after every step.  The origin of a queued hit's ray, its direction
+// and gradient weights are read back from the sample's records there.
+template <int K>
+struct RenderBwdQJob {
+    const RenderArgs &a;
+    SceneDev S;
+    BwdWalker<K> w;
+    GradVisitQ v;
+    WaveStageN<64> *stage;
+    int spp;
+
+    __device__ RenderBwdQJob(const RenderArgs &a_, GradQueue *q, WaveStageN<64> *st)
+        : a(a_), S(a_.S), v(a_.S, a_.tcut), stage(st), spp(a_.nc + a_.ng + a_.ne)
+    {
+        v.q = q;
+        queue_init(q);
+        stage_init(st);
+    }
+    __device__ __forceinline__ BwdWalker<K> &walker() { return w; }
+    __device__ __forceinline__ GradVisitQ &visit() { return v; }
+
+    __device__ __forceinline__ float3 weight(int64_t r, int64_t p) const
+    {
+        const float inv = 1.0f / (float)spp;
+        const float3 gp = make_float3(a.grad[3 * p] * inv, a.grad[3 * p + 1] * inv, a.grad[3 * p + 2] * inv);
+        const float4 r1 = a.rays[3 * r + 1];
+        return make_float3(r1.x * gp.x, r1.y * gp.y, r1.z * gp.z);
+    }
 
     __device__ __forceinline__ bool begin(int64_t g)
     {
@@ -287,22 +367,68 @@ struct RenderBwdJob {
         if (a.hits && a.hits[r] <= (uint32_t)a.hcap) return false;  // done from its stored list
         const int64_t p = r / spp;
         const float inv = 1.0f / (float)spp;
-        const float3 gp = make_float3(a.grad[3 * p] * inv, a.grad[3 * p + 1] * inv, a.grad[3 * p + 2] * inv);
-        if (gp.x == 0.0f && gp.y == 0.0f && gp.z == 0.0f) return false;
+        if (a.grad[3 * p] * inv == 0.0f && a.grad[3 * p + 1] * inv == 0.0f && a.grad[3 * p + 2] * inv == 0.0f)
+            return false;
+        const float3 gC = weight(r, p);  // recomputed the same way where its hits are drained
         const float4 r1 = a.rays[3 * r + 1], r2 = a.rays[3 * r + 2];
-        const float3 gC = make_float3(r1.x * gp.x, r1.y * gp.y, r1.z * gp.z);
         const float gT = gC.x * r1.w + gC.y * r2.x + gC.z * r2.y;
         const float4 sv = a.saved[r];
         const float3 x = make_float3(a.x[3 * p], a.x[3 * p + 1], a.x[3 * p + 2]);
         const float3 d = make_float3(r0.x, r0.y, r0.z);
-        v.reset(x, d, gC, gT, make_float3(sv.x, sv.y, sv.z), sv.w);
+        v.reset(x, d, gC, gT, make_float3(sv.x, sv.y, sv.z), sv.w, (uint32_t)r);
         w.start(S, x, d, a.tmin, stop_bound(a.saved_t, r, INFINITY));
         return true;
     }
 
     __device__ __forceinline__ void finish(int64_t) {}
-    __device__ __forceinline__ void after_step() { stage_sync(a.g.acc, v.stage, false); }
-    __device__ __forceinline__ void drain() { stage_sync(a.g.acc, v.stage, true); }
+
+    // All 64 lanes, at a wavefront-uniform point: the chain rule of the
+    // queued hits, 64 at a time (and the remainder too when `all`), staged
+    // and added to the surfels' lines.
+    __device__ __forceinline__ void drain_hits(bool all)
+    {
+        GradQueue *q = v.q;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        int n = __builtin_amdgcn_readfirstlane(*(volatile int *)&q->count);
+        const int lane = threadIdx.x & 63;
+        while (n >= 64 || (all && n > 0)) {
+            const int head = __builtin_amdgcn_readfirstlane(*(volatile int *)&q->head);
+            const int m = n < 64 ? n : 64;
+            if (lane < m) {
+                const int e = (head + lane) & (kQueueCap - 1);
+                const uint32_t p = reinterpret_cast<volatile uint32_t *>(q->p)[e];
+                const int64_t r = (int64_t)reinterpret_cast<volatile uint32_t *>(q->r)[e];
+                const float dA = reinterpret_cast<volatile float *>(q->dA)[e];
+                const float wgt = reinterpret_cast<volatile float *>(q->w)[e];
+                const float4 *rec = S.rec + 4 * (size_t)p;
+                const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2], r3 = rec[3];
+                const float4 c = S.col[p], qt = S.quat[p];
+                const int64_t px = r / spp;
+                const float3 x = make_float3(a.x[3 * px], a.x[3 * px + 1], a.x[3 * px + 2]);
+                const float4 d4 = a.rays[3 * r];
+                const float3 d = make_float3(d4.x, d4.y, d4.z);
+                const float3 gC = weight(r, px);
+                HitGeo hg;
+                value_geo(r0, r1, r2, r3, x, d, hg);
+                const float G = expf(-0.5f * hg.rho2);
+                const float al = r1.w * G;
+                float terms[13];
+                hit_param_grads<false>(hg, r1, r2, r3, d, al, G, dA, 0.0f, make_float3(0.f, 0.f, 0.f), qt, r3.w, c.w,
+                                       terms);
+                terms[10] = wgt * gC.x; terms[11] = wgt * gC.y; terms[12] = wgt * gC.z;
+                stage_add(stage, __float_as_uint(r2.w), terms);
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            if (lane == 0) {
+                *(volatile int *)&q->head = (head + m) & (kQueueCap - 1);
+                *(volatile int *)&q->count = n - m;
+            }
+            stage_sync(a.g.acc, stage, true);
+            n -= m;
+        }
+    }
+    __device__ __forceinline__ void after_step() { drain_hits(false); }
+    __device__ __forceinline__ void drain() { drain_hits(true); }
 };
 
 // kHitList: the launch stores hit lists (a.hits set); a separate kernel, so
@@ -337,11 +463,21 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k
     run_persistent<K>(job, a.counters, (int64_t)a.H * a.W * (a.nc + a.ng + a.ne));
 }
 
-template <int K>
+template <int K, bool kOrigin>
 __global__ void __launch_bounds__(256) GRT_OCCUPANCY k_render_bwd(RenderArgs a)
 {
     __shared__ WaveStage stages[4];
-    RenderBwdJob<K> job(a, &stages[(threadIdx.x >> 6) & 3]);
+    RenderBwdJob<K, kOrigin> job(a, &stages[(threadIdx.x >> 6) & 3]);
+    run_persistent<K>(job, a.counters, (int64_t)a.H * a.W * (a.nc + a.ng + a.ne));
+}
+
+template <int K>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GRT_BWDQ_WAVES))) k_render_bwd_q(RenderArgs a)
+{
+    __shared__ WaveStageN<64> stages[4];
+    __shared__ GradQueue queues[4];
+    const int wave = (threadIdx.x >> 6) & 3;
+    RenderBwdQJob<K> job(a, &queues[wave], &stages[wave]);
     run_persistent<K>(job, a.counters, (int64_t)a.H * a.W * (a.nc + a.ng + a.ne));
 }
 
@@ -349,7 +485,9 @@ __global__ void __launch_bounds__(256) GRT_OCCUPANCY k_render_bwd(RenderArgs a)
 // its composited hits in order (no traversal).  Samples whose list
 // overflowed are left to the re-traversal kernel.  The wavefront steps
 // through the lists together, one hit per lane per step, so that its staged
-// terms are flushed at wavefront-uniform points.
+// terms are flushed at wavefront-uniform points.  kOrigin: also writes each
+// sample's origin gradient (overflowed samples: by the re-traversal).
+template <bool kOrigin>
 __global__ void __launch_bounds__(256) k_render_bwd_stored(RenderArgs a)
 {
     __shared__ WaveStage stages[4];
@@ -362,8 +500,9 @@ __global__ void __launch_bounds__(256) k_render_bwd_stored(RenderArgs a)
     const int64_t r = g < nray ? (a.order ? (int64_t)a.order[g] : g) : 0;
     const uint32_t nh = g < nray && a.S.n > 0 ? a.hits[r] : 0u;
     const float4 r0 = nh ? a.rays[3 * r] : make_float4(0.f, 0.f, 0.f, 0.f);
-    GradVisit v(a.S, a.tcut, a.g);
+    GradVisitT<kOrigin> v(a.S, a.tcut, a.g);
     v.stage = stage;
+    v.gmu = make_float3(0.f, 0.f, 0.f);
     uint32_t cnt = 0;
     float3 x = make_float3(0.f, 0.f, 0.f), d = x;
     const uint32_t *list = a.hits + nray + r * a.hcap;
@@ -387,6 +526,76 @@ __global__ void __launch_bounds__(256) k_render_bwd_stored(RenderArgs a)
         stage_sync(a.g.acc, stage, false);
     }
     stage_sync(a.g.acc, stage, true);
+    if constexpr (kOrigin) {
+        if (g < nray && !(nh > (uint32_t)a.hcap && r0.w != 0.0f))
+            a.gorig[r] = make_float4(-v.gmu.x, -v.gmu.y, -v.gmu.z, 0.0f);
+    }
+}
+
+// Gradients of the loss with respect to each pixel's shading state (x, the
+// stored normal and view direction, albedo, roughness, metallic), each
+// sample's direction and mixture pdf held fixed; one thread per pixel, its
+// samples in order.  The sample's weight f (n.w) / q is differentiated from
+// the regenerated direction and pdf (in double), its incident radiance L_i =
+// c_rt + T L_env comes from the forward's saved state, and x moves every
+// secondary ray's origin (the per-sample origin gradients of the backward
+// pass, a.gorig).  Unit n and wo are the stored vectors over their lengths,
+// so their gradients are projected off the unit vector and divided by them.
+__global__ void __launch_bounds__(256) k_render_shade_grad(RenderArgs a, ShadeGradOut o)
+{
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= (int64_t)a.H * a.W) return;
+    const int spp = a.nc + a.ng + a.ne;
+    ShadeGrad g{};
+    double gx[3] = {0.0, 0.0, 0.0};
+    Shade s;
+    const bool lit = load_pixel(a, p, s);
+    if (lit) {
+        const double gp[3] = {a.grad[3 * p], a.grad[3 * p + 1], a.grad[3 * p + 2]};
+        for (int j = 0; j < spp; ++j) {
+            const int64_t r = p * spp + j;
+            if (a.rays[3 * r].w == 0.0f) continue;  // below the horizon: not traced
+            const float4 go = a.gorig[r];
+            gx[0] += go.x; gx[1] += go.y; gx[2] += go.z;
+            V3 w;
+            float3 wf, wt;
+            double q;
+            draw(a, s, p, j, w, wf, q, wt);
+            if (!(q > 0.0)) continue;
+            const float4 sv = a.saved[r], r1 = a.rays[3 * r + 1], r2 = a.rays[3 * r + 2];
+            const float Li[3] = {sv.x + sv.w * r1.w, sv.y + sv.w * r2.x, sv.z + sv.w * r2.y};
+            double u[3];
+            for (int c = 0; c < 3; ++c) u[c] = gp[c] * (double)Li[c] / ((double)spp * q);
+            brdf_cos_backward(s.n, s.wo, w, s.alb, s.rough, s.metal, u, g);
+        }
+    }
+    V3 gn = v3(0.0, 0.0, 0.0), gw = gn;
+    if (lit) {
+        const double ln = sqrt((double)a.n[3 * p] * a.n[3 * p] + (double)a.n[3 * p + 1] * a.n[3 * p + 1] +
+                               (double)a.n[3 * p + 2] * a.n[3 * p + 2]);
+        const double lo = sqrt((double)a.wo[3 * p] * a.wo[3 * p] + (double)a.wo[3 * p + 1] * a.wo[3 * p + 1] +
+                               (double)a.wo[3 * p + 2] * a.wo[3 * p + 2]);
+        const double pn = dot(s.n, g.n), po = dot(s.wo, g.wo);
+        gn = v3((g.n.x - s.n.x * pn) / ln, (g.n.y - s.n.y * pn) / ln, (g.n.z - s.n.z * pn) / ln);
+        gw = v3((g.wo.x - s.wo.x * po) / lo, (g.wo.y - s.wo.y * po) / lo, (g.wo.z - s.wo.z * po) / lo);
+    }
+    auto put3 = [&](float *dst, double x, double y, double z) {
+        if (dst) { dst[3 * p] = (float)x; dst[3 * p + 1] = (float)y; dst[3 * p + 2] = (float)z; }
+    };
+    put3(o.x, gx[0], gx[1], gx[2]);
+    put3(o.n, gn.x, gn.y, gn.z);
+    put3(o.wo, gw.x, gw.y, gw.z);
+    put3(o.alb, g.alb.x, g.alb.y, g.alb.z);
+    if (o.rough) o.rough[p] = (float)g.rough;
+    if (o.metal) o.metal[p] = (float)g.metal;
+}
+
+hipError_t launch_render_shade_grad(const RenderArgs &a, const ShadeGradOut &o, hipStream_t st)
+{
+    const int64_t npix = (int64_t)a.H * a.W;
+    if (npix <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_render_shade_grad, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st, a, o);
+    return hipGetLastError();
 }
 
 __global__ void k_render_reduce(int64_t npix, int spp, const float4 *__restrict__ contrib, float *__restrict__ out)
@@ -416,13 +625,27 @@ static hipError_t go_render(const RenderArgs &a, int num_cu, hipStream_t st)
     return a.hits ? go_render_as<K, true>(a, num_cu, st) : go_render_as<K, false>(a, num_cu, st);
 }
 
+template <int K, bool kOrigin>
+static hipError_t go_render_bwd_as(const RenderArgs &a, int num_cu, hipStream_t st)
+{
+    const int64_t total = (int64_t)a.H * a.W * (a.nc + a.ng + a.ne);
+    const int nb = persistent_blocks(k_render_bwd<K, kOrigin>, num_cu, total);
+    hipLaunchKernelGGL((k_render_bwd<K, kOrigin>), dim3(nb), dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
 template <int K>
 static hipError_t go_render_bwd(const RenderArgs &a, int num_cu, hipStream_t st)
 {
+    if (a.gorig) return go_render_bwd_as<K, true>(a, num_cu, st);
+#if GRT_BWD_QUEUE
     const int64_t total = (int64_t)a.H * a.W * (a.nc + a.ng + a.ne);
-    const int nb = persistent_blocks(k_render_bwd<K>, num_cu, total);
-    hipLaunchKernelGGL(k_render_bwd<K>, dim3(nb), dim3(256), 0, st, a);
+    const int nb = persistent_blocks(k_render_bwd_q<K>, num_cu, total);
+    hipLaunchKernelGGL(k_render_bwd_q<K>, dim3(nb), dim3(256), 0, st, a);
     return hipGetLastError();
+#else
+    return go_render_bwd_as<K, false>(a, num_cu, st);
+#endif
 }
 
 hipError_t launch_render_backward_stored(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st)
@@ -433,7 +656,10 @@ hipError_t launch_render_backward_stored(const RenderArgs &a, const RenderWS &w,
     if (e != hipSuccess) return e;
     if ((e = launch_render_gen(a, st)) != hipSuccess) return e;
     if (a.order && (e = launch_ray_order(a, w, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_render_bwd_stored, dim3((unsigned)((nray + 255) / 256)), dim3(256), 0, st, a);
+    if (a.gorig)
+        hipLaunchKernelGGL(k_render_bwd_stored<true>, dim3((unsigned)((nray + 255) / 256)), dim3(256), 0, st, a);
+    else
+        hipLaunchKernelGGL(k_render_bwd_stored<false>, dim3((unsigned)((nray + 255) / 256)), dim3(256), 0, st, a);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     // samples whose list overflowed: re-traverse (the others return at once)
     RenderArgs b = a;

@@ -69,6 +69,10 @@ class grt_gbuffer_grad(C.Structure):
     _fields_ = [("x", VP), ("n", VP), ("albedo", VP), ("rough", VP), ("metal", VP), ("depth", VP), ("rgb", VP)]
 
 
+class grt_shading_grads(C.Structure):
+    _fields_ = [("x", VP), ("n", VP), ("wo", VP), ("albedo", VP), ("rough", VP), ("metal", VP)]
+
+
 class grt_attr_grads(C.Structure):
     _fields_ = [("albedo", VP), ("rough", VP), ("metal", VP)]
 
@@ -177,6 +181,8 @@ SIGNATURES = {
     "grt_render_mis_noalloc": (C.c_int, [VP, VP, P(grt_gbuffer), P(grt_mis_opts), VP, VP, VP]),
     "grt_render_mis_backward": (C.c_int, [VP, VP, P(grt_gbuffer), P(grt_mis_opts), VP, VP, P(grt_surfel_grads),
                                           VP, C.c_size_t, VP]),
+    "grt_render_mis_backward_shading": (C.c_int, [VP, VP, P(grt_gbuffer), P(grt_mis_opts), VP, VP,
+                                                  P(grt_surfel_grads), P(grt_shading_grads), VP, C.c_size_t, VP]),
     "grt_render_hit_list_bytes": (C.c_size_t, [C.c_int64, C.c_int, C.c_int]),
     "grt_server_job_bytes": (C.c_size_t, [P(grt_job)]),
     "grt_server_workspace_bytes": (C.c_size_t, [P(grt_server_opts)]),
@@ -393,6 +399,13 @@ def grt_render_mis_backward(scene, env, gbuf, opts, grad_rgb, saved, grads: grt_
 # --------------------------------------------------------------------------
 # Owners of handles and workspaces
 # --------------------------------------------------------------------------
+
+def grt_render_mis_backward_shading(scene, env, gbuf, opts, grad_rgb, saved, grads: grt_surfel_grads,
+                                    shade: grt_shading_grads, workspace, stream=None):
+    _check(load_library().grt_render_mis_backward_shading(scene, env, C.byref(gbuf), C.byref(opts), _ptr(grad_rgb),
+                                                          _ptr(saved), C.byref(grads), C.byref(shade),
+                                                          _ptr(workspace), workspace.numel(), _stream(stream)))
+
 
 def _workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
@@ -876,6 +889,27 @@ def render_mis_backward(scene: Scene, env: Env, gb: GBuffer, grad_rgb, saved, sp
     return grads
 
 
+SHADING_KEYS = ("x", "n", "wo", "albedo", "rough", "metal")
+
+
+def render_mis_backward_shading(scene: Scene, env: Env, gb: GBuffer, grad_rgb, saved, split=(16, 8, 8), seed=0,
+                                job=0, t_min=1e-3, t_cut=1e-3, k=16, grads=None, stream=None, hits=None, hit_cap=0):
+    """render_mis_backward plus the gradients with respect to the shading
+    state (each sample's direction and pdf held fixed): returns (grads,
+    shade) with shade = {x, n, wo, albedo [npix,3], rough, metal [npix]}."""
+    dev = gb.x.device
+    if grads is None:
+        grads = zero_grads(scene.n, dev)
+    shade = {key: torch.empty((gb.npix, 3) if key not in ("rough", "metal") else (gb.npix,), device=dev)
+             for key in SHADING_KEYS}
+    opts = make_mis_opts(split, seed, job, t_min, t_cut, k, None, hits, hit_cap)
+    ws = _workspace(grt_render_workspace_bytes(gb.npix, sum(split)), dev)
+    grt_render_mis_backward_shading(scene.handle, env.handle, gb.struct(), opts, grad_rgb.contiguous(), saved,
+                                    _grads_struct(grads), grt_shading_grads(*(_ptr(shade[key]) for key in SHADING_KEYS)),
+                                    ws, stream)
+    return grads, shade
+
+
 # --------------------------------------------------------------------------
 # Autograd (Sec. 3.2: gradients backpropagate through the secondary rays)
 # --------------------------------------------------------------------------
@@ -928,6 +962,38 @@ class RenderMISFn(torch.autograd.Function):
                                 hits=ctx_.hits, hit_cap=hit_cap)
         return (g["means"], g["scales"], g["quats"], g["opacity"], g["rgb"], None, None, None, None, None, None, None,
                 None, None)
+
+
+class RenderMISShadedFn(torch.autograd.Function):
+    """c_pbr image as a function of the surfel parameters and of the shading
+    state (x, n, wo, albedo, rough, metal), e.g. the maps GBufferFn returns,
+    so that a loss on the render reaches the surfels both through the
+    secondary rays and through the primary G-buffer.  Each sample's direction
+    and mixture pdf are held fixed in the backward."""
+
+    @staticmethod
+    def forward(ctx_, means, scales, quats, opacity, rgb, x, n, wo, albedo, rough, metal, valid, gctx, env, H, W,
+                split, seed, k, alpha_min, hit_cap=0):
+        scene = Scene(gctx, means.detach().contiguous(), scales.detach().contiguous(), quats.detach().contiguous(),
+                      opacity.detach().contiguous(), rgb.detach().contiguous(), alpha_min)
+        gb = GBuffer(H, W, *(t.detach().contiguous() for t in (x, n, wo, albedo, rough, metal)), valid.contiguous())
+        hits = make_hit_list(gb.npix, sum(split), hit_cap, gb.x.device) if hit_cap > 0 else None
+        res = render_mis(scene, env, gb, split=split, seed=seed, k=k, save=True, hits=hits, hit_cap=hit_cap)
+        ctx_.scene, ctx_.env, ctx_.gb, ctx_.cfg = scene, env, gb, (split, seed, k, hit_cap)
+        ctx_.saved_state, ctx_.hits = res["saved"], hits
+        return res["rgb"]
+
+    @staticmethod
+    def backward(ctx_, g_rgb):
+        split, seed, k, hit_cap = ctx_.cfg
+        kw = dict(split=split, seed=seed, k=k, hits=ctx_.hits, hit_cap=hit_cap)
+        if any(ctx_.needs_input_grad[5:11]):
+            g, sh = render_mis_backward_shading(ctx_.scene, ctx_.env, ctx_.gb, g_rgb, ctx_.saved_state, **kw)
+            gs = tuple(sh[key] for key in SHADING_KEYS)
+        else:
+            g = render_mis_backward(ctx_.scene, ctx_.env, ctx_.gb, g_rgb, ctx_.saved_state, **kw)
+            gs = (None,) * 6
+        return (g["means"], g["scales"], g["quats"], g["opacity"], g["rgb"]) + gs + (None,) * 10
 
 
 class GBufferFn(torch.autograd.Function):

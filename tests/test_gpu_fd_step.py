@@ -1,0 +1,225 @@
+"""The differentiable step on the 300k-surfel scene (800x800 G-buffer, 32 spp
+split 16/8/8, 256x512 environment; Sec. 3.2, Eq. mis) checked against
+central finite differences.  The loss is the L2 distance to a target
+rendered from the surfels with perturbed radiance and opacity (sigma 0.05),
+summed over a seeded subset of 512 covered pixels.  The GPU renders and
+differentiates the whole image (the upstream gradient is zero off the
+subset), by re-traversal and from stored hit lists; 64 random surfels, each
+composited by at least one of the subset's samples, are differentiated
+numerically with the oracle's forward.
+
+The pixels that composite a chosen surfel are disjoint between chosen
+surfels, so one perturbed evaluation serves all 64 at once: the loss over
+surfel i's pixels changes only with surfel i.  The hit sets do not change
+under the steps: on every sample of the chosen pixels, the chosen surfels'
+hit decisions and their order against their neighbours in depth are the
+same at every evaluated point as at the base point (checked by tracing them
+and their neighbours alone), and the cutoff's stop has a relative margin of
+1e-3.  Steps: 1e-6 for means (hits lie within a centimetre of the G-buffer
+point, where a larger step reorders them), 1e-5 for quaternions and
+opacity, 1e-4 of the scale for scales, 1e-3 for the radiance (linear); the
+difference quotient divides by the step as stored in float32.  Bar: max(1e-3 max(|g|, 1e-2 max|g|_block), 1e-5 S) per element,
+S the oracle's error scale, for the GPU against the differences, and the
+oracle's own gradient against them."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2607_22780_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+SPLIT, SEED = (16, 8, 8), 0
+BLOCKS = dict(means=(0, 3), scales=(3, 5), quats=(5, 9), opacity=(9, 10), rgb=(10, 13))
+NPIX, NSURF, MAXPIX = 512, 64, 3
+
+
+def fd_case():
+    """The scene, G-buffer and environment of the step, the pixel subset,
+    the oracle's image and target on it, and the chosen surfels with their
+    pixels (indices into the subset)."""
+    s = W.scene1()
+    gb = W.gbuffer1(800, 800)
+    env = W.envmap(256, 512, seed=0)
+    g = np.random.default_rng(12)
+    pix = np.sort(g.choice(np.nonzero(gb.valid)[0], NPIX, replace=False))
+    base = O.render_mis(s, gb, env, SPLIT, SEED, pix=pix, dump=True)
+    target = O.render_mis(W.perturbed(s), gb, env, SPLIT, SEED, pix=pix)
+    # each traced sample's composited hits
+    spp = sum(SPLIT)
+    tr = base["traced"].reshape(-1).astype(bool) & (base["q"].reshape(-1) > 0)
+    org = np.repeat(gb.x[pix], spp, axis=0)[tr]
+    hits = O.trace(s, org, base["dir"].reshape(-1, 3)[tr], t_min=1e-3, cap=256)
+    assert hits["nhit"].max() <= 256
+    sample_px = np.repeat(np.arange(NPIX), spp)[tr]
+    cut_ok = base["margins"][..., 3].reshape(-1)[tr] > 1e-3  # the cutoff's stop stays put
+    by_surfel = {}
+    for r in range(len(sample_px)):
+        for i in hits["ids"][r, :hits["nhit"][r]]:
+            by_surfel.setdefault(int(i), set()).add(int(sample_px[r]))
+    dirs = base["dir"].reshape(-1, 3)[tr]
+    picked, used = [], set()
+    for i in g.permutation(sorted(by_surfel)):
+        i = int(i)
+        px = by_surfel[i]
+        if len(px) > MAXPIX or (px & used):
+            continue
+        rows = np.nonzero(np.isin(sample_px, sorted(px)))[0]
+        if not cut_ok[rows].all() or not in_depth_order(i, hits, rows):
+            continue
+        picked.append((i, sorted(px), rows))
+        used |= px
+        if len(picked) == 2 * NSURF:
+            break
+    # the picked surfels' hit decisions, and their order against their
+    # neighbours in depth, on every sample of the picked pixels, at every
+    # point the differences evaluate (all picked surfels moved at once),
+    # against the base point: a trace of the picked surfels and their
+    # neighbours alone
+    ids = np.array([i for i, _, _ in picked])
+    rows = np.concatenate([r for _, _, r in picked])
+    owner = np.concatenate([np.full(len(r), n) for n, (_, _, r) in enumerate(picked)])
+    near = set()
+    for r in rows:
+        lst = hits["ids"][r, :hits["nhit"][r]].tolist()
+        for j, i in enumerate(lst):
+            if i in set(ids.tolist()):
+                near.update(lst[max(j - 1, 0):j + 2])
+    others = np.array(sorted(near - set(ids.tolist())), dtype=np.int64)
+    sub = W.Surfels(*(np.ascontiguousarray(a[np.concatenate([ids, others])]) for a in s.arrays()))
+    ref = composited_order(sub, org[rows], dirs[rows])
+    bad = np.zeros(len(picked), bool)
+    h = step_sizes(s, ids)
+    for k in range(13):
+        for sgn in (1.0, -1.0):
+            moved = composited_order(perturb(sub, np.arange(len(ids)), k, sgn * h[:, k]), org[rows], dirs[rows])
+            bad[owner[[a != b for a, b in zip(ref, moved)]]] = True
+    chosen = [(i, px) for (i, px, _), b in zip(picked, bad) if not b][:NSURF]
+    assert len(chosen) == NSURF, len(chosen)
+    return s, gb, env, pix, base, target, chosen
+
+
+def composited_order(sub, org, dirs):
+    """Per ray, the surfels of `sub` it composites, in order."""
+    t = O.trace(sub, org, dirs, t_min=1e-3, cap=len(sub.opacity))
+    return [tuple(t["ids"][r, :t["nhit"][r]].tolist()) for r in range(len(org))]
+
+
+def perturb(s, ids, k, dx):
+    """A copy of the surfels with parameter slot k of `ids` moved by dx
+    (rounded to float32)."""
+    sp = W.Surfels(*(np.array(a, copy=True) for a in s.arrays()))
+    a, c = slot_view(sp, k)
+    if c is None:
+        a[ids] = (a[ids].astype(np.float64) + dx).astype(np.float32)
+    else:
+        a[ids, c] = (a[ids, c].astype(np.float64) + dx).astype(np.float32)
+    return sp
+
+
+def in_depth_order(i, hits, rows):
+    """Where surfel i is composited, its depth is 1e-4 or more from its
+    neighbours' in the compositing order."""
+    for r in rows:
+        ids, tau = hits["ids"][r, :hits["nhit"][r]], hits["tau"][r, :hits["nhit"][r]]
+        for j in np.nonzero(ids == i)[0]:
+            gaps = [abs(tau[j] - tau[j2]) for j2 in (j - 1, j + 1) if 0 <= j2 < len(tau)]
+            if gaps and min(gaps) < 1e-4:
+                return False
+    return True
+
+
+def step_sizes(s, ids):
+    """Per chosen surfel and parameter slot (13), the nominal step."""
+    h = np.empty((len(ids), 13))
+    h[:, 0:3] = 1e-6
+    h[:, 3:5] = 1e-4 * s.scales[ids]
+    h[:, 5:9] = 1e-5
+    h[:, 9] = 1e-5
+    h[:, 10:13] = 1e-3
+    return h
+
+
+def slot_view(s, k):
+    """(array, column) of parameter slot k."""
+    if k < 3:
+        return s.means, k
+    if k < 5:
+        return s.scales, k - 3
+    if k < 9:
+        return s.quats, k - 5
+    if k == 9:
+        return s.opacity, None
+    return s.rgb, k - 10
+
+
+def finite_differences(s, gb, env, pix, target, chosen):
+    """[64, 13] central differences of the subset loss, one pair of
+    evaluations per parameter slot for all chosen surfels at once."""
+    ids = np.array([i for i, _ in chosen])
+    local = sorted({p for _, px in chosen for p in px})
+    where = {p: j for j, p in enumerate(local)}
+    sub = pix[local]
+    h = step_sizes(s, ids)
+    fd = np.zeros((len(ids), 13))
+    for k in range(13):
+        vals, steps = [], []
+        for sgn in (1.0, -1.0):
+            sp = perturb(s, ids, k, sgn * h[:, k])
+            a, c = slot_view(sp, k)
+            steps.append((a[ids] if c is None else a[ids, c]).astype(np.float64))
+            img = O.render_mis(sp, gb, env, SPLIT, SEED, pix=sub)
+            vals.append(((img - target[local]) ** 2).sum(axis=1))
+        dstep = steps[0] - steps[1]
+        assert np.all(dstep > 0)
+        for n, (_, px) in enumerate(chosen):
+            rows = [where[p] for p in px]
+            fd[n, k] = (vals[0][rows].sum() - vals[1][rows].sum()) / dstep[n]
+    return fd
+
+
+@pytest.fixture(scope="module")
+def fd_ref():
+    s, gb, env, pix, base, target, chosen = fd_case()
+    fd = finite_differences(s, gb, env, pix, target, chosen)
+    # the oracle's own gradient of the same loss (on the pixels that matter)
+    local = sorted({p for _, px in chosen for p in px})
+    up = 2.0 * (base["rgb"] - target)
+    ids = np.array([i for i, _ in chosen])
+    g13, g13_abs = O.render_mis_backward(s, gb, env, SPLIT, SEED, up[local], pix=pix[local], with_abs=True)
+    return dict(s=s, gb=gb, env=env, pix=pix, up=up, ids=ids, fd=fd, g13=g13[ids], g13_abs=g13_abs[ids])
+
+
+def check(got, ref, name):
+    from gpu_util import grad_close
+    for b, (lo, hi) in BLOCKS.items():
+        grad_close(got[:, lo:hi], ref["fd"][:, lo:hi], f"{name} {b}", ref["g13_abs"][:, lo:hi])
+
+
+def test_oracle_gradient_against_differences(fd_ref):
+    check(fd_ref["g13"], fd_ref, "oracle")
+
+
+@pytest.mark.parametrize("cap", [0, 64])
+def test_gpu_gradient_against_differences(fd_ref, cap):
+    """Re-traversal (cap 0) and stored hit lists (64 per sample, the rest
+    re-traversed) over the whole 800x800 image."""
+    from paper_2607_22780_amd import grt
+    from gpu_util import t, scene_tensors
+    ctx = grt.Context(0)
+    s, gb, env, pix = fd_ref["s"], fd_ref["gb"], fd_ref["env"], fd_ref["pix"]
+    scene = grt.Scene(ctx, *scene_tensors(s))
+    E = grt.Env(ctx, t(env))
+    dev = torch.device("cuda", 0)
+    G = grt.GBuffer.from_numpy(gb, dev)
+    spp = sum(SPLIT)
+    hits = grt.make_hit_list(gb.npix, spp, cap, dev) if cap else None
+    fwd = grt.render_mis(scene, E, G, split=SPLIT, seed=SEED, k=12, save=True, hits=hits, hit_cap=cap)
+    up = torch.zeros(gb.npix, 3, device=dev)
+    up[torch.from_numpy(pix).to(dev)] = t(fd_ref["up"].astype(np.float32))
+    gg = grt.render_mis_backward(scene, E, G, up, fwd["saved"], split=SPLIT, seed=SEED, k=8, hits=hits, hit_cap=cap)
+    torch.cuda.synchronize()
+    ids = torch.from_numpy(fd_ref["ids"]).to(dev)
+    got = np.concatenate([gg[b][ids].reshape(len(ids), -1).cpu().numpy().astype(np.float64) for b in BLOCKS], axis=1)
+    check(got, fd_ref, f"gpu cap={cap}")
