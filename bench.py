@@ -324,6 +324,16 @@ def _gbuffer_task(key):
     return key, W.gbuffer3(res, res, cam_stream=10 + cam)
 
 
+def serve_rate(n, load, mrays_s, per_request_s=2e-3):
+    """The Poisson rate at which one launch per request would be busy `load`
+    of the time: mean service = rays / (the relighting leg's rate) plus a
+    fixed cost per request (uploads, tables, sort, launches)."""
+    from paper_2607_22780_amd import workloads as W
+    reqs = W.requests4(n, 1.0)
+    mean_s = float(np.mean([q.res * q.res * q.spp / (mrays_s * 1e6) + per_request_s for q in reqs]))
+    return load / mean_s
+
+
 def serve_inputs(n, rate):
     """Relighting requests over the room scene: Poisson arrivals; resolution,
     spp, camera and a 128x256 environment map per request."""
@@ -474,8 +484,11 @@ def main():
     ap.add_argument("--hit-cap", type=int, default=64, help="hits stored per sample in the stored-list legs")
     ap.add_argument("--serve-requests", type=int, default=220)
     ap.add_argument("--serve-warm", type=int, default=20)
-    ap.add_argument("--serve-rate", type=float, default=5.9,
-                    help="Poisson arrival rate, requests/s (5.9: about 70%% load for one launch per request)")
+    ap.add_argument("--serve-rate", type=float, default=0.0,
+                    help="Poisson arrival rate, requests/s (0: --serve-load of one launch per request's capacity)")
+    ap.add_argument("--serve-load", type=float, default=0.7,
+                    help="offered load when the rate is derived: the rate at which one launch per request, at the "
+                         "relighting leg's measured Mrays/s plus 2 ms per request, would be busy this share of time")
     ap.add_argument("--serve-slack", type=float, default=-1.0, help="server deadline seconds per ray (-1: default)")
     ap.add_argument("--serve-epoch", type=int, default=0, help="server rays per epoch (0: default)")
     ap.add_argument("--count-work", action="store_true", help="recount per-ray work with the oracle and exit")
@@ -510,10 +523,10 @@ def main():
     params = [t(a).requires_grad_(True) for a in s.arrays()]
     upstream = t(np.random.default_rng(0).normal(0, 1, (gb.npix, 3)).astype(np.float32))
 
-    def step():
+    def step(timers=None):
         for p in params:
             p.grad = None
-        img = grt.RenderMISFn.apply(*params, ctx, E, G, SPLIT, SEED, args.k, 1.0 / 255.0, 0, args.k_bwd)
+        img = grt.RenderMISFn.apply(*params, ctx, E, G, SPLIT, SEED, args.k, 1.0 / 255.0, 0, args.k_bwd, timers)
         loss = (img * upstream).sum()
         loss.backward()
         return img
@@ -523,12 +536,18 @@ def main():
         step()
     torch.cuda.synchronize()
 
+    # the trace kernels of every timed step, timed by the library with HIP
+    # events on their launch stream (a timer pair per step: no sync inside)
+    timers = [(grt.Timer(ctx), grt.Timer(ctx)) for _ in range(args.steps)]
     log(f"bench: timing {args.steps} steps")
     t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
+    for i in range(args.steps):
+        step(timers[i])
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / max(args.steps, 1)
+    kern_fwd_ms = float(np.mean([a.ms() for a, _ in timers])) if timers else None
+    kern_bwd_ms = float(np.mean([b.ms() for _, b in timers])) if timers else None
+    del timers
 
     # per-kernel timing with events on the launch stream (torch's current one)
     st = torch.cuda.current_stream()
@@ -651,8 +670,10 @@ def main():
     wc = load_work("room1m_1024px_32spp")
     if wc:
         bf, bb = bytes_per_ray(wc)
-        dominant = "bwd" if bwd_ms >= fwd_ms else "fwd"
-        ms = bwd_ms if dominant == "bwd" else fwd_ms
+        # the trace kernels alone, averaged over the timed steps
+        kf, kb = kern_fwd_ms, kern_bwd_ms
+        dominant = "bwd" if kb >= kf else "fwd"
+        ms = kb if dominant == "bwd" else kf
         per_ray = bb if dominant == "bwd" else bf
         kname = "k_render_bwd" if dominant == "bwd" else "k_render"
         traffic = l2_hit = None
@@ -666,7 +687,9 @@ def main():
                     traffic=traffic, l2_hit=l2_hit, kernel=kname, bytes_per_ray=round(per_ray, 1),
                     kernel_ms=round(ms, 3), traffic_gbs=round(traffic / (ms * 1e-3) / 1e9, 1) if traffic else None,
                     traced_fraction=round(wc["traced_fraction"], 4), work_sample_rays=wc.get("sample_rays"),
-                    fwd_frac=roofline(bf, rays, fwd_ms)["frac"])
+                    kernel_timing=f"library HIP events around the trace kernel on its stream, mean of the "
+                                  f"{args.steps} timed steps",
+                    fwd_kernel_ms=round(kf, 3), fwd_frac=roofline(bf, rays, kf)["frac"])
 
     log("bench: device copy (achieved bandwidth)")
     copy = calib_copy()
@@ -674,9 +697,14 @@ def main():
     serve = None
     if not args.no_serve:
         log("bench: generating relighting requests")
-        reqs, gbs, envs = serve_inputs(args.serve_requests, args.serve_rate)
+        rate = args.serve_rate
+        if rate <= 0.0:
+            rate = serve_rate(args.serve_requests, args.serve_load, relight["mrays_s"]) if relight else 3.7
+        reqs, gbs, envs = serve_inputs(args.serve_requests, rate)
         serve = serve_leg(ctx, scene, args.k, reqs, gbs, envs, args.serve_warm, args.serve_slack, args.serve_epoch,
                           extra=args.serve_extra)
+        serve["arrival_rate_hz"] = round(rate, 4)
+        serve["offered_load"] = args.serve_load if args.serve_rate <= 0.0 and relight else None
         del reqs, gbs, envs
 
     cpu = None

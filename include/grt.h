@@ -411,7 +411,9 @@ typedef struct {
  *   uint32 record positions in compositing order (positions past hit_cap are
  *   not stored).  grt_render_mis writes them; grt_render_mis_backward given
  *   them differentiates from the stored lists instead of re-traversing, and
- *   re-traverses only samples whose count exceeds hit_cap.  NULL: not used. */
+ *   re-traverses only samples whose count exceeds hit_cap.  NULL: not used.
+ * timer: optional kernel timer (grt_timer_create), NULL: none. */
+typedef struct grt_timer grt_timer;
 typedef struct {
     int n_cos, n_ggx, n_env;
     uint64_t seed;
@@ -422,7 +424,20 @@ typedef struct {
     float *sample_dump;
     uint32_t *hit_list;
     int hit_cap;
+    grt_timer *timer;
 } grt_mis_opts;
+
+/* Kernel timer: two HIP events that grt_render_mis, grt_render_mis_noalloc
+ * and grt_render_mis_backward(_shading) record on their stream around the
+ * persistent trace kernel(s) alone (after the sample generation and the
+ * coherent-order sort, before the per-pixel reduction or the gradient
+ * application), when opts->timer is set; NULL: nothing recorded.  A timer
+ * belongs to the context's device; one call at a time may use it.
+ * grt_timer_ms waits for the last recording to complete and returns its
+ * elapsed milliseconds (GRT_ERR_INVALID if nothing was recorded yet). */
+int grt_timer_create(grt_ctx *ctx, grt_timer **out);
+int grt_timer_ms(grt_timer *timer, float *ms);
+int grt_timer_destroy(grt_timer *timer);
 
 /* Bytes of a stored hit list for npix * spp samples (4 * nray * (1 + hit_cap)),
  * 0 on bad arguments. */
@@ -644,9 +659,12 @@ int grt_denoise(grt_ctx *ctx, int H, int W, const float *rgb, const float *depth
  * workspace:     device memory the caller owns (e.g. a torch tensor), 256-byte
  *                aligned, at least grt_server_workspace_bytes(opts) bytes,
  *                borrowed until grt_server_destroy returns: the request pool,
- *                the epochs' job and chunk tables and their claim counters
- *                all live there (the server allocates no device memory; it
- *                holds a few pinned host buffers of tables and flags). */
+ *                the epochs' job and chunk tables and their claim counters,
+ *                and the DFG table that every relighting request shares (it
+ *                depends on nothing but its resolution, so the server builds
+ *                it once) all live there (the server allocates no device
+ *                memory; it holds a few pinned host buffers of tables and
+ *                flags). */
 typedef struct {
     size_t mem_budget;
     int max_jobs;

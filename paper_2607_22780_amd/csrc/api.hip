@@ -24,6 +24,20 @@ std::mutex g_scratch_mu;
 void *g_scratch_dev[kMaxDevices] = {};
 }  // namespace
 
+// A kernel timer: events recorded around a call's persistent trace kernels.
+struct grt_timer {
+    grt_ctx *ctx;
+    grt::KernelTimer ev;
+    bool recorded = false;
+};
+
+static const grt::KernelTimer *use_timer(const grt_mis_opts *o)
+{
+    if (!o || !o->timer) return nullptr;
+    o->timer->recorded = true;
+    return &o->timer->ev;
+}
+
 struct grt_scene {
     grt_ctx *ctx;
     grt_surfels s;
@@ -215,6 +229,50 @@ int grt_ctx_create(int device, grt_ctx **out)
 int grt_ctx_destroy(grt_ctx *ctx)
 {
     delete ctx;
+    return GRT_OK;
+}
+
+int grt_timer_create(grt_ctx *ctx, grt_timer **out)
+{
+    if (!ctx || !out) return fail(GRT_ERR_INVALID, "ctx/out is NULL");
+    *out = nullptr;
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    grt_timer *t = new (std::nothrow) grt_timer();
+    if (!t) return fail(GRT_ERR_OOM, "timer");
+    t->ctx = ctx;
+    hipError_t e = hipEventCreate(&t->ev.begin);
+    if (e == hipSuccess) {
+        e = hipEventCreate(&t->ev.end);
+        if (e != hipSuccess) (void)hipEventDestroy(t->ev.begin);
+    }
+    if (e != hipSuccess) {
+        delete t;
+        return hip_fail(e, "hipEventCreate");
+    }
+    *out = t;
+    return GRT_OK;
+}
+
+int grt_timer_ms(grt_timer *t, float *ms)
+{
+    if (!t || !ms) return fail(GRT_ERR_INVALID, "timer/ms is NULL");
+    if (!t->recorded) return fail(GRT_ERR_INVALID, "the timer has recorded nothing yet");
+    int rc = set_device(t->ctx);
+    if (rc) return rc;
+    hipError_t e = hipEventSynchronize(t->ev.end);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, t->ev.begin, t->ev.end);
+    if (e != hipSuccess) return hip_fail(e, "timer read");
+    return GRT_OK;
+}
+
+int grt_timer_destroy(grt_timer *t)
+{
+    if (!t) return GRT_OK;
+    (void)set_device(t->ctx);
+    (void)hipEventDestroy(t->ev.begin);
+    (void)hipEventDestroy(t->ev.end);
+    delete t;
     return GRT_OK;
 }
 
@@ -810,7 +868,9 @@ int grt_render_mis(const grt_scene *scene, const grt_env *env, const grt_gbuffer
     a.rays = w.rays;
     a.order = a.S.n >= 2 ? w.v1 : nullptr;
     if ((rc = set_device(scene->ctx))) return rc;
-    hipError_t e = grt::launch_render(a, w, opts->k, scene->ctx->num_cu, (hipStream_t)stream);
+    if (opts->timer && opts->timer->ctx->device != scene->ctx->device)
+        return fail(GRT_ERR_INVALID, "the timer belongs to another device");
+    hipError_t e = grt::launch_render(a, w, opts->k, scene->ctx->num_cu, (hipStream_t)stream, use_timer(opts));
     if (e != hipSuccess) return hip_fail(e, "render launch");
     return GRT_OK;
 }
@@ -862,12 +922,15 @@ static int render_backward(const grt_scene *scene, const grt_env *env, const grt
     // the backward does not use the contribution slots: they hold the
     // per-sample origin gradients when the shading state is differentiated
     a.gorig = shade ? w.contrib : nullptr;
+    if (opts->timer && opts->timer->ctx->device != scene->ctx->device)
+        return fail(GRT_ERR_INVALID, "the timer belongs to another device");
     if ((rc = set_device(scene->ctx))) return rc;
     const hipStream_t st = (hipStream_t)stream;
+    const grt::KernelTimer *tm = use_timer(opts);
     hipError_t e = grt::launch_grad_lines_zero(a.g.acc, scene->s.n, st);
     if (e == hipSuccess)
-        e = a.hits ? grt::launch_render_backward_stored(a, w, opts->k, scene->ctx->num_cu, st)
-                   : grt::launch_render_backward(a, w, opts->k, scene->ctx->num_cu, st);
+        e = a.hits ? grt::launch_render_backward_stored(a, w, opts->k, scene->ctx->num_cu, st, tm)
+                   : grt::launch_render_backward(a, w, opts->k, scene->ctx->num_cu, st, tm);
     if (e == hipSuccess) e = grt::launch_grad_lines_apply(a.g, scene->s.n, st);
     if (e == hipSuccess && shade) {
         const grt::ShadeGradOut o{shade->x, shade->n, shade->wo, shade->albedo, shade->rough, shade->metal};

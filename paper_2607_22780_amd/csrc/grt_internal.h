@@ -296,7 +296,10 @@ struct DenoiseArgs {
     float *out;
 };
 hipError_t launch_denoise(const DenoiseArgs &a, hipStream_t st);
-hipError_t launch_env_prefilter(const float *rgb, int H, int W, const EnvWS &w, hipStream_t st);
+// The prefiltered direction tables of an environment, and (lut) the DFG
+// table, which depends on nothing but its resolution.
+hipError_t launch_env_prefilter(const float *rgb, int H, int W, const EnvWS &w, hipStream_t st, bool lut = true);
+hipError_t launch_dfg_lut(float *lut, hipStream_t st);
 
 struct RenderArgs {
     SceneDev S;
@@ -377,10 +380,17 @@ hipError_t launch_render_relight_mesh(const RenderArgs &a, const MeshTraceArgs &
 // the Morton code of the origin in the scene's root box (untraced last).
 // Sets nothing on the host; a.order must point at w.v1 afterwards.
 hipError_t launch_ray_order(const RenderArgs &a, const RenderWS &w, hipStream_t st);
-hipError_t launch_render(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st);
-hipError_t launch_render_backward(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st);
+// Events recorded around the persistent trace kernel(s) of a launch (null: none).
+struct KernelTimer {
+    hipEvent_t begin, end;
+};
+hipError_t launch_render(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st,
+                         const KernelTimer *tm = nullptr);
+hipError_t launch_render_backward(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st,
+                                  const KernelTimer *tm = nullptr);
 // Backward from stored hit lists (a.hits); re-traverses overflowing samples.
-hipError_t launch_render_backward_stored(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st);
+hipError_t launch_render_backward_stored(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st,
+                                         const KernelTimer *tm = nullptr);
 // After a backward with a.gorig set: the gradients with respect to each
 // pixel's shading state (null outputs are not written).
 struct ShadeGradOut {

@@ -161,7 +161,10 @@ struct WaveStageN {
     float v[Cap * kStageStride];
     int count;
 };
-using WaveStage = WaveStageN<128>;
+#ifndef GRT_STAGE_CAP
+#define GRT_STAGE_CAP 128
+#endif
+using WaveStage = WaveStageN<GRT_STAGE_CAP>;
 
 // Active lanes: stage one hit each (13 terms of surfel id).
 template <class Stage>
@@ -324,100 +327,6 @@ struct GradVisitT {
 };
 
 using GradVisit = GradVisitT<false>;
-
-// The radiance backward with each hit's chain rule taken off the traversal.
-// Compositing a hit in a step runs on the lanes that have one to composite,
-// often a few of the wavefront; only what must follow the ray in order stays
-// there (alpha, the running sum P, T and dL/dalpha).  The hit is queued per
-// wavefront -- record position, sample index, dL/dalpha and its weight T
-// alpha -- and the chain to the surfel's parameters runs later for 64 queued
-// hits at once, one per lane, at a wavefront-uniform point.  The result is
-// the same terms as GradVisit's; only the order of the atomic adds differs.
-constexpr int kQueueCap = 128;  // a power of two; >= 63 + 64 (a drain leaves < 64, a step adds <= 64)
-struct GradQueue {
-    uint32_t p[kQueueCap];
-    uint32_t r[kQueueCap];
-    float dA[kQueueCap];
-    float w[kQueueCap];
-    int head, count;
-};
-
-__device__ __forceinline__ void queue_init(GradQueue *q)
-{
-    if ((threadIdx.x & 63) == 0) {
-        *(volatile int *)&q->head = 0;
-        *(volatile int *)&q->count = 0;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-}
-
-// Active lanes: queue one hit each.
-__device__ __forceinline__ void queue_push(GradQueue *q, uint32_t p, uint32_t r, float dA, float w)
-{
-    const uint64_t m = __ballot(1);
-    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-    volatile int *cnt = &q->count;
-    const int n = __builtin_amdgcn_readfirstlane(*cnt);
-    const int head = __builtin_amdgcn_readfirstlane(*(volatile int *)&q->head);
-    const int e = (head + n + rank) & (kQueueCap - 1);
-    reinterpret_cast<volatile uint32_t *>(q->p)[e] = p;
-    reinterpret_cast<volatile uint32_t *>(q->r)[e] = r;
-    reinterpret_cast<volatile float *>(q->dA)[e] = dA;
-    reinterpret_cast<volatile float *>(q->w)[e] = w;
-    if (rank == 0) *cnt = n + __popcll(m);
-}
-
-struct GradVisitQ {
-    const float4 *col;
-    float tcut;
-    GradQueue *q = nullptr;
-    uint32_t r;  // the lane's sample
-    float3 o, d, gC, Cf;
-    float gT, Tf;
-    float T, Td;
-    float3 P;
-
-    __device__ GradVisitQ() {}
-    __device__ GradVisitQ(const SceneDev &S, float t_cut) : col(S.col), tcut(t_cut) {}
-
-    __device__ __forceinline__ void reset(float3 o_, float3 d_, float3 gC_, float gT_, float3 Cf_, float Tf_,
-                                          uint32_t r_)
-    {
-        o = o_;
-        d = d_;
-        gC = gC_;
-        gT = gT_;
-        Cf = Cf_;
-        Tf = Tf_;
-        r = r_;
-        T = 1.0f;
-        Td = 1.0f;
-        P = make_float3(0.f, 0.f, 0.f);
-    }
-
-    __device__ __forceinline__ bool operator()(uint32_t p, uint32_t id, float tau, const float4 r0, const float4 r1,
-                                               const float4 r2, const float4 r3, float crho2)
-    {
-        const float4 c = col[p];
-        const float op = r1.w;
-        HitGeo hg;
-        value_geo(r0, r1, r2, r3, o, d, hg);
-        const float G = expf(-0.5f * hg.rho2);
-        const float a = op * G;
-        const float w = T * a;
-        P.x += w * c.x; P.y += w * c.y; P.z += w * c.z;
-        float dA = T * (gC.x * c.x + gC.y * c.y + gC.z * c.z);
-        const float om = 1.0f - a;
-        if (om >= 1e-6f) {
-            float behind = gC.x * (Cf.x - P.x) + gC.y * (Cf.y - P.y) + gC.z * (Cf.z - P.z) + gT * Tf;
-            dA -= behind / om;
-        }
-        queue_push(q, p, r, dA, w);
-        T = T * (1.0f - a);
-        Td = trans_step(Td, hit_alpha(op, crho2));
-        return Td < tcut;
-    }
-};
 
 // Backward of the primary-ray G-buffer (Eq. deferred_maps on traced camera
 // rays).  Every map is a ratio S_f / W of blended sums S_f = sum_k w_k f_k,

@@ -175,10 +175,17 @@ __global__ void __launch_bounds__(256) k_dfg_lut(float *__restrict__ lut)
     }
 }
 
-hipError_t launch_env_prefilter(const float *rgb, int H, int W, const EnvWS &w, hipStream_t st)
+hipError_t launch_env_prefilter(const float *rgb, int H, int W, const EnvWS &w, hipStream_t st, bool lut)
 {
     hipLaunchKernelGGL(k_env_prefilter, dim3(kPfH * kPfW), dim3(64), 0, st, H, W, rgb, w.Ed, w.Es);
-    hipLaunchKernelGGL(k_dfg_lut, dim3(kLutN * kLutN), dim3(256), 0, st, w.lut);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || !lut) return e;
+    return launch_dfg_lut(w.lut, st);
+}
+
+hipError_t launch_dfg_lut(float *lut, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_dfg_lut, dim3(kLutN * kLutN), dim3(256), 0, st, lut);
     return hipGetLastError();
 }
 
@@ -320,117 +327,6 @@ struct RenderBwdJob {
     int64_t cur = 0;  // the lane's sample (kOrigin)
 };
 
-#ifndef GRT_BWD_QUEUE
-#define GRT_BWD_QUEUE 0
-#endif
-#ifndef GRT_BWDQ_WAVES
-#define GRT_BWDQ_WAVES 3
-#endif
-
-// The benchmarked backward: RenderBwdJob's work with each hit's chain rule
-// queued (GradVisitQ) and run 64 hits at a time at the wavefront-uniform
-// point after every step.  The origin of a queued hit's ray, its direction
-// and gradient weights are read back from the sample's records there.
-template <int K>
-struct RenderBwdQJob {
-    const RenderArgs &a;
-    SceneDev S;
-    BwdWalker<K> w;
-    GradVisitQ v;
-    WaveStageN<64> *stage;
-    int spp;
-
-    __device__ RenderBwdQJob(const RenderArgs &a_, GradQueue *q, WaveStageN<64> *st)
-        : a(a_), S(a_.S), v(a_.S, a_.tcut), stage(st), spp(a_.nc + a_.ng + a_.ne)
-    {
-        v.q = q;
-        queue_init(q);
-        stage_init(st);
-    }
-    __device__ __forceinline__ BwdWalker<K> &walker() { return w; }
-    __device__ __forceinline__ GradVisitQ &visit() { return v; }
-
-    __device__ __forceinline__ float3 weight(int64_t r, int64_t p) const
-    {
-        const float inv = 1.0f / (float)spp;
-        const float3 gp = make_float3(a.grad[3 * p] * inv, a.grad[3 * p + 1] * inv, a.grad[3 * p + 2] * inv);
-        const float4 r1 = a.rays[3 * r + 1];
-        return make_float3(r1.x * gp.x, r1.y * gp.y, r1.z * gp.z);
-    }
-
-    __device__ __forceinline__ bool begin(int64_t g)
-    {
-        if (S.n <= 0) return false;
-        const int64_t r = a.order ? (int64_t)a.order[g] : g;
-        const float4 r0 = a.rays[3 * r];
-        if (r0.w == 0.0f) return false;
-        if (a.hits && a.hits[r] <= (uint32_t)a.hcap) return false;  // done from its stored list
-        const int64_t p = r / spp;
-        const float inv = 1.0f / (float)spp;
-        if (a.grad[3 * p] * inv == 0.0f && a.grad[3 * p + 1] * inv == 0.0f && a.grad[3 * p + 2] * inv == 0.0f)
-            return false;
-        const float3 gC = weight(r, p);  // recomputed the same way where its hits are drained
-        const float4 r1 = a.rays[3 * r + 1], r2 = a.rays[3 * r + 2];
-        const float gT = gC.x * r1.w + gC.y * r2.x + gC.z * r2.y;
-        const float4 sv = a.saved[r];
-        const float3 x = make_float3(a.x[3 * p], a.x[3 * p + 1], a.x[3 * p + 2]);
-        const float3 d = make_float3(r0.x, r0.y, r0.z);
-        v.reset(x, d, gC, gT, make_float3(sv.x, sv.y, sv.z), sv.w, (uint32_t)r);
-        w.start(S, x, d, a.tmin, stop_bound(a.saved_t, r, INFINITY));
-        return true;
-    }
-
-    __device__ __forceinline__ void finish(int64_t) {}
-
-    // All 64 lanes, at a wavefront-uniform point: the chain rule of the
-    // queued hits, 64 at a time (and the remainder too when `all`), staged
-    // and added to the surfels' lines.
-    __device__ __forceinline__ void drain_hits(bool all)
-    {
-        GradQueue *q = v.q;
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        int n = __builtin_amdgcn_readfirstlane(*(volatile int *)&q->count);
-        const int lane = threadIdx.x & 63;
-        while (n >= 64 || (all && n > 0)) {
-            const int head = __builtin_amdgcn_readfirstlane(*(volatile int *)&q->head);
-            const int m = n < 64 ? n : 64;
-            if (lane < m) {
-                const int e = (head + lane) & (kQueueCap - 1);
-                const uint32_t p = reinterpret_cast<volatile uint32_t *>(q->p)[e];
-                const int64_t r = (int64_t)reinterpret_cast<volatile uint32_t *>(q->r)[e];
-                const float dA = reinterpret_cast<volatile float *>(q->dA)[e];
-                const float wgt = reinterpret_cast<volatile float *>(q->w)[e];
-                const float4 *rec = S.rec + 4 * (size_t)p;
-                const float4 r0 = rec[0], r1 = rec[1], r2 = rec[2], r3 = rec[3];
-                const float4 c = S.col[p], qt = S.quat[p];
-                const int64_t px = r / spp;
-                const float3 x = make_float3(a.x[3 * px], a.x[3 * px + 1], a.x[3 * px + 2]);
-                const float4 d4 = a.rays[3 * r];
-                const float3 d = make_float3(d4.x, d4.y, d4.z);
-                const float3 gC = weight(r, px);
-                HitGeo hg;
-                value_geo(r0, r1, r2, r3, x, d, hg);
-                const float G = expf(-0.5f * hg.rho2);
-                const float al = r1.w * G;
-                float terms[13];
-                hit_param_grads<false>(hg, r1, r2, r3, d, al, G, dA, 0.0f, make_float3(0.f, 0.f, 0.f), qt, r3.w, c.w,
-                                       terms);
-                terms[10] = wgt * gC.x; terms[11] = wgt * gC.y; terms[12] = wgt * gC.z;
-                stage_add(stage, __float_as_uint(r2.w), terms);
-            }
-            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-            if (lane == 0) {
-                *(volatile int *)&q->head = (head + m) & (kQueueCap - 1);
-                *(volatile int *)&q->count = n - m;
-            }
-            stage_sync(a.g.acc, stage, true);
-            n -= m;
-        }
-    }
-    __device__ __forceinline__ void after_step() { drain_hits(false); }
-    __device__ __forceinline__ void drain() { drain_hits(true); }
-};
-
 // kHitList: the launch stores hit lists (a.hits set); a separate kernel, so
 // that the plain forward carries no list pointer in its registers.
 template <int K, bool kHitList>
@@ -442,8 +338,11 @@ __global__ void __launch_bounds__(256) GRT_OCCUPANCY k_render(RenderArgs a)
 
 // The forward with a 12-hit buffer fits 3 wavefronts per SIMD (168 VGPRs)
 // when the compiler is held to it; it then beats K = 8 (fewer rounds).
+#ifndef GRT_FWD12_WAVES
+#define GRT_FWD12_WAVES 3
+#endif
 template <int K, bool kHitList>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_render_w3(RenderArgs a)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GRT_FWD12_WAVES))) k_render_w3(RenderArgs a)
 {
     RenderJob<K, kHitList> job(a);
     run_persistent<K>(job, a.counters, (int64_t)a.H * a.W * (a.nc + a.ng + a.ne));
@@ -468,16 +367,6 @@ __global__ void __launch_bounds__(256) GRT_OCCUPANCY k_render_bwd(RenderArgs a)
 {
     __shared__ WaveStage stages[4];
     RenderBwdJob<K, kOrigin> job(a, &stages[(threadIdx.x >> 6) & 3]);
-    run_persistent<K>(job, a.counters, (int64_t)a.H * a.W * (a.nc + a.ng + a.ne));
-}
-
-template <int K>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(GRT_BWDQ_WAVES))) k_render_bwd_q(RenderArgs a)
-{
-    __shared__ WaveStageN<64> stages[4];
-    __shared__ GradQueue queues[4];
-    const int wave = (threadIdx.x >> 6) & 3;
-    RenderBwdQJob<K> job(a, &queues[wave], &stages[wave]);
     run_persistent<K>(job, a.counters, (int64_t)a.H * a.W * (a.nc + a.ng + a.ne));
 }
 
@@ -637,18 +526,16 @@ static hipError_t go_render_bwd_as(const RenderArgs &a, int num_cu, hipStream_t 
 template <int K>
 static hipError_t go_render_bwd(const RenderArgs &a, int num_cu, hipStream_t st)
 {
-    if (a.gorig) return go_render_bwd_as<K, true>(a, num_cu, st);
-#if GRT_BWD_QUEUE
-    const int64_t total = (int64_t)a.H * a.W * (a.nc + a.ng + a.ne);
-    const int nb = persistent_blocks(k_render_bwd_q<K>, num_cu, total);
-    hipLaunchKernelGGL(k_render_bwd_q<K>, dim3(nb), dim3(256), 0, st, a);
-    return hipGetLastError();
-#else
-    return go_render_bwd_as<K, false>(a, num_cu, st);
-#endif
+    return a.gorig ? go_render_bwd_as<K, true>(a, num_cu, st) : go_render_bwd_as<K, false>(a, num_cu, st);
 }
 
-hipError_t launch_render_backward_stored(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st)
+static hipError_t timer_mark(const KernelTimer *tm, bool end, hipStream_t st)
+{
+    return tm ? hipEventRecord(end ? tm->end : tm->begin, st) : hipSuccess;
+}
+
+hipError_t launch_render_backward_stored(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st,
+                                         const KernelTimer *tm)
 {
     const int64_t nray = (int64_t)a.H * a.W * (a.nc + a.ng + a.ne);
     if (nray <= 0) return hipSuccess;
@@ -656,6 +543,7 @@ hipError_t launch_render_backward_stored(const RenderArgs &a, const RenderWS &w,
     if (e != hipSuccess) return e;
     if ((e = launch_render_gen(a, st)) != hipSuccess) return e;
     if (a.order && (e = launch_ray_order(a, w, st)) != hipSuccess) return e;
+    if ((e = timer_mark(tm, false, st)) != hipSuccess) return e;
     if (a.gorig)
         hipLaunchKernelGGL(k_render_bwd_stored<true>, dim3((unsigned)((nray + 255) / 256)), dim3(256), 0, st, a);
     else
@@ -665,15 +553,17 @@ hipError_t launch_render_backward_stored(const RenderArgs &a, const RenderWS &w,
     RenderArgs b = a;
     b.order = nullptr;
     switch (k) {
-    case 1: return go_render_bwd<1>(b, num_cu, st);
-    case 2: return go_render_bwd<2>(b, num_cu, st);
-    case 4: return go_render_bwd<4>(b, num_cu, st);
-    case 8: return go_render_bwd<8>(b, num_cu, st);
-    case 12: return go_render_bwd<12>(b, num_cu, st);
-    case 16: return go_render_bwd<16>(b, num_cu, st);
-    case 32: return go_render_bwd<32>(b, num_cu, st);
+    case 1: e = go_render_bwd<1>(b, num_cu, st); break;
+    case 2: e = go_render_bwd<2>(b, num_cu, st); break;
+    case 4: e = go_render_bwd<4>(b, num_cu, st); break;
+    case 8: e = go_render_bwd<8>(b, num_cu, st); break;
+    case 12: e = go_render_bwd<12>(b, num_cu, st); break;
+    case 16: e = go_render_bwd<16>(b, num_cu, st); break;
+    case 32: e = go_render_bwd<32>(b, num_cu, st); break;
     default: return hipErrorInvalidValue;
     }
+    if (e != hipSuccess) return e;
+    return timer_mark(tm, true, st);
 }
 
 hipError_t launch_render_gen(const RenderArgs &a, hipStream_t st)
@@ -746,7 +636,8 @@ hipError_t launch_ray_order(const RenderArgs &a, const RenderWS &w, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_render(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st)
+hipError_t launch_render(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st,
+                         const KernelTimer *tm)
 {
     const int64_t npix = (int64_t)a.H * a.W;
     if (npix <= 0) return hipSuccess;
@@ -754,6 +645,7 @@ hipError_t launch_render(const RenderArgs &a, const RenderWS &w, int k, int num_
     if (e != hipSuccess) return e;
     if ((e = launch_render_gen(a, st)) != hipSuccess) return e;
     if (a.order && (e = launch_ray_order(a, w, st)) != hipSuccess) return e;
+    if ((e = timer_mark(tm, false, st)) != hipSuccess) return e;
     switch (k) {
     case 1: e = go_render<1>(a, num_cu, st); break;
     case 2: e = go_render<2>(a, num_cu, st); break;
@@ -765,6 +657,7 @@ hipError_t launch_render(const RenderArgs &a, const RenderWS &w, int k, int num_
     default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
+    if ((e = timer_mark(tm, true, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_render_reduce, dim3((unsigned)((npix + 255) / 256)), dim3(256), 0, st, npix,
                        a.nc + a.ng + a.ne, a.contrib, a.out);
     return hipGetLastError();
@@ -832,23 +725,27 @@ hipError_t launch_render_relight_mesh(const RenderArgs &a, const MeshTraceArgs &
     return hipGetLastError();
 }
 
-hipError_t launch_render_backward(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st)
+hipError_t launch_render_backward(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st,
+                                  const KernelTimer *tm)
 {
     if ((int64_t)a.H * a.W <= 0) return hipSuccess;
     hipError_t e = launch_zero_counters(a.counters, st);
     if (e != hipSuccess) return e;
     if ((e = launch_render_gen(a, st)) != hipSuccess) return e;
     if (a.order && (e = launch_ray_order(a, w, st)) != hipSuccess) return e;
+    if ((e = timer_mark(tm, false, st)) != hipSuccess) return e;
     switch (k) {
-    case 1: return go_render_bwd<1>(a, num_cu, st);
-    case 2: return go_render_bwd<2>(a, num_cu, st);
-    case 4: return go_render_bwd<4>(a, num_cu, st);
-    case 8: return go_render_bwd<8>(a, num_cu, st);
-    case 12: return go_render_bwd<12>(a, num_cu, st);
-    case 16: return go_render_bwd<16>(a, num_cu, st);
-    case 32: return go_render_bwd<32>(a, num_cu, st);
+    case 1: e = go_render_bwd<1>(a, num_cu, st); break;
+    case 2: e = go_render_bwd<2>(a, num_cu, st); break;
+    case 4: e = go_render_bwd<4>(a, num_cu, st); break;
+    case 8: e = go_render_bwd<8>(a, num_cu, st); break;
+    case 12: e = go_render_bwd<12>(a, num_cu, st); break;
+    case 16: e = go_render_bwd<16>(a, num_cu, st); break;
+    case 32: e = go_render_bwd<32>(a, num_cu, st); break;
     default: return hipErrorInvalidValue;
     }
+    if (e != hipSuccess) return e;
+    return timer_mark(tm, true, st);
 }
 
 }  // namespace grt

@@ -410,6 +410,7 @@ struct grt_server {
     std::vector<int> free_slots;
     hipStream_t copy = nullptr;
     unsigned long long *copy_counters = nullptr;  // ray fetch of G-buffer traces on the copy stream
+    float *lut = nullptr;                          // the shared DFG table (workspace)
     grt::EpochSlot ep[2];
     int chunk_cap = 0;  // chunk table entries per epoch
     double rate = 5e7;  // traced rays per second, running estimate (launch gate)
@@ -521,7 +522,7 @@ hipError_t upload(grt_server *s, ServerJob &j)
     if (q.camera_request && (e = trace_request_gbuffer(s, j)) != hipSuccess) return e;
     if ((e = grt::launch_env_build(a.E.rgb, q.env_H, q.env_W, j.env, s->copy)) != hipSuccess) return e;
     // relighting: the prefiltered environment and the DFG table (Eq. relight_splitsum)
-    if (j.relight && (e = grt::launch_env_prefilter(a.E.rgb, q.env_H, q.env_W, j.env, s->copy)) != hipSuccess)
+    if (j.relight && (e = grt::launch_env_prefilter(a.E.rgb, q.env_H, q.env_W, j.env, s->copy, false)) != hipSuccess)
         return e;
     // every sample's ray record up front, so epochs only trace, and the
     // samples' coherent traversal order
@@ -557,7 +558,7 @@ void setup_args(grt_server *s, ServerJob &j)
     if (j.relight) {
         a.E.Ed = j.env.Ed;
         a.E.Es = j.env.Es;
-        a.E.lut = j.env.lut;
+        a.E.lut = s->lut;
         a.sa_albedo = s->opts.attrs.albedo;
         a.sa_rough = s->opts.attrs.rough;
         a.sa_metal = s->opts.attrs.metal;
@@ -954,6 +955,7 @@ struct ServerWS {
     grt::ServeChunk *d_chunks[2];
     unsigned long long *counters[2];
     unsigned long long *copy_counters;
+    float *lut;  // the DFG table every relighting request shares
     char *pool;
     size_t pool_bytes;
     size_t bytes;
@@ -975,6 +977,7 @@ ServerWS carve_server(void *base, const grt_server_opts &o)
         w.counters[b] = (unsigned long long *)take(grt::kCounterBytes);
     }
     w.copy_counters = (unsigned long long *)take(grt::kCounterBytes);
+    w.lut = (float *)take(sizeof(float) * 2 * grt::kLutN * grt::kLutN);
     w.pool_bytes = o.mem_budget & ~(size_t)255;
     w.pool = take(w.pool_bytes);
     w.bytes = off;
@@ -1035,8 +1038,12 @@ int grt_server_create(grt_ctx *ctx, const grt_scene *scene, const grt_server_opt
     const ServerWS w = carve_server(opts->workspace, *opts);
     s->pool = w.pool;
     s->copy_counters = w.copy_counters;
+    s->lut = w.lut;
     bool ok = hipSetDevice(ctx->device) == hipSuccess;
     ok = ok && hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking) == hipSuccess;
+    // the DFG table once, ahead of every upload on the copy stream (relighting
+    // epochs wait for their request's upload)
+    ok = ok && grt::launch_dfg_lut(s->lut, s->copy) == hipSuccess;
     for (int b = 0; b < 2; ++b) {
         grt::EpochSlot &E = s->ep[b];
         E.d_jobs = w.d_jobs[b];

@@ -102,7 +102,7 @@ class grt_gbuffer(C.Structure):
 class grt_mis_opts(C.Structure):
     _fields_ = [("n_cos", C.c_int), ("n_ggx", C.c_int), ("n_env", C.c_int), ("seed", C.c_uint64),
                 ("job", C.c_uint32), ("t_min", C.c_float), ("t_cut", C.c_float), ("k", C.c_int),
-                ("sample_dump", VP), ("hit_list", VP), ("hit_cap", C.c_int)]
+                ("sample_dump", VP), ("hit_list", VP), ("hit_cap", C.c_int), ("timer", VP)]
 
 
 class grt_server_opts(C.Structure):
@@ -184,6 +184,9 @@ SIGNATURES = {
     "grt_render_mis_backward_shading": (C.c_int, [VP, VP, P(grt_gbuffer), P(grt_mis_opts), VP, VP,
                                                   P(grt_surfel_grads), P(grt_shading_grads), VP, C.c_size_t, VP]),
     "grt_render_hit_list_bytes": (C.c_size_t, [C.c_int64, C.c_int, C.c_int]),
+    "grt_timer_create": (C.c_int, [VP, P(VP)]),
+    "grt_timer_ms": (C.c_int, [VP, P(C.c_float)]),
+    "grt_timer_destroy": (C.c_int, [VP]),
     "grt_server_job_bytes": (C.c_size_t, [P(grt_job)]),
     "grt_server_workspace_bytes": (C.c_size_t, [P(grt_server_opts)]),
     "grt_server_create": (C.c_int, [VP, VP, P(grt_server_opts), P(VP)]),
@@ -728,7 +731,30 @@ class GBuffer:
                            _ptr(self.rough), _ptr(self.metal), _ptr(self.valid))
 
 
-def make_mis_opts(split=(16, 8, 8), seed=0, job=0, t_min=1e-3, t_cut=1e-3, k=16, dump=None, hits=None, hit_cap=0):
+class Timer:
+    """Kernel timer (grt_timer): pass as ``timer=`` to render_mis /
+    render_mis_backward; ``ms()`` is the last recorded trace kernel's time."""
+
+    def __init__(self, ctx: Context):
+        self._ctx = ctx
+        h = VP()
+        _check(load_library().grt_timer_create(ctx.handle, C.byref(h)))
+        self.handle = h
+
+    def ms(self) -> float:
+        v = C.c_float()
+        _check(load_library().grt_timer_ms(self.handle, C.byref(v)))
+        return float(v.value)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            load_library().grt_timer_destroy(h)
+            self.handle = None
+
+
+def make_mis_opts(split=(16, 8, 8), seed=0, job=0, t_min=1e-3, t_cut=1e-3, k=16, dump=None, hits=None, hit_cap=0,
+                  timer=None):
     o = grt_mis_opts()
     o.n_cos, o.n_ggx, o.n_env = split
     o.seed = seed
@@ -739,6 +765,7 @@ def make_mis_opts(split=(16, 8, 8), seed=0, job=0, t_min=1e-3, t_cut=1e-3, k=16,
     o.sample_dump = _ptr(dump)
     o.hit_list = _ptr(hits)
     o.hit_cap = int(hit_cap) if hits is not None else 0
+    o.timer = timer.handle if timer is not None else None
     return o
 
 
@@ -753,7 +780,7 @@ def make_hit_list(npix: int, spp: int, hit_cap: int, device):
 
 
 def render_mis(scene: Scene, env: Env, gb: GBuffer, split=(16, 8, 8), seed=0, job=0, t_min=1e-3, t_cut=1e-3, k=16,
-               save=False, dump=False, workspace=None, stream=None, hits=None, hit_cap=0):
+               save=False, dump=False, workspace=None, stream=None, hits=None, hit_cap=0, timer=None):
     """c_pbr [npix,3]; with ``save`` also the per-sample state for the
     backward ("saved", flat; views "saved_ct" [nray,4] = (c_rt, T) and
     "saved_stop" [nray] = the depth of the last composited hit, 0 if none),
@@ -763,7 +790,7 @@ def render_mis(scene: Scene, env: Env, gb: GBuffer, split=(16, 8, 8), seed=0, jo
     out = torch.empty(gb.npix, 3, device=dev)
     saved = torch.empty(grt_render_saved_bytes(gb.npix, spp) // 4, device=dev) if save else None
     dmp = torch.zeros(gb.npix, spp, 10, device=dev) if dump else None
-    opts = make_mis_opts(split, seed, job, t_min, t_cut, k, dmp, hits, hit_cap)
+    opts = make_mis_opts(split, seed, job, t_min, t_cut, k, dmp, hits, hit_cap, timer)
     need = grt_render_workspace_bytes(gb.npix, spp)
     if workspace is None or workspace.numel() < need:
         workspace = _workspace(need, dev)
@@ -877,12 +904,12 @@ def denoise(ctx: Context, rgb, depth, normal, valid, H: int, W: int, radius=3, s
 
 
 def render_mis_backward(scene: Scene, env: Env, gb: GBuffer, grad_rgb, saved, split=(16, 8, 8), seed=0, job=0,
-                        t_min=1e-3, t_cut=1e-3, k=16, grads=None, stream=None, hits=None, hit_cap=0):
+                        t_min=1e-3, t_cut=1e-3, k=16, grads=None, stream=None, hits=None, hit_cap=0, timer=None):
     """Gradients into `grads` (+=).  With `hits` (the forward's stored hit
     lists) the backward works from the lists instead of re-traversing."""
     if grads is None:
         grads = zero_grads(scene.n, gb.x.device)
-    opts = make_mis_opts(split, seed, job, t_min, t_cut, k, None, hits, hit_cap)
+    opts = make_mis_opts(split, seed, job, t_min, t_cut, k, None, hits, hit_cap, timer)
     ws = _workspace(grt_render_workspace_bytes(gb.npix, sum(split)), gb.x.device)
     grt_render_mis_backward(scene.handle, env.handle, gb.struct(), opts, grad_rgb.contiguous(), saved,
                             _grads_struct(grads), ws, stream)
@@ -942,26 +969,28 @@ class RenderMISFn(torch.autograd.Function):
 
     @staticmethod
     def forward(ctx_, means, scales, quats, opacity, rgb, gctx, env, gb, split, seed, k, alpha_min, hit_cap=0,
-                k_bwd=None):
+                k_bwd=None, timers=None):
         """hit_cap > 0: store up to hit_cap hits per sample in the forward and
         differentiate from the stored lists; 0: re-traverse in the backward.
         k_bwd: k-buffer size of the backward (default k; results do not
-        depend on either)."""
+        depend on either).  timers: optional (forward, backward) Timer pair
+        that records the trace kernels of the two passes."""
         scene = Scene(gctx, means.detach().contiguous(), scales.detach().contiguous(), quats.detach().contiguous(),
                       opacity.detach().contiguous(), rgb.detach().contiguous(), alpha_min)
         hits = make_hit_list(gb.npix, sum(split), hit_cap, gb.x.device) if hit_cap > 0 else None
-        res = render_mis(scene, env, gb, split=split, seed=seed, k=k, save=True, hits=hits, hit_cap=hit_cap)
+        tf, tb = timers if timers is not None else (None, None)
+        res = render_mis(scene, env, gb, split=split, seed=seed, k=k, save=True, hits=hits, hit_cap=hit_cap, timer=tf)
         ctx_.scene, ctx_.env, ctx_.gb, ctx_.cfg = scene, env, gb, (split, seed, k if k_bwd is None else k_bwd, hit_cap)
-        ctx_.saved_state, ctx_.hits = res["saved"], hits
+        ctx_.saved_state, ctx_.hits, ctx_.timer = res["saved"], hits, tb
         return res["rgb"]
 
     @staticmethod
     def backward(ctx_, g_rgb):
         split, seed, k, hit_cap = ctx_.cfg
         g = render_mis_backward(ctx_.scene, ctx_.env, ctx_.gb, g_rgb, ctx_.saved_state, split=split, seed=seed, k=k,
-                                hits=ctx_.hits, hit_cap=hit_cap)
+                                hits=ctx_.hits, hit_cap=hit_cap, timer=ctx_.timer)
         return (g["means"], g["scales"], g["quats"], g["opacity"], g["rgb"], None, None, None, None, None, None, None,
-                None, None)
+                None, None, None)
 
 
 class RenderMISShadedFn(torch.autograd.Function):

@@ -152,3 +152,32 @@ def test_full_config1_sampled_pixels(grt_ctx):
     clean = ~edge.any(axis=1)
     np.testing.assert_allclose(out[pix][clean], ref["rgb"][clean], rtol=RTOL, atol=ATOL)
     assert np.all(out[gb.valid == 0] == 0.0)
+
+
+def test_kernel_timer(grt_ctx):
+    """The library's kernel timer brackets the trace kernel alone: positive,
+    at most the whole call's time, and an error before anything is recorded;
+    the timed render equals the untimed one."""
+    grt, ctx = grt_ctx
+    from gpu_util import t, scene_tensors
+    s = W.scene1(n=20000, seed=0, s_lo=0.01, s_hi=0.06)
+    gb = W.gbuffer1(64, 48, seed=0)
+    env = W.envmap(64, 128, seed=0)
+    scene = grt.Scene(ctx, *scene_tensors(s))
+    E = grt.Env(ctx, t(env))
+    G = grt.GBuffer.from_numpy(gb, torch.device("cuda", 0))
+    tf, tb = grt.Timer(ctx), grt.Timer(ctx)
+    with pytest.raises(grt.GrtError):
+        tf.ms()
+    st = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    fwd = grt.render_mis(scene, E, G, split=(8, 4, 4), seed=1, k=12, save=True, timer=tf)
+    e1.record(st)
+    torch.cuda.synchronize()
+    plain = grt.render_mis(scene, E, G, split=(8, 4, 4), seed=1, k=12)
+    np.testing.assert_array_equal(fwd["rgb"].cpu().numpy(), plain["rgb"].cpu().numpy())
+    assert 0.0 < tf.ms() <= e0.elapsed_time(e1) * 1.01 + 0.01
+    up = torch.ones(gb.npix, 3, device="cuda")
+    grt.render_mis_backward(scene, E, G, up, fwd["saved"], split=(8, 4, 4), seed=1, k=8, timer=tb)
+    assert tb.ms() > 0.0
