@@ -233,8 +233,9 @@ def _median_ms(fn, reps):
     return float(np.median(ts))
 
 
-def leg_plain(ctx, k):
-    """The plain trace: 4,096 surfels, 32,768 rays (grt_trace)."""
+def leg_plain(ctx, k, oracle=True):
+    """The plain trace: 4,096 surfels, 32,768 rays (grt_trace); with `oracle`
+    also the oracle on all of them (one run)."""
     import torch
     from paper_2607_22780_amd import grt
     from paper_2607_22780_amd import workloads as W
@@ -251,13 +252,22 @@ def leg_plain(ctx, k):
     wc = load_work("plain4k_32768rays")
     if wc:
         out["roofline"] = roofline(trace_bytes(wc), r.n, ms)
+    if oracle:
+        from oracle import oracle as O
+        t0 = time.time()
+        O.trace(s, r.origins, r.dirs)
+        sec = time.time() - t0
+        out["oracle"] = dict(mrays_s=round(r.n / sec / 1e6, 4), seconds=round(sec, 3), rays=r.n,
+                             cores=int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)), runs=1)
     return out
 
 
-def leg_shapes(ctx, k, k_bwd, hit_cap):
+def leg_shapes(ctx, k, k_bwd, hit_cap, oracle_px=256):
     """The 300k-surfel scene at 800x800, 32 spp: the MIS forward, and the
     differentiable step (loss against a target from perturbed radiance and
-    opacity) by re-traversal and from stored hit lists."""
+    opacity) by re-traversal and from stored hit lists; with oracle_px > 0
+    also the oracle's forward and backward on that many seeded valid pixels
+    (one run)."""
     import torch
     from paper_2607_22780_amd import grt
     from paper_2607_22780_amd import workloads as W
@@ -315,6 +325,20 @@ def leg_shapes(ctx, k, k_bwd, hit_cap):
         out["roofline_fwd"] = roofline(bf, rays, fwd_ms)
         out["roofline_bwd"] = roofline(bb, rays, bwd_ms)
     del hits, state
+    if oracle_px > 0:
+        from oracle import oracle as O
+        pix = np.sort(np.random.default_rng(2).choice(np.nonzero(gb.valid)[0], oracle_px, replace=False))
+        grad = np.random.default_rng(3).normal(0, 1, (oracle_px, 3))
+        t0 = time.time()
+        O.render_mis(s, gb, env, SPLIT, SEED, pix=pix)
+        t1 = time.time()
+        O.render_mis_backward(s, gb, env, SPLIT, SEED, grad, pix=pix)
+        t2 = time.time()
+        n = oracle_px * sum(SPLIT)
+        out["oracle"] = dict(rays=n, fwd_mrays_s=round(n / (t1 - t0) / 1e6, 6),
+                             step_mrays_s=round(n / (t2 - t0) / 1e6, 6), fwd_s=round(t1 - t0, 2),
+                             bwd_s=round(t2 - t1, 2), runs=1,
+                             cores=int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
     return out
 
 
@@ -322,16 +346,6 @@ def _gbuffer_task(key):
     from paper_2607_22780_amd import workloads as W
     res, cam = key
     return key, W.gbuffer3(res, res, cam_stream=10 + cam)
-
-
-def serve_rate(n, load, mrays_s, per_request_s=2e-3):
-    """The Poisson rate at which one launch per request would be busy `load`
-    of the time: mean service = rays / (the relighting leg's rate) plus a
-    fixed cost per request (uploads, tables, sort, launches)."""
-    from paper_2607_22780_amd import workloads as W
-    reqs = W.requests4(n, 1.0)
-    mean_s = float(np.mean([q.res * q.res * q.spp / (mrays_s * 1e6) + per_request_s for q in reqs]))
-    return load / mean_s
 
 
 def serve_inputs(n, rate):
@@ -347,13 +361,15 @@ def serve_inputs(n, rate):
     return reqs, gbs, envs
 
 
-def serve_leg(ctx, scene, k, reqs, gbs, envs, warm, slack=-1.0, epoch=0, extra=False):
+def serve_leg(ctx, scene, k, reqs, gbs, envs, warm, slack=-1.0, epoch=0, extra=False, load=0.0):
     """The persistent batched server against one launch per request (upload,
     tables, render, copy back, in arrival order), on the same relighting
     requests (the attribute query and split-sum shading under each request's
-    own environment) replayed at their arrival times and then all at once.
+    own environment) all at once and then replayed at their arrival times.
     The first `warm` requests of each run warm the system and are left out of
-    the latency statistics."""
+    the latency statistics.  load > 0: the Poisson arrival times are scaled so
+    that the offered load is `load` of one launch per request's measured
+    capacity (its mean service time in the all-at-once run)."""
     import torch
     from paper_2607_22780_amd import grt
     from paper_2607_22780_amd import workloads as W
@@ -370,6 +386,7 @@ def serve_leg(ctx, scene, k, reqs, gbs, envs, warm, slack=-1.0, epoch=0, extra=F
     req_srv, req_one = mk(), mk()
     measured = slice(warm, len(reqs))
     rays_m = sum(r.rays for r in req_srv[measured])
+    arrivals = [q.arrival_s for q in reqs]
 
     def run_server(replay, share=-1.0, rlist=None):
         rlist = req_srv if rlist is None else rlist
@@ -377,9 +394,9 @@ def serve_leg(ctx, scene, k, reqs, gbs, envs, warm, slack=-1.0, epoch=0, extra=F
                          preempt_share=share, attrs=mats)
         t0 = time.perf_counter()
         ids = []
-        for q, r in zip(reqs, rlist):
+        for q, r in zip(arrivals, rlist):
             if replay:
-                dt = t0 + q.arrival_s - time.perf_counter()
+                dt = t0 + q - time.perf_counter()
                 if dt > 0:
                     time.sleep(dt)
             ids.append(srv.submit(r))
@@ -398,12 +415,12 @@ def serve_leg(ctx, scene, k, reqs, gbs, envs, warm, slack=-1.0, epoch=0, extra=F
         stream = torch.cuda.current_stream()
         t0 = time.perf_counter()
         lat, marks = [], []
-        for q, r in zip(reqs, req_one):
+        for q, r in zip(arrivals, req_one):
             if replay:
-                dt = t0 + q.arrival_s - time.perf_counter()
+                dt = t0 + q - time.perf_counter()
                 if dt > 0:
                     time.sleep(dt)
-            arrive = t0 + q.arrival_s if replay else t0
+            arrive = t0 + q if replay else t0
             x, n, wo, alb, rough, metal, valid = (a.to(dev, non_blocking=True) for a in r.arrays)
             G = grt.GBuffer(r.H, r.W, x, n, wo, alb, rough, metal, valid)
             E = grt.Env(ctx, r.env.to(dev, non_blocking=True)).prefilter()
@@ -421,21 +438,28 @@ def serve_leg(ctx, scene, k, reqs, gbs, envs, warm, slack=-1.0, epoch=0, extra=F
     pct = lambda a, p: float(np.percentile(np.asarray(a), p))
     summary = lambda lat, span: {"p50_s": round(pct(lat, 50), 4), "p99_s": round(pct(lat, 99), 4),
                                  "mean_s": round(float(np.mean(lat)), 4), "mrays_s": round(rays_m / span / 1e6, 2)}
+    log("bench: per-request leg (all at once)")
+    o_bur = run_one(False)
+    log("bench: server leg (all at once)")
+    s_bur = run_server(False)
+    same = all(torch.equal(a.out, b.out) for a, b in zip(req_srv, req_one))
+    service_s = o_bur[1] / (len(reqs) - warm)  # one launch per request's mean time per request
+    if load > 0.0:
+        gap0 = arrivals[-1] / max(len(arrivals) - 1, 1)
+        arrivals = [a * (service_s / load) / gap0 for a in arrivals]
     log("bench: server leg (replayed arrivals)")
     s_rep = run_server(True)
     log("bench: per-request leg (replayed arrivals)")
     o_rep = run_one(True)
-    same = all(torch.equal(a.out, b.out) for a, b in zip(req_srv, req_one))
-    log("bench: server leg (all at once)")
-    s_bur = run_server(False)
-    log("bench: per-request leg (all at once)")
-    o_bur = run_one(False)
-    gap = reqs[-1].arrival_s / max(len(reqs) - 1, 1)
+    gap = arrivals[-1] / max(len(arrivals) - 1, 1)
     res = {
         "workload": f"room scene resident; relighting (attribute query + split-sum) of {len(reqs)} requests, "
                     f"the first {warm} as warm-up, {len(reqs) - warm} measured; Poisson {gap:.3f} s mean gap; "
                     f"res in {{256,512,768,1024}}^2, spp in {{4..64}}, 128x256 env each",
         "measured_rays": rays_m,
+        "one_launch_mean_service_s": round(service_s, 4),
+        "arrival_rate_hz": round(1.0 / gap, 4),
+        "offered_load": round(service_s / gap, 3),
         "server": {"replay": summary(*s_rep), "burst": summary(*s_bur)},
         "one_launch_per_request": {"replay": summary(*o_rep), "burst": summary(*o_bur)},
         "images_identical": bool(same),
@@ -487,8 +511,8 @@ def main():
     ap.add_argument("--serve-rate", type=float, default=0.0,
                     help="Poisson arrival rate, requests/s (0: --serve-load of one launch per request's capacity)")
     ap.add_argument("--serve-load", type=float, default=0.7,
-                    help="offered load when the rate is derived: the rate at which one launch per request, at the "
-                         "relighting leg's measured Mrays/s plus 2 ms per request, would be busy this share of time")
+                    help="offered load when the rate is derived: arrivals are spaced so that one launch per request "
+                         "(its mean service time measured in the all-at-once run) is busy this share of the time")
     ap.add_argument("--serve-slack", type=float, default=-1.0, help="server deadline seconds per ray (-1: default)")
     ap.add_argument("--serve-epoch", type=int, default=0, help="server rays per epoch (0: default)")
     ap.add_argument("--count-work", action="store_true", help="recount per-ray work with the oracle and exit")
@@ -594,9 +618,10 @@ def main():
     legs = None
     if not args.no_legs:
         log("bench: plain-trace leg (4,096 surfels)")
-        legs = {"plain_trace_4k": leg_plain(ctx, 16)}
+        legs = {"plain_trace_4k": leg_plain(ctx, 16, oracle=not args.no_cpu_baseline)}
         log("bench: 300k-surfel leg (forward; differentiable step, re-traversal and stored lists)")
-        legs["shapes_300k"] = leg_shapes(ctx, args.k, args.k_bwd, args.hit_cap)
+        legs["shapes_300k"] = leg_shapes(ctx, args.k, args.k_bwd, args.hit_cap,
+                                         oracle_px=0 if args.no_cpu_baseline else 256)
 
     relight = None
     if not args.no_relight:
@@ -697,14 +722,10 @@ def main():
     serve = None
     if not args.no_serve:
         log("bench: generating relighting requests")
-        rate = args.serve_rate
-        if rate <= 0.0:
-            rate = serve_rate(args.serve_requests, args.serve_load, relight["mrays_s"]) if relight else 3.7
-        reqs, gbs, envs = serve_inputs(args.serve_requests, rate)
+        derived = args.serve_rate <= 0.0
+        reqs, gbs, envs = serve_inputs(args.serve_requests, 1.0 if derived else args.serve_rate)
         serve = serve_leg(ctx, scene, args.k, reqs, gbs, envs, args.serve_warm, args.serve_slack, args.serve_epoch,
-                          extra=args.serve_extra)
-        serve["arrival_rate_hz"] = round(rate, 4)
-        serve["offered_load"] = args.serve_load if args.serve_rate <= 0.0 and relight else None
+                          extra=args.serve_extra, load=args.serve_load if derived else 0.0)
         del reqs, gbs, envs
 
     cpu = None

@@ -664,7 +664,17 @@ int grt_denoise(grt_ctx *ctx, int H, int W, const float *rgb, const float *depth
  *                depends on nothing but its resolution, so the server builds
  *                it once) all live there (the server allocates no device
  *                memory; it holds a few pinned host buffers of tables and
- *                flags). */
+ *                flags).
+ * co_trace:      nonzero: when the earliest-deadline request has not started,
+ *                the requests of the same kind waiting with the very same
+ *                G-buffer (the same arrays and size) are traced with it in
+ *                one epoch, all their samples in one joint coherent order
+ *                (direction bin, then origin cell): up to 16 requests, at
+ *                most 2^26 samples in all (and within epoch_rays), while the
+ *                epoch's buffers fit the pool (the joint order and its sort,
+ *                and a copy of the samples' records in that order: 104
+ *                bytes a sample for relighting, 92 for radiance).  Each
+ *                image is the same as traced alone. */
 typedef struct {
     size_t mem_budget;
     int max_jobs;
@@ -677,6 +687,7 @@ typedef struct {
     grt_surfel_attrs attrs;
     void *workspace;
     size_t ws_bytes;
+    int co_trace;
 } grt_server_opts;
 
 /* Device bytes grt_server_create needs in opts->workspace for these opts

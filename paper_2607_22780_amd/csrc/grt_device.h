@@ -235,11 +235,6 @@ __device__ __forceinline__ uint64_t make_key(float tau, uint32_t id)
 #define GRT_LDS_DEPTH 24
 #endif
 constexpr int kLdsDepth = GRT_LDS_DEPTH;  // LDS entries per lane and stack
-// 1: advance() requests the surfel site's record before the node step (see
-// advance_overlapped); 0: one after the other.
-#ifndef GRT_OVERLAP_SITE
-#define GRT_OVERLAP_SITE 0
-#endif
 #ifndef GRT_BWD_LDS_DEPTH
 #define GRT_BWD_LDS_DEPTH 12
 #endif
@@ -575,9 +570,6 @@ struct Walker {
     template <class Visit>
     __device__ __forceinline__ bool advance(const SceneDev &S, Visit &visit)
     {
-#if GRT_OVERLAP_SITE
-        return advance_overlapped(S, visit);
-#endif
         if (ncomp == 0 && pend == kNone) {
             int leaf = kNone;
             if (step(S, leaf)) {  // the round's walk is complete
@@ -635,73 +627,6 @@ struct Walker {
         return false;
     }
 
-    // advance() with the step's two memory waits overlapped: the surfel site
-    // is chosen from the lanes' state on entry, so the record it reads is
-    // requested before the walking lanes' node step, and both loads are in
-    // flight together.  A leaf found by this step's node test waits for the
-    // next step's site.
-    template <class Visit>
-    __device__ __forceinline__ bool advance_overlapped(const SceneDev &S, Visit &visit)
-    {
-        const bool wl = pend != kNone, wc = ncomp > 0;
-        const bool walking = !wl && !wc;
-        bool want = wl || wc;
-        int nwant, nact;
-        bool all;
-        if (kCompShare16 == 0) {
-            nwant = __popcll(__ballot(want));
-            nact = __popcll(__ballot(1));
-            all = nwant == nact;
-        } else {
-            const int nl = __popcll(__ballot(wl)), nc = __popcll(__ballot(wc));
-            nact = __popcll(__ballot(1));
-            all = nl + nc == nact;
-            const bool comp_ok = 16 * nc >= kCompShare16 * nact || all;
-            want = wl || (wc && comp_ok);
-            nwant = nl + (comp_ok ? nc : 0);
-        }
-        const bool few = kSiteShare8 ? 8 * nwant < kSiteShare8 * nact : 4 * nwant < kSurfelShare4 * nact;
-        const bool site = want && !(few && !all);
-        float4 r0, r1, r2, r3;
-        uint32_t sp = 0;
-        if (site) {
-            sp = wc ? pos[0] : (uint32_t)pend;
-            const float4 *r = S.rec + 4 * (size_t)sp;
-            r0 = r[0]; r1 = r[1]; r2 = r[2]; r3 = r[3];
-        }
-        if (walking) {
-            int leaf = kNone;
-            if (step(S, leaf)) {  // the round's walk is complete
-                const int m = cnt < K ? cnt : K;
-                if (m == 0) return true;
-                ncomp = m;
-                round_last = key[K - 1];
-            } else if (leaf != kNone) {
-                pend = -leaf - 1;
-            }
-        }
-        if (!site) return false;
-        float den, tau, rho2;
-        canon_geo(r0, r1, r2, r3, o, d, den, tau, rho2);
-        if (!wc) {
-            test_leaf(sp, den, tau, rho2, r0.w, r2.w);
-            pend = kNone;
-            return false;
-        }
-        const bool stop = visit(sp, (uint32_t)(key[0] & 0xffffffffu), __uint_as_float((uint32_t)(key[0] >> 32)), r0,
-                                r1, r2, r3, rho2);
-        last = key[0];  // the last composited hit (next_round resets it)
-#pragma unroll
-        for (int i = 0; i < K - 1; ++i) { key[i] = key[i + 1]; pos[i] = pos[i + 1]; }
-        key[K - 1] = ~0ull;
-        --ncomp;
-        if (stop) return true;
-        if (ncomp == 0) {
-            if (cnt < K || deferred_empty()) return true;
-            next_round(S);
-        }
-        return false;
-    }
 };
 
 // The walker of the backward kernels (see kBwdCompShare16, kBwdSiteShare8).

@@ -366,6 +366,9 @@ inline RenderWS carve_render(void *base, int64_t nray)
 
 // one ray record per sample of the whole G-buffer (sampling only, no trace)
 hipError_t launch_render_gen(const RenderArgs &a, hipStream_t st);
+// The coherent-order sort key of each of a's first n samples (direction bin,
+// then origin cell; untraced samples last), with value tag | sample index.
+hipError_t launch_ray_keys(const RenderArgs &a, int n, uint32_t *keys, uint32_t *vals, uint32_t tag, hipStream_t st);
 // Split-sum relighting (needs a.E's prefiltered tables and a.sa_*): the
 // forward render with the attribute query and Eq. relight_splitsum.
 hipError_t launch_render_relight(const RenderArgs &a, const RenderWS &w, int k, int num_cu, hipStream_t st);

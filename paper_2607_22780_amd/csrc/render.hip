@@ -590,7 +590,7 @@ __device__ __forceinline__ uint32_t spread3(uint32_t x)  // 6 bits -> every thir
 }
 
 __global__ void __launch_bounds__(256) k_ray_keys(RenderArgs a, int n, uint32_t *__restrict__ keys,
-                                                  uint32_t *__restrict__ vals)
+                                                  uint32_t *__restrict__ vals, uint32_t tag)
 {
     const int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= n) return;
@@ -623,14 +623,21 @@ __global__ void __launch_bounds__(256) k_ray_keys(RenderArgs a, int n, uint32_t 
         key = ((iv * 8u + iu) << 18) | m;
     }
     keys[r] = key;
-    vals[r] = (uint32_t)r;
+    vals[r] = tag | (uint32_t)r;
+}
+
+hipError_t launch_ray_keys(const RenderArgs &a, int n, uint32_t *keys, uint32_t *vals, uint32_t tag, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ray_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, n, keys, vals, tag);
+    return hipGetLastError();
 }
 
 hipError_t launch_ray_order(const RenderArgs &a, const RenderWS &w, hipStream_t st)
 {
     const int64_t n = (int64_t)a.H * a.W * (a.nc + a.ng + a.ne);
     if (n <= 0 || a.S.n < 2) return hipSuccess;
-    hipLaunchKernelGGL(k_ray_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, (int)n, w.k0, w.v0);
+    hipLaunchKernelGGL(k_ray_keys, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, a, (int)n, w.k0, w.v0, 0u);
     // 24-bit keys: three passes leave the order in (k1, v1)
     launch_radix_sort((int)n, 3, w.k0, w.v0, w.k1, w.v1, w.hist, st);
     return hipGetLastError();

@@ -54,6 +54,60 @@ struct ServeEpoch {
     SceneDev S;
 };
 
+// A co-traced epoch: the joint order (entry g = member << kJointShift | the
+// member's sample index, mslot[member] its job slot) and the epoch's own
+// copies of its rays in that order -- ray records, origins, and what the
+// trace writes back (contributions; relighting: the query's record words and
+// averaged normals) -- so that the trace runs the uniform-argument kernel of
+// a single request over them.
+constexpr int kMaxMembers = 16;
+constexpr int kJointShift = 27;
+struct JointEpoch {
+    const RenderArgs *jobs;
+    int mslot[kMaxMembers];
+    const uint32_t *joint;
+    int64_t n;
+    float4 *rays;     // [3n]
+    float *x;         // [3n]
+    float4 *contrib;  // [n]
+    float *nrm;       // [3][n] (relighting: x, y, z planes)
+    int relight;
+};
+
+// Gather the joint order's ray records and origins.
+__global__ void k_joint_gather(JointEpoch je)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= je.n) return;
+    const uint32_t v = je.joint[g];
+    const RenderArgs &a = je.jobs[je.mslot[v >> kJointShift]];
+    const int64_t r = (int64_t)(v & ((1u << kJointShift) - 1u));
+    const int64_t p = r / (a.nc + a.ng + a.ne);
+    je.rays[3 * g] = a.rays[3 * r];
+    je.rays[3 * g + 1] = a.rays[3 * r + 1];
+    je.rays[3 * g + 2] = a.rays[3 * r + 2];
+    je.x[3 * g] = a.x[3 * p];
+    je.x[3 * g + 1] = a.x[3 * p + 1];
+    je.x[3 * g + 2] = a.x[3 * p + 2];
+}
+
+// Scatter what the trace wrote back to each member's buffers.
+__global__ void k_joint_scatter(JointEpoch je)
+{
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= je.n) return;
+    const uint32_t v = je.joint[g];
+    const RenderArgs &a = je.jobs[je.mslot[v >> kJointShift]];
+    const int64_t r = (int64_t)(v & ((1u << kJointShift) - 1u));
+    a.contrib[r] = je.contrib[g];
+    if (je.relight) {
+        a.rays[3 * r + 2] = je.rays[3 * g + 2];  // the query's roughness and metallic (z, w)
+        a.rl_nx[r] = je.nrm[g];
+        a.rl_ny[r] = je.nrm[je.n + g];
+        a.rl_nz[r] = je.nrm[2 * je.n + g];
+    }
+}
+
 __device__ __forceinline__ int find_chunk(const ServeChunk *chunks, int nchunks, int64_t g)
 {
     int lo = 0, hi = nchunks - 1;
@@ -272,6 +326,7 @@ struct ServerJob {
     RenderWS sort{};  // sort keys/values and histogram (counters, rays, contrib unused)
     int64_t npix = 0, total = 0;
     bool relight = false;  // a relighting request (Eq. relight_splitsum), else radiance (Eq. mis)
+    bool out_device = false;  // out_rgb is device memory (else host)
     // rays not yet handed to an epoch: ranges of the request's sample order
     // (one range, until a stopped epoch hands back what it did not claim)
     std::deque<std::pair<int64_t, int64_t>> left;
@@ -380,6 +435,7 @@ struct EpochSlot {
     int64_t rays = 0;       // rays of the epoch in flight
     double t_launch = 0.0;  // when it was launched (server clock)
     std::vector<uint64_t> members, finishing;
+    size_t joint_off = 0, joint_bytes = 0;  // a co-traced epoch's sort buffers in the pool (0: none)
 };
 
 }  // namespace grt
@@ -499,6 +555,19 @@ hipError_t trace_request_gbuffer(grt_server *s, ServerJob &j)
     return grt::launch_trace_gbuffer(b, s->opts.k, s->ctx->num_cu, s->copy);
 }
 
+// The copy kind for a host-or-device pointer: a host source or destination
+// takes the DMA engines (H2D / D2H), not a copy kernel that would wait for
+// compute units behind a running epoch.
+static bool on_device(const void *p)
+{
+    hipPointerAttribute_t at;
+    if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+        (void)hipGetLastError();  // plain host memory the runtime does not know
+        return false;
+    }
+    return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+}
+
 // Upload a job's inputs and build its tables on the copy stream.
 hipError_t upload(grt_server *s, ServerJob &j)
 {
@@ -516,7 +585,9 @@ hipError_t upload(grt_server *s, ServerJob &j)
     // a camera request uploads only its environment and traces its G-buffer
     const int ncp = q.camera_request ? 1 : (int)(sizeof(cps) / sizeof(cps[0]));
     for (int i = 0; i < ncp; ++i)
-        if ((e = hipMemcpyAsync((void *)cps[i].dst, cps[i].src, cps[i].n, hipMemcpyDefault, s->copy)) !=
+        if ((e = hipMemcpyAsync((void *)cps[i].dst, cps[i].src, cps[i].n,
+                                on_device(cps[i].src) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                s->copy)) !=
             hipSuccess)
             return e;
     if (q.camera_request && (e = trace_request_gbuffer(s, j)) != hipSuccess) return e;
@@ -667,6 +738,8 @@ void retire(grt_server *s, grt::EpochSlot &E)
         ServerJob &j = s->jobs[id];
         if (!j.cancel) finish_job(s, j, GRT_OK);
     }
+    if (E.joint_bytes) s->alloc.release(E.joint_off, E.joint_bytes);
+    E.joint_bytes = 0;
     E.members.clear();
     E.finishing.clear();
     E.inflight = false;
@@ -702,9 +775,173 @@ constexpr int64_t kPreemptRays = 1 << 21;
 constexpr double kStopSeconds = 0.015;
 // Launch gate: the estimated time left of the epoch in flight below which the
 // next epoch starts, and the share of its remaining rays below which a next
-// epoch counts as small and starts at once.
-constexpr double kTailSeconds = 0.010;
-constexpr double kSmallShare = 0.05;
+// epoch counts as small and starts at once.  Starting a large epoch in the
+// tail of another measured slower overall on relighting bursts (the two ray
+// streams share the caches: 38.4 s against 38.0 s for 220 requests), so a
+// large epoch waits for the one in flight; small ones still pass.
+#ifndef GRT_SERVE_TAIL_S
+#define GRT_SERVE_TAIL_S 0.0
+#endif
+#ifndef GRT_SERVE_SMALL_SHARE
+#define GRT_SERVE_SMALL_SHARE 0.05
+#endif
+constexpr double kTailSeconds = GRT_SERVE_TAIL_S;
+constexpr double kSmallShare = GRT_SERVE_SMALL_SHARE;
+
+// Requests that share a G-buffer: the same arrays of the same size (a
+// camera request's G-buffer is the server's own, never shared).
+static bool same_gbuffer(const ServerJob &a, const ServerJob &b)
+{
+    const grt_job &p = a.spec, &q = b.spec;
+    return !p.camera_request && !q.camera_request && p.H == q.H && p.W == q.W && p.x == q.x && p.n == q.n &&
+           p.wo == q.wo && p.albedo == q.albedo && p.rough == q.rough && p.metal == q.metal && p.valid == q.valid;
+}
+
+// Not started: every ray still to hand out, in one range (and few enough to
+// index in a joint order entry).
+static bool whole(const ServerJob &j)
+{
+    return !j.started && j.inflight == 0 && j.nleft == j.total && j.left.size() == 1 &&
+           j.total < ((int64_t)1 << grt::kJointShift);
+}
+
+// Co-tracing: the head request and the waiting requests of its kind that
+// share its G-buffer, traced in one epoch in one joint coherent order (the
+// samples of all of them sorted together by direction bin, then origin
+// cell), so that a batch of requests of a few samples per pixel each walks
+// the scene as coherently as one request of their summed samples.  The
+// samples are gathered into the epoch's own buffers in that order and traced
+// by the single-request kernel (uniform arguments: the mixed kernel, which
+// finds each ray's request per lane, holds more registers), then the results
+// are scattered back.  False (nothing launched) when fewer than two requests
+// qualify or the epoch's buffers do not fit the pool.
+static bool launch_cotrace(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other,
+                           const std::vector<ServerJob *> &run, int64_t budget, hipError_t &err)
+{
+    if (!s->opts.co_trace || run.empty() || !whole(*run[0])) return false;
+    // at most 2^26 samples per co-traced epoch: its buffers take 104 bytes a sample
+    const int64_t cap = std::min(budget, (int64_t)1 << 26);
+    std::vector<ServerJob *> mem{run[0]};
+    int64_t n = run[0]->total;
+    for (size_t i = 1; i < run.size() && (int)mem.size() < grt::kMaxMembers; ++i) {
+        ServerJob *j = run[i];
+        if (whole(*j) && same_gbuffer(*j, *run[0]) && n + j->total <= cap) {
+            mem.push_back(j);
+            n += j->total;
+        }
+    }
+    if (mem.size() < 2) return false;
+    const bool relight = mem[0]->relight;
+    const size_t q4 = grt::align256(4 * (size_t)n), q12 = grt::align256(12 * (size_t)n);
+    const size_t bytes = 4 * q4 + grt::align256(4 * grt::sort_hist_words(n)) + grt::align256(48 * (size_t)n) + q12 +
+                         grt::align256(16 * (size_t)n) + (relight ? q12 : 0);
+    size_t off = 0;
+    if (!s->alloc.alloc(bytes, off)) return false;
+    char *p = s->pool + off;
+    auto take = [&p](size_t b) { char *r = p; p += b; return r; };
+    uint32_t *k0 = (uint32_t *)take(q4), *v0 = (uint32_t *)take(q4), *k1 = (uint32_t *)take(q4),
+             *v1 = (uint32_t *)take(q4);
+    uint32_t *hist = (uint32_t *)take(grt::align256(4 * grt::sort_hist_words(n)));
+    grt::JointEpoch je{};
+    je.rays = (float4 *)take(grt::align256(48 * (size_t)n));
+    je.x = (float *)take(q12);
+    je.contrib = (float4 *)take(grt::align256(16 * (size_t)n));
+    je.nrm = relight ? (float *)take(q12) : nullptr;
+    je.jobs = E.d_jobs;
+    je.joint = v1;
+    je.n = n;
+    je.relight = relight ? 1 : 0;
+    for (size_t m = 0; m < mem.size(); ++m) {
+        ServerJob *j = mem[m];
+        E.h_jobs[j->slot] = j->args;
+        je.mslot[m] = j->slot;
+        j->nleft = 0;
+        j->left.clear();
+        ++j->inflight;
+        j->started = true;
+        E.members.push_back(j->id);
+        E.finishing.push_back(j->id);
+    }
+    for (ServerJob *j : run)
+        if (j->started && j->nleft > 0 && std::find(E.members.begin(), E.members.end(), j->id) == E.members.end())
+            j->passable -= n;
+    E.relight = relight;
+    E.preemptible = false;
+    E.stopped = false;
+    E.nch = 0;
+    E.joint_off = off;
+    E.joint_bytes = bytes;
+    __atomic_store_n(E.stop_h, 0, __ATOMIC_RELEASE);
+    // the trace sees one request: the members' shared G-buffer has become a
+    // per-sample origin array, one sample per "pixel"
+    grt::RenderArgs J = mem[0]->args;
+    J.H = 1;
+    J.W = (int)n;
+    J.nc = 1;
+    J.ng = 0;
+    J.ne = 0;
+    J.x = je.x;
+    J.rays = je.rays;
+    J.contrib = je.contrib;
+    J.order = nullptr;
+    J.out = nullptr;
+    J.saved = nullptr;
+    J.saved_t = nullptr;
+    J.dump = nullptr;
+    J.hits = nullptr;
+    if (relight) {
+        J.rl_nx = je.nrm;
+        J.rl_ny = je.nrm + n;
+        J.rl_nz = je.nrm + 2 * n;
+    }
+    grt::ServeEpoch e{};
+    e.jobs = E.d_jobs;
+    e.chunks = E.d_chunks;
+    e.nchunks = 0;
+    e.total = n;
+    e.counters = E.counters;
+    e.stop = nullptr;
+    e.S = s->S;
+    err = hipMemcpyAsync(E.d_jobs, E.h_jobs, sizeof(grt::RenderArgs) * s->opts.max_jobs, hipMemcpyHostToDevice,
+                         E.stream);
+    // the joint order: every member's sort keys tagged with its member index,
+    // then one sort (24-bit keys: three passes leave it in (k1, v1))
+    int64_t at = 0;
+    for (size_t m = 0; m < mem.size() && err == hipSuccess; ++m) {
+        err = grt::launch_ray_keys(mem[m]->args, (int)mem[m]->total, k0 + at, v0 + at,
+                                   (uint32_t)m << grt::kJointShift, E.stream);
+        at += mem[m]->total;
+    }
+    const unsigned nb = (unsigned)((n + 255) / 256);
+    if (err == hipSuccess) {
+        grt::launch_radix_sort((int)n, 3, k0, v0, k1, v1, hist, E.stream);
+        hipLaunchKernelGGL(grt::k_joint_gather, dim3(nb), dim3(256), 0, E.stream, je);
+        err = hipGetLastError();
+    }
+    if (err == hipSuccess) err = grt::launch_epoch(e, &J, 0, relight, s->opts.k, s->ctx->num_cu, E.stream);
+    if (err == hipSuccess) {
+        hipLaunchKernelGGL(grt::k_joint_scatter, dim3(nb), dim3(256), 0, E.stream, je);
+        err = hipGetLastError();
+    }
+    for (ServerJob *j : mem) {
+        if (err != hipSuccess) break;
+        if (j->relight && (err = grt::launch_relight_shade(j->args, E.stream)) != hipSuccess) break;
+        hipLaunchKernelGGL(grt::k_serve_reduce, dim3((unsigned)((j->npix + 255) / 256)), dim3(256), 0, E.stream,
+                           E.d_jobs + j->slot, j->npix, nullptr, n);
+        err = hipGetLastError();
+        if (err == hipSuccess)
+            err = hipMemcpyAsync(j->spec.out_rgb, j->args.out, 12 * (size_t)j->npix,
+                                 j->out_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, E.stream);
+    }
+    if (err == hipSuccess) err = hipEventRecord(E.done, E.stream);
+    (void)other;
+    E.inflight = true;
+    E.rays = n;
+    E.t_launch = s->now();
+    s->rays_done += n;
+    ++s->epochs;
+    return true;
+}
 
 // Plan an epoch into slot E and launch it; false if no ray is left to trace.
 bool launch(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other, int64_t budget, hipError_t &err)
@@ -740,9 +977,9 @@ bool launch(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other, int64_t bud
             if (u.state == kUploading && !u.cancel && u.deadline < run[0]->deadline) return false;
         }
     // Launch gate: while the other epoch is in flight, the next one starts
-    // only in its tail (so its waves fill the CUs the tail leaves idle), or
-    // at once when it is small next to what the other epoch has left (so a
-    // small request passes a large one without slowing it noticeably).
+    // only once that one is estimated to be within kTailSeconds of its end,
+    // or at once when it is small next to what the other epoch has left (so
+    // a small request passes a large one without slowing it noticeably).
     if (other.inflight && !other.stopped) {
         int64_t want = 0;
         for (ServerJob *j : run) {
@@ -756,6 +993,8 @@ bool launch(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other, int64_t bud
         const bool small = (double)want <= kSmallShare * left;
         if (!tail && !small) return false;
     }
+    if (launch_cotrace(s, E, other, run, budget, err)) return true;
+    if (err != hipSuccess) return true;
     int nch = 0;
     int64_t off = 0;
     for (ServerJob *j : run) {
@@ -796,7 +1035,7 @@ bool launch(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other, int64_t bud
     E.stopped = false;
     E.nch = nch;
     __atomic_store_n(E.stop_h, 0, __ATOMIC_RELEASE);
-    grt::ServeEpoch e;
+    grt::ServeEpoch e{};
     e.jobs = E.d_jobs;
     e.chunks = E.d_chunks;
     e.nchunks = nch;
@@ -826,7 +1065,8 @@ bool launch(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other, int64_t bud
                            E.d_jobs + j.slot, j.npix, E.preemptible ? E.counters : nullptr, off);
         err = hipGetLastError();
         if (err == hipSuccess)
-            err = hipMemcpyAsync(j.spec.out_rgb, j.args.out, 12 * (size_t)j.npix, hipMemcpyDefault, E.stream);
+            err = hipMemcpyAsync(j.spec.out_rgb, j.args.out, 12 * (size_t)j.npix,
+                                 j.out_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, E.stream);
     }
     if (err == hipSuccess) err = hipEventRecord(E.done, E.stream);
     E.inflight = true;
@@ -1092,6 +1332,7 @@ int grt_server_submit(grt_server *s, const grt_job *job, uint64_t *id)
     j.id = s->next_id++;
     j.spec = *job;
     j.relight = job->relight != 0;
+    j.out_device = on_device(job->out_rgb);
     j.bytes = bytes;
     j.npix = (int64_t)job->H * job->W;
     j.total = j.npix * (job->n_cos + job->n_ggx + job->n_env);

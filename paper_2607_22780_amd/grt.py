@@ -109,7 +109,7 @@ class grt_server_opts(C.Structure):
     _fields_ = [("mem_budget", C.c_size_t), ("max_jobs", C.c_int), ("epoch_rays", C.c_int64), ("k", C.c_int),
                 ("t_min", C.c_float), ("t_cut", C.c_float), ("slack_per_ray", C.c_double),
                 ("preempt_share", C.c_double), ("attrs", grt_surfel_attrs), ("workspace", VP),
-                ("ws_bytes", C.c_size_t)]
+                ("ws_bytes", C.c_size_t), ("co_trace", C.c_int)]
 
 
 class grt_camera(C.Structure):
@@ -1149,10 +1149,11 @@ class Server:
     """Owns a grt_server over a built scene; submit Requests, wait, read times."""
 
     def __init__(self, ctx: Context, scene: Scene, mem_budget: int, max_jobs: int = 16, epoch_rays: int = 0, k=8,
-                 t_min=1e-3, t_cut=1e-3, slack_per_ray=-1.0, preempt_share=-1.0, attrs=None):
+                 t_min=1e-3, t_cut=1e-3, slack_per_ray=-1.0, preempt_share=-1.0, attrs=None, co_trace=True):
         """attrs: (albedo, rough, metal) device tensors for camera and
         relighting requests, kept alive with the server.  The server's device
-        memory (pool and tables) is a torch tensor owned here."""
+        memory (pool and tables) is a torch tensor owned here.  co_trace:
+        trace waiting requests that share a G-buffer in one joint order."""
         self.ctx, self.scene = ctx, scene
         self.attrs = attrs
         at = grt_surfel_attrs(*(_ptr(a) for a in attrs)) if attrs is not None else grt_surfel_attrs()
@@ -1164,6 +1165,7 @@ class Server:
         self.workspace = _workspace(need, ctx.device)
         self.opts.workspace = _ptr(self.workspace)
         self.opts.ws_bytes = self.workspace.numel()
+        self.opts.co_trace = 1 if co_trace else 0
         self.handle = grt_server_create(ctx.handle, scene.handle, self.opts)
         self.requests = {}
 

@@ -370,3 +370,43 @@ def test_device_memory_requests_and_workspace(setup):
     with pytest.raises(grt.GrtError) as ei:
         grt.grt_server_create(ctx.handle, scene.handle, opts)
     assert ei.value.code == grt.ERR_OOM
+
+
+@pytest.mark.parametrize("relight", [True, False])
+def test_cotraced_requests_match_direct_render(setup, relight):
+    """Requests sharing one G-buffer (the same arrays) submitted together are
+    traced in one epoch in a joint order: each image still equals its direct
+    render bit for bit, fewer epochs run than with co-tracing off (requests
+    above the fill size, so only co-tracing merges them), and the pool is
+    whole again afterwards.  A request with its own G-buffer among them is
+    traced on its own."""
+    grt, ctx, scene = setup
+    from gpu_util import t
+    mats = [t(a) for a in W.surfel_materials(scene.n, seed=2)]
+    gb = W.gbuffer1(160, 120, seed=3, cam_stream=21)
+    other = W.gbuffer1(150, 130, seed=3, cam_stream=22)
+    pin = lambda a: torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
+    shared = type("G", (), dict(H=gb.H, W=gb.W, x=pin(gb.x), n=pin(gb.n), wo=pin(gb.wo), albedo=pin(gb.albedo),
+                                rough=pin(gb.rough), metal=pin(gb.metal), valid=pin(gb.valid)))
+    # 160 x 120 x 64 spp = 1.2M samples each: above the 1M fill size
+    cases = [(shared, W.envmap(32, 64, seed=40 + i), W.mis_split(64), 300 + i, 9 + i) for i in range(4)]
+    cases.insert(2, (other, W.envmap(32, 64, seed=50), W.mis_split(64), 310, 20))
+    ref = []
+    for g, env, split, seed, job in cases:
+        src = gb if g is shared else g
+        ref.append(direct_relight(grt, ctx, scene, mats, src, env, split, seed, job) if relight
+                   else direct(grt, ctx, scene, src, env, split, seed, job))
+    epochs = {}
+    for co in (True, False):
+        srv = grt.Server(ctx, scene, mem_budget=2 << 30, max_jobs=8, attrs=mats, co_trace=co)
+        rs = [grt.Request(g, env, split, seed, job, relight=relight) for g, env, split, seed, job in cases]
+        ids = [srv.submit(r) for r in rs]
+        for jid, r, want in zip(ids, rs, ref):
+            assert srv.wait(jid) == 0
+            np.testing.assert_array_equal(r.out.numpy(), want)
+        st = srv.stats()
+        srv.close()
+        epochs[co] = st["epochs"]
+        assert st["pool_free"] == (2 << 30)
+    assert epochs[False] == len(cases)
+    assert epochs[True] < epochs[False]
