@@ -491,6 +491,40 @@ def calib_copy():
             "frac_of_peak": round(gbs / HBM_PEAK_GBS, 3)}
 
 
+def walk_stats_run(k, k_bwd):
+    """Walk counters of one differentiable step of the room workload, from
+    the library compiled with -DGRT_STATS (its kernels run slower; the
+    per-ray counts do not depend on timing, the per-step lane counts only
+    through the order in which wavefronts claim rays)."""
+    import torch
+    from paper_2607_22780_amd import grt
+    grt.load_library(grt.STATS_LIB_PATH)
+    dev = torch.device("cuda", 0)
+    s, gb, env = make_inputs()
+    t = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    ctx = grt.Context(0)
+    scene = grt.Scene(ctx, *(t(a) for a in s.arrays()))
+    E = grt.Env(ctx, t(env))
+    G = grt.GBuffer.from_numpy(gb, dev)
+    upstream = t(np.random.default_rng(0).normal(0, 1, (gb.npix, 3)).astype(np.float32))
+    grt.walk_stats(ctx, reset=True)
+    res = grt.render_mis(scene, E, G, split=SPLIT, seed=SEED, k=k, save=True)
+    grt.render_mis_backward(scene, E, G, upstream, res["saved"], split=SPLIT, seed=SEED, k=k_bwd)
+    st = grt.walk_stats(ctx, reset=True)
+    out = {}
+    for kind, d in st.items():
+        n = max(d["rays"], 1)
+        row = {"rays": d["rays"]}
+        for key in ("node_visits", "leaf_tests", "composites", "rounds", "restarts", "deferred"):
+            row[key + "_per_ray"] = round(d[key] / n, 3)
+        row["lane_steps_per_ray"] = round(d["active_lanes"] / n, 3)
+        row["wave_steps_x64_per_ray"] = round(64 * d["wave_steps"] / n, 3)
+        row["active_lanes_per_step"] = round(d["active_lanes"] / max(d["wave_steps"], 1), 3)
+        out[kind] = row
+    return {"walk_stats": out, "k": k, "k_bwd": k_bwd,
+            "config": {"workload": f"room 1M surfels, {RES}x{RES} G-buffer, 32 spp (16/8/8)"}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -520,6 +554,8 @@ def main():
     ap.add_argument("--serve-epoch", type=int, default=0, help="server rays per epoch (0: default)")
     ap.add_argument("--count-work", action="store_true", help="recount per-ray work with the oracle and exit")
     ap.add_argument("--calib-copy", action="store_true", help="only time a plain 1 GiB device copy and exit")
+    ap.add_argument("--walk-stats", action="store_true",
+                    help="only count the walk of one step with the instrumented library (libgrt_stats.so) and exit")
     args = ap.parse_args()
 
     if args.count_work:
@@ -535,6 +571,9 @@ def main():
 
     if args.calib_copy:
         print(json.dumps(calib_copy()))
+        return
+    if args.walk_stats:
+        print(json.dumps(walk_stats_run(args.k, args.k_bwd)))
         return
 
     dev = torch.device("cuda", 0)

@@ -439,6 +439,20 @@ int grt_timer_create(grt_ctx *ctx, grt_timer **out);
 int grt_timer_ms(grt_timer *timer, float *ms);
 int grt_timer_destroy(grt_timer *timer);
 
+/* Walk statistics (Sec. 3.1 traversal, counted per ray): only a library
+ * compiled with -DGRT_STATS keeps them (the default build returns
+ * GRT_ERR_INVALID); the counting slows its kernels.  Sums since the last reset,
+ * over the context's device, per kernel kind: row 0 the forward radiance trace
+ * of grt_render_mis (and _noalloc), row 1 the backward re-traversal of
+ * grt_render_mis_backward(_shading).  Columns (GRT_WALK_STATS): rays traced,
+ * 4-wide node visits, leaf tests, composited hits, k-buffer rounds, rounds
+ * restarted at the root (deferred list dropped), deferred items, wavefront
+ * steps, active lanes summed over those steps.  out: host array
+ * [2][GRT_WALK_STATS] (caller-owned); reset != 0 zeroes the sums after the
+ * read.  Synchronises the device. */
+#define GRT_WALK_STATS 9
+int grt_walk_stats(grt_ctx *ctx, uint64_t *out, int reset);
+
 /* Bytes of a stored hit list for npix * spp samples (4 * nray * (1 + hit_cap)),
  * 0 on bad arguments. */
 size_t grt_render_hit_list_bytes(int64_t npix, int spp, int hit_cap);

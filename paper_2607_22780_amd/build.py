@@ -15,6 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgrt.so")
+# walk statistics (grt_walk_stats): the same sources with -DGRT_STATS
+STATS_LIB = os.path.join(HERE, "libgrt_stats.so")
 SOURCES = ["api.hip", "scene.hip", "trace.hip", "render.hip", "server.hip", "denoise.hip", "mesh.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -26,8 +28,8 @@ FLAGS = [
 ]
 
 
-def _objs(jobs: int = 4, verbose: bool = False):
-    build_dir = os.path.join(HERE, "_build")
+def _objs(jobs: int = 4, verbose: bool = False, stats: bool = False):
+    build_dir = os.path.join(HERE, "_build", "stats") if stats else os.path.join(HERE, "_build")
     os.makedirs(build_dir, exist_ok=True)
     inc = ["-I", CSRC, "-I", os.path.join(ROOT, "include")]
     procs, objs = [], []
@@ -36,7 +38,7 @@ def _objs(jobs: int = 4, verbose: bool = False):
         if not os.path.exists(path):
             continue
         obj = os.path.join(build_dir, src.replace(".hip", ".o"))
-        cmd = [HIPCC] + FLAGS + inc + ["-c", path, "-o", obj]
+        cmd = [HIPCC] + FLAGS + (["-DGRT_STATS"] if stats else []) + inc + ["-c", path, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((subprocess.Popen(cmd), src))
@@ -49,18 +51,20 @@ def _objs(jobs: int = 4, verbose: bool = False):
     return objs
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, stats: bool = False) -> str:
+    """Build libgrt.so, or with stats the instrumented libgrt_stats.so."""
     t0 = time.time()
-    objs = _objs(verbose=verbose)
-    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", LIB + ".tmp"] + objs
+    lib = STATS_LIB if stats else LIB
+    objs = _objs(verbose=verbose, stats=stats)
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", lib + ".tmp"] + objs
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(lib + ".tmp", lib)
     if verbose:
-        print(f"built {LIB} in {time.time() - t0:.1f}s", flush=True)
-    return LIB
+        print(f"built {lib} in {time.time() - t0:.1f}s", flush=True)
+    return lib
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, stats="--stats" in sys.argv[1:])

@@ -276,6 +276,20 @@ int grt_timer_destroy(grt_timer *t)
     return GRT_OK;
 }
 
+int grt_walk_stats(grt_ctx *ctx, uint64_t *out, int reset)
+{
+    if (!ctx || !out) return fail(GRT_ERR_INVALID, "ctx/out is NULL");
+    if (!grt::walk_stats_built()) return fail(GRT_ERR_INVALID, "the library was built without walk statistics");
+    int rc = set_device(ctx);
+    if (rc) return rc;
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    static_assert(sizeof(uint64_t) == sizeof(unsigned long long), "64-bit sums");
+    e = grt::walk_stats_read(reinterpret_cast<unsigned long long *>(out), reset != 0);
+    if (e != hipSuccess) return hip_fail(e, "walk statistics");
+    return GRT_OK;
+}
+
 size_t grt_scene_workspace_bytes(int64_t n)
 {
     if (n < 0) return 0;

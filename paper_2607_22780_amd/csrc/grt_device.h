@@ -343,7 +343,7 @@ struct Walker {
     int pend;             // leaf waiting for the next surfel step (record position), or kNone
     uint64_t round_last;  // largest key of the round's full buffer
 #ifdef GRT_STATS
-    int st_nodes, st_leaves, st_rounds, st_lost, st_deferred;
+    int st_nodes, st_leaves, st_comps, st_rounds, st_lost, st_deferred;
 #endif
 
     __device__ __forceinline__ void clear_buffer()
@@ -371,7 +371,7 @@ struct Walker {
         cur = S.n == 1 ? -1 : 0;
         clear_buffer();
 #ifdef GRT_STATS
-        st_nodes = st_leaves = st_lost = st_deferred = 0;
+        st_nodes = st_leaves = st_comps = st_lost = st_deferred = 0;
         st_rounds = 1;
 #endif
     }
@@ -614,6 +614,9 @@ struct Walker {
         }
         const bool stop = visit(sp, (uint32_t)(key[0] & 0xffffffffu), __uint_as_float((uint32_t)(key[0] >> 32)), r0,
                                 r1, r2, r3, rho2);
+#ifdef GRT_STATS
+        ++st_comps;
+#endif
         last = key[0];  // the last composited hit (next_round resets it)
 #pragma unroll
         for (int i = 0; i < K - 1; ++i) { key[i] = key[i + 1]; pos[i] = pos[i + 1]; }
@@ -666,6 +669,47 @@ constexpr int kChunk = 64;
 
 __host__ __device__ __forceinline__ int64_t part_begin(int64_t total, int q) { return total * q / kParts; }
 
+#ifdef GRT_STATS
+// Walk statistics of the instrumented build.  Per kernel kind (a Job with
+// kStatSlot 0: the forward radiance trace, 1: the backward re-traversal;
+// other jobs are not counted), sums over the rays each kind traced and over
+// its wavefront steps; each TU holds its own copy (render kernels: render.hip).
+enum { kStRays, kStNodes, kStLeaves, kStComps, kStRounds, kStRestarts, kStDeferred, kStSteps, kStActive, kNumWalkStats };
+static __device__ unsigned long long g_walk_stats[2][kNumWalkStats];
+
+template <class J, class = void>
+struct StatSlot { static constexpr int value = -1; };
+template <class J>
+struct StatSlot<J, std::void_t<decltype(J::kStatSlot)>> { static constexpr int value = J::kStatSlot; };
+
+// The lane's sums of a finished ray's walk counters.
+template <class W>
+__device__ __forceinline__ void walk_tally(uint32_t (&t)[kNumWalkStats], const W &w)
+{
+    ++t[kStRays];
+    t[kStNodes] += w.st_nodes;
+    t[kStLeaves] += w.st_leaves;
+    t[kStComps] += w.st_comps;
+    t[kStRounds] += w.st_rounds;
+    t[kStRestarts] += w.st_lost;
+    t[kStDeferred] += w.st_deferred;
+}
+
+// Adds the wavefront's sums to the kind's totals (all lanes, wavefront-uniform point).
+template <int kSlot>
+__device__ __forceinline__ void walk_flush(const uint32_t (&t)[kNumWalkStats])
+{
+    if constexpr (kSlot >= 0) {
+#pragma unroll
+        for (int i = 0; i < kNumWalkStats; ++i) {
+            unsigned long long v = t[i];
+            for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+            if ((threadIdx.x & 63) == 0) atomicAdd(&g_walk_stats[kSlot][i], v);
+        }
+    }
+}
+#endif
+
 // stop: optional flag in host memory; once it reads non-zero, wavefronts
 // claim no further chunks, finish the rays they hold and leave, so the claim
 // counters then say exactly which rays were traced (a prefix of each
@@ -696,6 +740,9 @@ __device__ __forceinline__ void run_persistent(Job &job, unsigned long long *cou
         F.walk.reset();
         F.def.reset();
     }
+#ifdef GRT_STATS
+    uint32_t tally[kNumWalkStats] = {};
+#endif
     for (;;) {
         const uint64_t idle = __ballot(!active);
         if (idle && !exhausted) {
@@ -732,15 +779,28 @@ __device__ __forceinline__ void run_persistent(Job &job, unsigned long long *cou
                 pool_next += (int64_t)(nidle < avail ? nidle : avail);
             }
         }
-        if (!__ballot(active)) {
+        const uint64_t busy = __ballot(active);
+        if (!busy) {
             if (exhausted) {
+#ifdef GRT_STATS
+                walk_flush<StatSlot<Job>::value>(tally);
+#endif
                 job.drain();
                 break;
             }
             continue;
         }
+#ifdef GRT_STATS
+        if (lane == 0) {
+            ++tally[kStSteps];
+            tally[kStActive] += (uint32_t)__popcll(busy);
+        }
+#endif
         if (active) {
             if (job.walker().advance(job.S, job.visit())) {
+#ifdef GRT_STATS
+                walk_tally(tally, job.walker());
+#endif
                 job.finish(ray);
                 active = false;
             }

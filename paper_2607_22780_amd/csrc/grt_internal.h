@@ -301,6 +301,12 @@ hipError_t launch_denoise(const DenoiseArgs &a, hipStream_t st);
 hipError_t launch_env_prefilter(const float *rgb, int H, int W, const EnvWS &w, hipStream_t st, bool lut = true);
 hipError_t launch_dfg_lut(float *lut, hipStream_t st);
 
+// Walk statistics of the instrumented build (compiled with GRT_STATS): 2 x 9
+// sums of the render kernels' walks; reset zeroes them after the read.  The
+// caller synchronises the device first.
+bool walk_stats_built();
+hipError_t walk_stats_read(unsigned long long *out, bool reset);
+
 struct RenderArgs {
     SceneDev S;
     EnvDev E;

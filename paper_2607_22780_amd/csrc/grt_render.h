@@ -508,10 +508,6 @@ struct ShadeTrace {
         if (a.dump) {
             float *dp = a.dump + r * 10;
             dp[7] = Li.x; dp[8] = Li.y; dp[9] = Li.z;
-#ifdef GRT_STATS
-            dp[3] = (float)w.st_nodes; dp[4] = (float)w.st_leaves; dp[5] = (float)w.st_rounds;
-            dp[6] = (float)w.st_lost; dp[7] = (float)w.st_deferred; dp[8] = (float)v.cnt;
-#endif
         }
     }
 };

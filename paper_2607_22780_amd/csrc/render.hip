@@ -203,6 +203,7 @@ __global__ void __launch_bounds__(256) k_render_gen(RenderArgs a)
 // ---------------------------------------------------------------------------
 template <int K, bool kHitList>
 struct RenderJob {
+    static constexpr int kStatSlot = 0;  // walk statistics (instrumented build)
     const RenderArgs &a;
     SceneDev S;
     ShadeTrace<K, kHitList> t;
@@ -273,6 +274,7 @@ __global__ void __launch_bounds__(256) k_relight_shade(RenderArgs a, int64_t tot
 // left to that kernel).
 template <int K, bool kOrigin>
 struct RenderBwdJob {
+    static constexpr int kStatSlot = 1;  // walk statistics (instrumented build)
     const RenderArgs &a;
     SceneDev S;
     BwdWalker<K> w;
@@ -753,6 +755,31 @@ hipError_t launch_render_backward(const RenderArgs &a, const RenderWS &w, int k,
     }
     if (e != hipSuccess) return e;
     return timer_mark(tm, true, st);
+}
+
+bool walk_stats_built()
+{
+#ifdef GRT_STATS
+    return true;
+#else
+    return false;
+#endif
+}
+
+hipError_t walk_stats_read(unsigned long long *out, bool reset)
+{
+#ifdef GRT_STATS
+    hipError_t e = hipMemcpyFromSymbol(out, HIP_SYMBOL(g_walk_stats), sizeof(g_walk_stats));
+    if (e == hipSuccess && reset) {
+        unsigned long long zero[2][kNumWalkStats] = {};
+        e = hipMemcpyToSymbol(HIP_SYMBOL(g_walk_stats), zero, sizeof(zero));
+    }
+    return e;
+#else
+    (void)out;
+    (void)reset;
+    return hipErrorNotSupported;
+#endif
 }
 
 }  // namespace grt

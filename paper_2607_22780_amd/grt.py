@@ -16,6 +16,8 @@ import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libgrt.so")
+# the same sources compiled with -DGRT_STATS (walk statistics; slower kernels)
+STATS_LIB_PATH = os.path.join(HERE, "libgrt_stats.so")
 
 OK = 0
 ERR_INVALID = -1
@@ -187,6 +189,7 @@ SIGNATURES = {
     "grt_timer_create": (C.c_int, [VP, P(VP)]),
     "grt_timer_ms": (C.c_int, [VP, P(C.c_float)]),
     "grt_timer_destroy": (C.c_int, [VP]),
+    "grt_walk_stats": (C.c_int, [VP, P(C.c_uint64), C.c_int]),
     "grt_server_job_bytes": (C.c_size_t, [P(grt_job)]),
     "grt_server_workspace_bytes": (C.c_size_t, [P(grt_server_opts)]),
     "grt_server_create": (C.c_int, [VP, VP, P(grt_server_opts), P(VP)]),
@@ -751,6 +754,20 @@ class Timer:
         if h:
             load_library().grt_timer_destroy(h)
             self.handle = None
+
+
+WALK_STATS = ("rays", "node_visits", "leaf_tests", "composites", "rounds", "restarts", "deferred", "wave_steps",
+              "active_lanes")
+
+
+def walk_stats(ctx: Context, reset: bool = True) -> dict:
+    """The walk statistics (grt_walk_stats) of a library built with
+    -DGRT_STATS: {"forward": {...}, "backward": {...}} of WALK_STATS sums."""
+    out = (C.c_uint64 * (2 * len(WALK_STATS)))()
+    _check(load_library().grt_walk_stats(ctx.handle, out, int(reset)))
+    v = list(out)
+    n = len(WALK_STATS)
+    return {kind: dict(zip(WALK_STATS, v[i * n:(i + 1) * n])) for i, kind in enumerate(("forward", "backward"))}
 
 
 def make_mis_opts(split=(16, 8, 8), seed=0, job=0, t_min=1e-3, t_cut=1e-3, k=16, dump=None, hits=None, hit_cap=0,
