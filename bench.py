@@ -531,7 +531,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--k", type=int, default=12, help="k-buffer size of the forward")
-    ap.add_argument("--k-bwd", type=int, default=8, help="k-buffer size of the backward")
+    ap.add_argument("--k-bwd", type=int, default=9, help="k-buffer size of the backward")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=192, help="pixels of the step the oracle times per run")
     ap.add_argument("--no-serve", action="store_true", help="skip the relighting-server leg")

@@ -750,9 +750,8 @@ class Timer:
         return float(v.value)
 
     def __del__(self):
-        h = getattr(self, "handle", None)
-        if h:
-            load_library().grt_timer_destroy(h)
+        if getattr(self, "handle", None) and _LIB is not None:
+            _LIB.grt_timer_destroy(self.handle)
             self.handle = None
 
 
