@@ -361,7 +361,8 @@ def serve_inputs(n, rate):
     return reqs, gbs, envs
 
 
-def serve_leg(ctx, scene, k, reqs, gbs, envs, warm, slack=-1.0, epoch=0, extra=False, load=0.0):
+def serve_leg(ctx, scene, k, reqs, gbs, envs, warm, slack=-1.0, epoch=0, extra=False, load=0.0, slack_alt=-1.0,
+              small=0):
     """The persistent batched server against one launch per request (upload,
     tables, render, copy back, in arrival order), on the same relighting
     requests (the attribute query and split-sum shading under each request's
@@ -369,7 +370,12 @@ def serve_leg(ctx, scene, k, reqs, gbs, envs, warm, slack=-1.0, epoch=0, extra=F
     The first `warm` requests of each run warm the system and are left out of
     the latency statistics.  load > 0: the Poisson arrival times are scaled so
     that the offered load is `load` of one launch per request's measured
-    capacity (its mean service time in the all-at-once run)."""
+    capacity (its mean service time in the all-at-once run).  slack_alt >= 0:
+    the server's replay once more at that slack.  small > 0: a stream of that
+    many small requests (256x256, 4 or 8 spp) submitted at once, where one
+    launch per request is bound by each launch's slowest rays and the server
+    batches requests into epochs of up to 1M rays.  k: the relighting query's
+    k-buffer size, on both sides."""
     import torch
     from paper_2607_22780_amd import grt
     from paper_2607_22780_amd import workloads as W
@@ -388,13 +394,15 @@ def serve_leg(ctx, scene, k, reqs, gbs, envs, warm, slack=-1.0, epoch=0, extra=F
     rays_m = sum(r.rays for r in req_srv[measured])
     arrivals = [q.arrival_s for q in reqs]
 
-    def run_server(replay, share=-1.0, rlist=None):
+    def run_server(replay, share=-1.0, rlist=None, sl=None, arr=None, meas=None):
         rlist = req_srv if rlist is None else rlist
-        srv = grt.Server(ctx, scene, mem_budget=48 << 30, max_jobs=16, k=k, slack_per_ray=slack, epoch_rays=epoch,
-                         preempt_share=share, attrs=mats)
+        arr = arrivals if arr is None else arr
+        meas = measured if meas is None else meas
+        srv = grt.Server(ctx, scene, mem_budget=48 << 30, max_jobs=16, k=12, k_relight=k,
+                         slack_per_ray=slack if sl is None else sl, epoch_rays=epoch, preempt_share=share, attrs=mats)
         t0 = time.perf_counter()
         ids = []
-        for q, r in zip(arrivals, rlist):
+        for q, r in zip(arr, rlist):
             if replay:
                 dt = t0 + q - time.perf_counter()
                 if dt > 0:
@@ -406,16 +414,19 @@ def serve_leg(ctx, scene, k, reqs, gbs, envs, warm, slack=-1.0, epoch=0, extra=F
                 raise grt.GrtError(st, "server request failed")
         times = [srv.times(j) for j in ids]
         srv.close()
-        lat = [d - s for s, _, d in times][measured]
-        tm = times[measured]
+        lat = [d - s for s, _, d in times][meas]
+        tm = times[meas]
         span = max(d for _, _, d in tm) - min(s for s, _, _ in tm)
         return lat, span
 
-    def run_one(replay):
+    def run_one(replay, rlist=None, arr=None, meas=None):
+        rlist = req_one if rlist is None else rlist
+        arr = arrivals if arr is None else arr
+        meas = measured if meas is None else meas
         stream = torch.cuda.current_stream()
         t0 = time.perf_counter()
         lat, marks = [], []
-        for q, r in zip(arrivals, req_one):
+        for q, r in zip(arr, rlist):
             if replay:
                 dt = t0 + q - time.perf_counter()
                 if dt > 0:
@@ -432,8 +443,8 @@ def serve_leg(ctx, scene, k, reqs, gbs, envs, warm, slack=-1.0, epoch=0, extra=F
             lat.append(done - arrive)
             marks.append((arrive, done))
             del E
-        tm = marks[measured]
-        return lat[measured], max(d for _, d in tm) - min(a for a, _ in tm)
+        tm = marks[meas]
+        return lat[meas], max(d for _, d in tm) - min(a for a, _ in tm)
 
     pct = lambda a, p: float(np.percentile(np.asarray(a), p))
     summary = lambda lat, span: {"p50_s": round(pct(lat, 50), 4), "p99_s": round(pct(lat, 99), 4),
@@ -449,6 +460,10 @@ def serve_leg(ctx, scene, k, reqs, gbs, envs, warm, slack=-1.0, epoch=0, extra=F
         arrivals = [a * (service_s / load) / gap0 for a in arrivals]
     log("bench: server leg (replayed arrivals)")
     s_rep = run_server(True)
+    s_alt = None
+    if slack_alt >= 0.0:
+        log(f"bench: server leg (replayed arrivals, slack {slack_alt:g} s/ray)")
+        s_alt = run_server(True, sl=slack_alt)
     log("bench: per-request leg (replayed arrivals)")
     o_rep = run_one(True)
     gap = arrivals[-1] / max(len(arrivals) - 1, 1)
@@ -465,6 +480,29 @@ def serve_leg(ctx, scene, k, reqs, gbs, envs, warm, slack=-1.0, epoch=0, extra=F
         "one_launch_per_request": {"replay": summary(*o_rep), "burst": summary(*o_bur)},
         "images_identical": bool(same),
     }
+    if s_alt is not None:
+        res[f"server_replay_slack_{slack_alt:g}"] = summary(*s_alt)
+    if small > 0:
+        # small requests only: 256x256 at 4 or 8 spp over the four cameras,
+        # all submitted at once (no warm-up left out)
+        g = np.random.default_rng(17)
+        cams = sorted(c for r, c in pinned if r == 256)
+        sm = [(int(g.choice(cams)), int(g.choice([4, 8]))) for _ in range(small)]
+        env_of = lambda i: envs[i % len(envs)]
+        mk_small = lambda: [grt.Request(pinned[(256, cam)], pin(env_of(i)), W.mis_split(spp), 7000 + i, 9000 + i,
+                                        relight=True) for i, (cam, spp) in enumerate(sm)]
+        zero, allm = [0.0] * small, slice(0, small)
+        sm_rays = sum(256 * 256 * spp for _, spp in sm)
+        log(f"bench: small-request stream ({small} requests, all at once)")
+        ro, rs = mk_small(), mk_small()
+        o_sm = run_one(False, rlist=ro, arr=zero, meas=allm)
+        s_sm = run_server(False, rlist=rs, arr=zero, meas=allm)
+        same_sm = all(torch.equal(a.out, b.out) for a, b in zip(rs, ro))
+        summ = lambda lat, span: {"p50_s": round(pct(lat, 50), 4), "p99_s": round(pct(lat, 99), 4),
+                                  "mean_s": round(float(np.mean(lat)), 4), "mrays_s": round(sm_rays / span / 1e6, 2)}
+        res["small_request_stream"] = {"requests": small, "rays": sm_rays, "res": 256, "spp": [4, 8],
+                                       "server": summ(*s_sm), "one_launch_per_request": summ(*o_sm),
+                                       "images_identical": bool(same_sm)}
     if extra:
         log("bench: server leg with preemption (radiance requests, replayed arrivals)")
         rad = [grt.Request(pinned[(q.res, q.cam)], pin(envs[i]), splits[i], q.seed, q.rid) for i, q in enumerate(reqs)]
@@ -532,6 +570,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--k", type=int, default=12, help="k-buffer size of the forward")
     ap.add_argument("--k-bwd", type=int, default=9, help="k-buffer size of the backward")
+    ap.add_argument("--k-relight", type=int, default=10, help="k-buffer size of the relighting query")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=192, help="pixels of the step the oracle times per run")
     ap.add_argument("--no-serve", action="store_true", help="skip the relighting-server leg")
@@ -548,9 +587,13 @@ def main():
     ap.add_argument("--serve-load", type=float, default=0.7,
                     help="offered load when the rate is derived: arrivals are spaced so that one launch per request "
                          "(its mean service time measured in the all-at-once run) is busy this share of the time")
-    ap.add_argument("--serve-slack", type=float, default=1e-8,
-                    help="server deadline seconds per ray (-1: the server's default, 4e-8); 1e-8 keeps large "
-                         "requests close to arrival order, which measured the best p99 at 0.7 load")
+    ap.add_argument("--serve-slack", type=float, default=0.0,
+                    help="server deadline seconds per ray (-1: the server's default, 4e-8); 0 is arrival order, "
+                         "which gives the lowest p99 on one GPU")
+    ap.add_argument("--serve-slack-alt", type=float, default=2e-8,
+                    help="a second replay of the server at this slack (lower mean latency; negative: skip)")
+    ap.add_argument("--serve-small", type=int, default=200,
+                    help="requests of the small-request stream (256x256, 4 or 8 spp, all at once; 0: skip)")
     ap.add_argument("--serve-epoch", type=int, default=0, help="server rays per epoch (0: default)")
     ap.add_argument("--count-work", action="store_true", help="recount per-ray work with the oracle and exit")
     ap.add_argument("--calib-copy", action="store_true", help="only time a plain 1 GiB device copy and exit")
@@ -678,7 +721,7 @@ def main():
         for _ in range(3):
             ef0.record(st); E2.prefilter(); ef1.record(st)
             eg0.record(st)
-            out = grt.render_relight(scene, E2, *mats, G, split=SPLIT, seed=SEED, k=args.k)
+            out = grt.render_relight(scene, E2, *mats, G, split=SPLIT, seed=SEED, k=args.k_relight)
             eg1.record(st)
             torch.cuda.synchronize()
             pf.append(ef0.elapsed_time(ef1)); rf.append(eg0.elapsed_time(eg1))
@@ -766,8 +809,9 @@ def main():
         log("bench: generating relighting requests")
         derived = args.serve_rate <= 0.0
         reqs, gbs, envs = serve_inputs(args.serve_requests, 1.0 if derived else args.serve_rate)
-        serve = serve_leg(ctx, scene, args.k, reqs, gbs, envs, args.serve_warm, args.serve_slack, args.serve_epoch,
-                          extra=args.serve_extra, load=args.serve_load if derived else 0.0)
+        serve = serve_leg(ctx, scene, args.k_relight, reqs, gbs, envs, args.serve_warm, args.serve_slack, args.serve_epoch,
+                          extra=args.serve_extra, load=args.serve_load if derived else 0.0,
+                          slack_alt=args.serve_slack_alt, small=args.serve_small)
         del reqs, gbs, envs
 
     cpu = None

@@ -403,8 +403,9 @@ typedef struct {
  * alpha = roughness^2), then N_e environment samples.
  * t_min: self-intersection offset along the secondary ray (1e-3).
  * k: k-nearest hit buffer size per traversal round, one of 1,2,4,8,12,16,32;
- *   grt_render_mis_backward(_shading) also takes 9 (results do not depend on
- *   k; the room workload runs 12 forward, 9 backward).
+ *   grt_render_mis_backward(_shading) also takes 9 and grt_render_relight 10
+ *   (results do not depend on k; the room workload runs 12 forward, 9
+ *   backward, 10 relighting).
  * sample_dump: optional [npix, spp, 10] floats per sample: direction (3),
  *   mixture pdf q, weight f cos/q (3), incident radiance L_i (3); zeros for
  *   samples below the horizon or invalid pixels.
@@ -664,6 +665,7 @@ int grt_denoise(grt_ctx *ctx, int H, int W, const float *rgb, const float *depth
  *                takes the rest of the earliest-deadline request, plus the
  *                next requests while the epoch stays within 1,048,576 rays.
  * k:             k-buffer size, 4, 8, 12 or 16.  t_min, t_cut as in grt_mis_opts.
+ * k_relight:     k-buffer size of relighting epochs, 4, 8, 10, 12 or 16 (0 = k).
  * slack_per_ray: seconds of deadline per ray (0 = arrival order only;
  *                negative = 4e-8, about twice a request's time alone).
  * preempt_share: rays that more urgent requests may run ahead of a started
@@ -691,7 +693,9 @@ int grt_denoise(grt_ctx *ctx, int H, int W, const float *rgb, const float *depth
  *                epoch's buffers fit the pool (the joint order and its sort,
  *                and a copy of the samples' records in that order: 104
  *                bytes a sample for relighting, 92 for radiance).  Each
- *                image is the same as traced alone. */
+ *                image is the same as traced alone.  Every member finishes
+ *                with the group, so the earliest request waits for the
+ *                others: 0 keeps requests in deadline order. */
 typedef struct {
     size_t mem_budget;
     int max_jobs;
@@ -705,6 +709,7 @@ typedef struct {
     void *workspace;
     size_t ws_bytes;
     int co_trace;
+    int k_relight;
 } grt_server_opts;
 
 /* Device bytes grt_server_create needs in opts->workspace for these opts

@@ -518,10 +518,24 @@ struct ShadeTrace {
 // albedo) in the sample's contribution slot, (roughness, metallic) in the
 // spare words of its ray record, the averaged normal in rl_n*.  `a` may
 // differ per lane (the server mixes requests).
-template <int K>
+//
+// kPerRayArgs: lanes may trace for different requests (the server's mixed
+// epochs), so the query's tables are set with each ray.  Otherwise the job
+// sets them once (bind) and they stay wavefront-uniform: held per lane, the
+// five values pushed the K = 12 kernel to 23 spilled registers.
+template <int K, bool kPerRayArgs = false>
 struct RelightTrace {
     Walker<K> w;
     AttrVisit v;
+
+    __device__ __forceinline__ void bind(const RenderArgs &a, const SceneDev &S)
+    {
+        v.rec = S.rec;
+        v.albedo = a.sa_albedo;
+        v.rough = a.sa_rough;
+        v.metal = a.sa_metal;
+        v.tcut = a.tcut;
+    }
 
     __device__ __forceinline__ bool begin(const RenderArgs &a, const SceneDev &S, int64_t r)
     {
@@ -533,11 +547,7 @@ struct RelightTrace {
         const int64_t p = r / (a.nc + a.ng + a.ne);
         const float3 x = make_float3(a.x[3 * p], a.x[3 * p + 1], a.x[3 * p + 2]);
         const float3 d = make_float3(r0.x, r0.y, r0.z);
-        v.rec = S.rec;
-        v.albedo = a.sa_albedo;
-        v.rough = a.sa_rough;
-        v.metal = a.sa_metal;
-        v.tcut = a.tcut;
+        if constexpr (kPerRayArgs) bind(a, S);
         v.reset(x, d);
         w.start(S, x, d, a.tmin, INFINITY);
         if (S.n <= 0) {
@@ -559,6 +569,16 @@ struct RelightTrace {
         a.rl_nz[r] = v.N.z * inv;
     }
 };
+
+// Once per job, for jobs whose lanes all trace for one request: the
+// relighting query's tables (the radiance trace needs nothing).
+template <class Trace>
+__device__ __forceinline__ void bind_trace(Trace &, const RenderArgs &, const SceneDev &) {}
+template <int K>
+__device__ __forceinline__ void bind_trace(RelightTrace<K, false> &t, const RenderArgs &a, const SceneDev &S)
+{
+    t.bind(a, S);
+}
 
 // c_pbr = (1/N_r) sum_j contrib[p, j], summed in sample order
 __device__ __forceinline__ void reduce_pixel(int64_t p, int spp, const float4 *__restrict__ contrib,

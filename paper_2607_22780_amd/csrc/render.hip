@@ -232,7 +232,7 @@ struct RelightJob {
     RelightTrace<K> t;
     int64_t r;
 
-    __device__ RelightJob(const RenderArgs &a_) : a(a_), S(a_.S), r(0) {}
+    __device__ RelightJob(const RenderArgs &a_) : a(a_), S(a_.S), r(0) { t.bind(a, S); }
     __device__ __forceinline__ Walker<K> &walker() { return t.w; }
     __device__ __forceinline__ AttrVisit &visit() { return t.v; }
     __device__ __forceinline__ bool begin(int64_t g)
@@ -677,7 +677,7 @@ template <int K>
 static hipError_t go_relight(const RenderArgs &a, int num_cu, hipStream_t st)
 {
     const int64_t total = (int64_t)a.H * a.W * (a.nc + a.ng + a.ne);
-    if constexpr (K == 12) {
+    if constexpr (K == 10 || K == 12) {
         const int nb = persistent_blocks(k_render_relight_w3<K>, num_cu, total);
         hipLaunchKernelGGL(k_render_relight_w3<K>, dim3(nb), dim3(256), 0, st, a);
     } else {
@@ -700,6 +700,7 @@ hipError_t launch_render_relight(const RenderArgs &a, const RenderWS &w, int k, 
     case 2: e = go_relight<2>(a, num_cu, st); break;
     case 4: e = go_relight<4>(a, num_cu, st); break;
     case 8: e = go_relight<8>(a, num_cu, st); break;
+    case 10: e = go_relight<10>(a, num_cu, st); break;
     case 12: e = go_relight<12>(a, num_cu, st); break;
     case 16: e = go_relight<16>(a, num_cu, st); break;
     case 32: e = go_relight<32>(a, num_cu, st); break;

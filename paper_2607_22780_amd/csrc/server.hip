@@ -185,7 +185,10 @@ struct ServeOneJob {
     int64_t r;
 
     __device__ ServeOneJob(const RenderArgs &a_, const ServeChunk *c, int nc, int64_t r0_)
-        : a(a_), S(a_.S), chunks(c), nchunks(nc), r0(r0_), r(0) {}
+        : a(a_), S(a_.S), chunks(c), nchunks(nc), r0(r0_), r(0)
+    {
+        bind_trace(t, a, S);
+    }
     __device__ __forceinline__ Walker<K> &walker() { return t.w; }
     __device__ __forceinline__ decltype(t.v) &visit() { return t.v; }
     __device__ __forceinline__ bool begin(int64_t g)
@@ -245,10 +248,11 @@ __global__ void k_serve_reduce(const RenderArgs *a, int64_t npix, const unsigned
     reduce_pixel(p, a->nc + a->ng + a->ne, a->contrib, a->out);
 }
 
+// K = 10 (relighting) and 12 held to 3 wavefronts per SIMD, as in a direct render
 template <int K, class Trace, bool kStop>
 static hipError_t go_serve_as(const ServeEpoch &e, int num_cu, hipStream_t st)
 {
-    if constexpr (K == 12) {
+    if constexpr (K == 10 || K == 12) {
         const int nb = persistent_blocks(k_serve_w3<K, Trace, kStop>, num_cu, e.total);
         hipLaunchKernelGGL((k_serve_w3<K, Trace, kStop>), dim3(nb), dim3(256), 0, st, e);
     } else {
@@ -261,7 +265,7 @@ static hipError_t go_serve_as(const ServeEpoch &e, int num_cu, hipStream_t st)
 template <int K, class Trace, bool kPlain>
 static hipError_t go_serve_one_as(const RenderArgs &a, const ServeEpoch &e, int64_t r0, int num_cu, hipStream_t st)
 {
-    if constexpr (K == 12) {
+    if constexpr (K == 10 || K == 12) {
         const int nb = persistent_blocks(k_serve_one_w3<K, Trace, kPlain>, num_cu, e.total);
         hipLaunchKernelGGL((k_serve_one_w3<K, Trace, kPlain>), dim3(nb), dim3(256), 0, st, a, e.chunks, e.nchunks,
                            r0, e.total, e.counters, e.stop);
@@ -273,14 +277,24 @@ static hipError_t go_serve_one_as(const RenderArgs &a, const ServeEpoch &e, int6
     return hipGetLastError();
 }
 
-// Radiance epochs may be stopped; relighting epochs never are.
+// Radiance epochs may be stopped; relighting epochs never are.  A mixed
+// epoch's lanes trace for different requests, so its relighting query takes
+// its tables with each ray; those per-lane tables spill at K = 10, so mixed
+// epochs then run the 8-entry buffer (the size changes no result).
+template <int K>
+static hipError_t go_relight_epoch(const ServeEpoch &e, const RenderArgs *one, int64_t r0, int num_cu,
+                                   hipStream_t st)
+{
+    constexpr int Km = K == 10 ? 8 : K;
+    return one ? go_serve_one_as<K, RelightTrace<K>, true>(*one, e, r0, num_cu, st)
+               : go_serve_as<Km, RelightTrace<Km, true>, false>(e, num_cu, st);
+}
+
 template <int K>
 static hipError_t go_epoch(const ServeEpoch &e, const RenderArgs *one, int64_t r0, bool relight, int num_cu,
                            hipStream_t st)
 {
-    if (relight)
-        return one ? go_serve_one_as<K, RelightTrace<K>, true>(*one, e, r0, num_cu, st)
-                   : go_serve_as<K, RelightTrace<K>, false>(e, num_cu, st);
+    if (relight) return go_relight_epoch<K>(e, one, r0, num_cu, st);
     if (one)
         return (!e.stop && e.nchunks <= 1) ? go_serve_one_as<K, ShadeTrace<K>, true>(*one, e, r0, num_cu, st)
                                            : go_serve_one_as<K, ShadeTrace<K>, false>(*one, e, r0, num_cu, st);
@@ -299,6 +313,7 @@ static hipError_t launch_epoch(const ServeEpoch &e, const RenderArgs *one, int64
     switch (k) {
     case 4: return go_epoch<4>(e, one, r0, relight, num_cu, st);
     case 8: return go_epoch<8>(e, one, r0, relight, num_cu, st);
+    case 10: return relight ? go_relight_epoch<10>(e, one, r0, num_cu, st) : hipErrorInvalidValue;
     case 12: return go_epoch<12>(e, one, r0, relight, num_cu, st);
     case 16: return go_epoch<16>(e, one, r0, relight, num_cu, st);
     default: return hipErrorInvalidValue;
@@ -767,7 +782,10 @@ void sweep(grt_server *s)
 }
 
 // Requests are batched into one epoch only while it stays within this many rays.
-constexpr int64_t kFillRays = 1 << 20;
+#ifndef GRT_SERVE_FILL_RAYS
+#define GRT_SERVE_FILL_RAYS (1 << 20)
+#endif
+constexpr int64_t kFillRays = GRT_SERVE_FILL_RAYS;
 // A single-request epoch of at least this many rays can be stopped when a
 // request with an earlier deadline arrives, unless it is estimated to end
 // within kStopSeconds anyway.
@@ -815,6 +833,12 @@ static bool whole(const ServerJob &j)
 // finds each ray's request per lane, holds more registers), then the results
 // are scattered back.  False (nothing launched) when fewer than two requests
 // qualify or the epoch's buffers do not fit the pool.
+// k of an epoch's trace: relighting epochs take k_relight when it is set
+static int epoch_k(const grt_server *s, bool relight)
+{
+    return relight && s->opts.k_relight ? s->opts.k_relight : s->opts.k;
+}
+
 static bool launch_cotrace(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other,
                            const std::vector<ServerJob *> &run, int64_t budget, hipError_t &err)
 {
@@ -918,7 +942,7 @@ static bool launch_cotrace(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &oth
         hipLaunchKernelGGL(grt::k_joint_gather, dim3(nb), dim3(256), 0, E.stream, je);
         err = hipGetLastError();
     }
-    if (err == hipSuccess) err = grt::launch_epoch(e, &J, 0, relight, s->opts.k, s->ctx->num_cu, E.stream);
+    if (err == hipSuccess) err = grt::launch_epoch(e, &J, 0, relight, epoch_k(s, relight), s->ctx->num_cu, E.stream);
     if (err == hipSuccess) {
         hipLaunchKernelGGL(grt::k_joint_scatter, dim3(nb), dim3(256), 0, E.stream, je);
         err = hipGetLastError();
@@ -988,8 +1012,13 @@ bool launch(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other, int64_t bud
             want += take;
             if (want >= budget) break;
         }
+        // (kTailSeconds 0: never on the estimate alone.  The rate is a mean
+        // and an epoch's end is its slowest rays, so an estimate that says
+        // the other epoch is over comes early; a large epoch started then held
+        // the CUs that the other's shading and per-pixel sum still needed,
+        // and a 4M-ray request waited 0.47 s for a 38M-ray one.)
         const double left = (double)other.rays - s->rate * (s->now() - other.t_launch);
-        const bool tail = left <= s->rate * kTailSeconds;
+        const bool tail = kTailSeconds > 0.0 && left <= s->rate * kTailSeconds;
         const bool small = (double)want <= kSmallShare * left;
         if (!tail && !small) return false;
     }
@@ -1049,7 +1078,7 @@ bool launch(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other, int64_t bud
         err = hipMemcpyAsync(E.d_chunks, E.h_chunks, sizeof(grt::ServeChunk) * nch, hipMemcpyHostToDevice, E.stream);
     const grt::RenderArgs *one = E.members.size() == 1 ? &E.h_jobs[E.h_chunks[0].slot] : nullptr;
     if (err == hipSuccess)
-        err = grt::launch_epoch(e, one, E.h_chunks[0].begin, relight, s->opts.k, s->ctx->num_cu, E.stream);
+        err = grt::launch_epoch(e, one, E.h_chunks[0].begin, relight, epoch_k(s, relight), s->ctx->num_cu, E.stream);
     if (err == hipSuccess && E.preemptible)
         err = hipMemcpyAsync(E.h_counters, E.counters, grt::kParts * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                              E.stream);
@@ -1258,6 +1287,9 @@ int grt_server_create(grt_ctx *ctx, const grt_scene *scene, const grt_server_opt
     if (((uintptr_t)opts->workspace & 255u) != 0) return sfail(GRT_ERR_INVALID, "server workspace must be 256-byte aligned");
     if (!(opts->k == 4 || opts->k == 8 || opts->k == 12 || opts->k == 16))
         return sfail(GRT_ERR_INVALID, "server k must be 4, 8, 12 or 16");
+    if (!(opts->k_relight == 0 || opts->k_relight == 4 || opts->k_relight == 8 || opts->k_relight == 10 ||
+          opts->k_relight == 12 || opts->k_relight == 16))
+        return sfail(GRT_ERR_INVALID, "server k_relight must be 0, 4, 8, 10, 12 or 16");
     if (!(opts->t_min >= 0.0f) || !(opts->t_cut >= 0.0f && opts->t_cut < 1.0f))
         return sfail(GRT_ERR_INVALID, "bad t_min / t_cut");
     grt_server *s = new (std::nothrow) grt_server;

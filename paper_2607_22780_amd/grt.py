@@ -111,7 +111,7 @@ class grt_server_opts(C.Structure):
     _fields_ = [("mem_budget", C.c_size_t), ("max_jobs", C.c_int), ("epoch_rays", C.c_int64), ("k", C.c_int),
                 ("t_min", C.c_float), ("t_cut", C.c_float), ("slack_per_ray", C.c_double),
                 ("preempt_share", C.c_double), ("attrs", grt_surfel_attrs), ("workspace", VP),
-                ("ws_bytes", C.c_size_t), ("co_trace", C.c_int)]
+                ("ws_bytes", C.c_size_t), ("co_trace", C.c_int), ("k_relight", C.c_int)]
 
 
 class grt_camera(C.Structure):
@@ -823,7 +823,7 @@ def render_mis(scene: Scene, env: Env, gb: GBuffer, split=(16, 8, 8), seed=0, jo
 
 
 def render_relight(scene: Scene, env: Env, albedo, rough, metal, gb: GBuffer, split=(16, 8, 8), seed=0, job=0,
-                   t_min=1e-3, t_cut=1e-3, k=12, dump=False, workspace=None, stream=None):
+                   t_min=1e-3, t_cut=1e-3, k=10, dump=False, workspace=None, stream=None):
     """Relit c_pbr [npix,3] under the prefiltered `env` (Sec. 3.5.1, Eq.
     relight_splitsum), surfel attributes albedo [n,3], rough [n], metal [n]."""
     dev = gb.x.device
@@ -1165,11 +1165,15 @@ class Server:
     """Owns a grt_server over a built scene; submit Requests, wait, read times."""
 
     def __init__(self, ctx: Context, scene: Scene, mem_budget: int, max_jobs: int = 16, epoch_rays: int = 0, k=8,
-                 t_min=1e-3, t_cut=1e-3, slack_per_ray=-1.0, preempt_share=-1.0, attrs=None, co_trace=True):
+                 t_min=1e-3, t_cut=1e-3, slack_per_ray=-1.0, preempt_share=-1.0, attrs=None, co_trace=False,
+                 k_relight=10):
         """attrs: (albedo, rough, metal) device tensors for camera and
         relighting requests, kept alive with the server.  The server's device
         memory (pool and tables) is a torch tensor owned here.  co_trace:
-        trace waiting requests that share a G-buffer in one joint order."""
+        trace waiting requests that share a G-buffer in one joint order (off
+        by default: it holds the earliest request until the whole group is
+        done, and did not raise throughput on the relighting mix).
+        k_relight: k-buffer size of relighting epochs (k for radiance)."""
         self.ctx, self.scene = ctx, scene
         self.attrs = attrs
         at = grt_surfel_attrs(*(_ptr(a) for a in attrs)) if attrs is not None else grt_surfel_attrs()
@@ -1182,6 +1186,7 @@ class Server:
         self.opts.workspace = _ptr(self.workspace)
         self.opts.ws_bytes = self.workspace.numel()
         self.opts.co_trace = 1 if co_trace else 0
+        self.opts.k_relight = int(k_relight)
         self.handle = grt_server_create(ctx.handle, scene.handle, self.opts)
         self.requests = {}
 
