@@ -663,7 +663,9 @@ int grt_denoise(grt_ctx *ctx, int H, int W, const float *rgb, const float *depth
  * max_jobs:      requests resident at once (1..256).
  * epoch_rays:    at most this many rays per epoch (0 = 134,217,728); an epoch
  *                takes the rest of the earliest-deadline request, plus the
- *                next requests while the epoch stays within 1,048,576 rays.
+ *                next requests while the epoch stays within 4,194,304 rays.
+ *                One epoch runs at a time (the next starts once the one in
+ *                flight is done, or stopped).
  * k:             k-buffer size, 4, 8, 12 or 16.  t_min, t_cut as in grt_mis_opts.
  * k_relight:     k-buffer size of relighting epochs, 4, 8, 10, 12 or 16 (0 = k).
  * slack_per_ray: seconds of deadline per ray (0 = arrival order only;

@@ -781,9 +781,12 @@ void sweep(grt_server *s)
     s->resident.swap(keep);
 }
 
-// Requests are batched into one epoch only while it stays within this many rays.
+// Requests are batched into one epoch only while it stays within this many
+// rays.  A lone launch of a few hundred thousand rays is bound by its slowest
+// rays; on a stream of 256x256 requests at 4 or 8 spp, epochs of up to 4M
+// rays traced 59 Mrays/s, 1M-ray epochs 43, one launch per request 26.
 #ifndef GRT_SERVE_FILL_RAYS
-#define GRT_SERVE_FILL_RAYS (1 << 20)
+#define GRT_SERVE_FILL_RAYS (1 << 22)
 #endif
 constexpr int64_t kFillRays = GRT_SERVE_FILL_RAYS;
 // A single-request epoch of at least this many rays can be stopped when a
@@ -793,15 +796,18 @@ constexpr int64_t kPreemptRays = 1 << 21;
 constexpr double kStopSeconds = 0.015;
 // Launch gate: the estimated time left of the epoch in flight below which the
 // next epoch starts, and the share of its remaining rays below which a next
-// epoch counts as small and starts at once.  Starting a large epoch in the
-// tail of another measured slower overall on relighting bursts (the two ray
-// streams share the caches: 38.4 s against 38.0 s for 220 requests), so a
-// large epoch waits for the one in flight; small ones still pass.
+// epoch counts as small and starts at once.  Both are off: an epoch started
+// while another is in flight takes the CUs as the other's waves leave, so the
+// other's shading and per-pixel sum, queued behind it, wait for it to end.
+// Starting a large epoch in the tail of another measured slower on
+// relighting bursts (38.4 s against 38.0 s for 220 requests: the two ray
+// streams share the caches), and letting small epochs pass made the
+// replay's tail latencies vary by 10% from run to run and rise on average.
 #ifndef GRT_SERVE_TAIL_S
 #define GRT_SERVE_TAIL_S 0.0
 #endif
 #ifndef GRT_SERVE_SMALL_SHARE
-#define GRT_SERVE_SMALL_SHARE 0.05
+#define GRT_SERVE_SMALL_SHARE 0.0
 #endif
 constexpr double kTailSeconds = GRT_SERVE_TAIL_S;
 constexpr double kSmallShare = GRT_SERVE_SMALL_SHARE;
@@ -1002,8 +1008,8 @@ bool launch(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other, int64_t bud
         }
     // Launch gate: while the other epoch is in flight, the next one starts
     // only once that one is estimated to be within kTailSeconds of its end,
-    // or at once when it is small next to what the other epoch has left (so
-    // a small request passes a large one without slowing it noticeably).
+    // or at once when it is small next to what the other epoch has left (both
+    // off as built: the next epoch waits for the one in flight).
     if (other.inflight && !other.stopped) {
         int64_t want = 0;
         for (ServerJob *j : run) {
@@ -1019,7 +1025,7 @@ bool launch(grt_server *s, grt::EpochSlot &E, grt::EpochSlot &other, int64_t bud
         // and a 4M-ray request waited 0.47 s for a 38M-ray one.)
         const double left = (double)other.rays - s->rate * (s->now() - other.t_launch);
         const bool tail = kTailSeconds > 0.0 && left <= s->rate * kTailSeconds;
-        const bool small = (double)want <= kSmallShare * left;
+        const bool small = kSmallShare > 0.0 && (double)want <= kSmallShare * left;
         if (!tail && !small) return false;
     }
     if (launch_cotrace(s, E, other, run, budget, err)) return true;

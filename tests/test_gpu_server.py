@@ -388,9 +388,9 @@ def test_cotraced_requests_match_direct_render(setup, relight):
     pin = lambda a: torch.from_numpy(np.ascontiguousarray(a)).pin_memory()
     shared = type("G", (), dict(H=gb.H, W=gb.W, x=pin(gb.x), n=pin(gb.n), wo=pin(gb.wo), albedo=pin(gb.albedo),
                                 rough=pin(gb.rough), metal=pin(gb.metal), valid=pin(gb.valid)))
-    # 160 x 120 x 64 spp = 1.2M samples each: above the 1M fill size
-    cases = [(shared, W.envmap(32, 64, seed=40 + i), W.mis_split(64), 300 + i, 9 + i) for i in range(4)]
-    cases.insert(2, (other, W.envmap(32, 64, seed=50), W.mis_split(64), 310, 20))
+    # 160 x 120 x 128 spp = 2.5M samples each: two exceed the 4M fill size
+    cases = [(shared, W.envmap(32, 64, seed=40 + i), W.mis_split(128), 300 + i, 9 + i) for i in range(4)]
+    cases.insert(2, (other, W.envmap(32, 64, seed=50), W.mis_split(128), 310, 20))
     ref = []
     for g, env, split, seed, job in cases:
         src = gb if g is shared else g
