@@ -459,12 +459,23 @@ __device__ __forceinline__ void gen_ray(const RenderArgs &a, int64_t r)
 
 // The persistent-loop job of the forward render: begin loads the ray record
 // (skipping untraced samples), finish writes f L_i cos / q and the saved
-// (C, T).  `a` may differ per lane (the server mixes jobs).  kHitList: the
-// launch stores hit lists (a.hits); only then does the visitor carry one.
-template <int K, bool kHitList = false>
+// (C, T).  kHitList: the launch stores hit lists (a.hits); only then does the
+// visitor carry one.  kPerRayArgs: lanes may trace for different requests
+// (the server's mixed epochs), so the visitor's tables are set with each
+// ray; otherwise the job sets them once (bind) and they stay
+// wavefront-uniform (at K = 12 that removed the kernel's 2 spilled registers
+// and 3% of its time).
+template <int K, bool kHitList = false, bool kPerRayArgs = false>
 struct ShadeTrace {
     Walker<K> w;
     CompositeVisit<kHitList> v;
+
+    __device__ __forceinline__ void bind(const RenderArgs &a, const SceneDev &S)
+    {
+        v.rec = S.rec;
+        v.col = S.col;
+        v.tcut = a.tcut;
+    }
 
     __device__ __forceinline__ bool begin(const RenderArgs &a, const SceneDev &S, int64_t r)
     {
@@ -483,9 +494,7 @@ struct ShadeTrace {
         }
         const float3 x = make_float3(a.x[3 * p], a.x[3 * p + 1], a.x[3 * p + 2]);
         const float3 d = make_float3(r0.x, r0.y, r0.z);
-        v.rec = S.rec;
-        v.col = S.col;
-        v.tcut = a.tcut;
+        if constexpr (kPerRayArgs) bind(a, S);
         v.reset(x, d);
         w.start(S, x, d, a.tmin, INFINITY);
         if (S.n <= 0) {
@@ -570,10 +579,13 @@ struct RelightTrace {
     }
 };
 
-// Once per job, for jobs whose lanes all trace for one request: the
-// relighting query's tables (the radiance trace needs nothing).
-template <class Trace>
-__device__ __forceinline__ void bind_trace(Trace &, const RenderArgs &, const SceneDev &) {}
+// Once per job, for jobs whose lanes all trace for one request: the trace's
+// tables (a per-ray trace takes them in begin).
+template <int K, bool kHitList>
+__device__ __forceinline__ void bind_trace(ShadeTrace<K, kHitList, false> &t, const RenderArgs &a, const SceneDev &S)
+{
+    t.bind(a, S);
+}
 template <int K>
 __device__ __forceinline__ void bind_trace(RelightTrace<K, false> &t, const RenderArgs &a, const SceneDev &S)
 {

@@ -209,7 +209,7 @@ struct RenderJob {
     ShadeTrace<K, kHitList> t;
     int64_t r;  // sample index of the lane's ray
 
-    __device__ RenderJob(const RenderArgs &a_) : a(a_), S(a_.S), r(0) {}
+    __device__ RenderJob(const RenderArgs &a_) : a(a_), S(a_.S), r(0) { t.bind(a, S); }
     __device__ __forceinline__ Walker<K> &walker() { return t.w; }
     __device__ __forceinline__ decltype(t.v) &visit() { return t.v; }
     __device__ __forceinline__ bool begin(int64_t g)

@@ -118,9 +118,10 @@ __device__ __forceinline__ int find_chunk(const ServeChunk *chunks, int nchunks,
     return lo;
 }
 
-// Trace: ShadeTrace<K> (the radiance trace of Eq. mis) or RelightTrace<K>
-// (the attribute query of relighting, Eq. trace_attr); an epoch holds
-// requests of one kind.
+// Trace: ShadeTrace<K, false, true> (the radiance trace of Eq. mis) or
+// RelightTrace<K, true> (the attribute query of relighting, Eq.
+// trace_attr), both taking their request's tables with each ray; an epoch
+// holds requests of one kind.
 template <int K, class Trace>
 struct ServeJob {
     const ServeEpoch &e;
@@ -298,8 +299,8 @@ static hipError_t go_epoch(const ServeEpoch &e, const RenderArgs *one, int64_t r
     if (one)
         return (!e.stop && e.nchunks <= 1) ? go_serve_one_as<K, ShadeTrace<K>, true>(*one, e, r0, num_cu, st)
                                            : go_serve_one_as<K, ShadeTrace<K>, false>(*one, e, r0, num_cu, st);
-    return e.stop ? go_serve_as<K, ShadeTrace<K>, true>(e, num_cu, st)
-                  : go_serve_as<K, ShadeTrace<K>, false>(e, num_cu, st);
+    return e.stop ? go_serve_as<K, ShadeTrace<K, false, true>, true>(e, num_cu, st)
+                  : go_serve_as<K, ShadeTrace<K, false, true>, false>(e, num_cu, st);
 }
 
 // one: the request when every chunk of the epoch is of that one request, else
