@@ -568,9 +568,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--k", type=int, default=12, help="k-buffer size of the forward")
+    ap.add_argument("--k", type=int, default=14, help="k-buffer size of the forward")
     ap.add_argument("--k-bwd", type=int, default=9, help="k-buffer size of the backward")
-    ap.add_argument("--k-relight", type=int, default=10, help="k-buffer size of the relighting query")
+    ap.add_argument("--k-relight", type=int, default=12, help="k-buffer size of the relighting query")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=192, help="pixels of the step the oracle times per run")
     ap.add_argument("--no-serve", action="store_true", help="skip the relighting-server leg")
@@ -735,7 +735,7 @@ def main():
         holder = {}
 
         def gtrace():
-            holder["g"] = grt.trace_gbuffer(scene, *mats, co, cd, gb.H, gb.W, k=args.k)
+            holder["g"] = grt.trace_gbuffer(scene, *mats, co, cd, gb.H, gb.W, k=12)
 
         gt_ms = _median_ms(gtrace, 5)
         gbt = holder.pop("g")
@@ -747,7 +747,7 @@ def main():
         gzs = grt.zero_grads(scene.n, dev)
         gza = dict(albedo=torch.zeros(scene.n, 3, device=dev), rough=torch.zeros(scene.n, device=dev),
                    metal=torch.zeros(scene.n, device=dev))
-        gbw_ms = _median_ms(lambda: grt.trace_gbuffer_backward(scene, *mats, co, cd, gbt, gup, k=args.k, grads=gzs,
+        gbw_ms = _median_ms(lambda: grt.trace_gbuffer_backward(scene, *mats, co, cd, gbt, gup, k=12, grads=gzs,
                                                                attr_grads=gza), 3)
         del gbt, gup, gzs, gza
         # the same relit frame with the mesh backend answering the query

@@ -403,9 +403,9 @@ typedef struct {
  * alpha = roughness^2), then N_e environment samples.
  * t_min: self-intersection offset along the secondary ray (1e-3).
  * k: k-nearest hit buffer size per traversal round, one of 1,2,4,8,12,16,32;
- *   grt_render_mis_backward(_shading) also takes 9 and grt_render_relight 10
- *   (results do not depend on k; the room workload runs 12 forward, 9
- *   backward, 10 relighting).
+ *   grt_render_mis (and _noalloc) also takes 14 and grt_render_mis_backward
+ *   (_shading) 9 (results do not depend on k; the room workload runs 14
+ *   forward, 9 backward, 12 relighting).
  * sample_dump: optional [npix, spp, 10] floats per sample: direction (3),
  *   mixture pdf q, weight f cos/q (3), incident radiance L_i (3); zeros for
  *   samples below the horizon or invalid pixels.
@@ -667,7 +667,7 @@ int grt_denoise(grt_ctx *ctx, int H, int W, const float *rgb, const float *depth
  *                One epoch runs at a time (the next starts once the one in
  *                flight is done, or stopped).
  * k:             k-buffer size, 4, 8, 12 or 16.  t_min, t_cut as in grt_mis_opts.
- * k_relight:     k-buffer size of relighting epochs, 4, 8, 10, 12 or 16 (0 = k).
+ * k_relight:     k-buffer size of relighting epochs, 4, 8, 12 or 16 (0 = k).
  * slack_per_ray: seconds of deadline per ray (0 = arrival order only;
  *                negative = 4e-8, about twice a request's time alone).
  * preempt_share: rays that more urgent requests may run ahead of a started

@@ -108,8 +108,8 @@ int check_rays(const grt_rays *r)
     return GRT_OK;
 }
 
-// extra: one more size a call takes (the MIS backward 9, relighting 10: the
-// largest that fit their kernels' register budgets), 0: none
+// extra: one more size a call takes (the MIS forward 14, its backward 9:
+// sizes that fit their kernels' register budgets), 0: none
 static int check_k(int k, int extra = 0)
 {
     if (k == 1 || k == 2 || k == 4 || k == 8 || k == 12 || k == 16 || k == 32) return GRT_OK;
@@ -797,7 +797,7 @@ int grt_render_relight(const grt_scene *scene, const grt_env *env, const grt_sur
                        void *stream)
 {
     grt::RenderArgs a;
-    int rc = fill_render_args(scene, env, g, opts, a, 10);
+    int rc = fill_render_args(scene, env, g, opts, a);
     if (rc) return rc;
     if (!env->prefiltered) return fail(GRT_ERR_NOT_BUILT, "relighting needs grt_env_prefilter first");
     if (!attrs) return fail(GRT_ERR_INVALID, "attrs is NULL");
@@ -870,7 +870,7 @@ int grt_render_mis(const grt_scene *scene, const grt_env *env, const grt_gbuffer
                    float *out_rgb, void *saved, void *workspace, size_t ws_bytes, void *stream)
 {
     grt::RenderArgs a;
-    int rc = fill_render_args(scene, env, g, opts, a);
+    int rc = fill_render_args(scene, env, g, opts, a, 14);
     if (rc) return rc;
     if ((int64_t)g->H * g->W > 0 && !out_rgb) return fail(GRT_ERR_INVALID, "out_rgb is NULL");
     if (saved && !aligned(saved, 16)) return fail(GRT_ERR_INVALID, "saved must be 16-byte aligned");

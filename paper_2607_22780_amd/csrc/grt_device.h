@@ -613,7 +613,7 @@ struct Walker {
             return false;
         }
         const bool stop = visit(sp, (uint32_t)(key[0] & 0xffffffffu), __uint_as_float((uint32_t)(key[0] >> 32)), r0,
-                                r1, r2, r3, rho2);
+                                r1, r2, r3, rho2, o, d);
 #ifdef GRT_STATS
         ++st_comps;
 #endif

@@ -16,7 +16,6 @@ template <bool kHitList>
 struct CompositeVisit {
     const float4 *rec;
     const float4 *col;
-    float3 o, d;
     float tcut;
     float3 C;
     float T, Td;
@@ -30,10 +29,8 @@ struct CompositeVisit {
     __device__ CompositeVisit() {}
     __device__ CompositeVisit(const SceneDev &S, float t_cut) : rec(S.rec), col(S.col), tcut(t_cut) {}
 
-    __device__ __forceinline__ void reset(float3 o_, float3 d_)
+    __device__ __forceinline__ void reset()
     {
-        o = o_;
-        d = d_;
         C = make_float3(0.f, 0.f, 0.f);
         T = 1.0f;
         Td = 1.0f;
@@ -43,7 +40,8 @@ struct CompositeVisit {
     // Hit p (record r0..r3, canonical rho^2 crho2) of the ray, in order;
     // true when compositing stops after it.
     __device__ __forceinline__ bool operator()(uint32_t p, uint32_t id, float tau, const float4 r0, const float4 r1,
-                                               const float4 r2, const float4 r3, float crho2)
+                                               const float4 r2, const float4 r3, float crho2, const float3 o,
+                                               const float3 d)
     {
         const float4 c = col[p];
         HitGeo g;
@@ -71,7 +69,6 @@ __device__ __forceinline__ float dot3(float3 a, float3 b) { return a.x * b.x + a
 struct AttrVisit {
     const float4 *rec;
     const float *albedo, *rough, *metal;  // per surfel id
-    float3 o, d;
     float tcut;
     float T, Td, W, R, M;
     float3 A, N;
@@ -80,10 +77,8 @@ struct AttrVisit {
     __device__ AttrVisit(const SceneDev &S, float t_cut, const float *al, const float *ro, const float *me)
         : rec(S.rec), albedo(al), rough(ro), metal(me), tcut(t_cut) {}
 
-    __device__ __forceinline__ void reset(float3 o_, float3 d_)
+    __device__ __forceinline__ void reset()
     {
-        o = o_;
-        d = d_;
         T = 1.0f;
         Td = 1.0f;
         W = 0.0f; R = 0.0f; M = 0.0f;
@@ -92,7 +87,8 @@ struct AttrVisit {
     }
 
     __device__ __forceinline__ bool operator()(uint32_t p, uint32_t id, float tau, const float4 r0, const float4 r1,
-                                               const float4 r2, const float4 r3, float crho2)
+                                               const float4 r2, const float4 r3, float crho2, const float3 o,
+                                               const float3 d)
     {
         HitGeo g;
         value_geo(r0, r1, r2, r3, o, d, g);
@@ -123,15 +119,16 @@ struct GBufVisit : AttrVisit {
     __device__ GBufVisit(const SceneDev &S, float t_cut, const float *al, const float *ro, const float *me)
         : AttrVisit(S, t_cut, al, ro, me), col(S.col) {}
 
-    __device__ __forceinline__ void reset(float3 o_, float3 d_)
+    __device__ __forceinline__ void reset()
     {
-        AttrVisit::reset(o_, d_);
+        AttrVisit::reset();
         Dsum = 0.0f;
         Csum = make_float3(0.f, 0.f, 0.f);
     }
 
     __device__ __forceinline__ bool operator()(uint32_t p, uint32_t id, float tau, const float4 r0, const float4 r1,
-                                               const float4 r2, const float4 r3, float crho2)
+                                               const float4 r2, const float4 r3, float crho2, const float3 o,
+                                               const float3 d)
     {
         HitGeo g;
         value_geo(r0, r1, r2, r3, o, d, g);
@@ -140,7 +137,7 @@ struct GBufVisit : AttrVisit {
         const float4 c = col[p];
         Dsum += w * tau;
         Csum.x += w * c.x; Csum.y += w * c.y; Csum.z += w * c.z;
-        return AttrVisit::operator()(p, id, tau, r0, r1, r2, r3, crho2);
+        return AttrVisit::operator()(p, id, tau, r0, r1, r2, r3, crho2, o, d);
     }
 };
 
@@ -269,7 +266,7 @@ struct GradVisitT {
     float tcut;
     GradPtrs g;
     WaveStage *stage = nullptr;  // the wavefront's staging list
-    float3 o, d, gC, Cf;
+    float3 gC, Cf;
     float gT, Tf;
     float T, Td;
     float3 P;
@@ -280,10 +277,8 @@ struct GradVisitT {
     __device__ GradVisitT(const SceneDev &S, float t_cut, const GradPtrs &gp)
         : rec(S.rec), col(S.col), tcut(t_cut), g(gp), quat(S.quat) {}
 
-    __device__ __forceinline__ void reset(float3 o_, float3 d_, float3 gC_, float gT_, float3 Cf_, float Tf_)
+    __device__ __forceinline__ void reset(float3 gC_, float gT_, float3 Cf_, float Tf_)
     {
-        o = o_;
-        d = d_;
         gC = gC_;
         gT = gT_;
         Cf = Cf_;
@@ -295,7 +290,8 @@ struct GradVisitT {
     }
 
     __device__ __forceinline__ bool operator()(uint32_t p, uint32_t id, float tau, const float4 r0, const float4 r1,
-                                               const float4 r2, const float4 r3, float crho2)
+                                               const float4 r2, const float4 r3, float crho2, const float3 o,
+                                               const float3 d)
     {
         const float4 c = col[p];
         const float op = r1.w;
@@ -344,7 +340,6 @@ struct GBufGradVisit {
     float tcut;
     GradPtrs g;
     WaveStage *stage = nullptr;
-    float3 o, d;
     float kD, kR, kM, e0;  // upstream gradients over W, and sum_f g_f F_f / W
     float3 kA, kC, kN;
     float T, Td, P;
@@ -354,17 +349,16 @@ struct GBufGradVisit {
     __device__ GBufGradVisit(const SceneDev &S, float t_cut, const GradPtrs &gp)
         : rec(S.rec), col(S.col), tcut(t_cut), g(gp), quat(S.quat) {}
 
-    __device__ __forceinline__ void reset(float3 o_, float3 d_)
+    __device__ __forceinline__ void reset()
     {
-        o = o_;
-        d = d_;
         T = 1.0f;
         Td = 1.0f;
         P = 0.0f;
     }
 
     __device__ __forceinline__ bool operator()(uint32_t p, uint32_t id, float tau, const float4 r0, const float4 r1,
-                                               const float4 r2, const float4 r3, float crho2)
+                                               const float4 r2, const float4 r3, float crho2, const float3 o,
+                                               const float3 d)
     {
         const float4 c = col[p];
         const float op = r1.w;
@@ -411,7 +405,7 @@ __device__ __forceinline__ bool visit_hit(Visit &visit, const float4 *rec, uint3
     const float4 r0 = r[0], r1 = r[1], r2 = r[2], r3 = r[3];
     float den, tau, rho2;
     canon_geo(r0, r1, r2, r3, o, d, den, tau, rho2);
-    return visit(p, __float_as_uint(r2.w), tau, r0, r1, r2, r3, rho2);
+    return visit(p, __float_as_uint(r2.w), tau, r0, r1, r2, r3, rho2, o, d);
 }
 
 }  // namespace grt

@@ -495,7 +495,7 @@ struct ShadeTrace {
         const float3 x = make_float3(a.x[3 * p], a.x[3 * p + 1], a.x[3 * p + 2]);
         const float3 d = make_float3(r0.x, r0.y, r0.z);
         if constexpr (kPerRayArgs) bind(a, S);
-        v.reset(x, d);
+        v.reset();
         w.start(S, x, d, a.tmin, INFINITY);
         if (S.n <= 0) {
             finish(a, r);
@@ -557,7 +557,7 @@ struct RelightTrace {
         const float3 x = make_float3(a.x[3 * p], a.x[3 * p + 1], a.x[3 * p + 2]);
         const float3 d = make_float3(r0.x, r0.y, r0.z);
         if constexpr (kPerRayArgs) bind(a, S);
-        v.reset(x, d);
+        v.reset();
         w.start(S, x, d, a.tmin, INFINITY);
         if (S.n <= 0) {
             finish(a, r);

@@ -313,7 +313,7 @@ struct RenderBwdJob {
         const float4 sv = a.saved[r];
         const float3 x = make_float3(a.x[3 * p], a.x[3 * p + 1], a.x[3 * p + 2]);
         const float3 d = make_float3(r0.x, r0.y, r0.z);
-        v.reset(x, d, gC, gT, make_float3(sv.x, sv.y, sv.z), sv.w);
+        v.reset(gC, gT, make_float3(sv.x, sv.y, sv.z), sv.w);
         w.start(S, x, d, a.tmin, stop_bound(a.saved_t, r, INFINITY));
         if constexpr (kOrigin) cur = r;
         return true;
@@ -408,7 +408,7 @@ __global__ void __launch_bounds__(256) k_render_bwd_stored(RenderArgs a)
             const float4 sv = a.saved[r];
             x = make_float3(a.x[3 * p], a.x[3 * p + 1], a.x[3 * p + 2]);
             d = make_float3(r0.x, r0.y, r0.z);
-            v.reset(x, d, gC, gT, make_float3(sv.x, sv.y, sv.z), sv.w);
+            v.reset(gC, gT, make_float3(sv.x, sv.y, sv.z), sv.w);
             cnt = nh;
         }
     }
@@ -500,7 +500,7 @@ template <int K, bool kHitList>
 static hipError_t go_render_as(const RenderArgs &a, int num_cu, hipStream_t st)
 {
     const int64_t total = (int64_t)a.H * a.W * (a.nc + a.ng + a.ne);
-    if constexpr (K == 12) {
+    if constexpr (K == 12 || K == 14) {
         const int nb = persistent_blocks(k_render_w3<K, kHitList>, num_cu, total);
         hipLaunchKernelGGL((k_render_w3<K, kHitList>), dim3(nb), dim3(256), 0, st, a);
     } else {
@@ -662,6 +662,7 @@ hipError_t launch_render(const RenderArgs &a, const RenderWS &w, int k, int num_
     case 4: e = go_render<4>(a, num_cu, st); break;
     case 8: e = go_render<8>(a, num_cu, st); break;
     case 12: e = go_render<12>(a, num_cu, st); break;
+    case 14: e = go_render<14>(a, num_cu, st); break;
     case 16: e = go_render<16>(a, num_cu, st); break;
     case 32: e = go_render<32>(a, num_cu, st); break;
     default: return hipErrorInvalidValue;
@@ -677,7 +678,7 @@ template <int K>
 static hipError_t go_relight(const RenderArgs &a, int num_cu, hipStream_t st)
 {
     const int64_t total = (int64_t)a.H * a.W * (a.nc + a.ng + a.ne);
-    if constexpr (K == 10 || K == 12) {
+    if constexpr (K == 12) {
         const int nb = persistent_blocks(k_render_relight_w3<K>, num_cu, total);
         hipLaunchKernelGGL(k_render_relight_w3<K>, dim3(nb), dim3(256), 0, st, a);
     } else {
@@ -700,7 +701,6 @@ hipError_t launch_render_relight(const RenderArgs &a, const RenderWS &w, int k, 
     case 2: e = go_relight<2>(a, num_cu, st); break;
     case 4: e = go_relight<4>(a, num_cu, st); break;
     case 8: e = go_relight<8>(a, num_cu, st); break;
-    case 10: e = go_relight<10>(a, num_cu, st); break;
     case 12: e = go_relight<12>(a, num_cu, st); break;
     case 16: e = go_relight<16>(a, num_cu, st); break;
     case 32: e = go_relight<32>(a, num_cu, st); break;

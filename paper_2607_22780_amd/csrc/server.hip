@@ -249,11 +249,11 @@ __global__ void k_serve_reduce(const RenderArgs *a, int64_t npix, const unsigned
     reduce_pixel(p, a->nc + a->ng + a->ne, a->contrib, a->out);
 }
 
-// K = 10 (relighting) and 12 held to 3 wavefronts per SIMD, as in a direct render
+// K = 12 held to 3 wavefronts per SIMD, as in a direct render
 template <int K, class Trace, bool kStop>
 static hipError_t go_serve_as(const ServeEpoch &e, int num_cu, hipStream_t st)
 {
-    if constexpr (K == 10 || K == 12) {
+    if constexpr (K == 12) {
         const int nb = persistent_blocks(k_serve_w3<K, Trace, kStop>, num_cu, e.total);
         hipLaunchKernelGGL((k_serve_w3<K, Trace, kStop>), dim3(nb), dim3(256), 0, st, e);
     } else {
@@ -266,7 +266,7 @@ static hipError_t go_serve_as(const ServeEpoch &e, int num_cu, hipStream_t st)
 template <int K, class Trace, bool kPlain>
 static hipError_t go_serve_one_as(const RenderArgs &a, const ServeEpoch &e, int64_t r0, int num_cu, hipStream_t st)
 {
-    if constexpr (K == 10 || K == 12) {
+    if constexpr (K == 12) {
         const int nb = persistent_blocks(k_serve_one_w3<K, Trace, kPlain>, num_cu, e.total);
         hipLaunchKernelGGL((k_serve_one_w3<K, Trace, kPlain>), dim3(nb), dim3(256), 0, st, a, e.chunks, e.nchunks,
                            r0, e.total, e.counters, e.stop);
@@ -280,13 +280,13 @@ static hipError_t go_serve_one_as(const RenderArgs &a, const ServeEpoch &e, int6
 
 // Radiance epochs may be stopped; relighting epochs never are.  A mixed
 // epoch's lanes trace for different requests, so its relighting query takes
-// its tables with each ray; those per-lane tables spill at K = 10, so mixed
+// its tables with each ray; those per-lane tables spill at K = 12, so mixed
 // epochs then run the 8-entry buffer (the size changes no result).
 template <int K>
 static hipError_t go_relight_epoch(const ServeEpoch &e, const RenderArgs *one, int64_t r0, int num_cu,
                                    hipStream_t st)
 {
-    constexpr int Km = K == 10 ? 8 : K;
+    constexpr int Km = K == 12 ? 8 : K;
     return one ? go_serve_one_as<K, RelightTrace<K>, true>(*one, e, r0, num_cu, st)
                : go_serve_as<Km, RelightTrace<Km, true>, false>(e, num_cu, st);
 }
@@ -314,7 +314,6 @@ static hipError_t launch_epoch(const ServeEpoch &e, const RenderArgs *one, int64
     switch (k) {
     case 4: return go_epoch<4>(e, one, r0, relight, num_cu, st);
     case 8: return go_epoch<8>(e, one, r0, relight, num_cu, st);
-    case 10: return relight ? go_relight_epoch<10>(e, one, r0, num_cu, st) : hipErrorInvalidValue;
     case 12: return go_epoch<12>(e, one, r0, relight, num_cu, st);
     case 16: return go_epoch<16>(e, one, r0, relight, num_cu, st);
     default: return hipErrorInvalidValue;
@@ -1294,9 +1293,9 @@ int grt_server_create(grt_ctx *ctx, const grt_scene *scene, const grt_server_opt
     if (((uintptr_t)opts->workspace & 255u) != 0) return sfail(GRT_ERR_INVALID, "server workspace must be 256-byte aligned");
     if (!(opts->k == 4 || opts->k == 8 || opts->k == 12 || opts->k == 16))
         return sfail(GRT_ERR_INVALID, "server k must be 4, 8, 12 or 16");
-    if (!(opts->k_relight == 0 || opts->k_relight == 4 || opts->k_relight == 8 || opts->k_relight == 10 ||
-          opts->k_relight == 12 || opts->k_relight == 16))
-        return sfail(GRT_ERR_INVALID, "server k_relight must be 0, 4, 8, 10, 12 or 16");
+    if (!(opts->k_relight == 0 || opts->k_relight == 4 || opts->k_relight == 8 || opts->k_relight == 12 ||
+          opts->k_relight == 16))
+        return sfail(GRT_ERR_INVALID, "server k_relight must be 0, 4, 8, 12 or 16");
     if (!(opts->t_min >= 0.0f) || !(opts->t_cut >= 0.0f && opts->t_cut < 1.0f))
         return sfail(GRT_ERR_INVALID, "bad t_min / t_cut");
     grt_server *s = new (std::nothrow) grt_server;

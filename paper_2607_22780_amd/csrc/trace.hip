@@ -51,7 +51,7 @@ struct TraceJob {
         const float3 d = make_float3(a.d[3 * r], a.d[3 * r + 1], a.d[3 * r + 2]);
         const float tmin = a.tmin_a ? fmaxf(a.tmin_a[r], 0.0f) : a.tmin;  // negative: 0
         const float tmax = a.tmax_a ? a.tmax_a[r] : a.tmax;
-        v.reset(o, d);
+        v.reset();
         if (a.dump_id) { v.did = a.dump_id + r * a.cap; v.dtau = a.dump_tau + r * a.cap; v.cap = a.cap; }
         w.start(S, o, d, tmin, tmax);
         if (S.n <= 0) {
@@ -111,7 +111,7 @@ struct TraceBwdJob {
         const float tmin = a.f.tmin_a ? fmaxf(a.f.tmin_a[r], 0.0f) : a.f.tmin;  // negative: 0
         const float tmax = a.f.tmax_a ? a.f.tmax_a[r] : a.f.tmax;
         const float3 C = make_float3(a.fwd_rgb[3 * r], a.fwd_rgb[3 * r + 1], a.fwd_rgb[3 * r + 2]);
-        v.reset(o, d, gC, gT, C, a.fwd_T[r]);
+        v.reset(gC, gT, C, a.fwd_T[r]);
         w.start(S, o, d, tmin, stop_bound(a.f.stop_depth, r, tmax));
         return true;
     }
@@ -148,7 +148,7 @@ struct TraceAttrJob {
         const float3 d = make_float3(a.f.d[3 * r], a.f.d[3 * r + 1], a.f.d[3 * r + 2]);
         const float tmin = a.f.tmin_a ? fmaxf(a.f.tmin_a[r], 0.0f) : a.f.tmin;  // negative: 0
         const float tmax = a.f.tmax_a ? a.f.tmax_a[r] : a.f.tmax;
-        v.reset(o, d);
+        v.reset();
         w.start(S, o, d, tmin, tmax);
         if (S.n <= 0) {
             finish(r);
@@ -191,7 +191,7 @@ struct TraceGBufJob {
         const float3 d = make_float3(a.f.d[3 * r], a.f.d[3 * r + 1], a.f.d[3 * r + 2]);
         const float tmin = a.f.tmin_a ? fmaxf(a.f.tmin_a[r], 0.0f) : a.f.tmin;  // negative: 0
         const float tmax = a.f.tmax_a ? a.f.tmax_a[r] : a.f.tmax;
-        v.reset(o, d);
+        v.reset();
         w.start(S, o, d, tmin, tmax);
         if (S.n <= 0) {
             finish(r);
@@ -207,11 +207,11 @@ struct TraceGBufJob {
         const float nl = sqrtf(N.x * N.x + N.y * N.y + N.z * N.z);
         const bool ok = v.W > 0.0f && 1.0f - v.T >= a.min_opacity && nl > 0.0f;
         const float in = ok ? 1.0f / nl : 0.0f, D = ok ? v.Dsum * inv : 0.0f, m = ok ? inv : 0.0f;
-        a.x[3 * r] = ok ? v.o.x + D * v.d.x : 0.0f;
-        a.x[3 * r + 1] = ok ? v.o.y + D * v.d.y : 0.0f;
-        a.x[3 * r + 2] = ok ? v.o.z + D * v.d.z : 0.0f;
+        a.x[3 * r] = ok ? w.o.x + D * w.d.x : 0.0f;  // the walker holds the ray
+        a.x[3 * r + 1] = ok ? w.o.y + D * w.d.y : 0.0f;
+        a.x[3 * r + 2] = ok ? w.o.z + D * w.d.z : 0.0f;
         a.n[3 * r] = N.x * in; a.n[3 * r + 1] = N.y * in; a.n[3 * r + 2] = N.z * in;
-        a.wo[3 * r] = ok ? -v.d.x : 0.0f; a.wo[3 * r + 1] = ok ? -v.d.y : 0.0f; a.wo[3 * r + 2] = ok ? -v.d.z : 0.0f;
+        a.wo[3 * r] = ok ? -w.d.x : 0.0f; a.wo[3 * r + 1] = ok ? -w.d.y : 0.0f; a.wo[3 * r + 2] = ok ? -w.d.z : 0.0f;
         a.out_albedo[3 * r] = v.A.x * m; a.out_albedo[3 * r + 1] = v.A.y * m; a.out_albedo[3 * r + 2] = v.A.z * m;
         a.out_rough[r] = v.R * m;
         a.out_metal[r] = v.M * m;
@@ -372,7 +372,7 @@ struct TraceGBufBwdJob {
         v.kN = make_float3((gn.x - nh.x * ndg) * iN, (gn.y - nh.y * ndg) * iN, (gn.z - nh.z * ndg) * iN);
         const float tmin = a.f.tmin_a ? fmaxf(a.f.tmin_a[r], 0.0f) : a.f.tmin;  // negative: 0
         const float tmax = a.f.tmax_a ? a.f.tmax_a[r] : a.f.tmax;
-        v.reset(o, d);
+        v.reset();
         w.start(S, o, d, tmin, stop_bound(a.f.stop_depth, r, tmax));
         return true;
     }

@@ -823,7 +823,7 @@ def render_mis(scene: Scene, env: Env, gb: GBuffer, split=(16, 8, 8), seed=0, jo
 
 
 def render_relight(scene: Scene, env: Env, albedo, rough, metal, gb: GBuffer, split=(16, 8, 8), seed=0, job=0,
-                   t_min=1e-3, t_cut=1e-3, k=10, dump=False, workspace=None, stream=None):
+                   t_min=1e-3, t_cut=1e-3, k=12, dump=False, workspace=None, stream=None):
     """Relit c_pbr [npix,3] under the prefiltered `env` (Sec. 3.5.1, Eq.
     relight_splitsum), surfel attributes albedo [n,3], rough [n], metal [n]."""
     dev = gb.x.device
@@ -988,15 +988,18 @@ class RenderMISFn(torch.autograd.Function):
                 k_bwd=None, timers=None):
         """hit_cap > 0: store up to hit_cap hits per sample in the forward and
         differentiate from the stored lists; 0: re-traverse in the backward.
-        k_bwd: k-buffer size of the backward (default k; results do not
-        depend on either).  timers: optional (forward, backward) Timer pair
-        that records the trace kernels of the two passes."""
+        k_bwd: k-buffer size of the backward (default k, or 9 when k is 14,
+        a size only the forward takes; results do not depend on either).
+        timers: optional (forward, backward) Timer pair that records the
+        trace kernels of the two passes."""
         scene = Scene(gctx, means.detach().contiguous(), scales.detach().contiguous(), quats.detach().contiguous(),
                       opacity.detach().contiguous(), rgb.detach().contiguous(), alpha_min)
         hits = make_hit_list(gb.npix, sum(split), hit_cap, gb.x.device) if hit_cap > 0 else None
         tf, tb = timers if timers is not None else (None, None)
         res = render_mis(scene, env, gb, split=split, seed=seed, k=k, save=True, hits=hits, hit_cap=hit_cap, timer=tf)
-        ctx_.scene, ctx_.env, ctx_.gb, ctx_.cfg = scene, env, gb, (split, seed, k if k_bwd is None else k_bwd, hit_cap)
+        if k_bwd is None:
+            k_bwd = 9 if k == 14 else k
+        ctx_.scene, ctx_.env, ctx_.gb, ctx_.cfg = scene, env, gb, (split, seed, k_bwd, hit_cap)
         ctx_.saved_state, ctx_.hits, ctx_.timer = res["saved"], hits, tb
         return res["rgb"]
 
@@ -1024,7 +1027,8 @@ class RenderMISShadedFn(torch.autograd.Function):
         gb = GBuffer(H, W, *(t.detach().contiguous() for t in (x, n, wo, albedo, rough, metal)), valid.contiguous())
         hits = make_hit_list(gb.npix, sum(split), hit_cap, gb.x.device) if hit_cap > 0 else None
         res = render_mis(scene, env, gb, split=split, seed=seed, k=k, save=True, hits=hits, hit_cap=hit_cap)
-        ctx_.scene, ctx_.env, ctx_.gb, ctx_.cfg = scene, env, gb, (split, seed, k, hit_cap)
+        # the backward's k (14 is a size only the forward takes)
+        ctx_.scene, ctx_.env, ctx_.gb, ctx_.cfg = scene, env, gb, (split, seed, 9 if k == 14 else k, hit_cap)
         ctx_.saved_state, ctx_.hits = res["saved"], hits
         return res["rgb"]
 
@@ -1166,7 +1170,7 @@ class Server:
 
     def __init__(self, ctx: Context, scene: Scene, mem_budget: int, max_jobs: int = 16, epoch_rays: int = 0, k=8,
                  t_min=1e-3, t_cut=1e-3, slack_per_ray=-1.0, preempt_share=-1.0, attrs=None, co_trace=False,
-                 k_relight=10):
+                 k_relight=12):
         """attrs: (albedo, rough, metal) device tensors for camera and
         relighting requests, kept alive with the server.  The server's device
         memory (pool and tables) is a torch tensor owned here.  co_trace:
