@@ -108,7 +108,7 @@ int check_rays(const grt_rays *r)
     return GRT_OK;
 }
 
-// extra: one more size a call takes (the MIS forward 14, its backward 9:
+// extra: one more size a call takes (the MIS forward 14, its backward 11:
 // sizes that fit their kernels' register budgets), 0: none
 static int check_k(int k, int extra = 0)
 {
@@ -922,7 +922,7 @@ static int render_backward(const grt_scene *scene, const grt_env *env, const grt
                            size_t ws_bytes, void *stream)
 {
     grt::RenderArgs a;
-    int rc = fill_render_args(scene, env, g, opts, a, 9);
+    int rc = fill_render_args(scene, env, g, opts, a, 11);
     if (rc) return rc;
     if ((int64_t)g->H * g->W > 0 && (!grad_rgb || !saved)) return fail(GRT_ERR_INVALID, "grad_rgb/saved is NULL");
     if (saved && !aligned(saved, 16)) return fail(GRT_ERR_INVALID, "saved must be 16-byte aligned");

@@ -332,7 +332,6 @@ struct Walker {
     float3 o, d, inv;
     float tmin, tmax;
     uint64_t last;        // start key of the round; while compositing, the last composited hit
-    float tlo, thi;
     uint64_t key[K];
     uint32_t pos[K];
     int cnt;
@@ -341,7 +340,6 @@ struct Walker {
     Frontier<D> F;        // walk stack and deferred list (LDS + private spill)
     int ncomp;            // buffered hits still to composite (0 while walking)
     int pend;             // leaf waiting for the next surfel step (record position), or kNone
-    uint64_t round_last;  // largest key of the round's full buffer
 #ifdef GRT_STATS
     int st_nodes, st_leaves, st_comps, st_rounds, st_lost, st_deferred;
 #endif
@@ -351,7 +349,19 @@ struct Walker {
 #pragma unroll
         for (int i = 0; i < K; ++i) { key[i] = ~0ull; pos[i] = 0; }
         cnt = 0;
-        thi = tmax;
+    }
+
+    // The round's walk covers [lo_bound, hi_bound]: from the last composited
+    // key's depth (tmin in the first round) to the full buffer's largest
+    // depth (tmax while it is not full).  Derived when needed rather than
+    // held, to keep two registers free.
+    __device__ __forceinline__ float lo_bound() const
+    {
+        return fmaxf(tmin, __uint_as_float((uint32_t)(last >> 32)));
+    }
+    __device__ __forceinline__ float hi_bound() const
+    {
+        return cnt >= K ? __uint_as_float((uint32_t)(key[K - 1] >> 32)) : tmax;
     }
 
     __device__ __forceinline__ void start(const SceneDev &S, float3 o_, float3 d_, float tmin_, float tmax_)
@@ -362,7 +372,6 @@ struct Walker {
         tmin = tmin_;
         tmax = tmax_;
         last = 0;
-        tlo = tmin;
         ncomp = 0;
         pend = kNone;
         F.walk.reset();
@@ -419,12 +428,11 @@ struct Walker {
         }
         if (!placed) { key[0] = k; pos[0] = p; }
         ++cnt;
-        if (cnt >= K) thi = __uint_as_float((uint32_t)(key[K - 1] >> 32));
     }
 
     // A child box met by the ray in [tlo, tmax]: process now if it starts
     // within thi, else defer it.
-    __device__ __forceinline__ bool keep_child(int c, bool hit, float tn)
+    __device__ __forceinline__ bool keep_child(int c, bool hit, float tn, float thi)
     {
         if (!hit) return false;
         if (tn > thi) {
@@ -464,6 +472,7 @@ struct Walker {
         ++st_nodes;
 #endif
         const Node4 *nd = S.nodes4 + cur;
+        const float tlo = lo_bound(), thi = hi_bound();
         const float4 lx = nd->lx, ly = nd->ly, lz = nd->lz, hx = nd->hx, hy = nd->hy, hz = nd->hz;
         const int4 ch = nd->ch;
         // all four boxes tested without branches (an unused slot's zero box
@@ -485,10 +494,10 @@ struct Walker {
         k1 = k1 & (ch.y != kNoChild);
         k2 = k2 & (ch.z != kNoChild);
         k3 = k3 & (ch.w != kNoChild);
-        k0 = keep_child(ch.x, k0, t0);
-        k1 = keep_child(ch.y, k1, t1);
-        k2 = keep_child(ch.z, k2, t2);
-        k3 = keep_child(ch.w, k3, t3);
+        k0 = keep_child(ch.x, k0, t0, thi);
+        k1 = keep_child(ch.y, k1, t1, thi);
+        k2 = keep_child(ch.z, k2, t2, thi);
+        k3 = keep_child(ch.w, k3, t3, thi);
         const int m = (int)k0 + (int)k1 + (int)k2 + (int)k3;
         // kept children first, by entry depth (a five-exchange sorting network)
         float s0 = k0 ? t0 : INFINITY, s1 = k1 ? t1 : INFINITY, s2 = k2 ? t2 : INFINITY, s3 = k3 ? t3 : INFINITY;
@@ -523,11 +532,11 @@ struct Walker {
         if (no >= 2) F.walk.push(o1);
     }
 
-    // Set up the next round from the deferred frontier (or the root).
+    // Set up the next round from the deferred frontier (or the root).  A next
+    // round follows only a full buffer whose K hits were all composited, so
+    // `last` already holds the round's largest key, where the next one starts.
     __device__ __forceinline__ void next_round(const SceneDev &S)
     {
-        last = round_last;
-        tlo = __uint_as_float((uint32_t)(last >> 32));
         clear_buffer();
 #ifdef GRT_STATS
         ++st_rounds;
@@ -576,7 +585,6 @@ struct Walker {
                 const int m = cnt < K ? cnt : K;
                 if (m == 0) return true;
                 ncomp = m;
-                round_last = key[K - 1];
             } else if (leaf != kNone) {
                 pend = -leaf - 1;
             }

@@ -559,7 +559,7 @@ hipError_t launch_render_backward_stored(const RenderArgs &a, const RenderWS &w,
     case 2: e = go_render_bwd<2>(b, num_cu, st); break;
     case 4: e = go_render_bwd<4>(b, num_cu, st); break;
     case 8: e = go_render_bwd<8>(b, num_cu, st); break;
-    case 9: e = go_render_bwd<9>(b, num_cu, st); break;
+    case 11: e = go_render_bwd<11>(b, num_cu, st); break;
     case 12: e = go_render_bwd<12>(b, num_cu, st); break;
     case 16: e = go_render_bwd<16>(b, num_cu, st); break;
     case 32: e = go_render_bwd<32>(b, num_cu, st); break;
@@ -750,7 +750,7 @@ hipError_t launch_render_backward(const RenderArgs &a, const RenderWS &w, int k,
     case 2: e = go_render_bwd<2>(a, num_cu, st); break;
     case 4: e = go_render_bwd<4>(a, num_cu, st); break;
     case 8: e = go_render_bwd<8>(a, num_cu, st); break;
-    case 9: e = go_render_bwd<9>(a, num_cu, st); break;
+    case 11: e = go_render_bwd<11>(a, num_cu, st); break;
     case 12: e = go_render_bwd<12>(a, num_cu, st); break;
     case 16: e = go_render_bwd<16>(a, num_cu, st); break;
     case 32: e = go_render_bwd<32>(a, num_cu, st); break;
