@@ -568,8 +568,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--k", type=int, default=14, help="k-buffer size of the forward")
-    ap.add_argument("--k-bwd", type=int, default=11, help="k-buffer size of the backward")
+    ap.add_argument("--k", type=int, default=16, help="k-buffer size of the forward")
+    ap.add_argument("--k-bwd", type=int, default=12, help="k-buffer size of the backward")
     ap.add_argument("--k-relight", type=int, default=12, help="k-buffer size of the relighting query")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=192, help="pixels of the step the oracle times per run")

@@ -108,13 +108,9 @@ int check_rays(const grt_rays *r)
     return GRT_OK;
 }
 
-// extra: one more size a call takes (the MIS forward 14, its backward 11:
-// sizes that fit their kernels' register budgets), 0: none
-static int check_k(int k, int extra = 0)
+static int check_k(int k)
 {
     if (k == 1 || k == 2 || k == 4 || k == 8 || k == 12 || k == 16 || k == 32) return GRT_OK;
-    if (extra && k == extra) return GRT_OK;
-    if (extra) return fail(GRT_ERR_INVALID, "k = %d is not one of 1,2,4,8,%d,12,16,32", k, extra);
     return fail(GRT_ERR_INVALID, "k = %d is not one of 1,2,4,8,12,16,32", k);
 }
 
@@ -637,22 +633,20 @@ size_t grt_render_workspace_bytes(int64_t npix, int spp)
     return grt::carve_render(nullptr, npix * spp).bytes;
 }
 
-static int fill_render_common(const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *o, grt::RenderArgs &a,
-                              int extra_k = 0);
+static int fill_render_common(const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *o, grt::RenderArgs &a);
 
 static int fill_render_args(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *o,
-                            grt::RenderArgs &a, int extra_k = 0)
+                            grt::RenderArgs &a)
 {
     int rc = check_scene(scene);
     if (rc) return rc;
-    if ((rc = fill_render_common(env, g, o, a, extra_k))) return rc;
+    if ((rc = fill_render_common(env, g, o, a))) return rc;
     a.S = scene_dev(scene);
     return GRT_OK;
 }
 
 // everything of a render but the scene (a.S left empty)
-static int fill_render_common(const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *o, grt::RenderArgs &a,
-                              int extra_k)
+static int fill_render_common(const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *o, grt::RenderArgs &a)
 {
     int rc;
     if (!env) return fail(GRT_ERR_INVALID, "env is NULL");
@@ -666,7 +660,7 @@ static int fill_render_common(const grt_env *env, const grt_gbuffer *g, const gr
     if (o->n_cos < 0 || o->n_ggx < 0 || o->n_env < 0 || o->n_cos + o->n_ggx + o->n_env <= 0 ||
         o->n_cos + o->n_ggx + o->n_env > 65536)
         return fail(GRT_ERR_INVALID, "bad sample allocation %d/%d/%d", o->n_cos, o->n_ggx, o->n_env);
-    if ((rc = check_k(o->k, extra_k))) return rc;
+    if ((rc = check_k(o->k))) return rc;
     if (!(o->t_min >= 0.0f)) return fail(GRT_ERR_INVALID, "t_min must be >= 0");
     if (!(o->t_cut >= 0.0f && o->t_cut < 1.0f)) return fail(GRT_ERR_INVALID, "t_cut must be in [0,1)");
     memset(&a, 0, sizeof(a));
@@ -870,7 +864,7 @@ int grt_render_mis(const grt_scene *scene, const grt_env *env, const grt_gbuffer
                    float *out_rgb, void *saved, void *workspace, size_t ws_bytes, void *stream)
 {
     grt::RenderArgs a;
-    int rc = fill_render_args(scene, env, g, opts, a, 14);
+    int rc = fill_render_args(scene, env, g, opts, a);
     if (rc) return rc;
     if ((int64_t)g->H * g->W > 0 && !out_rgb) return fail(GRT_ERR_INVALID, "out_rgb is NULL");
     if (saved && !aligned(saved, 16)) return fail(GRT_ERR_INVALID, "saved must be 16-byte aligned");
@@ -922,7 +916,7 @@ static int render_backward(const grt_scene *scene, const grt_env *env, const grt
                            size_t ws_bytes, void *stream)
 {
     grt::RenderArgs a;
-    int rc = fill_render_args(scene, env, g, opts, a, 11);
+    int rc = fill_render_args(scene, env, g, opts, a);
     if (rc) return rc;
     if ((int64_t)g->H * g->W > 0 && (!grad_rgb || !saved)) return fail(GRT_ERR_INVALID, "grad_rgb/saved is NULL");
     if (saved && !aligned(saved, 16)) return fail(GRT_ERR_INVALID, "saved must be 16-byte aligned");

@@ -262,13 +262,13 @@ constexpr int kNone = 0x7fffffff;
 
 template <int D>
 struct SpillStack {
-    int *lds;  // this lane's slot 0; slot i at lds[64 * i]
-    int *mem;  // private overflow array [kStackCap]
     int sp, spilled;
 
     __device__ __forceinline__ void reset() { sp = 0; spilled = 0; }
 
-    __device__ __forceinline__ void push(int x)
+    // lds: this lane's slot 0 of the stack (slot i at lds[64 * i]); mem:
+    // its private overflow array [kStackCap]
+    __device__ __forceinline__ void push(int x, int *lds, int *mem)
     {
         const int slot = sp % D;
         if (sp >= D && sp - D >= spilled) {
@@ -279,7 +279,7 @@ struct SpillStack {
         ++sp;
     }
 
-    __device__ __forceinline__ int pop()
+    __device__ __forceinline__ int pop(int *lds, int *mem)
     {
         --sp;
         if (sp < spilled) {
@@ -305,14 +305,23 @@ template <int D>
 struct Frontier {
     SpillStack<D> walk;  // the current round's walk stack
     SpillStack<D> def;   // deferrals for the next round
+    int *lds;            // this lane's slot 0 of stack 0; stack 1 starts D slots on
+    int *mem0, *mem1;    // the two stacks' private overflow arrays
+    int role;            // the stack that holds the walk (the other one defers)
 
-    // the deferred list becomes the walk stack (descriptor fields swapped, no copy)
+    __device__ __forceinline__ int *lds_of(int which) const { return lds + 64 * D * which; }
+    __device__ __forceinline__ int *mem_of(int which) const { return which ? mem1 : mem0; }
+    __device__ __forceinline__ void push_walk(int x) { walk.push(x, lds_of(role), mem_of(role)); }
+    __device__ __forceinline__ int pop_walk() { return walk.pop(lds_of(role), mem_of(role)); }
+    __device__ __forceinline__ void push_def(int x) { def.push(x, lds_of(role ^ 1), mem_of(role ^ 1)); }
+
+    // the deferred list becomes the walk stack (positions swapped, no copy)
     __device__ __forceinline__ void swap_roles()
     {
-        int *l = walk.lds, *m = walk.mem;
-        const int a = walk.sp, b = walk.spilled;
-        walk.lds = def.lds; walk.mem = def.mem; walk.sp = def.sp; walk.spilled = def.spilled;
-        def.lds = l; def.mem = m; def.sp = a; def.spilled = b;
+        const SpillStack<D> t = walk;
+        walk = def;
+        def = t;
+        role ^= 1;
     }
 };
 
@@ -393,7 +402,7 @@ struct Walker {
             F.def.reset();
             return;
         }
-        F.def.push(x);
+        F.push_def(x);
 #ifdef GRT_STATS
         ++st_deferred;
 #endif
@@ -449,7 +458,7 @@ struct Walker {
     {
         if (cur == kNone) {
             if (F.walk.sp == 0) return true;
-            cur = F.walk.pop();
+            cur = F.pop_walk();
         }
         if (cur < 0) {
             leaf = cur;
@@ -527,9 +536,9 @@ struct Walker {
             no = m - 1;
         }
         cur = no >= 1 ? o0 : kNone;
-        if (no >= 4) F.walk.push(o3);
-        if (no >= 3) F.walk.push(o2);
-        if (no >= 2) F.walk.push(o1);
+        if (no >= 4) F.push_walk(o3);
+        if (no >= 3) F.push_walk(o2);
+        if (no >= 2) F.push_walk(o1);
     }
 
     // Set up the next round from the deferred frontier (or the root).  A next
@@ -741,10 +750,10 @@ __device__ __forceinline__ void run_persistent(Job &job, unsigned long long *cou
     const int wave = (threadIdx.x >> 6) & 3;
     {
         auto &F = job.walker().F;
-        F.walk.lds = &lds_stacks[wave][0][0][lane];
-        F.def.lds = &lds_stacks[wave][1][0][lane];
-        F.walk.mem = spill0;
-        F.def.mem = spill1;
+        F.lds = &lds_stacks[wave][0][0][lane];
+        F.mem0 = spill0;
+        F.mem1 = spill1;
+        F.role = 0;
         F.walk.reset();
         F.def.reset();
     }

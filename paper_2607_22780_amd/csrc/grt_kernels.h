@@ -266,10 +266,10 @@ struct GradVisitT {
     float tcut;
     GradPtrs g;
     WaveStage *stage = nullptr;  // the wavefront's staging list
-    float3 gC, Cf;
-    float gT, Tf;
+    float3 gC;
+    float3 R;     // colour still ahead: the saved c_rt minus the hits composited so far
+    float gTf;    // dL/dT times the saved transmittance
     float T, Td;
-    float3 P;
     float3 gmu;
 
     __device__ GradVisitT() {}
@@ -280,12 +280,10 @@ struct GradVisitT {
     __device__ __forceinline__ void reset(float3 gC_, float gT_, float3 Cf_, float Tf_)
     {
         gC = gC_;
-        gT = gT_;
-        Cf = Cf_;
-        Tf = Tf_;
+        R = Cf_;
+        gTf = gT_ * Tf_;
         T = 1.0f;
         Td = 1.0f;
-        P = make_float3(0.f, 0.f, 0.f);
         gmu = make_float3(0.f, 0.f, 0.f);
     }
 
@@ -300,11 +298,11 @@ struct GradVisitT {
         const float G = expf(-0.5f * hg.rho2);
         const float a = op * G;
         const float w = T * a;
-        P.x += w * c.x; P.y += w * c.y; P.z += w * c.z;
+        R.x -= w * c.x; R.y -= w * c.y; R.z -= w * c.z;
         float dA = T * (gC.x * c.x + gC.y * c.y + gC.z * c.z);
         const float om = 1.0f - a;
         if (om >= 1e-6f) {
-            float behind = gC.x * (Cf.x - P.x) + gC.y * (Cf.y - P.y) + gC.z * (Cf.z - P.z) + gT * Tf;
+            float behind = gC.x * R.x + gC.y * R.y + gC.z * R.z + gTf;
             dA -= behind / om;
         }
         float terms[13];

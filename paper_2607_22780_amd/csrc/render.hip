@@ -500,7 +500,7 @@ template <int K, bool kHitList>
 static hipError_t go_render_as(const RenderArgs &a, int num_cu, hipStream_t st)
 {
     const int64_t total = (int64_t)a.H * a.W * (a.nc + a.ng + a.ne);
-    if constexpr (K == 12 || K == 14) {
+    if constexpr (K == 12 || K == 16) {
         const int nb = persistent_blocks(k_render_w3<K, kHitList>, num_cu, total);
         hipLaunchKernelGGL((k_render_w3<K, kHitList>), dim3(nb), dim3(256), 0, st, a);
     } else {
@@ -559,7 +559,6 @@ hipError_t launch_render_backward_stored(const RenderArgs &a, const RenderWS &w,
     case 2: e = go_render_bwd<2>(b, num_cu, st); break;
     case 4: e = go_render_bwd<4>(b, num_cu, st); break;
     case 8: e = go_render_bwd<8>(b, num_cu, st); break;
-    case 11: e = go_render_bwd<11>(b, num_cu, st); break;
     case 12: e = go_render_bwd<12>(b, num_cu, st); break;
     case 16: e = go_render_bwd<16>(b, num_cu, st); break;
     case 32: e = go_render_bwd<32>(b, num_cu, st); break;
@@ -662,7 +661,6 @@ hipError_t launch_render(const RenderArgs &a, const RenderWS &w, int k, int num_
     case 4: e = go_render<4>(a, num_cu, st); break;
     case 8: e = go_render<8>(a, num_cu, st); break;
     case 12: e = go_render<12>(a, num_cu, st); break;
-    case 14: e = go_render<14>(a, num_cu, st); break;
     case 16: e = go_render<16>(a, num_cu, st); break;
     case 32: e = go_render<32>(a, num_cu, st); break;
     default: return hipErrorInvalidValue;
@@ -750,7 +748,6 @@ hipError_t launch_render_backward(const RenderArgs &a, const RenderWS &w, int k,
     case 2: e = go_render_bwd<2>(a, num_cu, st); break;
     case 4: e = go_render_bwd<4>(a, num_cu, st); break;
     case 8: e = go_render_bwd<8>(a, num_cu, st); break;
-    case 11: e = go_render_bwd<11>(a, num_cu, st); break;
     case 12: e = go_render_bwd<12>(a, num_cu, st); break;
     case 16: e = go_render_bwd<16>(a, num_cu, st); break;
     case 32: e = go_render_bwd<32>(a, num_cu, st); break;

@@ -988,8 +988,8 @@ class RenderMISFn(torch.autograd.Function):
                 k_bwd=None, timers=None):
         """hit_cap > 0: store up to hit_cap hits per sample in the forward and
         differentiate from the stored lists; 0: re-traverse in the backward.
-        k_bwd: k-buffer size of the backward (default k, or 11 when k is 14,
-        a size only the forward takes; results do not depend on either).
+        k_bwd: k-buffer size of the backward (default k, at most 12: the
+        backward's register budget; results do not depend on either).
         timers: optional (forward, backward) Timer pair that records the
         trace kernels of the two passes."""
         scene = Scene(gctx, means.detach().contiguous(), scales.detach().contiguous(), quats.detach().contiguous(),
@@ -998,7 +998,7 @@ class RenderMISFn(torch.autograd.Function):
         tf, tb = timers if timers is not None else (None, None)
         res = render_mis(scene, env, gb, split=split, seed=seed, k=k, save=True, hits=hits, hit_cap=hit_cap, timer=tf)
         if k_bwd is None:
-            k_bwd = 11 if k == 14 else k
+            k_bwd = min(k, 12)
         ctx_.scene, ctx_.env, ctx_.gb, ctx_.cfg = scene, env, gb, (split, seed, k_bwd, hit_cap)
         ctx_.saved_state, ctx_.hits, ctx_.timer = res["saved"], hits, tb
         return res["rgb"]
@@ -1027,8 +1027,8 @@ class RenderMISShadedFn(torch.autograd.Function):
         gb = GBuffer(H, W, *(t.detach().contiguous() for t in (x, n, wo, albedo, rough, metal)), valid.contiguous())
         hits = make_hit_list(gb.npix, sum(split), hit_cap, gb.x.device) if hit_cap > 0 else None
         res = render_mis(scene, env, gb, split=split, seed=seed, k=k, save=True, hits=hits, hit_cap=hit_cap)
-        # the backward's k (14 is a size only the forward takes)
-        ctx_.scene, ctx_.env, ctx_.gb, ctx_.cfg = scene, env, gb, (split, seed, 11 if k == 14 else k, hit_cap)
+        # the backward's k: at most 12 (its register budget)
+        ctx_.scene, ctx_.env, ctx_.gb, ctx_.cfg = scene, env, gb, (split, seed, min(k, 12), hit_cap)
         ctx_.saved_state, ctx_.hits = res["saved"], hits
         return res["rgb"]
 
