@@ -296,8 +296,11 @@ def leg_shapes(ctx, k, k_bwd, hit_cap, oracle_px=256):
     bwd_ms = _median_ms(bwd, 5)
     hits = grt.make_hit_list(gb.npix, sum(SPLIT), hit_cap, dev)
 
+    # the list-writing forward carries the list pointer: at most K = 12 fits
+    # its register budget without spills
     def fwd_s():
-        state["f"] = grt.render_mis(scene, E, G, split=SPLIT, seed=SEED, k=k, save=True, hits=hits, hit_cap=hit_cap)
+        state["f"] = grt.render_mis(scene, E, G, split=SPLIT, seed=SEED, k=min(k, 12), save=True, hits=hits,
+                                    hit_cap=hit_cap)
 
     def bwd_s():
         up = 2.0 * (state["f"]["rgb"] - target)
@@ -569,7 +572,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--k", type=int, default=16, help="k-buffer size of the forward")
-    ap.add_argument("--k-bwd", type=int, default=12, help="k-buffer size of the backward")
+    ap.add_argument("--k-bwd", type=int, default=13, help="k-buffer size of the backward")
     ap.add_argument("--k-relight", type=int, default=12, help="k-buffer size of the relighting query")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-pixels", type=int, default=192, help="pixels of the step the oracle times per run")
@@ -683,7 +686,7 @@ def main():
         sf, sb = [], []
         for _ in range(max(args.steps // 2, 2)):
             ef0.record(st)
-            res = grt.render_mis(scene, E, G, split=SPLIT, seed=SEED, k=args.k, save=True, hits=hits,
+            res = grt.render_mis(scene, E, G, split=SPLIT, seed=SEED, k=min(args.k, 12), save=True, hits=hits,
                                  hit_cap=args.hit_cap)
             ef1.record(st)
             eg0.record(st)

@@ -402,9 +402,9 @@ typedef struct {
  * u = (word >> 8) 2^-24; j < N_c is cosine, then N_g GGX (visible normals,
  * alpha = roughness^2), then N_e environment samples.
  * t_min: self-intersection offset along the secondary ray (1e-3).
- * k: k-nearest hit buffer size per traversal round, one of 1,2,4,8,12,16,32
- *   (results do not depend on k; the room workload runs 16 forward, 12
- *   backward, 12 relighting).
+ * k: k-nearest hit buffer size per traversal round, one of 1,2,4,8,12,16,32;
+ *   grt_render_mis_backward(_shading) also takes 13 (results do not depend
+ *   on k; the room workload runs 16 forward, 13 backward, 12 relighting).
  * sample_dump: optional [npix, spp, 10] floats per sample: direction (3),
  *   mixture pdf q, weight f cos/q (3), incident radiance L_i (3); zeros for
  *   samples below the horizon or invalid pixels.

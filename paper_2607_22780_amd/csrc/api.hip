@@ -108,10 +108,13 @@ int check_rays(const grt_rays *r)
     return GRT_OK;
 }
 
-static int check_k(int k)
+// backward: the MIS backward also takes 13 (the size that fits its register
+// budget at 3 wavefronts per SIMD)
+static int check_k(int k, bool backward = false)
 {
     if (k == 1 || k == 2 || k == 4 || k == 8 || k == 12 || k == 16 || k == 32) return GRT_OK;
-    return fail(GRT_ERR_INVALID, "k = %d is not one of 1,2,4,8,12,16,32", k);
+    if (backward && k == 13) return GRT_OK;
+    return fail(GRT_ERR_INVALID, "k = %d is not one of 1,2,4,8,12,16,32%s", k, backward ? " (or 13)" : "");
 }
 
 int check_scene(const grt_scene *s)
@@ -633,20 +636,22 @@ size_t grt_render_workspace_bytes(int64_t npix, int spp)
     return grt::carve_render(nullptr, npix * spp).bytes;
 }
 
-static int fill_render_common(const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *o, grt::RenderArgs &a);
+static int fill_render_common(const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *o, grt::RenderArgs &a,
+                              bool backward = false);
 
 static int fill_render_args(const grt_scene *scene, const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *o,
-                            grt::RenderArgs &a)
+                            grt::RenderArgs &a, bool backward = false)
 {
     int rc = check_scene(scene);
     if (rc) return rc;
-    if ((rc = fill_render_common(env, g, o, a))) return rc;
+    if ((rc = fill_render_common(env, g, o, a, backward))) return rc;
     a.S = scene_dev(scene);
     return GRT_OK;
 }
 
 // everything of a render but the scene (a.S left empty)
-static int fill_render_common(const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *o, grt::RenderArgs &a)
+static int fill_render_common(const grt_env *env, const grt_gbuffer *g, const grt_mis_opts *o, grt::RenderArgs &a,
+                              bool backward)
 {
     int rc;
     if (!env) return fail(GRT_ERR_INVALID, "env is NULL");
@@ -660,7 +665,7 @@ static int fill_render_common(const grt_env *env, const grt_gbuffer *g, const gr
     if (o->n_cos < 0 || o->n_ggx < 0 || o->n_env < 0 || o->n_cos + o->n_ggx + o->n_env <= 0 ||
         o->n_cos + o->n_ggx + o->n_env > 65536)
         return fail(GRT_ERR_INVALID, "bad sample allocation %d/%d/%d", o->n_cos, o->n_ggx, o->n_env);
-    if ((rc = check_k(o->k))) return rc;
+    if ((rc = check_k(o->k, backward))) return rc;
     if (!(o->t_min >= 0.0f)) return fail(GRT_ERR_INVALID, "t_min must be >= 0");
     if (!(o->t_cut >= 0.0f && o->t_cut < 1.0f)) return fail(GRT_ERR_INVALID, "t_cut must be in [0,1)");
     memset(&a, 0, sizeof(a));
@@ -916,7 +921,7 @@ static int render_backward(const grt_scene *scene, const grt_env *env, const grt
                            size_t ws_bytes, void *stream)
 {
     grt::RenderArgs a;
-    int rc = fill_render_args(scene, env, g, opts, a);
+    int rc = fill_render_args(scene, env, g, opts, a, true);
     if (rc) return rc;
     if ((int64_t)g->H * g->W > 0 && (!grad_rgb || !saved)) return fail(GRT_ERR_INVALID, "grad_rgb/saved is NULL");
     if (saved && !aligned(saved, 16)) return fail(GRT_ERR_INVALID, "saved must be 16-byte aligned");

@@ -193,6 +193,15 @@ __device__ __forceinline__ float safe_inv(float d)
     return 1.0f / (fabsf(d) > 1e-30f ? d : copysignf(1e-30f, d));
 }
 
+// The walk's inverse direction, formed at each node step rather than held (3
+// registers): the hardware reciprocal (1 ulp) is far inside the slab test's
+// slack and the boxes' padding, so the test still rejects no box the ray
+// enters.
+__device__ __forceinline__ float fast_inv(float d)
+{
+    return __builtin_amdgcn_rcpf(fabsf(d) > 1e-30f ? d : copysignf(1e-30f, d));
+}
+
 __device__ __forceinline__ uint64_t make_key(float tau, uint32_t id)
 {
     return ((uint64_t)__float_as_uint(tau) << 32) | (uint64_t)id;
@@ -236,7 +245,7 @@ __device__ __forceinline__ uint64_t make_key(float tau, uint32_t id)
 #endif
 constexpr int kLdsDepth = GRT_LDS_DEPTH;  // LDS entries per lane and stack
 #ifndef GRT_BWD_LDS_DEPTH
-#define GRT_BWD_LDS_DEPTH 12
+#define GRT_BWD_LDS_DEPTH 16
 #endif
 constexpr int kBwdLdsDepth = GRT_BWD_LDS_DEPTH;  // backward kernels: their LDS also holds gradient tables
 // Backward kernels composite a hit (running the gradient chain) only in
@@ -338,7 +347,7 @@ struct Frontier {
 template <int K, int D = kLdsDepth, int kCompShare16 = GRT_FWD_COMP_SHARE16, int kSiteShare8 = 0>
 struct Walker {
     static constexpr int kDepth = D;  // LDS entries per lane and stack
-    float3 o, d, inv;
+    float3 o, d;
     float tmin, tmax;
     uint64_t last;        // start key of the round; while compositing, the last composited hit
     uint64_t key[K];
@@ -377,7 +386,6 @@ struct Walker {
     {
         o = o_;
         d = d_;
-        inv = make_float3(safe_inv(d.x), safe_inv(d.y), safe_inv(d.z));
         tmin = tmin_;
         tmax = tmax_;
         last = 0;
@@ -482,6 +490,7 @@ struct Walker {
 #endif
         const Node4 *nd = S.nodes4 + cur;
         const float tlo = lo_bound(), thi = hi_bound();
+        const float3 inv = make_float3(fast_inv(d.x), fast_inv(d.y), fast_inv(d.z));
         const float4 lx = nd->lx, ly = nd->ly, lz = nd->lz, hx = nd->hx, hy = nd->hy, hz = nd->hz;
         const int4 ch = nd->ch;
         // all four boxes tested without branches (an unused slot's zero box

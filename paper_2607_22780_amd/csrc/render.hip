@@ -372,6 +372,16 @@ __global__ void __launch_bounds__(256) GRT_OCCUPANCY k_render_bwd(RenderArgs a)
     run_persistent<K>(job, a.counters, (int64_t)a.H * a.W * (a.nc + a.ng + a.ne));
 }
 
+// The re-traversal with a 13-hit buffer fits 3 wavefronts per SIMD (168
+// VGPRs) when the compiler is held to it, and then beats K = 12.
+template <int K, bool kOrigin>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) k_render_bwd_w3(RenderArgs a)
+{
+    __shared__ WaveStage stages[4];
+    RenderBwdJob<K, kOrigin> job(a, &stages[(threadIdx.x >> 6) & 3]);
+    run_persistent<K>(job, a.counters, (int64_t)a.H * a.W * (a.nc + a.ng + a.ne));
+}
+
 // Backward from stored hit lists: one thread per sample runs the gradient of
 // its composited hits in order (no traversal).  Samples whose list
 // overflowed are left to the re-traversal kernel.  The wavefront steps
@@ -516,12 +526,19 @@ static hipError_t go_render(const RenderArgs &a, int num_cu, hipStream_t st)
     return a.hits ? go_render_as<K, true>(a, num_cu, st) : go_render_as<K, false>(a, num_cu, st);
 }
 
+// (the shading-state variant, kOrigin, keeps the plain kernel: it carries
+// the origin gradient too and would spill at 3 wavefronts per SIMD)
 template <int K, bool kOrigin>
 static hipError_t go_render_bwd_as(const RenderArgs &a, int num_cu, hipStream_t st)
 {
     const int64_t total = (int64_t)a.H * a.W * (a.nc + a.ng + a.ne);
-    const int nb = persistent_blocks(k_render_bwd<K, kOrigin>, num_cu, total);
-    hipLaunchKernelGGL((k_render_bwd<K, kOrigin>), dim3(nb), dim3(256), 0, st, a);
+    if constexpr (K == 13 && !kOrigin) {
+        const int nb = persistent_blocks(k_render_bwd_w3<K, kOrigin>, num_cu, total);
+        hipLaunchKernelGGL((k_render_bwd_w3<K, kOrigin>), dim3(nb), dim3(256), 0, st, a);
+    } else {
+        const int nb = persistent_blocks(k_render_bwd<K, kOrigin>, num_cu, total);
+        hipLaunchKernelGGL((k_render_bwd<K, kOrigin>), dim3(nb), dim3(256), 0, st, a);
+    }
     return hipGetLastError();
 }
 
@@ -560,6 +577,7 @@ hipError_t launch_render_backward_stored(const RenderArgs &a, const RenderWS &w,
     case 4: e = go_render_bwd<4>(b, num_cu, st); break;
     case 8: e = go_render_bwd<8>(b, num_cu, st); break;
     case 12: e = go_render_bwd<12>(b, num_cu, st); break;
+    case 13: e = go_render_bwd<13>(b, num_cu, st); break;
     case 16: e = go_render_bwd<16>(b, num_cu, st); break;
     case 32: e = go_render_bwd<32>(b, num_cu, st); break;
     default: return hipErrorInvalidValue;
@@ -749,6 +767,7 @@ hipError_t launch_render_backward(const RenderArgs &a, const RenderWS &w, int k,
     case 4: e = go_render_bwd<4>(a, num_cu, st); break;
     case 8: e = go_render_bwd<8>(a, num_cu, st); break;
     case 12: e = go_render_bwd<12>(a, num_cu, st); break;
+    case 13: e = go_render_bwd<13>(a, num_cu, st); break;
     case 16: e = go_render_bwd<16>(a, num_cu, st); break;
     case 32: e = go_render_bwd<32>(a, num_cu, st); break;
     default: return hipErrorInvalidValue;

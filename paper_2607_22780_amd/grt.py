@@ -988,7 +988,7 @@ class RenderMISFn(torch.autograd.Function):
                 k_bwd=None, timers=None):
         """hit_cap > 0: store up to hit_cap hits per sample in the forward and
         differentiate from the stored lists; 0: re-traverse in the backward.
-        k_bwd: k-buffer size of the backward (default k, at most 12: the
+        k_bwd: k-buffer size of the backward (default k, at most 13: the
         backward's register budget; results do not depend on either).
         timers: optional (forward, backward) Timer pair that records the
         trace kernels of the two passes."""
@@ -998,7 +998,7 @@ class RenderMISFn(torch.autograd.Function):
         tf, tb = timers if timers is not None else (None, None)
         res = render_mis(scene, env, gb, split=split, seed=seed, k=k, save=True, hits=hits, hit_cap=hit_cap, timer=tf)
         if k_bwd is None:
-            k_bwd = min(k, 12)
+            k_bwd = min(k, 13)
         ctx_.scene, ctx_.env, ctx_.gb, ctx_.cfg = scene, env, gb, (split, seed, k_bwd, hit_cap)
         ctx_.saved_state, ctx_.hits, ctx_.timer = res["saved"], hits, tb
         return res["rgb"]
