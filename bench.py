@@ -147,6 +147,15 @@ def bytes_per_ray(wc, env_hw=(256, 512)):
     return fwd, bwd
 
 
+def trace_kernel(kind, k):
+    """Base name of the kernel the library launches for the MIS forward
+    ("fwd") or its re-traversal backward ("bwd") at k-buffer size k (the
+    sizes held to 3 wavefronts per SIMD have their own kernels)."""
+    if kind == "bwd":
+        return "k_render_bwd_w3" if k == 13 else "k_render_bwd"
+    return "k_render_w3" if k in (12, 16) else "k_render"
+
+
 def roofline(bytes_per, units, ms):
     achieved = bytes_per * units / (ms * 1e-3) / 1e9
     return dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -788,7 +797,7 @@ def main():
         dominant = "bwd" if kb >= kf else "fwd"
         ms = kb if dominant == "bwd" else kf
         per_ray = bb if dominant == "bwd" else bf
-        kname = "k_render_bwd" if dominant == "bwd" else "k_render"
+        kname = trace_kernel(dominant, args.k_bwd if dominant == "bwd" else args.k)
         traffic = l2_hit = None
         if os.path.exists(TRAFFIC):
             tr = json.load(open(TRAFFIC))

@@ -159,7 +159,7 @@ struct WaveStageN {
     int count;
 };
 #ifndef GRT_STAGE_CAP
-#define GRT_STAGE_CAP 80
+#define GRT_STAGE_CAP 88
 #endif
 using WaveStage = WaveStageN<GRT_STAGE_CAP>;
 
