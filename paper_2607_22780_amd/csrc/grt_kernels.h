@@ -151,15 +151,17 @@ struct GBufVisit : AttrVisit {
 // hits per instruction.  Flushes run at wavefront-uniform points; a step
 // stages at most one hit per lane, so flushing whenever the list could not
 // take another full step keeps it from overflowing.
-constexpr int kStageStride = 14;  // 13 terms, then the surfel id
+constexpr int kStageStride = 16;  // 13 terms, then the surfel id (16-byte aligned entries)
 template <int Cap>
 struct WaveStageN {
     static constexpr int kCap = Cap;
-    float v[Cap * kStageStride];
+    alignas(16) float v[Cap * kStageStride];
     int count;
 };
+// 80 entries of 64 bytes: with the backward's 16-deep stacks, 52 KB of LDS
+// per workgroup, three workgroups per CU
 #ifndef GRT_STAGE_CAP
-#define GRT_STAGE_CAP 88
+#define GRT_STAGE_CAP 80
 #endif
 using WaveStage = WaveStageN<GRT_STAGE_CAP>;
 
@@ -171,10 +173,12 @@ __device__ __forceinline__ void stage_add(Stage *s, uint32_t id, const float (&t
     const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
     volatile int *cnt = &s->count;
     const int base = __builtin_amdgcn_readfirstlane(*cnt);
-    volatile float *e = &s->v[(base + rank) * kStageStride];
-#pragma unroll
-    for (int c = 0; c < 13; ++c) e[c] = t[c];
-    reinterpret_cast<volatile uint32_t *>(e)[13] = id;
+    // four 16-byte stores per entry; stage_sync's fences order them
+    float4 *e = reinterpret_cast<float4 *>(&s->v[(base + rank) * kStageStride]);
+    e[0] = make_float4(t[0], t[1], t[2], t[3]);
+    e[1] = make_float4(t[4], t[5], t[6], t[7]);
+    e[2] = make_float4(t[8], t[9], t[10], t[11]);
+    e[3] = make_float4(t[12], __uint_as_float(id), 0.0f, 0.0f);
     if (rank == 0) *cnt = base + __popcll(m);
 }
 
