@@ -280,15 +280,13 @@ static hipError_t go_serve_one_as(const RenderArgs &a, const ServeEpoch &e, int6
 
 // Radiance epochs may be stopped; relighting epochs never are.  A mixed
 // epoch's lanes trace for different requests, so its relighting query takes
-// its tables with each ray; those per-lane tables spill at K = 12, so mixed
-// epochs then run the 8-entry buffer (the size changes no result).
+// its tables with each ray.
 template <int K>
 static hipError_t go_relight_epoch(const ServeEpoch &e, const RenderArgs *one, int64_t r0, int num_cu,
                                    hipStream_t st)
 {
-    constexpr int Km = K == 12 ? 8 : K;
     return one ? go_serve_one_as<K, RelightTrace<K>, true>(*one, e, r0, num_cu, st)
-               : go_serve_as<Km, RelightTrace<Km, true>, false>(e, num_cu, st);
+               : go_serve_as<K, RelightTrace<K, true>, false>(e, num_cu, st);
 }
 
 template <int K>
