@@ -78,9 +78,11 @@ def test_trace_autograd_function(grt_ctx):
     check_grads(got, ref)
 
 
-def test_render_backward_small_scene(grt_ctx):
+@pytest.mark.parametrize("k_bwd", [16, 13])
+def test_render_backward_small_scene(grt_ctx, k_bwd):
     """Retrace backward of the MIS render on pixels whose every sample is
-    clear of knife edges (the rest get zero upstream gradient)."""
+    clear of knife edges (the rest get zero upstream gradient); 13 is the
+    benchmarked backward's hit-buffer size (its own kernel)."""
     grt, ctx = grt_ctx
     from gpu_util import t, scene_tensors
     s = W.scene1(n=20000, seed=0, s_lo=0.01, s_hi=0.06)
@@ -97,7 +99,7 @@ def test_render_backward_small_scene(grt_ctx):
     E = grt.Env(ctx, t(env))
     G = grt.GBuffer.from_numpy(gb, torch.device("cuda", 0))
     fwd = grt.render_mis(scene, E, G, split=split, seed=3, save=True)
-    gg = grt.render_mis_backward(scene, E, G, t(grad), fwd["saved"], split=split, seed=3)
+    gg = grt.render_mis_backward(scene, E, G, t(grad), fwd["saved"], split=split, seed=3, k=k_bwd)
     torch.cuda.synchronize()
     check_grads({k: v.cpu().numpy() for k, v in gg.items()}, ref)
 

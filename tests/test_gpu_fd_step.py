@@ -201,10 +201,11 @@ def test_oracle_gradient_against_differences(fd_ref):
     check(fd_ref["g13"], fd_ref, "oracle")
 
 
-@pytest.mark.parametrize("cap", [0, 64])
-def test_gpu_gradient_against_differences(fd_ref, cap):
+@pytest.mark.parametrize("cap,k,k_bwd", [(0, 12, 8), (64, 12, 8), (0, 16, 13)])
+def test_gpu_gradient_against_differences(fd_ref, cap, k, k_bwd):
     """Re-traversal (cap 0) and stored hit lists (64 per sample, the rest
-    re-traversed) over the whole 800x800 image."""
+    re-traversed) over the whole 800x800 image; (16, 13) are the hit-buffer
+    sizes of the benchmarked step."""
     from paper_2607_22780_amd import grt
     from gpu_util import t, scene_tensors
     ctx = grt.Context(0)
@@ -215,11 +216,12 @@ def test_gpu_gradient_against_differences(fd_ref, cap):
     G = grt.GBuffer.from_numpy(gb, dev)
     spp = sum(SPLIT)
     hits = grt.make_hit_list(gb.npix, spp, cap, dev) if cap else None
-    fwd = grt.render_mis(scene, E, G, split=SPLIT, seed=SEED, k=12, save=True, hits=hits, hit_cap=cap)
+    fwd = grt.render_mis(scene, E, G, split=SPLIT, seed=SEED, k=k, save=True, hits=hits, hit_cap=cap)
     up = torch.zeros(gb.npix, 3, device=dev)
     up[torch.from_numpy(pix).to(dev)] = t(fd_ref["up"].astype(np.float32))
-    gg = grt.render_mis_backward(scene, E, G, up, fwd["saved"], split=SPLIT, seed=SEED, k=8, hits=hits, hit_cap=cap)
+    gg = grt.render_mis_backward(scene, E, G, up, fwd["saved"], split=SPLIT, seed=SEED, k=k_bwd, hits=hits,
+                                 hit_cap=cap)
     torch.cuda.synchronize()
     ids = torch.from_numpy(fd_ref["ids"]).to(dev)
     got = np.concatenate([gg[b][ids].reshape(len(ids), -1).cpu().numpy().astype(np.float64) for b in BLOCKS], axis=1)
-    check(got, fd_ref, f"gpu cap={cap}")
+    check(got, fd_ref, f"gpu cap={cap} k={k}/{k_bwd}")
