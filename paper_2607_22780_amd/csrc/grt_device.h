@@ -555,7 +555,11 @@ struct Walker {
     // `last` already holds the round's largest key, where the next one starts.
     __device__ __forceinline__ void next_round(const SceneDev &S)
     {
-        clear_buffer();
+        // The buffer is empty already (every composite shifted an empty key in
+        // at its end, and the round composited all its hits), so only the
+        // count is reset: rewriting the keys would give the registers a
+        // second version to reconcile at every exit of the surfel step.
+        cnt = 0;
 #ifdef GRT_STATS
         ++st_rounds;
         st_lost += lost ? 1 : 0;
